@@ -1,0 +1,193 @@
+"""FP64 CPU oracle for the RAM advection step -- TEST INFRASTRUCTURE.
+
+Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product path never calls it, and it
+shares no code with the device library.
+
+The arithmetic lives in ``ram_oracle.c`` (plain loops, FP64, fixed summation
+order, one row at a time).  This module only marshals numpy arrays into it.
+Every function follows one passage of the paper:
+
+  shift            Section 3, Steps 1-3 (Eqs. Qmass_i, mass_advected,
+                   condition_p, mass_shift_algo, step3), reconstruction read as
+                   the derivative of the order-p Lagrange interpolant of the
+                   node cumulative;
+  residual         Eq. splitting_second with the PLM / van Leer slope of
+                   Section 3.1 and the swept-interval upwind face state;
+  step             the operator split of Section 1: shift, then residual;
+  shift_adjoint    transpose of the (linear) shift, plus dL/dv0;
+  residual_adjoint transpose of the residual Jacobian, plus dL/d(dv).
+
+Pins (tests/test_oracle_*.py) tie each function to what the paper and the
+mathematics fix; see the test module docstrings.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ram_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "libram_oracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (OpenMP over rows, no FP contraction)."""
+    if not force and os.path.exists(_LIB_PATH):
+        return _LIB_PATH
+    tmp = _LIB_PATH + ".tmp"
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+           "-fPIC", "-shared", "-std=c11", "-Wall", "-o", tmp, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB_PATH)
+    P = ctypes.c_void_p
+    I64 = ctypes.c_int64
+    D = ctypes.c_double
+    I = ctypes.c_int
+    lib.oracle_shift.argtypes = [I64, P, P, I, P, P, P, D, I, I, I]
+    lib.oracle_residual.argtypes = [I64, P, P, I, P, P, P, D, I]
+    lib.oracle_step.argtypes = [I64, P, P, I, P, P, P, D, I, I64, I]
+    lib.oracle_shift_adjoint.argtypes = [I64, P, P, I, P, P, P, P, D, I, P, I]
+    lib.oracle_residual_adjoint.argtypes = [I64, P, P, I, P, P, P, P, P, D, I]
+    lib.oracle_edges.argtypes = [P, P, I64, D, I, P, P, P, P, P]
+    lib.oracle_max_threads.argtypes = []
+    for f in ("oracle_shift", "oracle_residual", "oracle_step",
+              "oracle_shift_adjoint", "oracle_residual_adjoint", "oracle_edges",
+              "oracle_max_threads"):
+        getattr(lib, f).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def max_threads() -> int:
+    return int(_load().oracle_max_threads())
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data
+
+
+class Rows:
+    """Row geometry: ``row_ptr`` cell offsets and edges (shared or per row)."""
+
+    def __init__(self, row_ptr, edges, shared: bool):
+        self.row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        self.edges = _f64(edges)
+        self.shared = bool(shared)
+        self.n_rows = len(self.row_ptr) - 1
+        self.n_cells = int(self.row_ptr[-1])
+
+    @classmethod
+    def from_workload(cls, wl) -> "Rows":
+        return cls(wl.row_ptr, wl.edges, wl.edges_shared)
+
+    @classmethod
+    def single(cls, edges) -> "Rows":
+        edges = _f64(edges)
+        return cls(np.array([0, len(edges) - 1]), edges, True)
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise RuntimeError(f"oracle {what} failed with status {rc}")
+
+
+def shift(rows: Rows, q, v0, dt: float, order: int, variant: int = 0,
+          nthreads: int = 0) -> np.ndarray:
+    """One bulk shift of every row (variant 0 local form, 1 global cumulative)."""
+    q = _f64(q).reshape(-1)
+    v0 = _f64(np.broadcast_to(v0, (rows.n_rows,)))
+    out = np.empty_like(q)
+    rc = _load().oracle_shift(rows.n_rows, _ptr(rows.row_ptr), _ptr(rows.edges),
+                              int(rows.shared), _ptr(q), _ptr(out), _ptr(v0),
+                              float(dt), int(order), int(variant), int(nthreads))
+    _check(rc, "shift")
+    return out
+
+
+def residual(rows: Rows, q, dv, dt: float, nthreads: int = 0) -> np.ndarray:
+    q = _f64(q).reshape(-1)
+    dv = _f64(dv).reshape(-1)
+    out = np.empty_like(q)
+    rc = _load().oracle_residual(rows.n_rows, _ptr(rows.row_ptr),
+                                 _ptr(rows.edges), int(rows.shared), _ptr(q),
+                                 _ptr(out), _ptr(dv), float(dt), int(nthreads))
+    _check(rc, "residual")
+    return out
+
+
+def step(rows: Rows, q, v0, dv, dt: float, order: int, n_steps: int,
+         nthreads: int = 0) -> np.ndarray:
+    """n_steps of shift then residual (dv None: shift only)."""
+    q = _f64(q).reshape(-1).copy()
+    v0 = _f64(np.broadcast_to(v0, (rows.n_rows,)))
+    dvp = None if dv is None else _f64(dv).reshape(-1)
+    rc = _load().oracle_step(rows.n_rows, _ptr(rows.row_ptr), _ptr(rows.edges),
+                             int(rows.shared), _ptr(q), _ptr(v0), _ptr(dvp),
+                             float(dt), int(order), int(n_steps), int(nthreads))
+    _check(rc, "step")
+    return q
+
+
+def shift_adjoint(rows: Rows, q, qbar_out, v0, dt: float, order: int,
+                  want_v0bar: bool = True, nthreads: int = 0):
+    """Returns (qbar_in, v0bar) with v0bar = dt * d<qbar_out, S q>/ds per row."""
+    q = _f64(q).reshape(-1)
+    qb = _f64(qbar_out).reshape(-1)
+    v0 = _f64(np.broadcast_to(v0, (rows.n_rows,)))
+    out = np.empty_like(qb)
+    v0bar = np.zeros(rows.n_rows) if want_v0bar else None
+    rc = _load().oracle_shift_adjoint(rows.n_rows, _ptr(rows.row_ptr),
+                                      _ptr(rows.edges), int(rows.shared),
+                                      _ptr(q), _ptr(qb), _ptr(out), _ptr(v0),
+                                      float(dt), int(order), _ptr(v0bar),
+                                      int(nthreads))
+    _check(rc, "shift_adjoint")
+    return out, v0bar
+
+
+def residual_adjoint(rows: Rows, q, dv, qbar_out, dt: float,
+                     want_dvbar: bool = True, nthreads: int = 0):
+    """Returns (qbar_in, dvbar) at the forward state q."""
+    q = _f64(q).reshape(-1)
+    dv = _f64(dv).reshape(-1)
+    qb = _f64(qbar_out).reshape(-1)
+    out = np.empty_like(qb)
+    dvbar = np.zeros_like(qb) if want_dvbar else None
+    rc = _load().oracle_residual_adjoint(rows.n_rows, _ptr(rows.row_ptr),
+                                         _ptr(rows.edges), int(rows.shared),
+                                         _ptr(q), _ptr(dv), _ptr(qb), _ptr(out),
+                                         _ptr(dvbar), float(dt), int(nthreads))
+    _check(rc, "residual_adjoint")
+    return out, dvbar
+
+
+def edges_info(x, q, s: float, order: int):
+    """Per shifted node of one row: (xh, k, c, ell, dell) for e = 0..N-1."""
+    x = _f64(x)
+    q = _f64(q)
+    n = len(q)
+    xh = np.empty(n); ell = np.empty(n); dell = np.empty(n)
+    k = np.empty(n, dtype=np.int64); c = np.empty(n, dtype=np.int64)
+    _load().oracle_edges(_ptr(x), _ptr(q), n, float(s), int(order), _ptr(xh),
+                         _ptr(k), _ptr(c), _ptr(ell), _ptr(dell))
+    return xh, k, c, ell, dell

@@ -1,0 +1,492 @@
+/*
+ * ram_oracle.c -- plain, slow FP64 CPU oracle for the RAM advection step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the package smoke check and
+ * the benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header, table or helper with the device path.
+ *
+ * What it computes, per periodic row of N cells bounded by N+1 nodes x[0..N]
+ * (Section 2 of the paper):
+ *
+ *   shift      the bulk step of the operator split (Section 1, Eq.
+ *              splitting_first): the conservative remap of Section 3, Steps 1-3
+ *              (Eqs. Qmass_i, mass_advected, condition_p, mass_shift_algo,
+ *              step3).  The reconstruction q~ inside source cell c is the
+ *              derivative of the degree-p Lagrange interpolant of the node
+ *              cumulative C through the p+1 nodes c-lo .. c-lo+p (lo=(p-1)/2).
+ *              The mass of a destination cell is then the whole-cell masses it
+ *              covers plus two partial integrals of q~, exactly the shape of
+ *              Eq. mass_shift_algo.  Node N is node 0 of the next period
+ *              ("p(N) = p(0)", Section 3.2).
+ *   residual   the second half of the split (Eq. splitting_second): a finite-
+ *              volume upwind step with the PLM reconstruction and the van Leer
+ *              harmonic slope of Section 3.1; the face state is the average of
+ *              the upwind linear profile over the swept interval, i.e. Eq.
+ *              mass_shift_algo in its sub-cell (Lufkin) limit of Section 3.2.
+ *   step       shift, then residual (Section 1).
+ *   adjoints   transposes of the two linearised maps, written as scatter loops
+ *              (the device path gathers); plus the derivative w.r.t. the bulk
+ *              speed v0 (through x~ = x - v0 dt, Section 3.2).
+ *
+ * Everything is FP64, in a fixed summation order; build with
+ * -O2 -ffp-contract=off.  OpenMP parallelises over independent rows only.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORACLE_MAX_ORDER 9
+
+static int64_t wrap(int64_t m, int64_t n)
+{
+    int64_t r = m % n;
+    return r < 0 ? r + n : r;
+}
+
+/* Node coordinate of the periodically extended mesh, j in [-N, 2N]. */
+static double node_x(const double *x, int64_t n, double len, int64_t j)
+{
+    if (j < 0) return x[j + n] - len;
+    if (j > n) return x[j - n] + len;
+    return x[j];
+}
+
+/* Mass of (wrapped) cell m. */
+static double cell_mass(const double *x, const double *q, int64_t n, int64_t m)
+{
+    int64_t w = wrap(m, n);
+    return q[w] * (x[w + 1] - x[w]);
+}
+
+/* C(j) - C(c) for extended node indices, summed over the cells in between in
+ * ascending order (no global prefix, so it is exact for a single cell). */
+static double cum_diff(const double *x, const double *q, int64_t n, int64_t c,
+                       int64_t j)
+{
+    double s = 0.0;
+    if (j > c) {
+        for (int64_t m = c; m < j; ++m) s += cell_mass(x, q, n, m);
+        return s;
+    }
+    for (int64_t m = j; m < c; ++m) s += cell_mass(x, q, n, m);
+    return -s;
+}
+
+/* Largest j in [0, n-1] with x[j] <= xh (Eq. condition_p; right-continuous). */
+static int64_t find_cell(const double *x, int64_t n, double xh)
+{
+    int64_t lo = 0, hi = n - 1;
+    if (!(xh >= x[0])) return 0;
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo + 1) / 2;
+        if (x[mid] <= xh) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+/* Shifted node: x~ = x_e - s, written as xh + k L with xh in [x0, xN). */
+static void shifted_node(const double *x, int64_t n, double s, int64_t e,
+                         double *xh_out, int64_t *k_out)
+{
+    double len = x[n] - x[0];
+    double xt = x[e] - s;
+    double kf = floor((xt - x[0]) / len);
+    double xh = xt - kf * len;
+    int64_t k = (int64_t)kf;
+    if (xh >= x[n]) { xh -= len; k += 1; }
+    else if (xh < x[0]) { xh += len; k -= 1; }
+    *xh_out = xh;
+    *k_out = k;
+}
+
+/* Lagrange basis weight a on nodes X[0..p] evaluated at t. */
+static double lagrange_w(const double *X, int p, int a, double t)
+{
+    double w = 1.0;
+    for (int b = 0; b <= p; ++b)
+        if (b != a) w *= (t - X[b]) / (X[a] - X[b]);
+    return w;
+}
+
+/* Derivative of the Lagrange basis weight a at t. */
+static double lagrange_dw(const double *X, int p, int a, double t)
+{
+    double tot = 0.0;
+    for (int b = 0; b <= p; ++b) {
+        if (b == a) continue;
+        double term = 1.0 / (X[a] - X[b]);
+        for (int c = 0; c <= p; ++c)
+            if (c != a && c != b) term *= (t - X[c]) / (X[a] - X[c]);
+        tot += term;
+    }
+    return tot;
+}
+
+typedef struct {
+    double xh;      /* wrapped shifted node */
+    int64_t k;      /* wrap count */
+    int64_t c;      /* source cell containing xh */
+    int64_t g;      /* extended source index c + k N */
+    double ell;     /* C~(xh) - C(c): the partial integral of q~_c */
+    double dell;    /* q~_c(xh) = d C~ / dx at xh */
+} edge_t;
+
+/* Step 1 + the partial integrals of Step 2 for one shifted node. */
+static void edge_eval(const double *x, const double *q, int64_t n, double s,
+                      int p, int64_t e, int want_deriv, edge_t *out)
+{
+    double len = x[n] - x[0];
+    int lo = (p - 1) / 2;
+    double X[ORACLE_MAX_ORDER + 1], D[ORACLE_MAX_ORDER + 1];
+    shifted_node(x, n, s, e, &out->xh, &out->k);
+    out->c = find_cell(x, n, out->xh);
+    out->g = out->c + out->k * n;
+    for (int a = 0; a <= p; ++a) {
+        int64_t j = out->c - lo + a;
+        X[a] = node_x(x, n, len, j);
+        D[a] = cum_diff(x, q, n, out->c, j);
+    }
+    double ell = 0.0, dell = 0.0;
+    for (int a = 0; a <= p; ++a) {
+        ell += lagrange_w(X, p, a, out->xh) * D[a];
+        if (want_deriv) dell += lagrange_dw(X, p, a, out->xh) * D[a];
+    }
+    out->ell = ell;
+    out->dell = dell;
+}
+
+/* ---------------------------------------------------------------------- */
+/* bulk shift of one row                                                    */
+/* ---------------------------------------------------------------------- */
+
+/* variant 0: local form  M'_i = sum_{m=g_i}^{g_{i+1}-1} M_m + ell_{i+1} - ell_i
+ * variant 1: global form M'_i = (C(g_{i+1}) + ell_{i+1}) - (C(g_i) + ell_i)
+ *            with the extended cumulative C(j + kN) = C(j) + k M_tot. */
+static int shift_row(const double *x, const double *q, double *qout, int64_t n,
+                     double s, int p, int variant)
+{
+    edge_t *ed = (edge_t *)malloc(sizeof(edge_t) * (size_t)(n + 1));
+    double *cum = NULL;
+    if (!ed) return -6;
+    for (int64_t e = 0; e < n; ++e) edge_eval(x, q, n, s, p, e, 0, &ed[e]);
+    ed[n] = ed[0];
+    ed[n].k += 1;
+    ed[n].g += n;
+    if (variant == 1) {
+        cum = (double *)malloc(sizeof(double) * (size_t)(n + 1));
+        if (!cum) { free(ed); return -6; }
+        cum[0] = 0.0;
+        for (int64_t m = 0; m < n; ++m) cum[m + 1] = cum[m] + cell_mass(x, q, n, m);
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        double dx = x[i + 1] - x[i];
+        double mp;
+        if (variant == 0) {
+            double whole = 0.0;
+            for (int64_t m = ed[i].g; m < ed[i + 1].g; ++m) whole += cell_mass(x, q, n, m);
+            mp = whole + ed[i + 1].ell - ed[i].ell;
+        } else {
+            int64_t ga = ed[i].g, gb = ed[i + 1].g;
+            int64_t ka = (ga - wrap(ga, n)) / n, kb = (gb - wrap(gb, n)) / n;
+            double va = cum[wrap(ga, n)] + (double)ka * cum[n] + ed[i].ell;
+            double vb = cum[wrap(gb, n)] + (double)kb * cum[n] + ed[i + 1].ell;
+            mp = vb - va;
+        }
+        qout[i] = mp / dx;
+    }
+    free(ed);
+    free(cum);
+    return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* residual upwind step of one row                                          */
+/* ---------------------------------------------------------------------- */
+
+static double centre(const double *x, int64_t i) { return 0.5 * (x[i] + x[i + 1]); }
+
+/* distance between the centres of cells i and i+1 (periodic) */
+static double centre_gap(const double *x, int64_t n, int64_t i)
+{
+    double len = x[n] - x[0];
+    int64_t w = wrap(i, n);
+    if (w == n - 1) return centre(x, 0) + len - centre(x, n - 1);
+    return centre(x, w + 1) - centre(x, w);
+}
+
+/* van Leer harmonic slope of cell i (Section 3.1) */
+static double vl_slope(const double *x, const double *q, int64_t n, int64_t i)
+{
+    double qm = q[wrap(i - 1, n)], q0 = q[wrap(i, n)], qp = q[wrap(i + 1, n)];
+    double dp = (qp - q0) / centre_gap(x, n, i);
+    double dm = (q0 - qm) / centre_gap(x, n, i - 1);
+    if (dp * dm <= 0.0) return 0.0;
+    return 2.0 * dp * dm / (dp + dm);
+}
+
+/* upwind face state on face f (between cells f-1 and f) */
+static double face_state(const double *x, const double *q, int64_t n, int64_t f,
+                         double v, double dt)
+{
+    if (v >= 0.0) {
+        int64_t u = wrap(f - 1, n);
+        double dx = x[u + 1] - x[u];
+        return q[u] + 0.5 * vl_slope(x, q, n, u) * (dx - v * dt);
+    } else {
+        int64_t u = wrap(f, n);
+        double dx = x[u + 1] - x[u];
+        return q[u] - 0.5 * vl_slope(x, q, n, u) * (dx + v * dt);
+    }
+}
+
+static int residual_row(const double *x, const double *q, const double *dv,
+                        double *qout, int64_t n, double dt)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double dx = x[i + 1] - x[i];
+        double fl = dv[i] * face_state(x, q, n, i, dv[i], dt);
+        int64_t r = wrap(i + 1, n);
+        double fr = dv[r] * face_state(x, q, n, r, dv[r], dt);
+        /* M'' = M - dt (F_{i+1/2} - F_{i-1/2}), divided by dx (Eq. step3);
+         * written on Q so that dv = 0 is an exact identity */
+        qout[i] = q[i] - dt * (fr - fl) / dx;
+    }
+    return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* adjoints (scatter form)                                                  */
+/* ---------------------------------------------------------------------- */
+
+/* Transpose of the bulk shift at fixed s, plus s-bar.  qbar_in is overwritten.
+ * q is the forward input (only used for the v0 derivative). */
+static int shift_adjoint_row(const double *x, const double *q,
+                             const double *qbar_out, double *qbar_in, int64_t n,
+                             double s, int p, double *sbar)
+{
+    int lo = (p - 1) / 2;
+    double len = x[n] - x[0];
+    edge_t *ed = (edge_t *)malloc(sizeof(edge_t) * (size_t)(n + 1));
+    double *mbar = (double *)calloc((size_t)n, sizeof(double));
+    double *vbar = (double *)calloc((size_t)(n + 1), sizeof(double));
+    if (!ed || !mbar || !vbar) { free(ed); free(mbar); free(vbar); return -6; }
+    for (int64_t e = 0; e < n; ++e) edge_eval(x, q, n, s, p, e, sbar != NULL, &ed[e]);
+    ed[n] = ed[0];
+    ed[n].k += 1;
+    ed[n].g += n;
+    /* M'_i = whole_i + ell_{i+1} - ell_i */
+    for (int64_t i = 0; i < n; ++i) {
+        double mb = qbar_out[i] / (x[i + 1] - x[i]);
+        for (int64_t m = ed[i].g; m < ed[i + 1].g; ++m) mbar[wrap(m, n)] += mb;
+        vbar[i + 1] += mb;
+        vbar[i] -= mb;
+    }
+    /* node N shares node 0's partial integral */
+    vbar[0] += vbar[n];
+    double sb = 0.0;
+    for (int64_t e = 0; e < n; ++e) {
+        const edge_t *E = &ed[e];
+        double X[ORACLE_MAX_ORDER + 1];
+        for (int a = 0; a <= p; ++a) X[a] = node_x(x, n, len, E->c - lo + a);
+        for (int a = 0; a <= p; ++a) {
+            int64_t j = E->c - lo + a;
+            double w = lagrange_w(X, p, a, E->xh) * vbar[e];
+            /* D_a = C(j) - C(c) */
+            if (j > E->c)
+                for (int64_t m = E->c; m < j; ++m) mbar[wrap(m, n)] += w;
+            else
+                for (int64_t m = j; m < E->c; ++m) mbar[wrap(m, n)] -= w;
+        }
+        /* d ell / d s = -q~(xh) */
+        sb -= vbar[e] * E->dell;
+    }
+    for (int64_t m = 0; m < n; ++m) qbar_in[m] = mbar[m] * (x[m + 1] - x[m]);
+    if (sbar) *sbar = sb;
+    free(ed); free(mbar); free(vbar);
+    return 0;
+}
+
+/* Transpose of the Jacobian of the residual step at the forward state q.
+ * qbar_in is overwritten; dvbar is accumulated into when non-NULL. */
+static int residual_adjoint_row(const double *x, const double *q,
+                                const double *dv, const double *qbar_out,
+                                double *qbar_in, double *dvbar, int64_t n,
+                                double dt)
+{
+    double *sbar = (double *)calloc((size_t)n, sizeof(double));
+    if (!sbar) return -6;
+    for (int64_t i = 0; i < n; ++i) qbar_in[i] = qbar_out[i];
+    for (int64_t f = 0; f < n; ++f) {
+        int64_t fm = wrap(f - 1, n);
+        double v = dv[f];
+        /* F_f enters Q''_f with +dt/dx_f and Q''_{f-1} with -dt/dx_{f-1} */
+        double fbar = dt * (qbar_out[f] / (x[f + 1] - x[f])
+                            - qbar_out[fm] / (x[fm + 1] - x[fm]));
+        int64_t u = v >= 0.0 ? fm : f;
+        double dxu = x[u + 1] - x[u];
+        double sig = vl_slope(x, q, n, u);
+        double qs = face_state(x, q, n, f, v, dt);
+        if (dvbar) dvbar[f] += fbar * (qs - 0.5 * sig * v * dt);
+        double qsbar = fbar * v;
+        qbar_in[u] += qsbar;
+        sbar[u] += qsbar * 0.5 * (v >= 0.0 ? (dxu - v * dt) : -(dxu + v * dt));
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        if (sbar[i] == 0.0) continue;
+        double qm = q[wrap(i - 1, n)], q0 = q[i], qp = q[wrap(i + 1, n)];
+        double hp = centre_gap(x, n, i), hm = centre_gap(x, n, i - 1);
+        double a = (qp - q0) / hp, b = (q0 - qm) / hm;
+        if (a * b <= 0.0) continue;
+        double den = (a + b) * (a + b);
+        double abar = sbar[i] * 2.0 * b * b / den;
+        double bbar = sbar[i] * 2.0 * a * a / den;
+        qbar_in[wrap(i + 1, n)] += abar / hp;
+        qbar_in[i] -= abar / hp;
+        qbar_in[i] += bbar / hm;
+        qbar_in[wrap(i - 1, n)] -= bbar / hm;
+    }
+    free(sbar);
+    return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* batched entry points (rows are independent)                              */
+/* ---------------------------------------------------------------------- */
+
+static const double *row_mesh(const double *edges, int shared,
+                              const int64_t *row_ptr, int64_t r)
+{
+    return shared ? edges : edges + row_ptr[r] + r;
+}
+
+static void set_threads(int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+}
+
+int oracle_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+int oracle_shift(int64_t n_rows, const int64_t *row_ptr, const double *edges,
+                 int shared, const double *q, double *qout, const double *v0,
+                 double dt, int order, int variant, int nthreads)
+{
+    if (order < 1 || order > ORACLE_MAX_ORDER || (order % 2) == 0) return -2;
+    set_threads(nthreads);
+    int err = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
+    for (int64_t r = 0; r < n_rows; ++r) {
+        int64_t n = row_ptr[r + 1] - row_ptr[r];
+        if (n < order + 1) { err |= 1; continue; }
+        err |= shift_row(row_mesh(edges, shared, row_ptr, r), q + row_ptr[r],
+                         qout + row_ptr[r], n, v0[r] * dt, order, variant) != 0;
+    }
+    return err ? -1 : 0;
+}
+
+int oracle_residual(int64_t n_rows, const int64_t *row_ptr, const double *edges,
+                    int shared, const double *q, double *qout, const double *dv,
+                    double dt, int nthreads)
+{
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t r = 0; r < n_rows; ++r) {
+        int64_t n = row_ptr[r + 1] - row_ptr[r];
+        residual_row(row_mesh(edges, shared, row_ptr, r), q + row_ptr[r],
+                     dv + row_ptr[r], qout + row_ptr[r], n, dt);
+    }
+    return 0;
+}
+
+/* n_steps of (shift, then residual when dv != NULL); q is updated in place. */
+int oracle_step(int64_t n_rows, const int64_t *row_ptr, const double *edges,
+                int shared, double *q, const double *v0, const double *dv,
+                double dt, int order, int64_t n_steps, int nthreads)
+{
+    if (order < 1 || order > ORACLE_MAX_ORDER || (order % 2) == 0) return -2;
+    set_threads(nthreads);
+    int err = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
+    for (int64_t r = 0; r < n_rows; ++r) {
+        int64_t n = row_ptr[r + 1] - row_ptr[r];
+        const double *x = row_mesh(edges, shared, row_ptr, r);
+        double *qr = q + row_ptr[r];
+        double *tmp = (double *)malloc(sizeof(double) * (size_t)n);
+        if (!tmp || n < order + 1) { err |= 1; free(tmp); continue; }
+        for (int64_t st = 0; st < n_steps; ++st) {
+            shift_row(x, qr, tmp, n, v0[r] * dt, order, 0);
+            if (dv) residual_row(x, tmp, dv + row_ptr[r], qr, n, dt);
+            else memcpy(qr, tmp, sizeof(double) * (size_t)n);
+        }
+        free(tmp);
+    }
+    return err ? -1 : 0;
+}
+
+/* v0bar (per row) is accumulated with dt * s-bar when non-NULL. */
+int oracle_shift_adjoint(int64_t n_rows, const int64_t *row_ptr,
+                         const double *edges, int shared, const double *q,
+                         const double *qbar_out, double *qbar_in,
+                         const double *v0, double dt, int order, double *v0bar,
+                         int nthreads)
+{
+    if (order < 1 || order > ORACLE_MAX_ORDER || (order % 2) == 0) return -2;
+    set_threads(nthreads);
+    int err = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
+    for (int64_t r = 0; r < n_rows; ++r) {
+        int64_t n = row_ptr[r + 1] - row_ptr[r];
+        double sb = 0.0;
+        err |= shift_adjoint_row(row_mesh(edges, shared, row_ptr, r),
+                                 q + row_ptr[r], qbar_out + row_ptr[r],
+                                 qbar_in + row_ptr[r], n, v0[r] * dt, order,
+                                 v0bar ? &sb : NULL) != 0;
+        if (v0bar) v0bar[r] += dt * sb;
+    }
+    return err ? -1 : 0;
+}
+
+int oracle_residual_adjoint(int64_t n_rows, const int64_t *row_ptr,
+                            const double *edges, int shared, const double *q,
+                            const double *dv, const double *qbar_out,
+                            double *qbar_in, double *dvbar, double dt,
+                            int nthreads)
+{
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t r = 0; r < n_rows; ++r) {
+        int64_t n = row_ptr[r + 1] - row_ptr[r];
+        residual_adjoint_row(row_mesh(edges, shared, row_ptr, r), q + row_ptr[r],
+                             dv + row_ptr[r], qbar_out + row_ptr[r],
+                             qbar_in + row_ptr[r],
+                             dvbar ? dvbar + row_ptr[r] : NULL, n, dt);
+    }
+    return 0;
+}
+
+/* Per-edge diagnostics of one row (tests): xh, k, c, ell for e = 0..N-1. */
+int oracle_edges(const double *x, const double *q, int64_t n, double s,
+                 int order, double *xh, int64_t *k, int64_t *c, double *ell,
+                 double *dell)
+{
+    for (int64_t e = 0; e < n; ++e) {
+        edge_t E;
+        edge_eval(x, q, n, s, order, e, 1, &E);
+        xh[e] = E.xh; k[e] = E.k; c[e] = E.c; ell[e] = E.ell; dell[e] = E.dell;
+    }
+    return 0;
+}
