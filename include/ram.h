@@ -1,0 +1,155 @@
+/*
+ * ram.h -- C ABI of the RAM advection library for AMD MI355X (gfx950).
+ *
+ * RAM (Rapid Advection Algorithm on Arbitrary Meshes) solves the advection
+ * equation  dQ/dt + d(Q v)/dx = 0  with  v = v0 + dv  by operator splitting
+ * (paper Section 1, Eqs. advection_bulk, splitting_first, splitting_second):
+ * first an exact shift of every periodic row by s = v0*dt, evaluated as a
+ * conservative remap of a piecewise reconstruction (Section 3, Steps 1-3), then
+ * a standard upwind step for the residual velocity dv.
+ *
+ * Data model (paper Section 2):
+ *   row      one periodic 1D line of N cells bounded by N+1 strictly increasing
+ *            nodes x[0..N]; node N is identified with node 0 of the next
+ *            period (period L = x[N] - x[0]).
+ *   Q        cell averages (Eq. cellaverage_assumption), row-major, rows back
+ *            to back.  FP64 or FP32 (ram_dtype).
+ *   edges    node coordinates, always FP64: either one array x[0..n_cols]
+ *            shared by all rows, or every row's N_r+1 nodes concatenated (row r
+ *            at offset row_ptr[r] + r).
+ *   v0       bulk velocity per row, FP64 [n_rows] (constant along the row,
+ *            Section 1).
+ *   dv       residual velocity on faces, same shape and dtype as Q: entry i of
+ *            a row is the face between cells i-1 and i (periodic).
+ *
+ * Conventions
+ *   * Every array pointer is a DEVICE pointer owned by the caller, except where
+ *     a parameter says "host".  The library never frees caller memory.
+ *   * Calls are asynchronous on the context's stream (ram_set_stream); errors
+ *     detected on the host are returned before anything is launched, device
+ *     launch errors map to RAM_E_HIP.  ram_sync waits for the stream.
+ *   * Nothing throws across the ABI.  ram_last_error returns a detail message
+ *     for the calling thread's most recent failure.
+ *   * order (the degree p of the cumulative interpolant) must be 1, 3 or 5;
+ *     every row needs N_r >= order + 1 cells.
+ *   * Input and output arrays of one call must not alias.
+ */
+#ifndef RAM_H
+#define RAM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RAM_OK = 0,
+    RAM_E_INVALID_ARG = -1,  /* null pointer, bad size, bad dt, aliasing      */
+    RAM_E_UNSUPPORTED = -2,  /* order not in {1,3,5}, dtype/scan combination  */
+    RAM_E_MESH = -3,         /* non-monotone or non-finite nodes (validate)    */
+    RAM_E_CFL = -4,          /* |dv| dt exceeds an adjacent cell (validate)     */
+    RAM_E_HIP = -5,          /* a HIP runtime call failed                       */
+    RAM_E_NOMEM = -6         /* device scratch allocation failed                */
+} ram_status;
+
+typedef enum { RAM_F64 = 0, RAM_F32 = 1 } ram_dtype;
+
+/* Precision of the cumulative (prefix-sum) and its differences in the shift.
+ * FP64 state requires RAM_SCAN_F64. */
+typedef enum {
+    RAM_SCAN_F64 = 0,         /* FP64 prefix sums                              */
+    RAM_SCAN_F32_TWOSUM = 1,  /* compensated FP32 prefix (hi, lo) pairs        */
+    RAM_SCAN_F32 = 2          /* plain FP32 prefix (shows the cancellation)    */
+} ram_scan;
+
+typedef struct {
+    int64_t n_rows;           /* number of rows (>= 1)                          */
+    int64_t n_cols;           /* > 0: every row has n_cols cells; 0: ragged     */
+    const int64_t *row_ptr;   /* ragged: device, n_rows+1 cell offsets; else NULL */
+    int64_t n_cells;          /* ragged: total cells, = row_ptr[n_rows] (host)  */
+    int32_t edges_shared;     /* 1: one edges[n_cols+1] for every row (n_cols>0) */
+} ram_layout;
+
+typedef struct ram_ctx ram_ctx;
+
+/* Create a context on HIP device `device`, issuing work on `stream` (a
+ * hipStream_t; NULL = the null stream).  The context owns device scratch that
+ * it grows on demand.  Returns RAM_E_HIP if the device cannot be selected. */
+ram_status ram_create(ram_ctx **ctx, int device, void *stream);
+/* Release the context and its scratch (after waiting for its stream). */
+ram_status ram_destroy(ram_ctx *ctx);
+/* Change the stream later calls are issued on. */
+ram_status ram_set_stream(ram_ctx *ctx, void *stream);
+/* Wait until every call issued so far on the context's stream has finished;
+ * reports asynchronous device errors as RAM_E_HIP. */
+ram_status ram_sync(ram_ctx *ctx);
+
+/* Bulk shift (paper Section 3, Steps 1-3; Eqs. Qmass_i, mass_advected,
+ * condition_p, mass_shift_algo, step3): q_out = Q(x - v0[r]*dt) as the exact
+ * conservative remap of the piecewise reconstruction whose cumulative is the
+ * degree-`order` Lagrange interpolant of the node cumulative C_j = sum_{m<j}
+ * Q_m dx_m.  dt and v0 may have any sign and size (the remap is unbounded,
+ * Section 3.2).  q_in and q_out: `dtype`, n_cells each, must not alias. */
+ram_status ram_shift(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
+                     ram_scan scan, const void *q_in, void *q_out,
+                     const double *edges, const double *v0, double dt,
+                     int order);
+
+/* Residual upwind step (paper Eq. splitting_second): finite-volume update with
+ * the PLM reconstruction and van Leer harmonic slope of Section 3.1; the face
+ * value is the upwind profile averaged over the swept interval.  dv: faces, same
+ * shape and dtype as q.  Requires |dv_f| dt <= the adjacent cell sizes for
+ * stability (ram_validate checks it; this call does not). */
+ram_status ram_residual(ram_ctx *ctx, const ram_layout *layout,
+                        ram_dtype dtype, const void *q_in, void *q_out,
+                        const double *edges, const void *dv, double dt);
+
+/* n_steps operator-split steps (paper Section 1): shift, then residual; q is
+ * updated in place (the context's scratch holds the intermediate state).
+ * dv == NULL means dv = 0 (shift only). */
+ram_status ram_step(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
+                    ram_scan scan, void *q, const double *edges,
+                    const double *v0, const void *dv, double dt, int order,
+                    int64_t n_steps);
+
+/* Adjoint of ram_shift (the shift is linear in Q): qbar_in = S^T qbar_out,
+ * overwritten.  When v0bar_accum != NULL, also accumulates per row
+ *   v0bar_accum[r] += dt * d<qbar_out, S(s) q_fwd>/ds  at s = v0[r] dt,
+ * which needs the forward input q_fwd (else q_fwd may be NULL). */
+ram_status ram_shift_adjoint(ram_ctx *ctx, const ram_layout *layout,
+                             ram_dtype dtype, ram_scan scan,
+                             const void *q_fwd, const void *qbar_out,
+                             void *qbar_in, const double *edges,
+                             const double *v0, double dt, int order,
+                             double *v0bar_accum);
+
+/* Adjoint of ram_residual at the forward state q_fwd (the state the residual
+ * step read): qbar_in = J_q^T qbar_out (overwritten); when dvbar_accum != NULL
+ * it accumulates J_dv^T qbar_out (same dtype as q).  At the limiter's kink the
+ * slope derivative is taken as zero and at dv = 0 the dv >= 0 branch is used. */
+ram_status ram_residual_adjoint(ram_ctx *ctx, const ram_layout *layout,
+                                ram_dtype dtype, const void *q_fwd,
+                                const void *dv, const void *qbar_out,
+                                void *qbar_in, const double *edges, double dt,
+                                void *dvbar_accum);
+
+/* Host-side check of the inputs (synchronous; copies to the host): strictly
+ * increasing finite nodes (RAM_E_MESH), and when dv != NULL the residual
+ * Courant condition |dv_f| dt <= min(dx_{f-1}, dx_f) (RAM_E_CFL). */
+ram_status ram_validate(ram_ctx *ctx, const ram_layout *layout,
+                        ram_dtype dtype, const double *edges, const void *dv,
+                        double dt);
+
+/* Static description of a status code. */
+const char *ram_status_string(ram_status status);
+/* Detail of the calling thread's last failure ("" when none). */
+const char *ram_last_error(void);
+/* Library version string. */
+const char *ram_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RAM_H */

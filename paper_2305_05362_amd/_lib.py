@@ -1,0 +1,283 @@
+"""ctypes binding of libram.so (the C ABI declared in include/ram.h).
+
+Argument marshalling only: every step of the advection path runs in the HIP
+kernels of libram.so.  PyTorch supplies device memory (tensors) and the
+stream; the library never sees a torch type.  If the library is missing the
+import fails loudly -- there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libram.so")
+
+RAM_OK = 0
+RAM_E_INVALID_ARG = -1
+RAM_E_UNSUPPORTED = -2
+RAM_E_MESH = -3
+RAM_E_CFL = -4
+RAM_E_HIP = -5
+RAM_E_NOMEM = -6
+
+RAM_F64 = 0
+RAM_F32 = 1
+
+RAM_SCAN_F64 = 0
+RAM_SCAN_F32_TWOSUM = 1
+RAM_SCAN_F32 = 2
+
+SCANS = {"f64": RAM_SCAN_F64, "twosum": RAM_SCAN_F32_TWOSUM, "f32": RAM_SCAN_F32}
+
+
+class RamError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"RAM error {status}: {message}")
+        self.status = status
+
+
+class Layout(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int64), ("n_cols", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("n_cells", ctypes.c_int64),
+                ("edges_shared", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libram.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(
+            f"{path} is missing: build it with `python -m paper_2305_05362_amd.build` "
+            "(the RAM path has no non-HIP implementation)")
+    lib = ctypes.CDLL(path)
+    P, D, I, I64 = ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_int64
+    LP = ctypes.POINTER(Layout)
+    sig = {
+        "ram_create": [ctypes.POINTER(ctypes.c_void_p), I, P],
+        "ram_destroy": [P],
+        "ram_set_stream": [P, P],
+        "ram_sync": [P],
+        "ram_shift": [P, LP, I, I, P, P, P, P, D, I],
+        "ram_residual": [P, LP, I, P, P, P, P, D],
+        "ram_step": [P, LP, I, I, P, P, P, P, D, I, I64],
+        "ram_shift_adjoint": [P, LP, I, I, P, P, P, P, P, D, I, P],
+        "ram_residual_adjoint": [P, LP, I, P, P, P, P, P, D, P],
+        "ram_validate": [P, LP, I, P, P, D],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.ram_status_string.argtypes = [ctypes.c_int]
+    lib.ram_status_string.restype = ctypes.c_char_p
+    lib.ram_last_error.argtypes = []
+    lib.ram_last_error.restype = ctypes.c_char_p
+    lib.ram_version.argtypes = []
+    lib.ram_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def check(status: int):
+    if status != RAM_OK:
+        lib = load_library()
+        msg = lib.ram_last_error().decode() or lib.ram_status_string(status).decode()
+        raise RamError(status, msg)
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float64:
+        return RAM_F64
+    if t.dtype == torch.float32:
+        return RAM_F32
+    raise TypeError(f"state must be float64 or float32, got {t.dtype}")
+
+
+def _dev_ptr(t: Optional[torch.Tensor], dtype=None, name="tensor"):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    return t.data_ptr()
+
+
+class Rows:
+    """Device-side row geometry: node coordinates (FP64) and, for ragged
+    batches, the cell offsets ``row_ptr`` (int64, n_rows+1)."""
+
+    def __init__(self, edges: torch.Tensor, n_rows: int, n_cols: int = 0,
+                 row_ptr: Optional[torch.Tensor] = None, shared: bool = False,
+                 n_cells: Optional[int] = None):
+        self.edges = edges
+        self.row_ptr = row_ptr
+        self.n_rows = int(n_rows)
+        self.n_cols = int(n_cols)
+        self.shared = bool(shared)
+        if self.n_cols > 0:
+            self.n_cells = self.n_rows * self.n_cols
+        else:
+            if row_ptr is None:
+                raise ValueError("ragged rows need row_ptr")
+            self.n_cells = int(n_cells) if n_cells is not None else int(row_ptr[-1].item())
+        _dev_ptr(edges, torch.float64, "edges")
+        if row_ptr is not None:
+            _dev_ptr(row_ptr, torch.int64, "row_ptr")
+        self.layout = Layout(self.n_rows, self.n_cols,
+                             row_ptr.data_ptr() if (row_ptr is not None and self.n_cols == 0) else None,
+                             self.n_cells, 1 if self.shared else 0)
+
+    @classmethod
+    def from_workload(cls, wl, device="cuda") -> "Rows":
+        edges = torch.as_tensor(wl.edges, dtype=torch.float64, device=device)
+        if wl.n_cols > 0:
+            return cls(edges, wl.n_rows, wl.n_cols, None, wl.edges_shared)
+        rp = torch.as_tensor(wl.row_ptr, dtype=torch.int64, device=device)
+        return cls(edges, wl.n_rows, 0, rp, False, int(wl.row_ptr[-1]))
+
+
+class Context:
+    """One ram_ctx on a device; calls go to torch's current stream."""
+
+    def __init__(self, device: Optional[int] = None):
+        lib = load_library()
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = int(device)
+        self._lib = lib
+        h = ctypes.c_void_p()
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        check(lib.ram_create(ctypes.byref(h), self.device, ctypes.c_void_p(stream)))
+        self._h = h
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None) and self._h.value:
+                self._lib.ram_destroy(self._h)
+        except Exception:
+            pass
+
+    def _stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        check(self._lib.ram_set_stream(self._h, ctypes.c_void_p(s)))
+
+    def sync(self):
+        check(self._lib.ram_sync(self._h))
+
+    # -- the C ABI, one method per entry point ---------------------------
+    def ram_shift(self, rows: Rows, q_in, q_out, v0, dt: float, order: int,
+                  scan: int = RAM_SCAN_F64):
+        self._stream()
+        dt_code = _dtype_code(q_in)
+        check(self._lib.ram_shift(
+            self._h, ctypes.byref(rows.layout), dt_code, int(scan),
+            _dev_ptr(q_in, q_in.dtype, "q_in"), _dev_ptr(q_out, q_in.dtype, "q_out"),
+            _dev_ptr(rows.edges, torch.float64, "edges"),
+            _dev_ptr(v0, torch.float64, "v0"), float(dt), int(order)))
+        return q_out
+
+    def ram_residual(self, rows: Rows, q_in, q_out, dv, dt: float):
+        self._stream()
+        check(self._lib.ram_residual(
+            self._h, ctypes.byref(rows.layout), _dtype_code(q_in),
+            _dev_ptr(q_in, q_in.dtype, "q_in"), _dev_ptr(q_out, q_in.dtype, "q_out"),
+            _dev_ptr(rows.edges, torch.float64, "edges"),
+            _dev_ptr(dv, q_in.dtype, "dv"), float(dt)))
+        return q_out
+
+    def ram_step(self, rows: Rows, q, v0, dv, dt: float, order: int,
+                 n_steps: int, scan: int = RAM_SCAN_F64):
+        self._stream()
+        check(self._lib.ram_step(
+            self._h, ctypes.byref(rows.layout), _dtype_code(q), int(scan),
+            _dev_ptr(q, q.dtype, "q"), _dev_ptr(rows.edges, torch.float64, "edges"),
+            _dev_ptr(v0, torch.float64, "v0"), _dev_ptr(dv, q.dtype, "dv"),
+            float(dt), int(order), int(n_steps)))
+        return q
+
+    def ram_shift_adjoint(self, rows: Rows, q_fwd, qbar_out, qbar_in, v0,
+                          dt: float, order: int, v0bar=None,
+                          scan: int = RAM_SCAN_F64):
+        self._stream()
+        check(self._lib.ram_shift_adjoint(
+            self._h, ctypes.byref(rows.layout), _dtype_code(qbar_out), int(scan),
+            _dev_ptr(q_fwd, qbar_out.dtype, "q_fwd"),
+            _dev_ptr(qbar_out, qbar_out.dtype, "qbar_out"),
+            _dev_ptr(qbar_in, qbar_out.dtype, "qbar_in"),
+            _dev_ptr(rows.edges, torch.float64, "edges"),
+            _dev_ptr(v0, torch.float64, "v0"), float(dt), int(order),
+            _dev_ptr(v0bar, torch.float64, "v0bar")))
+        return qbar_in
+
+    def ram_residual_adjoint(self, rows: Rows, q_fwd, dv, qbar_out, qbar_in,
+                             dt: float, dvbar=None):
+        self._stream()
+        check(self._lib.ram_residual_adjoint(
+            self._h, ctypes.byref(rows.layout), _dtype_code(q_fwd),
+            _dev_ptr(q_fwd, q_fwd.dtype, "q_fwd"), _dev_ptr(dv, q_fwd.dtype, "dv"),
+            _dev_ptr(qbar_out, q_fwd.dtype, "qbar_out"),
+            _dev_ptr(qbar_in, q_fwd.dtype, "qbar_in"),
+            _dev_ptr(rows.edges, torch.float64, "edges"), float(dt),
+            _dev_ptr(dvbar, q_fwd.dtype, "dvbar")))
+        return qbar_in
+
+    def ram_validate(self, rows: Rows, dtype, dv=None, dt: float = 0.0):
+        self._stream()
+        code = RAM_F64 if dtype == torch.float64 else RAM_F32
+        check(self._lib.ram_validate(
+            self._h, ctypes.byref(rows.layout), code,
+            _dev_ptr(rows.edges, torch.float64, "edges"),
+            None if dv is None else _dev_ptr(dv, dv.dtype, "dv"), float(dt)))
+
+
+_contexts = {}
+
+
+def context(device: Optional[int] = None) -> Context:
+    """The per-device default context."""
+    if device is None:
+        device = torch.cuda.current_device()
+    ctx = _contexts.get(device)
+    if ctx is None:
+        ctx = Context(device)
+        _contexts[device] = ctx
+    return ctx
+
+
+def ram_shift(rows, q_in, q_out, v0, dt, order, scan=RAM_SCAN_F64):
+    return context(q_in.device.index).ram_shift(rows, q_in, q_out, v0, dt, order, scan)
+
+
+def ram_residual(rows, q_in, q_out, dv, dt):
+    return context(q_in.device.index).ram_residual(rows, q_in, q_out, dv, dt)
+
+
+def ram_step(rows, q, v0, dv, dt, order, n_steps, scan=RAM_SCAN_F64):
+    return context(q.device.index).ram_step(rows, q, v0, dv, dt, order, n_steps, scan)
+
+
+def ram_shift_adjoint(rows, q_fwd, qbar_out, qbar_in, v0, dt, order,
+                      v0bar=None, scan=RAM_SCAN_F64):
+    return context(qbar_out.device.index).ram_shift_adjoint(
+        rows, q_fwd, qbar_out, qbar_in, v0, dt, order, v0bar, scan)
+
+
+def ram_residual_adjoint(rows, q_fwd, dv, qbar_out, qbar_in, dt, dvbar=None):
+    return context(q_fwd.device.index).ram_residual_adjoint(
+        rows, q_fwd, dv, qbar_out, qbar_in, dt, dvbar)
+
+
+def ram_validate(rows, dtype, dv=None, dt=0.0):
+    return context(rows.edges.device.index).ram_validate(rows, dtype, dv, dt)

@@ -1,0 +1,338 @@
+// ram_adjoint.hip -- adjoint kernels of the RAM step for gfx950.
+//
+// The bulk shift is linear in Q: with V_e the interpolated cumulative at the
+// shifted node e and M'_i = V_{i+1} - V_i, its transpose is, per source cell m,
+//     Mbar_m = sum_e Vbar_e H_e(m),   Vbar_e = Mbar'_{e-1} - Mbar'_e,
+// where H_e(m) is the weight of M_m in V_e: 1 below the interpolation stencil,
+// a suffix sum of the Lagrange weights inside it, 0 above it.  Per destination
+// tile the sum telescopes to one Mbar' value plus the few stencils that
+// straddle m, so each source cell of the tile's window is a short gather.
+// Window cells shared with the neighbouring tiles (the P cells of the stencil
+// of each tile-boundary node) are accumulated with atomics after a zeroing
+// pass; every other cell is written once.
+//
+// The derivative with respect to v0 enters through x~ = x - v0 dt:
+//     dM'_i/ds = -(q~(x~_{i+1}) - q~(x~_i)),
+// with q~ the reconstruction (derivative of the interpolated cumulative).
+//
+// The residual adjoint is a gather over the two-cell halo: face fluxes,
+// upwind face states and van Leer slopes are transposed cell by cell; the
+// limiter's derivative is taken as zero where the one-sided slopes do not
+// have the same sign, and dv = 0 uses the dv >= 0 branch.
+#include "ram_device.h"
+
+namespace ram {
+namespace {
+
+using namespace dev;
+
+// Derivatives of the Lagrange basis at xh.
+template <int P>
+__device__ inline void lagrange_dweights(double xh, const double *X, double *dw)
+{
+    double t[P + 1];
+#pragma unroll
+    for (int a = 0; a <= P; ++a) t[a] = xh - X[a];
+#pragma unroll
+    for (int a = 0; a <= P; ++a) {
+        double den = 1.0;
+#pragma unroll
+        for (int b = 0; b <= P; ++b)
+            if (b != a) den *= X[a] - X[b];
+        double sum = 0.0;
+#pragma unroll
+        for (int b = 0; b <= P; ++b) {
+            if (b == a) continue;
+            double prod = 1.0;
+#pragma unroll
+            for (int c = 0; c <= P; ++c)
+                if (c != a && c != b) prod *= t[c];
+            sum += prod;
+        }
+        dw[a] = sum / den;
+    }
+}
+
+template <typename TQ>
+__device__ inline double mass_at(const double *x, const TQ *q, int n, int64_t m)
+{
+    const int w = wrapi(m, n);
+    return (double)q[w] * (x[w + 1] - x[w]);
+}
+
+// Shifted node e of a row (node N = node 0 of the next period): g = c + k N.
+__device__ inline int64_t locate(const double *x, int n, double s, int e,
+                                 double &xh)
+{
+    int64_t k;
+    if (e == n) {
+        shifted_node(x, n, s, 0, xh, k);
+        k += 1;
+    } else {
+        shifted_node(x, n, s, e, xh, k);
+    }
+    return (int64_t)find_cell(x, n, xh) + k * (int64_t)n;
+}
+
+// Zero the P window cells that start at each tile's first shifted node: the
+// only cells that more than one tile accumulates into.
+template <typename TQ, int P>
+__global__ __launch_bounds__(kBlock) void k_shift_adj_zero(ShiftAdjArgs a)
+{
+    constexpr int LO = (P - 1) / 2;
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= a.rows.n_tiles) return;
+    Tile ti;
+    if (!get_tile(a.rows, t, ti)) return;
+    const int n = ti.n;
+    if (n < P + 1) return;
+    const double s = a.v0[ti.row] * a.dt;
+    double xh;
+    const int64_t g0 = locate(ti.x, n, s, ti.i0, xh);
+    TQ *qbi = (TQ *)a.qbar_in + ti.qoff;
+    for (int b = 0; b < P; ++b) qbi[wrapi(g0 - LO + b, n)] = (TQ)0;
+}
+
+template <typename TQ, int P>
+__global__ __launch_bounds__(kBlock) void k_shift_adj(ShiftAdjArgs a)
+{
+    constexpr int LO = (P - 1) / 2;
+    __shared__ int64_t sg[kTile + 1];
+    __shared__ double svb[kTile + 1];     // tile-local Vbar of each node
+    __shared__ double shs[kTile + 1][P];  // suffix sums of the weights
+    __shared__ double sred[kBlock / 64];
+
+    Tile ti;
+    if (!get_tile(a.rows, blockIdx.x, ti)) return;
+    const int n = ti.n;
+    if (n < P + 1) return;
+    const double *x = ti.x;
+    const TQ *qbo = (const TQ *)a.qbar_out + ti.qoff;
+    TQ *qbi = (TQ *)a.qbar_in + ti.qoff;
+    const TQ *qf = a.q_fwd ? (const TQ *)a.q_fwd + ti.qoff : nullptr;
+    const double s = a.v0[ti.row] * a.dt;
+    const double len = x[n] - x[0];
+    const int i0 = ti.i0;
+    const int nd = min(kTile, n - i0);
+    const int ne = nd + 1;
+    const bool want_v0 = a.v0bar != nullptr && qf != nullptr;
+
+    double vpart = 0.0;
+    for (int t = threadIdx.x; t < ne; t += kBlock) {
+        double xh;
+        const int64_t g = locate(x, n, s, i0 + t, xh);
+        const int c = wrapi(g, n);
+        double X[P + 1], w[P + 1];
+#pragma unroll
+        for (int b = 0; b <= P; ++b) X[b] = node_x(x, n, len, c - LO + b);
+        lagrange_weights<P>(xh, X, w);
+        double acc = 0.0;
+#pragma unroll
+        for (int b = P; b >= 1; --b) {
+            acc += w[b];
+            shs[t][b - 1] = acc;
+        }
+        double vb = 0.0;
+        if (t >= 1) {
+            const int i = i0 + t - 1;
+            vb += (double)qbo[i] / (x[i + 1] - x[i]);
+        }
+        if (t <= nd - 1) {
+            const int i = i0 + t;
+            vb -= (double)qbo[i] / (x[i + 1] - x[i]);
+        }
+        svb[t] = vb;
+        sg[t] = g;
+        if (want_v0) {
+            double dw[P + 1];
+            lagrange_dweights<P>(xh, X, dw);
+            double dq = 0.0;
+#pragma unroll
+            for (int b = 0; b <= P; ++b) {
+                const int j = c - LO + b;
+                double d = 0.0;
+                if (j > c) {
+                    for (int m = c; m < j; ++m) d += mass_at(x, qf, n, m);
+                } else if (j < c) {
+                    for (int m = j; m < c; ++m) d += mass_at(x, qf, n, m);
+                    d = -d;
+                }
+                dq += dw[b] * d;
+            }
+            vpart -= vb * dq;
+        }
+    }
+    if (want_v0) {
+        for (int d = 32; d >= 1; d >>= 1) vpart += __shfl_xor(vpart, d);
+        if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = vpart;
+    }
+    __syncthreads();
+    if (want_v0 && threadIdx.x == 0) {
+        double tot = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) tot += sred[w];
+        atomicAdd(&a.v0bar[ti.row], a.dt * tot);
+    }
+
+    const int64_t wlo = sg[0] - LO;
+    const int W = (int)(sg[nd] - sg[0] + P);
+    const int base = wrapi(wlo, n);
+    for (int j = threadIdx.x; j < W; j += kBlock) {
+        const int64_t target = wlo + j + LO;
+        // first tile node whose stencil lies wholly above cell j
+        int lo = 0, hi = ne;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (sg[mid] > target) hi = mid; else lo = mid + 1;
+        }
+        double S = (lo >= 1 && lo <= nd)
+                       ? (double)qbo[i0 + lo - 1] / (x[i0 + lo] - x[i0 + lo - 1])
+                       : 0.0;
+        for (int t = lo - 1; t >= 0 && sg[t] > target - P; --t) {
+            const int b = (int)min((int64_t)(P - 1), max((int64_t)0, target - sg[t]));
+            S += svb[t] * shs[t][b];
+        }
+        const int mm = (base + j) % n;
+        const double val = S * (x[mm + 1] - x[mm]);
+        if (j >= P && j < W - P)
+            qbi[mm] = (TQ)val;
+        else
+            atomicAdd(&qbi[mm], (TQ)val);
+    }
+}
+
+template <typename TQ>
+__global__ __launch_bounds__(kBlock) void k_residual_adj(ResidualAdjArgs a)
+{
+    __shared__ double sq[kTile + 4];    // forward state, cells i0-2 .. i0+nd+1
+    __shared__ double sb[kTile + 4];    // qbar_out, same cells
+    __shared__ double sda[kTile + 2];   // dsigma/da / h+, cells i0-1 .. i0+nd
+    __shared__ double sdb[kTile + 2];   // dsigma/db / h-
+    __shared__ double sqsb[kTile + 3];  // face-state adjoint, faces i0-1 .. i0+nd+1
+    __shared__ double ssc[kTile + 3];   // slope adjoint each face sends upwind
+    __shared__ float sup[kTile + 3];    // 1 if the face's upwind cell is its left
+
+    Tile ti;
+    if (!get_tile(a.rows, blockIdx.x, ti)) return;
+    const int n = ti.n;
+    const double *x = ti.x;
+    const TQ *q = (const TQ *)a.q_fwd + ti.qoff;
+    const TQ *dv = (const TQ *)a.dv + ti.qoff;
+    const TQ *qbo = (const TQ *)a.qbar_out + ti.qoff;
+    TQ *qbi = (TQ *)a.qbar_in + ti.qoff;
+    TQ *dvb = a.dvbar ? (TQ *)a.dvbar + ti.qoff : nullptr;
+    const double dt = a.dt;
+    const double len = x[n] - x[0];
+    const int i0 = ti.i0;
+    const int nd = min(kTile, n - i0);
+
+    for (int t = threadIdx.x; t < nd + 4; t += kBlock) {
+        const int c = wrapi((int64_t)i0 - 2 + t, n);
+        sq[t] = (double)q[c];
+        sb[t] = (double)qbo[c];
+    }
+    __syncthreads();
+    // slopes' partial derivatives, cells i0-1+t
+    for (int t = threadIdx.x; t < nd + 2; t += kBlock) {
+        const int64_t i = (int64_t)i0 - 1 + t;
+        const double hp = centre_gap(x, n, len, i);
+        const double hm = centre_gap(x, n, len, i - 1);
+        const double ap = (sq[t + 2] - sq[t + 1]) / hp;
+        const double bm = (sq[t + 1] - sq[t]) / hm;
+        double da = 0.0, db = 0.0;
+        if (ap * bm > 0.0) {
+            const double den = (ap + bm) * (ap + bm);
+            da = 2.0 * bm * bm / den / hp;
+            db = 2.0 * ap * ap / den / hm;
+        }
+        sda[t] = da;
+        sdb[t] = db;
+    }
+    // faces i0-1+t: flux adjoint, face-state adjoint, slope adjoint sent upwind
+    for (int t = threadIdx.x; t < nd + 3; t += kBlock) {
+        const int64_t f = (int64_t)i0 - 1 + t;
+        const int fw = wrapi(f, n), fm = wrapi(f - 1, n);
+        const double v = (double)dv[fw];
+        // cells f and f-1 are sq/sb index t+1 and t
+        const double fbar = dt * (sb[t + 1] / (x[fw + 1] - x[fw]) -
+                                  sb[t] / (x[fm + 1] - x[fm]));
+        const double qsb = fbar * v;
+        const int u = v >= 0.0 ? fm : fw;
+        const double dxu = x[u + 1] - x[u];
+        sqsb[t] = qsb;
+        ssc[t] = qsb * 0.5 * (v >= 0.0 ? (dxu - v * dt) : -(dxu + v * dt));
+        sup[t] = v >= 0.0 ? 1.0f : 0.0f;
+        if (dvb && t >= 1 && t <= nd) {
+            // owned face i0+t-1; its upwind cell's slope from the forward state
+            const int su = v >= 0.0 ? t : t + 1;   // sq index of the upwind cell
+            const int64_t ui = (int64_t)i0 - 2 + su;
+            const double hp = centre_gap(x, n, len, ui);
+            const double hm = centre_gap(x, n, len, ui - 1);
+            const double dp = (sq[su + 1] - sq[su]) / hp;
+            const double dm = (sq[su] - sq[su - 1]) / hm;
+            const double sig = (dp * dm <= 0.0) ? 0.0 : 2.0 * dp * dm / (dp + dm);
+            const double qs = v >= 0.0 ? sq[su] + 0.5 * sig * (dxu - v * dt)
+                                       : sq[su] - 0.5 * sig * (dxu + v * dt);
+            dvb[fw] = (TQ)((double)dvb[fw] + fbar * (qs - 0.5 * sig * v * dt));
+        }
+    }
+    __syncthreads();
+    // cells: identity + face states + slopes of cells i-1, i, i+1
+    for (int t = threadIdx.x; t < nd; t += kBlock) {
+        // slope adjoint of cell i0-1+k gathered from its two faces (k, k+1)
+        auto sigbar = [&](int k) {
+            return (sup[k] == 0.0f ? ssc[k] : 0.0) + (sup[k + 1] != 0.0f ? ssc[k + 1] : 0.0);
+        };
+        const double sbm = sigbar(t), sb0 = sigbar(t + 1), sbp = sigbar(t + 2);
+        double g = sb[t + 2];
+        if (sup[t + 1] == 0.0f) g += sqsb[t + 1];   // face i, upwind = i
+        if (sup[t + 2] != 0.0f) g += sqsb[t + 2];   // face i+1, upwind = i
+        g += sbm * sda[t] + sb0 * (sdb[t + 1] - sda[t + 1]) - sbp * sdb[t + 2];
+        qbi[i0 + t] = (TQ)g;
+    }
+}
+
+template <typename TQ, int P>
+hipError_t shift_adj_order(const ShiftAdjArgs &a, hipStream_t st)
+{
+    const unsigned zgrid = (unsigned)((a.rows.n_tiles + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL((k_shift_adj_zero<TQ, P>), dim3(zgrid), dim3(kBlock), 0, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_shift_adj<TQ, P>), dim3((unsigned)a.rows.n_tiles),
+                       dim3(kBlock), 0, st, a);
+    return hipGetLastError();
+}
+
+template <typename TQ>
+hipError_t shift_adj_dispatch(const ShiftAdjArgs &a, int order, hipStream_t st)
+{
+    switch (order) {
+    case 1: return shift_adj_order<TQ, 1>(a, st);
+    case 3: return shift_adj_order<TQ, 3>(a, st);
+    default: return shift_adj_order<TQ, 5>(a, st);
+    }
+}
+
+} // namespace
+
+hipError_t launch_shift_adjoint(const ShiftAdjArgs &a, bool f64, int order,
+                                hipStream_t stream)
+{
+    if (a.rows.n_tiles <= 0) return hipSuccess;
+    if (f64) return shift_adj_dispatch<double>(a, order, stream);
+    return shift_adj_dispatch<float>(a, order, stream);
+}
+
+hipError_t launch_residual_adjoint(const ResidualAdjArgs &a, bool f64,
+                                   hipStream_t stream)
+{
+    if (a.rows.n_tiles <= 0) return hipSuccess;
+    const dim3 grid((unsigned)a.rows.n_tiles), block(kBlock);
+    if (f64)
+        hipLaunchKernelGGL(k_residual_adj<double>, grid, block, 0, stream, a);
+    else
+        hipLaunchKernelGGL(k_residual_adj<float>, grid, block, 0, stream, a);
+    return hipGetLastError();
+}
+
+} // namespace ram

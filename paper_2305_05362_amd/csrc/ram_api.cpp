@@ -1,0 +1,460 @@
+// ram_api.cpp -- C ABI of the RAM library (declared in include/ram.h): argument
+// checks, context and scratch management, dispatch to the HIP kernels.
+#include "ram.h"
+#include "ram_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+struct ram_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    void *scratch = nullptr;
+    size_t scratch_bytes = 0;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ram_status fail(ram_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+ram_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(RAM_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Select the context's device for the calling thread.  Every entry point
+// checks its arguments first (host logic only), then enters the context.
+ram_status enter(ram_ctx *ctx)
+{
+    if (!ctx) return fail(RAM_E_INVALID_ARG, "null context");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    return RAM_OK;
+}
+
+size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+ram_status ensure_scratch(ram_ctx *ctx, size_t bytes)
+{
+    if (bytes <= ctx->scratch_bytes) return RAM_OK;
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (ctx->scratch) (void)hipFree(ctx->scratch);
+    ctx->scratch = nullptr;
+    ctx->scratch_bytes = 0;
+    size_t want = align_up(bytes + bytes / 8);
+    e = hipMalloc(&ctx->scratch, want);
+    if (e != hipSuccess) {
+        ctx->scratch = nullptr;
+        return fail(RAM_E_NOMEM, "hipMalloc(%zu) for scratch: %s", want,
+                    hipGetErrorString(e));
+    }
+    ctx->scratch_bytes = want;
+    return RAM_OK;
+}
+
+size_t elem_size(ram_dtype dt) { return dt == RAM_F64 ? 8 : 4; }
+
+int64_t layout_cells(const ram_layout *L)
+{
+    return L->n_cols > 0 ? L->n_rows * L->n_cols : L->n_cells;
+}
+
+ram_status check_layout(const ram_layout *L, const double *edges)
+{
+    if (!L) return fail(RAM_E_INVALID_ARG, "null layout");
+    if (L->n_rows < 1) return fail(RAM_E_INVALID_ARG, "n_rows must be >= 1");
+    if (L->n_cols < 0) return fail(RAM_E_INVALID_ARG, "n_cols must be >= 0");
+    if (!edges) return fail(RAM_E_INVALID_ARG, "null edges");
+    if (L->n_cols == 0) {
+        if (!L->row_ptr) return fail(RAM_E_INVALID_ARG, "ragged layout needs row_ptr");
+        if (L->n_cells < 1) return fail(RAM_E_INVALID_ARG, "ragged layout needs n_cells >= 1");
+        if (L->edges_shared)
+            return fail(RAM_E_INVALID_ARG, "shared edges need uniform rows (n_cols > 0)");
+    }
+    if (L->n_cols > 0 && L->n_cols > INT32_MAX - 1)
+        return fail(RAM_E_INVALID_ARG, "rows longer than 2^31-2 cells");
+    return RAM_OK;
+}
+
+ram_status check_dtype(ram_dtype dt)
+{
+    if (dt != RAM_F64 && dt != RAM_F32)
+        return fail(RAM_E_UNSUPPORTED, "dtype must be RAM_F64 or RAM_F32");
+    return RAM_OK;
+}
+
+ram_status check_order(const ram_layout *L, int order)
+{
+    if (order != 1 && order != 3 && order != 5)
+        return fail(RAM_E_UNSUPPORTED, "order must be 1, 3 or 5 (got %d)", order);
+    if (L->n_cols > 0 && L->n_cols < order + 1)
+        return fail(RAM_E_INVALID_ARG, "rows need at least order+1 = %d cells", order + 1);
+    return RAM_OK;
+}
+
+ram_status check_scan(ram_dtype dt, ram_scan scan)
+{
+    if (scan != RAM_SCAN_F64 && scan != RAM_SCAN_F32_TWOSUM && scan != RAM_SCAN_F32)
+        return fail(RAM_E_UNSUPPORTED, "unknown scan precision %d", (int)scan);
+    if (dt == RAM_F64 && scan != RAM_SCAN_F64)
+        return fail(RAM_E_UNSUPPORTED, "FP64 state requires RAM_SCAN_F64");
+    return RAM_OK;
+}
+
+ram_status check_dt(double dt)
+{
+    if (!std::isfinite(dt)) return fail(RAM_E_INVALID_ARG, "dt must be finite");
+    return RAM_OK;
+}
+
+// Fill the kernel-side row description.  Ragged layouts get their tile table
+// built in scratch at byte offset `off` (advanced past what it uses).
+ram_status make_rows(ram_ctx *ctx, const ram_layout *L, const double *edges,
+                     size_t off, ram::Rows &R)
+{
+    R.n_rows = L->n_rows;
+    R.n_cols = L->n_cols;
+    R.edges = edges;
+    R.shared = L->edges_shared ? 1 : 0;
+    if (L->n_cols > 0) {
+        R.n_tiles = L->n_rows * ((L->n_cols + ram::kTile - 1) / ram::kTile);
+        return RAM_OK;
+    }
+    R.row_ptr = L->row_ptr;
+    R.n_tiles = ram::ragged_tile_bound(L->n_cells, L->n_rows);
+    char *base = (char *)ctx->scratch + off;
+    R.tile_ptr = (const int64_t *)base;
+    R.tile_row = (const int32_t *)(base + align_up(sizeof(int64_t) * (L->n_rows + 1)));
+    hipError_t e = ram::launch_tiles_prep(L->row_ptr, L->n_rows,
+                                          (int64_t *)R.tile_ptr,
+                                          (int32_t *)R.tile_row, ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "tile table launch");
+    return RAM_OK;
+}
+
+size_t rows_scratch(const ram_layout *L)
+{
+    if (L->n_cols > 0) return 0;
+    return align_up(sizeof(int64_t) * (L->n_rows + 1)) +
+           align_up(sizeof(int32_t) * ram::ragged_tile_bound(L->n_cells, L->n_rows));
+}
+
+} // namespace
+
+extern "C" {
+
+const char *ram_version(void) { return "ram-mi355x 0.1"; }
+
+const char *ram_last_error(void) { return g_last_error.c_str(); }
+
+const char *ram_status_string(ram_status s)
+{
+    switch (s) {
+    case RAM_OK: return "ok";
+    case RAM_E_INVALID_ARG: return "invalid argument";
+    case RAM_E_UNSUPPORTED: return "unsupported configuration";
+    case RAM_E_MESH: return "invalid mesh";
+    case RAM_E_CFL: return "residual Courant condition violated";
+    case RAM_E_HIP: return "HIP runtime error";
+    case RAM_E_NOMEM: return "out of device memory";
+    }
+    return "unknown status";
+}
+
+ram_status ram_create(ram_ctx **out, int device, void *stream)
+{
+    if (!out) return fail(RAM_E_INVALID_ARG, "null output pointer");
+    *out = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (device < 0 || device >= count)
+        return fail(RAM_E_INVALID_ARG, "device %d out of range (%d devices)", device, count);
+    e = hipSetDevice(device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    ram_ctx *ctx = new (std::nothrow) ram_ctx;
+    if (!ctx) return fail(RAM_E_NOMEM, "host allocation failed");
+    ctx->device = device;
+    ctx->stream = (hipStream_t)stream;
+    *out = ctx;
+    g_last_error.clear();
+    return RAM_OK;
+}
+
+ram_status ram_destroy(ram_ctx *ctx)
+{
+    if (!ctx) return RAM_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->scratch) (void)hipFree(ctx->scratch);
+    delete ctx;
+    return RAM_OK;
+}
+
+ram_status ram_set_stream(ram_ctx *ctx, void *stream)
+{
+    if (!ctx) return fail(RAM_E_INVALID_ARG, "null context");
+    ctx->stream = (hipStream_t)stream;
+    return RAM_OK;
+}
+
+ram_status ram_sync(ram_ctx *ctx)
+{
+    ram_status st = enter(ctx);
+    if (st != RAM_OK) return st;
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return RAM_OK;
+}
+
+ram_status ram_shift(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
+                     ram_scan scan, const void *q_in, void *q_out,
+                     const double *edges, const double *v0, double dt,
+                     int order)
+{
+    ram_status st;
+    g_last_error.clear();
+    if ((st = check_layout(layout, edges)) != RAM_OK) return st;
+    if ((st = check_dtype(dtype)) != RAM_OK) return st;
+    if ((st = check_scan(dtype, scan)) != RAM_OK) return st;
+    if ((st = check_order(layout, order)) != RAM_OK) return st;
+    if ((st = check_dt(dt)) != RAM_OK) return st;
+    if (!q_in || !q_out || !v0) return fail(RAM_E_INVALID_ARG, "null q_in, q_out or v0");
+    if (q_in == q_out) return fail(RAM_E_INVALID_ARG, "q_in and q_out must not alias");
+    if ((st = enter(ctx)) != RAM_OK) return st;
+    if ((st = ensure_scratch(ctx, rows_scratch(layout))) != RAM_OK) return st;
+    ram::ShiftArgs a;
+    if ((st = make_rows(ctx, layout, edges, 0, a.rows)) != RAM_OK) return st;
+    a.q_in = q_in;
+    a.q_out = q_out;
+    a.v0 = v0;
+    a.dt = dt;
+    hipError_t e = ram::launch_shift(a, dtype == RAM_F64, (int)scan, order, ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "shift launch");
+    return RAM_OK;
+}
+
+ram_status ram_residual(ram_ctx *ctx, const ram_layout *layout,
+                        ram_dtype dtype, const void *q_in, void *q_out,
+                        const double *edges, const void *dv, double dt)
+{
+    ram_status st;
+    g_last_error.clear();
+    if ((st = check_layout(layout, edges)) != RAM_OK) return st;
+    if ((st = check_dtype(dtype)) != RAM_OK) return st;
+    if ((st = check_dt(dt)) != RAM_OK) return st;
+    if (!q_in || !q_out || !dv) return fail(RAM_E_INVALID_ARG, "null q_in, q_out or dv");
+    if (q_in == q_out) return fail(RAM_E_INVALID_ARG, "q_in and q_out must not alias");
+    if ((st = enter(ctx)) != RAM_OK) return st;
+    if ((st = ensure_scratch(ctx, rows_scratch(layout))) != RAM_OK) return st;
+    ram::ResidualArgs a;
+    if ((st = make_rows(ctx, layout, edges, 0, a.rows)) != RAM_OK) return st;
+    a.q_in = q_in;
+    a.q_out = q_out;
+    a.dv = dv;
+    a.dt = dt;
+    hipError_t e = ram::launch_residual(a, dtype == RAM_F64, ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "residual launch");
+    return RAM_OK;
+}
+
+ram_status ram_step(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
+                    ram_scan scan, void *q, const double *edges,
+                    const double *v0, const void *dv, double dt, int order,
+                    int64_t n_steps)
+{
+    ram_status st;
+    g_last_error.clear();
+    if ((st = check_layout(layout, edges)) != RAM_OK) return st;
+    if ((st = check_dtype(dtype)) != RAM_OK) return st;
+    if ((st = check_scan(dtype, scan)) != RAM_OK) return st;
+    if ((st = check_order(layout, order)) != RAM_OK) return st;
+    if ((st = check_dt(dt)) != RAM_OK) return st;
+    if (!q || !v0) return fail(RAM_E_INVALID_ARG, "null q or v0");
+    if (n_steps < 0) return fail(RAM_E_INVALID_ARG, "n_steps must be >= 0");
+    if (n_steps == 0) return RAM_OK;
+    const size_t state_bytes = align_up(elem_size(dtype) * (size_t)layout_cells(layout));
+    if ((st = enter(ctx)) != RAM_OK) return st;
+    if ((st = ensure_scratch(ctx, state_bytes + rows_scratch(layout))) != RAM_OK) return st;
+    void *tmp = ctx->scratch;
+    ram::Rows R;
+    if ((st = make_rows(ctx, layout, edges, state_bytes, R)) != RAM_OK) return st;
+    ram::ShiftArgs sa;
+    sa.rows = R;
+    sa.v0 = v0;
+    sa.dt = dt;
+    ram::ResidualArgs ra;
+    ra.rows = R;
+    ra.dv = dv;
+    ra.dt = dt;
+    void *cur = q, *oth = tmp;
+    for (int64_t k = 0; k < n_steps; ++k) {
+        sa.q_in = cur;
+        sa.q_out = oth;
+        hipError_t e = ram::launch_shift(sa, dtype == RAM_F64, (int)scan, order, ctx->stream);
+        if (e != hipSuccess) return hip_fail(e, "shift launch");
+        if (dv) {
+            ra.q_in = oth;
+            ra.q_out = cur;
+            e = ram::launch_residual(ra, dtype == RAM_F64, ctx->stream);
+            if (e != hipSuccess) return hip_fail(e, "residual launch");
+        } else {
+            void *t = cur; cur = oth; oth = t;
+        }
+    }
+    if (cur != q) {
+        hipError_t e = ram::launch_copy(cur, q, (int64_t)(elem_size(dtype) * layout_cells(layout)),
+                                        ctx->stream);
+        if (e != hipSuccess) return hip_fail(e, "state copy");
+    }
+    return RAM_OK;
+}
+
+ram_status ram_shift_adjoint(ram_ctx *ctx, const ram_layout *layout,
+                             ram_dtype dtype, ram_scan scan,
+                             const void *q_fwd, const void *qbar_out,
+                             void *qbar_in, const double *edges,
+                             const double *v0, double dt, int order,
+                             double *v0bar_accum)
+{
+    ram_status st;
+    g_last_error.clear();
+    if ((st = check_layout(layout, edges)) != RAM_OK) return st;
+    if ((st = check_dtype(dtype)) != RAM_OK) return st;
+    if ((st = check_scan(dtype, scan)) != RAM_OK) return st;
+    if ((st = check_order(layout, order)) != RAM_OK) return st;
+    if ((st = check_dt(dt)) != RAM_OK) return st;
+    if (!qbar_out || !qbar_in || !v0) return fail(RAM_E_INVALID_ARG, "null qbar_out, qbar_in or v0");
+    if (qbar_in == qbar_out) return fail(RAM_E_INVALID_ARG, "qbar_in and qbar_out must not alias");
+    if (v0bar_accum && !q_fwd) return fail(RAM_E_INVALID_ARG, "v0bar needs the forward state q_fwd");
+    if ((st = enter(ctx)) != RAM_OK) return st;
+    if ((st = ensure_scratch(ctx, rows_scratch(layout))) != RAM_OK) return st;
+    ram::ShiftAdjArgs a;
+    if ((st = make_rows(ctx, layout, edges, 0, a.rows)) != RAM_OK) return st;
+    a.q_fwd = q_fwd;
+    a.qbar_out = qbar_out;
+    a.qbar_in = qbar_in;
+    a.v0 = v0;
+    a.dt = dt;
+    a.v0bar = v0bar_accum;
+    hipError_t e = ram::launch_shift_adjoint(a, dtype == RAM_F64, order, ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "shift adjoint launch");
+    return RAM_OK;
+}
+
+ram_status ram_residual_adjoint(ram_ctx *ctx, const ram_layout *layout,
+                                ram_dtype dtype, const void *q_fwd,
+                                const void *dv, const void *qbar_out,
+                                void *qbar_in, const double *edges, double dt,
+                                void *dvbar_accum)
+{
+    ram_status st;
+    g_last_error.clear();
+    if ((st = check_layout(layout, edges)) != RAM_OK) return st;
+    if ((st = check_dtype(dtype)) != RAM_OK) return st;
+    if ((st = check_dt(dt)) != RAM_OK) return st;
+    if (!q_fwd || !dv || !qbar_out || !qbar_in)
+        return fail(RAM_E_INVALID_ARG, "null q_fwd, dv, qbar_out or qbar_in");
+    if (qbar_in == qbar_out) return fail(RAM_E_INVALID_ARG, "qbar_in and qbar_out must not alias");
+    if ((st = enter(ctx)) != RAM_OK) return st;
+    if ((st = ensure_scratch(ctx, rows_scratch(layout))) != RAM_OK) return st;
+    ram::ResidualAdjArgs a;
+    if ((st = make_rows(ctx, layout, edges, 0, a.rows)) != RAM_OK) return st;
+    a.q_fwd = q_fwd;
+    a.dv = dv;
+    a.qbar_out = qbar_out;
+    a.qbar_in = qbar_in;
+    a.dvbar = dvbar_accum;
+    a.dt = dt;
+    hipError_t e = ram::launch_residual_adjoint(a, dtype == RAM_F64, ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "residual adjoint launch");
+    return RAM_OK;
+}
+
+ram_status ram_validate(ram_ctx *ctx, const ram_layout *layout,
+                        ram_dtype dtype, const double *edges, const void *dv,
+                        double dt)
+{
+    ram_status st;
+    g_last_error.clear();
+    if ((st = check_layout(layout, edges)) != RAM_OK) return st;
+    if ((st = check_dtype(dtype)) != RAM_OK) return st;
+    if ((st = check_dt(dt)) != RAM_OK) return st;
+    if ((st = enter(ctx)) != RAM_OK) return st;
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    const int64_t n_rows = layout->n_rows;
+    std::vector<int64_t> rp(n_rows + 1);
+    if (layout->n_cols > 0) {
+        for (int64_t r = 0; r <= n_rows; ++r) rp[r] = r * layout->n_cols;
+    } else {
+        e = hipMemcpy(rp.data(), layout->row_ptr, sizeof(int64_t) * (n_rows + 1),
+                      hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "copy row_ptr");
+        for (int64_t r = 0; r < n_rows; ++r)
+            if (rp[r + 1] < rp[r] + 1)
+                return fail(RAM_E_INVALID_ARG, "row %lld is empty or row_ptr decreases", (long long)r);
+        if (rp[0] != 0 || rp[n_rows] != layout->n_cells)
+            return fail(RAM_E_INVALID_ARG, "row_ptr must start at 0 and end at n_cells");
+    }
+    const bool shared = layout->edges_shared != 0;
+    const int64_t n_nodes = shared ? layout->n_cols + 1 : rp[n_rows] + n_rows;
+    std::vector<double> x(n_nodes);
+    e = hipMemcpy(x.data(), edges, sizeof(double) * n_nodes, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "copy edges");
+    std::vector<double> v;
+    if (dv) {
+        v.resize(rp[n_rows]);
+        if (dtype == RAM_F64) {
+            e = hipMemcpy(v.data(), dv, sizeof(double) * rp[n_rows], hipMemcpyDeviceToHost);
+        } else {
+            std::vector<float> vf(rp[n_rows]);
+            e = hipMemcpy(vf.data(), dv, sizeof(float) * rp[n_rows], hipMemcpyDeviceToHost);
+            for (size_t i = 0; i < vf.size(); ++i) v[i] = vf[i];
+        }
+        if (e != hipSuccess) return hip_fail(e, "copy dv");
+    }
+    for (int64_t r = 0; r < n_rows; ++r) {
+        const int64_t n = rp[r + 1] - rp[r];
+        const double *xr = shared ? x.data() : x.data() + rp[r] + r;
+        for (int64_t j = 0; j <= n; ++j)
+            if (!std::isfinite(xr[j]))
+                return fail(RAM_E_MESH, "row %lld node %lld is not finite", (long long)r, (long long)j);
+        for (int64_t j = 0; j < n; ++j)
+            if (!(xr[j + 1] > xr[j]))
+                return fail(RAM_E_MESH, "row %lld nodes not strictly increasing at %lld",
+                            (long long)r, (long long)j);
+        if (!dv) continue;
+        for (int64_t f = 0; f < n; ++f) {
+            const double a = std::fabs(v[rp[r] + f]);
+            if (!std::isfinite(a))
+                return fail(RAM_E_CFL, "row %lld face %lld: dv not finite", (long long)r, (long long)f);
+            const int64_t fm = (f + n - 1) % n;
+            const double lim = std::fmin(xr[f + 1] - xr[f], xr[fm + 1] - xr[fm]);
+            if (a * std::fabs(dt) > lim)
+                return fail(RAM_E_CFL, "row %lld face %lld: |dv| dt = %g exceeds %g",
+                            (long long)r, (long long)f, a * std::fabs(dt), lim);
+        }
+    }
+    return RAM_OK;
+}
+
+} // extern "C"

@@ -1,0 +1,212 @@
+// ram_device.h -- device-side helpers of the RAM HIP kernels (tile mapping,
+// periodic mesh access, shifted-node location, Lagrange weights, block scans
+// in three precisions).  Private to the library's .hip files.
+#pragma once
+
+#include "ram_internal.h"
+
+#include <math.h>
+
+namespace ram {
+namespace dev {
+
+
+struct Tile {
+    int64_t row;
+    int32_t i0;      // first destination cell of the tile within the row
+    int32_t n;       // cells in the row
+    int64_t qoff;    // offset of the row's first cell
+    const double *x; // the row's N+1 nodes
+};
+
+__device__ inline bool get_tile(const Rows &R, int64_t t, Tile &ti)
+{
+    if (R.n_cols > 0) {
+        const int64_t tpr = (R.n_cols + kTile - 1) / kTile;
+        ti.row = t / tpr;
+        if (ti.row >= R.n_rows) return false;
+        ti.i0 = (int32_t)((t - ti.row * tpr) * kTile);
+        ti.n = (int32_t)R.n_cols;
+        ti.qoff = ti.row * R.n_cols;
+        ti.x = R.shared ? R.edges : R.edges + ti.row * (R.n_cols + 1);
+    } else {
+        if (t >= R.tile_ptr[R.n_rows]) return false;
+        ti.row = R.tile_row[t];
+        ti.i0 = (int32_t)((t - R.tile_ptr[ti.row]) * kTile);
+        ti.qoff = R.row_ptr[ti.row];
+        ti.n = (int32_t)(R.row_ptr[ti.row + 1] - ti.qoff);
+        ti.x = R.edges + ti.qoff + ti.row;
+    }
+    return true;
+}
+
+__device__ inline int wrapi(int64_t m, int n)
+{
+    int64_t r = m % n;
+    return (int)(r < 0 ? r + n : r);
+}
+
+// Node of the periodically extended mesh, j in [-n, 2n].
+__device__ inline double node_x(const double *x, int n, double len, int j)
+{
+    if (j < 0) return x[j + n] - len;
+    if (j > n) return x[j - n] + len;
+    return x[j];
+}
+
+// Largest j in [0, n-1] with x[j] <= xh (right-continuous).
+__device__ inline int find_cell(const double *x, int n, double xh)
+{
+    if (!(xh >= x[0])) return 0;
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = lo + (hi - lo + 1) / 2;
+        if (x[mid] <= xh) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// x~ = x[e] - s written as xh + k L, xh in [x0, xN).
+__device__ inline void shifted_node(const double *x, int n, double s, int e,
+                                    double &xh, int64_t &k)
+{
+    const double len = x[n] - x[0];
+    const double xt = x[e] - s;
+    const double kf = floor((xt - x[0]) / len);
+    xh = xt - kf * len;
+    k = (int64_t)kf;
+    if (xh >= x[n]) { xh -= len; k += 1; }
+    else if (xh < x[0]) { xh += len; k -= 1; }
+}
+
+template <int P>
+__device__ inline void lagrange_weights(double xh, const double *X, double *w)
+{
+    double t[P + 1];
+#pragma unroll
+    for (int a = 0; a <= P; ++a) t[a] = xh - X[a];
+#pragma unroll
+    for (int a = 0; a <= P; ++a) {
+        double num = 1.0, den = 1.0;
+#pragma unroll
+        for (int b = 0; b <= P; ++b) {
+            if (b == a) continue;
+            num *= t[b];
+            den *= X[a] - X[b];
+        }
+        w[a] = num / den;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// prefix-sum precisions
+// ---------------------------------------------------------------------------
+
+__device__ inline void two_sum(float a, float b, float &s, float &e)
+{
+    s = a + b;
+    const float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+template <int S> struct Acc;
+
+template <> struct Acc<kScanF64> {
+    using M = double;
+    using A = double;
+    template <typename TQ>
+    __device__ static M mass(TQ q, double dx) { return (double)q * dx; }
+    __device__ static A zero() { return 0.0; }
+    __device__ static A add(A a, M m) { return a + m; }
+    __device__ static A comb(A a, A b) { return a + b; }
+    __device__ static double diff(A b, A a) { return b - a; }
+    __device__ static A shfl_up(A v, int d) { return __shfl_up(v, d); }
+};
+
+template <> struct Acc<kScanTwoSum> {
+    using M = float;
+    using A = float2;   // (hi, lo): value = hi + lo
+    template <typename TQ>
+    __device__ static M mass(TQ q, double dx) { return (float)q * (float)dx; }
+    __device__ static A zero() { return make_float2(0.f, 0.f); }
+    __device__ static A add(A a, M m)
+    {
+        float s, e;
+        two_sum(a.x, m, s, e);
+        const float lo = a.y + e;
+        const float hi = s + lo;
+        return make_float2(hi, lo - (hi - s));
+    }
+    __device__ static A comb(A a, A b)
+    {
+        float s, e;
+        two_sum(a.x, b.x, s, e);
+        const float lo = a.y + b.y + e;
+        const float hi = s + lo;
+        return make_float2(hi, lo - (hi - s));
+    }
+    __device__ static double diff(A b, A a)
+    {
+        return (double)((b.x - a.x) + (b.y - a.y));
+    }
+    __device__ static A shfl_up(A v, int d)
+    {
+        return make_float2(__shfl_up(v.x, d), __shfl_up(v.y, d));
+    }
+};
+
+template <> struct Acc<kScanF32> {
+    using M = float;
+    using A = float;
+    template <typename TQ>
+    __device__ static M mass(TQ q, double dx) { return (float)q * (float)dx; }
+    __device__ static A zero() { return 0.f; }
+    __device__ static A add(A a, M m) { return a + m; }
+    __device__ static A comb(A a, A b) { return a + b; }
+    __device__ static double diff(A b, A a) { return (double)(b - a); }
+    __device__ static A shfl_up(A v, int d) { return __shfl_up(v, d); }
+};
+
+// Exclusive scan over the workgroup of one value per thread; also returns
+// the total.  wave_tot: LDS scratch of kBlock/64 entries.
+template <class AC>
+__device__ typename AC::A block_exscan(typename AC::A v, typename AC::A *wave_tot,
+                                       typename AC::A &total)
+{
+    using A = typename AC::A;
+    const int lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
+    A inc = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const A o = AC::shfl_up(inc, d);
+        if (lane >= d) inc = AC::comb(o, inc);
+    }
+    A exc = AC::shfl_up(inc, 1);
+    if (lane == 0) exc = AC::zero();
+    if (lane == 63) wave_tot[wid] = inc;
+    __syncthreads();
+    A off = AC::zero();
+    A tot = AC::zero();
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+        if (w < wid) off = AC::comb(off, wave_tot[w]);
+        tot = AC::comb(tot, wave_tot[w]);
+    }
+    total = tot;
+    __syncthreads();
+    return AC::comb(off, exc);
+}
+
+__device__ inline double centre(const double *x, int i) { return 0.5 * (x[i] + x[i + 1]); }
+
+// Distance between the centres of cells i and i+1 (periodic).
+__device__ inline double centre_gap(const double *x, int n, double len, int64_t i)
+{
+    const int w = wrapi(i, n);
+    if (w == n - 1) return centre(x, 0) + len - centre(x, n - 1);
+    return centre(x, w + 1) - centre(x, w);
+}
+
+} // namespace dev
+} // namespace ram

@@ -1,0 +1,100 @@
+"""Host-side checks of the C ABI (no GPU needed).
+
+* libram.so loads and exports every function include/ram.h declares;
+* argument errors are reported with the documented status before the library
+  touches a device (a null context is only reported after the arguments).
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ram.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(ram_\w+)\s*\(", text, re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2305_05362_amd import _lib
+    return _lib.load_library()
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for want in ("ram_shift", "ram_residual", "ram_step", "ram_shift_adjoint",
+                 "ram_residual_adjoint", "ram_create", "ram_destroy",
+                 "ram_validate", "ram_status_string", "ram_last_error"):
+        assert want in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(lib):
+    assert lib.ram_status_string(0) == b"ok"
+    assert lib.ram_status_string(-2) == b"unsupported configuration"
+    assert lib.ram_version().startswith(b"ram-mi355x")
+
+
+def _layout(n_rows=2, n_cols=16, shared=1):
+    from paper_2305_05362_amd._lib import Layout
+    return Layout(n_rows, n_cols, None, 0, shared)
+
+
+def test_argument_errors_without_device(lib):
+    from paper_2305_05362_amd import _lib as R
+    L = _layout()
+    fake = ctypes.c_void_p(0x1000)     # never dereferenced: checks fail first
+    # even order
+    st = lib.ram_shift(None, ctypes.byref(L), R.RAM_F64, R.RAM_SCAN_F64, fake,
+                       ctypes.c_void_p(0x2000), fake, fake, 0.1, 2)
+    assert st == R.RAM_E_UNSUPPORTED and b"order" in lib.ram_last_error()
+    # FP64 state with an FP32 scan
+    st = lib.ram_shift(None, ctypes.byref(L), R.RAM_F64, R.RAM_SCAN_F32, fake,
+                       ctypes.c_void_p(0x2000), fake, fake, 0.1, 5)
+    assert st == R.RAM_E_UNSUPPORTED
+    # aliasing input and output
+    st = lib.ram_shift(None, ctypes.byref(L), R.RAM_F32, R.RAM_SCAN_F64, fake,
+                       fake, fake, fake, 0.1, 5)
+    assert st == R.RAM_E_INVALID_ARG and b"alias" in lib.ram_last_error()
+    # non-finite dt
+    st = lib.ram_residual(None, ctypes.byref(L), R.RAM_F64, fake,
+                          ctypes.c_void_p(0x2000), fake, fake, float("nan"))
+    assert st == R.RAM_E_INVALID_ARG and b"dt" in lib.ram_last_error()
+    # rows shorter than the stencil
+    L2 = _layout(1, 4)
+    st = lib.ram_step(None, ctypes.byref(L2), R.RAM_F64, R.RAM_SCAN_F64, fake,
+                      fake, fake, None, 0.1, 5, 3)
+    assert st == R.RAM_E_INVALID_ARG
+    # ragged layout without row_ptr
+    from paper_2305_05362_amd._lib import Layout
+    L3 = Layout(3, 0, None, 100, 0)
+    st = lib.ram_residual(None, ctypes.byref(L3), R.RAM_F64, fake,
+                          ctypes.c_void_p(0x2000), fake, fake, 0.1)
+    assert st == R.RAM_E_INVALID_ARG and b"row_ptr" in lib.ram_last_error()
+    # shared edges need uniform rows
+    L4 = Layout(3, 0, 0x3000, 100, 1)
+    st = lib.ram_residual(None, ctypes.byref(L4), R.RAM_F64, fake,
+                          ctypes.c_void_p(0x2000), fake, fake, 0.1)
+    assert st == R.RAM_E_INVALID_ARG
+    # null adjoint outputs
+    st = lib.ram_shift_adjoint(None, ctypes.byref(L), R.RAM_F64, R.RAM_SCAN_F64,
+                               None, fake, None, fake, fake, 0.1, 5, None)
+    assert st == R.RAM_E_INVALID_ARG
+    # v0bar without the forward state
+    st = lib.ram_shift_adjoint(None, ctypes.byref(L), R.RAM_F64, R.RAM_SCAN_F64,
+                               None, fake, ctypes.c_void_p(0x2000), fake, fake,
+                               0.1, 5, ctypes.c_void_p(0x4000))
+    assert st == R.RAM_E_INVALID_ARG and b"q_fwd" in lib.ram_last_error()
+    # valid arguments, null context: reported last
+    st = lib.ram_shift(None, ctypes.byref(L), R.RAM_F64, R.RAM_SCAN_F64, fake,
+                       ctypes.c_void_p(0x2000), fake, fake, 0.1, 5)
+    assert st == R.RAM_E_INVALID_ARG and b"context" in lib.ram_last_error()
