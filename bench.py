@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Throughput of the RAM advection step on one MI355X.
+
+Workload: the production-shaped polar disk, 2048 rows x 16384 azimuthal cells
+(periodic-bump azimuthal mesh 10x finer inside |phi| < 0.2, log radii on
+[0.4, 2.5]), Keplerian per-row bulk speed, residual velocity from the noisy
+sine recipe, order-5 interpolation of the cumulative, van Leer residual step.
+All inputs are seeded synthetic data resident in HBM before timing starts.
+
+Prints one JSON line.  ``value`` is the forward step throughput (bulk shift +
+residual, one step = every cell updated once) of the FP32-state path with the
+compensated (two-sum) FP32 prefix sums; beside it: the FP32 path with FP64
+prefix sums, the FP64 plain path, forward+adjoint, the one-step error against
+the FP64 oracle on sampled rows, the dominant kernel's HBM roofline, and the
+CPU oracle's throughput on a bounded sample (run on this host's cores).
+
+    python bench.py [--steps K] [--warmup W] [--adj-steps A] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gcell-updates/s per RAM step (fwd, fwd+adjoint) vs FP64 plain at stated L1 err"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=1000)
+    p.add_argument("--warmup", type=int, default=20)
+    p.add_argument("--adj-steps", type=int, default=100)
+    p.add_argument("--checkpoint", type=int, default=20)
+    p.add_argument("--fp64-steps", type=int, default=200)
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--cpu-seconds", type=float, default=12.0)
+    return p.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: the RAM rows shard without communication "
+              "and this build runs on a single MI355X; use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2305_05362_amd import _lib as R
+    from paper_2305_05362_amd import workloads as W
+    from paper_2305_05362_amd.autograd import rollout
+
+    R.load_library()           # fails loudly if the HIP library is missing
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    wl = W.cfg5()
+    n_cells = wl.n_cells
+    order = wl.order
+    rows = R.Rows.from_workload(wl, dev)
+    v0 = torch.as_tensor(wl.v0, dtype=torch.float64, device=dev)
+    q64 = torch.as_tensor(wl.q0.reshape(-1), dtype=torch.float64, device=dev)
+    dv64 = torch.as_tensor(wl.dv.reshape(-1), dtype=torch.float64, device=dev)
+    q32 = q64.float()
+    dv32 = dv64.float()
+    ctx = R.context(0)
+
+    def events():
+        return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def time_steps(q0, dv, scan, steps, warmup):
+        q = q0.clone()
+        ctx.ram_step(rows, q, v0, dv, wl.dt, order, warmup, scan)
+        torch.cuda.synchronize()
+        a, b = events()
+        a.record()
+        ctx.ram_step(rows, q, v0, dv, wl.dt, order, steps, scan)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / 1e3, q
+
+    def time_kernel(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        a, b = events()
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / 1e3 / reps
+
+    # --- headline: FP32 state, compensated FP32 prefix sums ----------------
+    t_ts, q_ts = time_steps(q32, dv32, R.RAM_SCAN_F32_TWOSUM, args.steps, args.warmup)
+    value = n_cells * args.steps / t_ts / 1e9
+    # --- FP32 state, FP64 prefix sums ---------------------------------------
+    k2 = max(1, args.steps // 4)
+    t_f64s, _ = time_steps(q32, dv32, R.RAM_SCAN_F64, k2, args.warmup)
+    v_f64s = n_cells * k2 / t_f64s / 1e9
+    # --- FP64 plain path ----------------------------------------------------
+    t64, q_64 = time_steps(q64, dv64, R.RAM_SCAN_F64, args.fp64_steps, args.warmup)
+    v64 = n_cells * args.fp64_steps / t64 / 1e9
+
+    # --- per-kernel durations (same stream, HIP events) --------------------
+    h32 = torch.empty_like(q32)
+    o32 = torch.empty_like(q32)
+    t_shift = time_kernel(lambda: ctx.ram_shift(rows, q32, h32, v0, wl.dt, order,
+                                                R.RAM_SCAN_F32_TWOSUM), 50)
+    t_res = time_kernel(lambda: ctx.ram_residual(rows, h32, o32, dv32, wl.dt), 50)
+    shift_bytes = 8.0 * n_cells          # read Q, write Q' (FP32); mesh L2-resident
+    res_bytes = 12.0 * n_cells           # read Q', dv, write Q''
+    kernels = {"shift_f32_twosum_us": t_shift * 1e6, "residual_f32_us": t_res * 1e6,
+               "shift_algorithmic_bytes_per_cell": 8, "residual_algorithmic_bytes_per_cell": 12}
+    if t_shift >= t_res:
+        dom, dom_b, dom_t = "k_shift<float,5,twosum>", shift_bytes, t_shift
+    else:
+        dom, dom_b, dom_t = "k_residual<float>", res_bytes, t_res
+    achieved = dom_b / dom_t / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None, "kernel": dom}
+
+    # --- forward + adjoint (checkpointed rollout) ---------------------------
+    ka = args.adj_steps
+    qa = q32.clone().requires_grad_(True)
+    dva = dv32.clone().requires_grad_(True)
+    v0a = v0.clone().requires_grad_(True)
+    g = torch.ones_like(q32)
+    out = rollout(qa, rows, v0a, dva, wl.dt, order, min(ka, 20), args.checkpoint,
+                  R.RAM_SCAN_F32_TWOSUM)
+    out.backward(g)                      # warm-up
+    torch.cuda.synchronize()
+    a, b = events()
+    a.record()
+    out = rollout(qa, rows, v0a, dva, wl.dt, order, ka, args.checkpoint,
+                  R.RAM_SCAN_F32_TWOSUM)
+    out.backward(g)
+    b.record()
+    torch.cuda.synchronize()
+    t_adj = a.elapsed_time(b) / 1e3
+    v_adj = n_cells * ka / t_adj / 1e9
+
+    # --- accuracy: one step vs the FP64 oracle on sampled rows; rollout drift
+    import oracle
+    pick = np.array([0, 511, 1024, 2047])
+    n = wl.n_cols
+    q32h = q32.cpu().numpy().reshape(wl.n_rows, n)
+    dv32h = dv32.cpu().numpy().reshape(wl.n_rows, n)
+    one = q32.clone()
+    ctx.ram_step(rows, one, v0, dv32, wl.dt, order, 1, R.RAM_SCAN_F32_TWOSUM)
+    torch.cuda.synchronize()
+    sub = oracle.Rows(np.arange(len(pick) + 1) * n, wl.edges, True)
+    ref = oracle.step(sub, q32h[pick].astype(np.float64), wl.v0[pick],
+                      dv32h[pick].astype(np.float64), wl.dt, order, 1)
+    got = one.cpu().numpy().reshape(wl.n_rows, n)[pick].reshape(-1).astype(np.float64)
+    err1 = float(np.sum(np.abs(got - ref)) / np.sum(np.abs(ref)))
+    # drift of the FP32 rollout against the FP64 path after the same steps
+    q_ref = q64.clone()
+    ctx.ram_step(rows, q_ref, v0, dv64, wl.dt, order, args.steps + args.warmup,
+                 R.RAM_SCAN_F64)
+    torch.cuda.synchronize()
+    drift = float((q_ts.double() - q_ref).abs().sum() / q_ref.abs().sum())
+
+    # --- CPU oracle baseline on a bounded sample ----------------------------
+    cpu = None
+    if not args.no_cpu:
+        n_s = 128
+        sub = oracle.Rows(np.arange(n_s + 1) * n, wl.edges, True)
+        qs = wl.q0[:n_s].astype(np.float64)
+        t0 = time.perf_counter()
+        oracle.step(sub, qs, wl.v0[:n_s], wl.dv[:n_s], wl.dt, order, 1)
+        t1 = time.perf_counter() - t0
+        steps_s = max(1, int(args.cpu_seconds / max(t1, 1e-3)))
+        t0 = time.perf_counter()
+        oracle.step(sub, qs, wl.v0[:n_s], wl.dv[:n_s], wl.dt, order, steps_s)
+        tc = time.perf_counter() - t0
+        cpu = {"value": n_s * n * steps_s / tc / 1e9, "unit": "Gcell-updates/s",
+               "cores": oracle.max_threads(), "kind": "oracle",
+               "sample": f"first {n_s} of 2048 rows x 16384 cells, {steps_s} FP64 steps "
+                         f"(shift + residual), {tc:.1f} s"}
+
+    res = {
+        "metric": METRIC, "value": round(value, 3), "unit": "Gcell-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(t_ts / args.steps * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "polar disk 2048 rows x 16384 cells, periodic-bump "
+                               "azimuthal mesh (10x refined |phi|<0.2), Keplerian v0, "
+                               "order-5 shift + van Leer residual",
+                   "rows": wl.n_rows, "cols": n, "order": order,
+                   "prefix_sums": "compensated FP32 (two-sum)", "dt": wl.dt},
+        "fwd_adjoint": {"value": round(v_adj, 3), "unit": "Gcell-updates/s",
+                        "steps": ka, "checkpoint": args.checkpoint},
+        "fp32_fp64scan": {"value": round(v_f64s, 3), "steps": k2},
+        "fp64_plain": {"value": round(v64, 3), "steps": args.fp64_steps},
+        "mixed_speedup_vs_fp64": round(value / v64, 3),
+        "error": {"one_step_rel_l1_vs_oracle": err1,
+                  "rollout_rel_l1_vs_fp64_path": drift,
+                  "rollout_steps": args.steps + args.warmup},
+        "kernels": kernels,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()
