@@ -113,7 +113,7 @@ __global__ __launch_bounds__(kBlock) void k_shift_adj(ShiftAdjArgs a)
     const double s = a.v0[ti.row] * a.dt;
     const double len = x[n] - x[0];
     const int i0 = ti.i0;
-    const int nd = min(kTile, n - i0);
+    const int nd = min(a.rows.tile, n - i0);
     const int ne = nd + 1;
     const bool want_v0 = a.v0bar != nullptr && qf != nullptr;
 
@@ -223,7 +223,7 @@ __global__ __launch_bounds__(kBlock) void k_residual_adj(ResidualAdjArgs a)
     const double dt = a.dt;
     const double len = x[n] - x[0];
     const int i0 = ti.i0;
-    const int nd = min(kTile, n - i0);
+    const int nd = min(a.rows.tile, n - i0);
 
     for (int t = threadIdx.x; t < nd + 4; t += kBlock) {
         const int c = wrapi((int64_t)i0 - 2 + t, n);

@@ -125,36 +125,75 @@ ram_status check_dt(double dt)
     return RAM_OK;
 }
 
-// Fill the kernel-side row description.  Ragged layouts get their tile table
-// built in scratch at byte offset `off` (advanced past what it uses).
+// Scratch plan of one call: the pieces are carved out of the context's single
+// device buffer, 256-byte aligned.
+struct Carve {
+    size_t off = 0;
+    size_t take(size_t bytes)
+    {
+        const size_t o = off;
+        off += align_up(bytes);
+        return o;
+    }
+};
+
+size_t ragged_bytes(const ram_layout *L, int tile)
+{
+    if (L->n_cols > 0) return 0;
+    return align_up(sizeof(int64_t) * (L->n_rows + 1)) +
+           align_up(sizeof(int32_t) * ram::ragged_tile_bound(L->n_cells, L->n_rows, tile));
+}
+
+struct RowsPlan {
+    size_t rag_off = 0, tab_off = 0;
+    int tile = ram::kTile;
+    int order = 0;          // > 0: build the shared-mesh tables for this order
+};
+
+// Reserve what make_rows will need.
+RowsPlan plan_rows(Carve &cv, const ram_layout *L, int tile, int tab_order)
+{
+    RowsPlan p;
+    p.tile = tile;
+    if (L->n_cols == 0) p.rag_off = cv.take(ragged_bytes(L, tile));
+    if (L->edges_shared && tab_order > 0) {
+        p.order = tab_order;
+        p.tab_off = cv.take(ram::mesh_tab_bytes(L->n_cols, tab_order));
+    }
+    return p;
+}
+
+// Fill the kernel-side row description (after ensure_scratch): ragged
+// batches get their tile table, shared meshes their tables.
 ram_status make_rows(ram_ctx *ctx, const ram_layout *L, const double *edges,
-                     size_t off, ram::Rows &R)
+                     const RowsPlan &p, ram::Rows &R)
 {
     R.n_rows = L->n_rows;
     R.n_cols = L->n_cols;
     R.edges = edges;
     R.shared = L->edges_shared ? 1 : 0;
+    R.tile = p.tile;
     if (L->n_cols > 0) {
-        R.n_tiles = L->n_rows * ((L->n_cols + ram::kTile - 1) / ram::kTile);
-        return RAM_OK;
+        R.n_tiles = L->n_rows * ((L->n_cols + p.tile - 1) / p.tile);
+    } else {
+        R.row_ptr = L->row_ptr;
+        R.n_tiles = ram::ragged_tile_bound(L->n_cells, L->n_rows, p.tile);
+        char *base = (char *)ctx->scratch + p.rag_off;
+        R.tile_ptr = (const int64_t *)base;
+        R.tile_row = (const int32_t *)(base + align_up(sizeof(int64_t) * (L->n_rows + 1)));
+        hipError_t e = ram::launch_tiles_prep(L->row_ptr, L->n_rows, p.tile,
+                                              (int64_t *)R.tile_ptr,
+                                              (int32_t *)R.tile_row, ctx->stream);
+        if (e != hipSuccess) return hip_fail(e, "tile table launch");
     }
-    R.row_ptr = L->row_ptr;
-    R.n_tiles = ram::ragged_tile_bound(L->n_cells, L->n_rows);
-    char *base = (char *)ctx->scratch + off;
-    R.tile_ptr = (const int64_t *)base;
-    R.tile_row = (const int32_t *)(base + align_up(sizeof(int64_t) * (L->n_rows + 1)));
-    hipError_t e = ram::launch_tiles_prep(L->row_ptr, L->n_rows,
-                                          (int64_t *)R.tile_ptr,
-                                          (int32_t *)R.tile_row, ctx->stream);
-    if (e != hipSuccess) return hip_fail(e, "tile table launch");
+    if (p.order > 0) {
+        hipError_t e = ram::launch_mesh_prep(edges, L->n_cols, p.order,
+                                             (char *)ctx->scratch + p.tab_off,
+                                             R.tab, ctx->stream);
+        if (e != hipSuccess) return hip_fail(e, "mesh table launch");
+        R.has_tab = 1;
+    }
     return RAM_OK;
-}
-
-size_t rows_scratch(const ram_layout *L)
-{
-    if (L->n_cols > 0) return 0;
-    return align_up(sizeof(int64_t) * (L->n_rows + 1)) +
-           align_up(sizeof(int32_t) * ram::ragged_tile_bound(L->n_cells, L->n_rows));
 }
 
 } // namespace
@@ -240,14 +279,16 @@ ram_status ram_shift(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
     if (!q_in || !q_out || !v0) return fail(RAM_E_INVALID_ARG, "null q_in, q_out or v0");
     if (q_in == q_out) return fail(RAM_E_INVALID_ARG, "q_in and q_out must not alias");
     if ((st = enter(ctx)) != RAM_OK) return st;
-    if ((st = ensure_scratch(ctx, rows_scratch(layout))) != RAM_OK) return st;
-    ram::ShiftArgs a;
-    if ((st = make_rows(ctx, layout, edges, 0, a.rows)) != RAM_OK) return st;
+    Carve cv;
+    RowsPlan rp = plan_rows(cv, layout, ram::step_tile(false), order);
+    if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
+    ram::StepArgs a;
+    if ((st = make_rows(ctx, layout, edges, rp, a.rows)) != RAM_OK) return st;
     a.q_in = q_in;
     a.q_out = q_out;
     a.v0 = v0;
     a.dt = dt;
-    hipError_t e = ram::launch_shift(a, dtype == RAM_F64, (int)scan, order, ctx->stream);
+    hipError_t e = ram::launch_step(a, dtype == RAM_F64, (int)scan, order, ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "shift launch");
     return RAM_OK;
 }
@@ -264,9 +305,11 @@ ram_status ram_residual(ram_ctx *ctx, const ram_layout *layout,
     if (!q_in || !q_out || !dv) return fail(RAM_E_INVALID_ARG, "null q_in, q_out or dv");
     if (q_in == q_out) return fail(RAM_E_INVALID_ARG, "q_in and q_out must not alias");
     if ((st = enter(ctx)) != RAM_OK) return st;
-    if ((st = ensure_scratch(ctx, rows_scratch(layout))) != RAM_OK) return st;
+    Carve cv;
+    RowsPlan rp = plan_rows(cv, layout, ram::kTile, 1);
+    if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
     ram::ResidualArgs a;
-    if ((st = make_rows(ctx, layout, edges, 0, a.rows)) != RAM_OK) return st;
+    if ((st = make_rows(ctx, layout, edges, rp, a.rows)) != RAM_OK) return st;
     a.q_in = q_in;
     a.q_out = q_out;
     a.dv = dv;
@@ -291,38 +334,28 @@ ram_status ram_step(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
     if (!q || !v0) return fail(RAM_E_INVALID_ARG, "null q or v0");
     if (n_steps < 0) return fail(RAM_E_INVALID_ARG, "n_steps must be >= 0");
     if (n_steps == 0) return RAM_OK;
-    const size_t state_bytes = align_up(elem_size(dtype) * (size_t)layout_cells(layout));
     if ((st = enter(ctx)) != RAM_OK) return st;
-    if ((st = ensure_scratch(ctx, state_bytes + rows_scratch(layout))) != RAM_OK) return st;
-    void *tmp = ctx->scratch;
-    ram::Rows R;
-    if ((st = make_rows(ctx, layout, edges, state_bytes, R)) != RAM_OK) return st;
-    ram::ShiftArgs sa;
-    sa.rows = R;
-    sa.v0 = v0;
-    sa.dt = dt;
-    ram::ResidualArgs ra;
-    ra.rows = R;
-    ra.dv = dv;
-    ra.dt = dt;
-    void *cur = q, *oth = tmp;
+    const size_t state_bytes = elem_size(dtype) * (size_t)layout_cells(layout);
+    Carve cv;
+    const size_t tmp_off = cv.take(state_bytes);
+    RowsPlan rp = plan_rows(cv, layout, ram::step_tile(dv != nullptr), order);
+    if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
+    ram::StepArgs a;
+    if ((st = make_rows(ctx, layout, edges, rp, a.rows)) != RAM_OK) return st;
+    a.v0 = v0;
+    a.dv = dv;
+    a.dt = dt;
+    // one fused launch per step, ping-ponging between q and the scratch state
+    void *cur = q, *oth = (char *)ctx->scratch + tmp_off;
     for (int64_t k = 0; k < n_steps; ++k) {
-        sa.q_in = cur;
-        sa.q_out = oth;
-        hipError_t e = ram::launch_shift(sa, dtype == RAM_F64, (int)scan, order, ctx->stream);
-        if (e != hipSuccess) return hip_fail(e, "shift launch");
-        if (dv) {
-            ra.q_in = oth;
-            ra.q_out = cur;
-            e = ram::launch_residual(ra, dtype == RAM_F64, ctx->stream);
-            if (e != hipSuccess) return hip_fail(e, "residual launch");
-        } else {
-            void *t = cur; cur = oth; oth = t;
-        }
+        a.q_in = cur;
+        a.q_out = oth;
+        hipError_t e = ram::launch_step(a, dtype == RAM_F64, (int)scan, order, ctx->stream);
+        if (e != hipSuccess) return hip_fail(e, "step launch");
+        void *t = cur; cur = oth; oth = t;
     }
     if (cur != q) {
-        hipError_t e = ram::launch_copy(cur, q, (int64_t)(elem_size(dtype) * layout_cells(layout)),
-                                        ctx->stream);
+        hipError_t e = ram::launch_copy(cur, q, (int64_t)state_bytes, ctx->stream);
         if (e != hipSuccess) return hip_fail(e, "state copy");
     }
     return RAM_OK;
@@ -346,9 +379,11 @@ ram_status ram_shift_adjoint(ram_ctx *ctx, const ram_layout *layout,
     if (qbar_in == qbar_out) return fail(RAM_E_INVALID_ARG, "qbar_in and qbar_out must not alias");
     if (v0bar_accum && !q_fwd) return fail(RAM_E_INVALID_ARG, "v0bar needs the forward state q_fwd");
     if ((st = enter(ctx)) != RAM_OK) return st;
-    if ((st = ensure_scratch(ctx, rows_scratch(layout))) != RAM_OK) return st;
+    Carve cv;
+    RowsPlan rp = plan_rows(cv, layout, ram::kTile, 0);
+    if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
     ram::ShiftAdjArgs a;
-    if ((st = make_rows(ctx, layout, edges, 0, a.rows)) != RAM_OK) return st;
+    if ((st = make_rows(ctx, layout, edges, rp, a.rows)) != RAM_OK) return st;
     a.q_fwd = q_fwd;
     a.qbar_out = qbar_out;
     a.qbar_in = qbar_in;
@@ -375,9 +410,11 @@ ram_status ram_residual_adjoint(ram_ctx *ctx, const ram_layout *layout,
         return fail(RAM_E_INVALID_ARG, "null q_fwd, dv, qbar_out or qbar_in");
     if (qbar_in == qbar_out) return fail(RAM_E_INVALID_ARG, "qbar_in and qbar_out must not alias");
     if ((st = enter(ctx)) != RAM_OK) return st;
-    if ((st = ensure_scratch(ctx, rows_scratch(layout))) != RAM_OK) return st;
+    Carve cv;
+    RowsPlan rp = plan_rows(cv, layout, ram::kTile, 0);
+    if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
     ram::ResidualAdjArgs a;
-    if ((st = make_rows(ctx, layout, edges, 0, a.rows)) != RAM_OK) return st;
+    if ((st = make_rows(ctx, layout, edges, rp, a.rows)) != RAM_OK) return st;
     a.q_fwd = q_fwd;
     a.dv = dv;
     a.qbar_out = qbar_out;

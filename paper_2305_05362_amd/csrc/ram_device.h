@@ -22,17 +22,17 @@ struct Tile {
 __device__ inline bool get_tile(const Rows &R, int64_t t, Tile &ti)
 {
     if (R.n_cols > 0) {
-        const int64_t tpr = (R.n_cols + kTile - 1) / kTile;
+        const int64_t tpr = (R.n_cols + R.tile - 1) / R.tile;
         ti.row = t / tpr;
         if (ti.row >= R.n_rows) return false;
-        ti.i0 = (int32_t)((t - ti.row * tpr) * kTile);
+        ti.i0 = (int32_t)((t - ti.row * tpr) * R.tile);
         ti.n = (int32_t)R.n_cols;
         ti.qoff = ti.row * R.n_cols;
         ti.x = R.shared ? R.edges : R.edges + ti.row * (R.n_cols + 1);
     } else {
         if (t >= R.tile_ptr[R.n_rows]) return false;
         ti.row = R.tile_row[t];
-        ti.i0 = (int32_t)((t - R.tile_ptr[ti.row]) * kTile);
+        ti.i0 = (int32_t)((t - R.tile_ptr[ti.row]) * R.tile);
         ti.qoff = R.row_ptr[ti.row];
         ti.n = (int32_t)(R.row_ptr[ti.row + 1] - ti.qoff);
         ti.x = R.edges + ti.qoff + ti.row;
@@ -64,6 +64,20 @@ __device__ inline int find_cell(const double *x, int n, double xh)
         if (x[mid] <= xh) lo = mid; else hi = mid - 1;
     }
     return lo;
+}
+
+// Same result as find_cell through the mesh's bucket index: start from the
+// bucket's lower-bound cell, step down while the node lies above xh (only after
+// rounding in the bucket number) and walk up over the few nodes in the bucket.
+__device__ inline int find_cell_tab(const double *x, int n, const MeshTab &tb,
+                                    double bscale, double xh)
+{
+    int b = (int)((xh - x[0]) * bscale);
+    b = min(max(b, 0), tb.nb - 1);
+    int c = tb.bucket[b];
+    while (c > 0 && x[c] > xh) --c;
+    while (c + 1 < n && x[c + 1] <= xh) ++c;
+    return c;
 }
 
 // x~ = x[e] - s written as xh + k L, xh in [x0, xN).
@@ -114,18 +128,20 @@ template <int S> struct Acc;
 template <> struct Acc<kScanF64> {
     using M = double;
     using A = double;
+    using D = double;   // type of prefix differences
     template <typename TQ>
     __device__ static M mass(TQ q, double dx) { return (double)q * dx; }
     __device__ static A zero() { return 0.0; }
     __device__ static A add(A a, M m) { return a + m; }
     __device__ static A comb(A a, A b) { return a + b; }
-    __device__ static double diff(A b, A a) { return b - a; }
+    __device__ static D diff(A b, A a) { return b - a; }
     __device__ static A shfl_up(A v, int d) { return __shfl_up(v, d); }
 };
 
 template <> struct Acc<kScanTwoSum> {
     using M = float;
     using A = float2;   // (hi, lo): value = hi + lo
+    using D = float;
     template <typename TQ>
     __device__ static M mass(TQ q, double dx) { return (float)q * (float)dx; }
     __device__ static A zero() { return make_float2(0.f, 0.f); }
@@ -145,9 +161,9 @@ template <> struct Acc<kScanTwoSum> {
         const float hi = s + lo;
         return make_float2(hi, lo - (hi - s));
     }
-    __device__ static double diff(A b, A a)
+    __device__ static D diff(A b, A a)
     {
-        return (double)((b.x - a.x) + (b.y - a.y));
+        return (b.x - a.x) + (b.y - a.y);
     }
     __device__ static A shfl_up(A v, int d)
     {
@@ -158,12 +174,13 @@ template <> struct Acc<kScanTwoSum> {
 template <> struct Acc<kScanF32> {
     using M = float;
     using A = float;
+    using D = float;
     template <typename TQ>
     __device__ static M mass(TQ q, double dx) { return (float)q * (float)dx; }
     __device__ static A zero() { return 0.f; }
     __device__ static A add(A a, M m) { return a + m; }
     __device__ static A comb(A a, A b) { return a + b; }
-    __device__ static double diff(A b, A a) { return (double)(b - a); }
+    __device__ static D diff(A b, A a) { return b - a; }
     __device__ static A shfl_up(A v, int d) { return __shfl_up(v, d); }
 };
 

@@ -15,6 +15,25 @@ constexpr int kWindowCap = 2048;
 
 enum ScanMode { kScanF64 = 0, kScanTwoSum = 1, kScanF32 = 2 };
 
+// Mesh-only tables for a mesh shared by every row (built once per call by
+// launch_mesh_prep): cell sizes and their reciprocals, reciprocal centre gaps
+// for the slopes, reciprocal Lagrange denominators of every source cell's
+// stencil, and a uniform bucket index over [x0, xN) that turns the cell
+// search into one lookup plus a short walk.
+struct MeshTab {
+    const double *dx = nullptr;
+    const double *dxinv = nullptr;
+    const double *hinv = nullptr;     // 1 / (centre_{j+1} - centre_j), periodic
+    const double *rden = nullptr;     // [n][order+1]
+    const float *dxf = nullptr;
+    const float *dxinvf = nullptr;
+    const float *hinvf = nullptr;
+    const float *rdenf = nullptr;     // scaled by dx_j^order (see k_mesh_prep)
+    const int32_t *bucket = nullptr;  // largest j with x_j <= x0 + b L / nb
+    int32_t nb = 0;
+    const double *bscale = nullptr;   // device scalar nb / L
+};
+
 // Where the rows are.  Uniform batches (n_cols > 0) map tile t to
 // (row = t / tiles_per_row, start = (t % tiles_per_row) * kTile); ragged
 // batches read the tile's row from tile_row (built by launch_tiles_prep).
@@ -25,15 +44,20 @@ struct Rows {
     const int64_t *tile_ptr = nullptr;// ragged: n_rows+1 first tile per row
     const int32_t *tile_row = nullptr;// ragged: row of each tile
     int64_t n_tiles = 0;              // grid size (upper bound when ragged)
+    int tile = kTile;                 // cells per tile (kernel-specific)
     const double *edges = nullptr;
     int shared = 1;                   // one node array for every row
+    MeshTab tab;                      // shared mesh: its tables
+    int has_tab = 0;                  // tab is filled in
 };
 
-struct ShiftArgs {
+// Bulk shift, optionally fused with the residual step (dv != null).
+struct StepArgs {
     Rows rows;
     const void *q_in = nullptr;
     void *q_out = nullptr;
     const double *v0 = nullptr;
+    const void *dv = nullptr;         // null: shift only
     double dt = 0.0;
 };
 
@@ -66,16 +90,26 @@ struct ResidualAdjArgs {
 };
 
 // Number of tiles a ragged batch can need at most (grid size).
-inline int64_t ragged_tile_bound(int64_t n_cells, int64_t n_rows)
+inline int64_t ragged_tile_bound(int64_t n_cells, int64_t n_rows, int tile)
 {
-    return n_cells / kTile + n_rows + 1;
+    return n_cells / tile + n_rows + 1;
 }
 
-hipError_t launch_tiles_prep(const int64_t *row_ptr, int64_t n_rows,
+// Destination cells per tile of the bulk-shift kernel: one shifted node per
+// thread, so kBlock-1 cells, less a two-cell halo per side when the residual
+// step is fused in.
+inline int step_tile(bool fused) { return kBlock - 1 - (fused ? 4 : 0); }
+
+hipError_t launch_tiles_prep(const int64_t *row_ptr, int64_t n_rows, int tile,
                              int64_t *tile_ptr, int32_t *tile_row,
                              hipStream_t stream);
-hipError_t launch_shift(const ShiftArgs &a, bool f64, int scan, int order,
-                        hipStream_t stream);
+// Bytes of scratch the shared-mesh tables of an n-cell mesh need.
+size_t mesh_tab_bytes(int64_t n, int order);
+// Build the tables in `mem` (mesh_tab_bytes) and point `tab` at them.
+hipError_t launch_mesh_prep(const double *x, int64_t n, int order, void *mem,
+                            MeshTab &tab, hipStream_t stream);
+hipError_t launch_step(const StepArgs &a, bool f64, int scan, int order,
+                       hipStream_t stream);
 hipError_t launch_residual(const ResidualArgs &a, bool f64,
                            hipStream_t stream);
 hipError_t launch_shift_adjoint(const ShiftAdjArgs &a, bool f64, int order,

@@ -1,34 +1,53 @@
-// ram_kernels.hip -- HIP kernels of the RAM advection step for gfx950.
+// ram_kernels.hip -- forward HIP kernels of the RAM advection step (gfx950).
 //
-// Layout: rows are independent periodic lines (paper Section 2).  Every kernel
-// works on tiles of kTile consecutive destination cells of one row, one
-// workgroup (kBlock threads = 4 wave64) per tile, row-major coalesced access.
+// Rows are independent periodic lines (paper Section 2).  Every kernel works
+// on tiles of consecutive cells of one row, one workgroup (kBlock threads =
+// four wave64) per tile, with row-major coalesced HBM access.
 //
-//   k_shift      bulk shift (Section 3, Steps 1-3).  Per tile:
-//                (1) each thread places one shifted node x~ = x - v0 dt on the
-//                    periodic mesh: wrap count k and source cell c
-//                    (Eq. condition_p);
-//                (2) the tile's source window [g_first - lo, g_last - lo + p)
-//                    is staged in LDS as cell masses M = Q dx (Eq. Qmass_i) and
-//                    turned into an exclusive prefix (the cumulative integral)
-//                    by a block scan in FP64, compensated FP32 or FP32;
-//                (3) each node's partial integral of the reconstruction is the
-//                    degree-p Lagrange interpolant of the window cumulative;
-//                (4) destination mass = whole source cells in between + the
-//                    two partial integrals (Eq. mass_shift_algo), divided by
-//                    dx (Eq. step3).
+//   k_step       bulk shift (Section 3, Steps 1-3), optionally fused with the
+//                residual upwind step (Eq. splitting_second).  Per tile, with
+//                one shifted node per thread:
+//                (A) x~ = x - v0 dt is wrapped into the period and its source
+//                    cell found (Eq. condition_p) -- through the mesh's bucket
+//                    index when the mesh is shared, by binary search when
+//                    every row has its own mesh; the Lagrange weights of the
+//                    node's degree-p stencil stay in registers;
+//                (B) the tile's source window is staged in LDS as cell masses
+//                    M = Q dx (Eq. Qmass_i) and turned into an exclusive prefix
+//                    (the cumulative integral) by a block scan in FP64,
+//                    compensated FP32 or plain FP32;
+//                (C) each node's partial integral of the reconstruction is the
+//                    Lagrange interpolant of the window cumulative;
+//                (D) destination mass = whole source cells in between + two
+//                    partial integrals (Eq. mass_shift_algo), times 1/dx
+//                    (Eq. step3);
+//                (E-G) fused residual: van Leer slopes (Section 3.1), upwind
+//                    swept-interval face fluxes and the conservative update,
+//                    on the shifted state still in LDS (two-cell halo a side).
 //                Windows wider than the LDS capacity take a direct path that
-//                sums masses from global memory.
-//   k_residual   residual upwind step (Eq. splitting_second) with the van
-//                Leer slope of Section 3.1; halo of two cells per side.
+//                sums the masses from global memory.
+//   k_residual   the residual step alone.
+//   k_mesh_prep  mesh-only tables of a shared mesh.
+//   k_tiles_prep tile table of a ragged batch.
 #include "ram_device.h"
+
+#include <type_traits>
 
 namespace ram {
 namespace {
 
 using namespace dev;
 
-// Mass of (wrapped) cell m of a row, FP64.
+constexpr int kWin = 1024;          // LDS window capacity, source cells
+
+// Periodic index for j in [-n, k n).
+__device__ inline int wrap_small(int j, int n)
+{
+    if (j < 0) j += n;
+    while (j >= n) j -= n;
+    return j;
+}
+
 template <typename TQ>
 __device__ inline double cell_mass(const double *x, const TQ *q, int n, int64_t m)
 {
@@ -36,7 +55,7 @@ __device__ inline double cell_mass(const double *x, const TQ *q, int n, int64_t 
     return (double)q[w] * (x[w + 1] - x[w]);
 }
 
-// Partial integral C~(xh) - C(c) computed from global memory (direct path).
+// Partial integral C~(xh) - C(c) from global memory (direct path).
 template <typename TQ, int P>
 __device__ double partial_direct(const double *x, const TQ *q, int n, double len,
                                  int64_t g, double xh)
@@ -63,80 +82,146 @@ __device__ double partial_direct(const double *x, const TQ *q, int n, double len
     return ell;
 }
 
+// Per-type views of the shared-mesh tables.
+template <typename T> struct TabT;
+template <> struct TabT<double> {
+    __device__ static const double *dx(const MeshTab &t) { return t.dx; }
+    __device__ static const double *dxinv(const MeshTab &t) { return t.dxinv; }
+    __device__ static const double *hinv(const MeshTab &t) { return t.hinv; }
+};
+template <> struct TabT<float> {
+    __device__ static const float *dx(const MeshTab &t) { return t.dxf; }
+    __device__ static const float *dxinv(const MeshTab &t) { return t.dxinvf; }
+    __device__ static const float *hinv(const MeshTab &t) { return t.hinvf; }
+};
+
+// Lagrange weights of the stencil nodes c-LO .. c-LO+P at xh, in WT.  Shared
+// meshes read the reciprocal denominators from the table (FP32: scaled by
+// dx_c^P, with the node offsets in units of dx_c, so every factor is O(1)).
+template <typename WT, int P>
+__device__ inline void stencil_weights(const double *x, int n, double len,
+                                       const Rows &R, int c, double xh, WT *w)
+{
+    constexpr int LO = (P - 1) / 2;
+    double X[P + 1];
+#pragma unroll
+    for (int a = 0; a <= P; ++a) X[a] = node_x(x, n, len, c - LO + a);
+    if (!R.has_tab) {
+        double wd[P + 1];
+        lagrange_weights<P>(xh, X, wd);
+#pragma unroll
+        for (int a = 0; a <= P; ++a) w[a] = (WT)wd[a];
+        return;
+    }
+    WT t[P + 1];
+    if constexpr (std::is_same<WT, double>::value) {
+#pragma unroll
+        for (int a = 0; a <= P; ++a) t[a] = xh - X[a];
+    } else {
+        const double sc = R.tab.dxinv[c];
+#pragma unroll
+        for (int a = 0; a <= P; ++a) t[a] = (float)((xh - X[a]) * sc);
+    }
+    // products of all t but one, from prefix and suffix products
+    WT pre[P + 1], suf[P + 1];
+    pre[0] = (WT)1;
+#pragma unroll
+    for (int a = 1; a <= P; ++a) pre[a] = pre[a - 1] * t[a - 1];
+    suf[P] = (WT)1;
+#pragma unroll
+    for (int a = P - 1; a >= 0; --a) suf[a] = suf[a + 1] * t[a + 1];
+#pragma unroll
+    for (int a = 0; a <= P; ++a) {
+        WT rd;
+        if constexpr (std::is_same<WT, double>::value) rd = R.tab.rden[c * (P + 1) + a];
+        else rd = R.tab.rdenf[c * (P + 1) + a];
+        w[a] = rd * (pre[a] * suf[a]);
+    }
+}
+
 // ---------------------------------------------------------------------------
-// bulk shift
+// bulk shift, optionally fused with the residual step
 // ---------------------------------------------------------------------------
 
 template <typename TQ, int P, int S>
-__global__ __launch_bounds__(kBlock) void k_shift(ShiftArgs a)
+__global__ __launch_bounds__(kBlock) void k_step(StepArgs a)
 {
     using AC = Acc<S>;
     using M = typename AC::M;
     using A = typename AC::A;
+    using D = typename std::conditional<std::is_same<TQ, double>::value, double,
+                                        typename AC::D>::type;
+    using CT = TQ;                     // arithmetic type of the state updates
     constexpr int LO = (P - 1) / 2;
 
-    __shared__ int64_t sg[kTile + 1];   // extended source index g = c + k N
-    __shared__ double sxh[kTile + 1];   // wrapped shifted node
-    __shared__ double sell[kTile + 1];  // partial integral C~(xh) - C(c)
-    __shared__ int sj[kTile + 1];       // window index of node c
-    __shared__ M sm[kWindowCap];        // window cell masses
-    __shared__ A sp[kWindowCap + 1];    // exclusive prefix of sm
+    __shared__ int64_t sg[kBlock];     // extended source index of each node
+    __shared__ D sell[kBlock];         // partial integral C~(xh) - C(c)
+    __shared__ int sjc[kBlock];        // window index of node c
+    __shared__ M sm[kWin];             // window cell masses
+    __shared__ A sp[kWin + 1];         // exclusive prefix of sm
     __shared__ A swt[kBlock / 64];
+    __shared__ CT sq[kBlock];          // shifted state (fused path)
+    __shared__ CT ssig[kBlock];        // van Leer slopes
+    __shared__ CT sf[kBlock];          // face fluxes
+    __shared__ int s_ok;
+    __shared__ int s_base;
 
+    const Rows &R = a.rows;
     Tile ti;
-    if (!get_tile(a.rows, blockIdx.x, ti)) return;
+    if (!get_tile(R, blockIdx.x, ti)) return;
     const int n = ti.n;
     if (n < P + 1) return;
+    const int H = a.dv ? 2 : 0;                 // residual halo
+    const int i0 = ti.i0;
+    const int nd = min(R.tile, n - i0);         // cells this tile writes
+    const int NC = nd + 2 * H;                  // shifted cells
+    const int NE = NC + 1;                      // shifted nodes (<= kBlock)
     const double *x = ti.x;
     const TQ *q = (const TQ *)a.q_in + ti.qoff;
     TQ *qo = (TQ *)a.q_out + ti.qoff;
     const double s = a.v0[ti.row] * a.dt;
     const double len = x[n] - x[0];
-    const int nd = min(kTile, n - ti.i0);
-    const int ne = nd + 1;
+    const int t = threadIdx.x;
 
-    // (1) shifted nodes and their source cells; node N is node 0 of the next
-    // period.
-    for (int t = threadIdx.x; t < ne; t += kBlock) {
-        const int e = ti.i0 + t;
-        double xh;
+    // (A) shifted node t = destination node i0 - H + t: cell and weights
+    int64_t g = 0;
+    double xh = 0.0;
+    TQ w[P + 1];
+    if (t < NE) {
+        int e = i0 - H + t;
+        int kx = 0;
+        if (e < 0) { e += n; kx = -1; }
+        while (e >= n) { e -= n; kx += 1; }
         int64_t k;
-        if (e == n) {
-            shifted_node(x, n, s, 0, xh, k);
-            k += 1;
-        } else {
-            shifted_node(x, n, s, e, xh, k);
-        }
-        const int c = find_cell(x, n, xh);
-        sg[t] = (int64_t)c + k * (int64_t)n;
-        sxh[t] = xh;
+        shifted_node(x, n, s, e, xh, k);
+        const int c = R.has_tab ? find_cell_tab(x, n, R.tab, *R.tab.bscale, xh)
+                               : find_cell(x, n, xh);
+        g = (int64_t)c + (k + kx) * (int64_t)n;
+        stencil_weights<TQ, P>(x, n, len, R, c, xh, w);
+        sg[t] = g;
     }
+    if (t == 0) s_ok = 1;
     __syncthreads();
+    // source indices must not decrease along the tile (otherwise: direct path)
+    if (t >= 1 && t < NE && sg[t] < sg[t - 1]) s_ok = 0;
+    const int64_t wlo = sg[0] - LO;
+    if (t == 0) s_base = wrapi(wlo, n);
+    __syncthreads();
+    const int64_t wide = sg[NE - 1] - sg[0] + P;
+    const bool windowed = s_ok && wide <= kWin;
 
-    // the source index of the shifted nodes is non-decreasing along the tile;
-    // anything else (never expected) takes the direct path, which has no
-    // LDS indexing to protect
-    __shared__ int s_order_ok;
-    if (threadIdx.x == 0) s_order_ok = 1;
-    __syncthreads();
-    for (int t = threadIdx.x + 1; t < ne; t += kBlock)
-        if (sg[t] < sg[t - 1]) s_order_ok = 0;
-    __syncthreads();
-
-    const int64_t g0 = sg[0];
-    const int64_t wide = sg[ne - 1] - g0 + P;
-    if (s_order_ok && wide <= kWindowCap) {
+    if (windowed) {
         const int W = (int)wide;
-        const int64_t wlo = g0 - LO;
-        const int base = wrapi(wlo, n);
-        // (2) window masses, then the block scan into the cumulative
-        for (int j = threadIdx.x; j < W; j += kBlock) {
-            const int mm = (base + j) % n;
-            sm[j] = AC::template mass<TQ>(q[mm], x[mm + 1] - x[mm]);
+        const int base = s_base;
+        // (B) window masses and the block scan into the cumulative
+        for (int j = t; j < W; j += kBlock) {
+            const int mm = wrap_small(base + j, n);
+            if (R.has_tab) sm[j] = (M)q[mm] * TabT<M>::dx(R.tab)[mm];
+            else sm[j] = AC::template mass<TQ>(q[mm], x[mm + 1] - x[mm]);
         }
         __syncthreads();
         const int per = (W + kBlock - 1) / kBlock;
-        const int j0 = min(W, (int)threadIdx.x * per);
+        const int j0 = min(W, t * per);
         const int j1 = min(W, j0 + per);
         A run = AC::zero();
         for (int j = j0; j < j1; ++j) run = AC::add(run, sm[j]);
@@ -146,111 +231,207 @@ __global__ __launch_bounds__(kBlock) void k_shift(ShiftArgs a)
             sp[j] = acc;
             acc = AC::add(acc, sm[j]);
         }
-        if (threadIdx.x == 0) sp[W] = total;
+        if (t == 0) sp[W] = total;
         __syncthreads();
-        // (3) partial integrals from the interpolated cumulative
-        for (int t = threadIdx.x; t < ne; t += kBlock) {
-            const int64_t g = sg[t];
-            const double xh = sxh[t];
-            const int c = wrapi(g, n);
+        // (C) partial integrals from the interpolated window cumulative
+        if (t < NE) {
             const int jc = (int)(g - wlo);
-            double X[P + 1], w[P + 1];
-#pragma unroll
-            for (int b = 0; b <= P; ++b) X[b] = node_x(x, n, len, c - LO + b);
-            lagrange_weights<P>(xh, X, w);
-            double ell = 0.0;
             const A pc = sp[jc];
+            D ell = (D)0;
 #pragma unroll
             for (int b = 0; b <= P; ++b)
-                if (b != LO) ell += w[b] * AC::diff(sp[jc - LO + b], pc);
+                if (b != LO) ell += (D)w[b] * (D)AC::diff(sp[jc - LO + b], pc);
             sell[t] = ell;
-            sj[t] = jc;
-        }
-        __syncthreads();
-        // (4) destination mass and Step 3
-        for (int t = threadIdx.x; t < nd; t += kBlock) {
-            const int ja = sj[t], jb = sj[t + 1];
-            const double whole = (jb - ja == 1) ? (double)sm[ja]
-                                                : AC::diff(sp[jb], sp[ja]);
-            const double mp = whole + (sell[t + 1] - sell[t]);
-            const int i = ti.i0 + t;
-            qo[i] = (TQ)(mp / (x[i + 1] - x[i]));
+            sjc[t] = jc;
         }
     } else {
-        // direct path for windows wider than the LDS capacity
-        for (int t = threadIdx.x; t < ne; t += kBlock)
-            sell[t] = partial_direct<TQ, P>(x, q, n, len, sg[t], sxh[t]);
-        __syncthreads();
-        for (int t = threadIdx.x; t < nd; t += kBlock) {
-            double whole = 0.0;
-            for (int64_t m = sg[t]; m < sg[t + 1]; ++m) whole += cell_mass(x, q, n, m);
-            const double mp = whole + (sell[t + 1] - sell[t]);
-            const int i = ti.i0 + t;
-            qo[i] = (TQ)(mp / (x[i + 1] - x[i]));
+        // direct path: masses summed from global memory in FP64
+        if (t < NE) sell[t] = (D)partial_direct<TQ, P>(x, q, n, len, g, xh);
+    }
+    __syncthreads();
+
+    // (D) destination masses and Step 3
+    if (t < NC) {
+        const int cell = wrap_small(i0 - H + t, n);
+        D mp;
+        if (windowed) {
+            const int ja = sjc[t], jb = sjc[t + 1];
+            const D whole = (jb - ja == 1) ? (D)sm[ja] : (D)AC::diff(sp[jb], sp[ja]);
+            mp = whole + (sell[t + 1] - sell[t]);
+        } else {
+            double wh = 0.0;
+            for (int64_t m = sg[t]; m < sg[t + 1]; ++m) wh += cell_mass(x, q, n, m);
+            mp = (D)(wh + ((double)sell[t + 1] - (double)sell[t]));
         }
+        CT qs;
+        if (R.has_tab) qs = (CT)(mp * (D)TabT<D>::dxinv(R.tab)[cell]);
+        else qs = (CT)(mp / (D)(x[cell + 1] - x[cell]));
+        if (H == 0) qo[cell] = (TQ)qs;
+        else sq[t] = qs;
+    }
+    if (H == 0) return;
+    __syncthreads();
+
+    // (E) van Leer slopes of cells i0-1 .. i0+nd (state index t+1)
+    const TQ *dv = (const TQ *)a.dv + ti.qoff;
+    const CT dt = (CT)a.dt;
+    if (t < nd + 2) {
+        const int cm = wrap_small(i0 - 2 + t, n);
+        const int c0 = wrap_small(i0 - 1 + t, n);
+        CT hp, hm;
+        if (R.has_tab) {
+            hp = TabT<CT>::hinv(R.tab)[c0];
+            hm = TabT<CT>::hinv(R.tab)[cm];
+        } else {
+            hp = (CT)(1.0 / centre_gap(x, n, len, c0));
+            hm = (CT)(1.0 / centre_gap(x, n, len, cm));
+        }
+        const CT dp = (sq[t + 2] - sq[t + 1]) * hp;
+        const CT dm = (sq[t + 1] - sq[t]) * hm;
+        ssig[t] = (dp * dm <= (CT)0) ? (CT)0 : (CT)2 * dp * dm / (dp + dm);
+    }
+    __syncthreads();
+    // (F) fluxes on faces i0 .. i0+nd (face f between cells f-1 and f)
+    if (t < nd + 1) {
+        const int f = wrap_small(i0 + t, n);
+        const CT v = (CT)dv[f];
+        CT qf;
+        if (v >= (CT)0) {
+            const int u = wrap_small(i0 + t - 1, n);
+            const CT dxu = R.has_tab ? TabT<CT>::dx(R.tab)[u] : (CT)(x[u + 1] - x[u]);
+            qf = sq[t + 1] + (CT)0.5 * ssig[t] * (dxu - v * dt);
+        } else {
+            const CT dxu = R.has_tab ? TabT<CT>::dx(R.tab)[f] : (CT)(x[f + 1] - x[f]);
+            qf = sq[t + 2] - (CT)0.5 * ssig[t + 1] * (dxu + v * dt);
+        }
+        sf[t] = v * qf;
+    }
+    __syncthreads();
+    // (G) conservative update of the tile's own cells
+    if (t < nd) {
+        const int i = i0 + t;
+        const CT inv = R.has_tab ? TabT<CT>::dxinv(R.tab)[i] : (CT)(1.0 / (x[i + 1] - x[i]));
+        qo[i] = (TQ)(sq[t + 2] - dt * (sf[t + 1] - sf[t]) * inv);
     }
 }
 
 // ---------------------------------------------------------------------------
-// residual upwind step
+// residual step alone
 // ---------------------------------------------------------------------------
 
 template <typename TQ>
 __global__ __launch_bounds__(kBlock) void k_residual(ResidualArgs a)
 {
-    __shared__ double sq[kTile + 4];    // cells i0-2 .. i0+nd+1
-    __shared__ double ssig[kTile + 2];  // slopes of cells i0-1 .. i0+nd
-    __shared__ double sf[kTile + 1];    // fluxes on faces i0 .. i0+nd
+    using CT = TQ;
+    __shared__ CT sq[kTile + 4];    // cells i0-2 .. i0+nd+1
+    __shared__ CT ssig[kTile + 2];  // slopes of cells i0-1 .. i0+nd
+    __shared__ CT sf[kTile + 1];    // fluxes on faces i0 .. i0+nd
 
+    const Rows &R = a.rows;
     Tile ti;
-    if (!get_tile(a.rows, blockIdx.x, ti)) return;
+    if (!get_tile(R, blockIdx.x, ti)) return;
     const int n = ti.n;
     const double *x = ti.x;
     const TQ *q = (const TQ *)a.q_in + ti.qoff;
     const TQ *dv = (const TQ *)a.dv + ti.qoff;
     TQ *qo = (TQ *)a.q_out + ti.qoff;
-    const double dt = a.dt;
+    const CT dt = (CT)a.dt;
     const double len = x[n] - x[0];
     const int i0 = ti.i0;
-    const int nd = min(kTile, n - i0);
+    const int nd = min(R.tile, n - i0);
 
     for (int t = threadIdx.x; t < nd + 4; t += kBlock)
-        sq[t] = (double)q[wrapi((int64_t)i0 - 2 + t, n)];
+        sq[t] = q[wrap_small(i0 - 2 + t, n)];
     __syncthreads();
     for (int t = threadIdx.x; t < nd + 2; t += kBlock) {
-        const int64_t i = (int64_t)i0 - 1 + t;
-        const double dp = (sq[t + 2] - sq[t + 1]) / centre_gap(x, n, len, i);
-        const double dm = (sq[t + 1] - sq[t]) / centre_gap(x, n, len, i - 1);
-        ssig[t] = (dp * dm <= 0.0) ? 0.0 : 2.0 * dp * dm / (dp + dm);
+        const int cm = wrap_small(i0 - 2 + t, n);
+        const int c0 = wrap_small(i0 - 1 + t, n);
+        CT hp, hm;
+        if (R.has_tab) {
+            hp = TabT<CT>::hinv(R.tab)[c0];
+            hm = TabT<CT>::hinv(R.tab)[cm];
+        } else {
+            hp = (CT)(1.0 / centre_gap(x, n, len, c0));
+            hm = (CT)(1.0 / centre_gap(x, n, len, cm));
+        }
+        const CT dp = (sq[t + 2] - sq[t + 1]) * hp;
+        const CT dm = (sq[t + 1] - sq[t]) * hm;
+        ssig[t] = (dp * dm <= (CT)0) ? (CT)0 : (CT)2 * dp * dm / (dp + dm);
     }
     __syncthreads();
     for (int t = threadIdx.x; t < nd + 1; t += kBlock) {
-        const int64_t f = (int64_t)i0 + t;
-        const double v = (double)dv[wrapi(f, n)];
-        double qs;
-        if (v >= 0.0) {
-            const int u = wrapi(f - 1, n);
-            qs = sq[t + 1] + 0.5 * ssig[t] * ((x[u + 1] - x[u]) - v * dt);
+        const int f = wrap_small(i0 + t, n);
+        const CT v = (CT)dv[f];
+        CT qf;
+        if (v >= (CT)0) {
+            const int u = wrap_small(i0 + t - 1, n);
+            const CT dxu = R.has_tab ? TabT<CT>::dx(R.tab)[u] : (CT)(x[u + 1] - x[u]);
+            qf = sq[t + 1] + (CT)0.5 * ssig[t] * (dxu - v * dt);
         } else {
-            const int u = wrapi(f, n);
-            qs = sq[t + 2] - 0.5 * ssig[t + 1] * ((x[u + 1] - x[u]) + v * dt);
+            const CT dxu = R.has_tab ? TabT<CT>::dx(R.tab)[f] : (CT)(x[f + 1] - x[f]);
+            qf = sq[t + 2] - (CT)0.5 * ssig[t + 1] * (dxu + v * dt);
         }
-        sf[t] = v * qs;
+        sf[t] = v * qf;
     }
     __syncthreads();
     for (int t = threadIdx.x; t < nd; t += kBlock) {
         const int i = i0 + t;
-        qo[i] = (TQ)(sq[t + 2] - dt * (sf[t + 1] - sf[t]) / (x[i + 1] - x[i]));
+        const CT inv = R.has_tab ? TabT<CT>::dxinv(R.tab)[i] : (CT)(1.0 / (x[i + 1] - x[i]));
+        qo[i] = (TQ)(sq[t + 2] - dt * (sf[t + 1] - sf[t]) * inv);
     }
 }
 
 // ---------------------------------------------------------------------------
-// ragged-row tile table: tile_ptr[r] = sum_{r'<r} ceil(N_r'/kTile) and
+// mesh-only tables of a shared mesh
+// ---------------------------------------------------------------------------
+
+struct MeshTabW {
+    double *dx, *dxinv, *hinv, *rden;
+    float *dxf, *dxinvf, *hinvf, *rdenf;
+    int32_t *bucket;
+    int32_t nb;
+    double *bscale;
+};
+
+template <int P>
+__global__ __launch_bounds__(256) void k_mesh_prep(const double *x, int n, MeshTabW T)
+{
+    constexpr int LO = (P - 1) / 2;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const double len = x[n] - x[0];
+    if (j < n) {
+        const double dx = x[j + 1] - x[j];
+        const double h = centre_gap(x, n, len, j);
+        T.dx[j] = dx;
+        T.dxinv[j] = 1.0 / dx;
+        T.hinv[j] = 1.0 / h;
+        T.dxf[j] = (float)dx;
+        T.dxinvf[j] = (float)(1.0 / dx);
+        T.hinvf[j] = (float)(1.0 / h);
+        double X[P + 1];
+        for (int a = 0; a <= P; ++a) X[a] = node_x(x, n, len, j - LO + a);
+        double scale = 1.0;
+        for (int a = 0; a < P; ++a) scale *= dx;
+        for (int a = 0; a <= P; ++a) {
+            double den = 1.0;
+            for (int b = 0; b <= P; ++b)
+                if (b != a) den *= X[a] - X[b];
+            T.rden[j * (P + 1) + a] = 1.0 / den;
+            // FP32 weights take node offsets in units of dx_j
+            T.rdenf[j * (P + 1) + a] = (float)(scale / den);
+        }
+    }
+    if (j < T.nb) T.bucket[j] = find_cell(x, n, x[0] + (double)j * (len / (double)T.nb));
+    if (j == 0) *T.bscale = (double)T.nb / len;
+}
+
+// ---------------------------------------------------------------------------
+// ragged-row tile table: tile_ptr[r] = sum_{r'<r} ceil(N_r'/tile) and
 // tile_row[t] = row of tile t.  One workgroup of 1024 threads.
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(1024) void k_tiles_prep(const int64_t *row_ptr,
-                                                     int64_t n_rows,
+                                                     int64_t n_rows, int tile,
                                                      int64_t *tile_ptr,
                                                      int32_t *tile_row)
 {
@@ -260,10 +441,9 @@ __global__ __launch_bounds__(1024) void k_tiles_prep(const int64_t *row_ptr,
     const int64_t r1 = min(n_rows, r0 + per);
     int64_t run = 0;
     for (int64_t r = r0; r < r1; ++r)
-        run += (row_ptr[r + 1] - row_ptr[r] + kTile - 1) / kTile;
+        run += (row_ptr[r + 1] - row_ptr[r] + tile - 1) / tile;
     stot[threadIdx.x] = run;
     __syncthreads();
-    // inclusive Hillis-Steele scan of the 1024 chunk totals
     for (int d = 1; d < 1024; d <<= 1) {
         const int64_t o = threadIdx.x >= (unsigned)d ? stot[threadIdx.x - d] : 0;
         __syncthreads();
@@ -273,59 +453,91 @@ __global__ __launch_bounds__(1024) void k_tiles_prep(const int64_t *row_ptr,
     int64_t acc = stot[threadIdx.x] - run;
     for (int64_t r = r0; r < r1; ++r) {
         tile_ptr[r] = acc;
-        const int64_t nt = (row_ptr[r + 1] - row_ptr[r] + kTile - 1) / kTile;
-        for (int64_t t = 0; t < nt; ++t) tile_row[acc + t] = (int32_t)r;
+        const int64_t nt = (row_ptr[r + 1] - row_ptr[r] + tile - 1) / tile;
+        for (int64_t k = 0; k < nt; ++k) tile_row[acc + k] = (int32_t)r;
         acc += nt;
     }
     if (threadIdx.x == 1023) tile_ptr[n_rows] = stot[1023];
 }
 
 template <typename TQ, int P>
-hipError_t shift_dispatch_scan(const ShiftArgs &a, int scan, hipStream_t st)
+hipError_t step_scan(const StepArgs &a, int scan, hipStream_t st)
 {
-    const dim3 grid((unsigned)a.rows.n_tiles), block(kBlock);
+    const dim3 g((unsigned)a.rows.n_tiles), b(kBlock);
     switch (scan) {
-    case kScanF64:
-        hipLaunchKernelGGL((k_shift<TQ, P, kScanF64>), grid, block, 0, st, a);
-        break;
-    case kScanTwoSum:
-        hipLaunchKernelGGL((k_shift<TQ, P, kScanTwoSum>), grid, block, 0, st, a);
-        break;
-    default:
-        hipLaunchKernelGGL((k_shift<TQ, P, kScanF32>), grid, block, 0, st, a);
-        break;
+    case kScanF64: hipLaunchKernelGGL((k_step<TQ, P, kScanF64>), g, b, 0, st, a); break;
+    case kScanTwoSum: hipLaunchKernelGGL((k_step<TQ, P, kScanTwoSum>), g, b, 0, st, a); break;
+    default: hipLaunchKernelGGL((k_step<TQ, P, kScanF32>), g, b, 0, st, a); break;
     }
     return hipGetLastError();
 }
 
 template <typename TQ>
-hipError_t shift_dispatch(const ShiftArgs &a, int scan, int order, hipStream_t st)
+hipError_t step_order(const StepArgs &a, int scan, int order, hipStream_t st)
 {
     switch (order) {
-    case 1: return shift_dispatch_scan<TQ, 1>(a, scan, st);
-    case 3: return shift_dispatch_scan<TQ, 3>(a, scan, st);
-    default: return shift_dispatch_scan<TQ, 5>(a, scan, st);
+    case 1: return step_scan<TQ, 1>(a, scan, st);
+    case 3: return step_scan<TQ, 3>(a, scan, st);
+    default: return step_scan<TQ, 5>(a, scan, st);
     }
 }
 
+size_t al256(size_t v) { return (v + 255) & ~size_t(255); }
+
 } // namespace
 
-hipError_t launch_tiles_prep(const int64_t *row_ptr, int64_t n_rows,
+size_t mesh_tab_bytes(int64_t n, int order)
+{
+    const int64_t nb = 4 * n;
+    return 3 * al256(8 * n) + 3 * al256(4 * n) + al256(8 * n * (order + 1)) +
+           al256(4 * n * (order + 1)) + al256(4 * nb) + al256(8);
+}
+
+hipError_t launch_mesh_prep(const double *x, int64_t n, int order, void *mem,
+                            MeshTab &tab, hipStream_t stream)
+{
+    char *p = (char *)mem;
+    MeshTabW w;
+    w.dx = (double *)p; p += al256(8 * n);
+    w.dxinv = (double *)p; p += al256(8 * n);
+    w.hinv = (double *)p; p += al256(8 * n);
+    w.dxf = (float *)p; p += al256(4 * n);
+    w.dxinvf = (float *)p; p += al256(4 * n);
+    w.hinvf = (float *)p; p += al256(4 * n);
+    w.rden = (double *)p; p += al256(8 * n * (order + 1));
+    w.rdenf = (float *)p; p += al256(4 * n * (order + 1));
+    w.bucket = (int32_t *)p; p += al256(4 * 4 * n);
+    w.nb = (int32_t)(4 * n);
+    w.bscale = (double *)p;
+    tab.dx = w.dx; tab.dxinv = w.dxinv; tab.hinv = w.hinv; tab.rden = w.rden;
+    tab.dxf = w.dxf; tab.dxinvf = w.dxinvf; tab.hinvf = w.hinvf; tab.rdenf = w.rdenf;
+    tab.bucket = w.bucket;
+    tab.nb = w.nb;
+    tab.bscale = w.bscale;
+    const unsigned grid = (unsigned)((w.nb + 255) / 256);
+    switch (order) {
+    case 1: hipLaunchKernelGGL(k_mesh_prep<1>, dim3(grid), dim3(256), 0, stream, x, (int)n, w); break;
+    case 3: hipLaunchKernelGGL(k_mesh_prep<3>, dim3(grid), dim3(256), 0, stream, x, (int)n, w); break;
+    default: hipLaunchKernelGGL(k_mesh_prep<5>, dim3(grid), dim3(256), 0, stream, x, (int)n, w); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_tiles_prep(const int64_t *row_ptr, int64_t n_rows, int tile,
                              int64_t *tile_ptr, int32_t *tile_row,
                              hipStream_t stream)
 {
     hipLaunchKernelGGL(k_tiles_prep, dim3(1), dim3(1024), 0, stream, row_ptr,
-                       n_rows, tile_ptr, tile_row);
+                       n_rows, tile, tile_ptr, tile_row);
     return hipGetLastError();
 }
 
-hipError_t launch_shift(const ShiftArgs &a, bool f64, int scan, int order,
-                        hipStream_t stream)
+hipError_t launch_step(const StepArgs &a, bool f64, int scan, int order,
+                       hipStream_t stream)
 {
     if (a.rows.n_tiles <= 0) return hipSuccess;
-    // FP64 state always scans in FP64
-    if (f64) return shift_dispatch<double>(a, kScanF64, order, stream);
-    return shift_dispatch<float>(a, scan, order, stream);
+    if (f64) return step_order<double>(a, kScanF64, order, stream);
+    return step_order<float>(a, scan, order, stream);
 }
 
 hipError_t launch_residual(const ResidualArgs &a, bool f64, hipStream_t stream)
