@@ -95,10 +95,12 @@ inline int64_t ragged_tile_bound(int64_t n_cells, int64_t n_rows, int tile)
     return n_cells / tile + n_rows + 1;
 }
 
-// Destination cells per tile of the bulk-shift kernel: one shifted node per
-// thread, so kBlock-1 cells, less a two-cell halo per side when the residual
-// step is fused in.
-inline int step_tile(bool fused) { return kBlock - 1 - (fused ? 4 : 0); }
+// Shifted nodes per thread in the bulk-shift kernel, and its destination
+// cells per tile: kBlock*kItems nodes bound kBlock*kItems-1 cells, less a
+// two-cell halo per side when the residual step is fused in.
+constexpr int kItems = 4;
+constexpr int kStepNodes = kBlock * kItems;
+inline int step_tile(bool fused) { return kStepNodes - 1 - (fused ? 4 : 0); }
 
 hipError_t launch_tiles_prep(const int64_t *row_ptr, int64_t n_rows, int tile,
                              int64_t *tile_ptr, int32_t *tile_row,

@@ -38,7 +38,6 @@ namespace {
 
 using namespace dev;
 
-constexpr int kWin = 1024;          // LDS window capacity, source cells
 
 // Periodic index for j in [-n, k n).
 __device__ inline int wrap_small(int j, int n)
@@ -143,6 +142,21 @@ __device__ inline void stencil_weights(const double *x, int n, double len,
 // bulk shift, optionally fused with the residual step
 // ---------------------------------------------------------------------------
 
+constexpr int kWinStep = 1536;      // LDS window capacity of k_step, cells
+
+// LDS of k_step.  The window (masses + prefix) is dead once the destination
+// masses are formed, so the shifted state, slopes and fluxes of the fused
+// residual reuse its bytes; the node indices of the exact-window path use
+// them before the window is loaded.
+template <typename M, typename A, typename D, typename CT>
+struct StepLds {
+    static constexpr size_t win = sizeof(M) * kWinStep + sizeof(A) * (kWinStep + 1);
+    static constexpr size_t res = 3 * sizeof(CT) * kStepNodes;
+    static constexpr size_t nodes = sizeof(int64_t) * kStepNodes;
+    static constexpr size_t uni0 = win > res ? win : res;
+    static constexpr size_t uni = uni0 > nodes ? uni0 : nodes;
+};
+
 template <typename TQ, int P, int S>
 __global__ __launch_bounds__(kBlock) void k_step(StepArgs a)
 {
@@ -152,19 +166,22 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a)
     using D = typename std::conditional<std::is_same<TQ, double>::value, double,
                                         typename AC::D>::type;
     using CT = TQ;                     // arithmetic type of the state updates
+    using L = StepLds<M, A, D, CT>;
     constexpr int LO = (P - 1) / 2;
+    constexpr int NI = kItems;
 
-    __shared__ int64_t sg[kBlock];     // extended source index of each node
-    __shared__ D sell[kBlock];         // partial integral C~(xh) - C(c)
-    __shared__ int sjc[kBlock];        // window index of node c
-    __shared__ M sm[kWin];             // window cell masses
-    __shared__ A sp[kWin + 1];         // exclusive prefix of sm
+    __shared__ int sjc[kStepNodes];    // window index of each node's cell
+    __shared__ D sell[kStepNodes];     // partial integral C~(xh) - C(c)
     __shared__ A swt[kBlock / 64];
-    __shared__ CT sq[kBlock];          // shifted state (fused path)
-    __shared__ CT ssig[kBlock];        // van Leer slopes
-    __shared__ CT sf[kBlock];          // face fluxes
-    __shared__ int s_ok;
-    __shared__ int s_base;
+    __shared__ __attribute__((aligned(16))) unsigned char su[L::uni];
+    __shared__ int s_flag;             // 1: window path usable
+    __shared__ long long s_wlo, s_whi;
+    M *sm = (M *)su;                                     // window masses
+    A *sp = (A *)(su + sizeof(M) * kWinStep);            // exclusive prefix
+    int64_t *sg = (int64_t *)su;                         // node indices
+    CT *sq = (CT *)su;                                   // shifted state
+    CT *ssig = sq + kStepNodes;                          // van Leer slopes
+    CT *sf = ssig + kStepNodes;                          // face fluxes
 
     const Rows &R = a.rows;
     Tile ti;
@@ -175,48 +192,102 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a)
     const int i0 = ti.i0;
     const int nd = min(R.tile, n - i0);         // cells this tile writes
     const int NC = nd + 2 * H;                  // shifted cells
-    const int NE = NC + 1;                      // shifted nodes (<= kBlock)
+    const int NE = NC + 1;                      // shifted nodes (<= kStepNodes)
     const double *x = ti.x;
     const TQ *q = (const TQ *)a.q_in + ti.qoff;
     TQ *qo = (TQ *)a.q_out + ti.qoff;
     const double s = a.v0[ti.row] * a.dt;
     const double len = x[n] - x[0];
     const int t = threadIdx.x;
+    const bool tab = R.has_tab != 0;
+    const double bsc = tab ? *R.tab.bscale : 0.0;
 
-    // (A) shifted node t = destination node i0 - H + t: cell and weights
-    int64_t g = 0;
-    double xh = 0.0;
-    TQ w[P + 1];
-    if (t < NE) {
-        int e = i0 - H + t;
+    // residual velocity of the faces this thread will need, fetched early
+    const TQ *dv = H ? (const TQ *)a.dv + ti.qoff : nullptr;
+    TQ dvr[NI];
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        const int f = t + k * kBlock;
+        dvr[k] = (H && f < nd + 1) ? dv[wrap_small(i0 + f, n)] : (TQ)0;
+    }
+
+    // conservative window from the bucket index (shared mesh): the first and
+    // last shifted nodes' buckets, widened by one bucket and the stencil
+    if (tab && t < 2) {
+        int e = t == 0 ? i0 - H : i0 - H + NE - 1;
         int kx = 0;
         if (e < 0) { e += n; kx = -1; }
         while (e >= n) { e -= n; kx += 1; }
+        double xh;
         int64_t k;
         shifted_node(x, n, s, e, xh, k);
-        const int c = R.has_tab ? find_cell_tab(x, n, R.tab, *R.tab.bscale, xh)
-                               : find_cell(x, n, xh);
-        g = (int64_t)c + (k + kx) * (int64_t)n;
-        stencil_weights<TQ, P>(x, n, len, R, c, xh, w);
-        sg[t] = g;
+        int b = (int)((xh - x[0]) * bsc);
+        b = min(max(b, 0), R.tab.nb - 1);
+        int64_t gb;
+        if (t == 0) {
+            gb = (int64_t)R.tab.bucket[max(b - 1, 0)] + (k + kx) * (int64_t)n;
+            s_wlo = gb - LO - 1;
+        } else {
+            gb = (int64_t)R.tab.bucket[min(b + 2, R.tab.nb - 1)] + (k + kx) * (int64_t)n;
+            if (b + 2 >= R.tab.nb) gb = (int64_t)n + (k + kx) * (int64_t)n;
+            s_whi = gb - LO + P + 2;
+        }
     }
-    if (t == 0) s_ok = 1;
+    if (t == 0) s_flag = 1;
+
+    // (A) shifted nodes e = i0 - H + t + k kBlock: cell and stencil weights
+    int64_t g[NI];
+    TQ w[NI][P + 1];
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        const int ei = t + k * kBlock;
+        g[k] = 0;
+        if (ei < NE) {
+            int e = i0 - H + ei;
+            int kx = 0;
+            if (e < 0) { e += n; kx = -1; }
+            while (e >= n) { e -= n; kx += 1; }
+            double xh;
+            int64_t kk;
+            shifted_node(x, n, s, e, xh, kk);
+            const int c = tab ? find_cell_tab(x, n, R.tab, bsc, xh) : find_cell(x, n, xh);
+            g[k] = (int64_t)c + (kk + kx) * (int64_t)n;
+            stencil_weights<TQ, P>(x, n, len, R, c, xh, w[k]);
+        }
+    }
+    if (!tab) {
+        // exact window from the first and last node
+#pragma unroll
+        for (int k = 0; k < NI; ++k)
+            if (t + k * kBlock < NE) sg[t + k * kBlock] = g[k];
+        __syncthreads();
+        if (t == 0) {
+            s_wlo = sg[0] - LO;
+            s_whi = sg[NE - 1] - LO + P;
+        }
+    }
     __syncthreads();
-    // source indices must not decrease along the tile (otherwise: direct path)
-    if (t >= 1 && t < NE && sg[t] < sg[t - 1]) s_ok = 0;
-    const int64_t wlo = sg[0] - LO;
-    if (t == 0) s_base = wrapi(wlo, n);
+    const int64_t wlo = s_wlo;
+    const int64_t wide = s_whi - s_wlo;
+    // every node's stencil must lie inside the window (else: direct path)
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        if (t + k * kBlock < NE) {
+            const int64_t jc = g[k] - wlo;
+            if (jc < LO || jc + P - LO > wide) s_flag = 0;
+        }
+    }
+    if (wide > kWinStep || wide < P) s_flag = 0;
     __syncthreads();
-    const int64_t wide = sg[NE - 1] - sg[0] + P;
-    const bool windowed = s_ok && wide <= kWin;
+    const bool windowed = s_flag != 0;
 
     if (windowed) {
         const int W = (int)wide;
-        const int base = s_base;
+        const int base = wrapi(wlo, n);
         // (B) window masses and the block scan into the cumulative
         for (int j = t; j < W; j += kBlock) {
             const int mm = wrap_small(base + j, n);
-            if (R.has_tab) sm[j] = (M)q[mm] * TabT<M>::dx(R.tab)[mm];
+            if (tab) sm[j] = (M)q[mm] * TabT<M>::dx(R.tab)[mm];
             else sm[j] = AC::template mass<TQ>(q[mm], x[mm + 1] - x[mm]);
         }
         __syncthreads();
@@ -234,84 +305,121 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a)
         if (t == 0) sp[W] = total;
         __syncthreads();
         // (C) partial integrals from the interpolated window cumulative
-        if (t < NE) {
-            const int jc = (int)(g - wlo);
-            const A pc = sp[jc];
-            D ell = (D)0;
 #pragma unroll
-            for (int b = 0; b <= P; ++b)
-                if (b != LO) ell += (D)w[b] * (D)AC::diff(sp[jc - LO + b], pc);
-            sell[t] = ell;
-            sjc[t] = jc;
+        for (int k = 0; k < NI; ++k) {
+            const int ei = t + k * kBlock;
+            if (ei < NE) {
+                const int jc = (int)(g[k] - wlo);
+                const A pc = sp[jc];
+                D ell = (D)0;
+#pragma unroll
+                for (int b = 0; b <= P; ++b)
+                    if (b != LO) ell += (D)w[k][b] * (D)AC::diff(sp[jc - LO + b], pc);
+                sell[ei] = ell;
+                sjc[ei] = jc;
+            }
         }
     } else {
         // direct path: masses summed from global memory in FP64
-        if (t < NE) sell[t] = (D)partial_direct<TQ, P>(x, q, n, len, g, xh);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+            const int ei = t + k * kBlock;
+            if (ei < NE) {
+                sg[ei] = g[k];
+                int e = i0 - H + ei;
+                if (e < 0) e += n;
+                while (e >= n) e -= n;
+                double xh;
+                int64_t kk;
+                shifted_node(x, n, s, e, xh, kk);
+                sell[ei] = (D)partial_direct<TQ, P>(x, q, n, len, g[k], xh);
+            }
+        }
     }
     __syncthreads();
 
     // (D) destination masses and Step 3
-    if (t < NC) {
-        const int cell = wrap_small(i0 - H + t, n);
-        D mp;
-        if (windowed) {
-            const int ja = sjc[t], jb = sjc[t + 1];
-            const D whole = (jb - ja == 1) ? (D)sm[ja] : (D)AC::diff(sp[jb], sp[ja]);
-            mp = whole + (sell[t + 1] - sell[t]);
-        } else {
-            double wh = 0.0;
-            for (int64_t m = sg[t]; m < sg[t + 1]; ++m) wh += cell_mass(x, q, n, m);
-            mp = (D)(wh + ((double)sell[t + 1] - (double)sell[t]));
+    CT qs[NI];
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        const int ci = t + k * kBlock;
+        qs[k] = (CT)0;
+        if (ci < NC) {
+            const int cell = wrap_small(i0 - H + ci, n);
+            D mp;
+            if (windowed) {
+                const int ja = sjc[ci], jb = sjc[ci + 1];
+                const D whole = (jb - ja == 1) ? (D)sm[ja] : (D)AC::diff(sp[jb], sp[ja]);
+                mp = whole + (sell[ci + 1] - sell[ci]);
+            } else {
+                double wh = 0.0;
+                for (int64_t m = sg[ci]; m < sg[ci + 1]; ++m) wh += cell_mass(x, q, n, m);
+                mp = (D)(wh + ((double)sell[ci + 1] - (double)sell[ci]));
+            }
+            if (tab) qs[k] = (CT)(mp * (D)TabT<D>::dxinv(R.tab)[cell]);
+            else qs[k] = (CT)(mp / (D)(x[cell + 1] - x[cell]));
+            if (H == 0) qo[cell] = (TQ)qs[k];
         }
-        CT qs;
-        if (R.has_tab) qs = (CT)(mp * (D)TabT<D>::dxinv(R.tab)[cell]);
-        else qs = (CT)(mp / (D)(x[cell + 1] - x[cell]));
-        if (H == 0) qo[cell] = (TQ)qs;
-        else sq[t] = qs;
     }
     if (H == 0) return;
+    __syncthreads();   // the window bytes become the residual's arrays
+#pragma unroll
+    for (int k = 0; k < NI; ++k)
+        if (t + k * kBlock < NC) sq[t + k * kBlock] = qs[k];
     __syncthreads();
 
-    // (E) van Leer slopes of cells i0-1 .. i0+nd (state index t+1)
-    const TQ *dv = (const TQ *)a.dv + ti.qoff;
+    // (E) van Leer slopes of cells i0-1 .. i0+nd (state index +1)
     const CT dt = (CT)a.dt;
-    if (t < nd + 2) {
-        const int cm = wrap_small(i0 - 2 + t, n);
-        const int c0 = wrap_small(i0 - 1 + t, n);
-        CT hp, hm;
-        if (R.has_tab) {
-            hp = TabT<CT>::hinv(R.tab)[c0];
-            hm = TabT<CT>::hinv(R.tab)[cm];
-        } else {
-            hp = (CT)(1.0 / centre_gap(x, n, len, c0));
-            hm = (CT)(1.0 / centre_gap(x, n, len, cm));
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        const int u = t + k * kBlock;
+        if (u < nd + 2) {
+            const int cm = wrap_small(i0 - 2 + u, n);
+            const int c0 = wrap_small(i0 - 1 + u, n);
+            CT hp, hm;
+            if (tab) {
+                hp = TabT<CT>::hinv(R.tab)[c0];
+                hm = TabT<CT>::hinv(R.tab)[cm];
+            } else {
+                hp = (CT)(1.0 / centre_gap(x, n, len, c0));
+                hm = (CT)(1.0 / centre_gap(x, n, len, cm));
+            }
+            const CT dp = (sq[u + 2] - sq[u + 1]) * hp;
+            const CT dm = (sq[u + 1] - sq[u]) * hm;
+            ssig[u] = (dp * dm <= (CT)0) ? (CT)0 : (CT)2 * dp * dm / (dp + dm);
         }
-        const CT dp = (sq[t + 2] - sq[t + 1]) * hp;
-        const CT dm = (sq[t + 1] - sq[t]) * hm;
-        ssig[t] = (dp * dm <= (CT)0) ? (CT)0 : (CT)2 * dp * dm / (dp + dm);
     }
     __syncthreads();
     // (F) fluxes on faces i0 .. i0+nd (face f between cells f-1 and f)
-    if (t < nd + 1) {
-        const int f = wrap_small(i0 + t, n);
-        const CT v = (CT)dv[f];
-        CT qf;
-        if (v >= (CT)0) {
-            const int u = wrap_small(i0 + t - 1, n);
-            const CT dxu = R.has_tab ? TabT<CT>::dx(R.tab)[u] : (CT)(x[u + 1] - x[u]);
-            qf = sq[t + 1] + (CT)0.5 * ssig[t] * (dxu - v * dt);
-        } else {
-            const CT dxu = R.has_tab ? TabT<CT>::dx(R.tab)[f] : (CT)(x[f + 1] - x[f]);
-            qf = sq[t + 2] - (CT)0.5 * ssig[t + 1] * (dxu + v * dt);
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        const int u = t + k * kBlock;
+        if (u < nd + 1) {
+            const int f = wrap_small(i0 + u, n);
+            const CT v = (CT)dvr[k];
+            CT qf;
+            if (v >= (CT)0) {
+                const int c = wrap_small(i0 + u - 1, n);
+                const CT dxu = tab ? TabT<CT>::dx(R.tab)[c] : (CT)(x[c + 1] - x[c]);
+                qf = sq[u + 1] + (CT)0.5 * ssig[u] * (dxu - v * dt);
+            } else {
+                const CT dxu = tab ? TabT<CT>::dx(R.tab)[f] : (CT)(x[f + 1] - x[f]);
+                qf = sq[u + 2] - (CT)0.5 * ssig[u + 1] * (dxu + v * dt);
+            }
+            sf[u] = v * qf;
         }
-        sf[t] = v * qf;
     }
     __syncthreads();
     // (G) conservative update of the tile's own cells
-    if (t < nd) {
-        const int i = i0 + t;
-        const CT inv = R.has_tab ? TabT<CT>::dxinv(R.tab)[i] : (CT)(1.0 / (x[i + 1] - x[i]));
-        qo[i] = (TQ)(sq[t + 2] - dt * (sf[t + 1] - sf[t]) * inv);
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        const int u = t + k * kBlock;
+        if (u < nd) {
+            const int i = i0 + u;
+            const CT inv = tab ? TabT<CT>::dxinv(R.tab)[i] : (CT)(1.0 / (x[i + 1] - x[i]));
+            qo[i] = (TQ)(sq[u + 2] - dt * (sf[u + 1] - sf[u]) * inv);
+        }
     }
 }
 
