@@ -93,6 +93,48 @@ __device__ inline void shifted_node(const double *x, int n, double s, int e,
     else if (xh < x[0]) { xh += len; k -= 1; }
 }
 
+// Same as shifted_node with the division by L replaced by a product with
+// 1/L: the wrap fix-ups keep xh in [x0, xN) and xh + k L = x~ either way.
+__device__ inline void shifted_node_inv(const double *x, int n, double s, int e,
+                                        double invlen, double len, double &xh,
+                                        int64_t &k)
+{
+    const double xt = x[e] - s;
+    const double kf = floor((xt - x[0]) * invlen);
+    xh = xt - kf * len;
+    k = (int64_t)kf;
+    if (xh >= x[n]) { xh -= len; k += 1; }
+    else if (xh < x[0]) { xh += len; k -= 1; }
+}
+
+// DPP lane movements of a wave64 (GFX9 encodings): shift right within a row
+// of 16 lanes, broadcast of lane 15 / 31 to the following rows, and a shift
+// right by one lane across the whole wave.  Lanes without a source read 0.
+enum : int {
+    kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114,
+    kDppRowShr8 = 0x118, kDppWaveShr1 = 0x138, kDppBcast15 = 0x142,
+    kDppBcast31 = 0x143
+};
+
+template <int CTRL, int RM, int BM>
+__device__ inline int dpp_i(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, RM, BM, false);
+}
+template <int CTRL, int RM, int BM>
+__device__ inline float dpp_f(float v)
+{
+    return __int_as_float(dpp_i<CTRL, RM, BM>(__float_as_int(v)));
+}
+template <int CTRL, int RM, int BM>
+__device__ inline double dpp_d(double v)
+{
+    const long long u = __double_as_longlong(v);
+    const int lo = dpp_i<CTRL, RM, BM>((int)(u & 0xffffffffll));
+    const int hi = dpp_i<CTRL, RM, BM>((int)(u >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 template <int P>
 __device__ inline void lagrange_weights(double xh, const double *X, double *w)
 {
@@ -136,6 +178,7 @@ template <> struct Acc<kScanF64> {
     __device__ static A comb(A a, A b) { return a + b; }
     __device__ static D diff(A b, A a) { return b - a; }
     __device__ static A shfl_up(A v, int d) { return __shfl_up(v, d); }
+    template <int C, int RM, int BM> __device__ static A dpp(A v) { return dpp_d<C, RM, BM>(v); }
 };
 
 template <> struct Acc<kScanTwoSum> {
@@ -169,6 +212,10 @@ template <> struct Acc<kScanTwoSum> {
     {
         return make_float2(__shfl_up(v.x, d), __shfl_up(v.y, d));
     }
+    template <int C, int RM, int BM> __device__ static A dpp(A v)
+    {
+        return make_float2(dpp_f<C, RM, BM>(v.x), dpp_f<C, RM, BM>(v.y));
+    }
 };
 
 template <> struct Acc<kScanF32> {
@@ -182,6 +229,7 @@ template <> struct Acc<kScanF32> {
     __device__ static A comb(A a, A b) { return a + b; }
     __device__ static D diff(A b, A a) { return b - a; }
     __device__ static A shfl_up(A v, int d) { return __shfl_up(v, d); }
+    template <int C, int RM, int BM> __device__ static A dpp(A v) { return dpp_f<C, RM, BM>(v); }
 };
 
 // Exclusive scan over the workgroup of one value per thread; also returns
@@ -200,6 +248,40 @@ __device__ typename AC::A block_exscan(typename AC::A v, typename AC::A *wave_to
         if (lane >= d) inc = AC::comb(o, inc);
     }
     A exc = AC::shfl_up(inc, 1);
+    if (lane == 0) exc = AC::zero();
+    if (lane == 63) wave_tot[wid] = inc;
+    __syncthreads();
+    A off = AC::zero();
+    A tot = AC::zero();
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+        if (w < wid) off = AC::comb(off, wave_tot[w]);
+        tot = AC::comb(tot, wave_tot[w]);
+    }
+    total = tot;
+    __syncthreads();
+    return AC::comb(off, exc);
+}
+
+// Exclusive scan over the workgroup of one value per thread, with DPP lane
+// movements inside each wave and the wave totals combined through LDS; also
+// returns the total.  wave_tot: LDS scratch of kBlock/64 entries.
+template <class AC>
+__device__ typename AC::A block_exscan_dpp(typename AC::A v,
+                                           typename AC::A *wave_tot,
+                                           typename AC::A &total)
+{
+    using A = typename AC::A;
+    const int lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
+    A inc = v;
+    inc = AC::comb(AC::template dpp<kDppRowShr1, 0xf, 0xf>(inc), inc);
+    inc = AC::comb(AC::template dpp<kDppRowShr2, 0xf, 0xf>(inc), inc);
+    inc = AC::comb(AC::template dpp<kDppRowShr4, 0xf, 0xf>(inc), inc);
+    inc = AC::comb(AC::template dpp<kDppRowShr8, 0xf, 0xf>(inc), inc);
+    inc = AC::comb(AC::template dpp<kDppBcast15, 0xa, 0xf>(inc), inc);
+    inc = AC::comb(AC::template dpp<kDppBcast31, 0xc, 0xf>(inc), inc);
+    A exc = AC::template dpp<kDppWaveShr1, 0xf, 0xf>(inc);
     if (lane == 0) exc = AC::zero();
     if (lane == 63) wave_tot[wid] = inc;
     __syncthreads();

@@ -24,15 +24,20 @@ struct MeshTab {
     const double *dx = nullptr;
     const double *dxinv = nullptr;
     const double *hinv = nullptr;     // 1 / (centre_{j+1} - centre_j), periodic
-    const double *rden = nullptr;     // [n][order+1]
+    const double *stc = nullptr;      // [n][2(order+1)]: stencil data, below
     const float *dxf = nullptr;
     const float *dxinvf = nullptr;
     const float *hinvf = nullptr;
-    const float *rdenf = nullptr;     // scaled by dx_j^order (see k_mesh_prep)
+    const float *stcf = nullptr;
     const int32_t *bucket = nullptr;  // largest j with x_j <= x0 + b L / nb
     int32_t nb = 0;
-    const double *bscale = nullptr;   // device scalar nb / L
+    const double *scal = nullptr;     // device scalars: nb / L, 1 / L
 };
+// Stencil data of source cell c (order p, lo = (p-1)/2), in units of dx_c:
+//   stc[c][a]       = (x_{c-lo+a} - x_c) / dx_c                   a = 0..p
+//   stc[c][p+1+a]   = 1 / prod_{b != a} (stc[c][a] - stc[c][b])
+// so the Lagrange weight of node a at theta = (xh - x_c)/dx_c is
+//   stc[c][p+1+a] * prod_{b != a} (theta - stc[c][b]).
 
 // Where the rows are.  Uniform batches (n_cols > 0) map tile t to
 // (row = t / tiles_per_row, start = (t % tiles_per_row) * kTile); ragged

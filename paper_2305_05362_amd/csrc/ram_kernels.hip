@@ -94,33 +94,32 @@ template <> struct TabT<float> {
     __device__ static const float *hinv(const MeshTab &t) { return t.hinvf; }
 };
 
-// Lagrange weights of the stencil nodes c-LO .. c-LO+P at xh, in WT.  Shared
-// meshes read the reciprocal denominators from the table (FP32: scaled by
-// dx_c^P, with the node offsets in units of dx_c, so every factor is O(1)).
+// Lagrange weights of the stencil nodes c-LO .. c-LO+P at xh, in WT.
+// Shared meshes use the per-cell stencil table: node offsets and reciprocal
+// denominators in units of dx_c, so only theta = (xh - x_c)/dx_c is formed in
+// FP64 and every factor is O(1).  Per-row meshes form the weights from the
+// nodes directly.
 template <typename WT, int P>
 __device__ inline void stencil_weights(const double *x, int n, double len,
                                        const Rows &R, int c, double xh, WT *w)
 {
     constexpr int LO = (P - 1) / 2;
-    double X[P + 1];
-#pragma unroll
-    for (int a = 0; a <= P; ++a) X[a] = node_x(x, n, len, c - LO + a);
     if (!R.has_tab) {
-        double wd[P + 1];
+        double X[P + 1], wd[P + 1];
+#pragma unroll
+        for (int a = 0; a <= P; ++a) X[a] = node_x(x, n, len, c - LO + a);
         lagrange_weights<P>(xh, X, wd);
 #pragma unroll
         for (int a = 0; a <= P; ++a) w[a] = (WT)wd[a];
         return;
     }
+    const WT *st;
+    if constexpr (std::is_same<WT, double>::value) st = R.tab.stc + c * (2 * (P + 1));
+    else st = R.tab.stcf + c * (2 * (P + 1));
+    const WT th = (WT)((xh - x[c]) * R.tab.dxinv[c]);
     WT t[P + 1];
-    if constexpr (std::is_same<WT, double>::value) {
 #pragma unroll
-        for (int a = 0; a <= P; ++a) t[a] = xh - X[a];
-    } else {
-        const double sc = R.tab.dxinv[c];
-#pragma unroll
-        for (int a = 0; a <= P; ++a) t[a] = (float)((xh - X[a]) * sc);
-    }
+    for (int a = 0; a <= P; ++a) t[a] = th - st[a];
     // products of all t but one, from prefix and suffix products
     WT pre[P + 1], suf[P + 1];
     pre[0] = (WT)1;
@@ -130,12 +129,43 @@ __device__ inline void stencil_weights(const double *x, int n, double len,
 #pragma unroll
     for (int a = P - 1; a >= 0; --a) suf[a] = suf[a + 1] * t[a + 1];
 #pragma unroll
-    for (int a = 0; a <= P; ++a) {
-        WT rd;
-        if constexpr (std::is_same<WT, double>::value) rd = R.tab.rden[c * (P + 1) + a];
-        else rd = R.tab.rdenf[c * (P + 1) + a];
-        w[a] = rd * (pre[a] * suf[a]);
-    }
+    for (int a = 0; a <= P; ++a) w[a] = st[P + 1 + a] * (pre[a] * suf[a]);
+}
+
+// Direct path of k_step (tiles whose source window does not fit in LDS):
+// partial integrals from global memory, FP64.
+template <typename TQ, int P>
+__device__ __attribute__((noinline)) double direct_partial(
+    const double *x, const TQ *q, int n, double len, double s, double invlen,
+    int e, int64_t g)
+{
+    if (e < 0) e += n;
+    while (e >= n) e -= n;
+    double xh;
+    int64_t kk;
+    shifted_node_inv(x, n, s, e, invlen, len, xh, kk);
+    return partial_direct<TQ, P>(x, q, n, len, g, xh);
+}
+
+template <typename TQ>
+__device__ __attribute__((noinline)) double direct_whole(const double *x,
+                                                         const TQ *q, int n,
+                                                         int64_t ga, int64_t gb)
+{
+    double wh = 0.0;
+    for (int64_t m = ga; m < gb; ++m) wh += cell_mass(x, q, n, m);
+    return wh;
+}
+
+// 2ab/(a+b) of the van Leer slope (a b > 0): FP32 with the hardware
+// reciprocal, FP64 with a division.
+__device__ inline float harmonic2(float a, float b)
+{
+    return 2.0f * a * b * __builtin_amdgcn_rcpf(a + b);
+}
+__device__ inline double harmonic2(double a, double b)
+{
+    return 2.0 * a * b / (a + b);
 }
 
 // ---------------------------------------------------------------------------
@@ -200,7 +230,8 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a)
     const double len = x[n] - x[0];
     const int t = threadIdx.x;
     const bool tab = R.has_tab != 0;
-    const double bsc = tab ? *R.tab.bscale : 0.0;
+    const double bsc = tab ? R.tab.scal[0] : 0.0;
+    const double invlen = tab ? R.tab.scal[1] : 1.0 / len;
 
     // residual velocity of the faces this thread will need, fetched early
     const TQ *dv = H ? (const TQ *)a.dv + ti.qoff : nullptr;
@@ -220,7 +251,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a)
         while (e >= n) { e -= n; kx += 1; }
         double xh;
         int64_t k;
-        shifted_node(x, n, s, e, xh, k);
+        shifted_node_inv(x, n, s, e, invlen, len, xh, k);
         int b = (int)((xh - x[0]) * bsc);
         b = min(max(b, 0), R.tab.nb - 1);
         int64_t gb;
@@ -249,7 +280,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a)
             while (e >= n) { e -= n; kx += 1; }
             double xh;
             int64_t kk;
-            shifted_node(x, n, s, e, xh, kk);
+            shifted_node_inv(x, n, s, e, invlen, len, xh, kk);
             const int c = tab ? find_cell_tab(x, n, R.tab, bsc, xh) : find_cell(x, n, xh);
             g[k] = (int64_t)c + (kk + kx) * (int64_t)n;
             stencil_weights<TQ, P>(x, n, len, R, c, xh, w[k]);
@@ -297,7 +328,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a)
         A run = AC::zero();
         for (int j = j0; j < j1; ++j) run = AC::add(run, sm[j]);
         A total;
-        A acc = block_exscan<AC>(run, swt, total);
+        A acc = block_exscan_dpp<AC>(run, swt, total);
         for (int j = j0; j < j1; ++j) {
             sp[j] = acc;
             acc = AC::add(acc, sm[j]);
@@ -327,13 +358,8 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a)
             const int ei = t + k * kBlock;
             if (ei < NE) {
                 sg[ei] = g[k];
-                int e = i0 - H + ei;
-                if (e < 0) e += n;
-                while (e >= n) e -= n;
-                double xh;
-                int64_t kk;
-                shifted_node(x, n, s, e, xh, kk);
-                sell[ei] = (D)partial_direct<TQ, P>(x, q, n, len, g[k], xh);
+                sell[ei] = (D)direct_partial<TQ, P>(x, q, n, len, s, invlen,
+                                                    i0 - H + ei, g[k]);
             }
         }
     }
@@ -353,8 +379,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a)
                 const D whole = (jb - ja == 1) ? (D)sm[ja] : (D)AC::diff(sp[jb], sp[ja]);
                 mp = whole + (sell[ci + 1] - sell[ci]);
             } else {
-                double wh = 0.0;
-                for (int64_t m = sg[ci]; m < sg[ci + 1]; ++m) wh += cell_mass(x, q, n, m);
+                const double wh = direct_whole<TQ>(x, q, n, sg[ci], sg[ci + 1]);
                 mp = (D)(wh + ((double)sell[ci + 1] - (double)sell[ci]));
             }
             if (tab) qs[k] = (CT)(mp * (D)TabT<D>::dxinv(R.tab)[cell]);
@@ -387,7 +412,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a)
             }
             const CT dp = (sq[u + 2] - sq[u + 1]) * hp;
             const CT dm = (sq[u + 1] - sq[u]) * hm;
-            ssig[u] = (dp * dm <= (CT)0) ? (CT)0 : (CT)2 * dp * dm / (dp + dm);
+            ssig[u] = (dp * dm <= (CT)0) ? (CT)0 : harmonic2(dp, dm);
         }
     }
     __syncthreads();
@@ -464,7 +489,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(ResidualArgs a)
         }
         const CT dp = (sq[t + 2] - sq[t + 1]) * hp;
         const CT dm = (sq[t + 1] - sq[t]) * hm;
-        ssig[t] = (dp * dm <= (CT)0) ? (CT)0 : (CT)2 * dp * dm / (dp + dm);
+        ssig[t] = (dp * dm <= (CT)0) ? (CT)0 : harmonic2(dp, dm);
     }
     __syncthreads();
     for (int t = threadIdx.x; t < nd + 1; t += kBlock) {
@@ -494,11 +519,11 @@ __global__ __launch_bounds__(kBlock) void k_residual(ResidualArgs a)
 // ---------------------------------------------------------------------------
 
 struct MeshTabW {
-    double *dx, *dxinv, *hinv, *rden;
-    float *dxf, *dxinvf, *hinvf, *rdenf;
+    double *dx, *dxinv, *hinv, *stc;
+    float *dxf, *dxinvf, *hinvf, *stcf;
     int32_t *bucket;
     int32_t nb;
-    double *bscale;
+    double *scal;
 };
 
 template <int P>
@@ -516,21 +541,27 @@ __global__ __launch_bounds__(256) void k_mesh_prep(const double *x, int n, MeshT
         T.dxf[j] = (float)dx;
         T.dxinvf[j] = (float)(1.0 / dx);
         T.hinvf[j] = (float)(1.0 / h);
-        double X[P + 1];
-        for (int a = 0; a <= P; ++a) X[a] = node_x(x, n, len, j - LO + a);
-        double scale = 1.0;
-        for (int a = 0; a < P; ++a) scale *= dx;
+        double th[P + 1];
+        const double xc = x[j];
+        for (int a = 0; a <= P; ++a) th[a] = (node_x(x, n, len, j - LO + a) - xc) / dx;
+        th[LO] = 0.0;
+        double *st = T.stc + j * (2 * (P + 1));
+        float *sf = T.stcf + j * (2 * (P + 1));
         for (int a = 0; a <= P; ++a) {
             double den = 1.0;
             for (int b = 0; b <= P; ++b)
-                if (b != a) den *= X[a] - X[b];
-            T.rden[j * (P + 1) + a] = 1.0 / den;
-            // FP32 weights take node offsets in units of dx_j
-            T.rdenf[j * (P + 1) + a] = (float)(scale / den);
+                if (b != a) den *= th[a] - th[b];
+            st[a] = th[a];
+            st[P + 1 + a] = 1.0 / den;
+            sf[a] = (float)th[a];
+            sf[P + 1 + a] = (float)(1.0 / den);
         }
     }
     if (j < T.nb) T.bucket[j] = find_cell(x, n, x[0] + (double)j * (len / (double)T.nb));
-    if (j == 0) *T.bscale = (double)T.nb / len;
+    if (j == 0) {
+        T.scal[0] = (double)T.nb / len;
+        T.scal[1] = 1.0 / len;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -597,8 +628,8 @@ size_t al256(size_t v) { return (v + 255) & ~size_t(255); }
 size_t mesh_tab_bytes(int64_t n, int order)
 {
     const int64_t nb = 4 * n;
-    return 3 * al256(8 * n) + 3 * al256(4 * n) + al256(8 * n * (order + 1)) +
-           al256(4 * n * (order + 1)) + al256(4 * nb) + al256(8);
+    return 3 * al256(8 * n) + 3 * al256(4 * n) + al256(8 * n * 2 * (order + 1)) +
+           al256(4 * n * 2 * (order + 1)) + al256(4 * nb) + al256(16);
 }
 
 hipError_t launch_mesh_prep(const double *x, int64_t n, int order, void *mem,
@@ -612,16 +643,16 @@ hipError_t launch_mesh_prep(const double *x, int64_t n, int order, void *mem,
     w.dxf = (float *)p; p += al256(4 * n);
     w.dxinvf = (float *)p; p += al256(4 * n);
     w.hinvf = (float *)p; p += al256(4 * n);
-    w.rden = (double *)p; p += al256(8 * n * (order + 1));
-    w.rdenf = (float *)p; p += al256(4 * n * (order + 1));
+    w.stc = (double *)p; p += al256(8 * n * 2 * (order + 1));
+    w.stcf = (float *)p; p += al256(4 * n * 2 * (order + 1));
     w.bucket = (int32_t *)p; p += al256(4 * 4 * n);
     w.nb = (int32_t)(4 * n);
-    w.bscale = (double *)p;
-    tab.dx = w.dx; tab.dxinv = w.dxinv; tab.hinv = w.hinv; tab.rden = w.rden;
-    tab.dxf = w.dxf; tab.dxinvf = w.dxinvf; tab.hinvf = w.hinvf; tab.rdenf = w.rdenf;
+    w.scal = (double *)p;
+    tab.dx = w.dx; tab.dxinv = w.dxinv; tab.hinv = w.hinv; tab.stc = w.stc;
+    tab.dxf = w.dxf; tab.dxinvf = w.dxinvf; tab.hinvf = w.hinvf; tab.stcf = w.stcf;
     tab.bucket = w.bucket;
     tab.nb = w.nb;
-    tab.bscale = w.bscale;
+    tab.scal = w.scal;
     const unsigned grid = (unsigned)((w.nb + 255) / 256);
     switch (order) {
     case 1: hipLaunchKernelGGL(k_mesh_prep<1>, dim3(grid), dim3(256), 0, stream, x, (int)n, w); break;
