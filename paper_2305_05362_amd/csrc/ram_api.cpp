@@ -196,6 +196,56 @@ ram_status make_rows(ram_ctx *ctx, const ram_layout *L, const double *edges,
     return RAM_OK;
 }
 
+int64_t tiles_of(const ram_layout *L, int tile)
+{
+    if (L->n_cols > 0) return L->n_rows * ((L->n_cols + tile - 1) / tile);
+    return ram::ragged_tile_bound(L->n_cells, L->n_rows, tile);
+}
+
+// n_steps launches of the bulk-shift kernel (fused with the residual when
+// a.dv is set).  n_steps == 1 writes a.q_out; n_steps > 1 updates a.q_in in
+// place, ping-ponging with `tmp`.  Shared meshes take the specialised kernel
+// after planning the tiles' windows once.
+ram_status launch_steps(ram_ctx *ctx, ram::StepArgs a, ram_dtype dtype,
+                        ram_scan scan, int order, int64_t n_steps, void *tmp,
+                        size_t wlo_off, size_t w_off, size_t state_bytes)
+{
+    const bool f64 = dtype == RAM_F64;
+    const bool shared = a.rows.has_tab != 0 && a.rows.n_cols > 0;
+    hipError_t e;
+    if (shared) {
+        int64_t *wlo = (int64_t *)((char *)ctx->scratch + wlo_off);
+        int32_t *w = (int32_t *)((char *)ctx->scratch + w_off);
+        e = ram::launch_plan(a, order, wlo, w, ctx->stream);
+        if (e != hipSuccess) return hip_fail(e, "window plan launch");
+        a.plan_wlo = wlo;
+        a.plan_w = w;
+    }
+    auto one = [&](const ram::StepArgs &s) {
+        return shared ? ram::launch_step_shared(s, f64, (int)scan, order, ctx->stream)
+                      : ram::launch_step(s, f64, (int)scan, order, ctx->stream);
+    };
+    if (n_steps == 1 && a.q_out) {
+        e = one(a);
+        if (e != hipSuccess) return hip_fail(e, "step launch");
+        return RAM_OK;
+    }
+    void *q = const_cast<void *>(a.q_in);
+    void *cur = q, *oth = tmp;
+    for (int64_t k = 0; k < n_steps; ++k) {
+        a.q_in = cur;
+        a.q_out = oth;
+        e = one(a);
+        if (e != hipSuccess) return hip_fail(e, "step launch");
+        void *t = cur; cur = oth; oth = t;
+    }
+    if (cur != q) {
+        e = ram::launch_copy(cur, q, (int64_t)state_bytes, ctx->stream);
+        if (e != hipSuccess) return hip_fail(e, "state copy");
+    }
+    return RAM_OK;
+}
+
 } // namespace
 
 extern "C" {
@@ -281,6 +331,8 @@ ram_status ram_shift(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
     if ((st = enter(ctx)) != RAM_OK) return st;
     Carve cv;
     RowsPlan rp = plan_rows(cv, layout, ram::step_tile(false), order);
+    const int64_t nt = tiles_of(layout, rp.tile);
+    const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(sizeof(int32_t) * nt);
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
     ram::StepArgs a;
     if ((st = make_rows(ctx, layout, edges, rp, a.rows)) != RAM_OK) return st;
@@ -288,8 +340,8 @@ ram_status ram_shift(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
     a.q_out = q_out;
     a.v0 = v0;
     a.dt = dt;
-    hipError_t e = ram::launch_step(a, dtype == RAM_F64, (int)scan, order, ctx->stream);
-    if (e != hipSuccess) return hip_fail(e, "shift launch");
+    if ((st = launch_steps(ctx, a, dtype, scan, order, 1, nullptr, wlo_off, w_off, 0)) != RAM_OK)
+        return st;
     return RAM_OK;
 }
 
@@ -339,25 +391,19 @@ ram_status ram_step(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
     Carve cv;
     const size_t tmp_off = cv.take(state_bytes);
     RowsPlan rp = plan_rows(cv, layout, ram::step_tile(dv != nullptr), order);
+    const int64_t nt = tiles_of(layout, rp.tile);
+    const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(sizeof(int32_t) * nt);
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
     ram::StepArgs a;
     if ((st = make_rows(ctx, layout, edges, rp, a.rows)) != RAM_OK) return st;
+    a.q_in = q;
     a.v0 = v0;
     a.dv = dv;
     a.dt = dt;
-    // one fused launch per step, ping-ponging between q and the scratch state
-    void *cur = q, *oth = (char *)ctx->scratch + tmp_off;
-    for (int64_t k = 0; k < n_steps; ++k) {
-        a.q_in = cur;
-        a.q_out = oth;
-        hipError_t e = ram::launch_step(a, dtype == RAM_F64, (int)scan, order, ctx->stream);
-        if (e != hipSuccess) return hip_fail(e, "step launch");
-        void *t = cur; cur = oth; oth = t;
-    }
-    if (cur != q) {
-        hipError_t e = ram::launch_copy(cur, q, (int64_t)state_bytes, ctx->stream);
-        if (e != hipSuccess) return hip_fail(e, "state copy");
-    }
+    void *tmp = (char *)ctx->scratch + tmp_off;
+    if ((st = launch_steps(ctx, a, dtype, scan, order, n_steps, tmp, wlo_off, w_off,
+                           state_bytes)) != RAM_OK)
+        return st;
     return RAM_OK;
 }
 

@@ -307,5 +307,96 @@ __device__ inline double centre_gap(const double *x, int n, double len, int64_t 
     return centre(x, w + 1) - centre(x, w);
 }
 
+// Periodic index for j in [-n, k n).
+__device__ inline int wrap_small(int j, int n)
+{
+    if (j < 0) j += n;
+    while (j >= n) j -= n;
+    return j;
+}
+
+template <typename TQ>
+__device__ inline double cell_mass(const double *x, const TQ *q, int n, int64_t m)
+{
+    const int w = wrapi(m, n);
+    return (double)q[w] * (x[w + 1] - x[w]);
+}
+
+// Partial integral C~(xh) - C(c) from global memory (direct path).
+template <typename TQ, int P>
+__device__ double partial_direct(const double *x, const TQ *q, int n, double len,
+                                 int64_t g, double xh)
+{
+    constexpr int LO = (P - 1) / 2;
+    const int c = wrapi(g, n);
+    double X[P + 1], w[P + 1];
+#pragma unroll
+    for (int a = 0; a <= P; ++a) X[a] = node_x(x, n, len, c - LO + a);
+    lagrange_weights<P>(xh, X, w);
+    double ell = 0.0;
+#pragma unroll
+    for (int a = 0; a <= P; ++a) {
+        const int j = c - LO + a;
+        double d = 0.0;
+        if (j > c) {
+            for (int m = c; m < j; ++m) d += cell_mass(x, q, n, m);
+        } else if (j < c) {
+            for (int m = j; m < c; ++m) d += cell_mass(x, q, n, m);
+            d = -d;
+        }
+        ell += w[a] * d;
+    }
+    return ell;
+}
+
+// Per-type views of the shared-mesh tables.
+template <typename T> struct TabT;
+template <> struct TabT<double> {
+    __device__ static const double *dx(const MeshTab &t) { return t.dx; }
+    __device__ static const double *dxinv(const MeshTab &t) { return t.dxinv; }
+    __device__ static const double *hinv(const MeshTab &t) { return t.hinv; }
+};
+template <> struct TabT<float> {
+    __device__ static const float *dx(const MeshTab &t) { return t.dxf; }
+    __device__ static const float *dxinv(const MeshTab &t) { return t.dxinvf; }
+    __device__ static const float *hinv(const MeshTab &t) { return t.hinvf; }
+};
+
+// 2ab/(a+b) of the van Leer slope (a b > 0): FP32 with the hardware
+// reciprocal, FP64 with a division.
+__device__ inline float harmonic2(float a, float b)
+{
+    return 2.0f * a * b * __builtin_amdgcn_rcpf(a + b);
+}
+__device__ inline double harmonic2(double a, double b)
+{
+    return 2.0 * a * b / (a + b);
+}
+
+// Direct path of k_step (tiles whose source window does not fit in LDS):
+// partial integrals from global memory, FP64.
+template <typename TQ, int P>
+__device__ __attribute__((noinline)) double direct_partial(
+    const double *x, const TQ *q, int n, double len, double s, double invlen,
+    int e, int64_t g)
+{
+    if (e < 0) e += n;
+    while (e >= n) e -= n;
+    double xh;
+    int64_t kk;
+    shifted_node_inv(x, n, s, e, invlen, len, xh, kk);
+    return partial_direct<TQ, P>(x, q, n, len, g, xh);
+}
+
+template <typename TQ>
+__device__ __attribute__((noinline)) double direct_whole(const double *x,
+                                                         const TQ *q, int n,
+                                                         int64_t ga, int64_t gb)
+{
+    double wh = 0.0;
+    for (int64_t m = ga; m < gb; ++m) wh += cell_mass(x, q, n, m);
+    return wh;
+}
+
 } // namespace dev
 } // namespace ram

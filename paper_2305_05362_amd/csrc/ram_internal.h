@@ -30,9 +30,24 @@ struct MeshTab {
     const float *hinvf = nullptr;
     const float *stcf = nullptr;
     const int32_t *bucket = nullptr;  // largest j with x_j <= x0 + b L / nb
+    const double2 *bnext = nullptr;   // per bucket: the next two nodes (or +inf)
     int32_t nb = 0;
     const double *scal = nullptr;     // device scalars: nb / L, 1 / L
+    const void *crf = nullptr;        // CellRec<float>[n]
+    const void *crd = nullptr;        // CellRec<double>[n]
 };
+
+// Everything the bulk shift needs about source cell c in one record (one
+// cache line in FP32, two in FP64): x_c, 1/dx_c, and the stencil data
+// (offsets and reciprocal denominators, as in MeshTab::stc) in type T.
+template <typename T> struct CellRec {
+    double xc;
+    double dxinv;
+    T th[6];
+    T rd[6];
+};
+static_assert(sizeof(CellRec<float>) == 64, "one cache line");
+static_assert(sizeof(CellRec<double>) == 112, "FP64 record");
 // Stencil data of source cell c (order p, lo = (p-1)/2), in units of dx_c:
 //   stc[c][a]       = (x_{c-lo+a} - x_c) / dx_c                   a = 0..p
 //   stc[c][p+1+a]   = 1 / prod_{b != a} (stc[c][a] - stc[c][b])
@@ -64,6 +79,8 @@ struct StepArgs {
     const double *v0 = nullptr;
     const void *dv = nullptr;         // null: shift only
     double dt = 0.0;
+    const int64_t *plan_wlo = nullptr;  // shared mesh: per-tile window start
+    const int32_t *plan_w = nullptr;    // ... and length (-1: direct path)
 };
 
 struct ResidualArgs {
@@ -117,6 +134,12 @@ hipError_t launch_mesh_prep(const double *x, int64_t n, int order, void *mem,
                             MeshTab &tab, hipStream_t stream);
 hipError_t launch_step(const StepArgs &a, bool f64, int scan, int order,
                        hipStream_t stream);
+// Shared-mesh specialisation: plan the tiles' source windows once per call
+// (launch_plan, into n_tiles int64 + int32), then one launch per step.
+hipError_t launch_plan(const StepArgs &a, int order, int64_t *wlo, int32_t *w,
+                       hipStream_t stream);
+hipError_t launch_step_shared(const StepArgs &a, bool f64, int scan, int order,
+                              hipStream_t stream);
 hipError_t launch_residual(const ResidualArgs &a, bool f64,
                            hipStream_t stream);
 hipError_t launch_shift_adjoint(const ShiftAdjArgs &a, bool f64, int order,

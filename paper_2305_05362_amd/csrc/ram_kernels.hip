@@ -39,61 +39,6 @@ namespace {
 using namespace dev;
 
 
-// Periodic index for j in [-n, k n).
-__device__ inline int wrap_small(int j, int n)
-{
-    if (j < 0) j += n;
-    while (j >= n) j -= n;
-    return j;
-}
-
-template <typename TQ>
-__device__ inline double cell_mass(const double *x, const TQ *q, int n, int64_t m)
-{
-    const int w = wrapi(m, n);
-    return (double)q[w] * (x[w + 1] - x[w]);
-}
-
-// Partial integral C~(xh) - C(c) from global memory (direct path).
-template <typename TQ, int P>
-__device__ double partial_direct(const double *x, const TQ *q, int n, double len,
-                                 int64_t g, double xh)
-{
-    constexpr int LO = (P - 1) / 2;
-    const int c = wrapi(g, n);
-    double X[P + 1], w[P + 1];
-#pragma unroll
-    for (int a = 0; a <= P; ++a) X[a] = node_x(x, n, len, c - LO + a);
-    lagrange_weights<P>(xh, X, w);
-    double ell = 0.0;
-#pragma unroll
-    for (int a = 0; a <= P; ++a) {
-        const int j = c - LO + a;
-        double d = 0.0;
-        if (j > c) {
-            for (int m = c; m < j; ++m) d += cell_mass(x, q, n, m);
-        } else if (j < c) {
-            for (int m = j; m < c; ++m) d += cell_mass(x, q, n, m);
-            d = -d;
-        }
-        ell += w[a] * d;
-    }
-    return ell;
-}
-
-// Per-type views of the shared-mesh tables.
-template <typename T> struct TabT;
-template <> struct TabT<double> {
-    __device__ static const double *dx(const MeshTab &t) { return t.dx; }
-    __device__ static const double *dxinv(const MeshTab &t) { return t.dxinv; }
-    __device__ static const double *hinv(const MeshTab &t) { return t.hinv; }
-};
-template <> struct TabT<float> {
-    __device__ static const float *dx(const MeshTab &t) { return t.dxf; }
-    __device__ static const float *dxinv(const MeshTab &t) { return t.dxinvf; }
-    __device__ static const float *hinv(const MeshTab &t) { return t.hinvf; }
-};
-
 // Lagrange weights of the stencil nodes c-LO .. c-LO+P at xh, in WT.
 // Shared meshes use the per-cell stencil table: node offsets and reciprocal
 // denominators in units of dx_c, so only theta = (xh - x_c)/dx_c is formed in
@@ -132,41 +77,6 @@ __device__ inline void stencil_weights(const double *x, int n, double len,
     for (int a = 0; a <= P; ++a) w[a] = st[P + 1 + a] * (pre[a] * suf[a]);
 }
 
-// Direct path of k_step (tiles whose source window does not fit in LDS):
-// partial integrals from global memory, FP64.
-template <typename TQ, int P>
-__device__ __attribute__((noinline)) double direct_partial(
-    const double *x, const TQ *q, int n, double len, double s, double invlen,
-    int e, int64_t g)
-{
-    if (e < 0) e += n;
-    while (e >= n) e -= n;
-    double xh;
-    int64_t kk;
-    shifted_node_inv(x, n, s, e, invlen, len, xh, kk);
-    return partial_direct<TQ, P>(x, q, n, len, g, xh);
-}
-
-template <typename TQ>
-__device__ __attribute__((noinline)) double direct_whole(const double *x,
-                                                         const TQ *q, int n,
-                                                         int64_t ga, int64_t gb)
-{
-    double wh = 0.0;
-    for (int64_t m = ga; m < gb; ++m) wh += cell_mass(x, q, n, m);
-    return wh;
-}
-
-// 2ab/(a+b) of the van Leer slope (a b > 0): FP32 with the hardware
-// reciprocal, FP64 with a division.
-__device__ inline float harmonic2(float a, float b)
-{
-    return 2.0f * a * b * __builtin_amdgcn_rcpf(a + b);
-}
-__device__ inline double harmonic2(double a, double b)
-{
-    return 2.0 * a * b / (a + b);
-}
 
 // ---------------------------------------------------------------------------
 // bulk shift, optionally fused with the residual step
@@ -522,8 +432,11 @@ struct MeshTabW {
     double *dx, *dxinv, *hinv, *stc;
     float *dxf, *dxinvf, *hinvf, *stcf;
     int32_t *bucket;
+    double2 *bnext;
     int32_t nb;
     double *scal;
+    CellRec<float> *crf;
+    CellRec<double> *crd;
 };
 
 template <int P>
@@ -547,6 +460,14 @@ __global__ __launch_bounds__(256) void k_mesh_prep(const double *x, int n, MeshT
         th[LO] = 0.0;
         double *st = T.stc + j * (2 * (P + 1));
         float *sf = T.stcf + j * (2 * (P + 1));
+        CellRec<float> rf;
+        CellRec<double> rd;
+        rf.xc = rd.xc = xc;
+        rf.dxinv = rd.dxinv = 1.0 / dx;
+        for (int a = 0; a < 6; ++a) {
+            rf.th[a] = rf.rd[a] = 0.0f;
+            rd.th[a] = rd.rd[a] = 0.0;
+        }
         for (int a = 0; a <= P; ++a) {
             double den = 1.0;
             for (int b = 0; b <= P; ++b)
@@ -555,9 +476,24 @@ __global__ __launch_bounds__(256) void k_mesh_prep(const double *x, int n, MeshT
             st[P + 1 + a] = 1.0 / den;
             sf[a] = (float)th[a];
             sf[P + 1 + a] = (float)(1.0 / den);
+            rf.th[a] = (float)th[a];
+            rf.rd[a] = (float)(1.0 / den);
+            rd.th[a] = th[a];
+            rd.rd[a] = 1.0 / den;
         }
+        T.crf[j] = rf;
+        T.crd[j] = rd;
     }
-    if (j < T.nb) T.bucket[j] = find_cell(x, n, x[0] + (double)j * (len / (double)T.nb));
+    if (j < T.nb) {
+        // lower-bound cell of bucket j, taken a hair below the bucket start so
+        // that a bucket number rounded up by one still bounds the cell from
+        // below; then the next two nodes (+inf past the last cell)
+        const double w = len / (double)T.nb;
+        const int c0 = find_cell(x, n, x[0] + ((double)j - 1e-6) * w);
+        T.bucket[j] = c0;
+        const double inf = __builtin_huge_val();
+        T.bnext[j] = make_double2(c0 + 1 < n ? x[c0 + 1] : inf, c0 + 2 < n ? x[c0 + 2] : inf);
+    }
     if (j == 0) {
         T.scal[0] = (double)T.nb / len;
         T.scal[1] = 1.0 / len;
@@ -629,7 +565,8 @@ size_t mesh_tab_bytes(int64_t n, int order)
 {
     const int64_t nb = 4 * n;
     return 3 * al256(8 * n) + 3 * al256(4 * n) + al256(8 * n * 2 * (order + 1)) +
-           al256(4 * n * 2 * (order + 1)) + al256(4 * nb) + al256(16);
+           al256(4 * n * 2 * (order + 1)) + al256(4 * nb) + al256(16 * nb) + al256(16) +
+           al256(sizeof(CellRec<float>) * n) + al256(sizeof(CellRec<double>) * n);
 }
 
 hipError_t launch_mesh_prep(const double *x, int64_t n, int order, void *mem,
@@ -647,12 +584,18 @@ hipError_t launch_mesh_prep(const double *x, int64_t n, int order, void *mem,
     w.stcf = (float *)p; p += al256(4 * n * 2 * (order + 1));
     w.bucket = (int32_t *)p; p += al256(4 * 4 * n);
     w.nb = (int32_t)(4 * n);
-    w.scal = (double *)p;
+    w.bnext = (double2 *)p; p += al256(16 * 4 * n);
+    w.scal = (double *)p; p += al256(16);
+    w.crf = (CellRec<float> *)p; p += al256(sizeof(CellRec<float>) * n);
+    w.crd = (CellRec<double> *)p;
     tab.dx = w.dx; tab.dxinv = w.dxinv; tab.hinv = w.hinv; tab.stc = w.stc;
     tab.dxf = w.dxf; tab.dxinvf = w.dxinvf; tab.hinvf = w.hinvf; tab.stcf = w.stcf;
     tab.bucket = w.bucket;
     tab.nb = w.nb;
     tab.scal = w.scal;
+    tab.bnext = w.bnext;
+    tab.crf = w.crf;
+    tab.crd = w.crd;
     const unsigned grid = (unsigned)((w.nb + 255) / 256);
     switch (order) {
     case 1: hipLaunchKernelGGL(k_mesh_prep<1>, dim3(grid), dim3(256), 0, stream, x, (int)n, w); break;
