@@ -29,7 +29,7 @@ constexpr int kWinRegs = kWinSh / kBlock;       // window cells per thread
 template <typename M, typename A, typename CT>
 struct ShLds {
     static constexpr size_t win = sizeof(M) * kWinSh + sizeof(A) * (kWinSh + 1);
-    static constexpr size_t res = 3 * sizeof(CT) * kStepNodes;
+    static constexpr size_t res = 2 * sizeof(CT) * kStepNodes;
     static constexpr size_t uni = win > res ? win : res;
 };
 
@@ -129,7 +129,13 @@ __global__ __launch_bounds__(256) void k_plan(StepArgs a, int64_t *wlo_out,
     w_out[tile] = (wide >= P && wide <= kWinSh) ? (int32_t)wide : -1;
 }
 
-template <typename TQ, int P, int S>
+// Periodic index for j in [-n, 2n).
+__device__ inline int wrap1(int j, int n)
+{
+    return j < 0 ? j + n : (j >= n ? j - n : j);
+}
+
+template <typename TQ, int P, int S, int H>
 __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
 {
     using AC = Acc<S>;
@@ -139,6 +145,7 @@ __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
     using L = ShLds<M, A, CT>;
     constexpr int LO = (P - 1) / 2;
     constexpr int NI = kItems;
+    constexpr int WCAP = kWinSh;
 
     __shared__ int sjc[kStepNodes];      // window index of each node's cell
     __shared__ CT sell[kStepNodes];      // partial integral C~(xh) - C(c)
@@ -146,72 +153,58 @@ __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
     __shared__ __attribute__((aligned(16))) unsigned char su[L::uni];
     __shared__ int s_flag;
     M *sm = (M *)su;                                 // window masses
-    A *sp = (A *)(su + sizeof(M) * kWinSh);          // exclusive prefix
+    A *sp = (A *)(su + sizeof(M) * WCAP);            // exclusive prefix
     int64_t *sg = (int64_t *)su;                     // direct path: node indices
     CT *sq = (CT *)su;                               // shifted state
-    CT *ssig = sq + kStepNodes;                      // van Leer slopes
-    CT *sf = ssig + kStepNodes;                      // face fluxes
+    CT *sf = sq + kStepNodes;                        // face fluxes
 
     const Rows &R = a.rows;
     const MeshTab &tb = R.tab;
     const int n = (int)R.n_cols;
-    const int64_t tile = blockIdx.x;
-    const int64_t tpr = (n + R.tile - 1) / R.tile;
-    const int64_t row = tile / tpr;
-    const int i0 = (int)(tile - row * tpr) * R.tile;
-    const int H = a.dv ? 2 : 0;
+    const int tpr = (n + R.tile - 1) / R.tile;
+    const int row = (int)(blockIdx.x / (unsigned)tpr);
+    const int i0 = ((int)blockIdx.x - row * tpr) * R.tile;
     const int nd = min(R.tile, n - i0);
     const int NC = nd + 2 * H;
     const int NE = NC + 1;
     const bool inner = (i0 - H >= 0) && (i0 + nd + H < n);
     const double *x = R.edges;
-    const int64_t qoff = row * (int64_t)n;
+    const int64_t qoff = (int64_t)row * n;
     const TQ *q = (const TQ *)a.q_in + qoff;
     TQ *qo = (TQ *)a.q_out + qoff;
     const double s = a.v0[row] * a.dt;
     const double len = x[n] - x[0];
     const double bsc = tb.scal[0], invlen = tb.scal[1];
-    const int64_t wlo = a.plan_wlo[tile];
-    const int W = a.plan_w[tile];
+    const int64_t wlo = a.plan_wlo[blockIdx.x];
+    const int W = a.plan_w[blockIdx.x];
     const int t = threadIdx.x;
-    auto wrp = [&](int j) { return inner ? j : wrap_small(j, n); };
 
     // ---- loads that do not depend on the search, issued first ------------
     double xe[NI];
 #pragma unroll
     for (int k = 0; k < NI; ++k) {
         const int ei = t + k * kBlock;
-        xe[k] = ei < NE ? x[wrp(i0 - H + ei)] : 0.0;
+        const int e = i0 - H + ei;
+        xe[k] = ei < NE ? x[inner ? e : wrap1(e, n)] : 0.0;
     }
+    // window start inside the row: wlo mod n, without a 64-bit division in
+    // the common case of a window at most one period away
+    int base = 0;
+    if (W > 0) {
+        const int64_t kk = wlo >= 0 ? wlo / n : -((-wlo + n - 1) / n);
+        base = (int)(wlo - kk * n);
+    }
+    const bool wsmall = W + base <= 2 * n;
     M wq[kWinRegs], wd[kWinRegs];
-    const int base = W > 0 ? wrapi(wlo, n) : 0;
 #pragma unroll
     for (int r = 0; r < kWinRegs; ++r) {
         const int j = t + r * kBlock;
         if (j < W) {
             int mm = base + j;
-            if (mm >= n) mm = wrap_small(mm, n);
+            if (wsmall) mm = mm >= n ? mm - n : mm;
+            else mm = wrap_small(mm, n);
             wq[r] = (M)q[mm];
             wd[r] = TabT<M>::dx(tb)[mm];
-        }
-    }
-    TQ dvr[NI];
-    CT hp[NI], hm[NI], dxl[NI], dxr[NI], dxi[NI];
-    if (H) {
-        const TQ *dv = (const TQ *)a.dv + qoff;
-#pragma unroll
-        for (int k = 0; k < NI; ++k) {
-            const int u = t + k * kBlock;
-            if (u < nd + 2) {                       // slope of cell i0-1+u
-                hp[k] = TabT<CT>::hinv(tb)[wrp(i0 - 1 + u)];
-                hm[k] = TabT<CT>::hinv(tb)[wrp(i0 - 2 + u)];
-            }
-            if (u < nd + 1) {                       // face i0+u
-                dvr[k] = dv[wrp(i0 + u)];
-                dxl[k] = TabT<CT>::dx(tb)[wrp(i0 - 1 + u)];
-                dxr[k] = TabT<CT>::dx(tb)[wrp(i0 + u)];
-            }
-            if (u < nd) dxi[k] = TabT<CT>::dxinv(tb)[i0 + u];
         }
     }
 
@@ -225,7 +218,7 @@ __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
         g[k] = 0;
         if (ei < NE) {
             const int e = i0 - H + ei;
-            const int kx = e < 0 ? -1 : (e >= n ? (e / n) : 0);
+            const int kx = e < 0 ? -1 : (e >= n ? 1 : 0);
             g[k] = node_eval<CT, P>(x, n, tb, bsc, invlen, len, s, xe[k], kx, w[k]);
             const int64_t jc = g[k] - wlo;
             ok = ok && jc >= LO && jc + P - LO <= W;
@@ -235,12 +228,10 @@ __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
     __syncthreads();
     if (!ok) s_flag = 0;
     // ---- (B) window masses and the block scan ------------------------------
-    if (W > 0) {
 #pragma unroll
-        for (int r = 0; r < kWinRegs; ++r) {
-            const int j = t + r * kBlock;
-            if (j < W) sm[j] = wq[r] * wd[r];
-        }
+    for (int r = 0; r < kWinRegs; ++r) {
+        const int j = t + r * kBlock;
+        if (j < W) sm[j] = wq[r] * wd[r];
     }
     __syncthreads();
     const bool windowed = s_flag != 0;
@@ -248,13 +239,23 @@ __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
         const int per = (W + kBlock - 1) / kBlock;
         const int j0 = min(W, t * per);
         const int j1 = min(W, j0 + per);
+        M mine[kWinRegs];
         A run = AC::zero();
-        for (int j = j0; j < j1; ++j) run = AC::add(run, sm[j]);
+#pragma unroll
+        for (int r = 0; r < kWinRegs; ++r) {
+            if (j0 + r < j1) {
+                mine[r] = sm[j0 + r];
+                run = AC::add(run, mine[r]);
+            }
+        }
         A total;
         A acc = block_exscan_dpp<AC>(run, swt, total);
-        for (int j = j0; j < j1; ++j) {
-            sp[j] = acc;
-            acc = AC::add(acc, sm[j]);
+#pragma unroll
+        for (int r = 0; r < kWinRegs; ++r) {
+            if (j0 + r < j1) {
+                sp[j0 + r] = acc;
+                acc = AC::add(acc, mine[r]);
+            }
         }
         if (t == 0) sp[W] = total;
         __syncthreads();
@@ -285,6 +286,33 @@ __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
             }
         }
     }
+
+    // residual inputs, fetched while the partial integrals settle
+    const CT dt = (CT)a.dt;
+    TQ dvr[NI];
+    CT dxl[NI], dxr[NI], h0[NI], h1[NI], h2[NI], dxi[NI];
+    if (H) {
+        const TQ *dv = (const TQ *)a.dv + qoff;
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+            const int u = t + k * kBlock;
+            if (u < nd + 1) {                        // face f = i0+u
+                const int f = i0 + u;
+                const int fm = inner ? f - 1 : wrap1(f - 1, n);
+                const int fp = inner ? f : wrap1(f, n);
+                const int fmm = inner ? f - 2 : wrap1(f - 2, n);
+                const int fpp = inner ? f + 1 : wrap1(f + 1, n);
+                dvr[k] = dv[fp];
+                dxl[k] = TabT<CT>::dx(tb)[fm];
+                dxr[k] = TabT<CT>::dx(tb)[fp];
+                h0[k] = TabT<CT>::hinv(tb)[fmm];     // gap (f-2, f-1)
+                h1[k] = TabT<CT>::hinv(tb)[fm];      // gap (f-1, f)
+                h2[k] = TabT<CT>::hinv(tb)[fp];      // gap (f, f+1)
+                (void)fpp;
+            }
+            if (u < nd) dxi[k] = TabT<CT>::dxinv(tb)[i0 + u];
+        }
+    }
     __syncthreads();
 
     // ---- (D) destination masses, Step 3 ------------------------------------
@@ -294,7 +322,8 @@ __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
         const int ci = t + k * kBlock;
         qs[k] = (CT)0;
         if (ci < NC) {
-            const int cell = wrp(i0 - H + ci);
+            const int c0 = i0 - H + ci;
+            const int cell = inner ? c0 : wrap1(c0, n);
             CT mp;
             if (windowed) {
                 const int ja = sjc[ci], jb = sjc[ci + 1];
@@ -315,35 +344,27 @@ __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
         if (t + k * kBlock < NC) sq[t + k * kBlock] = qs[k];
     __syncthreads();
 
-    // ---- (E) van Leer slopes of cells i0-1 .. i0+nd --------------------------
-    const CT dt = (CT)a.dt;
-#pragma unroll
-    for (int k = 0; k < NI; ++k) {
-        const int u = t + k * kBlock;
-        if (u < nd + 2) {
-            const CT dp = (sq[u + 2] - sq[u + 1]) * hp[k];
-            const CT dm = (sq[u + 1] - sq[u]) * hm[k];
-            ssig[u] = (dp * dm <= (CT)0) ? (CT)0 : harmonic2(dp, dm);
-        }
-    }
-    __syncthreads();
-    // ---- (F) upwind fluxes on faces i0 .. i0+nd ------------------------------
+    // ---- (E) fluxes on faces i0 .. i0+nd, with the upwind cell's slope -----
+    // face i0+u lies between cells i0+u-1 (state index u+1) and i0+u (u+2)
 #pragma unroll
     for (int k = 0; k < NI; ++k) {
         const int u = t + k * kBlock;
         if (u < nd + 1) {
             const CT v = (CT)dvr[k];
             const bool up = v >= (CT)0;
-            // upwind cell f-1 (state u+1, slope u, size dxl) or f (u+2, u+1, dxr)
-            const CT qu = up ? sq[u + 1] : sq[u + 2];
-            const CT su = up ? ssig[u] : ssig[u + 1];
-            const CT dxu = up ? dxl[k] : dxr[k];
-            const CT half = up ? (CT)0.5 * (dxu - v * dt) : (CT)-0.5 * (dxu + v * dt);
-            sf[u] = v * (qu + su * half);
+            const int c = up ? u + 1 : u + 2;             // upwind cell, state index
+            const CT qm = sq[c - 1], q0 = sq[c], qp = sq[c + 1];
+            const CT hpl = up ? h1[k] : h2[k];
+            const CT hmi = up ? h0[k] : h1[k];
+            const CT dp = (qp - q0) * hpl;
+            const CT dm = (q0 - qm) * hmi;
+            const CT sig = (dp * dm <= (CT)0) ? (CT)0 : harmonic2(dp, dm);
+            const CT half = up ? (CT)0.5 * (dxl[k] - v * dt) : (CT)-0.5 * (dxr[k] + v * dt);
+            sf[u] = v * (q0 + sig * half);
         }
     }
     __syncthreads();
-    // ---- (G) conservative update --------------------------------------------
+    // ---- (F) conservative update --------------------------------------------
 #pragma unroll
     for (int k = 0; k < NI; ++k) {
         const int u = t + k * kBlock;
@@ -351,16 +372,23 @@ __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
     }
 }
 
-template <typename TQ, int P>
-hipError_t step_sh_scan(const StepArgs &a, int scan, hipStream_t st)
+template <typename TQ, int P, int H>
+hipError_t step_sh_h(const StepArgs &a, int scan, hipStream_t st)
 {
     const dim3 g((unsigned)a.rows.n_tiles), b(kBlock);
     switch (scan) {
-    case kScanF64: hipLaunchKernelGGL((k_step_sh<TQ, P, kScanF64>), g, b, 0, st, a); break;
-    case kScanTwoSum: hipLaunchKernelGGL((k_step_sh<TQ, P, kScanTwoSum>), g, b, 0, st, a); break;
-    default: hipLaunchKernelGGL((k_step_sh<TQ, P, kScanF32>), g, b, 0, st, a); break;
+    case kScanF64: hipLaunchKernelGGL((k_step_sh<TQ, P, kScanF64, H>), g, b, 0, st, a); break;
+    case kScanTwoSum: hipLaunchKernelGGL((k_step_sh<TQ, P, kScanTwoSum, H>), g, b, 0, st, a); break;
+    default: hipLaunchKernelGGL((k_step_sh<TQ, P, kScanF32, H>), g, b, 0, st, a); break;
     }
     return hipGetLastError();
+}
+
+template <typename TQ, int P>
+hipError_t step_sh_scan(const StepArgs &a, int scan, hipStream_t st)
+{
+    if (a.dv) return step_sh_h<TQ, P, 2>(a, scan, st);
+    return step_sh_h<TQ, P, 0>(a, scan, st);
 }
 
 template <typename TQ>
