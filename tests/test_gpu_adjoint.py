@@ -87,55 +87,45 @@ def _fd(wl, rows, q0, dv, v0, area, tgt, steps, kind, idx, eps):
 
 
 def test_rollout_gradient_fd_cfg4():
-    """Central differences with eps = 1e-4 (and eps/2 for a Richardson
-    estimate) at 32 Q0 and 16 dv coordinates; coordinates whose two
-    differences disagree by more than 5% sit on a limiter or upwind kink and
-    are replaced by the next draw.  The v0 dependence is only piecewise smooth
-    (every shifted node that crosses a mesh node switches stencil), so for the
-    16 v0 coordinates the differences must converge to the adjoint as eps
-    shrinks (1e-4, 1e-5, 1e-6) instead of meeting a fixed bar at 1e-4."""
+    """Central differences at 32 Q0, 16 dv and 16 v0 coordinates, FP64 path.
+
+    The polar state carries 1e-3 white noise, so van Leer limiter kinks are
+    dense: a perturbation of 1e-4 moves some slope products through zero
+    somewhere in 200 steps, and the difference quotient then averages the
+    two branch derivatives (first-order error).  The differences are taken at
+    eps = 1e-4, 1e-5 and 1e-6; the bar (norm-wise <= 1e-5) applies at
+    eps = 1e-6, where the quotient resolves the branch the adjoint follows,
+    and the error must shrink with eps.  The v0 dependence is piecewise smooth
+    with a kink at every node crossing, so there the differences must converge
+    to the adjoint (median <= 1e-3 at 1e-6 and > 3x smaller than at 1e-4)."""
     wl = W.cfg4()
     steps, ckpt = 200, 20
     rows, q0, dv, v0, area = _setup(wl)
     tgt = _target(wl, rows, steps, torch.float64)
     gq, gdv, gv0, _ = _grads(wl, rows, q0, dv, v0, area, tgt, steps, ckpt)
     rng = W.rng_for(4, 5)
-    eps = 1e-4
     n = wl.n_cells
-    near = rng.permutation(np.where(np.abs(wl.q0.reshape(-1) - 1.0) > 1e-2)[0])
+    cq = rng.choice(np.where(np.abs(wl.q0.reshape(-1) - 1.0) > 1e-2)[0], 32, replace=False)
     rows_of = np.arange(n) // wl.n_cols
     dvh = wl.dv.reshape(-1)
-    pool_dv = rng.permutation(np.where((np.abs(dvh) > 10 * eps) & (rows_of > 400)
-                                       & (rows_of < 650))[0])
-    ad, fdr, fd1 = [], [], []
-    skipped = 0
-    for kind, pool, want, g in (("q", near, 32, gq), ("dv", pool_dv, 16, gdv)):
-        got = 0
-        for idx in pool:
-            if got == want:
-                break
-            f1 = _fd(wl, rows, q0, dv, v0, area, tgt, steps, kind, idx, eps)
-            f2 = _fd(wl, rows, q0, dv, v0, area, tgt, steps, kind, idx, eps / 2)
-            if abs(f1 - f2) > 0.05 * max(abs(f2), 1e-30):
-                skipped += 1
-                continue
+    cdv = rng.choice(np.where((np.abs(dvh) > 1e-3) & (rows_of > 400) & (rows_of < 650))[0],
+                     16, replace=False)
+    epss = (1e-4, 1e-5, 1e-6)
+    ad, fd = [], []
+    for kind, idxs, g in (("q", cq, gq), ("dv", cdv, gdv)):
+        for idx in idxs:
             ad.append(float(g[idx]))
-            fdr.append((4.0 * f2 - f1) / 3.0)
-            fd1.append(f1)
-            got += 1
-        assert got == want
-    ad, fdr, fd1 = map(np.array, (ad, fdr, fd1))
-    rel_r = np.linalg.norm(ad - fdr) / np.linalg.norm(fdr)
-    rel_1 = np.linalg.norm(ad - fd1) / np.linalg.norm(fd1)
-    print(f"Q0+dv: Richardson FD norm-wise rel {rel_r:.3e}; plain eps=1e-4 {rel_1:.3e}; "
-          f"kink coordinates replaced {skipped}")
-    assert rel_r <= 1e-5
+            fd.append([_fd(wl, rows, q0, dv, v0, area, tgt, steps, kind, idx, h) for h in epss])
+    ad, fd = np.array(ad), np.array(fd)
+    rel = [np.linalg.norm(ad - fd[:, i]) / np.linalg.norm(fd[:, i]) for i in range(3)]
+    print("Q0+dv: FD norm-wise rel at eps 1e-4/1e-5/1e-6: " + " ".join(f"{r:.3e}" for r in rel))
+    assert rel[2] <= 1e-5
+    assert rel[2] < rel[0]
     errs = []
     for idx in rng.choice(np.arange(wl.n_rows)[200:800], 16, replace=False):
         a = float(gv0[idx])
-        e = [abs(_fd(wl, rows, q0, dv, v0, area, tgt, steps, "v0", idx, h) - a) / abs(a)
-             for h in (1e-4, 1e-5, 1e-6)]
-        errs.append(e)
+        errs.append([abs(_fd(wl, rows, q0, dv, v0, area, tgt, steps, "v0", idx, h) - a) / abs(a)
+                     for h in epss])
     errs = np.array(errs)
     print("v0: median FD rel error at eps 1e-4/1e-5/1e-6:", np.median(errs, axis=0))
     assert np.median(errs[:, 2]) <= 1e-3
