@@ -134,6 +134,38 @@ ram_status ram_residual_adjoint(ram_ctx *ctx, const ram_layout *layout,
                                 void *qbar_in, const double *edges, double dt,
                                 void *dvbar_accum);
 
+/* n_steps operator-split steps, keeping the trajectory (what a reverse pass
+ * over the steps needs; paper Section 1 with Section 3 and Eq.
+ * splitting_second).  q_traj holds n_steps+1 states of n_cells each, back to
+ * back: slot 0 is the input, slot k+1 is written with step k's result.  When
+ * dv != NULL, q_half (n_steps states) receives each step's state after the
+ * shift, i.e. the state its residual step read; with dv == NULL it is unused
+ * and may be NULL.  Results equal ram_step's bit for bit. */
+ram_status ram_step_record(ram_ctx *ctx, const ram_layout *layout,
+                           ram_dtype dtype, ram_scan scan, void *q_traj,
+                           void *q_half, const double *edges, const double *v0,
+                           const void *dv, double dt, int order, int64_t n_steps);
+
+/* Adjoint of one step Q^{n+1} = Res(Shift(Q^n)) (the transposes of
+ * ram_residual_adjoint and ram_shift_adjoint composed, in one pass over the
+ * data on a shared mesh):
+ *   qbar_in = S^T R_q^T qbar_out (overwritten),
+ *   dvbar_accum += R_dv^T qbar_out           (when non-NULL, dtype of q),
+ *   v0bar_accum[r] += dt d<R^T qbar_out, S(s) q_fwd>/ds at s = v0[r] dt
+ *                                             (when non-NULL, FP64).
+ * q_fwd is Q^n (needed only for v0bar), q_half the state after the shift
+ * (needed when dv != NULL; ram_step_record writes it).  dv == NULL: the step
+ * had no residual.  Same conventions at kinks as ram_residual_adjoint.  The
+ * residual part computes in dtype; the shift part accumulates in FP64 and
+ * rounds to dtype on the store.
+ * qbar_in must not alias any input. */
+ram_status ram_step_adjoint(ram_ctx *ctx, const ram_layout *layout,
+                            ram_dtype dtype, const void *q_fwd,
+                            const void *q_half, const void *dv,
+                            const void *qbar_out, void *qbar_in,
+                            const double *edges, const double *v0, double dt,
+                            int order, void *dvbar_accum, double *v0bar_accum);
+
 /* Host-side check of the inputs (synchronous; copies to the host): strictly
  * increasing finite nodes (RAM_E_MESH), and when dv != NULL the residual
  * Courant condition |dv_f| dt <= min(dx_{f-1}, dx_f) (RAM_E_CFL). */

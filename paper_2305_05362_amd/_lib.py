@@ -71,6 +71,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ram_step": [P, LP, I, I, P, P, P, P, D, I, I64],
         "ram_shift_adjoint": [P, LP, I, I, P, P, P, P, P, D, I, P],
         "ram_residual_adjoint": [P, LP, I, P, P, P, P, P, D, P],
+        "ram_step_record": [P, LP, I, I, P, P, P, P, P, D, I, I64],
+        "ram_step_adjoint": [P, LP, I, P, P, P, P, P, P, P, D, I, P, P],
         "ram_validate": [P, LP, I, P, P, D],
     }
     for name, args in sig.items():
@@ -233,6 +235,39 @@ class Context:
             _dev_ptr(dvbar, q_fwd.dtype, "dvbar")))
         return qbar_in
 
+    def ram_step_record(self, rows: Rows, q_traj, q_half, v0, dv, dt: float,
+                        order: int, n_steps: int, scan: int = RAM_SCAN_F64):
+        """q_traj: (n_steps+1, n_cells), slot 0 the input; q_half: (n_steps,
+        n_cells) or None when dv is None."""
+        self._stream()
+        n = int(n_steps)
+        if q_traj.numel() < (n + 1) * rows.n_cells:
+            raise ValueError("q_traj holds fewer than n_steps+1 states")
+        if dv is not None and (q_half is None or q_half.numel() < n * rows.n_cells):
+            raise ValueError("q_half holds fewer than n_steps states")
+        check(self._lib.ram_step_record(
+            self._h, ctypes.byref(rows.layout), _dtype_code(q_traj), int(scan),
+            _dev_ptr(q_traj, q_traj.dtype, "q_traj"),
+            _dev_ptr(q_half, q_traj.dtype, "q_half"),
+            _dev_ptr(rows.edges, torch.float64, "edges"),
+            _dev_ptr(v0, torch.float64, "v0"), _dev_ptr(dv, q_traj.dtype, "dv"),
+            float(dt), int(order), n))
+        return q_traj
+
+    def ram_step_adjoint(self, rows: Rows, q_fwd, q_half, dv, qbar_out, qbar_in,
+                         v0, dt: float, order: int, dvbar=None, v0bar=None):
+        self._stream()
+        t = qbar_out.dtype
+        check(self._lib.ram_step_adjoint(
+            self._h, ctypes.byref(rows.layout), _dtype_code(qbar_out),
+            _dev_ptr(q_fwd, t, "q_fwd"), _dev_ptr(q_half, t, "q_half"),
+            _dev_ptr(dv, t, "dv"), _dev_ptr(qbar_out, t, "qbar_out"),
+            _dev_ptr(qbar_in, t, "qbar_in"),
+            _dev_ptr(rows.edges, torch.float64, "edges"),
+            _dev_ptr(v0, torch.float64, "v0"), float(dt), int(order),
+            _dev_ptr(dvbar, t, "dvbar"), _dev_ptr(v0bar, torch.float64, "v0bar")))
+        return qbar_in
+
     def ram_validate(self, rows: Rows, dtype, dv=None, dt: float = 0.0):
         self._stream()
         code = RAM_F64 if dtype == torch.float64 else RAM_F32
@@ -277,6 +312,17 @@ def ram_shift_adjoint(rows, q_fwd, qbar_out, qbar_in, v0, dt, order,
 def ram_residual_adjoint(rows, q_fwd, dv, qbar_out, qbar_in, dt, dvbar=None):
     return context(q_fwd.device.index).ram_residual_adjoint(
         rows, q_fwd, dv, qbar_out, qbar_in, dt, dvbar)
+
+
+def ram_step_record(rows, q_traj, q_half, v0, dv, dt, order, n_steps, scan=RAM_SCAN_F64):
+    return context(q_traj.device.index).ram_step_record(
+        rows, q_traj, q_half, v0, dv, dt, order, n_steps, scan)
+
+
+def ram_step_adjoint(rows, q_fwd, q_half, dv, qbar_out, qbar_in, v0, dt, order,
+                     dvbar=None, v0bar=None):
+    return context(qbar_out.device.index).ram_step_adjoint(
+        rows, q_fwd, q_half, dv, qbar_out, qbar_in, v0, dt, order, dvbar, v0bar)
 
 
 def ram_validate(rows, dtype, dv=None, dt=0.0):

@@ -4,9 +4,10 @@ velocity dv and the per-row bulk velocity v0.
 
 Forward: n steps of (bulk shift, residual), keeping one state every
 ``checkpoint`` steps.  Backward: for each segment, newest first, recompute the
-segment from its checkpoint keeping the pre-shift and pre-residual states,
-then walk it backwards through the residual adjoint (dv-bar accumulates) and
-the shift adjoint (v0-bar accumulates).  Every step of both directions runs in
+segment from its checkpoint with ram_step_record (every state and every
+post-shift state), then walk it backwards with ram_step_adjoint (the residual
+transpose, dv-bar accumulating, then the shift transpose, v0-bar
+accumulating).  Every step of both directions runs in
 the library's HIP kernels; torch only holds the tensors.
 """
 from __future__ import annotations
@@ -63,29 +64,20 @@ class RamRollout(torch.autograd.Function):
         dvbar = torch.zeros_like(dv) if dv is not None else None
         v0bar = torch.zeros_like(v0, dtype=torch.float64)
         n_seg = len(checkpoints)
+        seg = min(fctx.checkpoint, fctx.n_steps)
+        traj = torch.empty((seg + 1, qbar.numel()), dtype=qbar.dtype, device=qbar.device)
+        half = torch.empty((seg, qbar.numel()), dtype=qbar.dtype,
+                           device=qbar.device) if dv is not None else None
         for sgi in range(n_seg - 1, -1, -1):
             start = sgi * fctx.checkpoint
             k = min(fctx.checkpoint, fctx.n_steps - start)
-            # recompute the segment, keeping the state before each shift and
-            # the state the residual step read
-            pre_shift, pre_res = [], []
-            q = checkpoints[sgi].clone()
-            for _ in range(k):
-                pre_shift.append(q)
-                h = torch.empty_like(q)
-                ctx.ram_shift(rows, q, h, v0, dt, order, scan)
-                if dv is not None:
-                    pre_res.append(h)
-                    q = torch.empty_like(h)
-                    ctx.ram_residual(rows, h, q, dv, dt)
-                else:
-                    q = h
+            # recompute the segment keeping every state and, with a residual,
+            # the state each residual step read (one fused launch per step)
+            traj[0].copy_(checkpoints[sgi].reshape(-1))
+            ctx.ram_step_record(rows, traj, half, v0, dv, dt, order, k, scan)
             for i in range(k - 1, -1, -1):
-                if dv is not None:
-                    ctx.ram_residual_adjoint(rows, pre_res[i], dv, qbar, tmp, dt, dvbar)
-                    qbar, tmp = tmp, qbar
-                ctx.ram_shift_adjoint(rows, pre_shift[i], qbar, tmp, v0, dt, order,
-                                      v0bar, scan)
+                ctx.ram_step_adjoint(rows, traj[i], None if half is None else half[i], dv,
+                                     qbar, tmp, v0, dt, order, dvbar, v0bar)
                 qbar, tmp = tmp, qbar
         return qbar, dvbar, v0bar.to(v0.dtype), None, None, None, None, None, None
 

@@ -1,0 +1,540 @@
+// ram_adjoint_shared.hip -- one RAM step backwards on rows sharing a mesh.
+//
+// The step is Q^n --shift--> Q^{n+1/2} --residual--> Q^{n+1}.  Given the
+// gradient Qbar^{n+1}, one tile of destination cells [i0, i0+nd) does, in one
+// pass:
+//
+//   (1) the residual adjoint (transpose of the upwind step's Jacobian at
+//       Q^{n+1/2}): Qbar^{n+1/2} on the tile's cells, and dvbar += on its
+//       faces -- slopes, face states and fluxes transposed over a two-cell
+//       halo; limiter derivative 0 where the one-sided slopes differ in sign,
+//       the dv >= 0 branch at dv = 0;
+//   (2) the shift adjoint.  With V_e the interpolated cumulative at shifted
+//       node e and M'_i = V_{i+1} - V_i, the transpose scatters
+//       Vbar_e = Mbar'_{e-1} - Mbar'_e through each node's Lagrange weights
+//       onto the window's node cumulative (Cbar, FP64 LDS atomics), and the
+//       source masses are the suffix sums Mbar_m = sum_{j > m} Cbar_j (a DPP
+//       block scan).  Source cells shared with the neighbouring tiles (the p
+//       cells of each boundary node's stencil) are accumulated with atomics
+//       after a zeroing pass; every other cell is written once;
+//   (3) v0bar += dt * sum_e -Vbar_e q~(x~_e), with q~ the reconstruction
+//       (derivative of the interpolated cumulative of Q^n) at the shifted
+//       node.
+//
+// Tiles whose source window does not fit in LDS gather instead: each window
+// cell telescopes the tile's Vbar down to one Mbar' plus the few stencils
+// that straddle it, with the weights recomputed from global memory.
+#include "ram_device.h"
+
+#include <type_traits>
+
+namespace ram {
+namespace {
+
+using namespace dev;
+
+constexpr int kWinA = 1536;             // LDS window capacity, cells
+
+template <typename T> struct RecA;
+template <> struct RecA<float> {
+    __device__ static const CellRec<float> *get(const MeshTab &t)
+    {
+        return (const CellRec<float> *)t.crf;
+    }
+};
+template <> struct RecA<double> {
+    __device__ static const CellRec<double> *get(const MeshTab &t)
+    {
+        return (const CellRec<double> *)t.crd;
+    }
+};
+
+__device__ inline int wrap1a(int j, int n)
+{
+    return j < 0 ? j + n : (j >= n ? j - n : j);
+}
+
+__device__ inline int cell_of_a(const double *x, int n, const MeshTab &tb,
+                                double bsc, double xh)
+{
+    int b = (int)((xh - x[0]) * bsc);
+    b = min(max(b, 0), tb.nb - 1);
+    int c = tb.bucket[b];
+    const double2 nx = tb.bnext[b];
+    c += (xh >= nx.x) ? 1 : 0;
+    if (xh >= nx.y) {
+        c += 1;
+        while (c + 1 < n && x[c + 1] <= xh) ++c;
+    }
+    return c;
+}
+
+// Shifted node -> extended source index g, its cell c, the wrapped position xh
+// and the Lagrange weights of its stencil in theta = (xh - x_c)/dx_c.
+template <typename WT, int P>
+__device__ inline int64_t node_eval_adj(const double *x, int n, const MeshTab &tb,
+                                        double bsc, double invlen, double len,
+                                        double s, double xe, int kx, WT *w, int &cc,
+                                        double &xh_out)
+{
+    const double xt = xe - s;
+    const double kf = floor((xt - x[0]) * invlen);
+    double xh = xt - kf * len;
+    int64_t k = (int64_t)kf;
+    if (xh >= x[n]) { xh -= len; k += 1; }
+    else if (xh < x[0]) { xh += len; k -= 1; }
+    const int c = cell_of_a(x, n, tb, bsc, xh);
+    const CellRec<WT> &r = RecA<WT>::get(tb)[c];
+    const WT th = (WT)((xh - r.xc) * r.dxinv);
+    WT t[P + 1];
+#pragma unroll
+    for (int a = 0; a <= P; ++a) t[a] = th - r.th[a];
+    WT pre[P + 1], suf[P + 1];
+    pre[0] = (WT)1;
+#pragma unroll
+    for (int a = 1; a <= P; ++a) pre[a] = pre[a - 1] * t[a - 1];
+    suf[P] = (WT)1;
+#pragma unroll
+    for (int a = P - 1; a >= 0; --a) suf[a] = suf[a + 1] * t[a + 1];
+#pragma unroll
+    for (int a = 0; a <= P; ++a) w[a] = r.rd[a] * (pre[a] * suf[a]);
+    cc = c;
+    xh_out = xh;
+    return (int64_t)c + (k + kx) * (int64_t)n;
+}
+
+// x-derivatives of the stencil weights at xh in cell c, FP64 (the product
+// rule carried through the prefix/suffix products).  FP64 whatever the state
+// type: the v0 gradient sums differences of the reconstruction between
+// neighbouring nodes, which rounding in the weights would swamp.
+template <int P>
+__device__ inline void node_dweights(const MeshTab &tb, int c, double xh, double *dw)
+{
+    const CellRec<double> &r = RecA<double>::get(tb)[c];
+    const double th = (xh - r.xc) * r.dxinv;
+    double t[P + 1], pre[P + 1], suf[P + 1], dpre[P + 1], dsuf[P + 1];
+#pragma unroll
+    for (int a = 0; a <= P; ++a) t[a] = th - r.th[a];
+    pre[0] = 1.0;
+    dpre[0] = 0.0;
+#pragma unroll
+    for (int a = 1; a <= P; ++a) {
+        pre[a] = pre[a - 1] * t[a - 1];
+        dpre[a] = dpre[a - 1] * t[a - 1] + pre[a - 1];
+    }
+    suf[P] = 1.0;
+    dsuf[P] = 0.0;
+#pragma unroll
+    for (int a = P - 1; a >= 0; --a) {
+        suf[a] = suf[a + 1] * t[a + 1];
+        dsuf[a] = dsuf[a + 1] * t[a + 1] + suf[a + 1];
+    }
+#pragma unroll
+    for (int a = 0; a <= P; ++a)
+        dw[a] = r.rd[a] * (dpre[a] * suf[a] + pre[a] * dsuf[a]) * r.dxinv;
+}
+
+// The reconstruction q~ at a shifted node from global memory (direct path).
+template <typename TQ, int P>
+__device__ __attribute__((noinline)) double direct_qtilde(
+    const double *x, const TQ *q, int n, const double *dw, int c)
+{
+    constexpr int LO = (P - 1) / 2;
+    double dq = 0.0;
+    for (int b = 0; b <= P; ++b) {
+        const int j = c - LO + b;
+        double d = 0.0;
+        if (j > c) {
+            for (int m = c; m < j; ++m) d += cell_mass(x, q, n, m);
+        } else if (j < c) {
+            for (int m = j; m < c; ++m) d += cell_mass(x, q, n, m);
+            d = -d;
+        }
+        dq += dw[b] * d;
+    }
+    return dq;
+}
+
+template <typename CT>
+struct AdjLds {
+    static constexpr size_t res = 6 * sizeof(CT) * (kStepNodes + 8) + (kStepNodes + 8);
+    static constexpr size_t win = 2 * sizeof(double) * (kWinA + 1);
+    static constexpr size_t nodes = 2 * sizeof(int64_t) * kStepNodes;
+    static constexpr size_t u0 = res > win ? res : win;
+    static constexpr size_t uni = u0 > nodes ? u0 : nodes;
+};
+
+template <typename TQ, int P, bool RES>
+__global__ __launch_bounds__(kBlock) void k_adj_sh(StepAdjArgs a)
+{
+    using CT = TQ;
+    using ACD = Acc<kScanF64>;
+    using L = AdjLds<CT>;
+    constexpr int LO = (P - 1) / 2;
+    constexpr int NI = kItems;
+
+    __shared__ double smb[kStepNodes];           // Mbar' of the tile's cells
+    __shared__ double sqt[kStepNodes];           // q~ at the tile's nodes
+    __shared__ double swt[kBlock / 64];
+    __shared__ double sred[kBlock / 64];
+    __shared__ __attribute__((aligned(16))) unsigned char su[L::uni];
+    __shared__ int s_flag;
+    // residual-adjoint arrays (index 0 <-> cell/face i0-2 resp. i0-1)
+    CT *sqh = (CT *)su;                          // Q^{n+1/2}, cells i0-2..
+    CT *sqb = sqh + (kStepNodes + 8);            // Qbar^{n+1}, same cells
+    CT *sqs = sqb + (kStepNodes + 8);            // face-state adjoint, faces i0-1..
+    CT *scs = sqs + (kStepNodes + 8);            // slope adjoint sent upwind
+    CT *sda = scs + (kStepNodes + 8);            // dsigma/da * hinv, cells i0-1..
+    CT *sdb = sda + (kStepNodes + 8);            // dsigma/db * hinv
+    unsigned char *sup = (unsigned char *)(sdb + (kStepNodes + 8));
+    // shift-adjoint arrays
+    double *scb = (double *)su;                  // Cbar on window nodes
+    double *spm = scb + (kWinA + 1);             // masses of the Q^n window
+    // direct path
+    int64_t *sgd = (int64_t *)su;
+
+    const Rows &R = a.rows;
+    const MeshTab &tb = R.tab;
+    const int n = (int)R.n_cols;
+    const int tpr = (n + R.tile - 1) / R.tile;
+    const int row = (int)(blockIdx.x / (unsigned)tpr);
+    const int i0 = ((int)blockIdx.x - row * tpr) * R.tile;
+    const int nd = min(R.tile, n - i0);
+    const int NE = nd + 1;
+    const bool inner = (i0 - 2 >= 0) && (i0 + nd + 2 < n);
+    const double *x = R.edges;
+    const int64_t qoff = (int64_t)row * n;
+    const TQ *qbo = (const TQ *)a.qbar_out + qoff;
+    TQ *qbi = (TQ *)a.qbar_in + qoff;
+    const TQ *qf = a.q_fwd ? (const TQ *)a.q_fwd + qoff : nullptr;
+    const bool want_v0 = a.v0bar != nullptr && qf != nullptr;
+    const double s = a.v0[row] * a.dt;
+    const double len = x[n] - x[0];
+    const double bsc = tb.scal[0], invlen = tb.scal[1];
+    const int64_t wlo = a.plan_wlo[blockIdx.x];
+    const int W = a.plan_w[blockIdx.x];
+    const int t = threadIdx.x;
+    auto wr = [&](int j) { return inner ? j : wrap1a(j, n); };
+    const CT dt = (CT)a.dt;
+
+    // ---- (1) residual adjoint: Mbar' of the tile's cells -------------------
+    if (RES) {
+        const TQ *qh = (const TQ *)a.q_half + qoff;
+        const TQ *dv = (const TQ *)a.dv + qoff;
+        TQ *dvb = a.dvbar ? (TQ *)a.dvbar + qoff : nullptr;
+        for (int u = t; u < nd + 4; u += kBlock) {
+            const int c = wr(i0 - 2 + u);
+            sqh[u] = (CT)qh[c];
+            sqb[u] = (CT)qbo[c];
+        }
+        __syncthreads();
+        // faces i0-1+u: flux adjoint, face-state adjoint, slope adjoint
+        for (int u = t; u < nd + 3; u += kBlock) {
+            const int f = wr(i0 - 1 + u), fm = wr(i0 - 2 + u);
+            const CT v = (CT)dv[f];
+            const bool up = v >= (CT)0;
+            const CT fbar = dt * (sqb[u + 1] * TabT<CT>::dxinv(tb)[f] -
+                                  sqb[u] * TabT<CT>::dxinv(tb)[fm]);
+            const CT qsb = fbar * v;
+            const int uc = up ? fm : f;
+            const CT dxu = TabT<CT>::dx(tb)[uc];
+            sqs[u] = qsb;
+            scs[u] = qsb * (up ? (CT)0.5 * (dxu - v * dt) : (CT)-0.5 * (dxu + v * dt));
+            sup[u] = up ? 1 : 0;
+            if (dvb && u >= 1 && u <= nd) {
+                // owned face i0+u-1: its upwind cell's slope at Q^{n+1/2}
+                const int su_ = up ? u : u + 1;            // state index of uc
+                const int ucm = wr(i0 - 2 + su_ - 1);
+                const CT hp = TabT<CT>::hinv(tb)[uc], hm = TabT<CT>::hinv(tb)[ucm];
+                const CT dp = (sqh[su_ + 1] - sqh[su_]) * hp;
+                const CT dm = (sqh[su_] - sqh[su_ - 1]) * hm;
+                const CT sig = (dp * dm <= (CT)0) ? (CT)0 : harmonic2(dp, dm);
+                const CT qs = sqh[su_] + sig * (up ? (CT)0.5 * (dxu - v * dt)
+                                                    : (CT)-0.5 * (dxu + v * dt));
+                dvb[f] = (TQ)((CT)dvb[f] + fbar * (qs - (CT)0.5 * sig * v * dt));
+            }
+        }
+        // cells i0-1+u: limiter partial derivatives (times the gap inverses)
+        for (int u = t; u < nd + 2; u += kBlock) {
+            const int j = wr(i0 - 1 + u), jm = wr(i0 - 2 + u);
+            const CT hp = TabT<CT>::hinv(tb)[j], hm = TabT<CT>::hinv(tb)[jm];
+            const CT ap = (sqh[u + 2] - sqh[u + 1]) * hp;
+            const CT bm = (sqh[u + 1] - sqh[u]) * hm;
+            CT da = (CT)0, db = (CT)0;
+            if (ap * bm > (CT)0) {
+                const CT inv = (CT)1 / ((ap + bm) * (ap + bm));
+                da = (CT)2 * bm * bm * inv * hp;
+                db = (CT)2 * ap * ap * inv * hm;
+            }
+            sda[u] = da;
+            sdb[u] = db;
+        }
+        __syncthreads();
+        for (int u = t; u < nd; u += kBlock) {
+            auto sigbar = [&](int k) {
+                return (sup[k] == 0 ? scs[k] : (CT)0) + (sup[k + 1] != 0 ? scs[k + 1] : (CT)0);
+            };
+            CT gsum = sqb[u + 2];
+            if (sup[u + 1] == 0) gsum += sqs[u + 1];
+            if (sup[u + 2] != 0) gsum += sqs[u + 2];
+            gsum += sigbar(u) * sda[u] + sigbar(u + 1) * (sdb[u + 1] - sda[u + 1]) -
+                    sigbar(u + 2) * sdb[u + 2];
+            smb[u] = (double)gsum * TabT<double>::dxinv(tb)[i0 + u];
+        }
+    } else {
+        for (int u = t; u < nd; u += kBlock)
+            smb[u] = (double)qbo[i0 + u] * TabT<double>::dxinv(tb)[i0 + u];
+    }
+    __syncthreads();
+
+    // ---- (2) shifted nodes, tile-local Vbar ---------------------------------
+    int64_t g[NI];
+    CT w[NI][P + 1];
+    double vb[NI], xh[NI];
+    int cc[NI];
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        const int e = t + k * kBlock;
+        g[k] = 0;
+        vb[k] = 0.0;
+        if (e < NE) {
+            const int en = i0 + e;
+            const int kx = en >= n ? 1 : 0;
+            const double xe = x[en >= n ? en - n : en];
+            g[k] = node_eval_adj<CT, P>(x, n, tb, bsc, invlen, len, s, xe, kx, w[k], cc[k],
+                                        xh[k]);
+            vb[k] = (e >= 1 ? smb[e - 1] : 0.0) - (e <= nd - 1 ? smb[e] : 0.0);
+            const int64_t jc = g[k] - wlo;
+            ok = ok && jc >= LO && jc + P - LO <= W;
+        }
+    }
+    if (t == 0) s_flag = W > 0 ? 1 : 0;
+    __syncthreads();
+    if (!ok) s_flag = 0;
+    __syncthreads();
+    const bool windowed = s_flag != 0;
+
+    if (windowed) {
+        // ---- Cbar scatter --------------------------------------------------
+        for (int j = t; j <= W; j += kBlock) scb[j] = 0.0;
+        int base = 0;
+        {
+            const int64_t kk = wlo >= 0 ? wlo / n : -((-wlo + n - 1) / n);
+            base = (int)(wlo - kk * n);
+        }
+        // forward window masses for the reconstruction at the nodes
+        if (want_v0) {
+            for (int j = t; j < W; j += kBlock) {
+                int mm = base + j;
+                mm = mm >= n ? wrap_small(mm, n) : mm;
+                spm[j] = (double)qf[mm] * TabT<double>::dx(tb)[mm];
+            }
+        }
+        __syncthreads();
+        // V_e = C(g) + sum_{a != lo} w_a (C(g-lo+a) - C(g)): the node's own
+        // cumulative enters with weight exactly one, so the suffix sums of
+        // cells below the stencil telescope without the weights' rounding
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+            if (t + k * kBlock < NE) {
+                const int jc = (int)(g[k] - wlo);
+                double part = 0.0;
+#pragma unroll
+                for (int b = 0; b <= P; ++b) {
+                    if (b == LO) continue;
+                    const double c = (double)w[k][b] * vb[k];
+                    atomicAdd(&scb[jc - LO + b], c);
+                    part += c;
+                }
+                atomicAdd(&scb[jc], vb[k] - part);
+            }
+        }
+        __syncthreads();
+        // ---- suffix sums over the window nodes -----------------------------
+        const int NN = W + 1;
+        const int per = (NN + kBlock - 1) / kBlock;
+        const int j0 = min(NN, t * per), j1 = min(NN, j0 + per);
+        double mine[8], run = 0.0;
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+            if (j0 + r < j1) {
+                mine[r] = scb[j0 + r];
+                run += mine[r];
+            }
+        double total;
+        double acc = block_exscan_dpp<ACD>(run, swt, total);
+        // S(cell j) = total - sum_{node <= j} Cbar
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+            if (j0 + r < j1) {
+                acc += mine[r];
+                scb[j0 + r] = total - acc;
+            }
+        __syncthreads();
+        // ---- Qbar = dx * S: interior cells once, shared cells by atomics ---
+        for (int j = t; j < W; j += kBlock) {
+            int mm = base + j;
+            mm = mm >= n ? wrap_small(mm, n) : mm;
+            const double val = scb[j] * TabT<double>::dx(tb)[mm];
+            if (j >= P && j < W - P) qbi[mm] = (TQ)val;
+            else atomicAdd(&qbi[mm], (TQ)val);
+        }
+        // reconstruction q~ at the nodes: sum_b w'_b (C(g-lo+b) - C(g)) / dx_c,
+        // the differences summed from the masses next to the node
+        if (want_v0) {
+#pragma unroll
+            for (int k = 0; k < NI; ++k) {
+                const int e = t + k * kBlock;
+                if (e < NE) {
+                    const int jc = (int)(g[k] - wlo);
+                    double dwd[P + 1];
+                    node_dweights<P>(tb, cc[k], xh[k], dwd);
+                    double dq = 0.0, up = 0.0, dn = 0.0;
+#pragma unroll
+                    for (int b = LO + 1; b <= P; ++b) {
+                        up += spm[jc + b - LO - 1];
+                        dq += dwd[b] * up;
+                    }
+#pragma unroll
+                    for (int b = LO - 1; b >= 0; --b) {
+                        dn += spm[jc - LO + b];
+                        dq -= dwd[b] * dn;
+                    }
+                    sqt[e] = dq;
+                }
+            }
+        }
+    } else {
+        // ---- direct path: gather per window cell ---------------------------
+        double *svb = (double *)(sgd + kStepNodes);
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+            if (t + k * kBlock < NE) {
+                sgd[t + k * kBlock] = g[k];
+                svb[t + k * kBlock] = vb[k];
+            }
+        }
+        __syncthreads();
+        // window bounds from the plan: this tile's first cell and the next
+        // tile's (the row's first tile one period on, for the last tile), so
+        // the shared cells are exactly the ones the zeroing pass cleared
+        const int64_t wl = wlo;
+        const bool last = i0 + nd >= n;
+        const int64_t wend =
+            (last ? a.plan_wlo[blockIdx.x - (tpr - 1)] + n : a.plan_wlo[blockIdx.x + 1]) + P;
+        const int Wd = (int)(wend - wl);
+        for (int j = t; j < Wd; j += kBlock) {
+            const int64_t target = wl + j + LO;
+            int lo = 0, hi = NE;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (sgd[mid] > target) hi = mid; else lo = mid + 1;
+            }
+            double S = (lo >= 1 && lo <= nd) ? smb[lo - 1] : 0.0;
+            for (int e = lo - 1; e >= 0 && sgd[e] > target - P; --e) {
+                const int en = i0 + e;
+                const int kx = en >= n ? 1 : 0;
+                double ww[P + 1], xh2;
+                int c2;
+                node_eval_adj<double, P>(x, n, tb, bsc, invlen, len, s,
+                                         x[en >= n ? en - n : en], kx, ww, c2, xh2);
+                // the share of the node's weights on cumulative nodes above
+                // the cell, with the node's own weight taken as one minus the
+                // others (the form the windowed scatter uses)
+                const int bmin = (int)min((int64_t)P, max((int64_t)1, target - sgd[e] + 1));
+                double h = 0.0;
+                if (bmin > LO) {
+                    for (int b = P; b >= bmin; --b) h += ww[b];
+                } else {
+                    for (int b = 0; b < bmin; ++b) h += ww[b];
+                    h = 1.0 - h;
+                }
+                S += svb[e] * h;
+            }
+            const int mm = wrapi(wl + j, n);
+            const double val = S * TabT<double>::dx(tb)[mm];
+            if (j >= P && j < Wd - P) qbi[mm] = (TQ)val;
+            else atomicAdd(&qbi[mm], (TQ)val);
+        }
+        if (want_v0) {
+#pragma unroll
+            for (int k = 0; k < NI; ++k) {
+                const int e = t + k * kBlock;
+                if (e < NE) {
+                    double dwd[P + 1];
+                    node_dweights<P>(tb, cc[k], xh[k], dwd);
+                    sqt[e] = direct_qtilde<TQ, P>(x, qf, n, dwd, cc[k]);
+                }
+            }
+        }
+    }
+    // ---- (3) v0bar ------------------------------------------------------------
+    // dV_e/ds = -q~_e; with Vbar_e = Mbar'_{e-1} - Mbar'_e the tile's sum
+    // telescopes to -sum_i Mbar'_i (q~_{i+1} - q~_i), which keeps the
+    // cancellation between neighbouring nodes inside one FP64 difference
+    if (want_v0) {
+        __syncthreads();
+        double vpart = 0.0;
+        for (int u = t; u < nd; u += kBlock) vpart -= smb[u] * (sqt[u + 1] - sqt[u]);
+        for (int d = 32; d >= 1; d >>= 1) vpart += __shfl_xor(vpart, d);
+        if ((t & 63) == 0) sred[t >> 6] = vpart;
+        __syncthreads();
+        if (t == 0) {
+            double tot = 0.0;
+            for (int wv = 0; wv < kBlock / 64; ++wv) tot += sred[wv];
+            atomicAdd(&a.v0bar[row], a.dt * tot);
+        }
+    }
+}
+
+// Zero the p cells at the start of every tile's window: the only cells more
+// than one tile accumulates into (a tile's last p window cells start the next
+// tile's window; the last tile of a row wraps onto the first).
+template <typename TQ, int P>
+__global__ __launch_bounds__(256) void k_adj_zero(StepAdjArgs a)
+{
+    const int64_t tile = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (tile >= a.rows.n_tiles) return;
+    const int n = (int)a.rows.n_cols;
+    const int tpr = (n + a.rows.tile - 1) / a.rows.tile;
+    const int64_t row = tile / tpr;
+    TQ *qbi = (TQ *)a.qbar_in + row * n;
+    const int64_t wlo = a.plan_wlo[tile];
+    for (int b = 0; b < P; ++b) qbi[wrapi(wlo + b, n)] = (TQ)0;
+}
+
+template <typename TQ, int P>
+hipError_t adj_order(const StepAdjArgs &a, hipStream_t st)
+{
+    const unsigned zg = (unsigned)((a.rows.n_tiles + 255) / 256);
+    hipLaunchKernelGGL((k_adj_zero<TQ, P>), dim3(zg), dim3(256), 0, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const dim3 g((unsigned)a.rows.n_tiles), b(kBlock);
+    if (a.dv) hipLaunchKernelGGL((k_adj_sh<TQ, P, true>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((k_adj_sh<TQ, P, false>), g, b, 0, st, a);
+    return hipGetLastError();
+}
+
+template <typename TQ>
+hipError_t adj_dispatch(const StepAdjArgs &a, int order, hipStream_t st)
+{
+    switch (order) {
+    case 1: return adj_order<TQ, 1>(a, st);
+    case 3: return adj_order<TQ, 3>(a, st);
+    default: return adj_order<TQ, 5>(a, st);
+    }
+}
+
+} // namespace
+
+hipError_t launch_step_adjoint_shared(const StepAdjArgs &a, bool f64, int order,
+                                      hipStream_t stream)
+{
+    if (a.rows.n_tiles <= 0) return hipSuccess;
+    if (f64) return adj_dispatch<double>(a, order, stream);
+    return adj_dispatch<float>(a, order, stream);
+}
+
+} // namespace ram

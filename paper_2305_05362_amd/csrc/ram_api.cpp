@@ -246,6 +246,46 @@ ram_status launch_steps(ram_ctx *ctx, ram::StepArgs a, ram_dtype dtype,
     return RAM_OK;
 }
 
+// One step backwards on a shared mesh: window plan of the shift (no halo),
+// then the zeroing pass and the fused adjoint.
+ram_status step_adjoint_shared(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
+                               const void *q_fwd, const void *q_half, const void *dv,
+                               const void *qbar_out, void *qbar_in, const double *edges,
+                               const double *v0, double dt, int order, void *dvbar,
+                               double *v0bar)
+{
+    ram_status st;
+    Carve cv;
+    RowsPlan rp = plan_rows(cv, layout, ram::step_tile(false), order);
+    const int64_t nt = tiles_of(layout, rp.tile);
+    const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(sizeof(int32_t) * nt);
+    if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
+    ram::StepArgs p;
+    if ((st = make_rows(ctx, layout, edges, rp, p.rows)) != RAM_OK) return st;
+    p.v0 = v0;
+    p.dt = dt;
+    int64_t *wlo = (int64_t *)((char *)ctx->scratch + wlo_off);
+    int32_t *w = (int32_t *)((char *)ctx->scratch + w_off);
+    hipError_t e = ram::launch_plan(p, order, wlo, w, ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "window plan launch");
+    ram::StepAdjArgs a;
+    a.rows = p.rows;
+    a.q_fwd = q_fwd;
+    a.q_half = q_half;
+    a.dv = dv;
+    a.qbar_out = qbar_out;
+    a.qbar_in = qbar_in;
+    a.dvbar = dvbar;
+    a.v0bar = v0bar;
+    a.v0 = v0;
+    a.dt = dt;
+    a.plan_wlo = wlo;
+    a.plan_w = w;
+    e = ram::launch_step_adjoint_shared(a, dtype == RAM_F64, order, ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "step adjoint launch");
+    return RAM_OK;
+}
+
 } // namespace
 
 extern "C" {
@@ -425,6 +465,9 @@ ram_status ram_shift_adjoint(ram_ctx *ctx, const ram_layout *layout,
     if (qbar_in == qbar_out) return fail(RAM_E_INVALID_ARG, "qbar_in and qbar_out must not alias");
     if (v0bar_accum && !q_fwd) return fail(RAM_E_INVALID_ARG, "v0bar needs the forward state q_fwd");
     if ((st = enter(ctx)) != RAM_OK) return st;
+    if (layout->edges_shared)
+        return step_adjoint_shared(ctx, layout, dtype, q_fwd, nullptr, nullptr, qbar_out,
+                                   qbar_in, edges, v0, dt, order, nullptr, v0bar_accum);
     Carve cv;
     RowsPlan rp = plan_rows(cv, layout, ram::kTile, 0);
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
@@ -469,6 +512,115 @@ ram_status ram_residual_adjoint(ram_ctx *ctx, const ram_layout *layout,
     a.dt = dt;
     hipError_t e = ram::launch_residual_adjoint(a, dtype == RAM_F64, ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "residual adjoint launch");
+    return RAM_OK;
+}
+
+ram_status ram_step_record(ram_ctx *ctx, const ram_layout *layout,
+                           ram_dtype dtype, ram_scan scan, void *q_traj,
+                           void *q_half, const double *edges, const double *v0,
+                           const void *dv, double dt, int order, int64_t n_steps)
+{
+    ram_status st;
+    g_last_error.clear();
+    if ((st = check_layout(layout, edges)) != RAM_OK) return st;
+    if ((st = check_dtype(dtype)) != RAM_OK) return st;
+    if ((st = check_scan(dtype, scan)) != RAM_OK) return st;
+    if ((st = check_order(layout, order)) != RAM_OK) return st;
+    if ((st = check_dt(dt)) != RAM_OK) return st;
+    if (!q_traj || !v0) return fail(RAM_E_INVALID_ARG, "null q_traj or v0");
+    if (dv && !q_half) return fail(RAM_E_INVALID_ARG, "a step with dv needs q_half");
+    if (n_steps < 0) return fail(RAM_E_INVALID_ARG, "n_steps must be >= 0");
+    if (n_steps == 0) return RAM_OK;
+    if ((st = enter(ctx)) != RAM_OK) return st;
+    const size_t state_bytes = elem_size(dtype) * (size_t)layout_cells(layout);
+    Carve cv;
+    RowsPlan rp = plan_rows(cv, layout, ram::step_tile(dv != nullptr), order);
+    const int64_t nt = tiles_of(layout, rp.tile);
+    const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(sizeof(int32_t) * nt);
+    if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
+    ram::StepArgs a;
+    if ((st = make_rows(ctx, layout, edges, rp, a.rows)) != RAM_OK) return st;
+    a.v0 = v0;
+    a.dv = dv;
+    a.dt = dt;
+    const bool f64 = dtype == RAM_F64;
+    const bool shared = a.rows.has_tab != 0 && a.rows.n_cols > 0;
+    hipError_t e;
+    if (shared) {
+        int64_t *wlo = (int64_t *)((char *)ctx->scratch + wlo_off);
+        int32_t *w = (int32_t *)((char *)ctx->scratch + w_off);
+        e = ram::launch_plan(a, order, wlo, w, ctx->stream);
+        if (e != hipSuccess) return hip_fail(e, "window plan launch");
+        a.plan_wlo = wlo;
+        a.plan_w = w;
+    }
+    for (int64_t k = 0; k < n_steps; ++k) {
+        a.q_in = (const char *)q_traj + k * state_bytes;
+        a.q_out = (char *)q_traj + (k + 1) * state_bytes;
+        a.q_mid = dv ? (char *)q_half + k * state_bytes : nullptr;
+        e = shared ? ram::launch_step_shared(a, f64, (int)scan, order, ctx->stream)
+                   : ram::launch_step(a, f64, (int)scan, order, ctx->stream);
+        if (e != hipSuccess) return hip_fail(e, "step launch");
+    }
+    return RAM_OK;
+}
+
+ram_status ram_step_adjoint(ram_ctx *ctx, const ram_layout *layout,
+                            ram_dtype dtype, const void *q_fwd,
+                            const void *q_half, const void *dv,
+                            const void *qbar_out, void *qbar_in,
+                            const double *edges, const double *v0, double dt,
+                            int order, void *dvbar_accum, double *v0bar_accum)
+{
+    ram_status st;
+    g_last_error.clear();
+    if ((st = check_layout(layout, edges)) != RAM_OK) return st;
+    if ((st = check_dtype(dtype)) != RAM_OK) return st;
+    if ((st = check_order(layout, order)) != RAM_OK) return st;
+    if ((st = check_dt(dt)) != RAM_OK) return st;
+    if (!qbar_out || !qbar_in || !v0) return fail(RAM_E_INVALID_ARG, "null qbar_out, qbar_in or v0");
+    if (dv && !q_half) return fail(RAM_E_INVALID_ARG, "a step with dv needs q_half");
+    if (v0bar_accum && !q_fwd) return fail(RAM_E_INVALID_ARG, "v0bar needs the forward state q_fwd");
+    if (dvbar_accum && !dv) return fail(RAM_E_INVALID_ARG, "dvbar needs dv");
+    if (qbar_in == qbar_out || qbar_in == q_fwd || qbar_in == q_half || qbar_in == dv)
+        return fail(RAM_E_INVALID_ARG, "qbar_in must not alias an input");
+    if ((st = enter(ctx)) != RAM_OK) return st;
+    if (layout->edges_shared)
+        return step_adjoint_shared(ctx, layout, dtype, q_fwd, q_half, dv, qbar_out, qbar_in,
+                                   edges, v0, dt, order, dvbar_accum, v0bar_accum);
+    // per-row meshes: the residual transpose into scratch, then the shift's
+    const size_t state_bytes = elem_size(dtype) * (size_t)layout_cells(layout);
+    Carve cv;
+    const size_t mid_off = dv ? cv.take(state_bytes) : 0;
+    RowsPlan rp = plan_rows(cv, layout, ram::kTile, 0);
+    if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
+    ram::Rows rows;
+    if ((st = make_rows(ctx, layout, edges, rp, rows)) != RAM_OK) return st;
+    const void *qb = qbar_out;
+    hipError_t e;
+    if (dv) {
+        ram::ResidualAdjArgs r;
+        r.rows = rows;
+        r.q_fwd = q_half;
+        r.dv = dv;
+        r.qbar_out = qbar_out;
+        r.qbar_in = (char *)ctx->scratch + mid_off;
+        r.dvbar = dvbar_accum;
+        r.dt = dt;
+        e = ram::launch_residual_adjoint(r, dtype == RAM_F64, ctx->stream);
+        if (e != hipSuccess) return hip_fail(e, "residual adjoint launch");
+        qb = r.qbar_in;
+    }
+    ram::ShiftAdjArgs a;
+    a.rows = rows;
+    a.q_fwd = q_fwd;
+    a.qbar_out = qb;
+    a.qbar_in = qbar_in;
+    a.v0 = v0;
+    a.dt = dt;
+    a.v0bar = v0bar_accum;
+    e = ram::launch_shift_adjoint(a, dtype == RAM_F64, order, ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "shift adjoint launch");
     return RAM_OK;
 }
 

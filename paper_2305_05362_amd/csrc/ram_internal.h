@@ -81,6 +81,7 @@ struct StepArgs {
     double dt = 0.0;
     const int64_t *plan_wlo = nullptr;  // shared mesh: per-tile window start
     const int32_t *plan_w = nullptr;    // ... and length (-1: direct path)
+    void *q_mid = nullptr;              // optional: the state after the shift
 };
 
 struct ResidualArgs {
@@ -99,6 +100,23 @@ struct ShiftAdjArgs {
     const double *v0 = nullptr;
     double dt = 0.0;
     double *v0bar = nullptr;          // per-row accumulator or null
+};
+
+// One step backwards on a shared mesh (fused residual adjoint, then shift
+// adjoint).  dv == null: the step had no residual, qbar_out is the shift's.
+struct StepAdjArgs {
+    Rows rows;                          // tile = step_tile(false), tables set
+    const void *q_fwd = nullptr;        // state before the shift (v0bar)
+    const void *q_half = nullptr;       // state the residual read
+    const void *dv = nullptr;
+    const void *qbar_out = nullptr;
+    void *qbar_in = nullptr;
+    void *dvbar = nullptr;              // accumulator or null
+    double *v0bar = nullptr;            // accumulator or null
+    const double *v0 = nullptr;
+    double dt = 0.0;
+    const int64_t *plan_wlo = nullptr;  // window plan of the shift (no halo)
+    const int32_t *plan_w = nullptr;
 };
 
 struct ResidualAdjArgs {
@@ -146,6 +164,9 @@ hipError_t launch_shift_adjoint(const ShiftAdjArgs &a, bool f64, int order,
                                 hipStream_t stream);
 hipError_t launch_residual_adjoint(const ResidualAdjArgs &a, bool f64,
                                    hipStream_t stream);
+// Zero the cells several tiles accumulate into, then the fused adjoint.
+hipError_t launch_step_adjoint_shared(const StepAdjArgs &a, bool f64, int order,
+                                      hipStream_t stream);
 hipError_t launch_copy(const void *src, void *dst, int64_t bytes,
                        hipStream_t stream);
 

@@ -136,6 +136,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a)
     const double *x = ti.x;
     const TQ *q = (const TQ *)a.q_in + ti.qoff;
     TQ *qo = (TQ *)a.q_out + ti.qoff;
+    TQ *qmid = a.q_mid ? (TQ *)a.q_mid + ti.qoff : nullptr;
     const double s = a.v0[ti.row] * a.dt;
     const double len = x[n] - x[0];
     const int t = threadIdx.x;
@@ -295,6 +296,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a)
             if (tab) qs[k] = (CT)(mp * (D)TabT<D>::dxinv(R.tab)[cell]);
             else qs[k] = (CT)(mp / (D)(x[cell + 1] - x[cell]));
             if (H == 0) qo[cell] = (TQ)qs[k];
+            else if (qmid && ci >= H && ci < H + nd) qmid[cell] = (TQ)qs[k];
         }
     }
     if (H == 0) return;

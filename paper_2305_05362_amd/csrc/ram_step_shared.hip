@@ -172,6 +172,7 @@ __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
     const int64_t qoff = (int64_t)row * n;
     const TQ *q = (const TQ *)a.q_in + qoff;
     TQ *qo = (TQ *)a.q_out + qoff;
+    TQ *qmid = a.q_mid ? (TQ *)a.q_mid + qoff : nullptr;
     const double s = a.v0[row] * a.dt;
     const double len = x[n] - x[0];
     const double bsc = tb.scal[0], invlen = tb.scal[1];
@@ -335,6 +336,7 @@ __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
             }
             qs[k] = mp * TabT<CT>::dxinv(tb)[cell];
             if (H == 0) qo[cell] = (TQ)qs[k];
+            else if (qmid && ci >= H && ci < H + nd) qmid[cell] = (TQ)qs[k];
         }
     }
     if (H == 0) return;

@@ -98,3 +98,30 @@ def test_argument_errors_without_device(lib):
     st = lib.ram_shift(None, ctypes.byref(L), R.RAM_F64, R.RAM_SCAN_F64, fake,
                        ctypes.c_void_p(0x2000), fake, fake, 0.1, 5)
     assert st == R.RAM_E_INVALID_ARG and b"context" in lib.ram_last_error()
+
+
+def test_record_and_step_adjoint_argument_errors(lib):
+    from paper_2305_05362_amd import _lib as R
+    L = _layout()
+    a, b, c, d = (ctypes.c_void_p(0x1000 * i) for i in (1, 2, 3, 4))
+    # a step with a residual must record the post-shift states
+    st = lib.ram_step_record(None, ctypes.byref(L), R.RAM_F64, R.RAM_SCAN_F64, a, None,
+                             b, c, d, 0.1, 5, 4)
+    assert st == R.RAM_E_INVALID_ARG and b"q_half" in lib.ram_last_error()
+    st = lib.ram_step_record(None, ctypes.byref(L), R.RAM_F64, R.RAM_SCAN_F64, a, None,
+                             b, c, None, 0.1, 5, -1)
+    assert st == R.RAM_E_INVALID_ARG and b"n_steps" in lib.ram_last_error()
+    # adjoint: dvbar without dv, v0bar without q_fwd, aliasing output
+    st = lib.ram_step_adjoint(None, ctypes.byref(L), R.RAM_F64, a, None, None, b,
+                              c, d, d, 0.1, 5, ctypes.c_void_p(0x9000), None)
+    assert st == R.RAM_E_INVALID_ARG and b"dvbar" in lib.ram_last_error()
+    st = lib.ram_step_adjoint(None, ctypes.byref(L), R.RAM_F64, None, None, None, b,
+                              c, d, d, 0.1, 5, None, ctypes.c_void_p(0x9000))
+    assert st == R.RAM_E_INVALID_ARG and b"q_fwd" in lib.ram_last_error()
+    st = lib.ram_step_adjoint(None, ctypes.byref(L), R.RAM_F64, a, b, d, c,
+                              b, d, d, 0.1, 5, None, None)
+    assert st == R.RAM_E_INVALID_ARG and b"alias" in lib.ram_last_error()
+    # valid arguments, null context
+    st = lib.ram_step_adjoint(None, ctypes.byref(L), R.RAM_F64, a, b, d, c,
+                              ctypes.c_void_p(0x7000), d, d, 0.1, 5, None, None)
+    assert st == R.RAM_E_INVALID_ARG and b"context" in lib.ram_last_error()

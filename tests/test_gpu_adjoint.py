@@ -1,14 +1,14 @@
 """Gradients of the checkpointed RAM rollout (autograd over the HIP adjoints).
 
-* central finite differences (eps = 1e-4, FP64 path) at 64 seeded coordinates
-  of the polar 1024 x 4096 workload, 200 steps, checkpoint every 20:
-  32 in Q0, 16 in dv, 16 in v0; norm-wise relative error <= 1e-5;
+* central finite differences (eps = 1e-4, FP64 path) on the polar
+  1024 x 4096 workload, 200 steps, checkpoint every 20: 32 coordinates in Q0
+  and 16 in dv, norm-wise relative error <= 1e-5 (coordinates next to a kink
+  replaced by the next draw); 16 in v0 by convergence of the differences;
 * the FP64 oracle gradient on sampled rows (rows are independent, so a row's
   loss gradient only involves that row): relative L1 <= 1e-10;
 * the FP32-state gradient against the FP64 one (reported, loose bar);
 * checkpoint spacing does not change the gradient.
-Kinks (upwind switch at dv = 0) are avoided by drawing dv coordinates away
-from zero.
+dv coordinates are drawn away from zero (the upwind switch).
 """
 import numpy as np
 import pytest
@@ -87,17 +87,20 @@ def _fd(wl, rows, q0, dv, v0, area, tgt, steps, kind, idx, eps):
 
 
 def test_rollout_gradient_fd_cfg4():
-    """Central differences at 32 Q0, 16 dv and 16 v0 coordinates, FP64 path.
+    """Central differences at eps = 1e-4 (FP64 path) against the adjoint
+    gradient, 32 coordinates in Q0 and 16 in dv, norm-wise <= 1e-5.
 
-    The polar state carries 1e-3 white noise, so van Leer limiter kinks are
-    dense: a perturbation of 1e-4 moves some slope products through zero
-    somewhere in 200 steps, and the difference quotient then averages the
-    two branch derivatives (first-order error).  The differences are taken at
-    eps = 1e-4, 1e-5 and 1e-6; the bar (norm-wise <= 1e-5) applies at
-    eps = 1e-6, where the quotient resolves the branch the adjoint follows,
-    and the error must shrink with eps.  The v0 dependence is piecewise smooth
-    with a kink at every node crossing, so there the differences must converge
-    to the adjoint (median <= 1e-3 at 1e-6 and > 3x smaller than at 1e-4)."""
+    The loss is continuous but only piecewise smooth: the van Leer limiter
+    switches branch where a slope product crosses zero and the polar state
+    carries 1e-3 white noise, so such kinks are dense along a 200-step
+    rollout.  A coordinate whose +-eps interval holds a kink is detected by
+    comparing the differences at eps and eps/4 (on a smooth stretch they agree
+    to O(eps^2)) and is replaced by the next draw of the seeded sequence; the
+    number replaced is printed.  The v0 dependence has a kink wherever a
+    shifted node crosses a source node, which any eps on a 4096-cell row
+    does, so there the differences must converge to the adjoint instead
+    (median relative error <= 1e-3 at eps = 1e-6 and more than 3x below the
+    one at 1e-4); the oracle-gradient test pins v0bar exactly."""
     wl = W.cfg4()
     steps, ckpt = 200, 20
     rows, q0, dv, v0, area = _setup(wl)
@@ -105,22 +108,38 @@ def test_rollout_gradient_fd_cfg4():
     gq, gdv, gv0, _ = _grads(wl, rows, q0, dv, v0, area, tgt, steps, ckpt)
     rng = W.rng_for(4, 5)
     n = wl.n_cells
-    cq = rng.choice(np.where(np.abs(wl.q0.reshape(-1) - 1.0) > 1e-2)[0], 32, replace=False)
     rows_of = np.arange(n) // wl.n_cols
     dvh = wl.dv.reshape(-1)
-    cdv = rng.choice(np.where((np.abs(dvh) > 1e-3) & (rows_of > 400) & (rows_of < 650))[0],
-                     16, replace=False)
-    epss = (1e-4, 1e-5, 1e-6)
-    ad, fd = [], []
-    for kind, idxs, g in (("q", cq, gq), ("dv", cdv, gdv)):
-        for idx in idxs:
+    pools = {
+        "q": rng.permutation(np.where(np.abs(wl.q0.reshape(-1) - 1.0) > 1e-2)[0]),
+        "dv": rng.permutation(np.where((np.abs(dvh) > 1e-3) & (rows_of > 400)
+                                       & (rows_of < 650))[0]),
+    }
+    eps = 1e-4
+    ad, fd, replaced = [], [], 0
+    for kind, want, g in (("q", 32, gq), ("dv", 16, gdv)):
+        floor = 1e-3 * float(g.abs().max())
+        got = 0
+        for tries, idx in enumerate(pools[kind]):
+            assert tries < 20 * want, f"too many {kind} coordinates next to kinks"
+            f1 = _fd(wl, rows, q0, dv, v0, area, tgt, steps, kind, idx, eps)
+            f2 = _fd(wl, rows, q0, dv, v0, area, tgt, steps, kind, idx, eps / 4)
+            if abs(f1 - f2) > 1e-6 * max(abs(f2), floor):
+                replaced += 1
+                continue
             ad.append(float(g[idx]))
-            fd.append([_fd(wl, rows, q0, dv, v0, area, tgt, steps, kind, idx, h) for h in epss])
+            fd.append(f1)
+            got += 1
+            if got == want:
+                break
     ad, fd = np.array(ad), np.array(fd)
-    rel = [np.linalg.norm(ad - fd[:, i]) / np.linalg.norm(fd[:, i]) for i in range(3)]
-    print("Q0+dv: FD norm-wise rel at eps 1e-4/1e-5/1e-6: " + " ".join(f"{r:.3e}" for r in rel))
-    assert rel[2] <= 1e-5
-    assert rel[2] < rel[0]
+    rel = np.linalg.norm(ad - fd) / np.linalg.norm(fd)
+    per = np.abs(ad - fd) / np.maximum(np.abs(fd), 1e-3 * np.max(np.abs(fd)))
+    print(f"Q0+dv: FD norm-wise rel {rel:.3e}, worst per-coordinate {per.max():.3e}, "
+          f"{replaced} coordinates replaced (kink within eps)")
+    assert len(ad) == 48
+    assert rel <= 1e-5
+    epss = (1e-4, 1e-5, 1e-6)
     errs = []
     for idx in rng.choice(np.arange(wl.n_rows)[200:800], 16, replace=False):
         a = float(gv0[idx])
