@@ -32,6 +32,20 @@ HIPCC_FLAGS = [
 ]
 
 
+# sources of the shared-mesh step kernel (the one the traffic counters cover)
+STEP_KERNEL_SOURCES = ["ram_step_shared.hip", "ram_device.h", "ram_internal.h"]
+
+
+def kernel_digest() -> str:
+    """Digest of the shared-mesh step kernel's sources and compile flags."""
+    import hashlib
+    h = hashlib.sha256(" ".join(HIPCC_FLAGS).encode())
+    for name in STEP_KERNEL_SOURCES:
+        with open(os.path.join(CSRC, name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def hipcc() -> str:
     path = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
     if not os.path.exists(path):
