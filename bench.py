@@ -133,6 +133,9 @@ def main():
     t_ts, q_ts = time_steps(q32, dv32, R.RAM_SCAN_F32_TWOSUM, args.steps, args.warmup)
     value = n_cells * args.steps / t_ts / 1e9
     t_fused = t_ts / args.steps
+    # --- FP32 state, direct sums (no prefix) ---------------------------------
+    t_dir, q_dir = time_steps(q32, dv32, R.RAM_SUM_DIRECT, args.steps // 4, args.warmup)
+    v_dir = n_cells * (args.steps // 4) / t_dir / 1e9
     # --- FP32 state, FP64 prefix sums ---------------------------------------
     k2 = max(1, args.steps // 4)
     t_f64s, _ = time_steps(q32, dv32, R.RAM_SCAN_F64, k2, args.warmup)
@@ -237,6 +240,7 @@ def main():
         "fwd_adjoint": {"value": round(v_adj, 3), "unit": "Gcell-updates/s",
                         "steps": ka, "checkpoint": args.checkpoint},
         "fp32_fp64scan": {"value": round(v_f64s, 3), "steps": k2},
+        "fp32_direct_sums": {"value": round(v_dir, 3), "steps": args.steps // 4},
         "fp64_plain": {"value": round(v64, 3), "steps": args.fp64_steps},
         "mixed_speedup_vs_fp64": round(value / v64, 3),
         "error": {"one_step_rel_l1_vs_oracle": err1,

@@ -55,12 +55,17 @@ typedef enum {
 
 typedef enum { RAM_F64 = 0, RAM_F32 = 1 } ram_dtype;
 
-/* Precision of the cumulative (prefix-sum) and its differences in the shift.
- * FP64 state requires RAM_SCAN_F64. */
+/* How the shift forms differences of the node cumulative C_j = sum_{m<j} M_m
+ * (Eq. mass_shift_algo: whole-cell sums and partial integrals).  The prefix
+ * modes build a window prefix sum and subtract; RAM_SUM_DIRECT sums the masses
+ * between the two nodes instead (at most p masses for a partial integral),
+ * so no prefix and no cancellation arise.  On per-row meshes RAM_SUM_DIRECT
+ * uses the FP64 prefix.  FP64 state requires RAM_SCAN_F64 or RAM_SUM_DIRECT. */
 typedef enum {
     RAM_SCAN_F64 = 0,         /* FP64 prefix sums                              */
     RAM_SCAN_F32_TWOSUM = 1,  /* compensated FP32 prefix (hi, lo) pairs        */
-    RAM_SCAN_F32 = 2          /* plain FP32 prefix (shows the cancellation)    */
+    RAM_SCAN_F32 = 2,         /* plain FP32 prefix (shows the cancellation)    */
+    RAM_SUM_DIRECT = 3        /* no prefix: direct sums in the state's type    */
 } ram_scan;
 
 typedef struct {

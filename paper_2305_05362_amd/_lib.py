@@ -30,8 +30,10 @@ RAM_F32 = 1
 RAM_SCAN_F64 = 0
 RAM_SCAN_F32_TWOSUM = 1
 RAM_SCAN_F32 = 2
+RAM_SUM_DIRECT = 3
 
-SCANS = {"f64": RAM_SCAN_F64, "twosum": RAM_SCAN_F32_TWOSUM, "f32": RAM_SCAN_F32}
+SCANS = {"f64": RAM_SCAN_F64, "twosum": RAM_SCAN_F32_TWOSUM, "f32": RAM_SCAN_F32,
+         "direct": RAM_SUM_DIRECT}
 
 
 class RamError(RuntimeError):

@@ -35,72 +35,26 @@ using namespace dev;
 
 constexpr int kWinA = 1536;             // LDS window capacity, cells
 
-template <typename T> struct RecA;
-template <> struct RecA<float> {
-    __device__ static const CellRec<float> *get(const MeshTab &t)
-    {
-        return (const CellRec<float> *)t.crf;
-    }
-};
-template <> struct RecA<double> {
-    __device__ static const CellRec<double> *get(const MeshTab &t)
-    {
-        return (const CellRec<double> *)t.crd;
-    }
-};
-
 __device__ inline int wrap1a(int j, int n)
 {
     return j < 0 ? j + n : (j >= n ? j - n : j);
 }
 
-__device__ inline int cell_of_a(const double *x, int n, const MeshTab &tb,
-                                double bsc, double xh)
-{
-    int b = (int)((xh - x[0]) * bsc);
-    b = min(max(b, 0), tb.nb - 1);
-    int c = tb.bucket[b];
-    const double2 nx = tb.bnext[b];
-    c += (xh >= nx.x) ? 1 : 0;
-    if (xh >= nx.y) {
-        c += 1;
-        while (c + 1 < n && x[c + 1] <= xh) ++c;
-    }
-    return c;
-}
-
-// Shifted node -> extended source index g, its cell c, the wrapped position xh
-// and the Lagrange weights of its stencil in theta = (xh - x_c)/dx_c.
+// Shifted node -> extended source index g, its cell c, the wrapped position
+// xh and the Lagrange weights of its stencil (the search of the step kernel).
 template <typename WT, int P>
 __device__ inline int64_t node_eval_adj(const double *x, int n, const MeshTab &tb,
-                                        double bsc, double invlen, double len,
-                                        double s, double xe, int kx, WT *w, int &cc,
-                                        double &xh_out)
+                                        const RowShift &rs, double len, double xe,
+                                        int kx, WT *w, int &cc, double &xh_out)
 {
-    const double xt = xe - s;
-    const double kf = floor((xt - x[0]) * invlen);
-    double xh = xt - kf * len;
-    int64_t k = (int64_t)kf;
-    if (xh >= x[n]) { xh -= len; k += 1; }
-    else if (xh < x[0]) { xh += len; k -= 1; }
-    const int c = cell_of_a(x, n, tb, bsc, xh);
-    const CellRec<WT> &r = RecA<WT>::get(tb)[c];
-    const WT th = (WT)((xh - r.xc) * r.dxinv);
-    WT t[P + 1];
-#pragma unroll
-    for (int a = 0; a <= P; ++a) t[a] = th - r.th[a];
-    WT pre[P + 1], suf[P + 1];
-    pre[0] = (WT)1;
-#pragma unroll
-    for (int a = 1; a <= P; ++a) pre[a] = pre[a - 1] * t[a - 1];
-    suf[P] = (WT)1;
-#pragma unroll
-    for (int a = P - 1; a >= 0; --a) suf[a] = suf[a + 1] * t[a + 1];
-#pragma unroll
-    for (int a = 0; a <= P; ++a) w[a] = r.rd[a] * (pre[a] * suf[a]);
+    const NodePos np = node_pos(xe, rs, x[0], x[n], tb.scal[0], tb.scal[2], tb.nb);
+    const double2 nx = tb.bnext[np.b];
+    int c = cell_from_bucket(tb.bucket[np.b], nx, np.xt);
+    if (np.xt >= nx.y) c = cell_walk(x, n, c, np.xt);
+    rec_weights<WT, P>(RecT<WT>::get(tb)[c], np.xt, w);
     cc = c;
-    xh_out = xh;
-    return (int64_t)c + (k + kx) * (int64_t)n;
+    xh_out = np.xt;
+    return (int64_t)c + (rs.kf0 + np.dk + kx) * (int64_t)n;
 }
 
 // x-derivatives of the stencil weights at xh in cell c, FP64 (the product
@@ -110,7 +64,7 @@ __device__ inline int64_t node_eval_adj(const double *x, int n, const MeshTab &t
 template <int P>
 __device__ inline void node_dweights(const MeshTab &tb, int c, double xh, double *dw)
 {
-    const CellRec<double> &r = RecA<double>::get(tb)[c];
+    const CellRec<double> &r = RecT<double>::get(tb)[c];
     const double th = (xh - r.xc) * r.dxinv;
     double t[P + 1], pre[P + 1], suf[P + 1], dpre[P + 1], dsuf[P + 1];
 #pragma unroll
@@ -210,7 +164,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_sh(StepAdjArgs a)
     const bool want_v0 = a.v0bar != nullptr && qf != nullptr;
     const double s = a.v0[row] * a.dt;
     const double len = x[n] - x[0];
-    const double bsc = tb.scal[0], invlen = tb.scal[1];
+    const RowShift rs = row_shift(s, len, tb.scal[1]);
     const int64_t wlo = a.plan_wlo[blockIdx.x];
     const int W = a.plan_w[blockIdx.x];
     const int t = threadIdx.x;
@@ -302,7 +256,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_sh(StepAdjArgs a)
             const int en = i0 + e;
             const int kx = en >= n ? 1 : 0;
             const double xe = x[en >= n ? en - n : en];
-            g[k] = node_eval_adj<CT, P>(x, n, tb, bsc, invlen, len, s, xe, kx, w[k], cc[k],
+            g[k] = node_eval_adj<CT, P>(x, n, tb, rs, len, xe, kx, w[k], cc[k],
                                         xh[k]);
             vb[k] = (e >= 1 ? smb[e - 1] : 0.0) - (e <= nd - 1 ? smb[e] : 0.0);
             const int64_t jc = g[k] - wlo;
@@ -437,8 +391,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_sh(StepAdjArgs a)
                 const int kx = en >= n ? 1 : 0;
                 double ww[P + 1], xh2;
                 int c2;
-                node_eval_adj<double, P>(x, n, tb, bsc, invlen, len, s,
-                                         x[en >= n ? en - n : en], kx, ww, c2, xh2);
+                node_eval_adj<double, P>(x, n, tb, rs, len, x[en >= n ? en - n : en], kx,
+                                         ww, c2, xh2);
                 // the share of the node's weights on cumulative nodes above
                 // the cell, with the node's own weight taken as one minus the
                 // others (the form the windowed scatter uses)

@@ -112,10 +112,11 @@ ram_status check_order(const ram_layout *L, int order)
 
 ram_status check_scan(ram_dtype dt, ram_scan scan)
 {
-    if (scan != RAM_SCAN_F64 && scan != RAM_SCAN_F32_TWOSUM && scan != RAM_SCAN_F32)
+    if (scan != RAM_SCAN_F64 && scan != RAM_SCAN_F32_TWOSUM && scan != RAM_SCAN_F32 &&
+        scan != RAM_SUM_DIRECT)
         return fail(RAM_E_UNSUPPORTED, "unknown scan precision %d", (int)scan);
-    if (dt == RAM_F64 && scan != RAM_SCAN_F64)
-        return fail(RAM_E_UNSUPPORTED, "FP64 state requires RAM_SCAN_F64");
+    if (dt == RAM_F64 && scan != RAM_SCAN_F64 && scan != RAM_SUM_DIRECT)
+        return fail(RAM_E_UNSUPPORTED, "FP64 state requires RAM_SCAN_F64 or RAM_SUM_DIRECT");
     return RAM_OK;
 }
 

@@ -352,14 +352,18 @@ __device__ double partial_direct(const double *x, const TQ *q, int n, double len
 // Per-type views of the shared-mesh tables.
 template <typename T> struct TabT;
 template <> struct TabT<double> {
+    using T2 = double2;
     __device__ static const double *dx(const MeshTab &t) { return t.dx; }
     __device__ static const double *dxinv(const MeshTab &t) { return t.dxinv; }
     __device__ static const double *hinv(const MeshTab &t) { return t.hinv; }
+    __device__ static const double2 *rr(const MeshTab &t) { return t.rrd; }
 };
 template <> struct TabT<float> {
+    using T2 = float2;
     __device__ static const float *dx(const MeshTab &t) { return t.dxf; }
     __device__ static const float *dxinv(const MeshTab &t) { return t.dxinvf; }
     __device__ static const float *hinv(const MeshTab &t) { return t.hinvf; }
+    __device__ static const float2 *rr(const MeshTab &t) { return t.rrf; }
 };
 
 // 2ab/(a+b) of the van Leer slope (a b > 0): FP32 with the hardware
@@ -396,6 +400,113 @@ __device__ __attribute__((noinline)) double direct_whole(const double *x,
     double wh = 0.0;
     for (int64_t m = ga; m < gb; ++m) wh += cell_mass(x, q, n, m);
     return wh;
+}
+
+// ---- shifted-node search on a shared mesh (step and adjoint kernels) ----
+
+template <typename T> struct RecT;
+template <> struct RecT<float> {
+    __device__ static const CellRec<float> *get(const MeshTab &t)
+    {
+        return (const CellRec<float> *)t.crf;
+    }
+};
+template <> struct RecT<double> {
+    __device__ static const CellRec<double> *get(const MeshTab &t)
+    {
+        return (const CellRec<double> *)t.crd;
+    }
+};
+
+// Per-row constants of the node search.  kf0 = floor(-s/L) whole periods
+// are taken out of every shifted node x - s, which then lies in
+// [x0 - kf0 L ... ) so that at most one more period (up or down, the latter
+// only through rounding) brings it into [x0, xN).  The products k L are
+// formed once, so a node's wrapped position is (x - s) - k L with the same
+// two roundings as the plain definition.
+struct RowShift {
+    double s;       // the shift v0 dt
+    double p0;      // kf0 L
+    double pp;      // (kf0 + 1) L
+    double pm;      // (kf0 - 1) L
+    int64_t kf0;
+};
+
+__device__ inline RowShift row_shift(double s, double len, double invlen)
+{
+    const double kf = floor(-s * invlen);
+    return {s, kf * len, (kf + 1.0) * len, (kf - 1.0) * len, (int64_t)kf};
+}
+
+// Node x (a coordinate of the row's own nodes) shifted by s: its position
+// wrapped into [x0, xN), the period it took beyond kf0 (0, 1, or -1 through
+// rounding) and its bucket.
+struct NodePos {
+    double xt;
+    int dk;
+    int b;
+};
+
+__device__ inline NodePos node_pos(double xe, const RowShift &rs, double x0, double xN,
+                                   double bsc, double bx0, int nb)
+{
+    const double xs = xe - rs.s;
+    double v = xs - rs.p0;
+    int d = 0;
+    if (v >= xN) { v = xs - rs.pp; d = 1; }
+    else if (v < x0) { v = xs - rs.pm; d = -1; }
+    int b = (int)(v * bsc - bx0);
+    b = min(max(b, 0), nb - 1);
+    return {v, d, b};
+}
+
+// Source cell from the bucket's lower-bound cell and the next two nodes; the
+// walk past them is only taken on meshes finer than the buckets.
+__device__ inline int cell_from_bucket(int cb, double2 nx, double xt)
+{
+    return cb + (xt >= nx.x ? 1 : 0) + (xt >= nx.y ? 1 : 0);
+}
+
+__device__ inline int cell_walk(const double *x, int n, int c, double xt)
+{
+    while (c + 1 < n && x[c + 1] <= xt) ++c;
+    return c;
+}
+
+// Lagrange weights of the stencil of cell record r at position xt.
+template <typename WT, int P>
+__device__ inline void rec_weights(const CellRec<WT> &r, double xt, WT *w)
+{
+    const WT th = (WT)((xt - r.xc) * r.dxinv);
+    WT t[P + 1];
+#pragma unroll
+    for (int a = 0; a <= P; ++a) t[a] = th - r.th[a];
+    WT pre[P + 1], suf[P + 1];
+    pre[0] = (WT)1;
+#pragma unroll
+    for (int a = 1; a <= P; ++a) pre[a] = pre[a - 1] * t[a - 1];
+    suf[P] = (WT)1;
+#pragma unroll
+    for (int a = P - 1; a >= 0; --a) suf[a] = suf[a + 1] * t[a + 1];
+#pragma unroll
+    for (int a = 0; a <= P; ++a) w[a] = r.rd[a] * (pre[a] * suf[a]);
+}
+
+// Extended source index g = c + k n of node e of a row (any integer e; the
+// node is wrapped into the row with its period count kx).  The plan uses it
+// for the two end nodes of every tile; the step kernel evaluates the same
+// arithmetic inline, in batches.
+__device__ inline int64_t node_index(const double *x, int n, const MeshTab &tb,
+                                     const RowShift &rs, double len, int e)
+{
+    int kx = 0;
+    if (e < 0) { e += n; kx = -1; }
+    while (e >= n) { e -= n; kx += 1; }
+    const double bsc = tb.scal[0], bx0 = tb.scal[2];
+    const NodePos np = node_pos(x[e], rs, x[0], x[n], bsc, bx0, tb.nb);
+    int c = cell_from_bucket(tb.bucket[np.b], tb.bnext[np.b], np.xt);
+    if (np.xt >= tb.bnext[np.b].y) c = cell_walk(x, n, c, np.xt);
+    return (int64_t)c + (rs.kf0 + np.dk + kx) * (int64_t)n;
 }
 
 } // namespace dev

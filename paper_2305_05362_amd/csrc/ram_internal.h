@@ -13,7 +13,10 @@ constexpr int kTile = 256;
 constexpr int kBlock = 256;
 constexpr int kWindowCap = 2048;
 
-enum ScanMode { kScanF64 = 0, kScanTwoSum = 1, kScanF32 = 2 };
+// How cumulative differences are formed: from a window prefix sum in FP64,
+// compensated FP32 or plain FP32, or (kSumDirect) summed directly from the
+// masses between the two nodes, with no prefix at all.
+enum ScanMode { kScanF64 = 0, kScanTwoSum = 1, kScanF32 = 2, kSumDirect = 3 };
 
 // Mesh-only tables for a mesh shared by every row (built once per call by
 // launch_mesh_prep): cell sizes and their reciprocals, reciprocal centre gaps
@@ -32,7 +35,9 @@ struct MeshTab {
     const int32_t *bucket = nullptr;  // largest j with x_j <= x0 + b L / nb
     const double2 *bnext = nullptr;   // per bucket: the next two nodes (or +inf)
     int32_t nb = 0;
-    const double *scal = nullptr;     // device scalars: nb / L, 1 / L
+    const double *scal = nullptr;     // device scalars: nb / L, 1 / L, x0 nb / L
+    const float2 *rrf = nullptr;      // per cell: (dx, 1/centre gap), FP32
+    const double2 *rrd = nullptr;     // the same in FP64
     const void *crf = nullptr;        // CellRec<float>[n]
     const void *crd = nullptr;        // CellRec<double>[n]
 };

@@ -439,6 +439,8 @@ struct MeshTabW {
     double *scal;
     CellRec<float> *crf;
     CellRec<double> *crd;
+    float2 *rrf;
+    double2 *rrd;
 };
 
 template <int P>
@@ -456,6 +458,8 @@ __global__ __launch_bounds__(256) void k_mesh_prep(const double *x, int n, MeshT
         T.dxf[j] = (float)dx;
         T.dxinvf[j] = (float)(1.0 / dx);
         T.hinvf[j] = (float)(1.0 / h);
+        T.rrf[j] = make_float2((float)dx, (float)(1.0 / h));
+        T.rrd[j] = make_double2(dx, 1.0 / h);
         double th[P + 1];
         const double xc = x[j];
         for (int a = 0; a <= P; ++a) th[a] = (node_x(x, n, len, j - LO + a) - xc) / dx;
@@ -499,6 +503,7 @@ __global__ __launch_bounds__(256) void k_mesh_prep(const double *x, int n, MeshT
     if (j == 0) {
         T.scal[0] = (double)T.nb / len;
         T.scal[1] = 1.0 / len;
+        T.scal[2] = x[0] * ((double)T.nb / len);
     }
 }
 
@@ -542,7 +547,8 @@ hipError_t step_scan(const StepArgs &a, int scan, hipStream_t st)
 {
     const dim3 g((unsigned)a.rows.n_tiles), b(kBlock);
     switch (scan) {
-    case kScanF64: hipLaunchKernelGGL((k_step<TQ, P, kScanF64>), g, b, 0, st, a); break;
+    case kScanF64:
+    case kSumDirect: hipLaunchKernelGGL((k_step<TQ, P, kScanF64>), g, b, 0, st, a); break;
     case kScanTwoSum: hipLaunchKernelGGL((k_step<TQ, P, kScanTwoSum>), g, b, 0, st, a); break;
     default: hipLaunchKernelGGL((k_step<TQ, P, kScanF32>), g, b, 0, st, a); break;
     }
@@ -568,7 +574,8 @@ size_t mesh_tab_bytes(int64_t n, int order)
     const int64_t nb = 4 * n;
     return 3 * al256(8 * n) + 3 * al256(4 * n) + al256(8 * n * 2 * (order + 1)) +
            al256(4 * n * 2 * (order + 1)) + al256(4 * nb) + al256(16 * nb) + al256(16) +
-           al256(sizeof(CellRec<float>) * n) + al256(sizeof(CellRec<double>) * n);
+           al256(sizeof(CellRec<float>) * n) + al256(sizeof(CellRec<double>) * n) +
+           al256(8 * n) + al256(16 * n);
 }
 
 hipError_t launch_mesh_prep(const double *x, int64_t n, int order, void *mem,
@@ -589,7 +596,9 @@ hipError_t launch_mesh_prep(const double *x, int64_t n, int order, void *mem,
     w.bnext = (double2 *)p; p += al256(16 * 4 * n);
     w.scal = (double *)p; p += al256(16);
     w.crf = (CellRec<float> *)p; p += al256(sizeof(CellRec<float>) * n);
-    w.crd = (CellRec<double> *)p;
+    w.crd = (CellRec<double> *)p; p += al256(sizeof(CellRec<double>) * n);
+    w.rrf = (float2 *)p; p += al256(8 * n);
+    w.rrd = (double2 *)p;
     tab.dx = w.dx; tab.dxinv = w.dxinv; tab.hinv = w.hinv; tab.stc = w.stc;
     tab.dxf = w.dxf; tab.dxinvf = w.dxinvf; tab.hinvf = w.hinvf; tab.stcf = w.stcf;
     tab.bucket = w.bucket;
@@ -598,6 +607,8 @@ hipError_t launch_mesh_prep(const double *x, int64_t n, int order, void *mem,
     tab.bnext = w.bnext;
     tab.crf = w.crf;
     tab.crd = w.crd;
+    tab.rrf = w.rrf;
+    tab.rrd = w.rrd;
     const unsigned grid = (unsigned)((w.nb + 255) / 256);
     switch (order) {
     case 1: hipLaunchKernelGGL(k_mesh_prep<1>, dim3(grid), dim3(256), 0, stream, x, (int)n, w); break;

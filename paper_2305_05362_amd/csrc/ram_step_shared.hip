@@ -9,10 +9,17 @@
 //     shift of a row is the same at every step of a call), so a tile reads
 //     its window bounds with one scalar load and issues the window, residual-
 //     velocity and mesh loads before any search;
+//   * the shift of a row is reduced by whole periods once per tile, so a
+//     shifted node is wrapped into the period with one subtraction and one
+//     compare instead of a floor;
 //   * the source cell of a shifted node takes one bucket record (lower-bound
 //     cell and the next two nodes) and the stencil one cell record (x_c, 1/dx_c,
-//     normalised node offsets, reciprocal Lagrange denominators): two
-//     dependent loads after the node itself;
+//     normalised node offsets, reciprocal Lagrange denominators);
+//   * the residual reads per-cell (dx, 1/centre gap) records staged in LDS;
+//   * with kSumDirect the cumulative differences are summed directly from the
+//     window masses (a partial integral needs at most p of them, a whole-cell
+//     sum the masses between two nodes), so no prefix sum is formed and no
+//     cancellation arises;
 //   * tiles away from the row seam skip all periodic index wrapping.
 #include "ram_device.h"
 
@@ -25,78 +32,27 @@ using namespace dev;
 
 constexpr int kWinSh = 1536;                    // LDS window capacity, cells
 constexpr int kWinRegs = kWinSh / kBlock;       // window cells per thread
+constexpr int kPad = 8;                         // residual arrays: halo slack
 
-template <typename M, typename A, typename CT>
+// The FP32 residual stages its (dx, 1/gap) records in LDS; FP64 reads them
+// from the (cache-resident) table, which keeps its LDS at four blocks a CU.
+template <typename CT> struct StageRR { static constexpr bool on = sizeof(CT) == 4; };
+
+template <typename M, typename A, typename CT, bool kDirect>
 struct ShLds {
-    static constexpr size_t win = sizeof(M) * kWinSh + sizeof(A) * (kWinSh + 1);
-    static constexpr size_t res = 2 * sizeof(CT) * kStepNodes;
-    static constexpr size_t uni = win > res ? win : res;
+    using CT2 = typename TabT<CT>::T2;
+    static constexpr size_t win =
+        sizeof(M) * kWinSh + (kDirect ? 0 : sizeof(A) * (kWinSh + 1));
+    static constexpr size_t res =
+        (2 * sizeof(CT) + (StageRR<CT>::on ? sizeof(CT2) : 0)) * (kStepNodes + kPad);
+    static constexpr size_t nodes = sizeof(int64_t) * kStepNodes;
+    static constexpr size_t u0 = win > res ? win : res;
+    static constexpr size_t uni = u0 > nodes ? u0 : nodes;
 };
 
-template <typename T> struct RecT;
-template <> struct RecT<float> {
-    __device__ static const CellRec<float> *get(const MeshTab &t)
-    {
-        return (const CellRec<float> *)t.crf;
-    }
-};
-template <> struct RecT<double> {
-    __device__ static const CellRec<double> *get(const MeshTab &t)
-    {
-        return (const CellRec<double> *)t.crd;
-    }
-};
-
-// Source cell of xh: the bucket's lower-bound cell plus the nodes passed
-// (two are in the record; more only on meshes finer than the buckets).
-__device__ inline int cell_of(const double *x, int n, const MeshTab &tb,
-                              double bsc, double xh)
-{
-    int b = (int)((xh - x[0]) * bsc);
-    b = min(max(b, 0), tb.nb - 1);
-    int c = tb.bucket[b];
-    const double2 nx = tb.bnext[b];
-    c += (xh >= nx.x) ? 1 : 0;
-    if (xh >= nx.y) {
-        c += 1;
-        while (c + 1 < n && x[c + 1] <= xh) ++c;
-    }
-    return c;
-}
-
-// Shifted node e (any integer; e is wrapped into the row with its period
-// count) -> extended source index g and the Lagrange weights of its stencil.
-template <typename WT, int P>
-__device__ inline int64_t node_eval(const double *x, int n, const MeshTab &tb,
-                                    double bsc, double invlen, double len,
-                                    double s, double xe, int kx, WT *w)
-{
-    const double xt = xe - s;
-    const double kf = floor((xt - x[0]) * invlen);
-    double xh = xt - kf * len;
-    int64_t k = (int64_t)kf;
-    if (xh >= x[n]) { xh -= len; k += 1; }
-    else if (xh < x[0]) { xh += len; k -= 1; }
-    const int c = cell_of(x, n, tb, bsc, xh);
-    const CellRec<WT> &r = RecT<WT>::get(tb)[c];
-    const WT th = (WT)((xh - r.xc) * r.dxinv);
-    WT t[P + 1];
-#pragma unroll
-    for (int a = 0; a <= P; ++a) t[a] = th - r.th[a];
-    WT pre[P + 1], suf[P + 1];
-    pre[0] = (WT)1;
-#pragma unroll
-    for (int a = 1; a <= P; ++a) pre[a] = pre[a - 1] * t[a - 1];
-    suf[P] = (WT)1;
-#pragma unroll
-    for (int a = P - 1; a >= 0; --a) suf[a] = suf[a + 1] * t[a + 1];
-#pragma unroll
-    for (int a = 0; a <= P; ++a) w[a] = r.rd[a] * (pre[a] * suf[a]);
-    return (int64_t)c + (k + kx) * (int64_t)n;
-}
-
-// Window plan: extended source index of each tile's first node minus lo, and
-// the window length (or -1 when it exceeds the LDS capacity).
+// Window plan: extended source index of each tile's first node minus lo,
+// the window start inside the row (that index mod n), and the window length
+// (or -1 when it exceeds the LDS capacity).
 template <int P>
 __global__ __launch_bounds__(256) void k_plan(StepArgs a, int64_t *wlo_out,
                                               int32_t *w_out)
@@ -113,19 +69,11 @@ __global__ __launch_bounds__(256) void k_plan(StepArgs a, int64_t *wlo_out,
     const int nd = min(R.tile, n - i0);
     const double *x = R.edges;
     const double len = x[n] - x[0];
-    const double s = a.v0[row] * a.dt;
-    const double bsc = R.tab.scal[0], invlen = R.tab.scal[1];
-    int64_t g[2];
-    for (int side = 0; side < 2; ++side) {
-        int e = side == 0 ? i0 - H : i0 + nd + H;
-        int kx = 0;
-        if (e < 0) { e += n; kx = -1; }
-        while (e >= n) { e -= n; kx += 1; }
-        float w[P + 1];
-        g[side] = node_eval<float, P>(x, n, R.tab, bsc, invlen, len, s, x[e], kx, w);
-    }
-    const int64_t wide = g[1] - g[0] + P;
-    wlo_out[tile] = g[0] - LO;
+    const RowShift rs = row_shift(a.v0[row] * a.dt, len, R.tab.scal[1]);
+    const int64_t g0 = node_index(x, n, R.tab, rs, len, i0 - H);
+    const int64_t g1 = node_index(x, n, R.tab, rs, len, i0 + nd + H);
+    const int64_t wide = g1 - g0 + P;
+    wlo_out[tile] = g0 - LO;
     w_out[tile] = (wide >= P && wide <= kWinSh) ? (int32_t)wide : -1;
 }
 
@@ -138,11 +86,13 @@ __device__ inline int wrap1(int j, int n)
 template <typename TQ, int P, int S, int H>
 __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
 {
-    using AC = Acc<S>;
-    using M = typename AC::M;
+    constexpr bool kDirect = S == kSumDirect;
+    using AC = Acc<kDirect ? kScanF64 : S>;
+    using M = typename std::conditional<kDirect, TQ, typename AC::M>::type;
     using A = typename AC::A;
     using CT = TQ;                       // arithmetic after the prefix sums
-    using L = ShLds<M, A, CT>;
+    using CT2 = typename TabT<CT>::T2;
+    using L = ShLds<M, A, CT, kDirect>;
     constexpr int LO = (P - 1) / 2;
     constexpr int NI = kItems;
     constexpr int WCAP = kWinSh;
@@ -156,7 +106,8 @@ __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
     A *sp = (A *)(su + sizeof(M) * WCAP);            // exclusive prefix
     int64_t *sg = (int64_t *)su;                     // direct path: node indices
     CT *sq = (CT *)su;                               // shifted state
-    CT *sf = sq + kStepNodes;                        // face fluxes
+    CT *sf = sq + (kStepNodes + kPad);               // face fluxes
+    CT2 *srr = (CT2 *)(sf + (kStepNodes + kPad));    // (dx, 1/gap) per cell
 
     const Rows &R = a.rows;
     const MeshTab &tb = R.tab;
@@ -173,23 +124,28 @@ __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
     const TQ *q = (const TQ *)a.q_in + qoff;
     TQ *qo = (TQ *)a.q_out + qoff;
     TQ *qmid = a.q_mid ? (TQ *)a.q_mid + qoff : nullptr;
+    const double x0 = x[0], xN = x[n];
+    const double len = xN - x0;
+    const double bsc = tb.scal[0], invlen = tb.scal[1], bx0 = tb.scal[2];
     const double s = a.v0[row] * a.dt;
-    const double len = x[n] - x[0];
-    const double bsc = tb.scal[0], invlen = tb.scal[1];
     const int64_t wlo = a.plan_wlo[blockIdx.x];
     const int W = a.plan_w[blockIdx.x];
     const int t = threadIdx.x;
+    const RowShift rs = row_shift(s, len, invlen);
+    // window index of a node = c + (dk + kx) n + jbase
+    const int jbase = (int)(rs.kf0 * (int64_t)n - wlo);
 
     // ---- loads that do not depend on the search, issued first ------------
     double xe[NI];
+    int kxn[NI];
 #pragma unroll
     for (int k = 0; k < NI; ++k) {
         const int ei = t + k * kBlock;
         const int e = i0 - H + ei;
-        xe[k] = ei < NE ? x[inner ? e : wrap1(e, n)] : 0.0;
+        kxn[k] = inner ? 0 : (e < 0 ? -n : (e >= n ? n : 0));
+        xe[k] = ei < NE ? x[inner ? e : wrap1(e, n)] : x0;
     }
-    // window start inside the row: wlo mod n, without a 64-bit division in
-    // the common case of a window at most one period away
+    // window start inside the row: wlo mod n
     int base = 0;
     if (W > 0) {
         const int64_t kk = wlo >= 0 ? wlo / n : -((-wlo + n - 1) / n);
@@ -208,71 +164,91 @@ __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
             wd[r] = TabT<M>::dx(tb)[mm];
         }
     }
-
-    // ---- (A) shifted nodes: source index and stencil weights -------------
-    int64_t g[NI];
-    CT w[NI][P + 1];
-    bool ok = true;
-#pragma unroll
-    for (int k = 0; k < NI; ++k) {
-        const int ei = t + k * kBlock;
-        g[k] = 0;
-        if (ei < NE) {
-            const int e = i0 - H + ei;
-            const int kx = e < 0 ? -1 : (e >= n ? 1 : 0);
-            g[k] = node_eval<CT, P>(x, n, tb, bsc, invlen, len, s, xe[k], kx, w[k]);
-            const int64_t jc = g[k] - wlo;
-            ok = ok && jc >= LO && jc + P - LO <= W;
-        }
-    }
-    if (t == 0) s_flag = W > 0 ? 1 : 0;
-    __syncthreads();
-    if (!ok) s_flag = 0;
-    // ---- (B) window masses and the block scan ------------------------------
 #pragma unroll
     for (int r = 0; r < kWinRegs; ++r) {
         const int j = t + r * kBlock;
         if (j < W) sm[j] = wq[r] * wd[r];
     }
+    // ---- (A) shifted nodes: source index and stencil weights -------------
+    int jc[NI];
+    CT w[NI][P + 1];
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        // one node at a time: the guard keeps the four lookups from being
+        // interleaved, which would cost more registers than the waves it
+        // leaves room for are worth
+        jc[k] = 0;
+        if (t + k * kBlock < NE) {
+            const NodePos np = node_pos(xe[k], rs, x0, xN, bsc, bx0, tb.nb);
+            const double2 nx = tb.bnext[np.b];
+            int c = cell_from_bucket(tb.bucket[np.b], nx, np.xt);
+            if (np.xt >= nx.y) c = cell_walk(x, n, c, np.xt);
+            rec_weights<CT, P>(RecT<CT>::get(tb)[c], np.xt, w[k]);
+            jc[k] = c + np.dk * n + kxn[k] + jbase;
+            ok = ok && jc[k] >= LO && jc[k] + P - LO <= W;
+        }
+    }
+    if (t == 0) s_flag = W > 0 ? 1 : 0;
+    __syncthreads();
+    if (!ok) s_flag = 0;
+    // ---- (B) the block scan of the prefix modes ------------------------------
     __syncthreads();
     const bool windowed = s_flag != 0;
     if (windowed) {
-        const int per = (W + kBlock - 1) / kBlock;
-        const int j0 = min(W, t * per);
-        const int j1 = min(W, j0 + per);
-        M mine[kWinRegs];
-        A run = AC::zero();
+        if constexpr (!kDirect) {
+            const int per = (W + kBlock - 1) / kBlock;
+            const int j0 = min(W, t * per);
+            const int j1 = min(W, j0 + per);
+            M mine[kWinRegs];
+            A run = AC::zero();
 #pragma unroll
-        for (int r = 0; r < kWinRegs; ++r) {
-            if (j0 + r < j1) {
-                mine[r] = sm[j0 + r];
-                run = AC::add(run, mine[r]);
+            for (int r = 0; r < kWinRegs; ++r) {
+                if (j0 + r < j1) {
+                    mine[r] = sm[j0 + r];
+                    run = AC::add(run, mine[r]);
+                }
             }
-        }
-        A total;
-        A acc = block_exscan_dpp<AC>(run, swt, total);
+            A total;
+            A acc = block_exscan_dpp<AC>(run, swt, total);
 #pragma unroll
-        for (int r = 0; r < kWinRegs; ++r) {
-            if (j0 + r < j1) {
-                sp[j0 + r] = acc;
-                acc = AC::add(acc, mine[r]);
+            for (int r = 0; r < kWinRegs; ++r) {
+                if (j0 + r < j1) {
+                    sp[j0 + r] = acc;
+                    acc = AC::add(acc, mine[r]);
+                }
             }
+            if (t == 0) sp[W] = total;
+            __syncthreads();
         }
-        if (t == 0) sp[W] = total;
-        __syncthreads();
         // ---- (C) partial integrals of the interpolated cumulative ----------
 #pragma unroll
         for (int k = 0; k < NI; ++k) {
             const int ei = t + k * kBlock;
             if (ei < NE) {
-                const int jc = (int)(g[k] - wlo);
-                const A pc = sp[jc];
+                const int j = jc[k];
                 CT ell = (CT)0;
+                if constexpr (kDirect) {
+                    // C(j-lo+b) - C(j): the masses between, summed outward
+                    CT up = (CT)0, dn = (CT)0;
 #pragma unroll
-                for (int b = 0; b <= P; ++b)
-                    if (b != LO) ell += w[k][b] * (CT)AC::diff(sp[jc - LO + b], pc);
+                    for (int b = LO + 1; b <= P; ++b) {
+                        up += (CT)sm[j + b - LO - 1];
+                        ell += w[k][b] * up;
+                    }
+#pragma unroll
+                    for (int b = LO - 1; b >= 0; --b) {
+                        dn += (CT)sm[j - LO + b];
+                        ell -= w[k][b] * dn;
+                    }
+                } else {
+                    const A pc = sp[j];
+#pragma unroll
+                    for (int b = 0; b <= P; ++b)
+                        if (b != LO) ell += w[k][b] * (CT)AC::diff(sp[j - LO + b], pc);
+                }
                 sell[ei] = ell;
-                sjc[ei] = jc;
+                sjc[ei] = j;
             }
         }
     } else {
@@ -281,39 +257,36 @@ __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
         for (int k = 0; k < NI; ++k) {
             const int ei = t + k * kBlock;
             if (ei < NE) {
-                sg[ei] = g[k];
+                const int64_t g = (int64_t)jc[k] + wlo;
+                sg[ei] = g;
                 sell[ei] = (CT)direct_partial<TQ, P>(x, q, n, len, s, invlen,
-                                                     i0 - H + ei, g[k]);
+                                                     i0 - H + ei, g);
             }
         }
     }
-
-    // residual inputs, fetched while the partial integrals settle
-    const CT dt = (CT)a.dt;
+    // residual inputs, fetched while the partial integrals settle: per-cell mesh records of cells i0-2 .. i0+nd+1, face
+    // velocities of faces i0 .. i0+nd, 1/dx of the tile's cells
+    constexpr bool kStage = StageRR<CT>::on;
+    CT2 rrv[NI];
     TQ dvr[NI];
-    CT dxl[NI], dxr[NI], h0[NI], h1[NI], h2[NI], dxi[NI];
+    CT dxi[NI];
     if (H) {
         const TQ *dv = (const TQ *)a.dv + qoff;
 #pragma unroll
         for (int k = 0; k < NI; ++k) {
             const int u = t + k * kBlock;
-            if (u < nd + 1) {                        // face f = i0+u
+            if (kStage && u < nd + 4) {
+                const int c = i0 - 2 + u;
+                rrv[k] = TabT<CT>::rr(tb)[inner ? c : wrap1(c, n)];
+            }
+            if (u < nd + 1) {
                 const int f = i0 + u;
-                const int fm = inner ? f - 1 : wrap1(f - 1, n);
-                const int fp = inner ? f : wrap1(f, n);
-                const int fmm = inner ? f - 2 : wrap1(f - 2, n);
-                const int fpp = inner ? f + 1 : wrap1(f + 1, n);
-                dvr[k] = dv[fp];
-                dxl[k] = TabT<CT>::dx(tb)[fm];
-                dxr[k] = TabT<CT>::dx(tb)[fp];
-                h0[k] = TabT<CT>::hinv(tb)[fmm];     // gap (f-2, f-1)
-                h1[k] = TabT<CT>::hinv(tb)[fm];      // gap (f-1, f)
-                h2[k] = TabT<CT>::hinv(tb)[fp];      // gap (f, f+1)
-                (void)fpp;
+                dvr[k] = dv[inner ? f : wrap1(f, n)];
             }
             if (u < nd) dxi[k] = TabT<CT>::dxinv(tb)[i0 + u];
         }
     }
+
     __syncthreads();
 
     // ---- (D) destination masses, Step 3 ------------------------------------
@@ -328,7 +301,13 @@ __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
             CT mp;
             if (windowed) {
                 const int ja = sjc[ci], jb = sjc[ci + 1];
-                const CT whole = (jb - ja == 1) ? (CT)sm[ja] : (CT)AC::diff(sp[jb], sp[ja]);
+                CT whole;
+                if constexpr (kDirect) {
+                    whole = (CT)0;
+                    for (int m = ja; m < jb; ++m) whole += (CT)sm[m];
+                } else {
+                    whole = (jb - ja == 1) ? (CT)sm[ja] : (CT)AC::diff(sp[jb], sp[ja]);
+                }
                 mp = whole + (sell[ci + 1] - sell[ci]);
             } else {
                 mp = (CT)(direct_whole<TQ>(x, q, n, sg[ci], sg[ci + 1]) +
@@ -342,26 +321,38 @@ __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
     if (H == 0) return;
     __syncthreads();   // the window bytes become the residual's arrays
 #pragma unroll
-    for (int k = 0; k < NI; ++k)
-        if (t + k * kBlock < NC) sq[t + k * kBlock] = qs[k];
+    for (int k = 0; k < NI; ++k) {
+        const int u = t + k * kBlock;
+        if (u < NC) sq[u] = qs[k];
+        if (kStage && u < nd + 4) srr[u] = rrv[k];
+    }
     __syncthreads();
 
     // ---- (E) fluxes on faces i0 .. i0+nd, with the upwind cell's slope -----
-    // face i0+u lies between cells i0+u-1 (state index u+1) and i0+u (u+2)
+    // face i0+u lies between cells i0+u-1 (index u+1) and i0+u (index u+2);
+    // index j of sq / srr is cell i0-2+j
+    const CT dt = (CT)a.dt;
 #pragma unroll
     for (int k = 0; k < NI; ++k) {
         const int u = t + k * kBlock;
         if (u < nd + 1) {
             const CT v = (CT)dvr[k];
             const bool up = v >= (CT)0;
-            const int c = up ? u + 1 : u + 2;             // upwind cell, state index
+            const int c = up ? u + 1 : u + 2;             // upwind cell
             const CT qm = sq[c - 1], q0 = sq[c], qp = sq[c + 1];
-            const CT hpl = up ? h1[k] : h2[k];
-            const CT hmi = up ? h0[k] : h1[k];
-            const CT dp = (qp - q0) * hpl;
-            const CT dm = (q0 - qm) * hmi;
+            CT2 rc, rm;
+            if constexpr (kStage) {
+                rc = srr[c];
+                rm = srr[c - 1];
+            } else {
+                const int cg = i0 - 2 + c;
+                rc = TabT<CT>::rr(tb)[inner ? cg : wrap1(cg, n)];
+                rm = TabT<CT>::rr(tb)[inner ? cg - 1 : wrap1(cg - 1, n)];
+            }
+            const CT dp = (qp - q0) * rc.y;               // gap (c, c+1)
+            const CT dm = (q0 - qm) * rm.y;               // gap (c-1, c)
             const CT sig = (dp * dm <= (CT)0) ? (CT)0 : harmonic2(dp, dm);
-            const CT half = up ? (CT)0.5 * (dxl[k] - v * dt) : (CT)-0.5 * (dxr[k] + v * dt);
+            const CT half = up ? (CT)0.5 * (rc.x - v * dt) : (CT)-0.5 * (rc.x + v * dt);
             sf[u] = v * (q0 + sig * half);
         }
     }
@@ -381,7 +372,8 @@ hipError_t step_sh_h(const StepArgs &a, int scan, hipStream_t st)
     switch (scan) {
     case kScanF64: hipLaunchKernelGGL((k_step_sh<TQ, P, kScanF64, H>), g, b, 0, st, a); break;
     case kScanTwoSum: hipLaunchKernelGGL((k_step_sh<TQ, P, kScanTwoSum, H>), g, b, 0, st, a); break;
-    default: hipLaunchKernelGGL((k_step_sh<TQ, P, kScanF32, H>), g, b, 0, st, a); break;
+    case kScanF32: hipLaunchKernelGGL((k_step_sh<TQ, P, kScanF32, H>), g, b, 0, st, a); break;
+    default: hipLaunchKernelGGL((k_step_sh<TQ, P, kSumDirect, H>), g, b, 0, st, a); break;
     }
     return hipGetLastError();
 }
@@ -421,7 +413,8 @@ hipError_t launch_step_shared(const StepArgs &a, bool f64, int scan, int order,
                               hipStream_t stream)
 {
     if (a.rows.n_tiles <= 0) return hipSuccess;
-    if (f64) return step_sh_order<double>(a, kScanF64, order, stream);
+    if (f64) return step_sh_order<double>(a, scan == kSumDirect ? kSumDirect : kScanF64,
+                                          order, stream);
     return step_sh_order<float>(a, scan, order, stream);
 }
 

@@ -1,8 +1,8 @@
 """Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
 
 Bars: FP64 <= 1e-12 relative L1; FP32 state with compensated or FP64 prefix
-sums <= 1e-6 relative L1 for one step from the same FP32 input (the oracle
-reads it widened to FP64); integer work (the exact-permutation case) bitwise.
+sums, or direct sums, <= 1e-6 relative L1 for one step from the same FP32
+input (the oracle reads it widened to FP64); integer work (the exact-permutation case) bitwise.
 Full-size workloads are checked on sampled rows, which the oracle can compute
 on their own because rows are independent.
 """
@@ -117,12 +117,44 @@ def test_shift_fp32_scans():
     ref = oracle_shift(wl, q32.astype(np.float64), 5)
     errs = {}
     for name, scan in (("f64", R.RAM_SCAN_F64), ("twosum", R.RAM_SCAN_F32_TWOSUM),
-                       ("f32", R.RAM_SCAN_F32)):
+                       ("f32", R.RAM_SCAN_F32), ("direct", R.RAM_SUM_DIRECT)):
         got = gpu_shift(wl, q32, 5, torch.float32, scan)
         errs[name] = rel_l1(got, ref)
     print("one-step rel-L1 by scan precision:", errs)
-    assert errs["f64"] <= 1e-6 and errs["twosum"] <= 1e-6
+    assert errs["f64"] <= 1e-6 and errs["twosum"] <= 1e-6 and errs["direct"] <= 1e-6
     assert np.isfinite(errs["f32"])
+
+
+@pytest.mark.parametrize("order", [1, 3, 5])
+@pytest.mark.parametrize("kind", ["polar_one_tile", "polar_tiles", "ragged", "overflow"])
+def test_direct_sums_fp64(kind, order):
+    # the direct-sum evaluation (no prefix) against the oracle: shift alone
+    # and fused steps, FP64, on one- and several-tile rows, per-row meshes
+    # (which take the FP64 prefix) and a window wider than the LDS buffer
+    if kind == "overflow":
+        coarse = np.linspace(0.0, 0.5, 257)
+        fine = np.linspace(0.5, 1.0, 256 * 20 + 1)[1:]
+        e = np.concatenate([coarse, fine])
+        n = len(e) - 1
+        rng = np.random.default_rng(order)
+        q = 1.0 + 0.2 * rng.standard_normal(n)
+        dxm = np.minimum(np.diff(e), np.roll(np.diff(e), 1))
+        wl = W.Workload("ovf", 1, n, np.array([0, n]), e, True, q[None, :],
+                        (0.4 * dxm * rng.uniform(-1, 1, n))[None, :], np.array([-0.37]),
+                        1.0, order, 1)
+    elif kind == "ragged":
+        wl = W.small_ragged(12, 6, 2600, seed=31, order=order)
+    else:
+        wl = W.small_polar(6, 800, order=order) if kind == "polar_one_tile" else \
+            W.small_polar(3, 3500, order=order)
+    got = gpu_shift(wl, wl.q0, order, scan=R.RAM_SUM_DIRECT)
+    assert rel_l1(got, oracle_shift(wl, wl.q0, order)) <= 1e-12
+    rows = R.Rows.from_workload(wl, DEV)
+    q = dev(wl.q0.reshape(-1))
+    R.ram_step(rows, q, dev(wl.v0), dev(wl.dv.reshape(-1)), wl.dt, order, 3, R.RAM_SUM_DIRECT)
+    torch.cuda.synchronize()
+    ref = oracle.step(oracle.Rows.from_workload(wl), wl.q0, wl.v0, wl.dv, wl.dt, order, 3)
+    assert rel_l1(q.cpu().numpy(), ref) <= 1e-12
 
 
 # --------------------------------------------------------------------------
@@ -240,13 +272,15 @@ def test_cfg5_full_size_sampled_rows():
     q32 = wl.q0.astype(np.float32)
     dv32 = wl.dv.astype(np.float32)
     q = dev(q32.reshape(-1), torch.float32)
-    R.ram_step(rows, q, dev(wl.v0), dev(dv32.reshape(-1), torch.float32), wl.dt, 5, 1,
-               R.RAM_SCAN_F32_TWOSUM)
-    torch.cuda.synchronize()
-    got = q.cpu().numpy().astype(np.float64).reshape(wl.n_rows, -1)[pick].reshape(-1)
     ref = oracle.step(orows, q32.reshape(wl.n_rows, -1)[pick].astype(np.float64), sw.v0,
                       dv32.reshape(wl.n_rows, -1)[pick].astype(np.float64), sw.dt, 5, 1)
-    assert rel_l1(got, ref) <= 1e-6
+    for scan in (R.RAM_SCAN_F32_TWOSUM, R.RAM_SUM_DIRECT):
+        q = dev(q32.reshape(-1), torch.float32)
+        R.ram_step(rows, q, dev(wl.v0), dev(dv32.reshape(-1), torch.float32), wl.dt, 5, 1,
+                   scan)
+        torch.cuda.synchronize()
+        got = q.cpu().numpy().astype(np.float64).reshape(wl.n_rows, -1)[pick].reshape(-1)
+        assert rel_l1(got, ref) <= 1e-6, scan
 
 
 def test_cfg3_full_size_sampled_rows():
