@@ -57,27 +57,28 @@ __device__ inline int64_t node_eval_adj(const double *x, int n, const MeshTab &t
     return (int64_t)c + (rs.kf0 + np.dk + kx) * (int64_t)n;
 }
 
-// x-derivatives of the stencil weights at xh in cell c, FP64 (the product
-// rule carried through the prefix/suffix products).  FP64 whatever the state
-// type: the v0 gradient sums differences of the reconstruction between
-// neighbouring nodes, which rounding in the weights would swamp.
-template <int P>
+// x-derivatives of the stencil weights at xh in cell c (the product rule
+// carried through the prefix/suffix products), from the cell record of the
+// state's type: FP64 for an FP64 state; for an FP32 state the FP32 record
+// and arithmetic, so v0bar, which sums differences of the reconstruction
+// between neighbouring nodes, carries about 1e-4 relative rounding there.
+template <typename WT, int P>
 __device__ inline void node_dweights(const MeshTab &tb, int c, double xh, double *dw)
 {
-    const CellRec<double> &r = RecT<double>::get(tb)[c];
-    const double th = (xh - r.xc) * r.dxinv;
-    double t[P + 1], pre[P + 1], suf[P + 1], dpre[P + 1], dsuf[P + 1];
+    const CellRec<WT> &r = RecT<WT>::get(tb)[c];
+    const WT th = (WT)((xh - r.xc) * r.dxinv);
+    WT t[P + 1], pre[P + 1], suf[P + 1], dpre[P + 1], dsuf[P + 1];
 #pragma unroll
     for (int a = 0; a <= P; ++a) t[a] = th - r.th[a];
-    pre[0] = 1.0;
-    dpre[0] = 0.0;
+    pre[0] = (WT)1;
+    dpre[0] = (WT)0;
 #pragma unroll
     for (int a = 1; a <= P; ++a) {
         pre[a] = pre[a - 1] * t[a - 1];
         dpre[a] = dpre[a - 1] * t[a - 1] + pre[a - 1];
     }
-    suf[P] = 1.0;
-    dsuf[P] = 0.0;
+    suf[P] = (WT)1;
+    dsuf[P] = (WT)0;
 #pragma unroll
     for (int a = P - 1; a >= 0; --a) {
         suf[a] = suf[a + 1] * t[a + 1];
@@ -85,7 +86,7 @@ __device__ inline void node_dweights(const MeshTab &tb, int c, double xh, double
     }
 #pragma unroll
     for (int a = 0; a <= P; ++a)
-        dw[a] = r.rd[a] * (dpre[a] * suf[a] + pre[a] * dsuf[a]) * r.dxinv;
+        dw[a] = (double)(r.rd[a] * (dpre[a] * suf[a] + pre[a] * dsuf[a])) * r.dxinv;
 }
 
 // The reconstruction q~ at a shifted node from global memory (direct path).
@@ -111,7 +112,9 @@ __device__ __attribute__((noinline)) double direct_qtilde(
 
 template <typename CT>
 struct AdjLds {
-    static constexpr size_t res = 6 * sizeof(CT) * (kStepNodes + 8) + (kStepNodes + 8);
+    using CT2 = typename TabT<CT>::T2;
+    static constexpr int NP = kStepNodes + 8;
+    static constexpr size_t res = (4 * sizeof(CT) + sizeof(CT2)) * NP;
     static constexpr size_t win = 2 * sizeof(double) * (kWinA + 1);
     static constexpr size_t nodes = 2 * sizeof(int64_t) * kStepNodes;
     static constexpr size_t u0 = res > win ? res : win;
@@ -127,20 +130,20 @@ __global__ __launch_bounds__(kBlock) void k_adj_sh(StepAdjArgs a)
     constexpr int LO = (P - 1) / 2;
     constexpr int NI = kItems;
 
-    __shared__ double smb[kStepNodes];           // Mbar' of the tile's cells
-    __shared__ double sqt[kStepNodes];           // q~ at the tile's nodes
+    using CT2 = typename TabT<CT>::T2;
+    constexpr int NP = L::NP;
+    __shared__ CT smb[kStepNodes];               // Mbar' of the tile's cells
+    __shared__ double sedge[kItems][kBlock / 64]; // q~ of each wave's first lane
     __shared__ double swt[kBlock / 64];
     __shared__ double sred[kBlock / 64];
     __shared__ __attribute__((aligned(16))) unsigned char su[L::uni];
     __shared__ int s_flag;
-    // residual-adjoint arrays (index 0 <-> cell/face i0-2 resp. i0-1)
-    CT *sqh = (CT *)su;                          // Q^{n+1/2}, cells i0-2..
-    CT *sqb = sqh + (kStepNodes + 8);            // Qbar^{n+1}, same cells
-    CT *sqs = sqb + (kStepNodes + 8);            // face-state adjoint, faces i0-1..
-    CT *scs = sqs + (kStepNodes + 8);            // slope adjoint sent upwind
-    CT *sda = scs + (kStepNodes + 8);            // dsigma/da * hinv, cells i0-1..
-    CT *sdb = sda + (kStepNodes + 8);            // dsigma/db * hinv
-    unsigned char *sup = (unsigned char *)(sdb + (kStepNodes + 8));
+    // residual-adjoint staging, index j <-> cell (and face) i0-2+j
+    CT *sqh = (CT *)su;                          // Q^{n+1/2}
+    CT *sqb = sqh + NP;                          // Qbar^{n+1}
+    CT *sdi = sqb + NP;                          // 1/dx
+    CT *sdv = sdi + NP;                          // dv of face i0-2+j
+    CT2 *srr = (CT2 *)(sdv + NP);                // (dx, 1/centre gap)
     // shift-adjoint arrays
     double *scb = (double *)su;                  // Cbar on window nodes
     double *spm = scb + (kWinA + 1);             // masses of the Q^n window
@@ -172,72 +175,95 @@ __global__ __launch_bounds__(kBlock) void k_adj_sh(StepAdjArgs a)
     const CT dt = (CT)a.dt;
 
     // ---- (1) residual adjoint: Mbar' of the tile's cells -------------------
+    // Staged once: Q^{n+1/2}, Qbar^{n+1}, mesh records and dv of cells/faces
+    // i0-2 .. i0+nd+1; then every thread takes four consecutive cells and
+    // forms, from its window of cells a-2..a+5 and faces a-1..a+5 in
+    // registers, the face fluxes' adjoints, the limiter derivatives and the
+    // cells' Qbar^{n+1/2} (and dvbar of its four faces).
     if (RES) {
         const TQ *qh = (const TQ *)a.q_half + qoff;
         const TQ *dv = (const TQ *)a.dv + qoff;
         TQ *dvb = a.dvbar ? (TQ *)a.dvbar + qoff : nullptr;
-        for (int u = t; u < nd + 4; u += kBlock) {
-            const int c = wr(i0 - 2 + u);
-            sqh[u] = (CT)qh[c];
-            sqb[u] = (CT)qbo[c];
-        }
-        __syncthreads();
-        // faces i0-1+u: flux adjoint, face-state adjoint, slope adjoint
-        for (int u = t; u < nd + 3; u += kBlock) {
-            const int f = wr(i0 - 1 + u), fm = wr(i0 - 2 + u);
-            const CT v = (CT)dv[f];
-            const bool up = v >= (CT)0;
-            const CT fbar = dt * (sqb[u + 1] * TabT<CT>::dxinv(tb)[f] -
-                                  sqb[u] * TabT<CT>::dxinv(tb)[fm]);
-            const CT qsb = fbar * v;
-            const int uc = up ? fm : f;
-            const CT dxu = TabT<CT>::dx(tb)[uc];
-            sqs[u] = qsb;
-            scs[u] = qsb * (up ? (CT)0.5 * (dxu - v * dt) : (CT)-0.5 * (dxu + v * dt));
-            sup[u] = up ? 1 : 0;
-            if (dvb && u >= 1 && u <= nd) {
-                // owned face i0+u-1: its upwind cell's slope at Q^{n+1/2}
-                const int su_ = up ? u : u + 1;            // state index of uc
-                const int ucm = wr(i0 - 2 + su_ - 1);
-                const CT hp = TabT<CT>::hinv(tb)[uc], hm = TabT<CT>::hinv(tb)[ucm];
-                const CT dp = (sqh[su_ + 1] - sqh[su_]) * hp;
-                const CT dm = (sqh[su_] - sqh[su_ - 1]) * hm;
-                const CT sig = (dp * dm <= (CT)0) ? (CT)0 : harmonic2(dp, dm);
-                const CT qs = sqh[su_] + sig * (up ? (CT)0.5 * (dxu - v * dt)
-                                                    : (CT)-0.5 * (dxu + v * dt));
-                dvb[f] = (TQ)((CT)dvb[f] + fbar * (qs - (CT)0.5 * sig * v * dt));
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+            const int j = t + k * kBlock;
+            if (j < nd + 4) {
+                const int c = wr(i0 - 2 + j);
+                sqh[j] = (CT)qh[c];
+                sqb[j] = (CT)qbo[c];
+                sdi[j] = TabT<CT>::dxinv(tb)[c];
+                sdv[j] = (CT)dv[c];
+                srr[j] = TabT<CT>::rr(tb)[c];
             }
         }
-        // cells i0-1+u: limiter partial derivatives (times the gap inverses)
-        for (int u = t; u < nd + 2; u += kBlock) {
-            const int j = wr(i0 - 1 + u), jm = wr(i0 - 2 + u);
-            const CT hp = TabT<CT>::hinv(tb)[j], hm = TabT<CT>::hinv(tb)[jm];
-            const CT ap = (sqh[u + 2] - sqh[u + 1]) * hp;
-            const CT bm = (sqh[u + 1] - sqh[u]) * hm;
-            CT da = (CT)0, db = (CT)0;
-            if (ap * bm > (CT)0) {
-                const CT inv = (CT)1 / ((ap + bm) * (ap + bm));
-                da = (CT)2 * bm * bm * inv * hp;
-                db = (CT)2 * ap * ap * inv * hm;
-            }
-            sda[u] = da;
-            sdb[u] = db;
-        }
         __syncthreads();
-        for (int u = t; u < nd; u += kBlock) {
-            auto sigbar = [&](int k) {
-                return (sup[k] == 0 ? scs[k] : (CT)0) + (sup[k + 1] != 0 ? scs[k + 1] : (CT)0);
-            };
-            CT gsum = sqb[u + 2];
-            if (sup[u + 1] == 0) gsum += sqs[u + 1];
-            if (sup[u + 2] != 0) gsum += sqs[u + 2];
-            gsum += sigbar(u) * sda[u] + sigbar(u + 1) * (sdb[u + 1] - sda[u + 1]) -
-                    sigbar(u + 2) * sdb[u + 2];
-            smb[u] = (double)gsum * TabT<double>::dxinv(tb)[i0 + u];
+        const int u0 = 4 * t;                        // first cell of the thread
+        if (u0 < nd) {
+            CT q[8], qb[8], di[8], dx[8], hv[8], vv[7];
+#pragma unroll
+            for (int w = 0; w < 8; ++w) {
+                q[w] = sqh[u0 + w];
+                qb[w] = sqb[u0 + w];
+                di[w] = sdi[u0 + w];
+                const CT2 r = srr[u0 + w];
+                dx[w] = r.x;
+                hv[w] = r.y;
+            }
+#pragma unroll
+            for (int f = 0; f < 7; ++f) vv[f] = sdv[u0 + 1 + f];
+            // faces a-1+f, between window cells f and f+1
+            CT fbar[7], qsb[7], scs[7], half[7];
+            bool up[7];
+#pragma unroll
+            for (int f = 0; f < 7; ++f) {
+                const CT v = vv[f];
+                up[f] = v >= (CT)0;
+                fbar[f] = dt * (qb[f + 1] * di[f + 1] - qb[f] * di[f]);
+                half[f] = up[f] ? (CT)0.5 * (dx[f] - v * dt) : (CT)-0.5 * (dx[f + 1] + v * dt);
+                qsb[f] = fbar[f] * v;
+                scs[f] = qsb[f] * half[f];
+            }
+            // window cells 1..6: slope, limiter derivatives (times the gap
+            // inverses), and the slope adjoint each receives
+            CT sg[8], da[8], db[8], sb[8];
+#pragma unroll
+            for (int w = 1; w <= 6; ++w) {
+                const CT ap = (q[w + 1] - q[w]) * hv[w];
+                const CT bm = (q[w] - q[w - 1]) * hv[w - 1];
+                sg[w] = da[w] = db[w] = (CT)0;
+                if (ap * bm > (CT)0) {
+                    const CT sm = ap + bm;
+                    const CT inv = (CT)1 / (sm * sm);
+                    da[w] = (CT)2 * bm * bm * inv * hv[w];
+                    db[w] = (CT)2 * ap * ap * inv * hv[w - 1];
+                    sg[w] = harmonic2(ap, bm);
+                }
+                sb[w] = (up[w - 1] ? (CT)0 : scs[w - 1]) + (up[w] ? scs[w] : (CT)0);
+            }
+#pragma unroll
+            for (int w = 2; w <= 5; ++w) {
+                const int u = u0 + w - 2;
+                if (u < nd) {
+                    CT gs = qb[w];
+                    if (!up[w - 1]) gs += qsb[w - 1];
+                    if (up[w]) gs += qsb[w];
+                    gs += sb[w - 1] * da[w - 1] + sb[w] * (db[w] - da[w]) - sb[w + 1] * db[w + 1];
+                    smb[u] = gs * di[w];
+                    if (dvb) {
+                        // face i0+u = window face w-1, upwind cell w-1 or w
+                        const int f = w - 1;
+                        const int cu = up[f] ? f : f + 1;
+                        const CT v = vv[f];
+                        const CT qs = q[cu] + sg[cu] * half[f];
+                        dvb[i0 + u] = (TQ)((CT)dvb[i0 + u] +
+                                           fbar[f] * (qs - (CT)0.5 * sg[cu] * v * dt));
+                    }
+                }
+            }
         }
     } else {
         for (int u = t; u < nd; u += kBlock)
-            smb[u] = (double)qbo[i0 + u] * TabT<double>::dxinv(tb)[i0 + u];
+            smb[u] = (CT)qbo[i0 + u] * TabT<CT>::dxinv(tb)[i0 + u];
     }
     __syncthreads();
 
@@ -258,7 +284,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_sh(StepAdjArgs a)
             const double xe = x[en >= n ? en - n : en];
             g[k] = node_eval_adj<CT, P>(x, n, tb, rs, len, xe, kx, w[k], cc[k],
                                         xh[k]);
-            vb[k] = (e >= 1 ? smb[e - 1] : 0.0) - (e <= nd - 1 ? smb[e] : 0.0);
+            vb[k] = (e >= 1 ? (double)smb[e - 1] : 0.0) - (e <= nd - 1 ? (double)smb[e] : 0.0);
             const int64_t jc = g[k] - wlo;
             ok = ok && jc >= LO && jc + P - LO <= W;
         }
@@ -268,6 +294,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_sh(StepAdjArgs a)
     if (!ok) s_flag = 0;
     __syncthreads();
     const bool windowed = s_flag != 0;
+    double qt[NI];                               // q~ at the thread's nodes
+#pragma unroll
+    for (int k = 0; k < NI; ++k) qt[k] = 0.0;
 
     if (windowed) {
         // ---- Cbar scatter --------------------------------------------------
@@ -343,7 +372,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_sh(StepAdjArgs a)
                 if (e < NE) {
                     const int jc = (int)(g[k] - wlo);
                     double dwd[P + 1];
-                    node_dweights<P>(tb, cc[k], xh[k], dwd);
+                    node_dweights<CT, P>(tb, cc[k], xh[k], dwd);
                     double dq = 0.0, up = 0.0, dn = 0.0;
 #pragma unroll
                     for (int b = LO + 1; b <= P; ++b) {
@@ -355,7 +384,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_sh(StepAdjArgs a)
                         dn += spm[jc - LO + b];
                         dq -= dwd[b] * dn;
                     }
-                    sqt[e] = dq;
+                    qt[k] = dq;
                 }
             }
         }
@@ -385,7 +414,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_sh(StepAdjArgs a)
                 const int mid = (lo + hi) >> 1;
                 if (sgd[mid] > target) hi = mid; else lo = mid + 1;
             }
-            double S = (lo >= 1 && lo <= nd) ? smb[lo - 1] : 0.0;
+            double S = (lo >= 1 && lo <= nd) ? (double)smb[lo - 1] : 0.0;
             for (int e = lo - 1; e >= 0 && sgd[e] > target - P; --e) {
                 const int en = i0 + e;
                 const int kx = en >= n ? 1 : 0;
@@ -417,8 +446,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_sh(StepAdjArgs a)
                 const int e = t + k * kBlock;
                 if (e < NE) {
                     double dwd[P + 1];
-                    node_dweights<P>(tb, cc[k], xh[k], dwd);
-                    sqt[e] = direct_qtilde<TQ, P>(x, qf, n, dwd, cc[k]);
+                    node_dweights<CT, P>(tb, cc[k], xh[k], dwd);
+                    qt[k] = direct_qtilde<TQ, P>(x, qf, n, dwd, cc[k]);
                 }
             }
         }
@@ -428,9 +457,30 @@ __global__ __launch_bounds__(kBlock) void k_adj_sh(StepAdjArgs a)
     // telescopes to -sum_i Mbar'_i (q~_{i+1} - q~_i), which keeps the
     // cancellation between neighbouring nodes inside one FP64 difference
     if (want_v0) {
+        // q~ of node e+1: the next lane's, or across a wave boundary the
+        // next wave's first lane (the last thread's next node is thread 0's
+        // next item)
+        double qn[NI];
+#pragma unroll
+        for (int k = 0; k < NI; ++k) qn[k] = __shfl_down(qt[k], 1);
+        const int lane = t & 63, wv = t >> 6;
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < NI; ++k) sedge[k][wv] = qt[k];
+        }
         __syncthreads();
+        if (lane == 63) {
+#pragma unroll
+            for (int k = 0; k < NI; ++k)
+                qn[k] = wv + 1 < kBlock / 64 ? sedge[k][wv + 1]
+                                             : (k + 1 < NI ? sedge[k + 1][0] : 0.0);
+        }
         double vpart = 0.0;
-        for (int u = t; u < nd; u += kBlock) vpart -= smb[u] * (sqt[u + 1] - sqt[u]);
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+            const int u = t + k * kBlock;
+            if (u < nd) vpart -= (double)smb[u] * (qn[k] - qt[k]);
+        }
         for (int d = 32; d >= 1; d >>= 1) vpart += __shfl_xor(vpart, d);
         if ((t & 63) == 0) sred[t >> 6] = vpart;
         __syncthreads();

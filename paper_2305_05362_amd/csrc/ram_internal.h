@@ -110,7 +110,7 @@ struct ShiftAdjArgs {
 // One step backwards on a shared mesh (fused residual adjoint, then shift
 // adjoint).  dv == null: the step had no residual, qbar_out is the shift's.
 struct StepAdjArgs {
-    Rows rows;                          // tile = step_tile(false), tables set
+    Rows rows;                          // tile = step_tile(true), tables set
     const void *q_fwd = nullptr;        // state before the shift (v0bar)
     const void *q_half = nullptr;       // state the residual read
     const void *dv = nullptr;

