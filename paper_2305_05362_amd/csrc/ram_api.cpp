@@ -401,7 +401,7 @@ ram_status ram_residual(ram_ctx *ctx, const ram_layout *layout,
     if (q_in == q_out) return fail(RAM_E_INVALID_ARG, "q_in and q_out must not alias");
     if ((st = enter(ctx)) != RAM_OK) return st;
     Carve cv;
-    RowsPlan rp = plan_rows(cv, layout, ram::kTile, 1);
+    RowsPlan rp = plan_rows(cv, layout, ram::kResTile, 1);
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
     ram::ResidualArgs a;
     if ((st = make_rows(ctx, layout, edges, rp, a.rows)) != RAM_OK) return st;

@@ -12,6 +12,9 @@ namespace ram {
 constexpr int kTile = 256;
 constexpr int kBlock = 256;
 constexpr int kWindowCap = 2048;
+// Cells per tile of the residual step alone: four per thread, with the
+// two-cell halo a side staged in one item per thread.
+constexpr int kResTile = 1020;
 
 // How cumulative differences are formed: from a window prefix sum in FP64,
 // compensated FP32 or plain FP32, or (kSumDirect) summed directly from the

@@ -367,10 +367,18 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a)
 template <typename TQ>
 __global__ __launch_bounds__(kBlock) void k_residual(ResidualArgs a)
 {
+    // Staged once (index j <-> cell and face i0-2+j): the state, the face
+    // velocities and the mesh data (dx, 1/centre gap, 1/dx).  Each thread
+    // then updates four consecutive cells a..a+3 from its window of cells
+    // a-2..a+5 in registers: slopes of cells a-1..a+4, fluxes on faces
+    // a..a+4, the conservative update.
     using CT = TQ;
-    __shared__ CT sq[kTile + 4];    // cells i0-2 .. i0+nd+1
-    __shared__ CT ssig[kTile + 2];  // slopes of cells i0-1 .. i0+nd
-    __shared__ CT sf[kTile + 1];    // fluxes on faces i0 .. i0+nd
+    constexpr int NP = kStepNodes + 8;
+    __shared__ __attribute__((aligned(16))) CT sq[NP];
+    __shared__ __attribute__((aligned(16))) CT sdv[NP];
+    __shared__ __attribute__((aligned(16))) CT sdx[NP];
+    __shared__ __attribute__((aligned(16))) CT shv[NP];
+    __shared__ __attribute__((aligned(16))) CT sdi[NP];
 
     const Rows &R = a.rows;
     Tile ti;
@@ -381,48 +389,63 @@ __global__ __launch_bounds__(kBlock) void k_residual(ResidualArgs a)
     const TQ *dv = (const TQ *)a.dv + ti.qoff;
     TQ *qo = (TQ *)a.q_out + ti.qoff;
     const CT dt = (CT)a.dt;
-    const double len = x[n] - x[0];
     const int i0 = ti.i0;
     const int nd = min(R.tile, n - i0);
-
-    for (int t = threadIdx.x; t < nd + 4; t += kBlock)
-        sq[t] = q[wrap_small(i0 - 2 + t, n)];
-    __syncthreads();
-    for (int t = threadIdx.x; t < nd + 2; t += kBlock) {
-        const int cm = wrap_small(i0 - 2 + t, n);
-        const int c0 = wrap_small(i0 - 1 + t, n);
-        CT hp, hm;
-        if (R.has_tab) {
-            hp = TabT<CT>::hinv(R.tab)[c0];
-            hm = TabT<CT>::hinv(R.tab)[cm];
-        } else {
-            hp = (CT)(1.0 / centre_gap(x, n, len, c0));
-            hm = (CT)(1.0 / centre_gap(x, n, len, cm));
+    const bool tab = R.has_tab != 0;
+    const bool inner = (i0 - 2 >= 0) && (i0 + nd + 2 < n);
+    const int t = threadIdx.x;
+    const double len = x[n] - x[0];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const int j = t + k * kBlock;
+        if (j < nd + 4) {
+            const int c = inner ? i0 - 2 + j : wrap_small(i0 - 2 + j, n);
+            sq[j] = (CT)q[c];
+            sdv[j] = (CT)dv[c];
+            if (tab) {
+                const typename TabT<CT>::T2 r = TabT<CT>::rr(R.tab)[c];
+                sdx[j] = r.x;
+                shv[j] = r.y;
+                sdi[j] = TabT<CT>::dxinv(R.tab)[c];
+            } else {
+                const double d = x[c + 1] - x[c];
+                sdx[j] = (CT)d;
+                shv[j] = (CT)(1.0 / centre_gap(x, n, len, c));
+                sdi[j] = (CT)(1.0 / d);
+            }
         }
-        const CT dp = (sq[t + 2] - sq[t + 1]) * hp;
-        const CT dm = (sq[t + 1] - sq[t]) * hm;
-        ssig[t] = (dp * dm <= (CT)0) ? (CT)0 : harmonic2(dp, dm);
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < nd + 1; t += kBlock) {
-        const int f = wrap_small(i0 + t, n);
-        const CT v = (CT)dv[f];
+    const int u0 = 4 * t;
+    if (u0 >= nd) return;
+    CT qw[8], dx[8], hv[8];
+#pragma unroll
+    for (int w = 0; w < 8; ++w) {
+        qw[w] = sq[u0 + w];
+        dx[w] = sdx[u0 + w];
+        hv[w] = shv[u0 + w];
+    }
+    CT sg[8];
+#pragma unroll
+    for (int w = 1; w <= 6; ++w) {
+        const CT dp = (qw[w + 1] - qw[w]) * hv[w];
+        const CT dm = (qw[w] - qw[w - 1]) * hv[w - 1];
+        sg[w] = (dp * dm <= (CT)0) ? (CT)0 : harmonic2(dp, dm);
+    }
+    // face a+f lies between window cells f+1 and f+2
+    CT fl[5];
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+        const CT v = sdv[u0 + 2 + f];
         CT qf;
-        if (v >= (CT)0) {
-            const int u = wrap_small(i0 + t - 1, n);
-            const CT dxu = R.has_tab ? TabT<CT>::dx(R.tab)[u] : (CT)(x[u + 1] - x[u]);
-            qf = sq[t + 1] + (CT)0.5 * ssig[t] * (dxu - v * dt);
-        } else {
-            const CT dxu = R.has_tab ? TabT<CT>::dx(R.tab)[f] : (CT)(x[f + 1] - x[f]);
-            qf = sq[t + 2] - (CT)0.5 * ssig[t + 1] * (dxu + v * dt);
-        }
-        sf[t] = v * qf;
+        if (v >= (CT)0) qf = qw[f + 1] + (CT)0.5 * sg[f + 1] * (dx[f + 1] - v * dt);
+        else qf = qw[f + 2] - (CT)0.5 * sg[f + 2] * (dx[f + 2] + v * dt);
+        fl[f] = v * qf;
     }
-    __syncthreads();
-    for (int t = threadIdx.x; t < nd; t += kBlock) {
-        const int i = i0 + t;
-        const CT inv = R.has_tab ? TabT<CT>::dxinv(R.tab)[i] : (CT)(1.0 / (x[i + 1] - x[i]));
-        qo[i] = (TQ)(sq[t + 2] - dt * (sf[t + 1] - sf[t]) * inv);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int u = u0 + c;
+        if (u < nd) qo[i0 + u] = (TQ)(qw[c + 2] - dt * (fl[c + 1] - fl[c]) * sdi[u0 + c + 2]);
     }
 }
 
