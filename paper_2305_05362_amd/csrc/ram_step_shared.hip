@@ -97,7 +97,7 @@ __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
     constexpr int NI = kItems;
     constexpr int WCAP = kWinSh;
 
-    __shared__ int sjc[kStepNodes];      // window index of each node's cell
+    __shared__ short sjc[kStepNodes];    // window index of each node's cell (<= kWinSh)
     __shared__ CT sell[kStepNodes];      // partial integral C~(xh) - C(c)
     __shared__ A swt[kBlock / 64];
     __shared__ __attribute__((aligned(16))) unsigned char su[L::uni];
@@ -170,26 +170,76 @@ __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
         if (j < W) sm[j] = wq[r] * wd[r];
     }
     // ---- (A) shifted nodes: source index and stencil weights -------------
+    // Direct sums: the window masses are visible after one barrier, so each
+    // node's partial integral is formed as soon as its weights are, and the
+    // weights die there; the registers that frees pay for issuing the four
+    // nodes' bucket lookups together.  Prefix modes keep the weights until
+    // the scan is done and look the nodes up one at a time.
     int jc[NI];
     CT w[NI][P + 1];
     bool ok = true;
+    if (t == 0) s_flag = W > 0 ? 1 : 0;
+    if constexpr (kDirect) {
+        __syncthreads();
+        NodePos np[NI];
+        int cb[NI];
+        double2 nx[NI];
 #pragma unroll
-    for (int k = 0; k < NI; ++k) {
-        // one node at a time: the guard keeps the four lookups from being
-        // interleaved, which would cost more registers than the waves it
-        // leaves room for are worth
-        jc[k] = 0;
-        if (t + k * kBlock < NE) {
-            const NodePos np = node_pos(xe[k], rs, x0, xN, bsc, bx0, tb.nb);
-            const double2 nx = tb.bnext[np.b];
-            int c = cell_from_bucket(tb.bucket[np.b], nx, np.xt);
-            if (np.xt >= nx.y) c = cell_walk(x, n, c, np.xt);
-            rec_weights<CT, P>(RecT<CT>::get(tb)[c], np.xt, w[k]);
-            jc[k] = c + np.dk * n + kxn[k] + jbase;
-            ok = ok && jc[k] >= LO && jc[k] + P - LO <= W;
+        for (int k = 0; k < NI; ++k) {
+            np[k] = node_pos(xe[k], rs, x0, xN, bsc, bx0, tb.nb);
+            cb[k] = tb.bucket[np[k].b];
+            nx[k] = tb.bnext[np[k].b];
+        }
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+            const int ei = t + k * kBlock;
+            jc[k] = 0;
+            if (ei < NE) {
+                int c = cell_from_bucket(cb[k], nx[k], np[k].xt);
+                if (np[k].xt >= nx[k].y) c = cell_walk(x, n, c, np[k].xt);
+                CT wk[P + 1];
+                rec_weights<CT, P>(RecT<CT>::get(tb)[c], np[k].xt, wk);
+                const int j = c + np[k].dk * n + kxn[k] + jbase;
+                jc[k] = j;
+                const bool in = j >= LO && j + P - LO <= W;
+                ok = ok && in;
+                CT ell = (CT)0;
+                if (in) {
+                    // C(j-lo+b) - C(j): the masses between, summed outward
+                    CT up = (CT)0, dn = (CT)0;
+#pragma unroll
+                    for (int b = LO + 1; b <= P; ++b) {
+                        up += (CT)sm[j + b - LO - 1];
+                        ell += wk[b] * up;
+                    }
+#pragma unroll
+                    for (int b = LO - 1; b >= 0; --b) {
+                        dn += (CT)sm[j - LO + b];
+                        ell -= wk[b] * dn;
+                    }
+                }
+                sell[ei] = ell;
+                sjc[ei] = (short)j;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+            // one node at a time: the guard keeps the four lookups from being
+            // interleaved, which would cost more registers than the waves it
+            // leaves room for are worth
+            jc[k] = 0;
+            if (t + k * kBlock < NE) {
+                const NodePos np = node_pos(xe[k], rs, x0, xN, bsc, bx0, tb.nb);
+                const double2 nx = tb.bnext[np.b];
+                int c = cell_from_bucket(tb.bucket[np.b], nx, np.xt);
+                if (np.xt >= nx.y) c = cell_walk(x, n, c, np.xt);
+                rec_weights<CT, P>(RecT<CT>::get(tb)[c], np.xt, w[k]);
+                jc[k] = c + np.dk * n + kxn[k] + jbase;
+                ok = ok && jc[k] >= LO && jc[k] + P - LO <= W;
+            }
         }
     }
-    if (t == 0) s_flag = W > 0 ? 1 : 0;
     __syncthreads();
     if (!ok) s_flag = 0;
     // ---- (B) the block scan of the prefix modes ------------------------------
@@ -222,33 +272,20 @@ __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
             __syncthreads();
         }
         // ---- (C) partial integrals of the interpolated cumulative ----------
+        if constexpr (!kDirect) {
 #pragma unroll
-        for (int k = 0; k < NI; ++k) {
-            const int ei = t + k * kBlock;
-            if (ei < NE) {
-                const int j = jc[k];
-                CT ell = (CT)0;
-                if constexpr (kDirect) {
-                    // C(j-lo+b) - C(j): the masses between, summed outward
-                    CT up = (CT)0, dn = (CT)0;
-#pragma unroll
-                    for (int b = LO + 1; b <= P; ++b) {
-                        up += (CT)sm[j + b - LO - 1];
-                        ell += w[k][b] * up;
-                    }
-#pragma unroll
-                    for (int b = LO - 1; b >= 0; --b) {
-                        dn += (CT)sm[j - LO + b];
-                        ell -= w[k][b] * dn;
-                    }
-                } else {
+            for (int k = 0; k < NI; ++k) {
+                const int ei = t + k * kBlock;
+                if (ei < NE) {
+                    const int j = jc[k];
                     const A pc = sp[j];
+                    CT ell = (CT)0;
 #pragma unroll
                     for (int b = 0; b <= P; ++b)
                         if (b != LO) ell += w[k][b] * (CT)AC::diff(sp[j - LO + b], pc);
+                    sell[ei] = ell;
+                    sjc[ei] = (short)j;
                 }
-                sell[ei] = ell;
-                sjc[ei] = j;
             }
         }
     } else {
