@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -17,6 +18,15 @@ struct ram_ctx {
     hipStream_t stream = nullptr;
     void *scratch = nullptr;
     size_t scratch_bytes = 0;
+    // multi-step loops are captured once into a graph and replayed while the
+    // arguments stay the same (capture needs a stream of its own: the
+    // caller's may be the null stream)
+    hipStream_t cap_stream = nullptr;
+    struct Graph {
+        std::vector<unsigned char> key;
+        hipGraphExec_t exec = nullptr;
+    };
+    std::vector<Graph> graphs;          // most recently used first
 };
 
 namespace {
@@ -51,6 +61,11 @@ ram_status enter(ram_ctx *ctx)
 
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
+// Step loops of at least this many launches are captured into a graph; the
+// context keeps the most recent few.
+constexpr int64_t kGraphMinSteps = 4;
+constexpr size_t kGraphCache = 4;
+
 ram_status ensure_scratch(ram_ctx *ctx, size_t bytes)
 {
     if (bytes <= ctx->scratch_bytes) return RAM_OK;
@@ -59,6 +74,8 @@ ram_status ensure_scratch(ram_ctx *ctx, size_t bytes)
     if (ctx->scratch) (void)hipFree(ctx->scratch);
     ctx->scratch = nullptr;
     ctx->scratch_bytes = 0;
+    for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);   // stream is idle
+    ctx->graphs.clear();
     size_t want = align_up(bytes + bytes / 8);
     e = hipMalloc(&ctx->scratch, want);
     if (e != hipSuccess) {
@@ -222,28 +239,78 @@ ram_status launch_steps(ram_ctx *ctx, ram::StepArgs a, ram_dtype dtype,
         a.plan_wlo = wlo;
         a.plan_w = w;
     }
-    auto one = [&](const ram::StepArgs &s) {
-        return shared ? ram::launch_step_shared(s, f64, (int)scan, order, ctx->stream)
-                      : ram::launch_step(s, f64, (int)scan, order, ctx->stream);
+    auto one = [&](const ram::StepArgs &s, hipStream_t st) {
+        return shared ? ram::launch_step_shared(s, f64, (int)scan, order, st)
+                      : ram::launch_step(s, f64, (int)scan, order, st);
     };
     if (n_steps == 1 && a.q_out) {
-        e = one(a);
+        e = one(a, ctx->stream);
         if (e != hipSuccess) return hip_fail(e, "step launch");
         return RAM_OK;
     }
-    void *q = const_cast<void *>(a.q_in);
-    void *cur = q, *oth = tmp;
-    for (int64_t k = 0; k < n_steps; ++k) {
-        a.q_in = cur;
-        a.q_out = oth;
-        e = one(a);
+    // the ping-pong loop, on stream st
+    auto loop = [&](hipStream_t st) -> hipError_t {
+        ram::StepArgs b = a;
+        void *q = const_cast<void *>(a.q_in);
+        void *cur = q, *oth = tmp;
+        for (int64_t k = 0; k < n_steps; ++k) {
+            b.q_in = cur;
+            b.q_out = oth;
+            hipError_t r = one(b, st);
+            if (r != hipSuccess) return r;
+            void *t = cur; cur = oth; oth = t;
+        }
+        if (cur != q) return ram::launch_copy(cur, q, (int64_t)state_bytes, st);
+        return hipSuccess;
+    };
+    if (n_steps < kGraphMinSteps) {
+        e = loop(ctx->stream);
         if (e != hipSuccess) return hip_fail(e, "step launch");
-        void *t = cur; cur = oth; oth = t;
+        return RAM_OK;
     }
-    if (cur != q) {
-        e = ram::launch_copy(cur, q, (int64_t)state_bytes, ctx->stream);
-        if (e != hipSuccess) return hip_fail(e, "state copy");
+    // replay the captured loop when every argument is the same
+    std::vector<unsigned char> key(sizeof(a) + 4 * sizeof(int64_t));
+    std::memcpy(key.data(), &a, sizeof(a));
+    const int64_t extra[4] = {(int64_t)dtype * 16 + (int64_t)scan, order, n_steps,
+                              (int64_t)(intptr_t)tmp ^ (int64_t)state_bytes};
+    std::memcpy(key.data() + sizeof(a), extra, sizeof(extra));
+    size_t hit = ctx->graphs.size();
+    for (size_t i = 0; i < ctx->graphs.size(); ++i)
+        if (ctx->graphs[i].key == key) { hit = i; break; }
+    if (hit < ctx->graphs.size()) {
+        std::rotate(ctx->graphs.begin(), ctx->graphs.begin() + hit,
+                    ctx->graphs.begin() + hit + 1);
+    } else {
+        if (ctx->graphs.size() >= kGraphCache) {
+            e = hipStreamSynchronize(ctx->stream);          // the evicted one is done
+            if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+            (void)hipGraphExecDestroy(ctx->graphs.back().exec);
+            ctx->graphs.pop_back();
+        }
+        if (!ctx->cap_stream) {
+            e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
+        }
+        e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        const hipError_t le = loop(ctx->cap_stream);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(ctx->cap_stream, &g);
+        if (le != hipSuccess || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return hip_fail(le != hipSuccess ? le : e, "step loop capture");
+        }
+        hipGraphExec_t x = nullptr;
+        e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+        ram_ctx::Graph entry;
+        entry.key = std::move(key);
+        entry.exec = x;
+        ctx->graphs.insert(ctx->graphs.begin(), std::move(entry));
     }
+    e = hipGraphLaunch(ctx->graphs.front().exec, ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
     return RAM_OK;
 }
 
@@ -336,6 +403,8 @@ ram_status ram_destroy(ram_ctx *ctx)
     if (!ctx) return RAM_OK;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     if (ctx->scratch) (void)hipFree(ctx->scratch);
     delete ctx;
     return RAM_OK;
@@ -438,6 +507,7 @@ ram_status ram_step(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
     const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(sizeof(int32_t) * nt);
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
     ram::StepArgs a;
+    std::memset(&a, 0, sizeof(a));        // the graph key compares raw bytes
     if ((st = make_rows(ctx, layout, edges, rp, a.rows)) != RAM_OK) return st;
     a.q_in = q;
     a.v0 = v0;

@@ -31,6 +31,8 @@
 //   k_tiles_prep tile table of a ragged batch.
 #include "ram_device.h"
 
+#include <algorithm>
+
 #include <type_traits>
 
 namespace ram {
@@ -669,11 +671,30 @@ hipError_t launch_residual(const ResidualArgs &a, bool f64, hipStream_t stream)
     return hipGetLastError();
 }
 
+// Plain copy kernel (16-byte words, then the tail bytes): also usable inside
+// a captured graph, where it keeps copy nodes out.
+__global__ __launch_bounds__(256) void k_copy(const unsigned char *src, unsigned char *dst,
+                                              int64_t bytes)
+{
+    const int64_t nw = bytes / 16;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t i = i0; i < nw; i += stride)
+        ((uint4 *)dst)[i] = ((const uint4 *)src)[i];
+    for (int64_t b = nw * 16 + i0; b < bytes; b += stride) dst[b] = src[b];
+}
+
 hipError_t launch_copy(const void *src, void *dst, int64_t bytes,
                        hipStream_t stream)
 {
-    return hipMemcpyAsync(dst, src, (size_t)bytes, hipMemcpyDeviceToDevice,
-                          stream);
+    if (bytes <= 0) return hipSuccess;
+    if ((((uintptr_t)src | (uintptr_t)dst) & 15) != 0)
+        return hipMemcpyAsync(dst, src, (size_t)bytes, hipMemcpyDeviceToDevice, stream);
+    const int64_t nw = (bytes + 15) / 16;
+    const unsigned grid = (unsigned)std::min<int64_t>((nw + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_copy, dim3(grid), dim3(256), 0, stream,
+                       (const unsigned char *)src, (unsigned char *)dst, bytes);
+    return hipGetLastError();
 }
 
 } // namespace ram
