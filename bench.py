@@ -15,6 +15,10 @@ the FP64 oracle on sampled rows, the dominant kernel's HBM roofline, and the
 CPU oracle's throughput on a bounded sample (run on this host's cores).
 
     python bench.py [--steps K] [--warmup W] [--adj-steps A] [--no-cpu]
+
+The FP32 headline forms cumulative differences by summing the window masses
+directly (RAM_SUM_DIRECT); the compensated two-sum and FP64 prefix-sum
+variants and the FP64 path are reported beside it.
 """
 from __future__ import annotations
 
@@ -50,7 +54,7 @@ def parse():
 
 
 COPY_BYTES = 256 << 20
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_sh_f32_twosum_polar2048x16384_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_sh_f32_direct_polar2048x16384_traffic.md")
 
 
 def load_traffic():
@@ -126,7 +130,7 @@ def main():
 
     if args.profile_pass:
         q = q32.clone()
-        ctx.ram_step(rows, q, v0, dv32, wl.dt, order, args.steps, R.RAM_SCAN_F32_TWOSUM)
+        ctx.ram_step(rows, q, v0, dv32, wl.dt, order, args.steps, R.RAM_SUM_DIRECT)
         src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         dst.copy_(src)
@@ -135,16 +139,18 @@ def main():
                           "copy_bytes": COPY_BYTES}), flush=True)
         return
 
-    # --- headline: FP32 state, compensated FP32 prefix sums ----------------
+    # --- headline: FP32 state, cumulative differences summed directly ------
     # one fused shift+residual kernel per step (plus one mesh-table and one
     # window-plan kernel per call): the region time over the steps is the
     # fused kernel's average launch duration
-    t_ts, q_ts = time_steps(q32, dv32, R.RAM_SCAN_F32_TWOSUM, args.steps, args.warmup)
+    HEAD = R.RAM_SUM_DIRECT
+    t_ts, q_ts = time_steps(q32, dv32, HEAD, args.steps, args.warmup)
     value = n_cells * args.steps / t_ts / 1e9
     t_fused = t_ts / args.steps
-    # --- FP32 state, direct sums (no prefix) ---------------------------------
-    t_dir, q_dir = time_steps(q32, dv32, R.RAM_SUM_DIRECT, args.steps // 4, args.warmup)
-    v_dir = n_cells * (args.steps // 4) / t_dir / 1e9
+    # --- FP32 state, compensated FP32 prefix sums ---------------------------
+    k2s = max(1, args.steps // 4)
+    t_two, _ = time_steps(q32, dv32, R.RAM_SCAN_F32_TWOSUM, k2s, args.warmup)
+    v_two = n_cells * k2s / t_two / 1e9
     # --- FP32 state, FP64 prefix sums ---------------------------------------
     k2 = max(1, args.steps // 4)
     t_f64s, _ = time_steps(q32, dv32, R.RAM_SCAN_F64, k2, args.warmup)
@@ -172,12 +178,12 @@ def main():
     h32 = torch.empty_like(q32)
     o32 = torch.empty_like(q32)
     reps = 50
-    t_shift = time_kernel(lambda: ctx.ram_shift(rows, q32, h32, v0, wl.dt, order,
-                                                R.RAM_SCAN_F32_TWOSUM), reps)
+    t_shift = time_kernel(lambda: ctx.ram_shift(rows, q32, h32, v0, wl.dt, order, HEAD),
+                          reps)
     t_res = time_kernel(lambda: ctx.ram_residual(rows, h32, o32, dv32, wl.dt), reps)
     fused_bytes = 12.0 * n_cells         # read Q, read dv, write Q'' (FP32)
-    kernels = {"step_fused_f32_twosum_us": t_fused * 1e6,
-               "shift_only_f32_twosum_us": t_shift * 1e6,
+    kernels = {"step_fused_f32_direct_us": t_fused * 1e6,
+               "shift_only_f32_direct_us": t_shift * 1e6,
                "residual_only_f32_us": t_res * 1e6,
                "fused_algorithmic_bytes_per_cell": 12,
                "shift_only_algorithmic_bytes_per_cell": 8,
@@ -189,7 +195,7 @@ def main():
                 "traffic": None if tr is None else round(tr["traffic_bytes_per_launch"]),
                 "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled)",
                 "algorithmic_bytes_per_launch": fused_bytes,
-                "kernel": "k_step_sh<float, order 5, two-sum scan, fused residual>"}
+                "kernel": "k_step_sh<float, order 5, direct sums, fused residual>"}
 
     # --- forward + adjoint (checkpointed rollout) ---------------------------
     ka = args.adj_steps
@@ -197,14 +203,12 @@ def main():
     dva = dv32.clone().requires_grad_(True)
     v0a = v0.clone().requires_grad_(True)
     g = torch.ones_like(q32)
-    out = rollout(qa, rows, v0a, dva, wl.dt, order, min(ka, 20), args.checkpoint,
-                  R.RAM_SCAN_F32_TWOSUM)
+    out = rollout(qa, rows, v0a, dva, wl.dt, order, min(ka, 20), args.checkpoint, HEAD)
     out.backward(g)                      # warm-up
     torch.cuda.synchronize()
     a, b = events()
     a.record()
-    out = rollout(qa, rows, v0a, dva, wl.dt, order, ka, args.checkpoint,
-                  R.RAM_SCAN_F32_TWOSUM)
+    out = rollout(qa, rows, v0a, dva, wl.dt, order, ka, args.checkpoint, HEAD)
     out.backward(g)
     b.record()
     torch.cuda.synchronize()
@@ -218,7 +222,7 @@ def main():
     q32h = q32.cpu().numpy().reshape(wl.n_rows, n)
     dv32h = dv32.cpu().numpy().reshape(wl.n_rows, n)
     one = q32.clone()
-    ctx.ram_step(rows, one, v0, dv32, wl.dt, order, 1, R.RAM_SCAN_F32_TWOSUM)
+    ctx.ram_step(rows, one, v0, dv32, wl.dt, order, 1, HEAD)
     torch.cuda.synchronize()
     sub = oracle.Rows(np.arange(len(pick) + 1) * n, wl.edges, True)
     ref = oracle.step(sub, q32h[pick].astype(np.float64), wl.v0[pick],
@@ -260,11 +264,12 @@ def main():
                                "azimuthal mesh (10x refined |phi|<0.2), Keplerian v0, "
                                "order-5 shift + van Leer residual",
                    "rows": wl.n_rows, "cols": n, "order": order,
-                   "prefix_sums": "compensated FP32 (two-sum)", "dt": wl.dt},
+                   "cumulative_differences": "summed directly from FP32 masses (no prefix)",
+                   "dt": wl.dt},
         "fwd_adjoint": {"value": round(v_adj, 3), "unit": "Gcell-updates/s",
                         "steps": ka, "checkpoint": args.checkpoint},
         "fp32_fp64scan": {"value": round(v_f64s, 3), "steps": k2},
-        "fp32_direct_sums": {"value": round(v_dir, 3), "steps": args.steps // 4},
+        "fp32_twosum_prefix": {"value": round(v_two, 3), "steps": k2s},
         "fp64_plain": {"value": round(v64, 3), "steps": args.fp64_steps},
         "mixed_speedup_vs_fp64": round(value / v64, 3),
         "error": {"one_step_rel_l1_vs_oracle": err1,

@@ -301,11 +301,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_sh(StepAdjArgs a)
     if (windowed) {
         // ---- Cbar scatter --------------------------------------------------
         for (int j = t; j <= W; j += kBlock) scb[j] = 0.0;
-        int base = 0;
-        {
-            const int64_t kk = wlo >= 0 ? wlo / n : -((-wlo + n - 1) / n);
-            base = (int)(wlo - kk * n);
-        }
+        const int base = a.plan_w[R.n_tiles + blockIdx.x];   // wlo mod n
         // forward window masses for the reconstruction at the nodes
         if (want_v0) {
             for (int j = t; j < W; j += kBlock) {

@@ -328,7 +328,7 @@ ram_status step_adjoint_shared(ram_ctx *ctx, const ram_layout *layout, ram_dtype
     // size keeps them within one item per thread
     RowsPlan rp = plan_rows(cv, layout, ram::step_tile(true), order);
     const int64_t nt = tiles_of(layout, rp.tile);
-    const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(sizeof(int32_t) * nt);
+    const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(2 * sizeof(int32_t) * nt);
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
     ram::StepArgs p;
     if ((st = make_rows(ctx, layout, edges, rp, p.rows)) != RAM_OK) return st;
@@ -444,7 +444,7 @@ ram_status ram_shift(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
     Carve cv;
     RowsPlan rp = plan_rows(cv, layout, ram::step_tile(false), order);
     const int64_t nt = tiles_of(layout, rp.tile);
-    const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(sizeof(int32_t) * nt);
+    const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(2 * sizeof(int32_t) * nt);
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
     ram::StepArgs a;
     if ((st = make_rows(ctx, layout, edges, rp, a.rows)) != RAM_OK) return st;
@@ -504,7 +504,7 @@ ram_status ram_step(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
     const size_t tmp_off = cv.take(state_bytes);
     RowsPlan rp = plan_rows(cv, layout, ram::step_tile(dv != nullptr), order);
     const int64_t nt = tiles_of(layout, rp.tile);
-    const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(sizeof(int32_t) * nt);
+    const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(2 * sizeof(int32_t) * nt);
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
     ram::StepArgs a;
     std::memset(&a, 0, sizeof(a));        // the graph key compares raw bytes
@@ -609,7 +609,7 @@ ram_status ram_step_record(ram_ctx *ctx, const ram_layout *layout,
     Carve cv;
     RowsPlan rp = plan_rows(cv, layout, ram::step_tile(dv != nullptr), order);
     const int64_t nt = tiles_of(layout, rp.tile);
-    const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(sizeof(int32_t) * nt);
+    const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(2 * sizeof(int32_t) * nt);
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
     ram::StepArgs a;
     if ((st = make_rows(ctx, layout, edges, rp, a.rows)) != RAM_OK) return st;

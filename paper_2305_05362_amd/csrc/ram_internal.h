@@ -88,7 +88,8 @@ struct StepArgs {
     const void *dv = nullptr;         // null: shift only
     double dt = 0.0;
     const int64_t *plan_wlo = nullptr;  // shared mesh: per-tile window start
-    const int32_t *plan_w = nullptr;    // ... and length (-1: direct path)
+    const int32_t *plan_w = nullptr;    // ... length (-1: direct path), then
+                                        // [n_tiles + tile]: start mod n
     void *q_mid = nullptr;              // optional: the state after the shift
 };
 
@@ -124,7 +125,7 @@ struct StepAdjArgs {
     const double *v0 = nullptr;
     double dt = 0.0;
     const int64_t *plan_wlo = nullptr;  // window plan of the shift (no halo)
-    const int32_t *plan_w = nullptr;
+    const int32_t *plan_w = nullptr;    // [n_tiles] lengths, [n_tiles] starts mod n
 };
 
 struct ResidualAdjArgs {
@@ -161,7 +162,7 @@ hipError_t launch_mesh_prep(const double *x, int64_t n, int order, void *mem,
 hipError_t launch_step(const StepArgs &a, bool f64, int scan, int order,
                        hipStream_t stream);
 // Shared-mesh specialisation: plan the tiles' source windows once per call
-// (launch_plan, into n_tiles int64 + int32), then one launch per step.
+// (launch_plan, into n_tiles int64 + 2 n_tiles int32), then one launch per step.
 hipError_t launch_plan(const StepArgs &a, int order, int64_t *wlo, int32_t *w,
                        hipStream_t stream);
 hipError_t launch_step_shared(const StepArgs &a, bool f64, int scan, int order,

@@ -50,9 +50,10 @@ struct ShLds {
     static constexpr size_t uni = u0 > nodes ? u0 : nodes;
 };
 
-// Window plan: extended source index of each tile's first node minus lo,
-// the window start inside the row (that index mod n), and the window length
-// (or -1 when it exceeds the LDS capacity).
+// Window plan: extended source index of each tile's first node minus lo
+// (wlo_out), the window length or -1 when it exceeds the LDS capacity
+// (w_out[tile]), and the window start inside the row, wlo mod n
+// (w_out[n_tiles + tile]).
 template <int P>
 __global__ __launch_bounds__(256) void k_plan(StepArgs a, int64_t *wlo_out,
                                               int32_t *w_out)
@@ -73,8 +74,12 @@ __global__ __launch_bounds__(256) void k_plan(StepArgs a, int64_t *wlo_out,
     const int64_t g0 = node_index(x, n, R.tab, rs, len, i0 - H);
     const int64_t g1 = node_index(x, n, R.tab, rs, len, i0 + nd + H);
     const int64_t wide = g1 - g0 + P;
-    wlo_out[tile] = g0 - LO;
+    const int64_t wlo = g0 - LO;
+    wlo_out[tile] = wlo;
     w_out[tile] = (wide >= P && wide <= kWinSh) ? (int32_t)wide : -1;
+    // the window start inside the row, wlo mod n
+    const int64_t kk = wlo >= 0 ? wlo / n : -((-wlo + n - 1) / n);
+    w_out[R.n_tiles + tile] = (int32_t)(wlo - kk * n);
 }
 
 // Periodic index for j in [-n, 2n).
@@ -146,11 +151,7 @@ __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
         xe[k] = ei < NE ? x[inner ? e : wrap1(e, n)] : x0;
     }
     // window start inside the row: wlo mod n
-    int base = 0;
-    if (W > 0) {
-        const int64_t kk = wlo >= 0 ? wlo / n : -((-wlo + n - 1) / n);
-        base = (int)(wlo - kk * n);
-    }
+    const int base = a.plan_w[R.n_tiles + blockIdx.x];   // wlo mod n
     const bool wsmall = W + base <= 2 * n;
     M wq[kWinRegs], wd[kWinRegs];
 #pragma unroll
