@@ -450,11 +450,12 @@ struct NodePos {
 __device__ inline NodePos node_pos(double xe, const RowShift &rs, double x0, double xN,
                                    double bsc, double bx0, int nb)
 {
+    // all three candidates, then selects (no divergent branch)
     const double xs = xe - rs.s;
-    double v = xs - rs.p0;
-    int d = 0;
-    if (v >= xN) { v = xs - rs.pp; d = 1; }
-    else if (v < x0) { v = xs - rs.pm; d = -1; }
+    const double v0 = xs - rs.p0, vp = xs - rs.pp, vm = xs - rs.pm;
+    const bool hi = v0 >= xN, lo = v0 < x0;
+    const double v = hi ? vp : (lo ? vm : v0);
+    const int d = hi ? 1 : (lo ? -1 : 0);
     int b = (int)(v * bsc - bx0);
     b = min(max(b, 0), nb - 1);
     return {v, d, b};

@@ -95,9 +95,42 @@ struct StepLds {
     static constexpr size_t win = sizeof(M) * kWinStep + sizeof(A) * (kWinStep + 1);
     static constexpr size_t res = 3 * sizeof(CT) * kStepNodes;
     static constexpr size_t nodes = sizeof(int64_t) * kStepNodes;
+    // per-row meshes, before the window is loaded: the window's node
+    // coordinates (FP64) and their periods relative to the first
+    static constexpr size_t stage = (sizeof(double) + sizeof(short)) * (kWinStep + 1);
     static constexpr size_t uni0 = win > res ? win : res;
-    static constexpr size_t uni = uni0 > nodes ? uni0 : nodes;
+    static constexpr size_t uni1 = uni0 > nodes ? uni0 : nodes;
+    static constexpr size_t uni = uni1 > stage ? uni1 : stage;
 };
+
+// Lagrange weights at t of the nodes X[0..P] given relative to the stencil's
+// cell (X[lo] = 0, X[lo+1] = dx_c): normalised by dx_c, products of all
+// differences but one, one division per weight, in WT.
+template <typename WT, int P>
+__device__ inline void lagrange_rel(double t, const double *X, WT *w)
+{
+    constexpr int LO = (P - 1) / 2;
+    const double inv = 1.0 / X[LO + 1];
+    WT th[P + 1];
+#pragma unroll
+    for (int a = 0; a <= P; ++a) th[a] = (WT)(X[a] * inv);
+    const WT tt = (WT)(t * inv);
+    WT pre[P + 1], suf[P + 1];
+    pre[0] = (WT)1;
+#pragma unroll
+    for (int a = 1; a <= P; ++a) pre[a] = pre[a - 1] * (tt - th[a - 1]);
+    suf[P] = (WT)1;
+#pragma unroll
+    for (int a = P - 1; a >= 0; --a) suf[a] = suf[a + 1] * (tt - th[a + 1]);
+#pragma unroll
+    for (int a = 0; a <= P; ++a) {
+        WT den = (WT)1;
+#pragma unroll
+        for (int b = 0; b <= P; ++b)
+            if (b != a) den *= th[a] - th[b];
+        w[a] = pre[a] * suf[a] / den;
+    }
+}
 
 template <typename TQ, int P, int S>
 __global__ __launch_bounds__(kBlock) void k_step(StepArgs a)
@@ -179,6 +212,46 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a)
     }
     if (t == 0) s_flag = 1;
 
+    // Per-row meshes: the tile's window from its two end nodes (global
+    // searches by two threads), then the window's node coordinates staged in
+    // LDS, where every node finds its cell and its stencil nodes.
+    double *sxs = (double *)su;                          // window nodes (FP64)
+    short *skq = (short *)(su + sizeof(double) * (kWinStep + 1));   // periods
+    if (!tab) {
+        if (t < 2) {
+            int e = t == 0 ? i0 - H : i0 - H + NE - 1;
+            int kx = 0;
+            if (e < 0) { e += n; kx = -1; }
+            while (e >= n) { e -= n; kx += 1; }
+            double xh;
+            int64_t k;
+            shifted_node_inv(x, n, s, e, invlen, len, xh, k);
+            const int64_t gg = (int64_t)find_cell(x, n, xh) + (k + kx) * (int64_t)n;
+            if (t == 0) s_wlo = gg - LO;
+            else s_whi = gg - LO + P;
+        }
+        __syncthreads();
+    }
+    int64_t pwlo = 0, pk0 = 0;
+    bool stage = false;
+    int pW = 0;
+    if (!tab) {
+        pwlo = s_wlo;
+        pk0 = pwlo >= 0 ? pwlo / n : -((-pwlo + n - 1) / n);   // period of wlo
+        stage = s_whi - pwlo >= P && s_whi - pwlo <= kWinStep;
+        pW = stage ? (int)(s_whi - pwlo) : 0;
+    }
+    if (stage) {
+        const int pbase = (int)(pwlo - pk0 * n);
+        for (int j = t; j <= pW; j += kBlock) {
+            int m = pbase + j, kq = 0;
+            while (m >= n) { m -= n; ++kq; }
+            sxs[j] = x[m];
+            skq[j] = (short)kq;
+        }
+        __syncthreads();
+    }
+
     // (A) shifted nodes e = i0 - H + t + k kBlock: cell and stencil weights
     int64_t g[NI];
     TQ w[NI][P + 1];
@@ -194,20 +267,42 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a)
             double xh;
             int64_t kk;
             shifted_node_inv(x, n, s, e, invlen, len, xh, kk);
-            const int c = tab ? find_cell_tab(x, n, R.tab, bsc, xh) : find_cell(x, n, xh);
-            g[k] = (int64_t)c + (kk + kx) * (int64_t)n;
-            stencil_weights<TQ, P>(x, n, len, R, c, xh, w[k]);
-        }
-    }
-    if (!tab) {
-        // exact window from the first and last node
+            bool done = false;
+            if (stage) {
+                // the last window cell whose left node is at or below the
+                // shifted node, comparing (period, coordinate) pairs exactly
+                const int dk = (int)(kk + kx - pk0);
+                auto le = [&](int j) {
+                    const int kj = skq[j];
+                    return kj < dk || (kj == dk && sxs[j] <= xh);
+                };
+                int lo = 0, hi = pW + 1;
+                if (le(0)) {
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (le(mid)) lo = mid;
+                        else hi = mid;
+                    }
+                    if (lo - LO >= 0 && lo - LO + P <= pW) {
+                        g[k] = pwlo + lo;
+                        const double xc = sxs[lo];
+                        const int kc = skq[lo];
+                        double X[P + 1];
 #pragma unroll
-        for (int k = 0; k < NI; ++k)
-            if (t + k * kBlock < NE) sg[t + k * kBlock] = g[k];
-        __syncthreads();
-        if (t == 0) {
-            s_wlo = sg[0] - LO;
-            s_whi = sg[NE - 1] - LO + P;
+                        for (int b = 0; b <= P; ++b) {
+                            const int jb = lo - LO + b;
+                            X[b] = (sxs[jb] - xc) + (double)(skq[jb] - kc) * len;
+                        }
+                        lagrange_rel<TQ, P>(xh - xc, X, w[k]);
+                        done = true;
+                    }
+                }
+            }
+            if (!done) {
+                const int c = tab ? find_cell_tab(x, n, R.tab, bsc, xh) : find_cell(x, n, xh);
+                g[k] = (int64_t)c + (kk + kx) * (int64_t)n;
+                stencil_weights<TQ, P>(x, n, len, R, c, xh, w[k]);
+            }
         }
     }
     __syncthreads();
