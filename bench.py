@@ -214,6 +214,22 @@ def main():
     torch.cuda.synchronize()
     t_adj = a.elapsed_time(b) / 1e3
     v_adj = n_cells * ka / t_adj / 1e9
+    # the same with every state kept ((2 ka + 1) states in HBM, no recompute);
+    # one untimed pass first so the allocator holds the trajectory's memory
+    del out
+    out = rollout(qa, rows, v0a, dva, wl.dt, order, ka, 0, HEAD)
+    out.backward(g)
+    del out
+    torch.cuda.synchronize()
+    a, b = events()
+    a.record()
+    out = rollout(qa, rows, v0a, dva, wl.dt, order, ka, 0, HEAD)
+    out.backward(g)
+    b.record()
+    torch.cuda.synchronize()
+    t_adj_all = a.elapsed_time(b) / 1e3
+    v_adj_all = n_cells * ka / t_adj_all / 1e9
+    del out
 
     # --- accuracy: one step vs the FP64 oracle on sampled rows; rollout drift
     import oracle
@@ -268,6 +284,10 @@ def main():
                    "dt": wl.dt},
         "fwd_adjoint": {"value": round(v_adj, 3), "unit": "Gcell-updates/s",
                         "steps": ka, "checkpoint": args.checkpoint},
+        "fwd_adjoint_all_states_kept": {"value": round(v_adj_all, 3),
+                                        "unit": "Gcell-updates/s", "steps": ka,
+                                        "state_memory_gb": round((2 * ka + 1) * n_cells * 4
+                                                                 / 1e9, 1)},
         "fp32_fp64scan": {"value": round(v_f64s, 3), "steps": k2},
         "fp32_twosum_prefix": {"value": round(v_two, 3), "steps": k2s},
         "fp64_plain": {"value": round(v64, 3), "steps": args.fp64_steps},

@@ -3,7 +3,8 @@ steps, with gradients with respect to the initial state Q0, the residual
 velocity dv and the per-row bulk velocity v0.
 
 Forward: n steps of (bulk shift, residual), keeping one state every
-``checkpoint`` steps.  Backward: for each segment, newest first, recompute the
+``checkpoint`` steps (or, with checkpoint 0, every state and post-shift
+state, so the backward pass needs no recomputation).  Backward: for each segment, newest first, recompute the
 segment from its checkpoint with ram_step_record (every state and every
 post-shift state), then walk it backwards with ram_step_adjoint (the residual
 transpose, dv-bar accumulating, then the shift transpose, v0-bar
@@ -39,13 +40,27 @@ class RamRollout(torch.autograd.Function):
                 n_steps: int, checkpoint: int, scan: int):
         ctx = R.context(q0.device.index)
         dvc = None if dv is None else dv.detach().contiguous()
-        q, saved = _rollout(ctx, rows, q0.detach().contiguous(), dvc,
-                            v0.detach().contiguous(), dt, order, n_steps,
-                            checkpoint, scan, keep=True)
+        v0c = v0.detach().contiguous()
         fctx.rows = rows
         fctx.dt, fctx.order, fctx.n_steps = float(dt), int(order), int(n_steps)
         fctx.checkpoint, fctx.scan = int(checkpoint), int(scan)
         fctx.has_dv = dv is not None
+        fctx.stored = checkpoint <= 0 or checkpoint >= n_steps
+        if fctx.stored:
+            # keep every state and every post-shift state: no recomputation
+            # in the backward pass ((2n+1) states of memory)
+            qc = q0.detach().contiguous().reshape(-1)
+            traj = torch.empty((n_steps + 1, qc.numel()), dtype=qc.dtype, device=qc.device)
+            half = torch.empty((n_steps, qc.numel()), dtype=qc.dtype,
+                               device=qc.device) if dvc is not None else None
+            traj[0].copy_(qc)
+            ctx.ram_step_record(rows, traj, half, v0c, dvc, dt, order, n_steps, scan)
+            q = traj[n_steps].clone().reshape(q0.shape)
+            fctx.save_for_backward(v0.detach(), *([dvc] if dvc is not None else []), traj,
+                                   *([half] if half is not None else []))
+            return q
+        q, saved = _rollout(ctx, rows, q0.detach().contiguous(), dvc, v0c, dt, order,
+                            n_steps, checkpoint, scan, keep=True)
         fctx.save_for_backward(v0.detach(), *([dvc] if dvc is not None else []), *saved)
         return q
 
@@ -63,6 +78,14 @@ class RamRollout(torch.autograd.Function):
         tmp = torch.empty_like(qbar)
         dvbar = torch.zeros_like(dv) if dv is not None else None
         v0bar = torch.zeros_like(v0, dtype=torch.float64)
+        if fctx.stored:
+            traj = checkpoints[0]
+            half = checkpoints[1] if dv is not None else None
+            for i in range(fctx.n_steps - 1, -1, -1):
+                ctx.ram_step_adjoint(rows, traj[i], None if half is None else half[i], dv,
+                                     qbar, tmp, v0, dt, order, dvbar, v0bar)
+                qbar, tmp = tmp, qbar
+            return qbar, dvbar, v0bar.to(v0.dtype), None, None, None, None, None, None
         n_seg = len(checkpoints)
         seg = min(fctx.checkpoint, fctx.n_steps)
         traj = torch.empty((seg + 1, qbar.numel()), dtype=qbar.dtype, device=qbar.device)
@@ -85,5 +108,9 @@ class RamRollout(torch.autograd.Function):
 def rollout(q0: torch.Tensor, rows: R.Rows, v0: torch.Tensor,
             dv: Optional[torch.Tensor], dt: float, order: int, n_steps: int,
             checkpoint: int = 20, scan: int = R.RAM_SCAN_F64) -> torch.Tensor:
-    """Differentiable n-step rollout; gradients flow to q0, dv and v0."""
+    """Differentiable n-step rollout; gradients flow to q0, dv and v0.
+
+    checkpoint: keep one state every `checkpoint` steps and recompute each
+    segment in the backward pass; 0 (or >= n_steps) keeps every state and
+    post-shift state instead ((2n+1) states of memory, no recomputation)."""
     return RamRollout.apply(q0, dv, v0, rows, dt, order, n_steps, checkpoint, scan)

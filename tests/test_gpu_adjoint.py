@@ -7,7 +7,8 @@
 * the FP64 oracle gradient on sampled rows (rows are independent, so a row's
   loss gradient only involves that row): relative L1 <= 1e-10;
 * the FP32-state gradient against the FP64 one (reported, loose bar);
-* checkpoint spacing does not change the gradient.
+* checkpoint spacing does not change the gradient, nor does keeping every
+  state (no recomputation).
 dv coordinates are drawn away from zero (the upwind switch).
 """
 import numpy as np
@@ -202,10 +203,12 @@ def test_checkpoint_spacing_and_fp32_gradient():
     tgt = torch.as_tensor(wl.q0.reshape(-1) * 0.99, dtype=torch.float64, device=DEV)
     a = _grads(wl, rows, q0, dv, v0, area, tgt, steps, 40)
     b = _grads(wl, rows, q0, dv, v0, area, tgt, steps, 7)
+    st = _grads(wl, rows, q0, dv, v0, area, tgt, steps, 0)     # every state kept
     # recomputation is deterministic; only the order of the adjoint's atomic
     # accumulations differs between runs
-    for x, y in zip(a[:3], b[:3]):
+    for x, y, z in zip(a[:3], b[:3], st[:3]):
         assert float((x - y).abs().max()) <= 1e-10 * float(y.abs().max())
+        assert float((z - y).abs().max()) <= 1e-10 * float(y.abs().max())
     rows32, q32, dv32, _, area32 = _setup(wl, torch.float32)
     c = _grads(wl, rows32, q32, dv32, v0, area32, tgt, steps, 10, R.RAM_SCAN_F64)
     for x, y in zip(c[:3], a[:3]):
