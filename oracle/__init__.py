@@ -15,6 +15,9 @@ Every function follows one passage of the paper:
   residual         Eq. splitting_second with the PLM / van Leer slope of
                    Section 3.1 and the swept-interval upwind face state;
   step             the operator split of Section 1: shift, then residual;
+  shift_recon      Section 3's remap with the limited reconstructions of
+                   Section 3.1 (PLM / van Leer, PPM with App. A), and
+  step_recon       the split step built on it;
   shift_adjoint    transpose of the (linear) shift, plus dL/dv0;
   residual_adjoint transpose of the residual Jacobian, plus dL/d(dv).
 
@@ -66,9 +69,14 @@ def _load():
     lib.oracle_residual_adjoint.argtypes = [I64, P, P, I, P, P, P, P, P, D, I]
     lib.oracle_edges.argtypes = [P, P, I64, D, I, P, P, P, P, P]
     lib.oracle_max_threads.argtypes = []
+    lib.oracle_shift_recon.argtypes = [I64, P, P, I, P, P, P, D, I, I]
+    lib.oracle_step_recon.argtypes = [I64, P, P, I, P, P, P, D, I, I64, I]
+    lib.oracle_recon_cells.argtypes = [P, P, I64, I, I, P, P, P]
+    lib.oracle_edges_recon.argtypes = [P, P, I64, D, I, P, P]
     for f in ("oracle_shift", "oracle_residual", "oracle_step",
               "oracle_shift_adjoint", "oracle_residual_adjoint", "oracle_edges",
-              "oracle_max_threads"):
+              "oracle_max_threads", "oracle_shift_recon", "oracle_step_recon",
+              "oracle_recon_cells", "oracle_edges_recon"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -191,3 +199,61 @@ def edges_info(x, q, s: float, order: int):
     _load().oracle_edges(_ptr(x), _ptr(q), n, float(s), int(order), _ptr(xh),
                          _ptr(k), _ptr(c), _ptr(ell), _ptr(dell))
     return xh, k, c, ell, dell
+
+
+# limited reconstructions of the bulk shift (Section 3.1, App. A)
+PLM = 1
+PPM = 2
+FREE_DELTA = 1      # recon_cells only: leave delta<Q> unlimited
+FREE_PARABOLA = 2   # recon_cells only: skip the (QL, QR) constraints
+
+
+def shift_recon(rows: Rows, q, v0, dt: float, recon: int,
+                nthreads: int = 0) -> np.ndarray:
+    """One bulk shift of every row with the PLM (1) or PPM (2) reconstruction."""
+    q = _f64(q).reshape(-1)
+    v0 = _f64(np.broadcast_to(v0, (rows.n_rows,)))
+    out = np.empty_like(q)
+    rc = _load().oracle_shift_recon(rows.n_rows, _ptr(rows.row_ptr), _ptr(rows.edges),
+                                    int(rows.shared), _ptr(q), _ptr(out), _ptr(v0),
+                                    float(dt), int(recon), int(nthreads))
+    _check(rc, "shift_recon")
+    return out
+
+
+def step_recon(rows: Rows, q, v0, dv, dt: float, recon: int, n_steps: int,
+               nthreads: int = 0) -> np.ndarray:
+    """n_steps of limited shift then residual (dv None: shift only)."""
+    q = _f64(q).reshape(-1).copy()
+    v0 = _f64(np.broadcast_to(v0, (rows.n_rows,)))
+    dvp = None if dv is None else _f64(dv).reshape(-1)
+    rc = _load().oracle_step_recon(rows.n_rows, _ptr(rows.row_ptr), _ptr(rows.edges),
+                                   int(rows.shared), _ptr(q), _ptr(v0), _ptr(dvp),
+                                   float(dt), int(recon), int(n_steps), int(nthreads))
+    _check(rc, "step_recon")
+    return q
+
+
+def recon_cells(x, q, recon: int, flags: int = 0):
+    """Per cell of one row: PLM (Q, sigma, 0) or PPM (QL, QR, Q6)."""
+    x = _f64(x)
+    q = _f64(q)
+    n = len(q)
+    c0, c1, c2 = np.empty(n), np.empty(n), np.empty(n)
+    rc = _load().oracle_recon_cells(_ptr(x), _ptr(q), n, int(recon), int(flags),
+                                    _ptr(c0), _ptr(c1), _ptr(c2))
+    _check(rc, "recon_cells")
+    return c0, c1, c2
+
+
+def edges_recon(x, q, s: float, recon: int):
+    """Per shifted node of one row: extended source index g and partial integral."""
+    x = _f64(x)
+    q = _f64(q)
+    n = len(q)
+    g = np.empty(n, dtype=np.int64)
+    ell = np.empty(n)
+    rc = _load().oracle_edges_recon(_ptr(x), _ptr(q), n, float(s), int(recon),
+                                    _ptr(g), _ptr(ell))
+    _check(rc, "edges_recon")
+    return g, ell

@@ -24,6 +24,9 @@
  *              the upwind linear profile over the swept interval, i.e. Eq.
  *              mass_shift_algo in its sub-cell (Lufkin) limit of Section 3.2.
  *   step       shift, then residual (Section 1).
+ *   shift_recon the same remap with the limited (monotone) reconstructions of
+ *              Section 3.1 instead: PLM with the van Leer slope, or PPM with
+ *              the interface values and constraints of App. A.
  *   adjoints   transposes of the two linearised maps, written as scatter loops
  *              (the device path gathers); plus the derivative w.r.t. the bulk
  *              speed v0 (through x~ = x - v0 dt, Section 3.2).
@@ -259,6 +262,151 @@ static int residual_row(const double *x, const double *q, const double *dv,
 }
 
 /* ---------------------------------------------------------------------- */
+/* limited (monotone) reconstructions for the bulk shift                    */
+/* ---------------------------------------------------------------------- */
+/*
+ * The two reconstructions Section 3.1 uses for Step 1 of the shift:
+ *
+ *   PLM   q_c(x) = Q_c + sigma_c (x - x_c), x_c the cell centre (Section 2),
+ *         sigma_c the van Leer harmonic slope (the same slope as the residual).
+ *   PPM   the parabola of Colella & Woodward (1984) in the form Section 3.1
+ *         writes it, q_c = QL + xi (QR - QL) + Q6 xi (1 - xi),
+ *         Q6 = 6 Q_c - 3 (QL + QR), with xi = (x - x_{c-1/2}) / dx_c measured
+ *         from the cell's left node (the reading under which the parabola keeps
+ *         the cell's mass, Eq. Qmass_interp_1).  QL and QR are the interface
+ *         values of App. A (interpolation of the averages, limited slope
+ *         delta<Q>) after the App. A monotonicity constraints.
+ *
+ * App. A reading: the weights w1, w2, w3 take SUMS of neighbouring cell sizes
+ * where the printed text shows products (Colella & Woodward's Eq. 1.6; the
+ * printed products are not even dimensionally consistent), the limited slope
+ * keeps the sign of the unlimited one (their Eq. 1.8), and the third
+ * constraint reads -(QR - QL)^2 / 6 > (QR - QL) Qa.
+ *
+ * flags (used by the pins only): RECON_FREE_DELTA leaves delta<Q> unlimited,
+ * RECON_FREE_PARABOLA skips the constraints on (QL, QR).
+ */
+#define RECON_PLM 1
+#define RECON_PPM 2
+#define RECON_FREE_DELTA 1
+#define RECON_FREE_PARABOLA 2
+
+/* size and average of (wrapped) cell m */
+static double dx_w(const double *x, int64_t n, int64_t m)
+{
+    int64_t w = wrap(m, n);
+    return x[w + 1] - x[w];
+}
+
+static double q_w(const double *q, int64_t n, int64_t m) { return q[wrap(m, n)]; }
+
+/* delta<Q>_j of App. A: the slope of cell j times its size, limited so that
+ * the interface values stay between neighbouring averages */
+static double ppm_delta(const double *x, const double *q, int64_t n, int64_t j,
+                        int flags)
+{
+    double hm = dx_w(x, n, j - 1), h0 = dx_w(x, n, j), hp = dx_w(x, n, j + 1);
+    double up = q_w(q, n, j + 1) - q_w(q, n, j);
+    double dn = q_w(q, n, j) - q_w(q, n, j - 1);
+    double d = h0 / (hm + h0 + hp) *
+               ((2.0 * hm + h0) / (hp + h0) * up + (h0 + 2.0 * hp) / (hm + h0) * dn);
+    if (flags & RECON_FREE_DELTA) return d;
+    if (up * dn <= 0.0) return 0.0;
+    double mag = fmin(fabs(d), fmin(2.0 * fabs(up), 2.0 * fabs(dn)));
+    return copysign(mag, d);
+}
+
+/* <Q>_{j+1/2}: the value on the node between cells j and j+1 (App. A) */
+static double ppm_interface(const double *x, const double *q, int64_t n,
+                            int64_t j, int flags)
+{
+    double hm = dx_w(x, n, j - 1), h0 = dx_w(x, n, j);
+    double hp = dx_w(x, n, j + 1), hpp = dx_w(x, n, j + 2);
+    double a0 = q_w(q, n, j), a1 = q_w(q, n, j + 1);
+    double w1 = 2.0 * hp * h0 / (h0 + hp) *
+                ((hm + h0) / (2.0 * h0 + hp) - (hpp + hp) / (2.0 * hp + h0));
+    double w2 = -h0 * (hm + h0) / (2.0 * h0 + hp);
+    double w3 = hp * (hp + hpp) / (h0 + 2.0 * hp);
+    double corr = w1 * (a1 - a0) + w2 * ppm_delta(x, q, n, j + 1, flags) +
+                  w3 * ppm_delta(x, q, n, j, flags);
+    return a0 + h0 / (h0 + hp) * (a1 - a0) + corr / (hm + h0 + hp + hpp);
+}
+
+/* (QL, QR, Q6) of cell c after the App. A constraints */
+static void ppm_parabola(const double *x, const double *q, int64_t n, int64_t c,
+                         int flags, double *ql, double *qr, double *q6)
+{
+    double a = q_w(q, n, c);
+    double L = ppm_interface(x, q, n, c - 1, flags);
+    double R = ppm_interface(x, q, n, c, flags);
+    if (!(flags & RECON_FREE_PARABOLA)) {
+        if ((R - a) * (a - L) <= 0.0) {
+            /* a local extremum: the cell is flat */
+            L = a;
+            R = a;
+        } else {
+            double dq = R - L, qa = a - 0.5 * (L + R);
+            if (dq * qa > dq * dq / 6.0) L = 3.0 * a - 2.0 * R;
+            else if (-dq * dq / 6.0 > dq * qa) R = 3.0 * a - 2.0 * L;
+        }
+    }
+    *ql = L;
+    *qr = R;
+    *q6 = 6.0 * a - 3.0 * (L + R);
+}
+
+/* Integral of the limited q_c from the cell's left node to xh (Step 2's partial
+ * integral; x_c <= xh <= x_{c+1}, c in [0, n-1]). */
+static double limited_partial(const double *x, const double *q, int64_t n,
+                              int64_t c, double xh, int recon)
+{
+    double xl = x[c], h = x[c + 1] - x[c];
+    if (recon == RECON_PLM) {
+        double xc = centre(x, c), sig = vl_slope(x, q, n, c);
+        /* antiderivative of Q_c + sigma (y - x_c) between xl and xh */
+        return q[c] * (xh - xl) +
+               0.5 * sig * ((xh - xc) * (xh - xc) - (xl - xc) * (xl - xc));
+    }
+    double ql, qr, q6;
+    ppm_parabola(x, q, n, c, 0, &ql, &qr, &q6);
+    double th = (xh - xl) / h;
+    return h * (ql * th + 0.5 * (qr - ql) * th * th +
+                q6 * (0.5 * th * th - th * th * th / 3.0));
+}
+
+/* Bulk shift with a limited reconstruction, in the local form
+ * M'_i = sum_{m=g_i}^{g_{i+1}-1} M_m + ell_{i+1} - ell_i (Eq. mass_shift_algo). */
+static int shift_row_recon(const double *x, const double *q, double *qout,
+                           int64_t n, double s, int recon)
+{
+    int64_t *g = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    double *ell = (double *)malloc(sizeof(double) * (size_t)(n + 1));
+    if (!g || !ell) { free(g); free(ell); return -6; }
+    for (int64_t e = 0; e < n; ++e) {
+        double xh;
+        int64_t k;
+        shifted_node(x, n, s, e, &xh, &k);
+        int64_t c = find_cell(x, n, xh);
+        g[e] = c + k * n;
+        ell[e] = limited_partial(x, q, n, c, xh, recon);
+    }
+    /* node N is node 0 one period on */
+    g[n] = g[0] + n;
+    ell[n] = ell[0];
+    for (int64_t i = 0; i < n; ++i) {
+        double whole = 0.0;
+        for (int64_t m = g[i]; m < g[i + 1]; ++m) whole += cell_mass(x, q, n, m);
+        qout[i] = (whole + ell[i + 1] - ell[i]) / (x[i + 1] - x[i]);
+    }
+    free(g);
+    free(ell);
+    return 0;
+}
+
+/* fewest cells a row needs: the reconstruction stencil (3 or 5 cells) plus one */
+static int64_t recon_min_cells(int recon) { return recon == RECON_PLM ? 4 : 6; }
+
+/* ---------------------------------------------------------------------- */
 /* adjoints (scatter form)                                                  */
 /* ---------------------------------------------------------------------- */
 
@@ -487,6 +635,83 @@ int oracle_edges(const double *x, const double *q, int64_t n, double s,
         edge_t E;
         edge_eval(x, q, n, s, order, e, 1, &E);
         xh[e] = E.xh; k[e] = E.k; c[e] = E.c; ell[e] = E.ell; dell[e] = E.dell;
+    }
+    return 0;
+}
+
+/* Bulk shift with a limited reconstruction (recon 1 PLM, 2 PPM). */
+int oracle_shift_recon(int64_t n_rows, const int64_t *row_ptr, const double *edges,
+                       int shared, const double *q, double *qout, const double *v0,
+                       double dt, int recon, int nthreads)
+{
+    if (recon != RECON_PLM && recon != RECON_PPM) return -2;
+    set_threads(nthreads);
+    int err = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
+    for (int64_t r = 0; r < n_rows; ++r) {
+        int64_t n = row_ptr[r + 1] - row_ptr[r];
+        if (n < recon_min_cells(recon)) { err |= 1; continue; }
+        err |= shift_row_recon(row_mesh(edges, shared, row_ptr, r), q + row_ptr[r],
+                               qout + row_ptr[r], n, v0[r] * dt, recon) != 0;
+    }
+    return err ? -1 : 0;
+}
+
+/* n_steps of (limited shift, then residual when dv != NULL), q in place. */
+int oracle_step_recon(int64_t n_rows, const int64_t *row_ptr, const double *edges,
+                      int shared, double *q, const double *v0, const double *dv,
+                      double dt, int recon, int64_t n_steps, int nthreads)
+{
+    if (recon != RECON_PLM && recon != RECON_PPM) return -2;
+    set_threads(nthreads);
+    int err = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
+    for (int64_t r = 0; r < n_rows; ++r) {
+        int64_t n = row_ptr[r + 1] - row_ptr[r];
+        const double *x = row_mesh(edges, shared, row_ptr, r);
+        double *qr = q + row_ptr[r];
+        double *tmp = (double *)malloc(sizeof(double) * (size_t)n);
+        if (!tmp || n < recon_min_cells(recon)) { err |= 1; free(tmp); continue; }
+        for (int64_t st = 0; st < n_steps; ++st) {
+            shift_row_recon(x, qr, tmp, n, v0[r] * dt, recon);
+            if (dv) residual_row(x, tmp, dv + row_ptr[r], qr, n, dt);
+            else memcpy(qr, tmp, sizeof(double) * (size_t)n);
+        }
+        free(tmp);
+    }
+    return err ? -1 : 0;
+}
+
+/* Per-cell reconstruction of one row (tests): PLM (Q, sigma, 0), PPM
+ * (QL, QR, Q6); flags as for ppm_parabola. */
+int oracle_recon_cells(const double *x, const double *q, int64_t n, int recon,
+                       int flags, double *c0, double *c1, double *c2)
+{
+    if (recon != RECON_PLM && recon != RECON_PPM) return -2;
+    for (int64_t c = 0; c < n; ++c) {
+        if (recon == RECON_PLM) {
+            c0[c] = q[c];
+            c1[c] = vl_slope(x, q, n, c);
+            c2[c] = 0.0;
+        } else {
+            ppm_parabola(x, q, n, c, flags, &c0[c], &c1[c], &c2[c]);
+        }
+    }
+    return 0;
+}
+
+/* Limited-reconstruction partial integrals of one row's shifted nodes (tests). */
+int oracle_edges_recon(const double *x, const double *q, int64_t n, double s,
+                       int recon, int64_t *g, double *ell)
+{
+    if (recon != RECON_PLM && recon != RECON_PPM) return -2;
+    for (int64_t e = 0; e < n; ++e) {
+        double xh;
+        int64_t k;
+        shifted_node(x, n, s, e, &xh, &k);
+        int64_t c = find_cell(x, n, xh);
+        g[e] = c + k * n;
+        ell[e] = limited_partial(x, q, n, c, xh, recon);
     }
     return 0;
 }

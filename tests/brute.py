@@ -143,3 +143,48 @@ def residual_exact(edges, q, dv, dt) -> List[Fr]:
 
 def to_fr(a) -> List[Fr]:
     return [Fr(x) for x in a]
+
+
+def shift_piecewise_exact(edges: Sequence[Fr], qfun, s: Fr) -> List[Fr]:
+    """Exact cell averages after shifting by s a piecewise function given
+    pointwise: qfun(c, xi) is the value of source cell c's reconstruction at
+    the normalised coordinate xi = (x - x_c)/dx_c in [0, 1].  Every overlap of
+    a destination interval with a periodic image of a source cell is
+    integrated by Simpson's rule, exact for the polynomials of degree <= 3 the
+    limited reconstructions are (Eq. mass_advected taken literally)."""
+    n = len(edges) - 1
+    L = edges[n] - edges[0]
+    out = []
+    for i in range(n):
+        a, b = edges[i] - s, edges[i + 1] - s
+        kmin = int((a - edges[0]) // L) - 1
+        kmax = int((b - edges[0]) // L) + 1
+        tot = Fr(0)
+        for k in range(kmin, kmax + 1):
+            for c in range(n):
+                lo_c, hi_c = edges[c] + k * L, edges[c + 1] + k * L
+                lo_, hi_ = max(a, lo_c), min(b, hi_c)
+                if hi_ > lo_:
+                    h = edges[c + 1] - edges[c]
+                    xa = (lo_ - lo_c) / h
+                    xb = (hi_ - lo_c) / h
+                    simpson = (qfun(c, xa) + 4 * qfun(c, (xa + xb) / 2) + qfun(c, xb)) / 6
+                    tot += simpson * (hi_ - lo_)
+        out.append(tot / (edges[i + 1] - edges[i]))
+    return out
+
+
+def lagrange_derivative(X: Sequence[Fr], Y: Sequence[Fr], t: Fr) -> Fr:
+    """Derivative at t of the polynomial through the points (X[a], Y[a])."""
+    m = len(X)
+    tot = Fr(0)
+    for a in range(m):
+        for b in range(m):
+            if b == a:
+                continue
+            term = Fr(1) / (X[a] - X[b])
+            for c in range(m):
+                if c != a and c != b:
+                    term *= (t - X[c]) / (X[a] - X[c])
+            tot += Y[a] * term
+    return tot
