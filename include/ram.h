@@ -68,6 +68,18 @@ typedef enum {
     RAM_SUM_DIRECT = 3        /* no prefix: direct sums in the state's type    */
 } ram_scan;
 
+/* Limited (monotone) reconstructions for the bulk shift (Section 3.1; App. A):
+ *   RAM_RECON_PLM  q_c(x) = Q_c + sigma_c (x - x_c), x_c the cell centre, with
+ *                  the van Leer harmonic slope of the centre-gap differences;
+ *   RAM_RECON_PPM  Colella & Woodward's parabola QL + xi (QR - QL) + Q6 xi (1-xi),
+ *                  xi from the cell's left node, Q6 = 6 Q_c - 3 (QL + QR), with
+ *                  the App. A interface values (neighbouring sizes summed in the
+ *                  weights, as in Colella & Woodward's Eq. 1.6), the limited
+ *                  slope (sign of the unlimited one) and the three constraints
+ *                  that flatten extrema and make every parabola monotone.
+ * Neither creates new extrema on a uniform mesh; both are nonlinear in Q. */
+typedef enum { RAM_RECON_PLM = 1, RAM_RECON_PPM = 2 } ram_recon;
+
 typedef struct {
     int64_t n_rows;           /* number of rows (>= 1)                          */
     int64_t n_cols;           /* > 0: every row has n_cols cells; 0: ragged     */
@@ -117,6 +129,27 @@ ram_status ram_step(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
                     ram_scan scan, void *q, const double *edges,
                     const double *v0, const void *dv, double dt, int order,
                     int64_t n_steps);
+
+/* Bulk shift with a limited reconstruction (paper Section 3, Steps 1-3, with
+ * Step 1 as in Section 3.1 / App. A): q_out = the conservative remap of the PLM
+ * or PPM profile of q_in shifted by v0[r]*dt (any sign and size).  The whole-
+ * cell masses are summed directly in `dtype` (no prefix sums); the PPM mesh
+ * weights of a shared mesh are tabulated once per call.  Every row needs
+ * N_r >= 4 cells (PLM) or >= 6 (PPM).  q_in and q_out: `dtype`, n_cells each,
+ * must not alias.  RAM_E_UNSUPPORTED for another recon value. */
+ram_status ram_shift_limited(ram_ctx *ctx, const ram_layout *layout,
+                             ram_dtype dtype, ram_recon recon, const void *q_in,
+                             void *q_out, const double *edges, const double *v0,
+                             double dt);
+
+/* n_steps operator-split steps (paper Section 1) with the limited shift:
+ * ram_shift_limited, then (dv != NULL) ram_residual; q updated in place, the
+ * context's scratch holds the intermediate state.  Loops of four or more steps
+ * are captured into a graph once and replayed while the arguments match. */
+ram_status ram_step_limited(ram_ctx *ctx, const ram_layout *layout,
+                            ram_dtype dtype, ram_recon recon, void *q,
+                            const double *edges, const double *v0,
+                            const void *dv, double dt, int64_t n_steps);
 
 /* Adjoint of ram_shift (the shift is linear in Q): qbar_in = S^T qbar_out,
  * overwritten.  When v0bar_accum != NULL, also accumulates per row

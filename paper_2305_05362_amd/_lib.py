@@ -35,6 +35,10 @@ RAM_SUM_DIRECT = 3
 SCANS = {"f64": RAM_SCAN_F64, "twosum": RAM_SCAN_F32_TWOSUM, "f32": RAM_SCAN_F32,
          "direct": RAM_SUM_DIRECT}
 
+RAM_RECON_PLM = 1
+RAM_RECON_PPM = 2
+RECONS = {"plm": RAM_RECON_PLM, "ppm": RAM_RECON_PPM}
+
 
 class RamError(RuntimeError):
     def __init__(self, status: int, message: str):
@@ -76,6 +80,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ram_step_record": [P, LP, I, I, P, P, P, P, P, D, I, I64],
         "ram_step_adjoint": [P, LP, I, P, P, P, P, P, P, P, D, I, P, P],
         "ram_validate": [P, LP, I, P, P, D],
+        "ram_shift_limited": [P, LP, I, I, P, P, P, P, D],
+        "ram_step_limited": [P, LP, I, I, P, P, P, P, D, I64],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -192,6 +198,25 @@ class Context:
             _dev_ptr(v0, torch.float64, "v0"), float(dt), int(order)))
         return q_out
 
+    def ram_shift_limited(self, rows: Rows, q_in, q_out, v0, dt: float, recon: int):
+        self._stream()
+        check(self._lib.ram_shift_limited(
+            self._h, ctypes.byref(rows.layout), _dtype_code(q_in), int(recon),
+            _dev_ptr(q_in, q_in.dtype, "q_in"), _dev_ptr(q_out, q_in.dtype, "q_out"),
+            _dev_ptr(rows.edges, torch.float64, "edges"),
+            _dev_ptr(v0, torch.float64, "v0"), float(dt)))
+        return q_out
+
+    def ram_step_limited(self, rows: Rows, q, v0, dv, dt: float, recon: int,
+                         n_steps: int):
+        self._stream()
+        check(self._lib.ram_step_limited(
+            self._h, ctypes.byref(rows.layout), _dtype_code(q), int(recon),
+            _dev_ptr(q, q.dtype, "q"), _dev_ptr(rows.edges, torch.float64, "edges"),
+            _dev_ptr(v0, torch.float64, "v0"), _dev_ptr(dv, q.dtype, "dv"),
+            float(dt), int(n_steps)))
+        return q
+
     def ram_residual(self, rows: Rows, q_in, q_out, dv, dt: float):
         self._stream()
         check(self._lib.ram_residual(
@@ -295,6 +320,14 @@ def context(device: Optional[int] = None) -> Context:
 
 def ram_shift(rows, q_in, q_out, v0, dt, order, scan=RAM_SCAN_F64):
     return context(q_in.device.index).ram_shift(rows, q_in, q_out, v0, dt, order, scan)
+
+
+def ram_shift_limited(rows, q_in, q_out, v0, dt, recon):
+    return context(q_in.device.index).ram_shift_limited(rows, q_in, q_out, v0, dt, recon)
+
+
+def ram_step_limited(rows, q, v0, dv, dt, recon, n_steps):
+    return context(q.device.index).ram_step_limited(rows, q, v0, dv, dt, recon, n_steps)
 
 
 def ram_residual(rows, q_in, q_out, dv, dt):

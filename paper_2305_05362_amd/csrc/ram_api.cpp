@@ -137,6 +137,17 @@ ram_status check_scan(ram_dtype dt, ram_scan scan)
     return RAM_OK;
 }
 
+ram_status check_recon(const ram_layout *L, ram_recon recon)
+{
+    if (recon != RAM_RECON_PLM && recon != RAM_RECON_PPM)
+        return fail(RAM_E_UNSUPPORTED, "recon must be RAM_RECON_PLM or RAM_RECON_PPM (got %d)",
+                    (int)recon);
+    const int need = recon == RAM_RECON_PLM ? 4 : 6;
+    if (L->n_cols > 0 && L->n_cols < need)
+        return fail(RAM_E_INVALID_ARG, "rows need at least %d cells", need);
+    return RAM_OK;
+}
+
 ram_status check_dt(double dt)
 {
     if (!std::isfinite(dt)) return fail(RAM_E_INVALID_ARG, "dt must be finite");
@@ -220,6 +231,72 @@ int64_t tiles_of(const ram_layout *L, int tile)
     return ram::ragged_tile_bound(L->n_cells, L->n_rows, tile);
 }
 
+// Run loop(stream) on the context's stream: directly for short loops, else
+// through a graph captured once per distinct key (every argument the loop's
+// launches depend on, as raw bytes) and replayed afterwards.
+template <typename F>
+ram_status run_graphed(ram_ctx *ctx, std::vector<unsigned char> key, int64_t n_steps,
+                       F &&loop)
+{
+    hipError_t e;
+    if (n_steps < kGraphMinSteps) {
+        e = loop(ctx->stream);
+        if (e != hipSuccess) return hip_fail(e, "step launch");
+        return RAM_OK;
+    }
+    size_t hit = ctx->graphs.size();
+    for (size_t i = 0; i < ctx->graphs.size(); ++i)
+        if (ctx->graphs[i].key == key) { hit = i; break; }
+    if (hit < ctx->graphs.size()) {
+        std::rotate(ctx->graphs.begin(), ctx->graphs.begin() + hit,
+                    ctx->graphs.begin() + hit + 1);
+    } else {
+        if (ctx->graphs.size() >= kGraphCache) {
+            e = hipStreamSynchronize(ctx->stream);          // the evicted one is done
+            if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+            (void)hipGraphExecDestroy(ctx->graphs.back().exec);
+            ctx->graphs.pop_back();
+        }
+        if (!ctx->cap_stream) {
+            e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
+        }
+        e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        const hipError_t le = loop(ctx->cap_stream);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(ctx->cap_stream, &g);
+        if (le != hipSuccess || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return hip_fail(le != hipSuccess ? le : e, "step loop capture");
+        }
+        hipGraphExec_t x = nullptr;
+        e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+        ram_ctx::Graph entry;
+        entry.key = std::move(key);
+        entry.exec = x;
+        ctx->graphs.insert(ctx->graphs.begin(), std::move(entry));
+    }
+    e = hipGraphLaunch(ctx->graphs.front().exec, ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return RAM_OK;
+}
+
+// Raw bytes of the arguments a loop depends on (the graph cache's key).
+template <typename... T>
+std::vector<unsigned char> key_of(const T &...parts)
+{
+    std::vector<unsigned char> k;
+    auto put = [&](const auto &p) {
+        const unsigned char *b = (const unsigned char *)&p;
+        k.insert(k.end(), b, b + sizeof(p));
+    };
+    (put(parts), ...);
+    return k;
+}
+
 // n_steps launches of the bulk-shift kernel (fused with the residual when
 // a.dv is set).  n_steps == 1 writes a.q_out; n_steps > 1 updates a.q_in in
 // place, ping-ponging with `tmp`.  Shared meshes take the specialised kernel
@@ -263,55 +340,9 @@ ram_status launch_steps(ram_ctx *ctx, ram::StepArgs a, ram_dtype dtype,
         if (cur != q) return ram::launch_copy(cur, q, (int64_t)state_bytes, st);
         return hipSuccess;
     };
-    if (n_steps < kGraphMinSteps) {
-        e = loop(ctx->stream);
-        if (e != hipSuccess) return hip_fail(e, "step launch");
-        return RAM_OK;
-    }
-    // replay the captured loop when every argument is the same
-    std::vector<unsigned char> key(sizeof(a) + 4 * sizeof(int64_t));
-    std::memcpy(key.data(), &a, sizeof(a));
     const int64_t extra[4] = {(int64_t)dtype * 16 + (int64_t)scan, order, n_steps,
                               (int64_t)(intptr_t)tmp ^ (int64_t)state_bytes};
-    std::memcpy(key.data() + sizeof(a), extra, sizeof(extra));
-    size_t hit = ctx->graphs.size();
-    for (size_t i = 0; i < ctx->graphs.size(); ++i)
-        if (ctx->graphs[i].key == key) { hit = i; break; }
-    if (hit < ctx->graphs.size()) {
-        std::rotate(ctx->graphs.begin(), ctx->graphs.begin() + hit,
-                    ctx->graphs.begin() + hit + 1);
-    } else {
-        if (ctx->graphs.size() >= kGraphCache) {
-            e = hipStreamSynchronize(ctx->stream);          // the evicted one is done
-            if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-            (void)hipGraphExecDestroy(ctx->graphs.back().exec);
-            ctx->graphs.pop_back();
-        }
-        if (!ctx->cap_stream) {
-            e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
-            if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
-        }
-        e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
-        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-        const hipError_t le = loop(ctx->cap_stream);
-        hipGraph_t g = nullptr;
-        e = hipStreamEndCapture(ctx->cap_stream, &g);
-        if (le != hipSuccess || e != hipSuccess) {
-            if (g) (void)hipGraphDestroy(g);
-            return hip_fail(le != hipSuccess ? le : e, "step loop capture");
-        }
-        hipGraphExec_t x = nullptr;
-        e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
-        ram_ctx::Graph entry;
-        entry.key = std::move(key);
-        entry.exec = x;
-        ctx->graphs.insert(ctx->graphs.begin(), std::move(entry));
-    }
-    e = hipGraphLaunch(ctx->graphs.front().exec, ctx->stream);
-    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
-    return RAM_OK;
+    return run_graphed(ctx, key_of(a, extra), n_steps, loop);
 }
 
 // One step backwards on a shared mesh: window plan of the shift (no halo),
@@ -518,6 +549,96 @@ ram_status ram_step(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
                            state_bytes)) != RAM_OK)
         return st;
     return RAM_OK;
+}
+
+ram_status ram_shift_limited(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
+                             ram_recon recon, const void *q_in, void *q_out,
+                             const double *edges, const double *v0, double dt)
+{
+    ram_status st;
+    g_last_error.clear();
+    if ((st = check_layout(layout, edges)) != RAM_OK) return st;
+    if ((st = check_dtype(dtype)) != RAM_OK) return st;
+    if ((st = check_recon(layout, recon)) != RAM_OK) return st;
+    if ((st = check_dt(dt)) != RAM_OK) return st;
+    if (!q_in || !q_out || !v0) return fail(RAM_E_INVALID_ARG, "null q_in, q_out or v0");
+    if (q_in == q_out) return fail(RAM_E_INVALID_ARG, "q_in and q_out must not alias");
+    if ((st = enter(ctx)) != RAM_OK) return st;
+    Carve cv;
+    RowsPlan rp = plan_rows(cv, layout, ram::step_tile(false), 1);
+    if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
+    ram::StepArgs a;
+    if ((st = make_rows(ctx, layout, edges, rp, a.rows)) != RAM_OK) return st;
+    a.q_in = q_in;
+    a.q_out = q_out;
+    a.v0 = v0;
+    a.dt = dt;
+    hipError_t e = ram::launch_shift_limited(a, dtype == RAM_F64, (int)recon, ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "limited shift launch");
+    return RAM_OK;
+}
+
+ram_status ram_step_limited(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
+                            ram_recon recon, void *q, const double *edges,
+                            const double *v0, const void *dv, double dt, int64_t n_steps)
+{
+    ram_status st;
+    g_last_error.clear();
+    if ((st = check_layout(layout, edges)) != RAM_OK) return st;
+    if ((st = check_dtype(dtype)) != RAM_OK) return st;
+    if ((st = check_recon(layout, recon)) != RAM_OK) return st;
+    if ((st = check_dt(dt)) != RAM_OK) return st;
+    if (!q || !v0) return fail(RAM_E_INVALID_ARG, "null q or v0");
+    if (n_steps < 0) return fail(RAM_E_INVALID_ARG, "n_steps must be >= 0");
+    if (n_steps == 0) return RAM_OK;
+    if ((st = enter(ctx)) != RAM_OK) return st;
+    const size_t state_bytes = elem_size(dtype) * (size_t)layout_cells(layout);
+    Carve cv;
+    const size_t tmp_off = cv.take(state_bytes);
+    // the shift's rows carry the mesh tables; the residual's rows share them
+    RowsPlan rp = plan_rows(cv, layout, ram::step_tile(false), 1);
+    RowsPlan rr = plan_rows(cv, layout, ram::kResTile, 0);
+    if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
+    ram::StepArgs a;
+    std::memset(&a, 0, sizeof(a));        // the graph key compares raw bytes
+    if ((st = make_rows(ctx, layout, edges, rp, a.rows)) != RAM_OK) return st;
+    ram::ResidualArgs r;
+    std::memset(&r, 0, sizeof(r));
+    if ((st = make_rows(ctx, layout, edges, rr, r.rows)) != RAM_OK) return st;
+    r.rows.tab = a.rows.tab;
+    r.rows.has_tab = a.rows.has_tab;
+    a.v0 = v0;
+    a.dt = dt;
+    r.dv = dv;
+    r.dt = dt;
+    void *tmp = (char *)ctx->scratch + tmp_off;
+    const bool f64 = dtype == RAM_F64;
+    // with the residual: shift q -> tmp, residual tmp -> q; without: the
+    // shifts ping-pong between q and tmp
+    auto loop = [&](hipStream_t st) -> hipError_t {
+        ram::StepArgs b = a;
+        ram::ResidualArgs c = r;
+        void *cur = q, *oth = tmp;
+        for (int64_t k = 0; k < n_steps; ++k) {
+            b.q_in = cur;
+            b.q_out = oth;
+            hipError_t e = ram::launch_shift_limited(b, f64, (int)recon, st);
+            if (e != hipSuccess) return e;
+            if (dv) {
+                c.q_in = oth;
+                c.q_out = cur;
+                e = ram::launch_residual(c, f64, st);
+                if (e != hipSuccess) return e;
+            } else {
+                void *t = cur; cur = oth; oth = t;
+            }
+        }
+        if (cur != q) return ram::launch_copy(cur, q, (int64_t)state_bytes, st);
+        return hipSuccess;
+    };
+    const int64_t extra[4] = {(int64_t)dtype * 16 + 256 * (int64_t)recon, -1, n_steps,
+                              (int64_t)(intptr_t)q ^ (int64_t)state_bytes};
+    return run_graphed(ctx, key_of(a, r, extra, tmp), n_steps, loop);
 }
 
 ram_status ram_shift_adjoint(ram_ctx *ctx, const ram_layout *layout,

@@ -510,5 +510,80 @@ __device__ inline int64_t node_index(const double *x, int n, const MeshTab &tb,
     return (int64_t)c + (rs.kf0 + np.dk + kx) * (int64_t)n;
 }
 
+// ---- limited reconstructions of the bulk shift (Section 3.1, App. A) ----
+//
+// Both are handed to the shift as the cubic
+//   ell(theta) = theta (A + theta (B + theta C)),
+// the integral of q_c from the cell's left node to x_c + theta dx_c, so that
+// ell(1) = M_c.
+
+// PPM mesh weights of cell j from the sizes h_{j-1}, h_j, h_{j+1}, h_{j+2}
+// (App. A with the neighbouring sizes summed, Colella & Woodward Eq. 1.6):
+//   delta_j   = d1 (a_{j+1} - a_j) + d2 (a_j - a_{j-1})
+//   a_{j+1/2} = a_j + e1 (a_{j+1} - a_j) + e2 delta_{j+1} + e3 delta_j
+struct PpmW {
+    double d1, d2, e1, e2, e3;
+};
+
+__device__ inline PpmW ppm_weights(double hm, double h0, double hp, double hpp)
+{
+    PpmW w;
+    const double f = h0 / (hm + h0 + hp);
+    w.d1 = f * (2.0 * hm + h0) / (hp + h0);
+    w.d2 = f * (h0 + 2.0 * hp) / (hm + h0);
+    const double inv = 1.0 / (hm + h0 + hp + hpp);
+    const double w1 = 2.0 * hp * h0 / (h0 + hp) *
+                      ((hm + h0) / (2.0 * h0 + hp) - (hpp + hp) / (2.0 * hp + h0));
+    w.e1 = h0 / (h0 + hp) + w1 * inv;
+    w.e2 = -h0 * (hm + h0) / (2.0 * h0 + hp) * inv;
+    w.e3 = hp * (hp + hpp) / (h0 + 2.0 * hp) * inv;
+    return w;
+}
+
+// Limited slope delta_j: zero at an extremum of the averages, otherwise at
+// most twice either one-sided difference, with the unlimited slope's sign.
+template <typename CT>
+__device__ inline CT ppm_delta(CT qm, CT q0, CT qp, CT d1, CT d2)
+{
+    const CT up = qp - q0, dn = q0 - qm;
+    const CT d = d1 * up + d2 * dn;
+    const CT mag = fmin(fabs(d), (CT)2 * fmin(fabs(up), fabs(dn)));
+    return up * dn <= (CT)0 ? (CT)0 : copysign(mag, d);
+}
+
+// Constrained parabola of a cell (average a, interface values L and R, size
+// h) as the cubic ell(theta).  An extremum is flat; an overshooting side is
+// pulled in until the parabola is monotone.
+template <typename CT>
+__device__ inline void ppm_cubic(CT a, CT L, CT R, CT h, CT &A, CT &B, CT &C)
+{
+    if ((R - a) * (a - L) <= (CT)0) {
+        L = a;
+        R = a;
+    } else {
+        const CT dq = R - L, qa = a - (CT)0.5 * (L + R);
+        const CT d6 = dq * dq * (CT)(1.0 / 6.0);
+        if (dq * qa > d6) L = (CT)3 * a - (CT)2 * R;
+        else if (-d6 > dq * qa) R = (CT)3 * a - (CT)2 * L;
+    }
+    const CT q6 = (CT)6 * a - (CT)3 * (L + R);
+    A = h * L;
+    B = (CT)0.5 * h * (R - L + q6);
+    C = h * q6 * (CT)(-1.0 / 3.0);
+}
+
+// PLM cell (mass M, size h, van Leer slope from the averages and the
+// reciprocal centre gaps) as the cubic ell(theta) with C = 0.
+template <typename CT>
+__device__ inline void plm_cubic(CT qm, CT q0, CT qp, CT gm, CT gp, CT M, CT h,
+                                 CT &A, CT &B)
+{
+    const CT dp = (qp - q0) * gp, dm = (q0 - qm) * gm;
+    const CT sig = (dp * dm <= (CT)0) ? (CT)0 : harmonic2(dp, dm);
+    const CT kap = (CT)0.5 * sig * h * h;
+    A = M - kap;
+    B = kap;
+}
+
 } // namespace dev
 } // namespace ram

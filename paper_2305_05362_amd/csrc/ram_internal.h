@@ -21,6 +21,10 @@ constexpr int kResTile = 1020;
 // masses between the two nodes, with no prefix at all.
 enum ScanMode { kScanF64 = 0, kScanTwoSum = 1, kScanF32 = 2, kSumDirect = 3 };
 
+// Limited reconstructions of the bulk shift (Section 3.1): PLM with the van
+// Leer slope, PPM with the interface values and constraints of App. A.
+enum Recon { kReconPLM = 1, kReconPPM = 2 };
+
 // Mesh-only tables for a mesh shared by every row (built once per call by
 // launch_mesh_prep): cell sizes and their reciprocals, reciprocal centre gaps
 // for the slopes, reciprocal Lagrange denominators of every source cell's
@@ -43,6 +47,10 @@ struct MeshTab {
     const double2 *rrd = nullptr;     // the same in FP64
     const void *crf = nullptr;        // CellRec<float>[n]
     const void *crd = nullptr;        // CellRec<double>[n]
+    // PPM interface weights (d1, d2, e1, e2, e3 of every cell; five arrays of
+    // n back to back), FP64 and FP32
+    const double *ppmd = nullptr;
+    const float *ppmf = nullptr;
 };
 
 // Everything the bulk shift needs about source cell c in one record (one
@@ -178,5 +186,8 @@ hipError_t launch_step_adjoint_shared(const StepAdjArgs &a, bool f64, int order,
                                       hipStream_t stream);
 hipError_t launch_copy(const void *src, void *dst, int64_t bytes,
                        hipStream_t stream);
+// Bulk shift with a limited reconstruction (recon: Recon); a.dv is ignored.
+hipError_t launch_shift_limited(const StepArgs &a, bool f64, int recon,
+                                hipStream_t stream);
 
 } // namespace ram

@@ -561,6 +561,8 @@ struct MeshTabW {
     CellRec<double> *crd;
     float2 *rrf;
     double2 *rrd;
+    double *ppmd;
+    float *ppmf;
 };
 
 template <int P>
@@ -609,6 +611,14 @@ __global__ __launch_bounds__(256) void k_mesh_prep(const double *x, int n, MeshT
         }
         T.crf[j] = rf;
         T.crd[j] = rd;
+        const PpmW pw = ppm_weights(x[wrap_small(j - 1, n) + 1] - x[wrap_small(j - 1, n)], dx,
+                                    x[wrap_small(j + 1, n) + 1] - x[wrap_small(j + 1, n)],
+                                    x[wrap_small(j + 2, n) + 1] - x[wrap_small(j + 2, n)]);
+        const double pv[5] = {pw.d1, pw.d2, pw.e1, pw.e2, pw.e3};
+        for (int k = 0; k < 5; ++k) {
+            T.ppmd[k * n + j] = pv[k];
+            T.ppmf[k * n + j] = (float)pv[k];
+        }
     }
     if (j < T.nb) {
         // lower-bound cell of bucket j, taken a hair below the bucket start so
@@ -695,7 +705,7 @@ size_t mesh_tab_bytes(int64_t n, int order)
     return 3 * al256(8 * n) + 3 * al256(4 * n) + al256(8 * n * 2 * (order + 1)) +
            al256(4 * n * 2 * (order + 1)) + al256(4 * nb) + al256(16 * nb) + al256(16) +
            al256(sizeof(CellRec<float>) * n) + al256(sizeof(CellRec<double>) * n) +
-           al256(8 * n) + al256(16 * n);
+           al256(8 * n) + al256(16 * n) + al256(40 * n) + al256(20 * n);
 }
 
 hipError_t launch_mesh_prep(const double *x, int64_t n, int order, void *mem,
@@ -718,7 +728,9 @@ hipError_t launch_mesh_prep(const double *x, int64_t n, int order, void *mem,
     w.crf = (CellRec<float> *)p; p += al256(sizeof(CellRec<float>) * n);
     w.crd = (CellRec<double> *)p; p += al256(sizeof(CellRec<double>) * n);
     w.rrf = (float2 *)p; p += al256(8 * n);
-    w.rrd = (double2 *)p;
+    w.rrd = (double2 *)p; p += al256(16 * n);
+    w.ppmd = (double *)p; p += al256(40 * n);
+    w.ppmf = (float *)p;
     tab.dx = w.dx; tab.dxinv = w.dxinv; tab.hinv = w.hinv; tab.stc = w.stc;
     tab.dxf = w.dxf; tab.dxinvf = w.dxinvf; tab.hinvf = w.hinvf; tab.stcf = w.stcf;
     tab.bucket = w.bucket;
@@ -729,6 +741,8 @@ hipError_t launch_mesh_prep(const double *x, int64_t n, int order, void *mem,
     tab.crd = w.crd;
     tab.rrf = w.rrf;
     tab.rrd = w.rrd;
+    tab.ppmd = w.ppmd;
+    tab.ppmf = w.ppmf;
     const unsigned grid = (unsigned)((w.nb + 255) / 256);
     switch (order) {
     case 1: hipLaunchKernelGGL(k_mesh_prep<1>, dim3(grid), dim3(256), 0, stream, x, (int)n, w); break;

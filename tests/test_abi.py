@@ -125,3 +125,36 @@ def test_record_and_step_adjoint_argument_errors(lib):
     st = lib.ram_step_adjoint(None, ctypes.byref(L), R.RAM_F64, a, b, d, c,
                               ctypes.c_void_p(0x7000), d, d, 0.1, 5, None, None)
     assert st == R.RAM_E_INVALID_ARG and b"context" in lib.ram_last_error()
+
+
+def test_limited_argument_errors(lib):
+    from paper_2305_05362_amd import _lib as R
+    L = _layout()
+    a, b, c, d = (ctypes.c_void_p(0x1000 * i) for i in (1, 2, 3, 4))
+    # unknown reconstruction
+    st = lib.ram_shift_limited(None, ctypes.byref(L), R.RAM_F64, 0, a, b, c, d, 0.1)
+    assert st == R.RAM_E_UNSUPPORTED and b"recon" in lib.ram_last_error()
+    st = lib.ram_step_limited(None, ctypes.byref(L), R.RAM_F32, 3, a, c, d, None, 0.1, 2)
+    assert st == R.RAM_E_UNSUPPORTED and b"recon" in lib.ram_last_error()
+    # rows shorter than the PPM stencil (5 cells) plus one
+    short = _layout(n_cols=5)
+    st = lib.ram_shift_limited(None, ctypes.byref(short), R.RAM_F64, R.RAM_RECON_PPM,
+                               a, b, c, d, 0.1)
+    assert st == R.RAM_E_INVALID_ARG and b"at least 6" in lib.ram_last_error()
+    # aliasing, non-finite dt, negative steps
+    st = lib.ram_shift_limited(None, ctypes.byref(L), R.RAM_F64, R.RAM_RECON_PLM,
+                               a, a, c, d, 0.1)
+    assert st == R.RAM_E_INVALID_ARG and b"alias" in lib.ram_last_error()
+    st = lib.ram_shift_limited(None, ctypes.byref(L), R.RAM_F64, R.RAM_RECON_PLM,
+                               a, b, c, d, float("nan"))
+    assert st == R.RAM_E_INVALID_ARG and b"dt" in lib.ram_last_error()
+    st = lib.ram_step_limited(None, ctypes.byref(L), R.RAM_F64, R.RAM_RECON_PPM,
+                              a, c, d, None, 0.1, -1)
+    assert st == R.RAM_E_INVALID_ARG and b"n_steps" in lib.ram_last_error()
+    # zero steps succeed without a context; valid arguments then need one
+    st = lib.ram_step_limited(None, ctypes.byref(L), R.RAM_F64, R.RAM_RECON_PPM,
+                              a, c, d, None, 0.1, 0)
+    assert st == R.RAM_OK
+    st = lib.ram_shift_limited(None, ctypes.byref(L), R.RAM_F64, R.RAM_RECON_PPM,
+                               a, b, c, d, 0.1)
+    assert st == R.RAM_E_INVALID_ARG and b"context" in lib.ram_last_error()
