@@ -18,7 +18,8 @@ CPU oracle's throughput on a bounded sample (run on this host's cores).
 
 The FP32 headline forms cumulative differences by summing the window masses
 directly (RAM_SUM_DIRECT); the compensated two-sum and FP64 prefix-sum
-variants and the FP64 path are reported beside it.
+variants and the FP64 path are reported beside it, and so are the limited (monotone)
+reconstructions of the bulk shift, PLM and PPM, on the same disk.
 """
 from __future__ import annotations
 
@@ -197,6 +198,36 @@ def main():
                 "algorithmic_bytes_per_launch": fused_bytes,
                 "kernel": "k_step_sh<float, order 5, direct sums, fused residual>"}
 
+    # --- limited reconstructions (PLM / PPM bulk shift, then the residual) --
+    # two kernels a step: the limited shift and the residual step alone
+    def time_limited(q0, dv, recon, steps, warmup):
+        q = q0.clone()
+        ctx.ram_step_limited(rows, q, v0, dv, wl.dt, recon, steps)     # captures
+        q.copy_(q0)
+        ctx.ram_step_limited(rows, q, v0, dv, wl.dt, recon, warmup)
+        torch.cuda.synchronize()
+        a, b = events()
+        a.record()
+        ctx.ram_step_limited(rows, q, v0, dv, wl.dt, recon, steps)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / 1e3
+
+    limited = {"unit": "Gcell-updates/s", "steps": max(1, args.steps // 4),
+               "shift_algorithmic_bytes_per_cell": {"f32": 8, "f64": 16}}
+    kl = limited["steps"]
+    for name, recon in (("plm", R.RAM_RECON_PLM), ("ppm", R.RAM_RECON_PPM)):
+        for tag, qq, dd, nb in (("f32", q32, dv32, 8.0), ("f64", q64, dv64, 16.0)):
+            t_l = time_limited(qq, dd, recon, kl, args.warmup)
+            hh = torch.empty_like(qq)
+            t_sh = time_kernel(lambda: ctx.ram_shift_limited(rows, qq, hh, v0, wl.dt, recon),
+                               reps)
+            del hh
+            limited[f"{name}_{tag}"] = {
+                "value": round(n_cells * kl / t_l / 1e9, 3),
+                "shift_kernel_us": round(t_sh * 1e6, 2),
+                "shift_hbm_frac": round(nb * n_cells / t_sh / 1e9 / HBM_PEAK_GBS, 4)}
+
     # --- forward + adjoint (checkpointed rollout) ---------------------------
     ka = args.adj_steps
     qa = q32.clone().requires_grad_(True)
@@ -245,6 +276,15 @@ def main():
                       dv32h[pick].astype(np.float64), wl.dt, order, 1)
     got = one.cpu().numpy().reshape(wl.n_rows, n)[pick].reshape(-1).astype(np.float64)
     err1 = float(np.sum(np.abs(got - ref)) / np.sum(np.abs(ref)))
+    for name, recon in (("plm", R.RAM_RECON_PLM), ("ppm", R.RAM_RECON_PPM)):
+        one = q32.clone()
+        ctx.ram_step_limited(rows, one, v0, dv32, wl.dt, recon, 1)
+        torch.cuda.synchronize()
+        ref = oracle.step_recon(sub, q32h[pick].astype(np.float64), wl.v0[pick],
+                                dv32h[pick].astype(np.float64), wl.dt, recon, 1)
+        got = one.cpu().numpy().reshape(wl.n_rows, n)[pick].reshape(-1).astype(np.float64)
+        limited[f"{name}_f32"]["one_step_rel_l1_vs_oracle"] = float(
+            np.sum(np.abs(got - ref)) / np.sum(np.abs(ref)))
     # drift of the FP32 rollout against the FP64 path after the same steps
     q_ref = q64.clone()
     ctx.ram_step(rows, q_ref, v0, dv64, wl.dt, order, args.steps + args.warmup,
@@ -296,6 +336,7 @@ def main():
                   "rollout_rel_l1_vs_fp64_path": drift,
                   "rollout_steps": args.steps + args.warmup},
         "ragged_cfg": ragged,
+        "limited_reconstructions": limited,
         "kernels": kernels,
         "roofline": roofline,
         "cpu_baseline": cpu,

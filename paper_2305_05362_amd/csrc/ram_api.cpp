@@ -300,23 +300,29 @@ std::vector<unsigned char> key_of(const T &...parts)
 // n_steps launches of the bulk-shift kernel (fused with the residual when
 // a.dv is set).  n_steps == 1 writes a.q_out; n_steps > 1 updates a.q_in in
 // place, ping-ponging with `tmp`.  Shared meshes take the specialised kernel
-// after planning the tiles' windows once.
+// after planning the tiles' windows once; recon != 0 (shared meshes only)
+// selects its limited-reconstruction mode, whose window halo is that of order
+// 3 (PLM) or 5 (PPM).
 ram_status launch_steps(ram_ctx *ctx, ram::StepArgs a, ram_dtype dtype,
                         ram_scan scan, int order, int64_t n_steps, void *tmp,
-                        size_t wlo_off, size_t w_off, size_t state_bytes)
+                        size_t wlo_off, size_t w_off, size_t state_bytes,
+                        int recon = 0)
 {
     const bool f64 = dtype == RAM_F64;
     const bool shared = a.rows.has_tab != 0 && a.rows.n_cols > 0;
+    if (recon && !shared) return fail(RAM_E_UNSUPPORTED, "internal: limited step loop needs a shared mesh");
     hipError_t e;
     if (shared) {
         int64_t *wlo = (int64_t *)((char *)ctx->scratch + wlo_off);
         int32_t *w = (int32_t *)((char *)ctx->scratch + w_off);
-        e = ram::launch_plan(a, order, wlo, w, ctx->stream);
+        const int plan_order = recon == 0 ? order : (recon == RAM_RECON_PLM ? 3 : 5);
+        e = ram::launch_plan(a, plan_order, wlo, w, ctx->stream);
         if (e != hipSuccess) return hip_fail(e, "window plan launch");
         a.plan_wlo = wlo;
         a.plan_w = w;
     }
     auto one = [&](const ram::StepArgs &s, hipStream_t st) {
+        if (recon) return ram::launch_step_shared_limited(s, f64, recon, st);
         return shared ? ram::launch_step_shared(s, f64, (int)scan, order, st)
                       : ram::launch_step(s, f64, (int)scan, order, st);
     };
@@ -340,8 +346,8 @@ ram_status launch_steps(ram_ctx *ctx, ram::StepArgs a, ram_dtype dtype,
         if (cur != q) return ram::launch_copy(cur, q, (int64_t)state_bytes, st);
         return hipSuccess;
     };
-    const int64_t extra[4] = {(int64_t)dtype * 16 + (int64_t)scan, order, n_steps,
-                              (int64_t)(intptr_t)tmp ^ (int64_t)state_bytes};
+    const int64_t extra[4] = {(int64_t)dtype * 16 + (int64_t)scan + 256 * (int64_t)recon,
+                              order, n_steps, (int64_t)(intptr_t)tmp ^ (int64_t)state_bytes};
     return run_graphed(ctx, key_of(a, extra), n_steps, loop);
 }
 
@@ -564,8 +570,12 @@ ram_status ram_shift_limited(ram_ctx *ctx, const ram_layout *layout, ram_dtype d
     if (!q_in || !q_out || !v0) return fail(RAM_E_INVALID_ARG, "null q_in, q_out or v0");
     if (q_in == q_out) return fail(RAM_E_INVALID_ARG, "q_in and q_out must not alias");
     if ((st = enter(ctx)) != RAM_OK) return st;
+    const bool shared = layout->edges_shared && layout->n_cols > 0;
     Carve cv;
     RowsPlan rp = plan_rows(cv, layout, ram::step_tile(false), 1);
+    const int64_t nt = tiles_of(layout, rp.tile);
+    const size_t wlo_off = shared ? cv.take(sizeof(int64_t) * nt) : 0;
+    const size_t w_off = shared ? cv.take(2 * sizeof(int32_t) * nt) : 0;
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
     ram::StepArgs a;
     if ((st = make_rows(ctx, layout, edges, rp, a.rows)) != RAM_OK) return st;
@@ -573,6 +583,9 @@ ram_status ram_shift_limited(ram_ctx *ctx, const ram_layout *layout, ram_dtype d
     a.q_out = q_out;
     a.v0 = v0;
     a.dt = dt;
+    if (shared)
+        return launch_steps(ctx, a, dtype, RAM_SUM_DIRECT, 0, 1, nullptr, wlo_off, w_off, 0,
+                            (int)recon);
     hipError_t e = ram::launch_shift_limited(a, dtype == RAM_F64, (int)recon, ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "limited shift launch");
     return RAM_OK;
@@ -593,9 +606,30 @@ ram_status ram_step_limited(ram_ctx *ctx, const ram_layout *layout, ram_dtype dt
     if (n_steps == 0) return RAM_OK;
     if ((st = enter(ctx)) != RAM_OK) return st;
     const size_t state_bytes = elem_size(dtype) * (size_t)layout_cells(layout);
+    if (layout->edges_shared && layout->n_cols > 0) {
+        // one fused kernel a step (limited shift + residual), window plan once
+        Carve cv;
+        const size_t tmp_off = cv.take(state_bytes);
+        RowsPlan rp = plan_rows(cv, layout, ram::step_tile(dv != nullptr), 1);
+        const int64_t nt = tiles_of(layout, rp.tile);
+        const size_t wlo_off = cv.take(sizeof(int64_t) * nt);
+        const size_t w_off = cv.take(2 * sizeof(int32_t) * nt);
+        if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
+        ram::StepArgs a;
+        std::memset(&a, 0, sizeof(a));    // the graph key compares raw bytes
+        if ((st = make_rows(ctx, layout, edges, rp, a.rows)) != RAM_OK) return st;
+        a.q_in = q;
+        a.v0 = v0;
+        a.dv = dv;
+        a.dt = dt;
+        return launch_steps(ctx, a, dtype, RAM_SUM_DIRECT, 0, n_steps,
+                            (char *)ctx->scratch + tmp_off, wlo_off, w_off, state_bytes,
+                            (int)recon);
+    }
     Carve cv;
     const size_t tmp_off = cv.take(state_bytes);
-    // the shift's rows carry the mesh tables; the residual's rows share them
+    // per-row meshes: the limited shift, then the residual kernel; the
+    // shift's rows carry the mesh tables, the residual's rows share them
     RowsPlan rp = plan_rows(cv, layout, ram::step_tile(false), 1);
     RowsPlan rr = plan_rows(cv, layout, ram::kResTile, 0);
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;

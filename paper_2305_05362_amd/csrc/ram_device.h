@@ -585,5 +585,48 @@ __device__ inline void plm_cubic(CT qm, CT q0, CT qp, CT gm, CT gp, CT M, CT h,
     B = kap;
 }
 
+// Stencil half-width of a limited reconstruction (cells a side).
+template <int R> struct LimHalo { static constexpr int lo = R == kReconPLM ? 1 : 2; };
+
+// Partial integral of the limited reconstruction of cell c at xh, from global
+// memory in FP64 (direct path).
+template <typename TQ, int R>
+__device__ __attribute__((noinline)) double lim_partial_global(const double *x,
+                                                               const TQ *q, int n,
+                                                               int c, double xh)
+{
+    constexpr int LO = LimHalo<R>::lo;
+    double qv[2 * LO + 1], h[2 * LO + 2];
+#pragma unroll
+    for (int a = 0; a <= 2 * LO; ++a) qv[a] = (double)q[wrapi(c - LO + a, n)];
+#pragma unroll
+    for (int a = 0; a <= 2 * LO + 1; ++a) {
+        const int m = wrapi(c - LO + a, n);
+        h[a] = x[m + 1] - x[m];
+    }
+    const double h0 = h[LO];
+    const double th = (xh - x[c]) / h0;
+    double A, B, C = 0.0;
+    if constexpr (R == kReconPLM) {
+        // reciprocal centre gaps (c-1, c) and (c, c+1)
+        const double gm = 2.0 / (h[0] + h[1]), gp = 2.0 / (h[1] + h[2]);
+        plm_cubic<double>(qv[0], qv[1], qv[2], gm, gp, qv[1] * h0, h0, A, B);
+    } else {
+        // limited slopes of cells c-1, c, c+1, then the interfaces c-1/2, c+1/2
+        double d[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const PpmW w = ppm_weights(h[k], h[k + 1], h[k + 2], h[k + 3]);
+            d[k] = ppm_delta<double>(qv[k], qv[k + 1], qv[k + 2], w.d1, w.d2);
+        }
+        const PpmW wl = ppm_weights(h[0], h[1], h[2], h[3]);
+        const PpmW wr = ppm_weights(h[1], h[2], h[3], h[4]);
+        const double L = qv[1] + wl.e1 * (qv[2] - qv[1]) + wl.e2 * d[1] + wl.e3 * d[0];
+        const double Rv = qv[2] + wr.e1 * (qv[3] - qv[2]) + wr.e2 * d[2] + wr.e3 * d[1];
+        ppm_cubic<double>(qv[2], L, Rv, h0, A, B, C);
+    }
+    return th * (A + th * (B + th * C));
+}
+
 } // namespace dev
 } // namespace ram

@@ -186,8 +186,14 @@ hipError_t launch_step_adjoint_shared(const StepAdjArgs &a, bool f64, int order,
                                       hipStream_t stream);
 hipError_t launch_copy(const void *src, void *dst, int64_t bytes,
                        hipStream_t stream);
-// Bulk shift with a limited reconstruction (recon: Recon); a.dv is ignored.
+// Bulk shift with a limited reconstruction (recon: Recon) on any layout; a.dv
+// is ignored.
 hipError_t launch_shift_limited(const StepArgs &a, bool f64, int recon,
                                 hipStream_t stream);
+// Shared meshes: the limited shift in the specialised step kernel, fused with
+// the residual when a.dv is set; needs the window plan of order 3 (PLM) or 5
+// (PPM) and the tables.
+hipError_t launch_step_shared_limited(const StepArgs &a, bool f64, int recon,
+                                      hipStream_t stream);
 
 } // namespace ram

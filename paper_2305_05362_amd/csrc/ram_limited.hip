@@ -1,6 +1,8 @@
 // ram_limited.hip -- bulk shift with the limited (monotone) reconstructions of
-// Section 3.1 on gfx950: PLM with the van Leer slope, or PPM with the
-// interface values and constraints of App. A.
+// Section 3.1 on gfx950 (PLM with the van Leer slope, or PPM with the
+// interface values and constraints of App. A), for rows that each have their
+// own mesh.  A mesh shared by every row takes the shared-mesh step kernel's
+// limited mode instead (window plan, tables, fused residual).
 //
 // Same remap as the Lagrange shift (Section 3, Steps 1-3; Eq.
 // mass_shift_algo): destination mass = the whole source cells between the two
@@ -14,9 +16,8 @@
 //   (1) two threads locate the tile's first and last shifted nodes; the source
 //       window is the cells between plus the reconstruction stencil (one cell
 //       a side for PLM, two for PPM);
-//   (2) every node finds its source cell -- bucket index on a shared mesh,
-//       binary search over the window's nodes staged in LDS on per-row meshes
-//       -- and keeps theta in FP64;
+//   (2) every node finds its source cell by a binary search over the window's
+//       nodes staged in LDS, and keeps theta in FP64;
 //   (3) the window's averages, sizes and masses go to LDS (coalesced loads);
 //   (4) every window cell's cubic is formed in LDS: PLM in one pass (slope
 //       from the neighbouring averages), PPM in three (limited slopes, then
@@ -34,8 +35,6 @@ namespace {
 using namespace dev;
 
 constexpr int kWinLim = 1536;     // LDS window capacity, cells
-
-template <int R> struct LimHalo { static constexpr int lo = R == kReconPLM ? 1 : 2; };
 
 template <typename CT>
 struct LimLds {
@@ -69,70 +68,18 @@ struct NodeLoc {
 };
 
 __device__ inline NodeLoc locate_node(const double *x, int n, double len,
-                                      double s, double invlen, bool tab,
-                                      const MeshTab &tb, int e)
+                                      double s, double invlen, int e)
 {
     int kx = 0;
     if (e >= n) { e -= n; kx = 1; }
     NodeLoc r;
-    if (tab) {
-        const RowShift rs = row_shift(s, len, invlen);
-        const NodePos np = node_pos(x[e], rs, x[0], x[n], tb.scal[0], tb.scal[2], tb.nb);
-        const double2 nx = tb.bnext[np.b];
-        int c = cell_from_bucket(tb.bucket[np.b], nx, np.xt);
-        if (np.xt >= nx.y) c = cell_walk(x, n, c, np.xt);
-        r.c = c;
-        r.xh = np.xt;
-        r.g = (int64_t)c + (rs.kf0 + np.dk + kx) * (int64_t)n;
-    } else {
-        double xh;
-        int64_t k;
-        shifted_node_inv(x, n, s, e, invlen, len, xh, k);
-        r.c = find_cell(x, n, xh);
-        r.xh = xh;
-        r.g = (int64_t)r.c + (k + kx) * (int64_t)n;
-    }
+    double xh;
+    int64_t k;
+    shifted_node_inv(x, n, s, e, invlen, len, xh, k);
+    r.c = find_cell(x, n, xh);
+    r.xh = xh;
+    r.g = (int64_t)r.c + (k + kx) * (int64_t)n;
     return r;
-}
-
-// Partial integral of the limited reconstruction of cell c at xh, from global
-// memory in FP64 (direct path).
-template <typename TQ, int R>
-__device__ __attribute__((noinline)) double lim_partial_global(const double *x,
-                                                               const TQ *q, int n,
-                                                               int c, double xh)
-{
-    constexpr int LO = LimHalo<R>::lo;
-    double qv[2 * LO + 1], h[2 * LO + 2];
-#pragma unroll
-    for (int a = 0; a <= 2 * LO; ++a) qv[a] = (double)q[wrapi(c - LO + a, n)];
-#pragma unroll
-    for (int a = 0; a <= 2 * LO + 1; ++a) {
-        const int m = wrapi(c - LO + a, n);
-        h[a] = x[m + 1] - x[m];
-    }
-    const double h0 = h[LO];
-    const double th = (xh - x[c]) / h0;
-    double A, B, C = 0.0;
-    if constexpr (R == kReconPLM) {
-        // reciprocal centre gaps (c-1, c) and (c, c+1)
-        const double gm = 2.0 / (h[0] + h[1]), gp = 2.0 / (h[1] + h[2]);
-        plm_cubic<double>(qv[0], qv[1], qv[2], gm, gp, qv[1] * h0, h0, A, B);
-    } else {
-        // limited slopes of cells c-1, c, c+1, then the interfaces c-1/2, c+1/2
-        double d[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const PpmW w = ppm_weights(h[k], h[k + 1], h[k + 2], h[k + 3]);
-            d[k] = ppm_delta<double>(qv[k], qv[k + 1], qv[k + 2], w.d1, w.d2);
-        }
-        const PpmW wl = ppm_weights(h[0], h[1], h[2], h[3]);
-        const PpmW wr = ppm_weights(h[1], h[2], h[3], h[4]);
-        const double L = qv[1] + wl.e1 * (qv[2] - qv[1]) + wl.e2 * d[1] + wl.e3 * d[0];
-        const double Rv = qv[2] + wr.e1 * (qv[3] - qv[2]) + wr.e2 * d[2] + wr.e3 * d[1];
-        ppm_cubic<double>(qv[2], L, Rv, h0, A, B, C);
-    }
-    return th * (A + th * (B + th * C));
 }
 
 template <typename TQ, int R>
@@ -169,16 +116,13 @@ __global__ __launch_bounds__(kBlock) void k_shift_lim(StepArgs a)
     const TQ *q = (const TQ *)a.q_in + ti.qoff;
     TQ *qo = (TQ *)a.q_out + ti.qoff;
     const double s = a.v0[ti.row] * a.dt;
-    const double x0 = x[0], xN = x[n];
-    const double len = xN - x0;
-    const bool tab = Rw.has_tab != 0;
-    const MeshTab &tb = Rw.tab;
-    const double invlen = tab ? tb.scal[1] : 1.0 / len;
+    const double len = x[n] - x[0];
+    const double invlen = 1.0 / len;
     const int t = threadIdx.x;
 
     // ---- (1) the source window from the tile's end nodes --------------------
     if (t < 2) {
-        const NodeLoc nl = locate_node(x, n, len, s, invlen, tab, tb, t == 0 ? i0 : i0 + nd);
+        const NodeLoc nl = locate_node(x, n, len, s, invlen, t == 0 ? i0 : i0 + nd);
         if (t == 0) s_lo = nl.g - LO;
         else s_hi = nl.g + LO + 1;
     }
@@ -195,7 +139,7 @@ __global__ __launch_bounds__(kBlock) void k_shift_lim(StepArgs a)
     int jc[NI];
     double th[NI];
     bool ok = fits;
-    if (fits && !tab) {
+    if (fits) {
         for (int j = t; j <= W; j += kBlock) {
             int m = base + j, kq = 0;
             if (m >= n) {
@@ -206,9 +150,6 @@ __global__ __launch_bounds__(kBlock) void k_shift_lim(StepArgs a)
             skq[j] = (short)kq;
         }
         __syncthreads();
-    }
-    if (fits) {
-        const RowShift rs = row_shift(s, len, invlen);
 #pragma unroll
         for (int k = 0; k < NI; ++k) {
             const int ei = t + k * kBlock;
@@ -217,46 +158,32 @@ __global__ __launch_bounds__(kBlock) void k_shift_lim(StepArgs a)
             if (ei < NE) {
                 int e = i0 + ei, kx = 0;
                 if (e >= n) { e -= n; kx = 1; }
-                if (tab) {
-                    const NodePos np = node_pos(x[e], rs, x0, xN, tb.scal[0], tb.scal[2], tb.nb);
-                    const double2 nx = tb.bnext[np.b];
-                    int c = cell_from_bucket(tb.bucket[np.b], nx, np.xt);
-                    if (np.xt >= nx.y) c = cell_walk(x, n, c, np.xt);
-                    const int64_t j = (int64_t)c + (rs.kf0 + np.dk + kx) * (int64_t)n - wlo;
-                    if (j >= LO && j <= W - LO - 1) {
-                        jc[k] = (int)j;
-                        th[k] = (np.xt - x[c]) * TabT<double>::dxinv(tb)[c];
-                    } else {
-                        ok = false;
+                double xh;
+                int64_t kk;
+                shifted_node_inv(x, n, s, e, invlen, len, xh, kk);
+                // the last window node at or below the shifted node,
+                // comparing (period, coordinate) pairs exactly
+                const int dk = (int)(kk + kx - pk0);
+                auto le = [&](int j) {
+                    const int kj = skq[j];
+                    return kj < dk || (kj == dk && sxs[j] <= xh);
+                };
+                int lo = 0, hi = W + 1;
+                if (le(0)) {
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (le(mid)) lo = mid;
+                        else hi = mid;
                     }
                 } else {
-                    double xh;
-                    int64_t kk;
-                    shifted_node_inv(x, n, s, e, invlen, len, xh, kk);
-                    // the last window node at or below the shifted node,
-                    // comparing (period, coordinate) pairs exactly
-                    const int dk = (int)(kk + kx - pk0);
-                    auto le = [&](int j) {
-                        const int kj = skq[j];
-                        return kj < dk || (kj == dk && sxs[j] <= xh);
-                    };
-                    int lo = 0, hi = W + 1;
-                    if (le(0)) {
-                        while (hi - lo > 1) {
-                            const int mid = (lo + hi) >> 1;
-                            if (le(mid)) lo = mid;
-                            else hi = mid;
-                        }
-                    } else {
-                        lo = -1;
-                    }
-                    if (lo >= LO && lo <= W - LO - 1) {
-                        const int c = mod_pos(base + lo, n);
-                        jc[k] = lo;
-                        th[k] = (xh - sxs[lo]) / (x[c + 1] - x[c]);
-                    } else {
-                        ok = false;
-                    }
+                    lo = -1;
+                }
+                if (lo >= LO && lo <= W - LO - 1) {
+                    const int c = mod_pos(base + lo, n);
+                    jc[k] = lo;
+                    th[k] = (xh - sxs[lo]) / (x[c + 1] - x[c]);
+                } else {
+                    ok = false;
                 }
             }
         }
@@ -271,15 +198,14 @@ __global__ __launch_bounds__(kBlock) void k_shift_lim(StepArgs a)
         for (int j = t; j < W; j += kBlock) {
             const int m = mod_pos(base + j, n);
             const CT qv = (CT)q[m];
-            const CT hv = tab ? TabT<CT>::dx(tb)[m] : (CT)(x[m + 1] - x[m]);
+            const CT hv = (CT)(x[m + 1] - x[m]);
             sq[j] = qv;
             sh[j] = hv;
             sm[j] = qv * hv;
             if constexpr (R == kReconPLM) {
                 // 1 / centre gap (j, j+1)
-                s2[j] = tab ? TabT<CT>::hinv(tb)[m]
-                            : (CT)(2.0 / ((x[m + 1] - x[m]) +
-                                          (x[mod_pos(m + 1, n) + 1] - x[mod_pos(m + 1, n)])));
+                const int m1 = mod_pos(m + 1, n);
+                s2[j] = (CT)(2.0 / ((x[m + 1] - x[m]) + (x[m1 + 1] - x[m1])));
             }
         }
         __syncthreads();
@@ -293,43 +219,19 @@ __global__ __launch_bounds__(kBlock) void k_shift_lim(StepArgs a)
                 sh[j] = B;           // cell j alone reads its own size
             }
         } else {
-            const CT *pw = nullptr;
-            if (tab) {
-                if constexpr (sizeof(CT) == 8) pw = (const CT *)tb.ppmd;
-                else pw = (const CT *)tb.ppmf;
-            }
             // limited slopes of cells 1 .. W-2
             for (int j = t + 1; j < W - 1; j += kBlock) {
-                CT d1, d2;
-                if (tab) {
-                    const int m = mod_pos(base + j, n);
-                    d1 = pw[m];
-                    d2 = pw[n + m];
-                } else {
-                    const PpmW w = ppm_weights((double)sh[j - 1], (double)sh[j],
-                                               (double)sh[j + 1], 1.0);
-                    d1 = (CT)w.d1;
-                    d2 = (CT)w.d2;
-                }
-                s1[j] = ppm_delta<CT>(sq[j - 1], sq[j], sq[j + 1], d1, d2);
+                const PpmW w = ppm_weights((double)sh[j - 1], (double)sh[j],
+                                           (double)sh[j + 1], 1.0);
+                s1[j] = ppm_delta<CT>(sq[j - 1], sq[j], sq[j + 1], (CT)w.d1, (CT)w.d2);
             }
             __syncthreads();
             // interface values between cells j and j+1, j = 1 .. W-3
             for (int j = t + 1; j < W - 2; j += kBlock) {
-                CT e1, e2, e3;
-                if (tab) {
-                    const int m = mod_pos(base + j, n);
-                    e1 = pw[2 * n + m];
-                    e2 = pw[3 * n + m];
-                    e3 = pw[4 * n + m];
-                } else {
-                    const PpmW w = ppm_weights((double)sh[j - 1], (double)sh[j],
-                                               (double)sh[j + 1], (double)sh[j + 2]);
-                    e1 = (CT)w.e1;
-                    e2 = (CT)w.e2;
-                    e3 = (CT)w.e3;
-                }
-                s2[j] = sq[j] + e1 * (sq[j + 1] - sq[j]) + e2 * s1[j + 1] + e3 * s1[j];
+                const PpmW w = ppm_weights((double)sh[j - 1], (double)sh[j],
+                                           (double)sh[j + 1], (double)sh[j + 2]);
+                s2[j] = sq[j] + (CT)w.e1 * (sq[j + 1] - sq[j]) + (CT)w.e2 * s1[j + 1] +
+                        (CT)w.e3 * s1[j];
             }
             __syncthreads();
             // constrained parabolas of cells 2 .. W-3
@@ -365,8 +267,7 @@ __global__ __launch_bounds__(kBlock) void k_shift_lim(StepArgs a)
                 for (int m = ja; m < jb; ++m) whole += sm[m];
                 const CT mp = whole + (sell[ci + 1] - sell[ci]);
                 const int cell = i0 + ci;
-                if (tab) qo[cell] = (TQ)(mp * TabT<CT>::dxinv(tb)[cell]);
-                else qo[cell] = (TQ)((double)mp / (x[cell + 1] - x[cell]));
+                qo[cell] = (TQ)((double)mp / (x[cell + 1] - x[cell]));
             }
         }
         return;
@@ -377,7 +278,7 @@ __global__ __launch_bounds__(kBlock) void k_shift_lim(StepArgs a)
     for (int k = 0; k < NI; ++k) {
         const int ei = t + k * kBlock;
         if (ei < NE) {
-            const NodeLoc nl = locate_node(x, n, len, s, invlen, tab, tb, i0 + ei);
+            const NodeLoc nl = locate_node(x, n, len, s, invlen, i0 + ei);
             sg[ei] = nl.g;
             sgl[ei] = lim_partial_global<TQ, R>(x, q, n, nl.c, nl.xh);
         }

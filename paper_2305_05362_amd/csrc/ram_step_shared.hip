@@ -21,6 +21,15 @@
 //     sum the masses between two nodes), so no prefix sum is formed and no
 //     cancellation arises;
 //   * tiles away from the row seam skip all periodic index wrapping.
+//
+// The same kernel serves the limited reconstructions of Section 3.1 (R = PLM
+// or PPM, direct sums only): after the window masses are stored, every window
+// cell's limited profile is reduced in LDS to its partial-integral cubic
+// ell(theta) (PLM: the slope term kappa = sigma dx^2 / 2; PPM: the limited
+// slopes, the interface values, then the constrained parabola's coefficients),
+// and each node evaluates its cell's cubic instead of Lagrange weights.  P is
+// then the Lagrange order whose stencil halo matches (3 for PLM, 5 for PPM),
+// which is what the window plan is made for.
 #include "ram_device.h"
 
 #include <type_traits>
@@ -38,11 +47,12 @@ constexpr int kPad = 8;                         // residual arrays: halo slack
 // from the (cache-resident) table, which keeps its LDS at four blocks a CU.
 template <typename CT> struct StageRR { static constexpr bool on = sizeof(CT) == 4; };
 
-template <typename M, typename A, typename CT, bool kDirect>
+template <typename M, typename A, typename CT, bool kDirect, int NX = 0>
 struct ShLds {
     using CT2 = typename TabT<CT>::T2;
+    // NX: window arrays of a limited reconstruction beside the masses
     static constexpr size_t win =
-        sizeof(M) * kWinSh + (kDirect ? 0 : sizeof(A) * (kWinSh + 1));
+        sizeof(M) * kWinSh * (1 + NX) + (kDirect ? 0 : sizeof(A) * (kWinSh + 1));
     static constexpr size_t res =
         (2 * sizeof(CT) + (StageRR<CT>::on ? sizeof(CT2) : 0)) * (kStepNodes + kPad);
     static constexpr size_t nodes = sizeof(int64_t) * kStepNodes;
@@ -88,16 +98,19 @@ __device__ inline int wrap1(int j, int n)
     return j < 0 ? j + n : (j >= n ? j - n : j);
 }
 
-template <typename TQ, int P, int S, int H>
+template <typename TQ, int P, int S, int H, int RECON = 0>
 __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
 {
     constexpr bool kDirect = S == kSumDirect;
+    constexpr bool kLim = RECON != 0;
+    static_assert(!kLim || (kDirect && P == (RECON == kReconPLM ? 3 : 5)),
+                  "limited reconstructions: direct sums, stencil halo of order 3 / 5");
     using AC = Acc<kDirect ? kScanF64 : S>;
     using M = typename std::conditional<kDirect, TQ, typename AC::M>::type;
     using A = typename AC::A;
     using CT = TQ;                       // arithmetic after the prefix sums
     using CT2 = typename TabT<CT>::T2;
-    using L = ShLds<M, A, CT, kDirect>;
+    using L = ShLds<M, A, CT, kDirect, kLim ? 3 : 0>;
     constexpr int LO = (P - 1) / 2;
     constexpr int NI = kItems;
     constexpr int WCAP = kWinSh;
@@ -113,6 +126,12 @@ __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
     CT *sq = (CT *)su;                               // shifted state
     CT *sf = sq + (kStepNodes + kPad);               // face fluxes
     CT2 *srr = (CT2 *)(sf + (kStepNodes + kPad));    // (dx, 1/gap) per cell
+    // limited reconstructions, beside the window masses:
+    //   PLM  sx1 averages, sx2 1/centre gap (j, j+1), sx3 kappa
+    //   PPM  sx1 averages (then C), sx2 limited slopes (then A), sx3 interfaces
+    CT *sx1 = (CT *)(su + sizeof(M) * WCAP);
+    CT *sx2 = sx1 + WCAP;
+    CT *sx3 = sx2 + WCAP;
 
     const Rows &R = a.rows;
     const MeshTab &tb = R.tab;
@@ -154,6 +173,8 @@ __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
     const int base = a.plan_w[R.n_tiles + blockIdx.x];   // wlo mod n
     const bool wsmall = W + base <= 2 * n;
     M wq[kWinRegs], wd[kWinRegs];
+    int wm[kWinRegs];                    // limited: the window cells' row index
+    CT wg[kWinRegs];                     // PLM: 1 / centre gap (j, j+1)
 #pragma unroll
     for (int r = 0; r < kWinRegs; ++r) {
         const int j = t + r * kBlock;
@@ -163,12 +184,18 @@ __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
             else mm = wrap_small(mm, n);
             wq[r] = (M)q[mm];
             wd[r] = TabT<M>::dx(tb)[mm];
+            if constexpr (kLim) wm[r] = mm;
+            if constexpr (RECON == kReconPLM) wg[r] = TabT<CT>::hinv(tb)[mm];
         }
     }
 #pragma unroll
     for (int r = 0; r < kWinRegs; ++r) {
         const int j = t + r * kBlock;
-        if (j < W) sm[j] = wq[r] * wd[r];
+        if (j < W) {
+            sm[j] = wq[r] * wd[r];
+            if constexpr (kLim) sx1[j] = wq[r];
+            if constexpr (RECON == kReconPLM) sx2[j] = wg[r];
+        }
     }
     // ---- (A) shifted nodes: source index and stencil weights -------------
     // Direct sums: the window masses are visible after one barrier, so each
@@ -182,6 +209,56 @@ __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
     if (t == 0) s_flag = W > 0 ? 1 : 0;
     if constexpr (kDirect) {
         __syncthreads();
+        if constexpr (RECON == kReconPLM) {
+            // kappa = sigma dx^2 / 2 of window cells 1 .. W-2
+#pragma unroll
+            for (int r = 0; r < kWinRegs; ++r) {
+                const int j = t + r * kBlock;
+                if (j >= 1 && j < W - 1) {
+                    const CT dp = (sx1[j + 1] - wq[r]) * sx2[j];
+                    const CT dm = (wq[r] - sx1[j - 1]) * sx2[j - 1];
+                    const CT sig = (dp * dm <= (CT)0) ? (CT)0 : harmonic2(dp, dm);
+                    sx3[j] = (CT)0.5 * sig * wd[r] * wd[r];
+                }
+            }
+            __syncthreads();
+        } else if constexpr (RECON == kReconPPM) {
+            const CT *pw;
+            if constexpr (sizeof(CT) == 8) pw = (const CT *)tb.ppmd;
+            else pw = (const CT *)tb.ppmf;
+            // limited slopes of window cells 1 .. W-2
+#pragma unroll
+            for (int r = 0; r < kWinRegs; ++r) {
+                const int j = t + r * kBlock;
+                if (j >= 1 && j < W - 1)
+                    sx2[j] = ppm_delta<CT>(sx1[j - 1], wq[r], sx1[j + 1], pw[wm[r]],
+                                           pw[n + wm[r]]);
+            }
+            __syncthreads();
+            // interface values between cells j and j+1, j = 1 .. W-3
+#pragma unroll
+            for (int r = 0; r < kWinRegs; ++r) {
+                const int j = t + r * kBlock;
+                if (j >= 1 && j < W - 2) {
+                    const int m = wm[r];
+                    sx3[j] = wq[r] + pw[2 * n + m] * (sx1[j + 1] - wq[r]) +
+                             pw[3 * n + m] * sx2[j + 1] + pw[4 * n + m] * sx2[j];
+                }
+            }
+            __syncthreads();
+            // constrained parabolas of cells 2 .. W-3: A and C (B = M - A - C)
+#pragma unroll
+            for (int r = 0; r < kWinRegs; ++r) {
+                const int j = t + r * kBlock;
+                if (j >= 2 && j < W - 2) {
+                    CT pa, pb, pc;
+                    ppm_cubic<CT>(wq[r], sx3[j - 1], sx3[j], wd[r], pa, pb, pc);
+                    sx2[j] = pa;           // the slopes are dead
+                    sx1[j] = pc;           // so are the averages
+                }
+            }
+            __syncthreads();
+        }
         NodePos np[NI];
         int cb[NI];
         double2 nx[NI];
@@ -199,13 +276,30 @@ __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
                 int c = cell_from_bucket(cb[k], nx[k], np[k].xt);
                 if (np[k].xt >= nx[k].y) c = cell_walk(x, n, c, np[k].xt);
                 CT wk[P + 1];
-                rec_weights<CT, P>(RecT<CT>::get(tb)[c], np[k].xt, wk);
+                CT tt = (CT)0;
+                if constexpr (kLim) {
+                    const CellRec<CT> &rc = RecT<CT>::get(tb)[c];
+                    tt = (CT)((np[k].xt - rc.xc) * rc.dxinv);
+                } else {
+                    rec_weights<CT, P>(RecT<CT>::get(tb)[c], np[k].xt, wk);
+                }
                 const int j = c + np[k].dk * n + kxn[k] + jbase;
                 jc[k] = j;
                 const bool in = j >= LO && j + P - LO <= W;
                 ok = ok && in;
                 CT ell = (CT)0;
-                if (in) {
+                if (kLim && in) {
+                    // the cell's cubic: PLM theta (M - kappa + theta kappa),
+                    // PPM theta (A + theta (B + theta C))
+                    if constexpr (RECON == kReconPLM) {
+                        const CT kap = sx3[j];
+                        ell = tt * ((CT)sm[j] - kap + tt * kap);
+                    } else {
+                        const CT pa = sx2[j], pc = sx1[j];
+                        const CT pb = (CT)sm[j] - pa - pc;
+                        ell = tt * (pa + tt * (pb + tt * pc));
+                    }
+                } else if (in) {
                     // C(j-lo+b) - C(j): the masses between, summed outward
                     CT up = (CT)0, dn = (CT)0;
 #pragma unroll
@@ -297,8 +391,20 @@ __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
             if (ei < NE) {
                 const int64_t g = (int64_t)jc[k] + wlo;
                 sg[ei] = g;
-                sell[ei] = (CT)direct_partial<TQ, P>(x, q, n, len, s, invlen,
-                                                     i0 - H + ei, g);
+                if constexpr (kLim) {
+                    // the node's cell and wrapped position as the search found
+                    // them, the profile from global memory
+                    int e = i0 - H + ei;
+                    e = e < 0 ? e + n : (e >= n ? e - n : e);
+                    const NodePos np = node_pos(x[e], rs, x0, xN, bsc, bx0, tb.nb);
+                    const double2 nx = tb.bnext[np.b];
+                    int c = cell_from_bucket(tb.bucket[np.b], nx, np.xt);
+                    if (np.xt >= nx.y) c = cell_walk(x, n, c, np.xt);
+                    sell[ei] = (CT)lim_partial_global<TQ, RECON>(x, q, n, c, np.xt);
+                } else {
+                    sell[ei] = (CT)direct_partial<TQ, P>(x, q, n, len, s, invlen,
+                                                         i0 - H + ei, g);
+                }
             }
         }
     }
@@ -433,7 +539,27 @@ hipError_t step_sh_order(const StepArgs &a, int scan, int order, hipStream_t st)
     }
 }
 
+template <typename TQ, int R>
+hipError_t step_sh_lim(const StepArgs &a, hipStream_t st)
+{
+    constexpr int P = R == kReconPLM ? 3 : 5;
+    const dim3 g((unsigned)a.rows.n_tiles), b(kBlock);
+    if (a.dv) hipLaunchKernelGGL((k_step_sh<TQ, P, kSumDirect, 2, R>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((k_step_sh<TQ, P, kSumDirect, 0, R>), g, b, 0, st, a);
+    return hipGetLastError();
+}
+
 } // namespace
+
+hipError_t launch_step_shared_limited(const StepArgs &a, bool f64, int recon,
+                                      hipStream_t stream)
+{
+    if (a.rows.n_tiles <= 0) return hipSuccess;
+    if (f64) return recon == kReconPLM ? step_sh_lim<double, kReconPLM>(a, stream)
+                                       : step_sh_lim<double, kReconPPM>(a, stream);
+    return recon == kReconPLM ? step_sh_lim<float, kReconPLM>(a, stream)
+                              : step_sh_lim<float, kReconPPM>(a, stream);
+}
 
 hipError_t launch_plan(const StepArgs &a, int order, int64_t *wlo, int32_t *w,
                        hipStream_t stream)

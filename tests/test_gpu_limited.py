@@ -6,9 +6,11 @@ oracle.
   minimum length, shifts below a cell, of many cells and of many periods
   either way, and a tile whose window overflows the on-chip buffer (direct
   path); FP32 <= 1e-6 against the oracle run on the same FP32 inputs;
-* ram_step_limited: equals ram_shift_limited then ram_residual bit for bit,
-  and matches the oracle's split step over 1 and 5 steps (the 5-step loop is
-  replayed from its captured graph on a second call);
+* ram_step_limited: without residual it is ram_shift_limited bit for bit; with
+  it, ram_shift_limited then ram_residual (bit for bit on per-row meshes, to
+  rounding where a shared mesh fuses the two into one kernel); it matches the
+  oracle's split step over 1 and 5 steps (the 5-step loop is replayed from its
+  captured graph on a second call);
 * the 2048 x 16384 polar disk in the configuration the benchmark times, on
   sampled rows (FP32 and FP64), plus every row's mass conserved and no value
   outside the input's range on a uniform mesh.
@@ -104,18 +106,32 @@ def test_shift_limited_fp32(kind, recon):
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("recon", RECONS)
-def test_step_limited_is_shift_then_residual(recon, dtype):
-    wl = _cases()["polar_tiles"]()
+@pytest.mark.parametrize("kind", ["polar_tiles", "ragged"])
+def test_step_limited_is_shift_then_residual(kind, recon, dtype):
+    wl = _cases()[kind]()
     rows = R.Rows.from_workload(wl, DEV)
     v0, dv = dev(wl.v0), dev(wl.dv, dtype)
-    q = dev(wl.q0, dtype)
-    R.ram_step_limited(rows, q, v0, dv, wl.dt, recon, 1)
-    half = torch.empty_like(q)
-    want = torch.empty_like(q)
-    R.ram_shift_limited(rows, dev(wl.q0, dtype), half, v0, wl.dt, recon)
+    q0 = dev(wl.q0, dtype)
+    half = torch.empty_like(q0)
+    want = torch.empty_like(q0)
+    R.ram_shift_limited(rows, q0, half, v0, wl.dt, recon)
     R.ram_residual(rows, half, want, dv, wl.dt)
+    # a step without residual is the shift, bit for bit
+    q = q0.clone()
+    R.ram_step_limited(rows, q, v0, None, wl.dt, recon, 1)
     torch.cuda.synchronize()
-    assert torch.equal(q, want)
+    assert torch.equal(q, half)
+    q = q0.clone()
+    R.ram_step_limited(rows, q, v0, dv, wl.dt, recon, 1)
+    torch.cuda.synchronize()
+    if kind == "ragged":
+        # per-row meshes: the shift kernel, then the residual kernel
+        assert torch.equal(q, want)
+    else:
+        # a shared mesh fuses the residual into the shift kernel (its own
+        # rounding order)
+        err = rel_l1(q.cpu().numpy().astype(np.float64), want.cpu().numpy().astype(np.float64))
+        assert err <= (1e-15 if dtype == torch.float64 else 1e-7), err
 
 
 @pytest.mark.parametrize("recon", RECONS)
