@@ -48,6 +48,9 @@ def parse():
     p.add_argument("--fp64-steps", type=int, default=200)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--items", type=int, default=0,
+                   help="shifted nodes per thread of the headline kernel (2..5); "
+                        "0: let the autotuner choose (untimed, before the timed region)")
     p.add_argument("--profile-pass", action="store_true",
                    help="short run for hardware-counter passes: the headline kernel "
                         "for --steps steps, the PPM step kernel for --steps steps, "
@@ -60,13 +63,16 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_sh_f32_direct_polar2048x16
 TRAFFIC_FILE_PPM = os.path.join(ROOT, "profiles", "k_step_sh_f32_ppm_polar2048x16384_traffic.md")
 
 
-def load_traffic(path=TRAFFIC_FILE):
+def load_traffic(path, kernel):
     """Measured HBM bytes per launch of a step kernel, if the committed
-    counter summary was taken on the current kernel sources."""
+    counter summary was taken on the current kernel sources and on this
+    instantiation (`kernel`, as rocprofv3 names it)."""
     from paper_2305_05362_amd.build import kernel_digest
     from paper_2305_05362_amd.rocprof_summary import read_traffic
     rec = read_traffic(path)
     if not rec or rec.get("source_digest") != kernel_digest():
+        return None
+    if rec.get("kernel_name", "").split("::")[-1] != kernel:
         return None
     return rec
 
@@ -131,6 +137,19 @@ def main():
         torch.cuda.synchronize()
         return a.elapsed_time(b) / 1e3 / reps
 
+    # --- launch schedule of the headline kernel: autotuned, or as given ----
+    from paper_2305_05362_amd.tune import tuned_schedule
+    if args.items:
+        ctx.set_schedule(args.items)
+        items, tune_us = args.items, {}
+    else:
+        items, tune_us, _ = tuned_schedule(ctx, rows, q32, v0, dv32, wl.dt, order,
+                                           R.RAM_SUM_DIRECT, cache_path=None)
+    schedule = {"items_per_thread": items,
+                "tile_cells": 256 * items - 5,
+                "tuned_us_per_step": {str(k): round(v, 2) for k, v in tune_us.items()},
+                "how": "given" if args.items else "autotuned before the timed region"}
+
     if args.profile_pass:
         q = q32.clone()
         ctx.ram_step(rows, q, v0, dv32, wl.dt, order, args.steps, R.RAM_SUM_DIRECT)
@@ -140,7 +159,7 @@ def main():
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"profile_pass": True, "steps": args.steps,
+        print(json.dumps({"profile_pass": True, "steps": args.steps, "items": items,
                           "copy_bytes": COPY_BYTES}), flush=True)
         return
 
@@ -194,13 +213,15 @@ def main():
                "shift_only_algorithmic_bytes_per_cell": 8,
                "residual_only_algorithmic_bytes_per_cell": 12}
     achieved = fused_bytes / t_fused / 1e9
-    tr = load_traffic()
+    head_kernel = f"k_step_sh<float, 5, 3, 2, 0, {items}>"
+    tr = load_traffic(TRAFFIC_FILE, head_kernel)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if tr is None else round(tr["traffic_bytes_per_launch"]),
                 "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled)",
                 "algorithmic_bytes_per_launch": fused_bytes,
-                "kernel": "k_step_sh<float, order 5, direct sums, fused residual>"}
+                "kernel": head_kernel + " (FP32, order 5, direct sums, fused residual, "
+                                        f"{items} nodes per thread)"}
 
     # --- limited reconstructions (PLM / PPM bulk shift, then the residual) --
     # two kernels a step: the limited shift and the residual step alone
@@ -223,7 +244,7 @@ def main():
                "step_algorithmic_bytes_per_cell": {"f32": 12, "f64": 24},
                "kernel": "k_step_sh<T, 3 (PLM) / 5 (PPM), direct sums, fused residual, recon>"}
     kl = limited["steps"]
-    tr_ppm = load_traffic(TRAFFIC_FILE_PPM)
+    tr_ppm = load_traffic(TRAFFIC_FILE_PPM, "k_step_sh<float, 5, 3, 2, 2, 4>")
     for name, recon in (("plm", R.RAM_RECON_PLM), ("ppm", R.RAM_RECON_PPM)):
         for tag, qq, dd, nb in (("f32", q32, dv32, 12.0), ("f64", q64, dv64, 24.0)):
             t_l = time_limited(qq, dd, recon, kl, args.warmup)
@@ -347,6 +368,7 @@ def main():
         "error": {"one_step_rel_l1_vs_oracle": err1,
                   "rollout_rel_l1_vs_fp64_path": drift,
                   "rollout_steps": args.steps + args.warmup},
+        "schedule": schedule,
         "ragged_cfg": ragged,
         "limited_reconstructions": limited,
         "kernels": kernels,

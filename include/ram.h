@@ -96,6 +96,25 @@ typedef struct ram_ctx ram_ctx;
 ram_status ram_create(ram_ctx **ctx, int device, void *stream);
 /* Release the context and its scratch (after waiting for its stream). */
 ram_status ram_destroy(ram_ctx *ctx);
+/* Launch schedule of the shared-mesh step kernel with RAM_SUM_DIRECT (the
+ * library's fastest path): each workgroup of 256 threads shifts
+ * 256 * items_per_thread nodes, i.e. a tile of 256 * items_per_thread - 1
+ * destination cells (4 fewer when the residual step is fused in).  Larger tiles
+ * mean fewer workgroups and less overlap between neighbouring tiles' windows,
+ * smaller ones more waves in flight; the best choice depends on the row length
+ * and the GPU, which is what an autotuner measures.  0 restores the default
+ * (4); other values than 0 and 2..5 give RAM_E_UNSUPPORTED.  The schedule is
+ * per context and applies to later ram_shift, ram_step and ram_step_record
+ * calls on shared meshes with RAM_SUM_DIRECT.  Every cell goes through the
+ * same operations under any schedule; results agree to rounding, not bit for
+ * bit (each variant is compiled on its own, and the compiler may fuse
+ * multiply-adds differently in each). */
+typedef struct {
+    int32_t items_per_thread;
+} ram_schedule;
+ram_status ram_set_schedule(ram_ctx *ctx, const ram_schedule *sched);
+ram_status ram_get_schedule(const ram_ctx *ctx, ram_schedule *sched);
+
 /* Change the stream later calls are issued on. */
 ram_status ram_set_stream(ram_ctx *ctx, void *stream);
 /* Wait until every call issued so far on the context's stream has finished;
@@ -203,6 +222,18 @@ ram_status ram_step_adjoint(ram_ctx *ctx, const ram_layout *layout,
                             const void *qbar_out, void *qbar_in,
                             const double *edges, const double *v0, double dt,
                             int order, void *dvbar_accum, double *v0bar_accum);
+
+/* Per-row checks of a state (not part of a step): for every row r, in FP64
+ * whatever the state's dtype,
+ *   out[3r]     = sum_i Q_i dx_i, the row's mass (Eq. Qmass_i summed; the
+ *                 shift and the residual conserve it, Eq. qmass_total),
+ *   out[3r + 1] = sum_i |Q_i - Qref_i| dx_i (0 when q_ref == NULL),
+ *   out[3r + 2] = max_i |Q_i|.
+ * q and q_ref: `dtype`, n_cells each; out: device, 3 * n_rows doubles.  The
+ * summation order is fixed, so results are reproducible. */
+ram_status ram_row_norms(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
+                         const void *q, const void *q_ref, const double *edges,
+                         double *out);
 
 /* Host-side check of the inputs (synchronous; copies to the host): strictly
  * increasing finite nodes (RAM_E_MESH), and when dv != NULL the residual

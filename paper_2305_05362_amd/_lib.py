@@ -52,6 +52,10 @@ class Layout(ctypes.Structure):
                 ("edges_shared", ctypes.c_int32)]
 
 
+class Schedule(ctypes.Structure):
+    _fields_ = [("items_per_thread", ctypes.c_int32)]
+
+
 _lib = None
 
 
@@ -82,6 +86,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ram_validate": [P, LP, I, P, P, D],
         "ram_shift_limited": [P, LP, I, I, P, P, P, P, D],
         "ram_step_limited": [P, LP, I, I, P, P, P, P, D, I64],
+        "ram_row_norms": [P, LP, I, P, P, P, P],
+        "ram_set_schedule": [P, ctypes.POINTER(Schedule)],
+        "ram_get_schedule": [P, ctypes.POINTER(Schedule)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -198,6 +205,16 @@ class Context:
             _dev_ptr(v0, torch.float64, "v0"), float(dt), int(order)))
         return q_out
 
+    def set_schedule(self, items_per_thread: int):
+        """Shifted nodes per thread of the shared-mesh direct-sum step kernel
+        (2..5; 0 = the default)."""
+        check(self._lib.ram_set_schedule(self._h, ctypes.byref(Schedule(int(items_per_thread)))))
+
+    def get_schedule(self) -> int:
+        sc = Schedule(0)
+        check(self._lib.ram_get_schedule(self._h, ctypes.byref(sc)))
+        return int(sc.items_per_thread)
+
     def ram_shift_limited(self, rows: Rows, q_in, q_out, v0, dt: float, recon: int):
         self._stream()
         check(self._lib.ram_shift_limited(
@@ -216,6 +233,18 @@ class Context:
             _dev_ptr(v0, torch.float64, "v0"), _dev_ptr(dv, q.dtype, "dv"),
             float(dt), int(n_steps)))
         return q
+
+    def ram_row_norms(self, rows: Rows, q, q_ref=None, out=None):
+        """Per-row (mass, dx-weighted L1 distance to q_ref, max |q|), FP64
+        tensor of shape [n_rows, 3] on q's device."""
+        self._stream()
+        if out is None:
+            out = torch.empty((rows.n_rows, 3), dtype=torch.float64, device=q.device)
+        check(self._lib.ram_row_norms(
+            self._h, ctypes.byref(rows.layout), _dtype_code(q), _dev_ptr(q, q.dtype, "q"),
+            _dev_ptr(q_ref, q.dtype, "q_ref"), _dev_ptr(rows.edges, torch.float64, "edges"),
+            _dev_ptr(out, torch.float64, "out")))
+        return out
 
     def ram_residual(self, rows: Rows, q_in, q_out, dv, dt: float):
         self._stream()
@@ -328,6 +357,10 @@ def ram_shift_limited(rows, q_in, q_out, v0, dt, recon):
 
 def ram_step_limited(rows, q, v0, dv, dt, recon, n_steps):
     return context(q.device.index).ram_step_limited(rows, q, v0, dv, dt, recon, n_steps)
+
+
+def ram_row_norms(rows, q, q_ref=None, out=None):
+    return context(q.device.index).ram_row_norms(rows, q, q_ref, out)
 
 
 def ram_residual(rows, q_in, q_out, dv, dt):

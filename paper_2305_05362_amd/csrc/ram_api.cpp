@@ -27,6 +27,9 @@ struct ram_ctx {
         hipGraphExec_t exec = nullptr;
     };
     std::vector<Graph> graphs;          // most recently used first
+    // schedule of the shared-mesh step kernel with direct sums: shifted
+    // nodes per thread (ram_set_schedule)
+    int items = ram::kItems;
 };
 
 namespace {
@@ -225,6 +228,14 @@ ram_status make_rows(ram_ctx *ctx, const ram_layout *L, const double *edges,
     return RAM_OK;
 }
 
+// Shifted nodes per thread the step kernel runs with: the context's schedule
+// for a shared mesh with direct sums, else the default.
+int sched_items(const ram_ctx *ctx, const ram_layout *L, ram_scan scan)
+{
+    const bool shared = L->edges_shared && L->n_cols > 0;
+    return (shared && scan == RAM_SUM_DIRECT) ? ctx->items : ram::kItems;
+}
+
 int64_t tiles_of(const ram_layout *L, int tile)
 {
     if (L->n_cols > 0) return L->n_rows * ((L->n_cols + tile - 1) / tile);
@@ -306,7 +317,7 @@ std::vector<unsigned char> key_of(const T &...parts)
 ram_status launch_steps(ram_ctx *ctx, ram::StepArgs a, ram_dtype dtype,
                         ram_scan scan, int order, int64_t n_steps, void *tmp,
                         size_t wlo_off, size_t w_off, size_t state_bytes,
-                        int recon = 0)
+                        int items, int recon = 0)
 {
     const bool f64 = dtype == RAM_F64;
     const bool shared = a.rows.has_tab != 0 && a.rows.n_cols > 0;
@@ -323,7 +334,7 @@ ram_status launch_steps(ram_ctx *ctx, ram::StepArgs a, ram_dtype dtype,
     }
     auto one = [&](const ram::StepArgs &s, hipStream_t st) {
         if (recon) return ram::launch_step_shared_limited(s, f64, recon, st);
-        return shared ? ram::launch_step_shared(s, f64, (int)scan, order, st)
+        return shared ? ram::launch_step_shared(s, f64, (int)scan, order, items, st)
                       : ram::launch_step(s, f64, (int)scan, order, st);
     };
     if (n_steps == 1 && a.q_out) {
@@ -346,7 +357,8 @@ ram_status launch_steps(ram_ctx *ctx, ram::StepArgs a, ram_dtype dtype,
         if (cur != q) return ram::launch_copy(cur, q, (int64_t)state_bytes, st);
         return hipSuccess;
     };
-    const int64_t extra[4] = {(int64_t)dtype * 16 + (int64_t)scan + 256 * (int64_t)recon,
+    const int64_t extra[4] = {(int64_t)dtype * 16 + (int64_t)scan + 256 * (int64_t)recon +
+                                  4096 * (int64_t)items,
                               order, n_steps, (int64_t)(intptr_t)tmp ^ (int64_t)state_bytes};
     return run_graphed(ctx, key_of(a, extra), n_steps, loop);
 }
@@ -447,6 +459,25 @@ ram_status ram_destroy(ram_ctx *ctx)
     return RAM_OK;
 }
 
+ram_status ram_set_schedule(ram_ctx *ctx, const ram_schedule *sched)
+{
+    if (!ctx) return fail(RAM_E_INVALID_ARG, "null context");
+    if (!sched) return fail(RAM_E_INVALID_ARG, "null schedule");
+    const int items = sched->items_per_thread == 0 ? ram::kItems : sched->items_per_thread;
+    if (!ram::valid_items(items))
+        return fail(RAM_E_UNSUPPORTED, "items_per_thread must be 0 or 2..5 (got %d)",
+                    (int)sched->items_per_thread);
+    ctx->items = items;
+    return RAM_OK;
+}
+
+ram_status ram_get_schedule(const ram_ctx *ctx, ram_schedule *sched)
+{
+    if (!ctx || !sched) return fail(RAM_E_INVALID_ARG, "null context or schedule");
+    sched->items_per_thread = ctx->items;
+    return RAM_OK;
+}
+
 ram_status ram_set_stream(ram_ctx *ctx, void *stream)
 {
     if (!ctx) return fail(RAM_E_INVALID_ARG, "null context");
@@ -478,8 +509,9 @@ ram_status ram_shift(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
     if (!q_in || !q_out || !v0) return fail(RAM_E_INVALID_ARG, "null q_in, q_out or v0");
     if (q_in == q_out) return fail(RAM_E_INVALID_ARG, "q_in and q_out must not alias");
     if ((st = enter(ctx)) != RAM_OK) return st;
+    const int items = sched_items(ctx, layout, scan);
     Carve cv;
-    RowsPlan rp = plan_rows(cv, layout, ram::step_tile(false), order);
+    RowsPlan rp = plan_rows(cv, layout, ram::step_tile_for(items, false), order);
     const int64_t nt = tiles_of(layout, rp.tile);
     const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(2 * sizeof(int32_t) * nt);
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
@@ -489,7 +521,8 @@ ram_status ram_shift(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
     a.q_out = q_out;
     a.v0 = v0;
     a.dt = dt;
-    if ((st = launch_steps(ctx, a, dtype, scan, order, 1, nullptr, wlo_off, w_off, 0)) != RAM_OK)
+    if ((st = launch_steps(ctx, a, dtype, scan, order, 1, nullptr, wlo_off, w_off, 0,
+                           items)) != RAM_OK)
         return st;
     return RAM_OK;
 }
@@ -539,7 +572,8 @@ ram_status ram_step(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
     const size_t state_bytes = elem_size(dtype) * (size_t)layout_cells(layout);
     Carve cv;
     const size_t tmp_off = cv.take(state_bytes);
-    RowsPlan rp = plan_rows(cv, layout, ram::step_tile(dv != nullptr), order);
+    const int items = sched_items(ctx, layout, scan);
+    RowsPlan rp = plan_rows(cv, layout, ram::step_tile_for(items, dv != nullptr), order);
     const int64_t nt = tiles_of(layout, rp.tile);
     const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(2 * sizeof(int32_t) * nt);
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
@@ -552,7 +586,7 @@ ram_status ram_step(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
     a.dt = dt;
     void *tmp = (char *)ctx->scratch + tmp_off;
     if ((st = launch_steps(ctx, a, dtype, scan, order, n_steps, tmp, wlo_off, w_off,
-                           state_bytes)) != RAM_OK)
+                           state_bytes, items)) != RAM_OK)
         return st;
     return RAM_OK;
 }
@@ -585,7 +619,7 @@ ram_status ram_shift_limited(ram_ctx *ctx, const ram_layout *layout, ram_dtype d
     a.dt = dt;
     if (shared)
         return launch_steps(ctx, a, dtype, RAM_SUM_DIRECT, 0, 1, nullptr, wlo_off, w_off, 0,
-                            (int)recon);
+                            ram::kItems, (int)recon);
     hipError_t e = ram::launch_shift_limited(a, dtype == RAM_F64, (int)recon, ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "limited shift launch");
     return RAM_OK;
@@ -624,7 +658,7 @@ ram_status ram_step_limited(ram_ctx *ctx, const ram_layout *layout, ram_dtype dt
         a.dt = dt;
         return launch_steps(ctx, a, dtype, RAM_SUM_DIRECT, 0, n_steps,
                             (char *)ctx->scratch + tmp_off, wlo_off, w_off, state_bytes,
-                            (int)recon);
+                            ram::kItems, (int)recon);
     }
     Carve cv;
     const size_t tmp_off = cv.take(state_bytes);
@@ -673,6 +707,27 @@ ram_status ram_step_limited(ram_ctx *ctx, const ram_layout *layout, ram_dtype dt
     const int64_t extra[4] = {(int64_t)dtype * 16 + 256 * (int64_t)recon, -1, n_steps,
                               (int64_t)(intptr_t)q ^ (int64_t)state_bytes};
     return run_graphed(ctx, key_of(a, r, extra, tmp), n_steps, loop);
+}
+
+ram_status ram_row_norms(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
+                         const void *q, const void *q_ref, const double *edges,
+                         double *out)
+{
+    ram_status st;
+    g_last_error.clear();
+    if ((st = check_layout(layout, edges)) != RAM_OK) return st;
+    if ((st = check_dtype(dtype)) != RAM_OK) return st;
+    if (!q || !out) return fail(RAM_E_INVALID_ARG, "null q or out");
+    if ((st = enter(ctx)) != RAM_OK) return st;
+    ram::Rows R;
+    R.n_rows = layout->n_rows;
+    R.n_cols = layout->n_cols;
+    R.row_ptr = layout->n_cols > 0 ? nullptr : layout->row_ptr;
+    R.edges = edges;
+    R.shared = layout->edges_shared ? 1 : 0;
+    hipError_t e = ram::launch_row_norms(R, dtype == RAM_F64, q, q_ref, out, ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "row norms launch");
+    return RAM_OK;
 }
 
 ram_status ram_shift_adjoint(ram_ctx *ctx, const ram_layout *layout,
@@ -762,7 +817,8 @@ ram_status ram_step_record(ram_ctx *ctx, const ram_layout *layout,
     if ((st = enter(ctx)) != RAM_OK) return st;
     const size_t state_bytes = elem_size(dtype) * (size_t)layout_cells(layout);
     Carve cv;
-    RowsPlan rp = plan_rows(cv, layout, ram::step_tile(dv != nullptr), order);
+    const int items = sched_items(ctx, layout, scan);
+    RowsPlan rp = plan_rows(cv, layout, ram::step_tile_for(items, dv != nullptr), order);
     const int64_t nt = tiles_of(layout, rp.tile);
     const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(2 * sizeof(int32_t) * nt);
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
@@ -786,7 +842,7 @@ ram_status ram_step_record(ram_ctx *ctx, const ram_layout *layout,
         a.q_in = (const char *)q_traj + k * state_bytes;
         a.q_out = (char *)q_traj + (k + 1) * state_bytes;
         a.q_mid = dv ? (char *)q_half + k * state_bytes : nullptr;
-        e = shared ? ram::launch_step_shared(a, f64, (int)scan, order, ctx->stream)
+        e = shared ? ram::launch_step_shared(a, f64, (int)scan, order, items, ctx->stream)
                    : ram::launch_step(a, f64, (int)scan, order, ctx->stream);
         if (e != hipSuccess) return hip_fail(e, "step launch");
     }

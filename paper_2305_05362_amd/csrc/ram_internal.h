@@ -158,6 +158,10 @@ inline int64_t ragged_tile_bound(int64_t n_cells, int64_t n_rows, int tile)
 constexpr int kItems = 4;
 constexpr int kStepNodes = kBlock * kItems;
 inline int step_tile(bool fused) { return kStepNodes - 1 - (fused ? 4 : 0); }
+// The shared-mesh kernel with direct sums also comes with 2, 3 and 5 nodes
+// per thread (a schedule the caller or the autotuner chooses).
+inline bool valid_items(int items) { return items >= 2 && items <= 5; }
+inline int step_tile_for(int items, bool fused) { return kBlock * items - 1 - (fused ? 4 : 0); }
 
 hipError_t launch_tiles_prep(const int64_t *row_ptr, int64_t n_rows, int tile,
                              int64_t *tile_ptr, int32_t *tile_row,
@@ -174,7 +178,7 @@ hipError_t launch_step(const StepArgs &a, bool f64, int scan, int order,
 hipError_t launch_plan(const StepArgs &a, int order, int64_t *wlo, int32_t *w,
                        hipStream_t stream);
 hipError_t launch_step_shared(const StepArgs &a, bool f64, int scan, int order,
-                              hipStream_t stream);
+                              int items, hipStream_t stream);
 hipError_t launch_residual(const ResidualArgs &a, bool f64,
                            hipStream_t stream);
 hipError_t launch_shift_adjoint(const ShiftAdjArgs &a, bool f64, int order,
@@ -190,6 +194,10 @@ hipError_t launch_copy(const void *src, void *dst, int64_t bytes,
 // is ignored.
 hipError_t launch_shift_limited(const StepArgs &a, bool f64, int recon,
                                 hipStream_t stream);
+// Per-row mass, dx-weighted L1 distance to qref (if non-null) and max |Q|,
+// three FP64 values per row (one workgroup per row).
+hipError_t launch_row_norms(const Rows &R, bool f64, const void *q, const void *qref,
+                            double *out, hipStream_t stream);
 // Shared meshes: the limited shift in the specialised step kernel, fused with
 // the residual when a.dv is set; needs the window plan of order 3 (PLM) or 5
 // (PPM) and the tables.

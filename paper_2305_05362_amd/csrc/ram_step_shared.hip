@@ -47,15 +47,15 @@ constexpr int kPad = 8;                         // residual arrays: halo slack
 // from the (cache-resident) table, which keeps its LDS at four blocks a CU.
 template <typename CT> struct StageRR { static constexpr bool on = sizeof(CT) == 4; };
 
-template <typename M, typename A, typename CT, bool kDirect, int NX = 0>
+template <typename M, typename A, typename CT, bool kDirect, int NX, int NODES>
 struct ShLds {
     using CT2 = typename TabT<CT>::T2;
     // NX: window arrays of a limited reconstruction beside the masses
     static constexpr size_t win =
         sizeof(M) * kWinSh * (1 + NX) + (kDirect ? 0 : sizeof(A) * (kWinSh + 1));
     static constexpr size_t res =
-        (2 * sizeof(CT) + (StageRR<CT>::on ? sizeof(CT2) : 0)) * (kStepNodes + kPad);
-    static constexpr size_t nodes = sizeof(int64_t) * kStepNodes;
+        (2 * sizeof(CT) + (StageRR<CT>::on ? sizeof(CT2) : 0)) * (NODES + kPad);
+    static constexpr size_t nodes = sizeof(int64_t) * NODES;
     static constexpr size_t u0 = win > res ? win : res;
     static constexpr size_t uni = u0 > nodes ? u0 : nodes;
 };
@@ -98,7 +98,7 @@ __device__ inline int wrap1(int j, int n)
     return j < 0 ? j + n : (j >= n ? j - n : j);
 }
 
-template <typename TQ, int P, int S, int H, int RECON = 0>
+template <typename TQ, int P, int S, int H, int RECON = 0, int NI = kItems>
 __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
 {
     constexpr bool kDirect = S == kSumDirect;
@@ -110,13 +110,13 @@ __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
     using A = typename AC::A;
     using CT = TQ;                       // arithmetic after the prefix sums
     using CT2 = typename TabT<CT>::T2;
-    using L = ShLds<M, A, CT, kDirect, kLim ? 3 : 0>;
+    constexpr int NODES = kBlock * NI;   // shifted nodes per tile
+    using L = ShLds<M, A, CT, kDirect, kLim ? 3 : 0, NODES>;
     constexpr int LO = (P - 1) / 2;
-    constexpr int NI = kItems;
     constexpr int WCAP = kWinSh;
 
-    __shared__ short sjc[kStepNodes];    // window index of each node's cell (<= kWinSh)
-    __shared__ CT sell[kStepNodes];      // partial integral C~(xh) - C(c)
+    __shared__ short sjc[NODES];         // window index of each node's cell (<= kWinSh)
+    __shared__ CT sell[NODES];           // partial integral C~(xh) - C(c)
     __shared__ A swt[kBlock / 64];
     __shared__ __attribute__((aligned(16))) unsigned char su[L::uni];
     __shared__ int s_flag;
@@ -124,8 +124,8 @@ __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
     A *sp = (A *)(su + sizeof(M) * WCAP);            // exclusive prefix
     int64_t *sg = (int64_t *)su;                     // direct path: node indices
     CT *sq = (CT *)su;                               // shifted state
-    CT *sf = sq + (kStepNodes + kPad);               // face fluxes
-    CT2 *srr = (CT2 *)(sf + (kStepNodes + kPad));    // (dx, 1/gap) per cell
+    CT *sf = sq + (NODES + kPad);                    // face fluxes
+    CT2 *srr = (CT2 *)(sf + (NODES + kPad));         // (dx, 1/gap) per cell
     // limited reconstructions, beside the window masses:
     //   PLM  sx1 averages, sx2 1/centre gap (j, j+1), sx3 kappa
     //   PPM  sx1 averages (then C), sx2 limited slopes (then A), sx3 interfaces
@@ -510,32 +510,40 @@ __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
 }
 
 template <typename TQ, int P, int H>
-hipError_t step_sh_h(const StepArgs &a, int scan, hipStream_t st)
+hipError_t step_sh_h(const StepArgs &a, int scan, int items, hipStream_t st)
 {
     const dim3 g((unsigned)a.rows.n_tiles), b(kBlock);
     switch (scan) {
     case kScanF64: hipLaunchKernelGGL((k_step_sh<TQ, P, kScanF64, H>), g, b, 0, st, a); break;
     case kScanTwoSum: hipLaunchKernelGGL((k_step_sh<TQ, P, kScanTwoSum, H>), g, b, 0, st, a); break;
     case kScanF32: hipLaunchKernelGGL((k_step_sh<TQ, P, kScanF32, H>), g, b, 0, st, a); break;
-    default: hipLaunchKernelGGL((k_step_sh<TQ, P, kSumDirect, H>), g, b, 0, st, a); break;
+    default:
+        // direct sums: the schedule picks the shifted nodes per thread
+        switch (items) {
+        case 2: hipLaunchKernelGGL((k_step_sh<TQ, P, kSumDirect, H, 0, 2>), g, b, 0, st, a); break;
+        case 3: hipLaunchKernelGGL((k_step_sh<TQ, P, kSumDirect, H, 0, 3>), g, b, 0, st, a); break;
+        case 5: hipLaunchKernelGGL((k_step_sh<TQ, P, kSumDirect, H, 0, 5>), g, b, 0, st, a); break;
+        default: hipLaunchKernelGGL((k_step_sh<TQ, P, kSumDirect, H>), g, b, 0, st, a); break;
+        }
+        break;
     }
     return hipGetLastError();
 }
 
 template <typename TQ, int P>
-hipError_t step_sh_scan(const StepArgs &a, int scan, hipStream_t st)
+hipError_t step_sh_scan(const StepArgs &a, int scan, int items, hipStream_t st)
 {
-    if (a.dv) return step_sh_h<TQ, P, 2>(a, scan, st);
-    return step_sh_h<TQ, P, 0>(a, scan, st);
+    if (a.dv) return step_sh_h<TQ, P, 2>(a, scan, items, st);
+    return step_sh_h<TQ, P, 0>(a, scan, items, st);
 }
 
 template <typename TQ>
-hipError_t step_sh_order(const StepArgs &a, int scan, int order, hipStream_t st)
+hipError_t step_sh_order(const StepArgs &a, int scan, int order, int items, hipStream_t st)
 {
     switch (order) {
-    case 1: return step_sh_scan<TQ, 1>(a, scan, st);
-    case 3: return step_sh_scan<TQ, 3>(a, scan, st);
-    default: return step_sh_scan<TQ, 5>(a, scan, st);
+    case 1: return step_sh_scan<TQ, 1>(a, scan, items, st);
+    case 3: return step_sh_scan<TQ, 3>(a, scan, items, st);
+    default: return step_sh_scan<TQ, 5>(a, scan, items, st);
     }
 }
 
@@ -574,12 +582,14 @@ hipError_t launch_plan(const StepArgs &a, int order, int64_t *wlo, int32_t *w,
 }
 
 hipError_t launch_step_shared(const StepArgs &a, bool f64, int scan, int order,
-                              hipStream_t stream)
+                              int items, hipStream_t stream)
 {
     if (a.rows.n_tiles <= 0) return hipSuccess;
+    if (a.rows.tile != step_tile_for(scan == kSumDirect ? items : kItems, a.dv != nullptr))
+        return hipErrorInvalidValue;       // the tiles were planned for another schedule
     if (f64) return step_sh_order<double>(a, scan == kSumDirect ? kSumDirect : kScanF64,
-                                          order, stream);
-    return step_sh_order<float>(a, scan, order, stream);
+                                          order, items, stream);
+    return step_sh_order<float>(a, scan, order, items, stream);
 }
 
 } // namespace ram

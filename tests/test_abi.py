@@ -158,3 +158,24 @@ def test_limited_argument_errors(lib):
     st = lib.ram_shift_limited(None, ctypes.byref(L), R.RAM_F64, R.RAM_RECON_PPM,
                                a, b, c, d, 0.1)
     assert st == R.RAM_E_INVALID_ARG and b"context" in lib.ram_last_error()
+
+
+def test_row_norms_argument_errors(lib):
+    from paper_2305_05362_amd import _lib as R
+    L = _layout()
+    a, c, d = (ctypes.c_void_p(0x1000 * i) for i in (1, 3, 4))
+    st = lib.ram_row_norms(None, ctypes.byref(L), R.RAM_F32, None, None, c, d)
+    assert st == R.RAM_E_INVALID_ARG and b"null q" in lib.ram_last_error()
+    st = lib.ram_row_norms(None, ctypes.byref(L), 7, a, None, c, d)
+    assert st == R.RAM_E_UNSUPPORTED
+    st = lib.ram_row_norms(None, ctypes.byref(L), R.RAM_F32, a, None, c, d)
+    assert st == R.RAM_E_INVALID_ARG and b"context" in lib.ram_last_error()
+
+
+def test_schedule_argument_errors(lib):
+    from paper_2305_05362_amd import _lib as R
+    sc = R.Schedule(3)
+    st = lib.ram_set_schedule(None, ctypes.byref(sc))
+    assert st == R.RAM_E_INVALID_ARG and b"context" in lib.ram_last_error()
+    st = lib.ram_get_schedule(None, ctypes.byref(sc))
+    assert st == R.RAM_E_INVALID_ARG
