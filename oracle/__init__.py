@@ -18,6 +18,8 @@ Every function follows one passage of the paper:
   shift_recon      Section 3's remap with the limited reconstructions of
                    Section 3.1 (PLM / van Leer, PPM with App. A), and
   step_recon       the split step built on it;
+  shift_recon_adjoint  transpose of the limited shift's Jacobian at the
+                   forward state (the branch each limiter takes), plus dL/dv0;
   shift_adjoint    transpose of the (linear) shift, plus dL/dv0;
   residual_adjoint transpose of the residual Jacobian, plus dL/d(dv).
 
@@ -73,10 +75,11 @@ def _load():
     lib.oracle_step_recon.argtypes = [I64, P, P, I, P, P, P, D, I, I64, I]
     lib.oracle_recon_cells.argtypes = [P, P, I64, I, I, P, P, P]
     lib.oracle_edges_recon.argtypes = [P, P, I64, D, I, P, P]
+    lib.oracle_shift_recon_adjoint.argtypes = [I64, P, P, I, P, P, P, P, D, I, P, I]
     for f in ("oracle_shift", "oracle_residual", "oracle_step",
               "oracle_shift_adjoint", "oracle_residual_adjoint", "oracle_edges",
               "oracle_max_threads", "oracle_shift_recon", "oracle_step_recon",
-              "oracle_recon_cells", "oracle_edges_recon"):
+              "oracle_recon_cells", "oracle_edges_recon", "oracle_shift_recon_adjoint"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -257,3 +260,19 @@ def edges_recon(x, q, s: float, recon: int):
                                     _ptr(g), _ptr(ell))
     _check(rc, "edges_recon")
     return g, ell
+
+
+def shift_recon_adjoint(rows: Rows, q, qbar_out, v0, dt: float, recon: int,
+                        want_v0bar: bool = True, nthreads: int = 0):
+    """Transpose of the limited shift's Jacobian at q: (qbar_in, v0bar)."""
+    q = _f64(q).reshape(-1)
+    qb = _f64(qbar_out).reshape(-1)
+    v0 = _f64(np.broadcast_to(v0, (rows.n_rows,)))
+    out = np.empty_like(qb)
+    v0bar = np.zeros(rows.n_rows) if want_v0bar else None
+    rc = _load().oracle_shift_recon_adjoint(rows.n_rows, _ptr(rows.row_ptr),
+                                            _ptr(rows.edges), int(rows.shared), _ptr(q),
+                                            _ptr(qb), _ptr(out), _ptr(v0), float(dt),
+                                            int(recon), _ptr(v0bar), int(nthreads))
+    _check(rc, "shift_recon_adjoint")
+    return out, v0bar

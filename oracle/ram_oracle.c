@@ -403,6 +403,166 @@ static int shift_row_recon(const double *x, const double *q, double *qout,
     return 0;
 }
 
+/* ---- linearisation of the limited shift (its adjoint) ------------------ */
+/*
+ * The limited shift is nonlinear in Q; its adjoint is the transpose of its
+ * Jacobian at the forward state.  Away from the limiters' switching points the
+ * Jacobian is that of the branch each limiter takes there; at a switching
+ * point the branch the forward evaluation takes is used (a zero slope where
+ * the one-sided differences do not share a sign, as for the residual).
+ *
+ * lim_partial_grad: the partial integral ell of source cell c at xh, its
+ * derivatives g[a] = d ell / d Q_{c-lo+a} (a = 0 .. 2 lo, lo = 1 PLM, 2 PPM),
+ * and the reconstruction's value q_c(xh) = d ell / d xh.
+ */
+static double lim_partial_grad(const double *x, const double *q, int64_t n,
+                               int64_t c, double xh, int recon, double *g,
+                               double *qval)
+{
+    double xl = x[c], h = x[c + 1] - x[c];
+    double th = (xh - xl) / h;
+    if (recon == RECON_PLM) {
+        double qm = q_w(q, n, c - 1), q0 = q[c], qp = q_w(q, n, c + 1);
+        double hp = centre_gap(x, n, c), hm = centre_gap(x, n, c - 1);
+        double a = (qp - q0) / hp, b = (q0 - qm) / hm;
+        double sig = 0.0, dsa = 0.0, dsb = 0.0;
+        if (a * b > 0.0) {
+            sig = 2.0 * a * b / (a + b);
+            dsa = 2.0 * b * b / ((a + b) * (a + b));
+            dsb = 2.0 * a * a / ((a + b) * (a + b));
+        }
+        /* ell = Q_c h th + sigma h^2 (th^2 - th) / 2 */
+        double ks = 0.5 * h * h * (th * th - th);
+        g[0] = ks * dsb * (-1.0 / hm);
+        g[1] = h * th + ks * (dsa * (-1.0 / hp) + dsb * (1.0 / hm));
+        g[2] = ks * dsa * (1.0 / hp);
+        *qval = q0 + sig * (xh - centre(x, c));
+        return q0 * h * th + ks * sig;
+    }
+    /* PPM: cells c-2 .. c+2 */
+    double av[5], hv[6];
+    for (int k = 0; k < 5; ++k) av[k] = q_w(q, n, c - 2 + k);
+    for (int k = 0; k < 6; ++k) hv[k] = dx_w(x, n, c - 2 + k);
+    /* limited slopes of cells c-1, c, c+1 (index k = 0, 1, 2) and their
+     * derivatives w.r.t. the averages of cells j-1, j, j+1 */
+    double dl[3], dd[3][3];
+    for (int k = 0; k < 3; ++k) {
+        double hm = hv[k], h0 = hv[k + 1], hp = hv[k + 2];
+        double up = av[k + 2] - av[k + 1], dn = av[k + 1] - av[k];
+        double f = h0 / (hm + h0 + hp);
+        double w1 = f * (2.0 * hm + h0) / (hp + h0), w2 = f * (h0 + 2.0 * hp) / (hm + h0);
+        double d = w1 * up + w2 * dn;
+        dd[k][0] = dd[k][1] = dd[k][2] = 0.0;
+        dl[k] = 0.0;
+        if (up * dn > 0.0) {
+            double mag = fmin(fabs(d), fmin(2.0 * fabs(up), 2.0 * fabs(dn)));
+            dl[k] = copysign(mag, d);
+            if (fabs(d) <= 2.0 * fabs(up) && fabs(d) <= 2.0 * fabs(dn)) {
+                dd[k][0] = -w2; dd[k][1] = w2 - w1; dd[k][2] = w1;
+            } else if (fabs(up) <= fabs(dn)) {
+                dd[k][1] = -2.0; dd[k][2] = 2.0;          /* 2 up */
+            } else {
+                dd[k][0] = -2.0; dd[k][1] = 2.0;          /* 2 dn */
+            }
+        }
+    }
+    /* interfaces c-1/2 (between cells c-1, c) and c+1/2 (c, c+1) */
+    double ew[2][3];
+    for (int side = 0; side < 2; ++side) {
+        double hm = hv[side], h0 = hv[side + 1], hp = hv[side + 2], hpp = hv[side + 3];
+        double w1 = 2.0 * hp * h0 / (h0 + hp) *
+                    ((hm + h0) / (2.0 * h0 + hp) - (hpp + hp) / (2.0 * hp + h0));
+        double inv = 1.0 / (hm + h0 + hp + hpp);
+        ew[side][0] = h0 / (h0 + hp) + w1 * inv;
+        ew[side][1] = -h0 * (hm + h0) / (2.0 * h0 + hp) * inv;
+        ew[side][2] = hp * (hp + hpp) / (h0 + 2.0 * hp) * inv;
+    }
+    /* Lr = a_{c-1} + e1 (a_c - a_{c-1}) + e2 delta_c + e3 delta_{c-1}, likewise Rr */
+    double Lr = av[1] + ew[0][0] * (av[2] - av[1]) + ew[0][1] * dl[1] + ew[0][2] * dl[0];
+    double Rr = av[2] + ew[1][0] * (av[3] - av[2]) + ew[1][1] * dl[2] + ew[1][2] * dl[1];
+    double a = av[2], L = Lr, R = Rr;
+    int branch = 0;      /* 0 none, 1 flat, 2 L pulled in, 3 R pulled in */
+    if ((R - a) * (a - L) <= 0.0) {
+        L = a; R = a; branch = 1;
+    } else {
+        double dq = R - L, qa = a - 0.5 * (L + R);
+        if (dq * qa > dq * dq / 6.0) { L = 3.0 * a - 2.0 * R; branch = 2; }
+        else if (-dq * dq / 6.0 > dq * qa) { R = 3.0 * a - 2.0 * L; branch = 3; }
+    }
+    double q6 = 6.0 * a - 3.0 * (L + R);
+    double th2 = th * th, th3 = th2 * th;
+    double ell = h * (L * th + 0.5 * (R - L) * th2 + q6 * (0.5 * th2 - th3 / 3.0));
+    *qval = L + th * (R - L) + q6 * th * (1.0 - th);
+    /* d ell / d (a, L, R) with Q6 expanded */
+    double ga = h * (3.0 * th2 - 2.0 * th3);
+    double gl = h * (th - 2.0 * th2 + th3);
+    double gr = h * (th3 - th2);
+    double ba = 0.0, bl = 0.0, br = 0.0;    /* adjoints of a, Lr, Rr */
+    switch (branch) {
+    case 1: ba = ga + gl + gr; break;
+    case 2: ba = ga + 3.0 * gl; br = -2.0 * gl + gr; break;
+    case 3: ba = ga + 3.0 * gr; bl = gl - 2.0 * gr; break;
+    default: ba = ga; bl = gl; br = gr; break;
+    }
+    double gb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double bd[3] = {0.0, 0.0, 0.0};         /* adjoints of the three slopes */
+    gb[2] += ba;
+    gb[1] += bl * (1.0 - ew[0][0]);
+    gb[2] += bl * ew[0][0];
+    bd[1] += bl * ew[0][1];
+    bd[0] += bl * ew[0][2];
+    gb[2] += br * (1.0 - ew[1][0]);
+    gb[3] += br * ew[1][0];
+    bd[2] += br * ew[1][1];
+    bd[1] += br * ew[1][2];
+    for (int k = 0; k < 3; ++k)
+        for (int t = 0; t < 3; ++t) gb[k + t] += bd[k] * dd[k][t];
+    for (int k = 0; k < 5; ++k) g[k] = gb[k];
+    return ell;
+}
+
+/* Transpose of the limited shift's Jacobian at q: qbar_in (overwritten) and
+ * sbar = d <qbar_out, S(q; s)> / ds. */
+static int shift_recon_adjoint_row(const double *x, const double *q,
+                                   const double *qbar_out, double *qbar_in,
+                                   int64_t n, double s, int recon, double *sbar)
+{
+    int lo = recon == RECON_PLM ? 1 : 2;
+    int64_t *g = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    double *gw = (double *)malloc(sizeof(double) * 5 * (size_t)(n + 1));
+    double *qv = (double *)malloc(sizeof(double) * (size_t)(n + 1));
+    int64_t *cc = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+    if (!g || !gw || !qv || !cc) { free(g); free(gw); free(qv); free(cc); return -6; }
+    for (int64_t e = 0; e < n; ++e) {
+        double xh;
+        int64_t k;
+        shifted_node(x, n, s, e, &xh, &k);
+        cc[e] = find_cell(x, n, xh);
+        g[e] = cc[e] + k * n;
+        lim_partial_grad(x, q, n, cc[e], xh, recon, gw + 5 * e, &qv[e]);
+    }
+    g[n] = g[0] + n;
+    cc[n] = cc[0];
+    qv[n] = qv[0];
+    memcpy(gw + 5 * n, gw, 5 * sizeof(double));
+    for (int64_t m = 0; m < n; ++m) qbar_in[m] = 0.0;
+    double sb = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        /* M'_i = sum_{m=g_i}^{g_{i+1}-1} Q_m dx_m + ell_{i+1} - ell_i, Q'_i = M'_i / dx_i */
+        double mb = qbar_out[i] / (x[i + 1] - x[i]);
+        for (int64_t m = g[i]; m < g[i + 1]; ++m) qbar_in[wrap(m, n)] += mb * dx_w(x, n, m);
+        for (int a = 0; a <= 2 * lo; ++a) {
+            qbar_in[wrap(cc[i + 1] - lo + a, n)] += mb * gw[5 * (i + 1) + a];
+            qbar_in[wrap(cc[i] - lo + a, n)] -= mb * gw[5 * i + a];
+        }
+        /* d ell / d s = -q_c(xh) */
+        sb -= mb * (qv[i + 1] - qv[i]);
+    }
+    if (sbar) *sbar = sb;
+    free(g); free(gw); free(qv); free(cc);
+    return 0;
+}
+
 /* fewest cells a row needs: the reconstruction stencil (3 or 5 cells) plus one */
 static int64_t recon_min_cells(int recon) { return recon == RECON_PLM ? 4 : 6; }
 
@@ -714,4 +874,28 @@ int oracle_edges_recon(const double *x, const double *q, int64_t n, double s,
         ell[e] = limited_partial(x, q, n, c, xh, recon);
     }
     return 0;
+}
+
+/* Adjoint of the limited shift at the forward state q: qbar_in overwritten;
+ * v0bar (per row, when non-NULL) accumulated with dt * d<qbar_out, S q>/ds. */
+int oracle_shift_recon_adjoint(int64_t n_rows, const int64_t *row_ptr,
+                               const double *edges, int shared, const double *q,
+                               const double *qbar_out, double *qbar_in,
+                               const double *v0, double dt, int recon, double *v0bar,
+                               int nthreads)
+{
+    if (recon != RECON_PLM && recon != RECON_PPM) return -2;
+    set_threads(nthreads);
+    int err = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
+    for (int64_t r = 0; r < n_rows; ++r) {
+        int64_t n = row_ptr[r + 1] - row_ptr[r];
+        if (n < recon_min_cells(recon)) { err |= 1; continue; }
+        double sb = 0.0;
+        err |= shift_recon_adjoint_row(row_mesh(edges, shared, row_ptr, r), q + row_ptr[r],
+                                       qbar_out + row_ptr[r], qbar_in + row_ptr[r], n,
+                                       v0[r] * dt, recon, v0bar ? &sb : NULL) != 0;
+        if (v0bar) v0bar[r] += dt * sb;
+    }
+    return err ? -1 : 0;
 }
