@@ -170,6 +170,23 @@ ram_status ram_step_limited(ram_ctx *ctx, const ram_layout *layout,
                             const double *edges, const double *v0,
                             const void *dv, double dt, int64_t n_steps);
 
+/* Adjoint of ram_shift_limited.  The limited shift is nonlinear in Q, so this
+ * is the transpose of its Jacobian at the forward state q_fwd (required),
+ * each limiter differentiated on the branch it takes there -- a zero slope
+ * where the one-sided differences do not share a sign, as in
+ * ram_residual_adjoint:
+ *   qbar_in = (dS/dQ at q_fwd)^T qbar_out (overwritten),
+ *   v0bar_accum[r] += dt * d<qbar_out, S(s) q_fwd>/ds at s = v0[r] dt (when
+ *   non-NULL; the derivative is minus the reconstruction at each shifted
+ *   node, FP64).
+ * Any layout; FP64 arithmetic inside, the result rounded to dtype. */
+ram_status ram_shift_limited_adjoint(ram_ctx *ctx, const ram_layout *layout,
+                                     ram_dtype dtype, ram_recon recon,
+                                     const void *q_fwd, const void *qbar_out,
+                                     void *qbar_in, const double *edges,
+                                     const double *v0, double dt,
+                                     double *v0bar_accum);
+
 /* Adjoint of ram_shift (the shift is linear in Q): qbar_in = S^T qbar_out,
  * overwritten.  When v0bar_accum != NULL, also accumulates per row
  *   v0bar_accum[r] += dt * d<qbar_out, S(s) q_fwd>/ds  at s = v0[r] dt,

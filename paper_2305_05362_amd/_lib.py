@@ -87,6 +87,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ram_shift_limited": [P, LP, I, I, P, P, P, P, D],
         "ram_step_limited": [P, LP, I, I, P, P, P, P, D, I64],
         "ram_row_norms": [P, LP, I, P, P, P, P],
+        "ram_shift_limited_adjoint": [P, LP, I, I, P, P, P, P, P, D, P],
         "ram_set_schedule": [P, ctypes.POINTER(Schedule)],
         "ram_get_schedule": [P, ctypes.POINTER(Schedule)],
     }
@@ -234,6 +235,19 @@ class Context:
             float(dt), int(n_steps)))
         return q
 
+    def ram_shift_limited_adjoint(self, rows: Rows, q_fwd, qbar_out, qbar_in, v0,
+                                  dt: float, recon: int, v0bar=None):
+        self._stream()
+        check(self._lib.ram_shift_limited_adjoint(
+            self._h, ctypes.byref(rows.layout), _dtype_code(qbar_out), int(recon),
+            _dev_ptr(q_fwd, qbar_out.dtype, "q_fwd"),
+            _dev_ptr(qbar_out, qbar_out.dtype, "qbar_out"),
+            _dev_ptr(qbar_in, qbar_out.dtype, "qbar_in"),
+            _dev_ptr(rows.edges, torch.float64, "edges"),
+            _dev_ptr(v0, torch.float64, "v0"), float(dt),
+            _dev_ptr(v0bar, torch.float64, "v0bar")))
+        return qbar_in
+
     def ram_row_norms(self, rows: Rows, q, q_ref=None, out=None):
         """Per-row (mass, dx-weighted L1 distance to q_ref, max |q|), FP64
         tensor of shape [n_rows, 3] on q's device."""
@@ -357,6 +371,11 @@ def ram_shift_limited(rows, q_in, q_out, v0, dt, recon):
 
 def ram_step_limited(rows, q, v0, dv, dt, recon, n_steps):
     return context(q.device.index).ram_step_limited(rows, q, v0, dv, dt, recon, n_steps)
+
+
+def ram_shift_limited_adjoint(rows, q_fwd, qbar_out, qbar_in, v0, dt, recon, v0bar=None):
+    return context(qbar_out.device.index).ram_shift_limited_adjoint(
+        rows, q_fwd, qbar_out, qbar_in, v0, dt, recon, v0bar)
 
 
 def ram_row_norms(rows, q, q_ref=None, out=None):

@@ -200,6 +200,215 @@ __global__ __launch_bounds__(kBlock) void k_shift_adj(ShiftAdjArgs a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// adjoint of the limited (PLM / PPM) shift
+// ---------------------------------------------------------------------------
+//
+// The limited shift is nonlinear in Q; its adjoint is the transpose of the
+// Jacobian at the forward state, each limiter differentiated on the branch it
+// takes there (a zero slope where the one-sided differences do not share a
+// sign).  Node e's partial integral ell_e depends on the averages of its
+// source cell's stencil c-lo .. c+lo, so the transpose gathers, for every
+// source cell m of a tile's window,
+//     Qbar_m = dx_m Mbar'_i  (m a whole cell of destination cell i)
+//            + sum_{e : |c_e - m| <= lo} Vbar_e d ell_e / d Q_m,
+// with Vbar_e = Mbar'_{e-1} - Mbar'_e.  Shared window cells are accumulated
+// with atomics after the zeroing pass, as for the Lagrange shift.
+
+// d ell / d Q_{c-lo+a} (a = 0 .. 2 lo) of the partial integral of cell c at
+// xh, and the reconstruction's value q_c(xh) (= d ell / d xh); FP64.
+template <typename TQ, int R>
+__device__ __attribute__((noinline)) void lim_grad(const double *x, const TQ *q, int n,
+                                                   double len, int c, double xh,
+                                                   double *gw, double &qval)
+{
+    const double h = x[c + 1] - x[c];
+    const double th = (xh - x[c]) / h;
+    if constexpr (R == kReconPLM) {
+        const double qm = (double)q[wrapi(c - 1, n)], q0 = (double)q[c];
+        const double qp = (double)q[wrapi(c + 1, n)];
+        const double hp = centre_gap(x, n, len, c), hm = centre_gap(x, n, len, c - 1);
+        const double a = (qp - q0) / hp, b = (q0 - qm) / hm;
+        double sig = 0.0, dsa = 0.0, dsb = 0.0;
+        if (a * b > 0.0) {
+            const double s2 = (a + b) * (a + b);
+            sig = 2.0 * a * b / (a + b);
+            dsa = 2.0 * b * b / s2;
+            dsb = 2.0 * a * a / s2;
+        }
+        // ell = Q_c h theta + sigma h^2 (theta^2 - theta) / 2
+        const double ks = 0.5 * h * h * (th * th - th);
+        gw[0] = -ks * dsb / hm;
+        gw[1] = h * th + ks * (dsb / hm - dsa / hp);
+        gw[2] = ks * dsa / hp;
+        qval = q0 + sig * (xh - 0.5 * (x[c] + x[c + 1]));
+    } else {
+        double av[5], hv[6];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) av[k] = (double)q[wrapi(c - 2 + k, n)];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const int m = wrapi(c - 2 + k, n);
+            hv[k] = x[m + 1] - x[m];
+        }
+        // limited slopes of cells c-1, c, c+1 and their derivatives w.r.t.
+        // the averages of each slope's cells j-1, j, j+1
+        double dl[3], dd[3][3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const PpmW w = ppm_weights(hv[k], hv[k + 1], hv[k + 2], hv[k + 3]);
+            const double up = av[k + 2] - av[k + 1], dn = av[k + 1] - av[k];
+            const double d = w.d1 * up + w.d2 * dn;
+            dd[k][0] = dd[k][1] = dd[k][2] = 0.0;
+            dl[k] = 0.0;
+            if (up * dn > 0.0) {
+                dl[k] = copysign(fmin(fabs(d), 2.0 * fmin(fabs(up), fabs(dn))), d);
+                if (fabs(d) <= 2.0 * fabs(up) && fabs(d) <= 2.0 * fabs(dn)) {
+                    dd[k][0] = -w.d2;
+                    dd[k][1] = w.d2 - w.d1;
+                    dd[k][2] = w.d1;
+                } else if (fabs(up) <= fabs(dn)) {
+                    dd[k][1] = -2.0;          // twice the upper difference
+                    dd[k][2] = 2.0;
+                } else {
+                    dd[k][0] = -2.0;          // twice the lower difference
+                    dd[k][1] = 2.0;
+                }
+            }
+        }
+        // interface values c-1/2 and c+1/2 before the constraints
+        const PpmW wl = ppm_weights(hv[0], hv[1], hv[2], hv[3]);
+        const PpmW wr = ppm_weights(hv[1], hv[2], hv[3], hv[4]);
+        const double Lr = av[1] + wl.e1 * (av[2] - av[1]) + wl.e2 * dl[1] + wl.e3 * dl[0];
+        const double Rr = av[2] + wr.e1 * (av[3] - av[2]) + wr.e2 * dl[2] + wr.e3 * dl[1];
+        const double a = av[2];
+        double L = Lr, Rv = Rr;
+        int branch = 0;                       // 1 flat, 2 L pulled in, 3 R pulled in
+        if ((Rv - a) * (a - L) <= 0.0) {
+            L = a;
+            Rv = a;
+            branch = 1;
+        } else {
+            const double dq = Rv - L, qa = a - 0.5 * (L + Rv);
+            if (dq * qa > dq * dq / 6.0) { L = 3.0 * a - 2.0 * Rv; branch = 2; }
+            else if (-dq * dq / 6.0 > dq * qa) { Rv = 3.0 * a - 2.0 * L; branch = 3; }
+        }
+        const double q6 = 6.0 * a - 3.0 * (L + Rv);
+        qval = L + th * (Rv - L) + q6 * th * (1.0 - th);
+        // d ell / d (a, L, R) with Q6 expanded, then back through the branch
+        const double th2 = th * th, th3 = th2 * th;
+        const double ga = h * (3.0 * th2 - 2.0 * th3);
+        const double gl = h * (th - 2.0 * th2 + th3);
+        const double gr = h * (th3 - th2);
+        double ba = ga, bl = gl, br = gr;
+        if (branch == 1) { ba = ga + gl + gr; bl = 0.0; br = 0.0; }
+        else if (branch == 2) { ba = ga + 3.0 * gl; bl = 0.0; br = gr - 2.0 * gl; }
+        else if (branch == 3) { ba = ga + 3.0 * gr; bl = gl - 2.0 * gr; br = 0.0; }
+        double gb[5] = {0.0, 0.0, ba, 0.0, 0.0};
+        double bd[3] = {bl * wl.e3, bl * wl.e2 + br * wr.e3, br * wr.e2};
+        gb[1] += bl * (1.0 - wl.e1);
+        gb[2] += bl * wl.e1 + br * (1.0 - wr.e1);
+        gb[3] += br * wr.e1;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int t = 0; t < 3; ++t) gb[k + t] += bd[k] * dd[k][t];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) gw[k] = gb[k];
+    }
+}
+
+template <typename TQ, int R>
+__global__ __launch_bounds__(kBlock) void k_shift_lim_adj(ShiftAdjArgs a)
+{
+    constexpr int LO = LimHalo<R>::lo;
+    constexpr int P = 2 * LO + 1;         // stencil cells
+    __shared__ int64_t sg[kTile + 1];     // extended source cell of each node
+    __shared__ double svb[kTile + 1];     // tile-local Vbar of each node
+    __shared__ double sgw[kTile + 1][P];  // d ell / d Q of its stencil cells
+    __shared__ double sred[kBlock / 64];
+
+    Tile ti;
+    if (!get_tile(a.rows, blockIdx.x, ti)) return;
+    const int n = ti.n;
+    if (n < P + 1) return;
+    const double *x = ti.x;
+    const TQ *qbo = (const TQ *)a.qbar_out + ti.qoff;
+    TQ *qbi = (TQ *)a.qbar_in + ti.qoff;
+    const TQ *qf = (const TQ *)a.q_fwd + ti.qoff;
+    const double s = a.v0[ti.row] * a.dt;
+    const double len = x[n] - x[0];
+    const int i0 = ti.i0;
+    const int nd = min(a.rows.tile, n - i0);
+    const int ne = nd + 1;
+    const bool want_v0 = a.v0bar != nullptr;
+
+    double vpart = 0.0;
+    for (int t = threadIdx.x; t < ne; t += kBlock) {
+        double xh;
+        const int64_t g = locate(x, n, s, i0 + t, xh);
+        const int c = wrapi(g, n);
+        double gw[P], qv;
+        lim_grad<TQ, R>(x, qf, n, len, c, xh, gw, qv);
+        double vb = 0.0;
+        if (t >= 1) {
+            const int i = i0 + t - 1;
+            vb += (double)qbo[i] / (x[i + 1] - x[i]);
+        }
+        if (t <= nd - 1) {
+            const int i = i0 + t;
+            vb -= (double)qbo[i] / (x[i + 1] - x[i]);
+        }
+        svb[t] = vb;
+        sg[t] = g;
+#pragma unroll
+        for (int b = 0; b < P; ++b) sgw[t][b] = gw[b];
+        vpart -= vb * qv;                 // d ell / d s = -q_c(xh)
+    }
+    if (want_v0) {
+        for (int d = 32; d >= 1; d >>= 1) vpart += __shfl_xor(vpart, d);
+        if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = vpart;
+    }
+    __syncthreads();
+    if (want_v0 && threadIdx.x == 0) {
+        double tot = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) tot += sred[w];
+        atomicAdd(&a.v0bar[ti.row], a.dt * tot);
+    }
+
+    const int64_t wlo = sg[0] - LO;
+    const int W = (int)(sg[nd] - sg[0] + P);
+    const int base = wrapi(wlo, n);
+    for (int j = threadIdx.x; j < W; j += kBlock) {
+        const int64_t m = wlo + j;
+        const int mm = (base + j) % n;
+        const double dxm = x[mm + 1] - x[mm];
+        // the destination cell whose whole-cell run holds m: the last node at
+        // or below m starts it
+        int lo = 0, hi = ne;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (sg[mid] > m) hi = mid; else lo = mid + 1;
+        }
+        double val = (lo >= 1 && lo <= nd)
+                         ? (double)qbo[i0 + lo - 1] / (x[i0 + lo] - x[i0 + lo - 1]) * dxm
+                         : 0.0;
+        // nodes whose stencil holds m: source cell within lo of m
+        lo = 0;
+        hi = ne;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (sg[mid] < m - LO) lo = mid + 1; else hi = mid;
+        }
+        for (int t = lo; t < ne && sg[t] <= m + LO; ++t)
+            val += svb[t] * sgw[t][(int)(m - (sg[t] - LO))];
+        if (j >= P && j < W - P)
+            qbi[mm] = (TQ)val;
+        else
+            atomicAdd(&qbi[mm], (TQ)val);
+    }
+}
+
 template <typename TQ>
 __global__ __launch_bounds__(kBlock) void k_residual_adj(ResidualAdjArgs a)
 {
@@ -314,6 +523,32 @@ hipError_t shift_adj_dispatch(const ShiftAdjArgs &a, int order, hipStream_t st)
 }
 
 } // namespace
+
+hipError_t launch_shift_limited_adjoint(const ShiftAdjArgs &a, bool f64, int recon,
+                                        hipStream_t stream)
+{
+    if (a.rows.n_tiles <= 0) return hipSuccess;
+    const dim3 gz((unsigned)((a.rows.n_tiles + kBlock - 1) / kBlock)), b(kBlock);
+    const dim3 g((unsigned)a.rows.n_tiles);
+    if (f64) {
+        if (recon == kReconPLM) {
+            hipLaunchKernelGGL((k_shift_adj_zero<double, 3>), gz, b, 0, stream, a);
+            hipLaunchKernelGGL((k_shift_lim_adj<double, kReconPLM>), g, b, 0, stream, a);
+        } else {
+            hipLaunchKernelGGL((k_shift_adj_zero<double, 5>), gz, b, 0, stream, a);
+            hipLaunchKernelGGL((k_shift_lim_adj<double, kReconPPM>), g, b, 0, stream, a);
+        }
+    } else {
+        if (recon == kReconPLM) {
+            hipLaunchKernelGGL((k_shift_adj_zero<float, 3>), gz, b, 0, stream, a);
+            hipLaunchKernelGGL((k_shift_lim_adj<float, kReconPLM>), g, b, 0, stream, a);
+        } else {
+            hipLaunchKernelGGL((k_shift_adj_zero<float, 5>), gz, b, 0, stream, a);
+            hipLaunchKernelGGL((k_shift_lim_adj<float, kReconPPM>), g, b, 0, stream, a);
+        }
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_shift_adjoint(const ShiftAdjArgs &a, bool f64, int order,
                                 hipStream_t stream)

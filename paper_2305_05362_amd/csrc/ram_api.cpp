@@ -709,6 +709,40 @@ ram_status ram_step_limited(ram_ctx *ctx, const ram_layout *layout, ram_dtype dt
     return run_graphed(ctx, key_of(a, r, extra, tmp), n_steps, loop);
 }
 
+ram_status ram_shift_limited_adjoint(ram_ctx *ctx, const ram_layout *layout,
+                                     ram_dtype dtype, ram_recon recon, const void *q_fwd,
+                                     const void *qbar_out, void *qbar_in,
+                                     const double *edges, const double *v0, double dt,
+                                     double *v0bar_accum)
+{
+    ram_status st;
+    g_last_error.clear();
+    if ((st = check_layout(layout, edges)) != RAM_OK) return st;
+    if ((st = check_dtype(dtype)) != RAM_OK) return st;
+    if ((st = check_recon(layout, recon)) != RAM_OK) return st;
+    if ((st = check_dt(dt)) != RAM_OK) return st;
+    if (!q_fwd || !qbar_out || !qbar_in || !v0)
+        return fail(RAM_E_INVALID_ARG, "null q_fwd, qbar_out, qbar_in or v0");
+    if (qbar_in == qbar_out || qbar_in == q_fwd)
+        return fail(RAM_E_INVALID_ARG, "qbar_in must not alias qbar_out or q_fwd");
+    if ((st = enter(ctx)) != RAM_OK) return st;
+    Carve cv;
+    RowsPlan rp = plan_rows(cv, layout, ram::kTile, 0);
+    if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
+    ram::ShiftAdjArgs a;
+    if ((st = make_rows(ctx, layout, edges, rp, a.rows)) != RAM_OK) return st;
+    a.q_fwd = q_fwd;
+    a.qbar_out = qbar_out;
+    a.qbar_in = qbar_in;
+    a.v0 = v0;
+    a.dt = dt;
+    a.v0bar = v0bar_accum;
+    hipError_t e = ram::launch_shift_limited_adjoint(a, dtype == RAM_F64, (int)recon,
+                                                     ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "limited shift adjoint launch");
+    return RAM_OK;
+}
+
 ram_status ram_row_norms(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
                          const void *q, const void *q_ref, const double *edges,
                          double *out)

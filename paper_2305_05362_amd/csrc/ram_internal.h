@@ -194,6 +194,10 @@ hipError_t launch_copy(const void *src, void *dst, int64_t bytes,
 // is ignored.
 hipError_t launch_shift_limited(const StepArgs &a, bool f64, int recon,
                                 hipStream_t stream);
+// Transpose of the limited shift's Jacobian at a.q_fwd (any layout; a zeroing
+// pass, then one gather kernel), v0bar accumulated when a.v0bar is set.
+hipError_t launch_shift_limited_adjoint(const ShiftAdjArgs &a, bool f64, int recon,
+                                        hipStream_t stream);
 // Per-row mass, dx-weighted L1 distance to qref (if non-null) and max |Q|,
 // three FP64 values per row (one workgroup per row).
 hipError_t launch_row_norms(const Rows &R, bool f64, const void *q, const void *qref,

@@ -179,3 +179,22 @@ def test_schedule_argument_errors(lib):
     assert st == R.RAM_E_INVALID_ARG and b"context" in lib.ram_last_error()
     st = lib.ram_get_schedule(None, ctypes.byref(sc))
     assert st == R.RAM_E_INVALID_ARG
+
+
+def test_limited_adjoint_argument_errors(lib):
+    from paper_2305_05362_amd import _lib as R
+    L = _layout()
+    a, b, c, d, e = (ctypes.c_void_p(0x1000 * i) for i in (1, 2, 3, 4, 5))
+    # the forward state is required (the map is nonlinear)
+    st = lib.ram_shift_limited_adjoint(None, ctypes.byref(L), R.RAM_F64, R.RAM_RECON_PPM,
+                                       None, b, c, d, e, 0.1, None)
+    assert st == R.RAM_E_INVALID_ARG and b"q_fwd" in lib.ram_last_error()
+    st = lib.ram_shift_limited_adjoint(None, ctypes.byref(L), R.RAM_F64, R.RAM_RECON_PPM,
+                                       a, b, a, d, e, 0.1, None)
+    assert st == R.RAM_E_INVALID_ARG and b"alias" in lib.ram_last_error()
+    st = lib.ram_shift_limited_adjoint(None, ctypes.byref(L), R.RAM_F64, 9,
+                                       a, b, c, d, e, 0.1, None)
+    assert st == R.RAM_E_UNSUPPORTED
+    st = lib.ram_shift_limited_adjoint(None, ctypes.byref(L), R.RAM_F32, R.RAM_RECON_PLM,
+                                       a, b, c, d, e, 0.1, None)
+    assert st == R.RAM_E_INVALID_ARG and b"context" in lib.ram_last_error()
