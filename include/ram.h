@@ -170,6 +170,16 @@ ram_status ram_step_limited(ram_ctx *ctx, const ram_layout *layout,
                             const double *edges, const double *v0,
                             const void *dv, double dt, int64_t n_steps);
 
+/* n_steps limited steps keeping the trajectory, as ram_step_record does for
+ * the Lagrange shift: q_traj holds n_steps+1 states (slot 0 the input), q_half
+ * (when dv != NULL) each step's post-shift state, the state its residual step
+ * read.  Results equal ram_step_limited's bit for bit. */
+ram_status ram_step_limited_record(ram_ctx *ctx, const ram_layout *layout,
+                                   ram_dtype dtype, ram_recon recon, void *q_traj,
+                                   void *q_half, const double *edges,
+                                   const double *v0, const void *dv, double dt,
+                                   int64_t n_steps);
+
 /* Adjoint of ram_shift_limited.  The limited shift is nonlinear in Q, so this
  * is the transpose of its Jacobian at the forward state q_fwd (required),
  * each limiter differentiated on the branch it takes there -- a zero slope

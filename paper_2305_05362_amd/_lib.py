@@ -88,6 +88,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ram_step_limited": [P, LP, I, I, P, P, P, P, D, I64],
         "ram_row_norms": [P, LP, I, P, P, P, P],
         "ram_shift_limited_adjoint": [P, LP, I, I, P, P, P, P, P, D, P],
+        "ram_step_limited_record": [P, LP, I, I, P, P, P, P, P, D, I64],
         "ram_set_schedule": [P, ctypes.POINTER(Schedule)],
         "ram_get_schedule": [P, ctypes.POINTER(Schedule)],
     }
@@ -234,6 +235,18 @@ class Context:
             _dev_ptr(v0, torch.float64, "v0"), _dev_ptr(dv, q.dtype, "dv"),
             float(dt), int(n_steps)))
         return q
+
+    def ram_step_limited_record(self, rows: Rows, q_traj, q_half, v0, dv, dt: float,
+                                recon: int, n_steps: int):
+        self._stream()
+        check(self._lib.ram_step_limited_record(
+            self._h, ctypes.byref(rows.layout), _dtype_code(q_traj), int(recon),
+            _dev_ptr(q_traj, q_traj.dtype, "q_traj"),
+            _dev_ptr(q_half, q_traj.dtype, "q_half"),
+            _dev_ptr(rows.edges, torch.float64, "edges"),
+            _dev_ptr(v0, torch.float64, "v0"), _dev_ptr(dv, q_traj.dtype, "dv"),
+            float(dt), int(n_steps)))
+        return q_traj
 
     def ram_shift_limited_adjoint(self, rows: Rows, q_fwd, qbar_out, qbar_in, v0,
                                   dt: float, recon: int, v0bar=None):

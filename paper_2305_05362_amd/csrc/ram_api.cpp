@@ -709,6 +709,80 @@ ram_status ram_step_limited(ram_ctx *ctx, const ram_layout *layout, ram_dtype dt
     return run_graphed(ctx, key_of(a, r, extra, tmp), n_steps, loop);
 }
 
+ram_status ram_step_limited_record(ram_ctx *ctx, const ram_layout *layout,
+                                   ram_dtype dtype, ram_recon recon, void *q_traj,
+                                   void *q_half, const double *edges, const double *v0,
+                                   const void *dv, double dt, int64_t n_steps)
+{
+    ram_status st;
+    g_last_error.clear();
+    if ((st = check_layout(layout, edges)) != RAM_OK) return st;
+    if ((st = check_dtype(dtype)) != RAM_OK) return st;
+    if ((st = check_recon(layout, recon)) != RAM_OK) return st;
+    if ((st = check_dt(dt)) != RAM_OK) return st;
+    if (!q_traj || !v0) return fail(RAM_E_INVALID_ARG, "null q_traj or v0");
+    if (dv && !q_half) return fail(RAM_E_INVALID_ARG, "a step with dv needs q_half");
+    if (n_steps < 0) return fail(RAM_E_INVALID_ARG, "n_steps must be >= 0");
+    if (n_steps == 0) return RAM_OK;
+    if ((st = enter(ctx)) != RAM_OK) return st;
+    const size_t state_bytes = elem_size(dtype) * (size_t)layout_cells(layout);
+    const bool f64 = dtype == RAM_F64;
+    const bool shared = layout->edges_shared && layout->n_cols > 0;
+    Carve cv;
+    // shared mesh: the fused kernel with the post-shift state written out;
+    // per-row meshes: the shift kernel into q_half, then the residual kernel
+    RowsPlan rp = plan_rows(cv, layout,
+                            shared ? ram::step_tile(dv != nullptr) : ram::step_tile(false), 1);
+    const int64_t nt = tiles_of(layout, rp.tile);
+    const size_t wlo_off = shared ? cv.take(sizeof(int64_t) * nt) : 0;
+    const size_t w_off = shared ? cv.take(2 * sizeof(int32_t) * nt) : 0;
+    RowsPlan rr = plan_rows(cv, layout, ram::kResTile, 0);
+    if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
+    ram::StepArgs a;
+    if ((st = make_rows(ctx, layout, edges, rp, a.rows)) != RAM_OK) return st;
+    ram::ResidualArgs r;
+    if (!shared) {
+        if ((st = make_rows(ctx, layout, edges, rr, r.rows)) != RAM_OK) return st;
+        r.rows.tab = a.rows.tab;
+        r.rows.has_tab = a.rows.has_tab;
+        r.dv = dv;
+        r.dt = dt;
+    }
+    a.v0 = v0;
+    a.dt = dt;
+    hipError_t e;
+    if (shared) {
+        a.dv = dv;
+        int64_t *wlo = (int64_t *)((char *)ctx->scratch + wlo_off);
+        int32_t *w = (int32_t *)((char *)ctx->scratch + w_off);
+        e = ram::launch_plan(a, recon == RAM_RECON_PLM ? 3 : 5, wlo, w, ctx->stream);
+        if (e != hipSuccess) return hip_fail(e, "window plan launch");
+        a.plan_wlo = wlo;
+        a.plan_w = w;
+    }
+    for (int64_t k = 0; k < n_steps; ++k) {
+        void *qi = (char *)q_traj + k * state_bytes;
+        void *qo = (char *)q_traj + (k + 1) * state_bytes;
+        void *qh = dv ? (char *)q_half + k * state_bytes : nullptr;
+        a.q_in = qi;
+        if (shared) {
+            a.q_out = qo;
+            a.q_mid = qh;
+            e = ram::launch_step_shared_limited(a, f64, (int)recon, ctx->stream);
+        } else {
+            a.q_out = dv ? qh : qo;
+            e = ram::launch_shift_limited(a, f64, (int)recon, ctx->stream);
+            if (e == hipSuccess && dv) {
+                r.q_in = qh;
+                r.q_out = qo;
+                e = ram::launch_residual(r, f64, ctx->stream);
+            }
+        }
+        if (e != hipSuccess) return hip_fail(e, "limited step launch");
+    }
+    return RAM_OK;
+}
+
 ram_status ram_shift_limited_adjoint(ram_ctx *ctx, const ram_layout *layout,
                                      ram_dtype dtype, ram_recon recon, const void *q_fwd,
                                      const void *qbar_out, void *qbar_in,
