@@ -182,6 +182,12 @@ def main():
     # --- FP64 plain path ----------------------------------------------------
     t64, q_64 = time_steps(q64, dv64, R.RAM_SCAN_F64, args.fp64_steps, args.warmup)
     v64 = n_cells * args.fp64_steps / t64 / 1e9
+    # --- FP64 with direct sums, its own tuned schedule ----------------------
+    items64, tune64, _ = tuned_schedule(ctx, rows, q64, v0, dv64, wl.dt, order,
+                                        R.RAM_SUM_DIRECT, cache_path=None)
+    t64d, _ = time_steps(q64, dv64, R.RAM_SUM_DIRECT, args.fp64_steps, args.warmup)
+    v64d = n_cells * args.fp64_steps / t64d / 1e9
+    ctx.set_schedule(items)                  # back to the headline's schedule
 
     # --- ragged rows with per-row meshes (4096 rows of 64..8192 cells) ------
     wl3 = W.cfg3()
@@ -260,6 +266,33 @@ def main():
                 ent["traffic"] = None if tr_ppm is None else \
                     round(tr_ppm["traffic_bytes_per_launch"])
             limited[f"{name}_{tag}"] = ent
+    # forward + adjoint of the PPM rollout (checkpointed, FP32 state): each
+    # backward step is the residual adjoint, then the limited shift adjoint
+    kla = max(1, args.adj_steps // 2)
+    qa = q32.clone().requires_grad_(True)
+    dva = dv32.clone().requires_grad_(True)
+    v0a = v0.clone().requires_grad_(True)
+    g = torch.ones_like(q32)
+    out = rollout(qa, rows, v0a, dva, wl.dt, order, min(kla, 10), args.checkpoint,
+                  recon=R.RAM_RECON_PPM)
+    out.backward(g)                      # warm-up
+    torch.cuda.synchronize()
+    a, b = events()
+    a.record()
+    out = rollout(qa, rows, v0a, dva, wl.dt, order, kla, args.checkpoint,
+                  recon=R.RAM_RECON_PPM)
+    out.backward(g)
+    b.record()
+    torch.cuda.synchronize()
+    del out
+    hh, oo = torch.empty_like(q32), torch.empty_like(q32)
+    t_ladj = time_kernel(lambda: ctx.ram_shift_limited_adjoint(
+        rows, q32, hh, oo, v0, wl.dt, R.RAM_RECON_PPM), reps)
+    del hh, oo
+    limited["ppm_f32"]["fwd_adjoint"] = {
+        "value": round(n_cells * kla / (a.elapsed_time(b) / 1e3) / 1e9, 3),
+        "steps": kla, "checkpoint": args.checkpoint,
+        "shift_adjoint_kernel_us": round(t_ladj * 1e6, 2)}
 
     # --- forward + adjoint (checkpointed rollout) ---------------------------
     ka = args.adj_steps
@@ -363,8 +396,14 @@ def main():
                                                                  / 1e9, 1)},
         "fp32_fp64scan": {"value": round(v_f64s, 3), "steps": k2},
         "fp32_twosum_prefix": {"value": round(v_two, 3), "steps": k2s},
-        "fp64_plain": {"value": round(v64, 3), "steps": args.fp64_steps},
+        "fp64_plain": {"value": round(v64, 3), "steps": args.fp64_steps,
+                       "cumulative_differences": "FP64 window prefix sums"},
+        "fp64_direct": {"value": round(v64d, 3), "steps": args.fp64_steps,
+                        "cumulative_differences": "summed directly in FP64",
+                        "items_per_thread": items64,
+                        "tuned_us_per_step": {str(k): round(v, 2) for k, v in tune64.items()}},
         "mixed_speedup_vs_fp64": round(value / v64, 3),
+        "mixed_speedup_vs_fp64_direct": round(value / v64d, 3),
         "error": {"one_step_rel_l1_vs_oracle": err1,
                   "rollout_rel_l1_vs_fp64_path": drift,
                   "rollout_steps": args.steps + args.warmup},
