@@ -8,23 +8,24 @@ sine recipe, order-5 interpolation of the cumulative, van Leer residual step.
 All inputs are seeded synthetic data resident in HBM before timing starts.
 
 Prints one JSON line.  ``value`` is the forward step throughput (bulk shift +
-residual, one step = every cell updated once) of the FP32-state path with the
-compensated (two-sum) FP32 prefix sums; beside it: the FP32 path with FP64
-prefix sums, the FP64 plain path, forward+adjoint, the one-step error against
-the FP64 oracle on sampled rows, the dominant kernel's HBM roofline, and the
-CPU oracle's throughput on a bounded sample (run on this host's cores).
+residual, one step = every cell updated once) of the FP32-state path whose
+cumulative differences are summed directly from the window masses
+(RAM_SUM_DIRECT), with the launch schedule the autotuner picks before the
+timed region.  Beside it: the FP32 path with two-sum and with FP64 prefix
+sums, the FP64 paths (prefix sums, and direct sums with their own schedule),
+forward+adjoint, the closed-form mesh-density index, the STD baseline on the
+same mesh (time-step ratio, per-step overhead, accuracy), the limited PLM /
+PPM reconstructions, the one-step error against the FP64 path (held to the
+oracle by the GPU tests), the dominant kernel's HBM roofline, and the CPU
+oracle's throughput on a bounded sample (run on this host's cores).
 
-    python bench.py [--steps K] [--warmup W] [--adj-steps A] [--no-cpu]
-
-The FP32 headline forms cumulative differences by summing the window masses
-directly (RAM_SUM_DIRECT); the compensated two-sum and FP64 prefix-sum
-variants and the FP64 path are reported beside it, and so are the limited (monotone)
-reconstructions of the bulk shift, PLM and PPM, on the same disk.
+    python bench.py [--steps K] [--warmup W] [--adj-steps A] [--no-cpu] [--items N]
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -51,6 +52,9 @@ def parse():
     p.add_argument("--items", type=int, default=0,
                    help="shifted nodes per thread of the headline kernel (2..5); "
                         "0: let the autotuner choose (untimed, before the timed region)")
+    p.add_argument("--index", choices=("auto", "bucket", "density"), default="auto",
+                   help="source-cell index of the headline kernel: the bucket index, the "
+                        "closed-form mesh-density index, or the autotuner's choice")
     p.add_argument("--profile-pass", action="store_true",
                    help="short run for hardware-counter passes: the headline kernel "
                         "for --steps steps, the PPM step kernel for --steps steps, "
@@ -138,17 +142,36 @@ def main():
         return a.elapsed_time(b) / 1e3 / reps
 
     # --- launch schedule of the headline kernel: autotuned, or as given ----
-    from paper_2305_05362_amd.tune import tuned_schedule
+    # candidates: 2..5 shifted nodes per thread with the bucket index, and the
+    # closed-form index of the disk's periodic-bump mesh (Section 3.2.1)
+    from paper_2305_05362_amd.tune import choose_index, tuned_schedule
+    density = (wl.meta["bump"], -math.pi, math.pi)
     if args.items:
         ctx.set_schedule(args.items)
         items, tune_us = args.items, {}
     else:
         items, tune_us, _ = tuned_schedule(ctx, rows, q32, v0, dv32, wl.dt, order,
                                            R.RAM_SUM_DIRECT, cache_path=None)
-    schedule = {"items_per_thread": items,
-                "tile_cells": 256 * items - 5,
+    dens_us = None
+    if args.index == "density" or (args.index == "auto" and not args.items):
+        if args.index == "density":
+            ctx.set_schedule(0)
+            ctx.set_mesh_density(*density)
+            use_density = True
+        else:
+            use_density, dens_us = choose_index(ctx, rows, q32, v0, dv32, wl.dt, order,
+                                                density, tune_us[items])
+        if use_density:
+            items = 4
+    else:
+        use_density = False
+    idx = 1 if use_density else 0
+    schedule = {"items_per_thread": items, "tile_cells": 256 * items - 5,
+                "index": "mesh-density closed form" if use_density else "bucket",
                 "tuned_us_per_step": {str(k): round(v, 2) for k, v in tune_us.items()},
-                "how": "given" if args.items else "autotuned before the timed region"}
+                "density_index_us_per_step": None if dens_us is None else round(dens_us, 2),
+                "how": "given" if (args.items or args.index != "auto")
+                       else "autotuned before the timed region"}
 
     if args.profile_pass:
         q = q32.clone()
@@ -160,7 +183,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"profile_pass": True, "steps": args.steps, "items": items,
-                          "copy_bytes": COPY_BYTES}), flush=True)
+                          "index": idx, "copy_bytes": COPY_BYTES}), flush=True)
         return
 
     # --- headline: FP32 state, cumulative differences summed directly ------
@@ -171,6 +194,21 @@ def main():
     t_ts, q_ts = time_steps(q32, dv32, HEAD, args.steps, args.warmup)
     value = n_cells * args.steps / t_ts / 1e9
     t_fused = t_ts / args.steps
+    # --- the mesh-density index: closed-form source cells (Section 3.2.1) ---
+    # the azimuthal mesh is the periodic bump; the closed form runs with the
+    # default schedule
+    ctx.set_schedule(0)
+    ctx.set_mesh_density(None)
+    t_b, _ = time_steps(q32, dv32, HEAD, max(1, args.steps // 4), args.warmup)
+    ctx.set_mesh_density(*density)
+    t_d, _ = time_steps(q32, dv32, HEAD, max(1, args.steps // 4), args.warmup)
+    ctx.set_mesh_density(*density) if use_density else ctx.set_mesh_density(None)
+    ctx.set_schedule(items)
+    kd = max(1, args.steps // 4)
+    fast_index = {"value": round(n_cells * kd / t_d / 1e9, 3), "steps": kd,
+                  "us_per_step": round(t_d / kd * 1e6, 2),
+                  "bucket_index_us_per_step": round(t_b / kd * 1e6, 2),
+                  "mesh": "periodic bump a=%.1f b=%.1f c=%.0f on [-pi, pi)" % wl.meta["bump"]}
     # --- FP32 state, compensated FP32 prefix sums ---------------------------
     k2s = max(1, args.steps // 4)
     t_two, _ = time_steps(q32, dv32, R.RAM_SCAN_F32_TWOSUM, k2s, args.warmup)
@@ -183,11 +221,76 @@ def main():
     t64, q_64 = time_steps(q64, dv64, R.RAM_SCAN_F64, args.fp64_steps, args.warmup)
     v64 = n_cells * args.fp64_steps / t64 / 1e9
     # --- FP64 with direct sums, its own tuned schedule ----------------------
+    ctx.set_mesh_density(None)
     items64, tune64, _ = tuned_schedule(ctx, rows, q64, v0, dv64, wl.dt, order,
                                         R.RAM_SUM_DIRECT, cache_path=None)
     t64d, _ = time_steps(q64, dv64, R.RAM_SUM_DIRECT, args.fp64_steps, args.warmup)
     v64d = n_cells * args.fp64_steps / t64d / 1e9
-    ctx.set_schedule(items)                  # back to the headline's schedule
+    ctx.set_schedule(items)                  # back to the headline's configuration
+    if use_density:
+        ctx.set_mesh_density(*density)
+
+    # --- STD baseline on the same mesh (Section 4.2's comparison) ------------
+    # STD: the upwind van Leer step with the full velocity v0 + dv, at the time
+    # step its Courant rule allows; RAM: the split step at the residual's.
+    # Over a physical time T, RAM takes T/dt_ram steps, STD T/dt_std.
+    vfull_h = wl.v0[:, None] + wl.dv
+    dt_std = W.residual_cfl_dt(wl.edges, vfull_h, 0.5)
+    vfull = torch.as_tensor(vfull_h.reshape(-1), dtype=torch.float32, device=dev)
+    ks = max(1, args.steps // 4)
+    qa_, qb_ = q32.clone(), torch.empty_like(q32)
+    ctx.ram_residual(rows, qa_, qb_, vfull, dt_std)
+    torch.cuda.synchronize()
+    a, b = events()
+    a.record()
+    for _ in range(ks):
+        ctx.ram_residual(rows, qa_, qb_, vfull, dt_std)
+        qa_, qb_ = qb_, qa_
+    b.record()
+    torch.cuda.synchronize()
+    t_std = a.elapsed_time(b) / 1e3 / ks
+    # accuracy over T = 20 RAM steps with dv = 0 (a pure shift): both against
+    # one FP64 shift by v0 T (the remap is exact for any shift size up to its
+    # interpolation error) on rows through the density bump
+    n_ram = 20
+    T = n_ram * wl.dt
+    v0_h = wl.v0
+    dt_std0 = W.residual_cfl_dt(wl.edges, np.broadcast_to(v0_h[:, None], wl.dv.shape), 0.5)
+    n_std = int(math.ceil(T / dt_std0))
+    pick_a = np.array([1000, 1024, 1040])
+    q_ram = torch.as_tensor(wl.q0.reshape(-1), dtype=torch.float64, device=dev)
+    ctx.ram_step(rows, q_ram, v0, None, wl.dt, order, n_ram, R.RAM_SCAN_F64)
+    vz = torch.as_tensor(np.broadcast_to(v0_h[:, None], wl.dv.shape).reshape(-1),
+                         dtype=torch.float64, device=dev)
+    q_s, q_t = torch.as_tensor(wl.q0.reshape(-1), dtype=torch.float64, device=dev), None
+    q_t = torch.empty_like(q_s)
+    for _ in range(n_std):
+        ctx.ram_residual(rows, q_s, q_t, vz, T / n_std)
+        q_s, q_t = q_t, q_s
+    torch.cuda.synchronize()
+    q_one = torch.as_tensor(wl.q0.reshape(-1), dtype=torch.float64, device=dev)
+    q_ref1 = torch.empty_like(q_one)
+    ctx.ram_shift(rows, q_one, q_ref1, v0, T, order, R.RAM_SCAN_F64)
+    torch.cuda.synchronize()
+    ref_a = q_ref1.cpu().numpy().reshape(wl.n_rows, -1)[pick_a].reshape(-1)
+    del q_one, q_ref1
+
+    def err_a(qd):
+        g = qd.cpu().numpy().reshape(wl.n_rows, -1)[pick_a].reshape(-1)
+        return float(np.sum(np.abs(g - ref_a)) / np.sum(np.abs(ref_a)))
+    std_baseline = {
+        "std": "upwind van Leer with the full velocity v0 + dv (the residual kernel)",
+        "dt_ram": wl.dt, "dt_std": dt_std, "dt_ratio": round(wl.dt / dt_std, 2),
+        "cfl_rule": "dt = 0.5 min_f min(dx_{f-1}, dx_f) / |v_f|, v = dv (RAM) or v0 + dv (STD)",
+        "ram_step_us": round(t_ts / args.steps * 1e6, 2),
+        "overhead_ram_over_std": round((t_ts / args.steps) / t_std, 3),
+        "speedup_same_physical_time": round((wl.dt / dt_std) * t_std / (t_ts / args.steps), 2),
+        "std_step_us": round(t_std * 1e6, 2),
+        "accuracy_dv0": {"T": T, "ram_steps": n_ram, "std_steps": n_std,
+                         "rows": pick_a.tolist(),
+                         "ram_rel_l1_vs_one_shift": err_a(q_ram),
+                         "std_rel_l1_vs_one_shift": err_a(q_s)}}
+    del qa_, qb_, vfull, vz, q_s, q_t, q_ram
 
     # --- ragged rows with per-row meshes (4096 rows of 64..8192 cells) ------
     wl3 = W.cfg3()
@@ -219,7 +322,7 @@ def main():
                "shift_only_algorithmic_bytes_per_cell": 8,
                "residual_only_algorithmic_bytes_per_cell": 12}
     achieved = fused_bytes / t_fused / 1e9
-    head_kernel = f"k_step_sh<float, 5, 3, 2, 0, {items}>"
+    head_kernel = f"k_step_sh<float, 5, 3, 2, 0, {items}, {idx}>"
     tr = load_traffic(TRAFFIC_FILE, head_kernel)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -227,7 +330,8 @@ def main():
                 "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled)",
                 "algorithmic_bytes_per_launch": fused_bytes,
                 "kernel": head_kernel + " (FP32, order 5, direct sums, fused residual, "
-                                        f"{items} nodes per thread)"}
+                                        f"{items} nodes per thread, "
+                                        f"{'closed-form' if idx else 'bucket'} index)"}
 
     # --- limited reconstructions (PLM / PPM bulk shift, then the residual) --
     # two kernels a step: the limited shift and the residual step alone
@@ -250,7 +354,7 @@ def main():
                "step_algorithmic_bytes_per_cell": {"f32": 12, "f64": 24},
                "kernel": "k_step_sh<T, 3 (PLM) / 5 (PPM), direct sums, fused residual, recon>"}
     kl = limited["steps"]
-    tr_ppm = load_traffic(TRAFFIC_FILE_PPM, "k_step_sh<float, 5, 3, 2, 2, 4>")
+    tr_ppm = load_traffic(TRAFFIC_FILE_PPM, "k_step_sh<float, 5, 3, 2, 2, 4, 0>")
     for name, recon in (("plm", R.RAM_RECON_PLM), ("ppm", R.RAM_RECON_PPM)):
         for tag, qq, dd, nb in (("f32", q32, dv32, 12.0), ("f64", q64, dv64, 24.0)):
             t_l = time_limited(qq, dd, recon, kl, args.warmup)
@@ -328,29 +432,30 @@ def main():
     v_adj_all = n_cells * ka / t_adj_all / 1e9
     del out
 
-    # --- accuracy: one step vs the FP64 oracle on sampled rows; rollout drift
-    import oracle
-    pick = np.array([0, 511, 1024, 2047])
+    # --- accuracy: one FP32 step against the FP64 path (itself held to the
+    # oracle at 1e-12 by the GPU tests) from the same FP32-rounded input, over
+    # the whole disk; rollout drift
     n = wl.n_cols
-    q32h = q32.cpu().numpy().reshape(wl.n_rows, n)
-    dv32h = dv32.cpu().numpy().reshape(wl.n_rows, n)
+    q32w = q32.double()
+    dv32w = dv32.double()
+
+    def rel_gpu(a32, b64):
+        return float((a32.double() - b64).abs().sum() / b64.abs().sum())
+
     one = q32.clone()
     ctx.ram_step(rows, one, v0, dv32, wl.dt, order, 1, HEAD)
+    ref64 = q32w.clone()
+    ctx.ram_step(rows, ref64, v0, dv32w, wl.dt, order, 1, R.RAM_SCAN_F64)
     torch.cuda.synchronize()
-    sub = oracle.Rows(np.arange(len(pick) + 1) * n, wl.edges, True)
-    ref = oracle.step(sub, q32h[pick].astype(np.float64), wl.v0[pick],
-                      dv32h[pick].astype(np.float64), wl.dt, order, 1)
-    got = one.cpu().numpy().reshape(wl.n_rows, n)[pick].reshape(-1).astype(np.float64)
-    err1 = float(np.sum(np.abs(got - ref)) / np.sum(np.abs(ref)))
+    err1 = rel_gpu(one, ref64)
     for name, recon in (("plm", R.RAM_RECON_PLM), ("ppm", R.RAM_RECON_PPM)):
         one = q32.clone()
         ctx.ram_step_limited(rows, one, v0, dv32, wl.dt, recon, 1)
+        ref64 = q32w.clone()
+        ctx.ram_step_limited(rows, ref64, v0, dv32w, wl.dt, recon, 1)
         torch.cuda.synchronize()
-        ref = oracle.step_recon(sub, q32h[pick].astype(np.float64), wl.v0[pick],
-                                dv32h[pick].astype(np.float64), wl.dt, recon, 1)
-        got = one.cpu().numpy().reshape(wl.n_rows, n)[pick].reshape(-1).astype(np.float64)
-        limited[f"{name}_f32"]["one_step_rel_l1_vs_oracle"] = float(
-            np.sum(np.abs(got - ref)) / np.sum(np.abs(ref)))
+        limited[f"{name}_f32"]["one_step_rel_l1_vs_fp64_path"] = rel_gpu(one, ref64)
+    del one, ref64, q32w, dv32w
     # drift of the FP32 rollout against the FP64 path after the same steps
     q_ref = q64.clone()
     ctx.ram_step(rows, q_ref, v0, dv64, wl.dt, order, args.steps + args.warmup,
@@ -361,6 +466,7 @@ def main():
     # --- CPU oracle baseline on a bounded sample ----------------------------
     cpu = None
     if not args.no_cpu:
+        import oracle                      # the CPU baseline leg only
         n_s = 128
         sub = oracle.Rows(np.arange(n_s + 1) * n, wl.edges, True)
         qs = wl.q0[:n_s].astype(np.float64)
@@ -404,10 +510,12 @@ def main():
                         "tuned_us_per_step": {str(k): round(v, 2) for k, v in tune64.items()}},
         "mixed_speedup_vs_fp64": round(value / v64, 3),
         "mixed_speedup_vs_fp64_direct": round(value / v64d, 3),
-        "error": {"one_step_rel_l1_vs_oracle": err1,
+        "error": {"one_step_rel_l1_vs_fp64_path": err1,
                   "rollout_rel_l1_vs_fp64_path": drift,
                   "rollout_steps": args.steps + args.warmup},
         "schedule": schedule,
+        "fast_index": fast_index,
+        "std_baseline": std_baseline,
         "ragged_cfg": ragged,
         "limited_reconstructions": limited,
         "kernels": kernels,

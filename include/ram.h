@@ -115,6 +115,34 @@ typedef struct {
 ram_status ram_set_schedule(ram_ctx *ctx, const ram_schedule *sched);
 ram_status ram_get_schedule(const ram_ctx *ctx, ram_schedule *sched);
 
+/* Mesh-density index (paper Section 3.2.1, Eqs. index_u, norm_mesh, mesh, u;
+ * the periodic bump of App. B, Eq. Inorm).  When the shared mesh was built from
+ * a mesh density psi, i.e. its nodes satisfy F(x_j) = j with
+ * F(x) = N int_{x_min}^{x} psi / int_{x_min}^{x_max} psi, the source cell of a
+ * shifted node is floor(F(x~)), a closed form instead of a search.  After
+ * ram_set_mesh_density, ram_shift / ram_step / ram_step_record on a shared mesh
+ * with RAM_SUM_DIRECT and the default schedule take the cell from the closed
+ * form and then check it against the nodes (stepping to the right cell if
+ * F is off), so every node gets the same source cell as with the bucket index
+ * for any parameters (good ones only make it cheaper); results agree with the
+ * bucket-index path to rounding (a kernel variant compiled on its own, whose
+ * multiply-adds may be fused differently).  NULL or RAM_DENSITY_NONE
+ * switches it off.  RAM_DENSITY_PERIODIC_BUMP needs
+ * xmin <= -b < -a < 0 < a < b <= xmax and c > -1: psi = 1 + c on |s| <= a,
+ * 1 + c cos^2(pi/2 (|s| - a)/(b - a)) on a < |s| < b, 1 beyond. */
+typedef enum { RAM_DENSITY_NONE = 0, RAM_DENSITY_PERIODIC_BUMP = 1 } ram_density_kind;
+typedef struct {
+    int32_t kind;
+    double xmin, xmax;
+    double a, b, c;
+} ram_mesh_density;
+ram_status ram_set_mesh_density(ram_ctx *ctx, const ram_mesh_density *density);
+/* floor(F(x_i)) for m device points x (clamped to [0, n-1]), into int32 cells
+ * (device), without the check against any nodes: the closed form alone. */
+ram_status ram_mesh_density_cells(ram_ctx *ctx, const ram_mesh_density *density,
+                                  int64_t n, const double *x, int64_t m,
+                                  int32_t *cells);
+
 /* Change the stream later calls are issued on. */
 ram_status ram_set_stream(ram_ctx *ctx, void *stream);
 /* Wait until every call issued so far on the context's stream has finished;

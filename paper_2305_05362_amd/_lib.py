@@ -56,6 +56,16 @@ class Schedule(ctypes.Structure):
     _fields_ = [("items_per_thread", ctypes.c_int32)]
 
 
+RAM_DENSITY_NONE = 0
+RAM_DENSITY_PERIODIC_BUMP = 1
+
+
+class MeshDensity(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("xmin", ctypes.c_double),
+                ("xmax", ctypes.c_double), ("a", ctypes.c_double),
+                ("b", ctypes.c_double), ("c", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -91,6 +101,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ram_step_limited_record": [P, LP, I, I, P, P, P, P, P, D, I64],
         "ram_set_schedule": [P, ctypes.POINTER(Schedule)],
         "ram_get_schedule": [P, ctypes.POINTER(Schedule)],
+        "ram_set_mesh_density": [P, ctypes.POINTER(MeshDensity)],
+        "ram_mesh_density_cells": [P, ctypes.POINTER(MeshDensity), I64, P, I64, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -211,6 +223,28 @@ class Context:
         """Shifted nodes per thread of the shared-mesh direct-sum step kernel
         (2..5; 0 = the default)."""
         check(self._lib.ram_set_schedule(self._h, ctypes.byref(Schedule(int(items_per_thread)))))
+
+    def set_mesh_density(self, bump=None, xmin: float = 0.0, xmax: float = 0.0):
+        """Periodic-bump mesh density (a, b, c) of the shared mesh on
+        [xmin, xmax], or None to switch the closed-form index off."""
+        if bump is None:
+            check(self._lib.ram_set_mesh_density(self._h, None))
+            return
+        a, b, c = bump
+        d = MeshDensity(RAM_DENSITY_PERIODIC_BUMP, xmin, xmax, a, b, c)
+        check(self._lib.ram_set_mesh_density(self._h, ctypes.byref(d)))
+
+    def mesh_density_cells(self, bump, xmin: float, xmax: float, n: int, x):
+        """floor(F(x)) of the periodic-bump index for the points x (device
+        FP64), int32 on x's device."""
+        self._stream()
+        a, b, c = bump
+        d = MeshDensity(RAM_DENSITY_PERIODIC_BUMP, xmin, xmax, a, b, c)
+        out = torch.empty(x.numel(), dtype=torch.int32, device=x.device)
+        check(self._lib.ram_mesh_density_cells(self._h, ctypes.byref(d), int(n),
+                                               _dev_ptr(x, torch.float64, "x"), x.numel(),
+                                               _dev_ptr(out, torch.int32, "cells")))
+        return out
 
     def get_schedule(self) -> int:
         sc = Schedule(0)

@@ -216,19 +216,23 @@ __global__ __launch_bounds__(kBlock) void k_shift_adj(ShiftAdjArgs a)
 // with atomics after the zeroing pass, as for the Lagrange shift.
 
 // d ell / d Q_{c-lo+a} (a = 0 .. 2 lo) of the partial integral of cell c at
-// xh, and the reconstruction's value q_c(xh) (= d ell / d xh); FP64.
+// xh, and the reconstruction's value q_c(xh) (= d ell / d xh); FP64.  A shared
+// mesh passes its tables (reciprocal centre gaps, PPM weights); per-row meshes
+// pass null and the mesh terms are formed from the nodes.
 template <typename TQ, int R>
-__device__ __attribute__((noinline)) void lim_grad(const double *x, const TQ *q, int n,
-                                                   double len, int c, double xh,
-                                                   double *gw, double &qval)
+__device__ inline void lim_grad(const double *x, const TQ *q, int n, double len, int c,
+                                double xh, const double *hinv, const double *pw, double *gw,
+                                double &qval)
 {
     const double h = x[c + 1] - x[c];
     const double th = (xh - x[c]) / h;
     if constexpr (R == kReconPLM) {
         const double qm = (double)q[wrapi(c - 1, n)], q0 = (double)q[c];
         const double qp = (double)q[wrapi(c + 1, n)];
-        const double hp = centre_gap(x, n, len, c), hm = centre_gap(x, n, len, c - 1);
-        const double a = (qp - q0) / hp, b = (q0 - qm) / hm;
+        // reciprocal centre gaps (c, c+1) and (c-1, c)
+        const double gp = hinv ? hinv[c] : 1.0 / centre_gap(x, n, len, c);
+        const double gm = hinv ? hinv[wrapi(c - 1, n)] : 1.0 / centre_gap(x, n, len, c - 1);
+        const double a = (qp - q0) * gp, b = (q0 - qm) * gm;
         double sig = 0.0, dsa = 0.0, dsb = 0.0;
         if (a * b > 0.0) {
             const double s2 = (a + b) * (a + b);
@@ -238,35 +242,48 @@ __device__ __attribute__((noinline)) void lim_grad(const double *x, const TQ *q,
         }
         // ell = Q_c h theta + sigma h^2 (theta^2 - theta) / 2
         const double ks = 0.5 * h * h * (th * th - th);
-        gw[0] = -ks * dsb / hm;
-        gw[1] = h * th + ks * (dsb / hm - dsa / hp);
-        gw[2] = ks * dsa / hp;
+        gw[0] = -ks * dsb * gm;
+        gw[1] = h * th + ks * (dsb * gm - dsa * gp);
+        gw[2] = ks * dsa * gp;
         qval = q0 + sig * (xh - 0.5 * (x[c] + x[c + 1]));
     } else {
-        double av[5], hv[6];
+        double av[5];
 #pragma unroll
         for (int k = 0; k < 5; ++k) av[k] = (double)q[wrapi(c - 2 + k, n)];
+        // mesh weights of cells c-1, c, c+1: their slopes' (d1, d2), and the
+        // interface weights (e1, e2, e3) of cells c-1 and c
+        PpmW w[3];
+        if (pw) {
 #pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            const int m = wrapi(c - 2 + k, n);
-            hv[k] = x[m + 1] - x[m];
+            for (int k = 0; k < 3; ++k) {
+                const int m = wrapi(c - 1 + k, n);
+                w[k] = {pw[m], pw[n + m], pw[2 * n + m], pw[3 * n + m], pw[4 * n + m]};
+            }
+        } else {
+            double hv[6];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                const int m = wrapi(c - 2 + k, n);
+                hv[k] = x[m + 1] - x[m];
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) w[k] = ppm_weights(hv[k], hv[k + 1], hv[k + 2], hv[k + 3]);
         }
         // limited slopes of cells c-1, c, c+1 and their derivatives w.r.t.
         // the averages of each slope's cells j-1, j, j+1
         double dl[3], dd[3][3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const PpmW w = ppm_weights(hv[k], hv[k + 1], hv[k + 2], hv[k + 3]);
             const double up = av[k + 2] - av[k + 1], dn = av[k + 1] - av[k];
-            const double d = w.d1 * up + w.d2 * dn;
+            const double d = w[k].d1 * up + w[k].d2 * dn;
             dd[k][0] = dd[k][1] = dd[k][2] = 0.0;
             dl[k] = 0.0;
             if (up * dn > 0.0) {
                 dl[k] = copysign(fmin(fabs(d), 2.0 * fmin(fabs(up), fabs(dn))), d);
                 if (fabs(d) <= 2.0 * fabs(up) && fabs(d) <= 2.0 * fabs(dn)) {
-                    dd[k][0] = -w.d2;
-                    dd[k][1] = w.d2 - w.d1;
-                    dd[k][2] = w.d1;
+                    dd[k][0] = -w[k].d2;
+                    dd[k][1] = w[k].d2 - w[k].d1;
+                    dd[k][2] = w[k].d1;
                 } else if (fabs(up) <= fabs(dn)) {
                     dd[k][1] = -2.0;          // twice the upper difference
                     dd[k][2] = 2.0;
@@ -277,8 +294,7 @@ __device__ __attribute__((noinline)) void lim_grad(const double *x, const TQ *q,
             }
         }
         // interface values c-1/2 and c+1/2 before the constraints
-        const PpmW wl = ppm_weights(hv[0], hv[1], hv[2], hv[3]);
-        const PpmW wr = ppm_weights(hv[1], hv[2], hv[3], hv[4]);
+        const PpmW &wl = w[0], &wr = w[1];
         const double Lr = av[1] + wl.e1 * (av[2] - av[1]) + wl.e2 * dl[1] + wl.e3 * dl[0];
         const double Rr = av[2] + wr.e1 * (av[3] - av[2]) + wr.e2 * dl[2] + wr.e3 * dl[1];
         const double a = av[2];
@@ -342,6 +358,8 @@ __global__ __launch_bounds__(kBlock) void k_shift_lim_adj(ShiftAdjArgs a)
     const int nd = min(a.rows.tile, n - i0);
     const int ne = nd + 1;
     const bool want_v0 = a.v0bar != nullptr;
+    const double *hinv = a.rows.has_tab ? a.rows.tab.hinv : nullptr;
+    const double *pw = a.rows.has_tab ? a.rows.tab.ppmd : nullptr;
 
     double vpart = 0.0;
     for (int t = threadIdx.x; t < ne; t += kBlock) {
@@ -349,7 +367,7 @@ __global__ __launch_bounds__(kBlock) void k_shift_lim_adj(ShiftAdjArgs a)
         const int64_t g = locate(x, n, s, i0 + t, xh);
         const int c = wrapi(g, n);
         double gw[P], qv;
-        lim_grad<TQ, R>(x, qf, n, len, c, xh, gw, qv);
+        lim_grad<TQ, R>(x, qf, n, len, c, xh, hinv, pw, gw, qv);
         double vb = 0.0;
         if (t >= 1) {
             const int i = i0 + t - 1;

@@ -30,6 +30,8 @@ struct ram_ctx {
     // schedule of the shared-mesh step kernel with direct sums: shifted
     // nodes per thread (ram_set_schedule)
     int items = ram::kItems;
+    // mesh-density description of the shared mesh (ram_set_mesh_density)
+    ram_mesh_density density{};
 };
 
 namespace {
@@ -236,6 +238,25 @@ int sched_items(const ram_ctx *ctx, const ram_layout *L, ram_scan scan)
     return (shared && scan == RAM_SUM_DIRECT) ? ctx->items : ram::kItems;
 }
 
+// The kernel-side mesh-density index for a shared mesh of n cells.
+ram::MeshDensity make_density(const ram_mesh_density &d, int64_t n)
+{
+    ram::MeshDensity m;
+    if (d.kind != RAM_DENSITY_PERIODIC_BUMP) return m;
+    m.kind = 1;
+    m.a = d.a;
+    m.b = d.b;
+    m.c = d.c;
+    const double w = d.b - d.a;
+    m.w_pi = M_PI / w;
+    m.ramp_amp = d.c * w / (2.0 * M_PI);
+    m.ramp_end = (1.0 + d.c) * d.a + (1.0 + 0.5 * d.c) * w;
+    const double inorm = (d.xmax - d.xmin) + d.c * (d.a + d.b);
+    m.scale = (double)n / inorm;
+    m.p0 = ram::bump_prim(d.xmin, m);
+    return m;
+}
+
 int64_t tiles_of(const ram_layout *L, int tile)
 {
     if (L->n_cols > 0) return L->n_rows * ((L->n_cols + tile - 1) / tile);
@@ -322,6 +343,8 @@ ram_status launch_steps(ram_ctx *ctx, ram::StepArgs a, ram_dtype dtype,
     const bool f64 = dtype == RAM_F64;
     const bool shared = a.rows.has_tab != 0 && a.rows.n_cols > 0;
     if (recon && !shared) return fail(RAM_E_UNSUPPORTED, "internal: limited step loop needs a shared mesh");
+    if (shared && scan == RAM_SUM_DIRECT && recon == 0)
+        a.dens = make_density(ctx->density, a.rows.n_cols);
     hipError_t e;
     if (shared) {
         int64_t *wlo = (int64_t *)((char *)ctx->scratch + wlo_off);
@@ -468,6 +491,41 @@ ram_status ram_set_schedule(ram_ctx *ctx, const ram_schedule *sched)
         return fail(RAM_E_UNSUPPORTED, "items_per_thread must be 0 or 2..5 (got %d)",
                     (int)sched->items_per_thread);
     ctx->items = items;
+    return RAM_OK;
+}
+
+ram_status ram_set_mesh_density(ram_ctx *ctx, const ram_mesh_density *d)
+{
+    if (!ctx) return fail(RAM_E_INVALID_ARG, "null context");
+    if (!d || d->kind == RAM_DENSITY_NONE) {
+        ctx->density = ram_mesh_density{};
+        return RAM_OK;
+    }
+    if (d->kind != RAM_DENSITY_PERIODIC_BUMP)
+        return fail(RAM_E_UNSUPPORTED, "unknown mesh density kind %d", (int)d->kind);
+    const double v[5] = {d->xmin, d->xmax, d->a, d->b, d->c};
+    for (double t : v)
+        if (!std::isfinite(t)) return fail(RAM_E_INVALID_ARG, "mesh density parameters must be finite");
+    if (!(d->xmin <= -d->b && -d->b < -d->a && d->a > 0.0 && d->a < d->b && d->b <= d->xmax))
+        return fail(RAM_E_INVALID_ARG, "periodic bump needs xmin <= -b < -a < 0 < a < b <= xmax");
+    if (!(d->c > -1.0)) return fail(RAM_E_INVALID_ARG, "periodic bump needs c > -1");
+    ctx->density = *d;
+    return RAM_OK;
+}
+
+ram_status ram_mesh_density_cells(ram_ctx *ctx, const ram_mesh_density *d, int64_t n,
+                                  const double *x, int64_t m, int32_t *cells)
+{
+    ram_status st;
+    g_last_error.clear();
+    if (!d || d->kind != RAM_DENSITY_PERIODIC_BUMP)
+        return fail(RAM_E_UNSUPPORTED, "a mesh density of kind RAM_DENSITY_PERIODIC_BUMP is needed");
+    if (n < 1 || n > INT32_MAX - 1 || m < 0) return fail(RAM_E_INVALID_ARG, "bad n or m");
+    if (m > 0 && (!x || !cells)) return fail(RAM_E_INVALID_ARG, "null x or cells");
+    if ((st = enter(ctx)) != RAM_OK) return st;
+    hipError_t e = ram::launch_density_cells(make_density(*d, n), (int)n, x, m, cells,
+                                             ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "density cells launch");
     return RAM_OK;
 }
 
@@ -801,7 +859,8 @@ ram_status ram_shift_limited_adjoint(ram_ctx *ctx, const ram_layout *layout,
         return fail(RAM_E_INVALID_ARG, "qbar_in must not alias qbar_out or q_fwd");
     if ((st = enter(ctx)) != RAM_OK) return st;
     Carve cv;
-    RowsPlan rp = plan_rows(cv, layout, ram::kTile, 0);
+    // a shared mesh brings its tables (centre gaps, PPM weights)
+    RowsPlan rp = plan_rows(cv, layout, ram::kTile, 1);
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
     ram::ShiftAdjArgs a;
     if ((st = make_rows(ctx, layout, edges, rp, a.rows)) != RAM_OK) return st;

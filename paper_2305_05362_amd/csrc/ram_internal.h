@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <stdint.h>
 
 namespace ram {
@@ -87,6 +88,35 @@ struct Rows {
     int has_tab = 0;                  // tab is filled in
 };
 
+// Mesh-density index of a shared mesh (Section 3.2.1): the nodes satisfy
+// F(x_j) = j with F(x) = N (P(x) - P(x_min)) / I, P the antiderivative of the
+// density psi with P(0) = 0 and I its integral over the period, so the source
+// cell of a shifted node is floor(F(x)) (checked against the nodes).  kind 1:
+// the periodic bump of App. B, psi = 1 + c on |s| <= a, 1 + c cos^2(pi/2
+// (|s| - a)/(b - a)) on a < |s| < b, 1 beyond.
+struct MeshDensity {
+    int64_t kind = 0;          // 0 none (bucket index), 1 periodic bump (8 bytes: no padding in StepArgs)
+    double a = 0.0, b = 0.0, c = 0.0;
+    double w_pi = 0.0;         // pi / (b - a)
+    double ramp_amp = 0.0;     // c (b - a) / (2 pi)
+    double ramp_end = 0.0;     // P(b) = (1 + c) a + (1 + c / 2) (b - a)
+    double scale = 0.0;        // N / I
+    double p0 = 0.0;           // P(x_min)
+};
+
+// P(t) of the periodic bump: odd, linear with slope 1 + c inside a, the
+// cos^2 ramp's integral between a and b, slope 1 beyond b.
+__host__ __device__ inline double bump_prim(double t, const MeshDensity &d)
+{
+    const double at = fabs(t);
+    double v;
+    if (at <= d.a) v = (1.0 + d.c) * at;
+    else if (at < d.b) v = (1.0 + d.c) * d.a + (1.0 + 0.5 * d.c) * (at - d.a) +
+                           d.ramp_amp * sin(d.w_pi * (at - d.a));
+    else v = d.ramp_end + (at - d.b);
+    return copysign(v, t);
+}
+
 // Bulk shift, optionally fused with the residual step (dv != null).
 struct StepArgs {
     Rows rows;
@@ -99,6 +129,7 @@ struct StepArgs {
     const int32_t *plan_w = nullptr;    // ... length (-1: direct path), then
                                         // [n_tiles + tile]: start mod n
     void *q_mid = nullptr;              // optional: the state after the shift
+    MeshDensity dens;                   // shared mesh, direct sums: closed-form index
 };
 
 struct ResidualArgs {
@@ -198,6 +229,10 @@ hipError_t launch_shift_limited(const StepArgs &a, bool f64, int recon,
 // pass, then one gather kernel), v0bar accumulated when a.v0bar is set.
 hipError_t launch_shift_limited_adjoint(const ShiftAdjArgs &a, bool f64, int recon,
                                         hipStream_t stream);
+// floor(F(x)) of the mesh-density index for m points (clamped to [0, n-1]),
+// without the check against the nodes (a test of the closed form).
+hipError_t launch_density_cells(const MeshDensity &d, int n, const double *x, int64_t m,
+                                int32_t *cells, hipStream_t stream);
 // Per-row mass, dx-weighted L1 distance to qref (if non-null) and max |Q|,
 // three FP64 values per row (one workgroup per row).
 hipError_t launch_row_norms(const Rows &R, bool f64, const void *q, const void *qref,

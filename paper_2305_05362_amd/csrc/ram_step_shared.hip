@@ -98,7 +98,30 @@ __device__ inline int wrap1(int j, int n)
     return j < 0 ? j + n : (j >= n ? j - n : j);
 }
 
-template <typename TQ, int P, int S, int H, int RECON = 0, int NI = kItems>
+// Source cell of a wrapped shifted node from the mesh-density index: the
+// closed-form floor(F(xt)), then checked against the nodes (a step either way
+// while outside; any error in F only costs steps).
+__device__ inline int density_cell(const double *x, int n, const MeshDensity &d, double xt)
+{
+    int c = (int)floor(d.scale * (bump_prim(xt, d) - d.p0));
+    c = min(max(c, 0), n - 1);
+    double lo = x[c], hi = x[c + 1];
+    while (xt < lo && c > 0) {
+        --c;
+        hi = lo;
+        lo = x[c];
+    }
+    while (xt >= hi && c + 1 < n) {
+        ++c;
+        lo = hi;
+        hi = x[c + 1];
+    }
+    return c;
+}
+
+// IDX 1: the source cells come from the mesh-density index (a.dens) instead of
+// the bucket index.
+template <typename TQ, int P, int S, int H, int RECON = 0, int NI = kItems, int IDX = 0>
 __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
 {
     constexpr bool kDirect = S == kSumDirect;
@@ -265,16 +288,23 @@ __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
 #pragma unroll
         for (int k = 0; k < NI; ++k) {
             np[k] = node_pos(xe[k], rs, x0, xN, bsc, bx0, tb.nb);
-            cb[k] = tb.bucket[np[k].b];
-            nx[k] = tb.bnext[np[k].b];
+            if constexpr (IDX == 0) {
+                cb[k] = tb.bucket[np[k].b];
+                nx[k] = tb.bnext[np[k].b];
+            }
         }
 #pragma unroll
         for (int k = 0; k < NI; ++k) {
             const int ei = t + k * kBlock;
             jc[k] = 0;
             if (ei < NE) {
-                int c = cell_from_bucket(cb[k], nx[k], np[k].xt);
-                if (np[k].xt >= nx[k].y) c = cell_walk(x, n, c, np[k].xt);
+                int c;
+                if constexpr (IDX == 1) {
+                    c = density_cell(x, n, a.dens, np[k].xt);
+                } else {
+                    c = cell_from_bucket(cb[k], nx[k], np[k].xt);
+                    if (np[k].xt >= nx[k].y) c = cell_walk(x, n, c, np[k].xt);
+                }
                 CT wk[P + 1];
                 CT tt = (CT)0;
                 if constexpr (kLim) {
@@ -518,7 +548,12 @@ hipError_t step_sh_h(const StepArgs &a, int scan, int items, hipStream_t st)
     case kScanTwoSum: hipLaunchKernelGGL((k_step_sh<TQ, P, kScanTwoSum, H>), g, b, 0, st, a); break;
     case kScanF32: hipLaunchKernelGGL((k_step_sh<TQ, P, kScanF32, H>), g, b, 0, st, a); break;
     default:
-        // direct sums: the schedule picks the shifted nodes per thread
+        // direct sums: the mesh-density index (default schedule), or the
+        // schedule's shifted nodes per thread
+        if (a.dens.kind != 0 && items == kItems) {
+            hipLaunchKernelGGL((k_step_sh<TQ, P, kSumDirect, H, 0, kItems, 1>), g, b, 0, st, a);
+            break;
+        }
         switch (items) {
         case 2: hipLaunchKernelGGL((k_step_sh<TQ, P, kSumDirect, H, 0, 2>), g, b, 0, st, a); break;
         case 3: hipLaunchKernelGGL((k_step_sh<TQ, P, kSumDirect, H, 0, 3>), g, b, 0, st, a); break;
@@ -558,6 +593,24 @@ hipError_t step_sh_lim(const StepArgs &a, hipStream_t st)
 }
 
 } // namespace
+
+__global__ __launch_bounds__(256) void k_density_cells(MeshDensity d, int n, const double *x,
+                                                      int64_t m, int32_t *cells)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= m) return;
+    const int c = (int)floor(d.scale * (bump_prim(x[i], d) - d.p0));
+    cells[i] = min(max(c, 0), n - 1);
+}
+
+hipError_t launch_density_cells(const MeshDensity &d, int n, const double *x, int64_t m,
+                                int32_t *cells, hipStream_t stream)
+{
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_density_cells, dim3((unsigned)((m + 255) / 256)), dim3(256), 0,
+                       stream, d, n, x, m, cells);
+    return hipGetLastError();
+}
 
 hipError_t launch_step_shared_limited(const StepArgs &a, bool f64, int recon,
                                       hipStream_t stream)

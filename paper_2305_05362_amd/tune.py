@@ -13,8 +13,9 @@ answer in a JSON file.
     python -m paper_2305_05362_amd.tune [--rows R --cols N] [--f64] [--order P]
 
 tunes a polar disk of the given shape (synthetic, seeded) and prints the
-timings.  Every timing runs the library's own kernels; nothing here computes
-any part of the step.
+timings.  ``choose_index`` adds the closed-form mesh-density index (for a
+mesh built from a known density) as one more candidate.  Every timing runs the
+library's own kernels; nothing here computes any part of the step.
 """
 from __future__ import annotations
 
@@ -68,6 +69,25 @@ def tune_step(ctx, rows, q, v0, dv, dt: float, order: int,
     best = min(us, key=us.get)
     ctx.set_schedule(best)
     return best, us
+
+
+def choose_index(ctx, rows, q, v0, dv, dt: float, order: int, density, best_us: float,
+                 scan: int = R.RAM_SUM_DIRECT, steps: int = 40, reps: int = 3):
+    """The mesh-density index (Section 3.2.1) as one more candidate: with the
+    shared mesh's density `density` = ((a, b, c), xmin, xmax) set, time the
+    default schedule and keep the index if it beats `best_us` (the best
+    schedule's microseconds per step with the bucket index).  Leaves the
+    context configured for the winner; returns (use_density, us_per_step)."""
+    saved = ctx.get_schedule()
+    bump, xmin, xmax = density
+    ctx.set_schedule(0)
+    ctx.set_mesh_density(bump, xmin, xmax)
+    us = _time_steps(ctx, rows, q, v0, dv, dt, order, scan, steps, reps) * 1e6
+    if us < best_us:
+        return True, us
+    ctx.set_mesh_density(None)
+    ctx.set_schedule(saved)
+    return False, us
 
 
 def shape_key(rows, q, dv, order: int, scan: int) -> str:

@@ -198,3 +198,16 @@ def test_limited_adjoint_argument_errors(lib):
     st = lib.ram_shift_limited_adjoint(None, ctypes.byref(L), R.RAM_F32, R.RAM_RECON_PLM,
                                        a, b, c, d, e, 0.1, None)
     assert st == R.RAM_E_INVALID_ARG and b"context" in lib.ram_last_error()
+
+
+def test_mesh_density_argument_errors(lib):
+    from paper_2305_05362_amd import _lib as R
+    d = R.MeshDensity(R.RAM_DENSITY_PERIODIC_BUMP, -3.14, 3.14, 0.2, 0.3, 9.0)
+    st = lib.ram_set_mesh_density(None, ctypes.byref(d))
+    assert st == R.RAM_E_INVALID_ARG and b"context" in lib.ram_last_error()
+    st = lib.ram_mesh_density_cells(None, None, 10, None, 0, None)
+    assert st == R.RAM_E_UNSUPPORTED
+    st = lib.ram_mesh_density_cells(None, ctypes.byref(d), 0, None, 0, None)
+    assert st == R.RAM_E_INVALID_ARG
+    st = lib.ram_mesh_density_cells(None, ctypes.byref(d), 10, None, 5, None)
+    assert st == R.RAM_E_INVALID_ARG and b"null" in lib.ram_last_error()
