@@ -20,6 +20,8 @@ Every function follows one passage of the paper:
   step_recon       the split step built on it;
   shift_recon_adjoint  transpose of the limited shift's Jacobian at the
                    forward state (the branch each limiter takes), plus dL/dv0;
+  radial           the radial transport of a polar grid (the residual's upwind
+                   scheme along r in polar geometry, closed edges);
   shift_adjoint    transpose of the (linear) shift, plus dL/dv0;
   residual_adjoint transpose of the residual Jacobian, plus dL/d(dv).
 
@@ -76,10 +78,12 @@ def _load():
     lib.oracle_recon_cells.argtypes = [P, P, I64, I, I, P, P, P]
     lib.oracle_edges_recon.argtypes = [P, P, I64, D, I, P, P]
     lib.oracle_shift_recon_adjoint.argtypes = [I64, P, P, I, P, P, P, P, D, I, P, I]
+    lib.oracle_radial.argtypes = [I64, I64, P, P, P, D, P, I]
     for f in ("oracle_shift", "oracle_residual", "oracle_step",
               "oracle_shift_adjoint", "oracle_residual_adjoint", "oracle_edges",
               "oracle_max_threads", "oracle_shift_recon", "oracle_step_recon",
-              "oracle_recon_cells", "oracle_edges_recon", "oracle_shift_recon_adjoint"):
+              "oracle_recon_cells", "oracle_edges_recon", "oracle_shift_recon_adjoint",
+              "oracle_radial"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -276,3 +280,18 @@ def shift_recon_adjoint(rows: Rows, q, qbar_out, v0, dt: float, recon: int,
                                             int(recon), _ptr(v0bar), int(nthreads))
     _check(rc, "shift_recon_adjoint")
     return out, v0bar
+
+
+def radial(r_edges, q, u, dt: float, nthreads: int = 0) -> np.ndarray:
+    """Radial transport step: q [n_rows, n_cols] (rows = radii), u
+    [n_rows + 1, n_cols] on the radial faces, r_edges [n_rows + 1]."""
+    re = _f64(r_edges)
+    q = _f64(q)
+    u = _f64(u)
+    n_rows, n_cols = q.shape
+    assert u.shape == (n_rows + 1, n_cols) and re.shape == (n_rows + 1,)
+    out = np.empty_like(q)
+    rc = _load().oracle_radial(n_rows, n_cols, _ptr(re), _ptr(q), _ptr(u), float(dt),
+                               _ptr(out), int(nthreads))
+    _check(rc, "radial")
+    return out
