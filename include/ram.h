@@ -290,6 +290,37 @@ ram_status ram_row_norms(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype
                          const void *q, const void *q_ref, const double *edges,
                          double *out);
 
+/* Radial transport of a polar grid: the standard-upwind half of a 2D
+ * dimensionally split step (paper Section 3: RAM along the direction of the
+ * bulk velocity, standard transport across it).  Rows are radii bounded by
+ * r_edges[0..n_rows] (FP64, device, increasing); every column (azimuthal
+ * cell) is advected along r by the radial velocity u on the radial faces
+ * ([n_rows + 1][n_cols], dtype; face j between rows j-1 and j) with the
+ * residual's upwind scheme (PLM, van Leer slope from centre gaps,
+ * swept-interval face value) in polar geometry:
+ *   q'_j = q_j - dt (r_{j+1/2} F_{j+1/2} - r_{j-1/2} F_{j-1/2}) / A_j,
+ *   F = u q*, A_j = (r_{j+1/2}^2 - r_{j-1/2}^2) / 2,
+ * with no flux through the inner and outer edges (u there is ignored) and a
+ * zero slope in the first and last rows, so sum_j A_j q_j of every column is
+ * conserved.  Uniform rows (n_cols > 0, at most 65535 rows); q_in, q_out
+ * must not alias.  Requires |u| dt <= the adjacent radial widths (not
+ * checked). */
+ram_status ram_radial_step(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
+                           const void *q_in, void *q_out, const double *r_edges,
+                           const void *u, double dt);
+
+/* n_steps 2D dimensionally split steps on a polar grid (Section 3), q in
+ * place.  Each step: the step along the rows (the bulk shift by v0[r] dt,
+ * then the residual with dv) -- ram_step's with recon = 0 (order, scan, its
+ * schedule and mesh density), or ram_step_limited's with recon = PLM / PPM
+ * (shared azimuthal mesh only; order and scan unused) -- then
+ * ram_radial_step across the rows with u.  Arguments as for those calls;
+ * loops of four or more steps are captured into a graph. */
+ram_status ram_step_split2d(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
+                            ram_scan scan, ram_recon recon, void *q, const double *edges,
+                            const double *v0, const void *dv, const double *r_edges,
+                            const void *u, double dt, int order, int64_t n_steps);
+
 /* Host-side check of the inputs (synchronous; copies to the host): strictly
  * increasing finite nodes (RAM_E_MESH), and when dv != NULL the residual
  * Courant condition |dv_f| dt <= min(dx_{f-1}, dx_f) (RAM_E_CFL). */

@@ -102,6 +102,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ram_set_schedule": [P, ctypes.POINTER(Schedule)],
         "ram_get_schedule": [P, ctypes.POINTER(Schedule)],
         "ram_set_mesh_density": [P, ctypes.POINTER(MeshDensity)],
+        "ram_radial_step": [P, LP, I, P, P, P, P, D],
+        "ram_step_split2d": [P, LP, I, I, I, P, P, P, P, P, P, D, I, I64],
         "ram_mesh_density_cells": [P, ctypes.POINTER(MeshDensity), I64, P, I64, P],
     }
     for name, args in sig.items():
@@ -295,6 +297,26 @@ class Context:
             _dev_ptr(v0bar, torch.float64, "v0bar")))
         return qbar_in
 
+    def ram_radial_step(self, rows: Rows, q_in, q_out, r_edges, u, dt: float):
+        self._stream()
+        check(self._lib.ram_radial_step(
+            self._h, ctypes.byref(rows.layout), _dtype_code(q_in),
+            _dev_ptr(q_in, q_in.dtype, "q_in"), _dev_ptr(q_out, q_in.dtype, "q_out"),
+            _dev_ptr(r_edges, torch.float64, "r_edges"), _dev_ptr(u, q_in.dtype, "u"),
+            float(dt)))
+        return q_out
+
+    def ram_step_split2d(self, rows: Rows, q, v0, dv, r_edges, u, dt: float, order: int,
+                         n_steps: int, scan: int = RAM_SCAN_F64, recon: int = 0):
+        self._stream()
+        check(self._lib.ram_step_split2d(
+            self._h, ctypes.byref(rows.layout), _dtype_code(q), int(scan), int(recon),
+            _dev_ptr(q, q.dtype, "q"), _dev_ptr(rows.edges, torch.float64, "edges"),
+            _dev_ptr(v0, torch.float64, "v0"), _dev_ptr(dv, q.dtype, "dv"),
+            _dev_ptr(r_edges, torch.float64, "r_edges"), _dev_ptr(u, q.dtype, "u"),
+            float(dt), int(order), int(n_steps)))
+        return q
+
     def ram_row_norms(self, rows: Rows, q, q_ref=None, out=None):
         """Per-row (mass, dx-weighted L1 distance to q_ref, max |q|), FP64
         tensor of shape [n_rows, 3] on q's device."""
@@ -427,6 +449,16 @@ def ram_shift_limited_adjoint(rows, q_fwd, qbar_out, qbar_in, v0, dt, recon, v0b
 
 def ram_row_norms(rows, q, q_ref=None, out=None):
     return context(q.device.index).ram_row_norms(rows, q, q_ref, out)
+
+
+def ram_radial_step(rows, q_in, q_out, r_edges, u, dt):
+    return context(q_in.device.index).ram_radial_step(rows, q_in, q_out, r_edges, u, dt)
+
+
+def ram_step_split2d(rows, q, v0, dv, r_edges, u, dt, order, n_steps, scan=RAM_SCAN_F64,
+                     recon=0):
+    return context(q.device.index).ram_step_split2d(rows, q, v0, dv, r_edges, u, dt, order,
+                                                    n_steps, scan, recon)
 
 
 def ram_residual(rows, q_in, q_out, dv, dt):

@@ -876,6 +876,129 @@ ram_status ram_shift_limited_adjoint(ram_ctx *ctx, const ram_layout *layout,
     return RAM_OK;
 }
 
+// q_out == nullptr checks an in-place caller (q_in is its state)
+ram_status check_radial(const ram_layout *layout, ram_dtype dtype, const void *q_in,
+                        const void *q_out, const double *r_edges, const void *u, double dt,
+                        bool in_place = false)
+{
+    ram_status st;
+    if (!layout) return fail(RAM_E_INVALID_ARG, "null layout");
+    if (layout->n_cols <= 0 || layout->n_rows < 1)
+        return fail(RAM_E_INVALID_ARG, "radial transport needs uniform rows (n_cols > 0)");
+    if (layout->n_rows > 65535) return fail(RAM_E_INVALID_ARG, "at most 65535 radial rows");
+    if ((st = check_dtype(dtype)) != RAM_OK) return st;
+    if ((st = check_dt(dt)) != RAM_OK) return st;
+    if (!q_in || (!q_out && !in_place) || !r_edges || !u)
+        return fail(RAM_E_INVALID_ARG, "null q, r_edges or u");
+    if (q_in == q_out) return fail(RAM_E_INVALID_ARG, "q_in and q_out must not alias");
+    return RAM_OK;
+}
+
+ram_status ram_radial_step(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
+                           const void *q_in, void *q_out, const double *r_edges,
+                           const void *u, double dt)
+{
+    ram_status st;
+    g_last_error.clear();
+    if ((st = check_radial(layout, dtype, q_in, q_out, r_edges, u, dt)) != RAM_OK) return st;
+    if ((st = enter(ctx)) != RAM_OK) return st;
+    ram::RadialArgs r;
+    r.n_rows = layout->n_rows;
+    r.n_cols = layout->n_cols;
+    r.r_edges = r_edges;
+    r.q_in = q_in;
+    r.q_out = q_out;
+    r.u = u;
+    r.dt = dt;
+    hipError_t e = ram::launch_radial(r, dtype == RAM_F64, ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "radial step launch");
+    return RAM_OK;
+}
+
+ram_status ram_step_split2d(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
+                            ram_scan scan, ram_recon recon, void *q, const double *edges,
+                            const double *v0, const void *dv, const double *r_edges,
+                            const void *u, double dt, int order, int64_t n_steps)
+{
+    ram_status st;
+    g_last_error.clear();
+    if ((st = check_layout(layout, edges)) != RAM_OK) return st;
+    if (recon == 0) {
+        if ((st = check_scan(dtype, scan)) != RAM_OK) return st;
+        if ((st = check_order(layout, order)) != RAM_OK) return st;
+    } else {
+        if ((st = check_dtype(dtype)) != RAM_OK) return st;
+        if ((st = check_recon(layout, recon)) != RAM_OK) return st;
+        if (!layout->edges_shared)
+            return fail(RAM_E_UNSUPPORTED, "limited split steps need a shared azimuthal mesh");
+        scan = RAM_SUM_DIRECT;
+    }
+    if ((st = check_radial(layout, dtype, q, nullptr, r_edges, u, dt, true)) != RAM_OK) return st;
+    if (!v0) return fail(RAM_E_INVALID_ARG, "null v0");
+    if (n_steps < 0) return fail(RAM_E_INVALID_ARG, "n_steps must be >= 0");
+    if (n_steps == 0) return RAM_OK;
+    if ((st = enter(ctx)) != RAM_OK) return st;
+    const size_t state_bytes = elem_size(dtype) * (size_t)layout_cells(layout);
+    const int items = recon ? ram::kItems : sched_items(ctx, layout, scan);
+    const int plan_order = recon == 0 ? order : (recon == RAM_RECON_PLM ? 3 : 5);
+    Carve cv;
+    const size_t tmp_off = cv.take(state_bytes);
+    RowsPlan rp = plan_rows(cv, layout, ram::step_tile_for(items, dv != nullptr), plan_order);
+    const int64_t nt = tiles_of(layout, rp.tile);
+    const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(2 * sizeof(int32_t) * nt);
+    if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
+    ram::StepArgs a;
+    std::memset(&a, 0, sizeof(a));        // the graph key compares raw bytes
+    if ((st = make_rows(ctx, layout, edges, rp, a.rows)) != RAM_OK) return st;
+    a.v0 = v0;
+    a.dv = dv;
+    a.dt = dt;
+    const bool f64 = dtype == RAM_F64;
+    const bool shared = a.rows.has_tab != 0 && a.rows.n_cols > 0;
+    if (shared) {
+        int64_t *wlo = (int64_t *)((char *)ctx->scratch + wlo_off);
+        int32_t *w = (int32_t *)((char *)ctx->scratch + w_off);
+        hipError_t e = ram::launch_plan(a, plan_order, wlo, w, ctx->stream);
+        if (e != hipSuccess) return hip_fail(e, "window plan launch");
+        a.plan_wlo = wlo;
+        a.plan_w = w;
+        if (scan == RAM_SUM_DIRECT && recon == 0)
+            a.dens = make_density(ctx->density, a.rows.n_cols);
+    }
+    ram::RadialArgs r;
+    std::memset(&r, 0, sizeof(r));
+    r.n_rows = layout->n_rows;
+    r.n_cols = layout->n_cols;
+    r.r_edges = r_edges;
+    r.u = u;
+    r.dt = dt;
+    void *tmp = (char *)ctx->scratch + tmp_off;
+    // per step: the RAM step along the rows (q -> tmp), then the radial step
+    // across them (tmp -> q)
+    auto loop = [&](hipStream_t st) -> hipError_t {
+        ram::StepArgs b = a;
+        ram::RadialArgs c = r;
+        for (int64_t k = 0; k < n_steps; ++k) {
+            b.q_in = q;
+            b.q_out = tmp;
+            hipError_t e;
+            if (recon) e = ram::launch_step_shared_limited(b, f64, (int)recon, st);
+            else if (shared) e = ram::launch_step_shared(b, f64, (int)scan, order, items, st);
+            else e = ram::launch_step(b, f64, (int)scan, order, st);
+            if (e != hipSuccess) return e;
+            c.q_in = tmp;
+            c.q_out = q;
+            e = ram::launch_radial(c, f64, st);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    const int64_t extra[4] = {(int64_t)dtype * 16 + (int64_t)scan + 256 * (int64_t)recon +
+                                  4096 * (int64_t)items,
+                              order, n_steps, (int64_t)(intptr_t)q};
+    return run_graphed(ctx, key_of(a, r, extra, tmp), n_steps, loop);
+}
+
 ram_status ram_row_norms(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
                          const void *q, const void *q_ref, const double *edges,
                          double *out)

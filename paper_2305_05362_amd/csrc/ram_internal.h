@@ -132,6 +132,18 @@ struct StepArgs {
     MeshDensity dens;                   // shared mesh, direct sums: closed-form index
 };
 
+// Radial transport of a polar grid (rows = radii): q [n_rows][n_cols], u on
+// the radial faces [n_rows + 1][n_cols], radial edges r_edges[n_rows + 1].
+struct RadialArgs {
+    int64_t n_rows = 0;
+    int64_t n_cols = 0;
+    const double *r_edges = nullptr;
+    const void *q_in = nullptr;
+    void *q_out = nullptr;
+    const void *u = nullptr;
+    double dt = 0.0;
+};
+
 struct ResidualArgs {
     Rows rows;
     const void *q_in = nullptr;
@@ -233,6 +245,7 @@ hipError_t launch_shift_limited_adjoint(const ShiftAdjArgs &a, bool f64, int rec
 // without the check against the nodes (a test of the closed form).
 hipError_t launch_density_cells(const MeshDensity &d, int n, const double *x, int64_t m,
                                 int32_t *cells, hipStream_t stream);
+hipError_t launch_radial(const RadialArgs &a, bool f64, hipStream_t stream);
 // Per-row mass, dx-weighted L1 distance to qref (if non-null) and max |Q|,
 // three FP64 values per row (one workgroup per row).
 hipError_t launch_row_norms(const Rows &R, bool f64, const void *q, const void *qref,

@@ -27,7 +27,8 @@ Workloads (the five synthetic configurations)
 
 Seeds: ``20230509 + 10*cfg + stream`` with stream 0 = state noise, 1 =
 residual velocity, 2 = row lengths and stretching, 3 = bulk speeds,
-4 = target perturbation, 5 = finite-difference coordinates.
+4 = target perturbation, 5 = finite-difference coordinates, 6 = radial
+velocity.
 """
 from __future__ import annotations
 
@@ -269,6 +270,46 @@ def polar(n_r: int, n_phi: int, cfg: int, order: int, steps: int,
                     q0, dv, v0, dt, order, steps,
                     meta={"r_edges": redges, "area": area,
                           "bump": (a, b, c)})
+
+
+def radial_velocity(wl: Workload, cfg: int, amp: float = 0.01) -> np.ndarray:
+    """Radial velocity of a polar workload on its radial faces, [n_r + 1,
+    n_phi] (face j between rows j-1 and j):
+    u_{j-1/2,i} = amp r_{j-1/2}^-1/2 sin(phi_i) zeta (zeta ~ N(0,1), stream 6,
+    phi_i the cell centre), a fraction `amp` of the Keplerian speed with the
+    residual's angular pattern; zero on the inner and outer edges."""
+    re = wl.meta["r_edges"]
+    pc = 0.5 * (wl.edges[:-1] + wl.edges[1:])
+    zeta = rng_for(cfg, 6).standard_normal((wl.n_rows + 1, wl.n_cols))
+    u = amp * re[:, None] ** -0.5 * np.sin(pc)[None, :] * zeta
+    u[0] = 0.0
+    u[-1] = 0.0
+    return u
+
+
+def radial_cfl_dt(r_edges: np.ndarray, u: np.ndarray, beta: float = 0.5) -> float:
+    """dt = beta * min over interior radial faces of min(dr_below, dr_above)/|u_f|
+    (the residual's Courant rule across the rows)."""
+    dr = np.diff(r_edges)
+    lim = np.minimum(dr[:-1], dr[1:])[:, None]
+    adv = np.abs(u[1:-1])
+    with np.errstate(divide="ignore"):
+        r = np.where(adv > 0, lim / adv, np.inf)
+    return float(beta * np.min(r)) if r.size else math.inf
+
+
+def cfl_2d_dt(phi_edges: np.ndarray, r_edges: np.ndarray, v_phi: np.ndarray,
+              u: np.ndarray, beta: float = 0.5) -> float:
+    """The 2D Courant rule of a split step (the advective terms of Section
+    4.2's time-step estimate): dt = beta min over cells of
+    [ |v_phi| / dphi + |u| / dr ]^-1, with v_phi the azimuthal (angular)
+    velocity the row step advects with at the cell's left face and |u| the
+    larger of the cell's two radial face speeds."""
+    dphi = np.diff(phi_edges)[None, :]
+    dr = np.diff(r_edges)[:, None]
+    um = np.maximum(np.abs(u[:-1]), np.abs(u[1:]))
+    rate = np.abs(v_phi) / dphi + um / dr
+    return float(beta / np.max(rate))
 
 
 def cfg2(order: int = 5) -> Workload:

@@ -211,3 +211,43 @@ def test_mesh_density_argument_errors(lib):
     assert st == R.RAM_E_INVALID_ARG
     st = lib.ram_mesh_density_cells(None, ctypes.byref(d), 10, None, 5, None)
     assert st == R.RAM_E_INVALID_ARG and b"null" in lib.ram_last_error()
+
+
+def test_radial_and_split_argument_errors(lib):
+    from paper_2305_05362_amd import _lib as R
+    L = _layout()
+    a, b, c, d, e, f = (ctypes.c_void_p(0x1000 * i) for i in (1, 2, 3, 4, 5, 6))
+    # ragged rows have no radial columns
+    Lr = R.Layout(2, 0, a, 16, 0)
+    st = lib.ram_radial_step(None, ctypes.byref(Lr), R.RAM_F64, a, b, c, d, 0.1)
+    assert st == R.RAM_E_INVALID_ARG and b"n_cols" in lib.ram_last_error()
+    st = lib.ram_radial_step(None, ctypes.byref(L), R.RAM_F64, a, a, c, d, 0.1)
+    assert st == R.RAM_E_INVALID_ARG and b"alias" in lib.ram_last_error()
+    st = lib.ram_radial_step(None, ctypes.byref(L), R.RAM_F64, a, b, None, d, 0.1)
+    assert st == R.RAM_E_INVALID_ARG and b"null" in lib.ram_last_error()
+    st = lib.ram_radial_step(None, ctypes.byref(L), R.RAM_F64, a, b, c, d, float("nan"))
+    assert st == R.RAM_E_INVALID_ARG and b"dt" in lib.ram_last_error()
+    st = lib.ram_radial_step(None, ctypes.byref(L), 5, a, b, c, d, 0.1)
+    assert st == R.RAM_E_UNSUPPORTED
+    st = lib.ram_radial_step(None, ctypes.byref(L), R.RAM_F32, a, b, c, d, 0.1)
+    assert st == R.RAM_E_INVALID_ARG and b"context" in lib.ram_last_error()
+    # the split step: row-step and radial checks, then the context
+    st = lib.ram_step_split2d(None, ctypes.byref(L), R.RAM_F64, R.RAM_SCAN_F64, 0, a, b, c,
+                              d, e, f, 0.1, 4, 1)
+    assert st == R.RAM_E_UNSUPPORTED and b"order" in lib.ram_last_error()
+    st = lib.ram_step_split2d(None, ctypes.byref(L), R.RAM_F64, R.RAM_SCAN_F64, 7, a, b, c,
+                              d, e, f, 0.1, 5, 1)
+    assert st == R.RAM_E_UNSUPPORTED and b"recon" in lib.ram_last_error()
+    Lp = _layout(shared=0)
+    st = lib.ram_step_split2d(None, ctypes.byref(Lp), R.RAM_F64, R.RAM_SCAN_F64,
+                              R.RAM_RECON_PLM, a, b, c, d, e, f, 0.1, 5, 1)
+    assert st == R.RAM_E_UNSUPPORTED and b"shared" in lib.ram_last_error()
+    st = lib.ram_step_split2d(None, ctypes.byref(L), R.RAM_F64, R.RAM_SCAN_F64, 0, a, b, c,
+                              d, None, f, 0.1, 5, 1)
+    assert st == R.RAM_E_INVALID_ARG and b"null" in lib.ram_last_error()
+    st = lib.ram_step_split2d(None, ctypes.byref(L), R.RAM_F64, R.RAM_SCAN_F64, 0, a, b, c,
+                              d, e, f, 0.1, 5, -1)
+    assert st == R.RAM_E_INVALID_ARG and b"n_steps" in lib.ram_last_error()
+    st = lib.ram_step_split2d(None, ctypes.byref(L), R.RAM_F32, R.RAM_SUM_DIRECT, 0, a, b, c,
+                              d, e, f, 0.1, 5, 1)
+    assert st == R.RAM_E_INVALID_ARG and b"context" in lib.ram_last_error()
