@@ -14,7 +14,9 @@ cumulative differences are summed directly from the window masses
 timed region.  Beside it: the FP32 path with two-sum and with FP64 prefix
 sums, the FP64 paths (prefix sums, and direct sums with their own schedule),
 forward+adjoint, the closed-form mesh-density index, the STD baseline on the
-same mesh (time-step ratio, per-step overhead, accuracy), the limited PLM /
+same mesh (time-step ratio, per-step overhead, accuracy), the 2D split step
+(RAM along the azimuth, then the radial step) against STD's split step, the
+limited PLM /
 PPM reconstructions, the one-step error against the FP64 path (held to the
 oracle by the GPU tests), the dominant kernel's HBM roofline, and the CPU
 oracle's throughput on a bounded sample (run on this host's cores).
@@ -292,6 +294,62 @@ def main():
                          "std_rel_l1_vs_one_shift": err_a(q_s)}}
     del qa_, qb_, vfull, vz, q_s, q_t, q_ram
 
+    # --- the 2D split step (Section 3's dimensional splitting, Section 4.2) --
+    # RAM along the azimuth (the step above), then the radial upwind step with
+    # a seeded radial velocity; STD: the residual kernel with the full
+    # azimuthal velocity, then the same radial step.  Time steps from the
+    # advective terms of Section 4.2's 2D Courant rule.
+    u_h = W.radial_velocity(wl, 5)
+    re_h = wl.meta["r_edges"]
+    dt2_ram = W.cfl_2d_dt(wl.edges, re_h, wl.dv, u_h, 0.5)
+    dt2_std = W.cfl_2d_dt(wl.edges, re_h, vfull_h, u_h, 0.5)
+    re_d = torch.as_tensor(re_h, dtype=torch.float64, device=dev)
+    u32 = torch.as_tensor(u_h.reshape(-1), dtype=torch.float32, device=dev)
+    k2d = max(1, args.steps // 4)
+
+    def time_split(recon):
+        q = q32.clone()
+        ctx.ram_step_split2d(rows, q, v0, dv32, re_d, u32, dt2_ram, order, k2d, HEAD,
+                             recon)                                    # captures
+        q.copy_(q32)
+        torch.cuda.synchronize()
+        a, b = events()
+        a.record()
+        ctx.ram_step_split2d(rows, q, v0, dv32, re_d, u32, dt2_ram, order, k2d, HEAD, recon)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / 1e3 / k2d
+
+    t2_ram = time_split(0)
+    t2_plm = time_split(R.RAM_RECON_PLM)
+    vfull2 = torch.as_tensor(vfull_h.reshape(-1), dtype=torch.float32, device=dev)
+    qa_, qb_ = q32.clone(), torch.empty_like(q32)
+
+    def std2d():
+        ctx.ram_residual(rows, qa_, qb_, vfull2, dt2_std)
+        ctx.ram_radial_step(rows, qb_, qa_, re_d, u32, dt2_std)
+    t2_std = time_kernel(std2d, k2d)
+    t_rad = time_kernel(lambda: ctx.ram_radial_step(rows, q32, qb_, re_d, u32, dt2_ram), 50)
+    del qa_, qb_, vfull2
+    split_2d = {
+        "radial": "upwind van Leer along r in polar geometry, closed edges; u = 0.01 "
+                  "r^-1/2 sin(phi) zeta (zeta ~ N(0,1))",
+        "cfl_rule": "dt = 0.5 / max_cells(|v_phi| / dphi + |u| / dr), v_phi = dv (RAM) "
+                    "or v0 + dv (STD)",
+        "dt_ram": dt2_ram, "dt_std": dt2_std, "dt_ratio": round(dt2_ram / dt2_std, 2),
+        "ram_split_step_us": round(t2_ram * 1e6, 2),
+        "ram_plm_split_step_us": round(t2_plm * 1e6, 2),
+        "std_split_step_us": round(t2_std * 1e6, 2),
+        "overhead_ram_over_std": round(t2_ram / t2_std, 3),
+        "speedup_same_physical_time": round((dt2_ram / dt2_std) * t2_std / t2_ram, 2),
+        "speedup_same_physical_time_plm": round((dt2_ram / dt2_std) * t2_std / t2_plm, 2),
+        "value": round(n_cells / t2_ram / 1e9, 3), "unit": "Gcell-updates/s",
+        "steps": k2d,
+        "radial_kernel_us": round(t_rad * 1e6, 2),
+        "radial_algorithmic_bytes_per_cell": 12,
+        "radial_hbm_frac": round(12.0 * n_cells / t_rad / 1e9 / HBM_PEAK_GBS, 4)}
+    del u32
+
     # --- ragged rows with per-row meshes (4096 rows of 64..8192 cells) ------
     wl3 = W.cfg3()
     rows3 = R.Rows.from_workload(wl3, dev)
@@ -516,6 +574,7 @@ def main():
         "schedule": schedule,
         "fast_index": fast_index,
         "std_baseline": std_baseline,
+        "split_2d": split_2d,
         "ragged_cfg": ragged,
         "limited_reconstructions": limited,
         "kernels": kernels,
