@@ -60,23 +60,25 @@ def parse():
     p.add_argument("--profile-pass", action="store_true",
                    help="short run for hardware-counter passes: the headline kernel "
                         "for --steps steps, the PPM step kernel for --steps steps, "
-                        "then a plain copy of COPY_BYTES")
+                        "--steps 2D split steps (headline + radial kernel), then a "
+                        "plain copy of COPY_BYTES")
     return p.parse_args()
 
 
 COPY_BYTES = 256 << 20
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_sh_f32_direct_polar2048x16384_traffic.md")
 TRAFFIC_FILE_PPM = os.path.join(ROOT, "profiles", "k_step_sh_f32_ppm_polar2048x16384_traffic.md")
+TRAFFIC_FILE_RADIAL = os.path.join(ROOT, "profiles", "k_radial_f32_polar2048x16384_traffic.md")
 
 
 def load_traffic(path, kernel):
-    """Measured HBM bytes per launch of a step kernel, if the committed
-    counter summary was taken on the current kernel sources and on this
+    """Measured HBM bytes per launch of a kernel, if the committed counter
+    summary was taken on the current kernel sources and on this
     instantiation (`kernel`, as rocprofv3 names it)."""
     from paper_2305_05362_amd.build import kernel_digest
     from paper_2305_05362_amd.rocprof_summary import read_traffic
     rec = read_traffic(path)
-    if not rec or rec.get("source_digest") != kernel_digest():
+    if not rec or rec.get("source_digest") != kernel_digest(kernel):
         return None
     if rec.get("kernel_name", "").split("::")[-1] != kernel:
         return None
@@ -180,6 +182,13 @@ def main():
         ctx.ram_step(rows, q, v0, dv32, wl.dt, order, args.steps, R.RAM_SUM_DIRECT)
         q.copy_(q32)
         ctx.ram_step_limited(rows, q, v0, dv32, wl.dt, R.RAM_RECON_PPM, args.steps)
+        # 2D split steps: the radial kernel (and as many more headline steps)
+        u_p = torch.as_tensor(W.radial_velocity(wl, 5).reshape(-1), dtype=torch.float32,
+                              device=dev)
+        re_p = torch.as_tensor(wl.meta["r_edges"], dtype=torch.float64, device=dev)
+        q.copy_(q32)
+        ctx.ram_step_split2d(rows, q, v0, dv32, re_p, u_p, wl.dt, order, args.steps,
+                             R.RAM_SUM_DIRECT)
         src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         dst.copy_(src)
@@ -330,6 +339,7 @@ def main():
         ctx.ram_radial_step(rows, qb_, qa_, re_d, u32, dt2_std)
     t2_std = time_kernel(std2d, k2d)
     t_rad = time_kernel(lambda: ctx.ram_radial_step(rows, q32, qb_, re_d, u32, dt2_ram), 50)
+    tr_rad = load_traffic(TRAFFIC_FILE_RADIAL, "k_radial<float, 16>")
     del qa_, qb_, vfull2
     split_2d = {
         "radial": "upwind van Leer along r in polar geometry, closed edges; u = 0.01 "
@@ -347,7 +357,8 @@ def main():
         "steps": k2d,
         "radial_kernel_us": round(t_rad * 1e6, 2),
         "radial_algorithmic_bytes_per_cell": 12,
-        "radial_hbm_frac": round(12.0 * n_cells / t_rad / 1e9 / HBM_PEAK_GBS, 4)}
+        "radial_hbm_frac": round(12.0 * n_cells / t_rad / 1e9 / HBM_PEAK_GBS, 4),
+        "radial_traffic": None if tr_rad is None else round(tr_rad["traffic_bytes_per_launch"])}
     del u32
 
     # --- ragged rows with per-row meshes (4096 rows of 64..8192 cells) ------

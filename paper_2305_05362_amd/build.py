@@ -34,13 +34,18 @@ HIPCC_FLAGS = [
 
 # sources of the shared-mesh step kernel (the one the traffic counters cover)
 STEP_KERNEL_SOURCES = ["ram_step_shared.hip", "ram_device.h", "ram_internal.h"]
+# sources of each kernel family whose counters are committed
+KERNEL_SOURCES = {"k_step_sh": STEP_KERNEL_SOURCES,
+                  "k_radial": ["ram_radial.hip", "ram_device.h", "ram_internal.h"]}
 
 
-def kernel_digest() -> str:
-    """Digest of the shared-mesh step kernel's sources and compile flags."""
+def kernel_digest(kernel: str = "k_step_sh") -> str:
+    """Digest of one kernel family's sources and the compile flags (`kernel`
+    names the family, e.g. "k_step_sh" or "k_radial<float, 16>")."""
     import hashlib
+    fam = kernel.split("<")[0].split("::")[-1]
     h = hashlib.sha256(" ".join(HIPCC_FLAGS).encode())
-    for name in STEP_KERNEL_SOURCES:
+    for name in KERNEL_SOURCES[fam]:
         with open(os.path.join(CSRC, name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -45,7 +45,7 @@ def _short(name: str, width: int = 90) -> str:
     return name if len(name) <= width else name[:width - 3] + "..."
 
 
-def stats(directory: str, command: str, out: str, top: int = 12) -> None:
+def stats(directory: str, command: str, out: str, top: int = 24) -> None:
     rows = list(csv.DictReader(open(_one(directory, "_kernel_stats.csv"))))
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
     lines = ["# Kernel durations (rocprofv3 --kernel-trace --stats)", "",
@@ -161,7 +161,7 @@ def main(argv=None):
     else:
         from .build import kernel_digest
         rec = traffic(a.fetch, a.write, a.kernel, a.copy_bytes, a.command, a.out,
-                      kernel_digest(), a.units, a.unit_name, a.bytes_per_unit)
+                      kernel_digest(a.kernel), a.units, a.unit_name, a.bytes_per_unit)
         json.dump(rec, sys.stdout)
         print()
 
