@@ -22,6 +22,9 @@ Every function follows one passage of the paper:
                    forward state (the branch each limiter takes), plus dL/dv0;
   radial           the radial transport of a polar grid (the residual's upwind
                    scheme along r in polar geometry, closed edges);
+  average4, point4 centre values -> cell averages with the fourth-order <Q>
+                   correction of Section 3.1, and back; step_point4 composes
+                   them with step for a state of centre values;
   shift_adjoint    transpose of the (linear) shift, plus dL/dv0;
   residual_adjoint transpose of the residual Jacobian, plus dL/d(dv).
 
@@ -79,11 +82,12 @@ def _load():
     lib.oracle_edges_recon.argtypes = [P, P, I64, D, I, P, P]
     lib.oracle_shift_recon_adjoint.argtypes = [I64, P, P, I, P, P, P, P, D, I, P, I]
     lib.oracle_radial.argtypes = [I64, I64, P, P, P, D, P, I]
+    lib.oracle_average4.argtypes = [I64, P, P, I, P, P, I, I]
     for f in ("oracle_shift", "oracle_residual", "oracle_step",
               "oracle_shift_adjoint", "oracle_residual_adjoint", "oracle_edges",
               "oracle_max_threads", "oracle_shift_recon", "oracle_step_recon",
               "oracle_recon_cells", "oracle_edges_recon", "oracle_shift_recon_adjoint",
-              "oracle_radial"):
+              "oracle_radial", "oracle_average4"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -295,3 +299,34 @@ def radial(r_edges, q, u, dt: float, nthreads: int = 0) -> np.ndarray:
                                _ptr(out), int(nthreads))
     _check(rc, "radial")
     return out
+
+
+def average4(rows: Rows, q, inverse: bool = False, nthreads: int = 0) -> np.ndarray:
+    """Centre values -> cell averages, <Q>_i = Q_i + dx_i^2 Q''_i / 24 with the
+    three-point Q'' through the neighbouring centres (inverse: averages ->
+    centre values, subtracting the same correction)."""
+    q = _f64(q).reshape(-1)
+    out = np.empty_like(q)
+    rc = _load().oracle_average4(rows.n_rows, _ptr(rows.row_ptr), _ptr(rows.edges),
+                                 int(rows.shared), _ptr(q), _ptr(out), int(bool(inverse)),
+                                 int(nthreads))
+    _check(rc, "average4")
+    return out
+
+
+def point4(rows: Rows, qavg, nthreads: int = 0) -> np.ndarray:
+    """Cell averages -> centre values (the inverse of average4)."""
+    return average4(rows, qavg, True, nthreads)
+
+
+def step_point4(rows: Rows, q, v0, dv, dt: float, order: int, n_steps: int,
+                nthreads: int = 0) -> np.ndarray:
+    """n steps on a state of centre values: each step converts to cell
+    averages, takes the split step (shift, then residual), and converts
+    back."""
+    q = _f64(q).reshape(-1).copy()
+    for _ in range(n_steps):
+        a = average4(rows, q, False, nthreads)
+        a = step(rows, a, v0, dv, dt, order, 1, nthreads)
+        q = average4(rows, a, True, nthreads)
+    return q
