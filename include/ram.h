@@ -321,6 +321,33 @@ ram_status ram_step_split2d(ram_ctx *ctx, const ram_layout *layout, ram_dtype dt
                             const double *v0, const void *dv, const double *r_edges,
                             const void *u, double dt, int order, int64_t n_steps);
 
+/* Centre values <-> cell averages with the fourth-order correction (Section
+ * 3.1: reading the state as cell averages is a second-order assumption; the
+ * paper names <Q>_i = Q_i + (Q_{i+1} - 2 Q_i + Q_{i-1}) / 24 on a uniform
+ * mesh).  to_centre = 0: q_in holds values at the cell centres and q_out gets
+ *   <Q>_i = Q_i + dx_i^2 Q''_i / 24,
+ * Q'' the three-point second derivative through the centres of cells i-1, i,
+ * i+1 of the periodic row (the printed formula on a uniform mesh);
+ * to_centre = 1: the inverse, Q_i = <Q>_i - dx_i^2 <Q>''_i / 24.  Both are
+ * fourth-order accurate on smooth meshes; on a uniform periodic row they
+ * conserve sum_i Q_i, on other meshes sum_i Q_i dx_i only to that order.  Any
+ * layout; q_in and q_out must not alias. */
+ram_status ram_cell_average(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
+                            const void *q_in, void *q_out, const double *edges,
+                            int to_centre);
+
+/* n_steps on a state of cell-centre values, q in place: each step converts
+ * the values to cell averages (ram_cell_average), takes the split step
+ * (recon = 0: ram_step's, with order and scan; RAM_RECON_PLM / _PPM:
+ * ram_step_limited's, shared meshes only), and converts back.  This lifts
+ * the second-order cap that taking centre values as averages puts on the
+ * shift of smooth data on non-uniform meshes.  Loops of four or more steps
+ * are captured into a graph. */
+ram_status ram_step_point4(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
+                           ram_scan scan, ram_recon recon, void *q, const double *edges,
+                           const double *v0, const void *dv, double dt, int order,
+                           int64_t n_steps);
+
 /* Host-side check of the inputs (synchronous; copies to the host): strictly
  * increasing finite nodes (RAM_E_MESH), and when dv != NULL the residual
  * Courant condition |dv_f| dt <= min(dx_{f-1}, dx_f) (RAM_E_CFL). */

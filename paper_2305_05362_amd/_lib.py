@@ -104,6 +104,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ram_set_mesh_density": [P, ctypes.POINTER(MeshDensity)],
         "ram_radial_step": [P, LP, I, P, P, P, P, D],
         "ram_step_split2d": [P, LP, I, I, I, P, P, P, P, P, P, D, I, I64],
+        "ram_cell_average": [P, LP, I, P, P, P, I],
+        "ram_step_point4": [P, LP, I, I, I, P, P, P, P, D, I, I64],
         "ram_mesh_density_cells": [P, ctypes.POINTER(MeshDensity), I64, P, I64, P],
     }
     for name, args in sig.items():
@@ -317,6 +319,24 @@ class Context:
             float(dt), int(order), int(n_steps)))
         return q
 
+    def ram_cell_average(self, rows: Rows, q_in, q_out, to_centre: bool = False):
+        self._stream()
+        check(self._lib.ram_cell_average(
+            self._h, ctypes.byref(rows.layout), _dtype_code(q_in),
+            _dev_ptr(q_in, q_in.dtype, "q_in"), _dev_ptr(q_out, q_in.dtype, "q_out"),
+            _dev_ptr(rows.edges, torch.float64, "edges"), int(bool(to_centre))))
+        return q_out
+
+    def ram_step_point4(self, rows: Rows, q, v0, dv, dt: float, order: int, n_steps: int,
+                        scan: int = RAM_SCAN_F64, recon: int = 0):
+        self._stream()
+        check(self._lib.ram_step_point4(
+            self._h, ctypes.byref(rows.layout), _dtype_code(q), int(scan), int(recon),
+            _dev_ptr(q, q.dtype, "q"), _dev_ptr(rows.edges, torch.float64, "edges"),
+            _dev_ptr(v0, torch.float64, "v0"), _dev_ptr(dv, q.dtype, "dv"), float(dt),
+            int(order), int(n_steps)))
+        return q
+
     def ram_row_norms(self, rows: Rows, q, q_ref=None, out=None):
         """Per-row (mass, dx-weighted L1 distance to q_ref, max |q|), FP64
         tensor of shape [n_rows, 3] on q's device."""
@@ -459,6 +479,15 @@ def ram_step_split2d(rows, q, v0, dv, r_edges, u, dt, order, n_steps, scan=RAM_S
                      recon=0):
     return context(q.device.index).ram_step_split2d(rows, q, v0, dv, r_edges, u, dt, order,
                                                     n_steps, scan, recon)
+
+
+def ram_cell_average(rows, q_in, q_out, to_centre=False):
+    return context(q_in.device.index).ram_cell_average(rows, q_in, q_out, to_centre)
+
+
+def ram_step_point4(rows, q, v0, dv, dt, order, n_steps, scan=RAM_SCAN_F64, recon=0):
+    return context(q.device.index).ram_step_point4(rows, q, v0, dv, dt, order, n_steps, scan,
+                                                   recon)
 
 
 def ram_residual(rows, q_in, q_out, dv, dt):

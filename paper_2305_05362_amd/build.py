@@ -20,7 +20,8 @@ LIB_PATH = os.path.join(HERE, "libram.so")
 ARCH = os.environ.get("RAM_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["ram_kernels.hip", "ram_step_shared.hip", "ram_adjoint.hip",
-           "ram_adjoint_shared.hip", "ram_limited.hip", "ram_reduce.hip", "ram_radial.hip", "ram_api.cpp"]
+           "ram_adjoint_shared.hip", "ram_limited.hip", "ram_reduce.hip", "ram_radial.hip",
+           "ram_average4.hip", "ram_api.cpp"]
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

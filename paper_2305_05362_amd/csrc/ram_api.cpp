@@ -915,13 +915,32 @@ ram_status ram_radial_step(ram_ctx *ctx, const ram_layout *layout, ram_dtype dty
     return RAM_OK;
 }
 
-ram_status ram_step_split2d(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
-                            ram_scan scan, ram_recon recon, void *q, const double *edges,
-                            const double *v0, const void *dv, const double *r_edges,
-                            const void *u, double dt, int order, int64_t n_steps)
+// The row step inside a loop that does more than the step each time (the 2D
+// split step, the step on centre values): its checks, and the tables, window
+// plan and index the step kernels read, set up once per call.
+struct RowStep {
+    ram::StepArgs a;
+    ram_scan scan = RAM_SCAN_F64;
+    int recon = 0, order = 0, items = 0;
+    bool f64 = false, shared = false;
+
+    hipError_t launch(const void *in, void *out, hipStream_t st) const
+    {
+        ram::StepArgs b = a;
+        b.q_in = in;
+        b.q_out = out;
+        if (recon) return ram::launch_step_shared_limited(b, f64, recon, st);
+        if (shared) return ram::launch_step_shared(b, f64, (int)scan, order, items, st);
+        return ram::launch_step(b, f64, (int)scan, order, st);
+    }
+};
+
+// Lagrange (recon 0: scan and order) or limited (shared meshes only) row step.
+ram_status check_row_step(const ram_layout *layout, ram_dtype dtype, ram_scan scan,
+                          ram_recon recon, const double *edges, const double *v0, int order,
+                          int64_t n_steps)
 {
     ram_status st;
-    g_last_error.clear();
     if ((st = check_layout(layout, edges)) != RAM_OK) return st;
     if (recon == 0) {
         if ((st = check_scan(dtype, scan)) != RAM_OK) return st;
@@ -929,42 +948,69 @@ ram_status ram_step_split2d(ram_ctx *ctx, const ram_layout *layout, ram_dtype dt
     } else {
         if ((st = check_dtype(dtype)) != RAM_OK) return st;
         if ((st = check_recon(layout, recon)) != RAM_OK) return st;
-        if (!layout->edges_shared)
-            return fail(RAM_E_UNSUPPORTED, "limited split steps need a shared azimuthal mesh");
-        scan = RAM_SUM_DIRECT;
+        if (!layout->edges_shared || layout->n_cols <= 0)
+            return fail(RAM_E_UNSUPPORTED, "limited steps in a loop need a shared mesh");
     }
-    if ((st = check_radial(layout, dtype, q, nullptr, r_edges, u, dt, true)) != RAM_OK) return st;
     if (!v0) return fail(RAM_E_INVALID_ARG, "null v0");
     if (n_steps < 0) return fail(RAM_E_INVALID_ARG, "n_steps must be >= 0");
-    if (n_steps == 0) return RAM_OK;
-    if ((st = enter(ctx)) != RAM_OK) return st;
-    const size_t state_bytes = elem_size(dtype) * (size_t)layout_cells(layout);
-    const int items = recon ? ram::kItems : sched_items(ctx, layout, scan);
+    return RAM_OK;
+}
+
+// After the caller has taken its own buffers from cv (and called enter).
+ram_status setup_row_step(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
+                          ram_scan scan, ram_recon recon, const double *edges,
+                          const double *v0, const void *dv, double dt, int order, Carve &cv,
+                          RowStep &rs)
+{
+    ram_status st;
+    if (recon) scan = RAM_SUM_DIRECT;
+    rs.scan = scan;
+    rs.recon = (int)recon;
+    rs.order = order;
+    rs.f64 = dtype == RAM_F64;
+    rs.items = recon ? ram::kItems : sched_items(ctx, layout, scan);
     const int plan_order = recon == 0 ? order : (recon == RAM_RECON_PLM ? 3 : 5);
-    Carve cv;
-    const size_t tmp_off = cv.take(state_bytes);
-    RowsPlan rp = plan_rows(cv, layout, ram::step_tile_for(items, dv != nullptr), plan_order);
+    RowsPlan rp = plan_rows(cv, layout, ram::step_tile_for(rs.items, dv != nullptr), plan_order);
     const int64_t nt = tiles_of(layout, rp.tile);
     const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(2 * sizeof(int32_t) * nt);
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
-    ram::StepArgs a;
-    std::memset(&a, 0, sizeof(a));        // the graph key compares raw bytes
-    if ((st = make_rows(ctx, layout, edges, rp, a.rows)) != RAM_OK) return st;
-    a.v0 = v0;
-    a.dv = dv;
-    a.dt = dt;
-    const bool f64 = dtype == RAM_F64;
-    const bool shared = a.rows.has_tab != 0 && a.rows.n_cols > 0;
-    if (shared) {
+    std::memset(&rs.a, 0, sizeof(rs.a));   // graph keys compare raw bytes
+    if ((st = make_rows(ctx, layout, edges, rp, rs.a.rows)) != RAM_OK) return st;
+    rs.a.v0 = v0;
+    rs.a.dv = dv;
+    rs.a.dt = dt;
+    rs.shared = rs.a.rows.has_tab != 0 && rs.a.rows.n_cols > 0;
+    if (rs.shared) {
         int64_t *wlo = (int64_t *)((char *)ctx->scratch + wlo_off);
         int32_t *w = (int32_t *)((char *)ctx->scratch + w_off);
-        hipError_t e = ram::launch_plan(a, plan_order, wlo, w, ctx->stream);
+        hipError_t e = ram::launch_plan(rs.a, plan_order, wlo, w, ctx->stream);
         if (e != hipSuccess) return hip_fail(e, "window plan launch");
-        a.plan_wlo = wlo;
-        a.plan_w = w;
+        rs.a.plan_wlo = wlo;
+        rs.a.plan_w = w;
         if (scan == RAM_SUM_DIRECT && recon == 0)
-            a.dens = make_density(ctx->density, a.rows.n_cols);
+            rs.a.dens = make_density(ctx->density, rs.a.rows.n_cols);
     }
+    return RAM_OK;
+}
+
+ram_status ram_step_split2d(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
+                            ram_scan scan, ram_recon recon, void *q, const double *edges,
+                            const double *v0, const void *dv, const double *r_edges,
+                            const void *u, double dt, int order, int64_t n_steps)
+{
+    ram_status st;
+    g_last_error.clear();
+    if ((st = check_row_step(layout, dtype, scan, recon, edges, v0, order, n_steps)) != RAM_OK)
+        return st;
+    if ((st = check_radial(layout, dtype, q, nullptr, r_edges, u, dt, true)) != RAM_OK) return st;
+    if (n_steps == 0) return RAM_OK;
+    if ((st = enter(ctx)) != RAM_OK) return st;
+    Carve cv;
+    const size_t tmp_off = cv.take(elem_size(dtype) * (size_t)layout_cells(layout));
+    RowStep rs;
+    if ((st = setup_row_step(ctx, layout, dtype, scan, recon, edges, v0, dv, dt, order, cv,
+                             rs)) != RAM_OK)
+        return st;
     ram::RadialArgs r;
     std::memset(&r, 0, sizeof(r));
     r.n_rows = layout->n_rows;
@@ -976,27 +1022,87 @@ ram_status ram_step_split2d(ram_ctx *ctx, const ram_layout *layout, ram_dtype dt
     // per step: the RAM step along the rows (q -> tmp), then the radial step
     // across them (tmp -> q)
     auto loop = [&](hipStream_t st) -> hipError_t {
-        ram::StepArgs b = a;
         ram::RadialArgs c = r;
         for (int64_t k = 0; k < n_steps; ++k) {
-            b.q_in = q;
-            b.q_out = tmp;
-            hipError_t e;
-            if (recon) e = ram::launch_step_shared_limited(b, f64, (int)recon, st);
-            else if (shared) e = ram::launch_step_shared(b, f64, (int)scan, order, items, st);
-            else e = ram::launch_step(b, f64, (int)scan, order, st);
+            hipError_t e = rs.launch(q, tmp, st);
             if (e != hipSuccess) return e;
             c.q_in = tmp;
             c.q_out = q;
-            e = ram::launch_radial(c, f64, st);
+            e = ram::launch_radial(c, rs.f64, st);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
     };
-    const int64_t extra[4] = {(int64_t)dtype * 16 + (int64_t)scan + 256 * (int64_t)recon +
-                                  4096 * (int64_t)items,
+    const int64_t extra[4] = {(int64_t)dtype * 16 + (int64_t)rs.scan + 256 * (int64_t)recon +
+                                  4096 * (int64_t)rs.items,
                               order, n_steps, (int64_t)(intptr_t)q};
-    return run_graphed(ctx, key_of(a, r, extra, tmp), n_steps, loop);
+    return run_graphed(ctx, key_of(rs.a, r, extra, tmp), n_steps, loop);
+}
+
+ram_status ram_cell_average(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
+                            const void *q_in, void *q_out, const double *edges, int to_centre)
+{
+    ram_status st;
+    g_last_error.clear();
+    if ((st = check_layout(layout, edges)) != RAM_OK) return st;
+    if ((st = check_dtype(dtype)) != RAM_OK) return st;
+    if (to_centre != 0 && to_centre != 1)
+        return fail(RAM_E_INVALID_ARG, "to_centre must be 0 or 1");
+    if (!q_in || !q_out) return fail(RAM_E_INVALID_ARG, "null q_in or q_out");
+    if (q_in == q_out) return fail(RAM_E_INVALID_ARG, "q_in and q_out must not alias");
+    if ((st = enter(ctx)) != RAM_OK) return st;
+    Carve cv;
+    RowsPlan rp = plan_rows(cv, layout, ram::kAvgTile, 0);
+    if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
+    ram::Rows R;
+    if ((st = make_rows(ctx, layout, edges, rp, R)) != RAM_OK) return st;
+    hipError_t e = ram::launch_average4(R, dtype == RAM_F64, to_centre != 0, q_in, q_out,
+                                        ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "cell average launch");
+    return RAM_OK;
+}
+
+ram_status ram_step_point4(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
+                           ram_scan scan, ram_recon recon, void *q, const double *edges,
+                           const double *v0, const void *dv, double dt, int order,
+                           int64_t n_steps)
+{
+    ram_status st;
+    g_last_error.clear();
+    if ((st = check_row_step(layout, dtype, scan, recon, edges, v0, order, n_steps)) != RAM_OK)
+        return st;
+    if ((st = check_dt(dt)) != RAM_OK) return st;
+    if (!q) return fail(RAM_E_INVALID_ARG, "null q");
+    if (n_steps == 0) return RAM_OK;
+    if ((st = enter(ctx)) != RAM_OK) return st;
+    const size_t state_bytes = elem_size(dtype) * (size_t)layout_cells(layout);
+    Carve cv;
+    const size_t t1_off = cv.take(state_bytes), t2_off = cv.take(state_bytes);
+    RowsPlan rc = plan_rows(cv, layout, ram::kAvgTile, 0);
+    RowStep rs;
+    if ((st = setup_row_step(ctx, layout, dtype, scan, recon, edges, v0, dv, dt, order, cv,
+                             rs)) != RAM_OK)
+        return st;
+    ram::Rows RC;
+    std::memset(&RC, 0, sizeof(RC));
+    if ((st = make_rows(ctx, layout, edges, rc, RC)) != RAM_OK) return st;
+    void *t1 = (char *)ctx->scratch + t1_off;
+    void *t2 = (char *)ctx->scratch + t2_off;
+    // per step: centre values -> averages (q -> t1), the step (t1 -> t2),
+    // averages -> centre values (t2 -> q)
+    auto loop = [&](hipStream_t st) -> hipError_t {
+        for (int64_t k = 0; k < n_steps; ++k) {
+            hipError_t e = ram::launch_average4(RC, rs.f64, false, q, t1, st);
+            if (e != hipSuccess) return e;
+            if ((e = rs.launch(t1, t2, st)) != hipSuccess) return e;
+            if ((e = ram::launch_average4(RC, rs.f64, true, t2, q, st)) != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    const int64_t extra[4] = {(int64_t)dtype * 16 + (int64_t)rs.scan + 256 * (int64_t)recon +
+                                  4096 * (int64_t)rs.items + (1 << 20),
+                              order, n_steps, (int64_t)(intptr_t)q};
+    return run_graphed(ctx, key_of(rs.a, RC, extra, t1), n_steps, loop);
 }
 
 ram_status ram_row_norms(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,

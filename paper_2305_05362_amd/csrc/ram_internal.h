@@ -16,6 +16,9 @@ constexpr int kWindowCap = 2048;
 // Cells per tile of the residual step alone: four per thread, with the
 // two-cell halo a side staged in one item per thread.
 constexpr int kResTile = 1020;
+// Centre value <-> cell average conversion: four cells per thread.
+constexpr int kAvgItems = 4;
+constexpr int kAvgTile = kBlock * kAvgItems;
 
 // How cumulative differences are formed: from a window prefix sum in FP64,
 // compensated FP32 or plain FP32, or (kSumDirect) summed directly from the
@@ -246,6 +249,10 @@ hipError_t launch_shift_limited_adjoint(const ShiftAdjArgs &a, bool f64, int rec
 hipError_t launch_density_cells(const MeshDensity &d, int n, const double *x, int64_t m,
                                 int32_t *cells, hipStream_t stream);
 hipError_t launch_radial(const RadialArgs &a, bool f64, hipStream_t stream);
+// Centre values -> cell averages (inverse: back) with the fourth-order
+// correction, every row of R (R.tile == kAvgTile); in and out must not alias.
+hipError_t launch_average4(const Rows &R, bool f64, bool inverse, const void *in, void *out,
+                           hipStream_t stream);
 // Per-row mass, dx-weighted L1 distance to qref (if non-null) and max |Q|,
 // three FP64 values per row (one workgroup per row).
 hipError_t launch_row_norms(const Rows &R, bool f64, const void *q, const void *qref,

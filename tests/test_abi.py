@@ -251,3 +251,39 @@ def test_radial_and_split_argument_errors(lib):
     st = lib.ram_step_split2d(None, ctypes.byref(L), R.RAM_F32, R.RAM_SUM_DIRECT, 0, a, b, c,
                               d, e, f, 0.1, 5, 1)
     assert st == R.RAM_E_INVALID_ARG and b"context" in lib.ram_last_error()
+
+
+def test_cell_average_and_point4_argument_errors(lib):
+    from paper_2305_05362_amd import _lib as R
+    L = _layout()
+    a, b, c, d = (ctypes.c_void_p(0x1000 * i) for i in (1, 2, 3, 4))
+    st = lib.ram_cell_average(None, ctypes.byref(L), R.RAM_F64, a, b, c, 2)
+    assert st == R.RAM_E_INVALID_ARG and b"to_centre" in lib.ram_last_error()
+    st = lib.ram_cell_average(None, ctypes.byref(L), R.RAM_F64, a, a, c, 0)
+    assert st == R.RAM_E_INVALID_ARG and b"alias" in lib.ram_last_error()
+    st = lib.ram_cell_average(None, ctypes.byref(L), R.RAM_F64, None, b, c, 0)
+    assert st == R.RAM_E_INVALID_ARG and b"null" in lib.ram_last_error()
+    st = lib.ram_cell_average(None, ctypes.byref(L), 9, a, b, c, 0)
+    assert st == R.RAM_E_UNSUPPORTED
+    st = lib.ram_cell_average(None, ctypes.byref(L), R.RAM_F32, a, b, c, 1)
+    assert st == R.RAM_E_INVALID_ARG and b"context" in lib.ram_last_error()
+    # the step on centre values: the row step's checks, then the context
+    st = lib.ram_step_point4(None, ctypes.byref(L), R.RAM_F64, R.RAM_SCAN_F64, 0, a, b, c, d,
+                             0.1, 2, 1)
+    assert st == R.RAM_E_UNSUPPORTED and b"order" in lib.ram_last_error()
+    Lp = _layout(shared=0)
+    st = lib.ram_step_point4(None, ctypes.byref(Lp), R.RAM_F64, R.RAM_SCAN_F64,
+                             R.RAM_RECON_PPM, a, b, c, d, 0.1, 5, 1)
+    assert st == R.RAM_E_UNSUPPORTED and b"shared" in lib.ram_last_error()
+    st = lib.ram_step_point4(None, ctypes.byref(L), R.RAM_F64, R.RAM_SCAN_F64, 0, a, b, c, d,
+                             0.1, 5, -3)
+    assert st == R.RAM_E_INVALID_ARG and b"n_steps" in lib.ram_last_error()
+    st = lib.ram_step_point4(None, ctypes.byref(L), R.RAM_F64, R.RAM_SCAN_F64, 0, None, b, c,
+                             d, 0.1, 5, 1)
+    assert st == R.RAM_E_INVALID_ARG and b"null q" in lib.ram_last_error()
+    st = lib.ram_step_point4(None, ctypes.byref(L), R.RAM_F64, R.RAM_SCAN_F64, 0, a, b, c, d,
+                             float("inf"), 5, 1)
+    assert st == R.RAM_E_INVALID_ARG and b"dt" in lib.ram_last_error()
+    st = lib.ram_step_point4(None, ctypes.byref(L), R.RAM_F32, R.RAM_SUM_DIRECT, 0, a, b, c,
+                             d, 0.1, 5, 1)
+    assert st == R.RAM_E_INVALID_ARG and b"context" in lib.ram_last_error()
