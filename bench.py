@@ -16,6 +16,7 @@ sums, the FP64 paths (prefix sums, and direct sums with their own schedule),
 forward+adjoint, the closed-form mesh-density index, the STD baseline on the
 same mesh (time-step ratio, per-step overhead, accuracy), the 2D split step
 (RAM along the azimuth, then the radial step) against STD's split step, the
+step on a state of centre values with the fourth-order <Q> conversion, the
 limited PLM /
 PPM reconstructions, the one-step error against the FP64 path (held to the
 oracle by the GPU tests), the dominant kernel's HBM roofline, and the CPU
@@ -361,6 +362,60 @@ def main():
         "radial_traffic": None if tr_rad is None else round(tr_rad["traffic_bytes_per_launch"])}
     del u32
 
+    # --- a state of centre values (Section 3.1's fourth-order <Q>) ----------
+    # each step converts the centre values to cell averages, takes the step
+    # and converts back: three kernels a step on the same disk
+    kp4 = max(1, args.steps // 4)
+    qp = q32.clone()
+    ctx.ram_step_point4(rows, qp, v0, dv32, wl.dt, order, kp4, HEAD)       # captures
+    qp.copy_(q32)
+    torch.cuda.synchronize()
+    a, b = events()
+    a.record()
+    ctx.ram_step_point4(rows, qp, v0, dv32, wl.dt, order, kp4, HEAD)
+    b.record()
+    torch.cuda.synchronize()
+    t_p4 = a.elapsed_time(b) / 1e3 / kp4
+    t_avg = time_kernel(lambda: ctx.ram_cell_average(rows, q32, qp, False), 50)
+    del qp
+    # accuracy against the exact solution: centre values of a smooth periodic
+    # function on a smoothly stretched mesh (x = xi + 0.5 sin xi), shifted by
+    # 0.2137 of the period in one step of order 5, FP64, with and without the
+    # conversion
+    s_p4 = 0.2137 * 2.0 * math.pi
+    acc = {}
+    for n_p in (256, 512):
+        xi = np.linspace(-math.pi, math.pi, n_p + 1)
+        xm = xi + 0.5 * np.sin(xi)
+        xm[0], xm[-1] = -math.pi, math.pi
+        cm = 0.5 * (xm[1:] + xm[:-1])
+        fm = lambda t: np.sin(t) + 0.3 * np.cos(3.0 * t)
+        rw = R.Rows(torch.as_tensor(xm, dtype=torch.float64, device=dev), 1, n_p, None, True)
+        one_v = torch.ones(1, dtype=torch.float64, device=dev)
+        qa = torch.as_tensor(fm(cm), dtype=torch.float64, device=dev)
+        qb = qa.clone()
+        ctx.ram_step_point4(rw, qa, one_v, None, s_p4, order, 1)
+        ctx.ram_step(rw, qb, one_v, None, s_p4, order, 1, R.RAM_SCAN_F64)
+        torch.cuda.synchronize()
+        want = fm(cm - s_p4)
+        acc[n_p] = (float(np.max(np.abs(qa.cpu().numpy() - want))),
+                    float(np.max(np.abs(qb.cpu().numpy() - want))))
+    point4 = {
+        "what": "state of centre values: convert to cell averages (<Q> = Q + dx^2 Q''/24), "
+                "step, convert back",
+        "value": round(n_cells / t_p4 / 1e9, 3), "unit": "Gcell-updates/s", "steps": kp4,
+        "step_us": round(t_p4 * 1e6, 2),
+        "overhead_over_step": round(t_p4 / t_fused, 3),
+        "conversion_kernel_us": round(t_avg * 1e6, 2),
+        "conversion_algorithmic_bytes_per_cell": 8,
+        "conversion_hbm_frac": round(8.0 * n_cells / t_avg / 1e9 / HBM_PEAK_GBS, 4),
+        "accuracy": {"mesh": "x = xi + 0.5 sin(xi) on [-pi, pi), shift 0.2137 periods, "
+                             "order 5, FP64, max error against the exact centre values",
+                     "with_conversion": {str(k): v[0] for k, v in acc.items()},
+                     "centre_values_as_averages": {str(k): v[1] for k, v in acc.items()},
+                     "order_with": round(math.log2(acc[256][0] / acc[512][0]), 2),
+                     "order_without": round(math.log2(acc[256][1] / acc[512][1]), 2)}}
+
     # --- ragged rows with per-row meshes (4096 rows of 64..8192 cells) ------
     wl3 = W.cfg3()
     rows3 = R.Rows.from_workload(wl3, dev)
@@ -586,6 +641,7 @@ def main():
         "fast_index": fast_index,
         "std_baseline": std_baseline,
         "split_2d": split_2d,
+        "centre_values_4th_order": point4,
         "ragged_cfg": ragged,
         "limited_reconstructions": limited,
         "kernels": kernels,

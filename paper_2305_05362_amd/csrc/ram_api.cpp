@@ -1039,6 +1039,9 @@ ram_status ram_step_split2d(ram_ctx *ctx, const ram_layout *layout, ram_dtype dt
     return run_graphed(ctx, key_of(rs.a, r, extra, tmp), n_steps, loop);
 }
 
+// Uniform rows sharing one mesh.
+bool shared_rows(const ram_layout *L) { return L->edges_shared && L->n_cols > 0; }
+
 ram_status ram_cell_average(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
                             const void *q_in, void *q_out, const double *edges, int to_centre)
 {
@@ -1053,11 +1056,17 @@ ram_status ram_cell_average(ram_ctx *ctx, const ram_layout *layout, ram_dtype dt
     if ((st = enter(ctx)) != RAM_OK) return st;
     Carve cv;
     RowsPlan rp = plan_rows(cv, layout, ram::kAvgTile, 0);
+    const bool tab = shared_rows(layout);
+    const size_t w_off = tab ? cv.take(2 * elem_size(dtype) * (size_t)layout->n_cols) : 0;
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
     ram::Rows R;
     if ((st = make_rows(ctx, layout, edges, rp, R)) != RAM_OK) return st;
-    hipError_t e = ram::launch_average4(R, dtype == RAM_F64, to_centre != 0, q_in, q_out,
-                                        ctx->stream);
+    const bool f64 = dtype == RAM_F64;
+    void *w = tab ? (char *)ctx->scratch + w_off : nullptr;
+    hipError_t e = hipSuccess;
+    if (tab) e = ram::launch_average4_weights(edges, layout->n_cols, f64, w, ctx->stream);
+    if (e == hipSuccess)
+        e = ram::launch_average4(R, f64, to_centre != 0, q_in, q_out, w, ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "cell average launch");
     return RAM_OK;
 }
@@ -1079,6 +1088,8 @@ ram_status ram_step_point4(ram_ctx *ctx, const ram_layout *layout, ram_dtype dty
     Carve cv;
     const size_t t1_off = cv.take(state_bytes), t2_off = cv.take(state_bytes);
     RowsPlan rc = plan_rows(cv, layout, ram::kAvgTile, 0);
+    const bool tab = shared_rows(layout);
+    const size_t w_off = tab ? cv.take(2 * elem_size(dtype) * (size_t)layout->n_cols) : 0;
     RowStep rs;
     if ((st = setup_row_step(ctx, layout, dtype, scan, recon, edges, v0, dv, dt, order, cv,
                              rs)) != RAM_OK)
@@ -1088,14 +1099,21 @@ ram_status ram_step_point4(ram_ctx *ctx, const ram_layout *layout, ram_dtype dty
     if ((st = make_rows(ctx, layout, edges, rc, RC)) != RAM_OK) return st;
     void *t1 = (char *)ctx->scratch + t1_off;
     void *t2 = (char *)ctx->scratch + t2_off;
+    void *w = tab ? (char *)ctx->scratch + w_off : nullptr;
+    if (tab) {
+        hipError_t e = ram::launch_average4_weights(edges, layout->n_cols, rs.f64, w,
+                                                    ctx->stream);
+        if (e != hipSuccess) return hip_fail(e, "cell average weights launch");
+    }
     // per step: centre values -> averages (q -> t1), the step (t1 -> t2),
     // averages -> centre values (t2 -> q)
     auto loop = [&](hipStream_t st) -> hipError_t {
         for (int64_t k = 0; k < n_steps; ++k) {
-            hipError_t e = ram::launch_average4(RC, rs.f64, false, q, t1, st);
+            hipError_t e = ram::launch_average4(RC, rs.f64, false, q, t1, w, st);
             if (e != hipSuccess) return e;
             if ((e = rs.launch(t1, t2, st)) != hipSuccess) return e;
-            if ((e = ram::launch_average4(RC, rs.f64, true, t2, q, st)) != hipSuccess) return e;
+            if ((e = ram::launch_average4(RC, rs.f64, true, t2, q, w, st)) != hipSuccess)
+                return e;
         }
         return hipSuccess;
     };

@@ -251,8 +251,12 @@ hipError_t launch_density_cells(const MeshDensity &d, int n, const double *x, in
 hipError_t launch_radial(const RadialArgs &a, bool f64, hipStream_t stream);
 // Centre values -> cell averages (inverse: back) with the fourth-order
 // correction, every row of R (R.tile == kAvgTile); in and out must not alias.
+// w: the (w+, w-) weights of a shared mesh from launch_average4_weights, in
+// the state's type, or null (formed from the nodes in the kernel).
+hipError_t launch_average4_weights(const double *x, int64_t n, bool f64, void *w,
+                                   hipStream_t stream);
 hipError_t launch_average4(const Rows &R, bool f64, bool inverse, const void *in, void *out,
-                           hipStream_t stream);
+                           const void *w, hipStream_t stream);
 // Per-row mass, dx-weighted L1 distance to qref (if non-null) and max |Q|,
 // three FP64 values per row (one workgroup per row).
 hipError_t launch_row_norms(const Rows &R, bool f64, const void *q, const void *qref,
