@@ -61,8 +61,9 @@ def parse():
     p.add_argument("--profile-pass", action="store_true",
                    help="short run for hardware-counter passes: the headline kernel "
                         "for --steps steps, the PPM step kernel for --steps steps, "
-                        "--steps 2D split steps (headline + radial kernel), then a "
-                        "plain copy of COPY_BYTES")
+                        "--steps 2D split steps (headline + radial kernel), --steps "
+                        "steps on centre values (conversion kernels), then a plain "
+                        "copy of COPY_BYTES")
     return p.parse_args()
 
 
@@ -70,6 +71,7 @@ COPY_BYTES = 256 << 20
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_sh_f32_direct_polar2048x16384_traffic.md")
 TRAFFIC_FILE_PPM = os.path.join(ROOT, "profiles", "k_step_sh_f32_ppm_polar2048x16384_traffic.md")
 TRAFFIC_FILE_RADIAL = os.path.join(ROOT, "profiles", "k_radial_f32_polar2048x16384_traffic.md")
+TRAFFIC_FILE_AVG4 = os.path.join(ROOT, "profiles", "k_average4_f32_polar2048x16384_traffic.md")
 
 
 def load_traffic(path, kernel):
@@ -190,6 +192,9 @@ def main():
         q.copy_(q32)
         ctx.ram_step_split2d(rows, q, v0, dv32, re_p, u_p, wl.dt, order, args.steps,
                              R.RAM_SUM_DIRECT)
+        # steps on centre values: the conversion kernel, both directions
+        q.copy_(q32)
+        ctx.ram_step_point4(rows, q, v0, dv32, wl.dt, order, args.steps, R.RAM_SUM_DIRECT)
         src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         dst.copy_(src)
@@ -377,6 +382,7 @@ def main():
     torch.cuda.synchronize()
     t_p4 = a.elapsed_time(b) / 1e3 / kp4
     t_avg = time_kernel(lambda: ctx.ram_cell_average(rows, q32, qp, False), 50)
+    tr_avg = load_traffic(TRAFFIC_FILE_AVG4, "k_average4<float, false>")
     del qp
     # accuracy against the exact solution: centre values of a smooth periodic
     # function on a smoothly stretched mesh (x = xi + 0.5 sin xi), shifted by
@@ -409,6 +415,8 @@ def main():
         "conversion_kernel_us": round(t_avg * 1e6, 2),
         "conversion_algorithmic_bytes_per_cell": 8,
         "conversion_hbm_frac": round(8.0 * n_cells / t_avg / 1e9 / HBM_PEAK_GBS, 4),
+        "conversion_traffic": None if tr_avg is None
+        else round(tr_avg["traffic_bytes_per_launch"]),
         "accuracy": {"mesh": "x = xi + 0.5 sin(xi) on [-pi, pi), shift 0.2137 periods, "
                              "order 5, FP64, max error against the exact centre values",
                      "with_conversion": {str(k): v[0] for k, v in acc.items()},
