@@ -382,7 +382,7 @@ def main():
     torch.cuda.synchronize()
     t_p4 = a.elapsed_time(b) / 1e3 / kp4
     t_avg = time_kernel(lambda: ctx.ram_cell_average(rows, q32, qp, False), 50)
-    tr_avg = load_traffic(TRAFFIC_FILE_AVG4, "k_average4<float, false>")
+    tr_avg = load_traffic(TRAFFIC_FILE_AVG4, "k_average4<float, 0>")
     del qp
     # accuracy against the exact solution: centre values of a smooth periodic
     # function on a smoothly stretched mesh (x = xi + 0.5 sin xi), shifted by

@@ -341,8 +341,11 @@ ram_status ram_cell_average(ram_ctx *ctx, const ram_layout *layout, ram_dtype dt
  * (recon = 0: ram_step's, with order and scan; RAM_RECON_PLM / _PPM:
  * ram_step_limited's, shared meshes only), and converts back.  This lifts
  * the second-order cap that taking centre values as averages puts on the
- * shift of smooth data on non-uniform meshes.  Loops of four or more steps
- * are captured into a graph. */
+ * shift of smooth data on non-uniform meshes.  Between two steps the
+ * conversion back and the next conversion to averages run as one pass (the
+ * centre values in between are not stored), so results agree with n single
+ * calls to rounding.  Loops of four or more steps are captured into a
+ * graph. */
 ram_status ram_step_point4(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
                            ram_scan scan, ram_recon recon, void *q, const double *edges,
                            const double *v0, const void *dv, double dt, int order,

@@ -1105,15 +1105,17 @@ ram_status ram_step_point4(ram_ctx *ctx, const ram_layout *layout, ram_dtype dty
                                                     ctx->stream);
         if (e != hipSuccess) return hip_fail(e, "cell average weights launch");
     }
-    // per step: centre values -> averages (q -> t1), the step (t1 -> t2),
-    // averages -> centre values (t2 -> q)
+    // centre values -> averages (q -> t1); per step the step (t1 -> t2),
+    // then, between steps, back to centre values and on to averages in one
+    // pass (t2 -> t1); after the last, back to centre values (t2 -> q)
     auto loop = [&](hipStream_t st) -> hipError_t {
+        hipError_t e = ram::launch_average4(RC, rs.f64, false, q, t1, w, st);
+        if (e != hipSuccess) return e;
         for (int64_t k = 0; k < n_steps; ++k) {
-            hipError_t e = ram::launch_average4(RC, rs.f64, false, q, t1, w, st);
-            if (e != hipSuccess) return e;
             if ((e = rs.launch(t1, t2, st)) != hipSuccess) return e;
-            if ((e = ram::launch_average4(RC, rs.f64, true, t2, q, w, st)) != hipSuccess)
-                return e;
+            e = k + 1 < n_steps ? ram::launch_average4_between(RC, rs.f64, t2, t1, w, st)
+                                : ram::launch_average4(RC, rs.f64, true, t2, q, w, st);
+            if (e != hipSuccess) return e;
         }
         return hipSuccess;
     };

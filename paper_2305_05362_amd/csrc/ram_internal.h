@@ -257,6 +257,10 @@ hipError_t launch_average4_weights(const double *x, int64_t n, bool f64, void *w
                                    hipStream_t stream);
 hipError_t launch_average4(const Rows &R, bool f64, bool inverse, const void *in, void *out,
                            const void *w, hipStream_t stream);
+// The inverse conversion, then the forward one, in one pass (between two
+// steps on centre values).
+hipError_t launch_average4_between(const Rows &R, bool f64, const void *in, void *out,
+                                   const void *w, hipStream_t stream);
 // Per-row mass, dx-weighted L1 distance to qref (if non-null) and max |Q|,
 // three FP64 values per row (one workgroup per row).
 hipError_t launch_row_norms(const Rows &R, bool f64, const void *q, const void *qref,

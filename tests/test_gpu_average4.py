@@ -11,8 +11,9 @@ the step on a state of centre values (C ABI), against the FP64 oracle.
   (the 5-step loop replayed from its graph on a second call), on shared and
   ragged meshes;
 * at the 2048 x 16384 disk's size in the benchmark's configuration: the
-  graphed loop equals the three calls made one by one, bit for bit, and
-  sampled rows match the oracle;
+  graphed loop (which converts back and forth between two steps in one
+  pass) equals the three calls made one by one to rounding, and sampled
+  rows match the oracle;
 * what the conversion is for, against the exact solution rather than the
   oracle: a point-sampled smooth function shifted on a smoothly stretched
   mesh converges at fourth order on the GPU with the conversion, at second
@@ -146,6 +147,23 @@ def test_step_point4_limited(recon):
                           R.RAM_SCAN_F64, recon)
 
 
+@pytest.mark.parametrize("kind", ["shared", "ragged"])
+def test_between_steps_pass_is_the_two_conversions(kind):
+    # FP64, ten steps: the loop's one-pass conversion between steps against
+    # separate calls (inverse, then forward conversion), to rounding
+    wl = W.small_polar(5, 1100) if kind == "shared" else W.small_ragged(9, 4, 1500, seed=53,
+                                                                        with_dv=False)
+    dvt = dev(wl.dv) if wl.dv is not None else None
+    rows = R.Rows.from_workload(wl, DEV)
+    a = dev(wl.q0)
+    R.ram_step_point4(rows, a, dev(wl.v0), dvt, wl.dt, 3, 10)
+    b = dev(wl.q0)
+    for _ in range(10):
+        R.ram_step_point4(rows, b, dev(wl.v0), dvt, wl.dt, 3, 1)
+    torch.cuda.synchronize()
+    assert float((a - b).abs().max()) <= 1e-13 * float(b.abs().max())
+
+
 def test_step_point4_fp32_direct():
     wl = W.small_polar(6, 2600)
     import dataclasses
@@ -180,7 +198,7 @@ def test_step_point4_full_size(big, use_density):
             ctx.ram_step(rows, t, v0, dv, wl.dt, 5, 1, R.RAM_SUM_DIRECT)
             ctx.ram_cell_average(rows, t, b, True)
         torch.cuda.synchronize()
-        assert torch.equal(a, b)
+        assert float((a - b).abs().max()) <= 1e-6 * float(b.abs().max())
         # sampled rows against the oracle, one step from FP32-rounded inputs
         pick = np.array([0, 1020, 1024, 2047])
         one = q0.clone()
