@@ -464,18 +464,20 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs a)
 template <typename TQ>
 __global__ __launch_bounds__(kBlock) void k_residual(ResidualArgs a)
 {
-    // Staged once (index j <-> cell and face i0-2+j): the state, the face
-    // velocities and the mesh data (dx, 1/centre gap, 1/dx).  Each thread
-    // then updates four consecutive cells a..a+3 from its window of cells
-    // a-2..a+5 in registers: slopes of cells a-1..a+4, fluxes on faces
-    // a..a+4, the conservative update.
+    // Staged once (index j <-> cell i0-2+j, and face i0-2+j between cells
+    // j-1 and j): the state, the face velocities and the mesh data (dx,
+    // 1/centre gap, 1/dx); every lane issues its loads before the first LDS
+    // store.  Then one face per lane (fluxes on faces i0 .. i0+nd, with the
+    // upwind cell's van Leer slope) and one cell per lane (the conservative
+    // update), lane-consecutive in LDS, so no access conflicts on a bank.
     using CT = TQ;
+    using CT2 = typename TabT<CT>::T2;
     constexpr int NP = kStepNodes + 8;
     __shared__ __attribute__((aligned(16))) CT sq[NP];
-    __shared__ __attribute__((aligned(16))) CT sdv[NP];
     __shared__ __attribute__((aligned(16))) CT sdx[NP];
     __shared__ __attribute__((aligned(16))) CT shv[NP];
     __shared__ __attribute__((aligned(16))) CT sdi[NP];
+    __shared__ __attribute__((aligned(16))) CT sf[NP];
 
     const Rows &R = a.rows;
     Tile ti;
@@ -492,57 +494,62 @@ __global__ __launch_bounds__(kBlock) void k_residual(ResidualArgs a)
     const bool inner = (i0 - 2 >= 0) && (i0 + nd + 2 < n);
     const int t = threadIdx.x;
     const double len = x[n] - x[0];
+    CT vq[kItems], vv[kItems], vdi[kItems];
+    CT2 vr[kItems];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const int j = min(t + k * kBlock, nd + 3);
+        const int c = inner ? i0 - 2 + j : wrap_small(i0 - 2 + j, n);
+        vq[k] = (CT)q[c];
+        vv[k] = (CT)dv[c];
+        if (tab) {
+            vr[k] = TabT<CT>::rr(R.tab)[c];
+            vdi[k] = TabT<CT>::dxinv(R.tab)[c];
+        }
+    }
+    CT vd[kItems];                       // face velocity of the face j (cell j's left)
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         const int j = t + k * kBlock;
         if (j < nd + 4) {
             const int c = inner ? i0 - 2 + j : wrap_small(i0 - 2 + j, n);
-            sq[j] = (CT)q[c];
-            sdv[j] = (CT)dv[c];
-            if (tab) {
-                const typename TabT<CT>::T2 r = TabT<CT>::rr(R.tab)[c];
-                sdx[j] = r.x;
-                shv[j] = r.y;
-                sdi[j] = TabT<CT>::dxinv(R.tab)[c];
-            } else {
+            if (!tab) {
                 const double d = x[c + 1] - x[c];
-                sdx[j] = (CT)d;
-                shv[j] = (CT)(1.0 / centre_gap(x, n, len, c));
-                sdi[j] = (CT)(1.0 / d);
+                vr[k].x = (CT)d;
+                vr[k].y = (CT)(1.0 / centre_gap(x, n, len, c));
+                vdi[k] = (CT)(1.0 / d);
             }
+            sq[j] = vq[k];
+            sdx[j] = vr[k].x;
+            shv[j] = vr[k].y;
+            sdi[j] = vdi[k];
+        }
+        vd[k] = vv[k];
+    }
+    __syncthreads();
+    // face f (0 .. nd) lies between cells f+1 and f+2; its velocity is the
+    // one staged with cell f+2
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const int f = t + k * kBlock - 2;
+        if (f >= 0 && f <= nd) {
+            const CT v = vd[k];
+            const bool up = v >= (CT)0;
+            const int c = up ? f + 1 : f + 2;             // upwind cell
+            const CT qm = sq[c - 1], q0 = sq[c], qp = sq[c + 1];
+            const CT dp = (qp - q0) * shv[c];
+            const CT dm = (q0 - qm) * shv[c - 1];
+            const CT sg = (dp * dm <= (CT)0) ? (CT)0 : harmonic2(dp, dm);
+            const CT qf = up ? q0 + (CT)0.5 * sg * (sdx[c] - v * dt)
+                             : q0 - (CT)0.5 * sg * (sdx[c] + v * dt);
+            sf[f] = v * qf;
         }
     }
     __syncthreads();
-    const int u0 = 4 * t;
-    if (u0 >= nd) return;
-    CT qw[8], dx[8], hv[8];
 #pragma unroll
-    for (int w = 0; w < 8; ++w) {
-        qw[w] = sq[u0 + w];
-        dx[w] = sdx[u0 + w];
-        hv[w] = shv[u0 + w];
-    }
-    CT sg[8];
-#pragma unroll
-    for (int w = 1; w <= 6; ++w) {
-        const CT dp = (qw[w + 1] - qw[w]) * hv[w];
-        const CT dm = (qw[w] - qw[w - 1]) * hv[w - 1];
-        sg[w] = (dp * dm <= (CT)0) ? (CT)0 : harmonic2(dp, dm);
-    }
-    // face a+f lies between window cells f+1 and f+2
-    CT fl[5];
-#pragma unroll
-    for (int f = 0; f < 5; ++f) {
-        const CT v = sdv[u0 + 2 + f];
-        CT qf;
-        if (v >= (CT)0) qf = qw[f + 1] + (CT)0.5 * sg[f + 1] * (dx[f + 1] - v * dt);
-        else qf = qw[f + 2] - (CT)0.5 * sg[f + 2] * (dx[f + 2] + v * dt);
-        fl[f] = v * qf;
-    }
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        const int u = u0 + c;
-        if (u < nd) qo[i0 + u] = (TQ)(qw[c + 2] - dt * (fl[c + 1] - fl[c]) * sdi[u0 + c + 2]);
+    for (int k = 0; k < kItems; ++k) {
+        const int u = t + k * kBlock;
+        if (u < nd) qo[i0 + u] = (TQ)(sq[u + 2] - dt * (sf[u + 1] - sf[u]) * sdi[u + 2]);
     }
 }
 
@@ -772,6 +779,8 @@ hipError_t launch_step(const StepArgs &a, bool f64, int scan, int order,
 hipError_t launch_residual(const ResidualArgs &a, bool f64, hipStream_t stream)
 {
     if (a.rows.n_tiles <= 0) return hipSuccess;
+    // the staged window (tile + 4 cells) must fit kItems slots a lane
+    if (a.rows.tile > kResTile) return hipErrorInvalidValue;
     const dim3 grid((unsigned)a.rows.n_tiles), block(kBlock);
     if (f64)
         hipLaunchKernelGGL(k_residual<double>, grid, block, 0, stream, a);
