@@ -563,6 +563,20 @@ def main():
     t_adj_all = a.elapsed_time(b) / 1e3
     v_adj_all = n_cells * ka / t_adj_all / 1e9
     del out
+    # the same rollout when only Q0 needs a gradient (v0 a fixed profile, dv
+    # given): the kernels skip the dv and v0 terms
+    qo_ = q32.clone().requires_grad_(True)
+    out = rollout(qo_, rows, v0, dv32, wl.dt, order, min(ka, 20), args.checkpoint, HEAD)
+    out.backward(g)
+    torch.cuda.synchronize()
+    a, b = events()
+    a.record()
+    out = rollout(qo_, rows, v0, dv32, wl.dt, order, ka, args.checkpoint, HEAD)
+    out.backward(g)
+    b.record()
+    torch.cuda.synchronize()
+    v_adj_q0 = n_cells * ka / (a.elapsed_time(b) / 1e3) / 1e9
+    del out, qo_
 
     # --- accuracy: one FP32 step against the FP64 path (itself held to the
     # oracle at 1e-12 by the GPU tests) from the same FP32-rounded input, over
@@ -628,6 +642,8 @@ def main():
                    "dt": wl.dt},
         "fwd_adjoint": {"value": round(v_adj, 3), "unit": "Gcell-updates/s",
                         "steps": ka, "checkpoint": args.checkpoint},
+        "fwd_adjoint_q0_grad_only": {"value": round(v_adj_q0, 3), "unit": "Gcell-updates/s",
+                                     "steps": ka, "checkpoint": args.checkpoint},
         "fwd_adjoint_all_states_kept": {"value": round(v_adj_all, 3),
                                         "unit": "Gcell-updates/s", "steps": ka,
                                         "state_memory_gb": round((2 * ka + 1) * n_cells * 4

@@ -109,8 +109,13 @@ class RamRollout(torch.autograd.Function):
         qbar = gq.contiguous().clone()
         tmp = torch.empty_like(qbar)
         work = torch.empty_like(qbar) if recon and dv is not None else None
-        dvbar = torch.zeros_like(dv) if dv is not None else None
-        v0bar = torch.zeros_like(v0, dtype=torch.float64)
+        # only the gradients an input asks for: the v0 term (the
+        # reconstruction at every shifted node) and the dv accumulation are
+        # skipped in the kernels when v0 or dv needs none
+        want_dv = dv is not None and fctx.needs_input_grad[1]
+        want_v0 = fctx.needs_input_grad[2]
+        dvbar = torch.zeros_like(dv) if want_dv else None
+        v0bar = torch.zeros_like(v0, dtype=torch.float64) if want_v0 else None
         if fctx.stored:
             traj = checkpoints[0]
             half = checkpoints[1] if dv is not None else None
@@ -118,7 +123,8 @@ class RamRollout(torch.autograd.Function):
                 _step_adjoint(ctx, rows, traj[i], None if half is None else half[i], dv,
                               qbar, tmp, work, v0, dt, order, recon, dvbar, v0bar)
                 qbar, tmp = tmp, qbar
-            return qbar, dvbar, v0bar.to(v0.dtype), None, None, None, None, None, None, None
+            return (qbar, dvbar, None if v0bar is None else v0bar.to(v0.dtype), None, None,
+                    None, None, None, None, None)
         n_seg = len(checkpoints)
         seg = min(fctx.checkpoint, fctx.n_steps)
         traj = torch.empty((seg + 1, qbar.numel()), dtype=qbar.dtype, device=qbar.device)
@@ -135,7 +141,8 @@ class RamRollout(torch.autograd.Function):
                 _step_adjoint(ctx, rows, traj[i], None if half is None else half[i], dv,
                               qbar, tmp, work, v0, dt, order, recon, dvbar, v0bar)
                 qbar, tmp = tmp, qbar
-        return qbar, dvbar, v0bar.to(v0.dtype), None, None, None, None, None, None, None
+        return (qbar, dvbar, None if v0bar is None else v0bar.to(v0.dtype), None, None, None,
+                None, None, None, None)
 
 
 def rollout(q0: torch.Tensor, rows: R.Rows, v0: torch.Tensor,
@@ -149,5 +156,6 @@ def rollout(q0: torch.Tensor, rows: R.Rows, v0: torch.Tensor,
     post-shift state instead ((2n+1) states of memory, no recomputation).
     recon: 0 for the order-`order` Lagrange shift (with `scan`), or
     RAM_RECON_PLM / RAM_RECON_PPM for the limited shift (order and scan are
-    then unused)."""
+    then unused).  The backward pass forms the dv and v0 gradients only when
+    those tensors require them."""
     return RamRollout.apply(q0, dv, v0, rows, dt, order, n_steps, checkpoint, scan, recon)

@@ -289,7 +289,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_sh(StepAdjArgs a)
             ok = ok && jc >= LO && jc + P - LO <= W;
         }
     }
-    if (t == 0) s_flag = W > 0 ? 1 : 0;
+    if (t == 0) s_flag = (W > 0 && W <= kWinA) ? 1 : 0;
     __syncthreads();
     if (!ok) s_flag = 0;
     __syncthreads();

@@ -215,3 +215,39 @@ def test_checkpoint_spacing_and_fp32_gradient():
         err = float((x - y).abs().sum() / y.abs().sum())
         print(f"FP32-state gradient rel-L1 vs FP64: {err:.2e}")
         assert err <= 1e-3
+
+
+@pytest.mark.parametrize("recon", [0, R.RAM_RECON_PPM])
+@pytest.mark.parametrize("ckpt", [0, 4])
+def test_only_requested_gradients(recon, ckpt):
+    """With only Q0 requiring a gradient the backward pass skips the dv and v0
+    terms; Q0's gradient is the one the full backward pass gives and dv / v0
+    get none.  With Q0 and v0 only, v0's gradient is unchanged too.  (To
+    rounding: the shift transpose accumulates in LDS with atomics, whose
+    order varies from run to run.)"""
+    wl = W.small_polar(6, 1500)
+    rows = R.Rows.from_workload(wl, DEV)
+    q0 = torch.as_tensor(wl.q0.reshape(-1), dtype=torch.float64, device=DEV)
+    dv = torch.as_tensor(wl.dv.reshape(-1), dtype=torch.float64, device=DEV)
+    v0 = torch.as_tensor(wl.v0, dtype=torch.float64, device=DEV)
+    g = torch.linspace(-1.0, 1.0, q0.numel(), dtype=torch.float64, device=DEV)
+
+    def run(need_dv, need_v0):
+        a = q0.clone().requires_grad_(True)
+        b = dv.clone().requires_grad_(need_dv)
+        c = v0.clone().requires_grad_(need_v0)
+        out = rollout(a, rows, c, b, wl.dt, 5, 8, ckpt, R.RAM_SCAN_F64, recon)
+        out.backward(g)
+        torch.cuda.synchronize()
+        return a.grad, b.grad, c.grad
+
+    def close(u, w):
+        return float((u - w).abs().max()) <= 1e-13 * float(w.abs().max())
+
+    fa, fb, fc = run(True, True)
+    oa, ob, oc = run(False, False)
+    assert ob is None and oc is None
+    assert close(oa, fa)
+    va, vb, vc = run(False, True)
+    assert vb is None
+    assert close(va, fa) and close(vc, fc)
