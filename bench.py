@@ -74,6 +74,17 @@ TRAFFIC_FILE_RADIAL = os.path.join(ROOT, "profiles", "k_radial_f32_polar2048x163
 TRAFFIC_FILE_AVG4 = os.path.join(ROOT, "profiles", "k_average4_f32_polar2048x16384_traffic.md")
 
 
+def _finite(v):
+    """The result with every non-finite float replaced by None (strict JSON)."""
+    if isinstance(v, dict):
+        return {k: _finite(x) for k, x in v.items()}
+    if isinstance(v, (list, tuple)):
+        return [_finite(x) for x in v]
+    if isinstance(v, float) and not math.isfinite(v):
+        return None
+    return v
+
+
 def load_traffic(path, kernel):
     """Measured HBM bytes per launch of a kernel, if the committed counter
     summary was taken on the current kernel sources and on this
@@ -431,13 +442,33 @@ def main():
     q3 = torch.as_tensor(wl3.q0, dtype=torch.float32, device=dev)
     k3 = max(1, args.steps // 5)
     t3, _ = time_steps(q3, None, R.RAM_SCAN_F32_TWOSUM, k3, args.warmup, rows3, v03, wl3.dt)
-    t3d, _ = time_steps(q3.double(), None, R.RAM_SCAN_F64, k3, args.warmup, rows3, v03, wl3.dt)
+    t3p, _ = time_steps(q3, None, R.RAM_SCAN_F32, k3, args.warmup, rows3, v03, wl3.dt)
+    t3d, _ = time_steps(q3.double(), None, R.RAM_SCAN_F64, k3, args.warmup, rows3, v03,
+                        wl3.dt)
+    # one step of each FP32 path against the FP64 one from the same
+    # FP32-rounded start: the plain FP32 window prefix shows the cancellation
+    # the compensated one removes.  (Over many steps the unlimited order-5
+    # interpolant is unstable on the rows whose neighbouring cells differ up
+    # to 20x in size -- the oracle diverges on them too, order 3 and the
+    # limited reconstructions do not -- and would amplify rounding there.)
+    ones = {}
+    for name, dtp, scan in (("f32_twosum", torch.float32, R.RAM_SCAN_F32_TWOSUM),
+                            ("f32_plain_prefix", torch.float32, R.RAM_SCAN_F32),
+                            ("f64", torch.float64, R.RAM_SCAN_F64)):
+        qq = q3.to(dtp).clone()
+        ctx.ram_step(rows3, qq, v03, None, wl3.dt, order, 1, scan)
+        ones[name] = qq
+    torch.cuda.synchronize()
+    e3 = lambda a32: float((a32.double() - ones["f64"]).abs().sum() / ones["f64"].abs().sum())
     ragged = {"workload": "4096 ragged rows, 64..8192 cells (16.9 M), per-row stretched "
                           "meshes, shift only, order 5", "steps": k3,
               "f32_twosum": round(wl3.n_cells * k3 / t3 / 1e9, 3),
+              "f32_plain_prefix": round(wl3.n_cells * k3 / t3p / 1e9, 3),
               "f64": round(wl3.n_cells * k3 / t3d / 1e9, 3),
-              "unit": "Gcell-updates/s"}
-    del q3
+              "unit": "Gcell-updates/s",
+              "one_step_rel_l1_vs_f64": {"f32_twosum": e3(ones["f32_twosum"]),
+                                         "f32_plain_prefix": e3(ones["f32_plain_prefix"])}}
+    del q3, ones
 
     # --- the shift-only and residual-only kernels on their own --------------
     h32 = torch.empty_like(q32)
@@ -454,6 +485,12 @@ def main():
                "shift_only_algorithmic_bytes_per_cell": 8,
                "residual_only_algorithmic_bytes_per_cell": 12}
     achieved = fused_bytes / t_fused / 1e9
+    # a plain device copy of the same order of bytes on this machine, for scale
+    src_c = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+    dst_c = torch.empty_like(src_c)
+    t_copy = time_kernel(lambda: dst_c.copy_(src_c), 20)
+    copy_gbs = 2.0 * COPY_BYTES / t_copy / 1e9
+    del src_c, dst_c
     head_kernel = f"k_step_sh<float, 5, 3, 2, 0, {items}, {idx}>"
     tr = load_traffic(TRAFFIC_FILE, head_kernel)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -461,6 +498,8 @@ def main():
                 "traffic": None if tr is None else round(tr["traffic_bytes_per_launch"]),
                 "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled)",
                 "algorithmic_bytes_per_launch": fused_bytes,
+                "copy_achieved": round(copy_gbs, 1),
+                "copy_note": "torch device copy of 256 MiB (read + write) on the same GPU",
                 "kernel": head_kernel + " (FP32, order 5, direct sums, fused residual, "
                                         f"{items} nodes per thread, "
                                         f"{'closed-form' if idx else 'bucket'} index)"}
@@ -623,10 +662,31 @@ def main():
         t0 = time.perf_counter()
         oracle.step(sub, qs, wl.v0[:n_s], wl.dv[:n_s], wl.dt, order, steps_s)
         tc = time.perf_counter() - t0
+        cores = oracle.max_threads()
+        # one thread on a smaller sample (the same rows' first 16)
+        n_1 = 16
+        sub1 = oracle.Rows(np.arange(n_1 + 1) * n, wl.edges, True)
+        q1 = wl.q0[:n_1].astype(np.float64)
+        k_1 = max(1, steps_s // 4)
+        t0 = time.perf_counter()
+        oracle.step(sub1, q1, wl.v0[:n_1], wl.dv[:n_1], wl.dt, order, k_1, nthreads=1)
+        t_1 = time.perf_counter() - t0
+        cpu_model = None
+        try:
+            with open("/proc/cpuinfo") as fh:
+                for line in fh:
+                    if line.startswith("model name"):
+                        cpu_model = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
         cpu = {"value": n_s * n * steps_s / tc / 1e9, "unit": "Gcell-updates/s",
-               "cores": oracle.max_threads(), "kind": "oracle",
+               "cores": cores, "kind": "oracle",
                "sample": f"first {n_s} of 2048 rows x 16384 cells, {steps_s} FP64 steps "
-                         f"(shift + residual), {tc:.1f} s"}
+                         f"(shift + residual), {tc:.1f} s",
+               "single_thread_value": n_1 * n * k_1 / t_1 / 1e9,
+               "single_thread_sample": f"first {n_1} rows, {k_1} steps, {t_1:.1f} s",
+               "cpu_model": cpu_model}
 
     res = {
         "metric": METRIC, "value": round(value, 3), "unit": "Gcell-updates/s",
@@ -672,7 +732,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
-    print(json.dumps(res), flush=True)
+    print(json.dumps(_finite(res), allow_nan=False), flush=True)
 
 
 if __name__ == "__main__":
