@@ -287,3 +287,23 @@ def test_cell_average_and_point4_argument_errors(lib):
     st = lib.ram_step_point4(None, ctypes.byref(L), R.RAM_F32, R.RAM_SUM_DIRECT, 0, a, b, c,
                              d, 0.1, 5, 1)
     assert st == R.RAM_E_INVALID_ARG and b"context" in lib.ram_last_error()
+
+
+def test_layout_errors(lib):
+    # an empty batch, negative widths, ragged layouts without offsets or with
+    # a shared mesh are refused before any device work, by every entry point
+    from paper_2305_05362_amd import _lib as R
+    a, b, c = (ctypes.c_void_p(0x1000 * i) for i in (1, 2, 3))
+    cases = [(R.Layout(0, 16, None, 0, 1), b"n_rows"),
+             (R.Layout(2, -1, None, 0, 1), b"n_cols"),
+             (R.Layout(2, 0, None, 10, 0), b"row_ptr"),
+             (R.Layout(2, 0, a, 0, 0), b"n_cells"),
+             (R.Layout(2, 0, a, 10, 1), b"shared")]
+    for L, msg in cases:
+        st = lib.ram_step(None, ctypes.byref(L), R.RAM_F64, R.RAM_SCAN_F64, a, b, c, None,
+                          0.1, 5, 1)
+        assert st == R.RAM_E_INVALID_ARG and msg in lib.ram_last_error(), msg
+        st = lib.ram_cell_average(None, ctypes.byref(L), R.RAM_F64, a, b, c, 0)
+        assert st == R.RAM_E_INVALID_ARG and msg in lib.ram_last_error(), msg
+    st = lib.ram_step(None, None, R.RAM_F64, R.RAM_SCAN_F64, a, b, c, None, 0.1, 5, 1)
+    assert st == R.RAM_E_INVALID_ARG and b"layout" in lib.ram_last_error()
