@@ -110,6 +110,31 @@ __device__ __attribute__((noinline)) double direct_qtilde(
     return dq;
 }
 
+// Eight consecutive values of an LDS array from index 4t (16-byte aligned):
+// 16-byte reads, lane-consecutive, so the banks serve them without conflict
+// (eight 4-byte reads four words apart per lane would conflict 8-way).
+template <typename T>
+__device__ inline void lds_read8(const T *p, T (&o)[8])
+{
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8 || sizeof(T) == 16, "element size");
+    if constexpr (sizeof(T) == 4) {
+        const float4 a = ((const float4 *)p)[0], b = ((const float4 *)p)[1];
+        const float v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+        for (int i = 0; i < 8; ++i) o[i] = __builtin_bit_cast(T, v[i]);
+    } else if constexpr (sizeof(T) == 8) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const double2 a = ((const double2 *)p)[i];
+            o[2 * i] = __builtin_bit_cast(T, a.x);
+            o[2 * i + 1] = __builtin_bit_cast(T, a.y);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) o[i] = p[i];
+    }
+}
+
 template <typename CT>
 struct AdjLds {
     using CT2 = typename TabT<CT>::T2;
@@ -199,18 +224,20 @@ __global__ __launch_bounds__(kBlock) void k_adj_sh(StepAdjArgs a)
         __syncthreads();
         const int u0 = 4 * t;                        // first cell of the thread
         if (u0 < nd) {
-            CT q[8], qb[8], di[8], dx[8], hv[8], vv[7];
+            CT q[8], qb[8], di[8], dx[8], hv[8], vv[7], v8[8];
+            CT2 r8[8];
+            lds_read8(sqh + u0, q);
+            lds_read8(sqb + u0, qb);
+            lds_read8(sdi + u0, di);
+            lds_read8(srr + u0, r8);
+            lds_read8(sdv + u0, v8);
 #pragma unroll
             for (int w = 0; w < 8; ++w) {
-                q[w] = sqh[u0 + w];
-                qb[w] = sqb[u0 + w];
-                di[w] = sdi[u0 + w];
-                const CT2 r = srr[u0 + w];
-                dx[w] = r.x;
-                hv[w] = r.y;
+                dx[w] = r8[w].x;
+                hv[w] = r8[w].y;
             }
 #pragma unroll
-            for (int f = 0; f < 7; ++f) vv[f] = sdv[u0 + 1 + f];
+            for (int f = 0; f < 7; ++f) vv[f] = v8[f + 1];
             // faces a-1+f, between window cells f and f+1
             CT fbar[7], qsb[7], scs[7], half[7];
             bool up[7];
