@@ -182,7 +182,15 @@ struct RowsPlan {
     size_t rag_off = 0, tab_off = 0;
     int tile = ram::kTile;
     int order = 0;          // > 0: build the shared-mesh tables for this order
+    bool uniform = false;   // and the uniform-run counts (the FP32 direct step)
 };
+
+// The step kernels use a shared mesh's uniform runs on the FP32 direct-sum
+// Lagrange path only.
+bool wants_uniform(ram_dtype dtype, ram_scan scan)
+{
+    return dtype == RAM_F32 && scan == RAM_SUM_DIRECT;
+}
 
 // Reserve what make_rows will need.
 RowsPlan plan_rows(Carve &cv, const ram_layout *L, int tile, int tab_order)
@@ -223,7 +231,7 @@ ram_status make_rows(ram_ctx *ctx, const ram_layout *L, const double *edges,
     if (p.order > 0) {
         hipError_t e = ram::launch_mesh_prep(edges, L->n_cols, p.order,
                                              (char *)ctx->scratch + p.tab_off,
-                                             R.tab, ctx->stream);
+                                             R.tab, ctx->stream, p.uniform);
         if (e != hipSuccess) return hip_fail(e, "mesh table launch");
         R.has_tab = 1;
     }
@@ -400,7 +408,7 @@ ram_status step_adjoint_shared(ram_ctx *ctx, const ram_layout *layout, ram_dtype
     // size keeps them within one item per thread
     RowsPlan rp = plan_rows(cv, layout, ram::step_tile(true), order);
     const int64_t nt = tiles_of(layout, rp.tile);
-    const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(2 * sizeof(int32_t) * nt);
+    const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(ram::kPlanW * sizeof(int32_t) * nt);
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
     ram::StepArgs p;
     if ((st = make_rows(ctx, layout, edges, rp, p.rows)) != RAM_OK) return st;
@@ -570,8 +578,9 @@ ram_status ram_shift(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
     const int items = sched_items(ctx, layout, scan);
     Carve cv;
     RowsPlan rp = plan_rows(cv, layout, ram::step_tile_for(items, false), order);
+    rp.uniform = wants_uniform(dtype, scan);
     const int64_t nt = tiles_of(layout, rp.tile);
-    const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(2 * sizeof(int32_t) * nt);
+    const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(ram::kPlanW * sizeof(int32_t) * nt);
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
     ram::StepArgs a;
     if ((st = make_rows(ctx, layout, edges, rp, a.rows)) != RAM_OK) return st;
@@ -632,8 +641,9 @@ ram_status ram_step(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
     const size_t tmp_off = cv.take(state_bytes);
     const int items = sched_items(ctx, layout, scan);
     RowsPlan rp = plan_rows(cv, layout, ram::step_tile_for(items, dv != nullptr), order);
+    rp.uniform = wants_uniform(dtype, scan);
     const int64_t nt = tiles_of(layout, rp.tile);
-    const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(2 * sizeof(int32_t) * nt);
+    const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(ram::kPlanW * sizeof(int32_t) * nt);
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
     ram::StepArgs a;
     std::memset(&a, 0, sizeof(a));        // the graph key compares raw bytes
@@ -667,7 +677,7 @@ ram_status ram_shift_limited(ram_ctx *ctx, const ram_layout *layout, ram_dtype d
     RowsPlan rp = plan_rows(cv, layout, ram::step_tile(false), 1);
     const int64_t nt = tiles_of(layout, rp.tile);
     const size_t wlo_off = shared ? cv.take(sizeof(int64_t) * nt) : 0;
-    const size_t w_off = shared ? cv.take(2 * sizeof(int32_t) * nt) : 0;
+    const size_t w_off = shared ? cv.take(ram::kPlanW * sizeof(int32_t) * nt) : 0;
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
     ram::StepArgs a;
     if ((st = make_rows(ctx, layout, edges, rp, a.rows)) != RAM_OK) return st;
@@ -705,7 +715,7 @@ ram_status ram_step_limited(ram_ctx *ctx, const ram_layout *layout, ram_dtype dt
         RowsPlan rp = plan_rows(cv, layout, ram::step_tile(dv != nullptr), 1);
         const int64_t nt = tiles_of(layout, rp.tile);
         const size_t wlo_off = cv.take(sizeof(int64_t) * nt);
-        const size_t w_off = cv.take(2 * sizeof(int32_t) * nt);
+        const size_t w_off = cv.take(ram::kPlanW * sizeof(int32_t) * nt);
         if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
         ram::StepArgs a;
         std::memset(&a, 0, sizeof(a));    // the graph key compares raw bytes
@@ -793,7 +803,7 @@ ram_status ram_step_limited_record(ram_ctx *ctx, const ram_layout *layout,
                             shared ? ram::step_tile(dv != nullptr) : ram::step_tile(false), 1);
     const int64_t nt = tiles_of(layout, rp.tile);
     const size_t wlo_off = shared ? cv.take(sizeof(int64_t) * nt) : 0;
-    const size_t w_off = shared ? cv.take(2 * sizeof(int32_t) * nt) : 0;
+    const size_t w_off = shared ? cv.take(ram::kPlanW * sizeof(int32_t) * nt) : 0;
     RowsPlan rr = plan_rows(cv, layout, ram::kResTile, 0);
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
     ram::StepArgs a;
@@ -971,8 +981,9 @@ ram_status setup_row_step(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtyp
     rs.items = recon ? ram::kItems : sched_items(ctx, layout, scan);
     const int plan_order = recon == 0 ? order : (recon == RAM_RECON_PLM ? 3 : 5);
     RowsPlan rp = plan_rows(cv, layout, ram::step_tile_for(rs.items, dv != nullptr), plan_order);
+    rp.uniform = recon == 0 && wants_uniform(dtype, scan);
     const int64_t nt = tiles_of(layout, rp.tile);
-    const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(2 * sizeof(int32_t) * nt);
+    const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(ram::kPlanW * sizeof(int32_t) * nt);
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
     std::memset(&rs.a, 0, sizeof(rs.a));   // graph keys compare raw bytes
     if ((st = make_rows(ctx, layout, edges, rp, rs.a.rows)) != RAM_OK) return st;
@@ -1235,8 +1246,9 @@ ram_status ram_step_record(ram_ctx *ctx, const ram_layout *layout,
     Carve cv;
     const int items = sched_items(ctx, layout, scan);
     RowsPlan rp = plan_rows(cv, layout, ram::step_tile_for(items, dv != nullptr), order);
+    rp.uniform = wants_uniform(dtype, scan);
     const int64_t nt = tiles_of(layout, rp.tile);
-    const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(2 * sizeof(int32_t) * nt);
+    const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(ram::kPlanW * sizeof(int32_t) * nt);
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
     ram::StepArgs a;
     if ((st = make_rows(ctx, layout, edges, rp, a.rows)) != RAM_OK) return st;

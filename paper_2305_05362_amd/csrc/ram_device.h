@@ -497,8 +497,8 @@ __device__ inline void rec_weights(const CellRec<WT> &r, double xt, WT *w)
 // node is wrapped into the row with its period count kx).  The plan uses it
 // for the two end nodes of every tile; the step kernel evaluates the same
 // arithmetic inline, in batches.
-__device__ inline int64_t node_index(const double *x, int n, const MeshTab &tb,
-                                     const RowShift &rs, double len, int e)
+__device__ inline int64_t node_locate(const double *x, int n, const MeshTab &tb,
+                                      const RowShift &rs, int e, double &xt, int &cell)
 {
     int kx = 0;
     if (e < 0) { e += n; kx = -1; }
@@ -507,7 +507,29 @@ __device__ inline int64_t node_index(const double *x, int n, const MeshTab &tb,
     const NodePos np = node_pos(x[e], rs, x[0], x[n], bsc, bx0, tb.nb);
     int c = cell_from_bucket(tb.bucket[np.b], tb.bnext[np.b], np.xt);
     if (np.xt >= tb.bnext[np.b].y) c = cell_walk(x, n, c, np.xt);
+    xt = np.xt;
+    cell = c;
     return (int64_t)c + (rs.kf0 + np.dk + kx) * (int64_t)n;
+}
+
+__device__ inline int64_t node_index(const double *x, int n, const MeshTab &tb,
+                                     const RowShift &rs, double len, int e)
+{
+    double xt;
+    int c;
+    (void)len;
+    return node_locate(x, n, tb, rs, e, xt, c);
+}
+
+// Non-uniform cells (MeshTab::nonu) among the extended source indices [a, b)
+// of a periodic row of n cells.
+__device__ inline int64_t nonu_count(const int32_t *pre, int n, int64_t a, int64_t b)
+{
+    auto upto = [&](int64_t i) {
+        const int64_t k = i >= 0 ? i / n : -((-i + n - 1) / n);
+        return k * (int64_t)pre[n] + pre[i - k * n];
+    };
+    return upto(b) - upto(a);
 }
 
 // ---- limited reconstructions of the bulk shift (Section 3.1, App. A) ----

@@ -16,6 +16,8 @@ constexpr int kWindowCap = 2048;
 // Cells per tile of the residual step alone: four per thread, with the
 // two-cell halo a side staged in one item per thread.
 constexpr int kResTile = 1020;
+// int32 entries per tile of the window plan
+constexpr int kPlanW = 3;
 // Centre value <-> cell average conversion: four cells per thread.
 constexpr int kAvgItems = 4;
 constexpr int kAvgTile = kBlock * kAvgItems;
@@ -55,7 +57,15 @@ struct MeshTab {
     // n back to back), FP64 and FP32
     const double *ppmd = nullptr;
     const float *ppmf = nullptr;
+    // prefix counts (n + 1) of the cells whose size differs from the mesh's
+    // largest by more than kUniformTol of it: a run with no such cell is
+    // uniformly spaced
+    const int32_t *nonu = nullptr;
 };
+
+// Relative spacing tolerance of a uniform run (a tile's shifted nodes then
+// share one stencil offset and one theta to within FP32 rounding).
+constexpr double kUniformTol = 1e-10;
 
 // Everything the bulk shift needs about source cell c in one record (one
 // cache line in FP32, two in FP64): x_c, 1/dx_c, and the stencil data
@@ -216,11 +226,14 @@ hipError_t launch_tiles_prep(const int64_t *row_ptr, int64_t n_rows, int tile,
 size_t mesh_tab_bytes(int64_t n, int order);
 // Build the tables in `mem` (mesh_tab_bytes) and point `tab` at them.
 hipError_t launch_mesh_prep(const double *x, int64_t n, int order, void *mem,
-                            MeshTab &tab, hipStream_t stream);
+                            MeshTab &tab, hipStream_t stream, bool uniform = false);
 hipError_t launch_step(const StepArgs &a, bool f64, int scan, int order,
                        hipStream_t stream);
 // Shared-mesh specialisation: plan the tiles' source windows once per call
-// (launch_plan, into n_tiles int64 + 2 n_tiles int32), then one launch per step.
+// (launch_plan, into n_tiles int64 + kPlanW n_tiles int32), then one launch per step.
+// The int32 part holds per tile its window length (-1: direct path), the
+// window start mod n, and, for a tile whose nodes and source window lie in
+// one uniform run, the float bits of its first node's theta (else -1.0f).
 hipError_t launch_plan(const StepArgs &a, int order, int64_t *wlo, int32_t *w,
                        hipStream_t stream);
 hipError_t launch_step_shared(const StepArgs &a, bool f64, int scan, int order,

@@ -570,6 +570,7 @@ struct MeshTabW {
     double2 *rrd;
     double *ppmd;
     float *ppmf;
+    int32_t *nonu;
 };
 
 template <int P>
@@ -644,6 +645,51 @@ __global__ __launch_bounds__(256) void k_mesh_prep(const double *x, int n, MeshT
     }
 }
 
+// Uniform runs of a shared mesh: prefix counts of the cells whose size
+// differs from the largest by more than kUniformTol of it.  One workgroup of
+// 1024 threads: the largest size by a coalesced pass and a block reduction;
+// then, 32 Ki cells at a time, every lane's flags for up to 32 chunks of 1024
+// cells (loads pipelined, no barrier between them) and a prefix per chunk
+// from one ballot per wave and the waves' totals in LDS.
+__global__ __launch_bounds__(1024) void k_mesh_uniform(const double *x, int n, int32_t *nonu)
+{
+    __shared__ double smax[16];
+    __shared__ int32_t swt[16];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    double m = 0.0;
+    for (int j = t; j < n; j += 1024) m = fmax(m, x[j + 1] - x[j]);
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if (lane == 0) smax[wv] = m;
+    __syncthreads();
+    double h = smax[0];
+    for (int w = 1; w < 16; ++w) h = fmax(h, smax[w]);
+    int32_t base = 0;
+    for (int s0 = 0; s0 < n; s0 += 32 * 1024) {
+        uint32_t bits = 0;
+#pragma unroll 8
+        for (int k = 0; k < 32; ++k) {
+            const int j = s0 + k * 1024 + t;
+            if (j < n && fabs((x[j + 1] - x[j]) - h) > kUniformTol * h) bits |= 1u << k;
+        }
+        for (int k = 0; k < 32 && s0 + k * 1024 < n; ++k) {
+            const int j = s0 + k * 1024 + t;
+            const uint64_t mask = __ballot((bits >> k) & 1u);
+            const int32_t below = __popcll(mask & ((1ull << lane) - 1ull));
+            if (lane == 0) swt[wv] = __popcll(mask);
+            __syncthreads();
+            int32_t before = base, tot = 0;
+            for (int w = 0; w < 16; ++w) {
+                if (w < wv) before += swt[w];
+                tot += swt[w];
+            }
+            if (j < n) nonu[j] = before + below;
+            base += tot;
+            __syncthreads();
+        }
+    }
+    if (t == 0) nonu[n] = base;
+}
+
 // ---------------------------------------------------------------------------
 // ragged-row tile table: tile_ptr[r] = sum_{r'<r} ceil(N_r'/tile) and
 // tile_row[t] = row of tile t.  One workgroup of 1024 threads.
@@ -712,11 +758,11 @@ size_t mesh_tab_bytes(int64_t n, int order)
     return 3 * al256(8 * n) + 3 * al256(4 * n) + al256(8 * n * 2 * (order + 1)) +
            al256(4 * n * 2 * (order + 1)) + al256(4 * nb) + al256(16 * nb) + al256(16) +
            al256(sizeof(CellRec<float>) * n) + al256(sizeof(CellRec<double>) * n) +
-           al256(8 * n) + al256(16 * n) + al256(40 * n) + al256(20 * n);
+           al256(8 * n) + al256(16 * n) + al256(40 * n) + al256(20 * n) + al256(4 * (n + 1));
 }
 
 hipError_t launch_mesh_prep(const double *x, int64_t n, int order, void *mem,
-                            MeshTab &tab, hipStream_t stream)
+                            MeshTab &tab, hipStream_t stream, bool uniform)
 {
     char *p = (char *)mem;
     MeshTabW w;
@@ -737,7 +783,8 @@ hipError_t launch_mesh_prep(const double *x, int64_t n, int order, void *mem,
     w.rrf = (float2 *)p; p += al256(8 * n);
     w.rrd = (double2 *)p; p += al256(16 * n);
     w.ppmd = (double *)p; p += al256(40 * n);
-    w.ppmf = (float *)p;
+    w.ppmf = (float *)p; p += al256(20 * n);
+    w.nonu = (int32_t *)p;
     tab.dx = w.dx; tab.dxinv = w.dxinv; tab.hinv = w.hinv; tab.stc = w.stc;
     tab.dxf = w.dxf; tab.dxinvf = w.dxinvf; tab.hinvf = w.hinvf; tab.stcf = w.stcf;
     tab.bucket = w.bucket;
@@ -750,12 +797,16 @@ hipError_t launch_mesh_prep(const double *x, int64_t n, int order, void *mem,
     tab.rrd = w.rrd;
     tab.ppmd = w.ppmd;
     tab.ppmf = w.ppmf;
+    tab.nonu = uniform ? w.nonu : nullptr;
     const unsigned grid = (unsigned)((w.nb + 255) / 256);
     switch (order) {
     case 1: hipLaunchKernelGGL(k_mesh_prep<1>, dim3(grid), dim3(256), 0, stream, x, (int)n, w); break;
     case 3: hipLaunchKernelGGL(k_mesh_prep<3>, dim3(grid), dim3(256), 0, stream, x, (int)n, w); break;
     default: hipLaunchKernelGGL(k_mesh_prep<5>, dim3(grid), dim3(256), 0, stream, x, (int)n, w); break;
     }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !uniform) return e;
+    hipLaunchKernelGGL(k_mesh_uniform, dim3(1), dim3(1024), 0, stream, x, (int)n, w.nonu);
     return hipGetLastError();
 }
 

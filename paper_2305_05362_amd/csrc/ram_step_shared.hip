@@ -81,7 +81,9 @@ __global__ __launch_bounds__(256) void k_plan(StepArgs a, int64_t *wlo_out,
     const double *x = R.edges;
     const double len = x[n] - x[0];
     const RowShift rs = row_shift(a.v0[row] * a.dt, len, R.tab.scal[1]);
-    const int64_t g0 = node_index(x, n, R.tab, rs, len, i0 - H);
+    double xt0;
+    int c0;
+    const int64_t g0 = node_locate(x, n, R.tab, rs, i0 - H, xt0, c0);
     const int64_t g1 = node_index(x, n, R.tab, rs, len, i0 + nd + H);
     const int64_t wide = g1 - g0 + P;
     const int64_t wlo = g0 - LO;
@@ -90,6 +92,16 @@ __global__ __launch_bounds__(256) void k_plan(StepArgs a, int64_t *wlo_out,
     // the window start inside the row, wlo mod n
     const int64_t kk = wlo >= 0 ? wlo / n : -((-wlo + n - 1) / n);
     w_out[R.n_tiles + tile] = (int32_t)(wlo - kk * n);
+    // a uniform tile: the cells on both sides of its nodes and its source
+    // window lie in the mesh's uniform run, and the window holds exactly one
+    // source cell per node (plus the stencil), so node i0 - H + k sits in
+    // window cell LO + k at the first node's theta
+    float thu = -1.0f;
+    if (R.tab.nonu && wide == nd + 2 * H + P &&
+        nonu_count(R.tab.nonu, n, i0 - H - 1, i0 + nd + H + 1) == 0 &&
+        nonu_count(R.tab.nonu, n, wlo, wlo + wide) == 0)
+        thu = (float)((xt0 - x[c0]) * R.tab.dxinv[c0]);
+    w_out[2 * R.n_tiles + tile] = __float_as_int(thu);
 }
 
 // Periodic index for j in [-n, 2n).
@@ -117,6 +129,30 @@ __device__ inline int density_cell(const double *x, int n, const MeshDensity &d,
         hi = x[c + 1];
     }
     return c;
+}
+
+// Lagrange weights of a uniform stencil (nodes at -LO .. P-LO cell sizes from
+// the cell's left node) at theta: the cell record's weights on a uniform run.
+template <typename CT, int P>
+__device__ inline void uniform_weights(CT th, CT *w)
+{
+    constexpr int LO = (P - 1) / 2;
+    CT t[P + 1], pre[P + 1], suf[P + 1];
+#pragma unroll
+    for (int a = 0; a <= P; ++a) t[a] = th - (CT)(a - LO);
+    pre[0] = (CT)1;
+#pragma unroll
+    for (int a = 1; a <= P; ++a) pre[a] = pre[a - 1] * t[a - 1];
+    suf[P] = (CT)1;
+#pragma unroll
+    for (int a = P - 1; a >= 0; --a) suf[a] = suf[a + 1] * t[a + 1];
+#pragma unroll
+    for (int a = 0; a <= P; ++a) {
+        double den = 1.0;                 // prod_{b != a} (a - b), exact
+        for (int b = 0; b <= P; ++b)
+            if (b != a) den *= (double)(a - b);
+        w[a] = (CT)(1.0 / den) * (pre[a] * suf[a]);
+    }
 }
 
 // IDX 1: the source cells come from the mesh-density index (a.dens) instead of
@@ -182,6 +218,17 @@ __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
     // window index of a node = c + (dk + kx) n + jbase
     const int jbase = (int)(rs.kf0 * (int64_t)n - wlo);
 
+    // A uniform tile (FP32, direct sums, Lagrange shift): the plan found its
+    // nodes and source window in the mesh's uniform run, so node k of the
+    // tile sits in window cell LO + k at one theta and every node shares one
+    // set of weights -- no search, no cell record (the per-node weights would
+    // agree with them to FP32 rounding).
+    bool uni = false;
+    float thu = -1.0f;
+    if constexpr (kDirect && !kLim && sizeof(TQ) == 4) {
+        thu = __int_as_float(a.plan_w[2 * R.n_tiles + blockIdx.x]);
+        uni = thu >= 0.0f;
+    }
     // ---- loads that do not depend on the search, issued first ------------
     double xe[NI];
     int kxn[NI];
@@ -190,7 +237,7 @@ __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
         const int ei = t + k * kBlock;
         const int e = i0 - H + ei;
         kxn[k] = inner ? 0 : (e < 0 ? -n : (e >= n ? n : 0));
-        xe[k] = ei < NE ? x[inner ? e : wrap1(e, n)] : x0;
+        xe[k] = (ei < NE && !uni) ? x[inner ? e : wrap1(e, n)] : x0;
     }
     // window start inside the row: wlo mod n
     const int base = a.plan_w[R.n_tiles + blockIdx.x];   // wlo mod n
@@ -282,6 +329,33 @@ __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
             }
             __syncthreads();
         }
+        if (uni) {
+            CT wu[P + 1];
+            uniform_weights<CT, P>((CT)thu, wu);
+#pragma unroll
+            for (int k = 0; k < NI; ++k) {
+                const int ei = t + k * kBlock;
+                jc[k] = 0;
+                if (ei < NE) {
+                    const int j = LO + ei;
+                    jc[k] = j;
+                    ok = ok && j + P - LO <= W;
+                    CT ell = (CT)0, up = (CT)0, dn = (CT)0;
+#pragma unroll
+                    for (int b = LO + 1; b <= P; ++b) {
+                        up += (CT)sm[j + b - LO - 1];
+                        ell += wu[b] * up;
+                    }
+#pragma unroll
+                    for (int b = LO - 1; b >= 0; --b) {
+                        dn += (CT)sm[j - LO + b];
+                        ell -= wu[b] * dn;
+                    }
+                    sell[ei] = ell;
+                    sjc[ei] = (short)j;
+                }
+            }
+        } else {
         NodePos np[NI];
         int cb[NI];
         double2 nx[NI];
@@ -346,6 +420,7 @@ __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
                 sell[ei] = ell;
                 sjc[ei] = (short)j;
             }
+        }
         }
     } else {
 #pragma unroll

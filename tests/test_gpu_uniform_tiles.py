@@ -1,0 +1,83 @@
+"""The FP32 direct-sum step on tiles that lie in a uniform run of a shared mesh
+(one stencil offset and one theta for every node of the tile, from the window
+plan) against the FP64 oracle run on the same FP32 inputs, <= 1e-6 relative
+L1:
+
+* a uniform mesh (every tile takes the uniform path), shifts below a cell,
+  of several cells and of many periods either way, with and without the
+  residual, over one and five steps;
+* the same mesh with one cell 0.1 % shorter (the rest stay the largest, so
+  the run holds every other cell): the tiles that see it must not take the
+  uniform path (the check would miss it by far more than 1e-6);
+* the polar disk's bump mesh, whose uniform run wraps over the periodic seam
+  and whose tiles straddle the run's ends.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2305_05362_amd import _lib as R
+from paper_2305_05362_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a).reshape(-1), dtype=dtype, device=DEV)
+
+
+def rel_l1(a, b):
+    return float(np.sum(np.abs(a - b)) / np.sum(np.abs(b)))
+
+
+def f32(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def _rows(edges, n_rows, seed, shifts):
+    n = len(edges) - 1
+    rng = np.random.default_rng(seed)
+    xc = 0.5 * (edges[:-1] + edges[1:])
+    q = 1.0 + 0.3 * np.sin(2 * np.pi * xc)[None, :] + 0.05 * rng.standard_normal((n_rows, n))
+    dv = 0.2 * np.diff(edges).min() * rng.uniform(-1, 1, (n_rows, n))
+    wl = W.Workload("uni", n_rows, n, np.arange(n_rows + 1) * n, edges, True, f32(q),
+                    f32(dv), np.asarray(shifts, dtype=np.float64), 1.0, 5, 1)
+    return wl
+
+
+def _check(wl, steps, with_dv):
+    rows = R.Rows.from_workload(wl, DEV)
+    q = dev(wl.q0, torch.float32)
+    dv = dev(wl.dv, torch.float32) if with_dv else None
+    R.ram_step(rows, q, dev(wl.v0), dv, wl.dt, 5, steps, R.RAM_SUM_DIRECT)
+    torch.cuda.synchronize()
+    want = oracle.step(oracle.Rows.from_workload(wl), wl.q0, wl.v0,
+                       wl.dv if with_dv else None, wl.dt, 5, steps)
+    return rel_l1(q.cpu().numpy().astype(np.float64), want)
+
+
+SHIFTS = [0.3 / 4096, 0.37 / 4096, 5.21 / 4096, -3.7 / 4096, 2.5 + 7.3 / 4096, -1.0 - 0.61 / 4096]
+
+
+@pytest.mark.parametrize("steps", [1, 5])
+@pytest.mark.parametrize("with_dv", [False, True])
+def test_uniform_mesh(steps, with_dv):
+    e = W.uniform_edges(4096, 0.0, 1.0)
+    assert _check(_rows(e, len(SHIFTS), 1, SHIFTS), steps, with_dv) <= 1e-6
+
+
+@pytest.mark.parametrize("cell", [0, 1500, 4095])
+def test_one_shorter_cell(cell):
+    e = W.uniform_edges(4096, 0.0, 1.0).copy()
+    h = e[1] - e[0]
+    e[cell + 1:] -= 1e-3 * h          # cell `cell` is 0.1 % shorter
+    e = e * (1.0 / e[-1])
+    assert _check(_rows(e, len(SHIFTS), 2, SHIFTS), 3, True) <= 1e-6
+
+
+def test_bump_mesh_runs_and_seam():
+    wl = W.small_polar(8, 6000)
+    w32 = _rows(wl.edges, 8, 3, wl.v0 * wl.dt)
+    assert _check(w32, 4, True) <= 1e-6
