@@ -713,6 +713,7 @@ ram_status ram_step_limited(ram_ctx *ctx, const ram_layout *layout, ram_dtype dt
         Carve cv;
         const size_t tmp_off = cv.take(state_bytes);
         RowsPlan rp = plan_rows(cv, layout, ram::step_tile(dv != nullptr), 1);
+        rp.uniform = dtype == RAM_F32;
         const int64_t nt = tiles_of(layout, rp.tile);
         const size_t wlo_off = cv.take(sizeof(int64_t) * nt);
         const size_t w_off = cv.take(ram::kPlanW * sizeof(int32_t) * nt);
@@ -801,6 +802,7 @@ ram_status ram_step_limited_record(ram_ctx *ctx, const ram_layout *layout,
     // per-row meshes: the shift kernel into q_half, then the residual kernel
     RowsPlan rp = plan_rows(cv, layout,
                             shared ? ram::step_tile(dv != nullptr) : ram::step_tile(false), 1);
+    rp.uniform = shared && dtype == RAM_F32;
     const int64_t nt = tiles_of(layout, rp.tile);
     const size_t wlo_off = shared ? cv.take(sizeof(int64_t) * nt) : 0;
     const size_t w_off = shared ? cv.take(ram::kPlanW * sizeof(int32_t) * nt) : 0;
@@ -981,7 +983,7 @@ ram_status setup_row_step(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtyp
     rs.items = recon ? ram::kItems : sched_items(ctx, layout, scan);
     const int plan_order = recon == 0 ? order : (recon == RAM_RECON_PLM ? 3 : 5);
     RowsPlan rp = plan_rows(cv, layout, ram::step_tile_for(rs.items, dv != nullptr), plan_order);
-    rp.uniform = recon == 0 && wants_uniform(dtype, scan);
+    rp.uniform = dtype == RAM_F32 && (recon != 0 || scan == RAM_SUM_DIRECT);
     const int64_t nt = tiles_of(layout, rp.tile);
     const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(ram::kPlanW * sizeof(int32_t) * nt);
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;

@@ -218,14 +218,15 @@ __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
     // window index of a node = c + (dk + kx) n + jbase
     const int jbase = (int)(rs.kf0 * (int64_t)n - wlo);
 
-    // A uniform tile (FP32, direct sums, Lagrange shift): the plan found its
-    // nodes and source window in the mesh's uniform run, so node k of the
-    // tile sits in window cell LO + k at one theta and every node shares one
-    // set of weights -- no search, no cell record (the per-node weights would
-    // agree with them to FP32 rounding).
+    // A uniform tile (FP32, direct sums): the plan found its nodes and source
+    // window in the mesh's uniform run, so node k of the tile sits in window
+    // cell LO + k at one theta -- no search, no cell record; the Lagrange
+    // shift shares one set of weights, the limited shift evaluates each
+    // cell's cubic at that theta (per-node values would agree to FP32
+    // rounding).
     bool uni = false;
     float thu = -1.0f;
-    if constexpr (kDirect && !kLim && sizeof(TQ) == 4) {
+    if constexpr (kDirect && sizeof(TQ) == 4) {
         thu = __int_as_float(a.plan_w[2 * R.n_tiles + blockIdx.x]);
         uni = thu >= 0.0f;
     }
@@ -329,7 +330,31 @@ __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
             }
             __syncthreads();
         }
-        if (uni) {
+        if (uni && kLim) {
+            // the limited cubic of each node's cell at the shared theta
+            const CT tt = (CT)thu;
+#pragma unroll
+            for (int k = 0; k < NI; ++k) {
+                const int ei = t + k * kBlock;
+                jc[k] = 0;
+                if (ei < NE) {
+                    const int j = LO + ei;
+                    jc[k] = j;
+                    ok = ok && j + P - LO <= W;
+                    CT ell;
+                    if constexpr (RECON == kReconPLM) {
+                        const CT kap = sx3[j];
+                        ell = tt * ((CT)sm[j] - kap + tt * kap);
+                    } else {
+                        const CT pa = sx2[j], pc = sx1[j];
+                        const CT pb = (CT)sm[j] - pa - pc;
+                        ell = tt * (pa + tt * (pb + tt * pc));
+                    }
+                    sell[ei] = ell;
+                    sjc[ei] = (short)j;
+                }
+            }
+        } else if (uni) {
             CT wu[P + 1];
             uniform_weights<CT, P>((CT)thu, wu);
 #pragma unroll

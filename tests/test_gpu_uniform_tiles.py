@@ -10,7 +10,9 @@ L1:
   the run holds every other cell): the tiles that see it must not take the
   uniform path (the check would miss it by far more than 1e-6);
 * the polar disk's bump mesh, whose uniform run wraps over the periodic seam
-  and whose tiles straddle the run's ends.
+  and whose tiles straddle the run's ends;
+* the limited PLM / PPM step on the same three meshes (each node's cell
+  cubic at the tile's shared theta), against the oracle's limited step.
 """
 import numpy as np
 import pytest
@@ -81,3 +83,29 @@ def test_bump_mesh_runs_and_seam():
     wl = W.small_polar(8, 6000)
     w32 = _rows(wl.edges, 8, 3, wl.v0 * wl.dt)
     assert _check(w32, 4, True) <= 1e-6
+
+
+def _check_limited(wl, steps, recon):
+    rows = R.Rows.from_workload(wl, DEV)
+    q = dev(wl.q0, torch.float32)
+    R.ram_step_limited(rows, q, dev(wl.v0), dev(wl.dv, torch.float32), wl.dt, recon, steps)
+    torch.cuda.synchronize()
+    want = oracle.step_recon(oracle.Rows.from_workload(wl), wl.q0, wl.v0, wl.dv, wl.dt,
+                             recon, steps)
+    return rel_l1(q.cpu().numpy().astype(np.float64), want)
+
+
+@pytest.mark.parametrize("recon", [R.RAM_RECON_PLM, R.RAM_RECON_PPM])
+@pytest.mark.parametrize("mesh", ["uniform", "shorter", "bump"])
+def test_limited_uniform_tiles(recon, mesh):
+    # the limited cubic of each cell at the tile's shared theta
+    if mesh == "bump":
+        wl0 = W.small_polar(8, 6000)
+        wl = _rows(wl0.edges, 8, 4, wl0.v0 * wl0.dt)
+    else:
+        e = W.uniform_edges(4096, 0.0, 1.0).copy()
+        if mesh == "shorter":
+            e[2001:] -= 1e-3 * (e[1] - e[0])
+            e = e * (1.0 / e[-1])
+        wl = _rows(e, len(SHIFTS), 5, SHIFTS)
+    assert _check_limited(wl, 3, recon) <= 1e-6
