@@ -295,6 +295,15 @@ __global__ __launch_bounds__(kBlock) void k_adj_sh(StepAdjArgs a)
     __syncthreads();
 
     // ---- (2) shifted nodes, tile-local Vbar ---------------------------------
+    // A uniform tile (FP32; the window plan found its nodes and window in the
+    // mesh's uniform run): node e sits in window cell LO + e at the plan's
+    // theta, so every node shares one set of weights and no search is made.
+    bool uni = false;
+    float thu = -1.0f;
+    if constexpr (sizeof(TQ) == 4) {
+        thu = __int_as_float(a.plan_w[2 * R.n_tiles + blockIdx.x]);
+        uni = thu >= 0.0f && W > 0 && W <= kWinA;
+    }
     int64_t g[NI];
     CT w[NI][P + 1];
     double vb[NI], xh[NI];
@@ -305,12 +314,19 @@ __global__ __launch_bounds__(kBlock) void k_adj_sh(StepAdjArgs a)
         const int e = t + k * kBlock;
         g[k] = 0;
         vb[k] = 0.0;
-        if (e < NE) {
+        if (e < NE && uni) {
+            g[k] = wlo + LO + e;
+            uniform_weights<CT, P>((CT)thu, w[k]);
+            cc[k] = 0;
+            xh[k] = 0.0;
+        } else if (e < NE) {
             const int en = i0 + e;
             const int kx = en >= n ? 1 : 0;
             const double xe = x[en >= n ? en - n : en];
             g[k] = node_eval_adj<CT, P>(x, n, tb, rs, len, xe, kx, w[k], cc[k],
                                         xh[k]);
+        }
+        if (e < NE) {
             vb[k] = (e >= 1 ? (double)smb[e - 1] : 0.0) - (e <= nd - 1 ? (double)smb[e] : 0.0);
             const int64_t jc = g[k] - wlo;
             ok = ok && jc >= LO && jc + P - LO <= W;
@@ -389,13 +405,21 @@ __global__ __launch_bounds__(kBlock) void k_adj_sh(StepAdjArgs a)
         // reconstruction q~ at the nodes: sum_b w'_b (C(g-lo+b) - C(g)) / dx_c,
         // the differences summed from the masses next to the node
         if (want_v0) {
+            // a uniform tile's derivative weights, once (one cell size in the run)
+            double dwu[P + 1];
+            if (uni) uniform_dweights<CT, P>((CT)thu, tb.dxinv[base], dwu);
 #pragma unroll
             for (int k = 0; k < NI; ++k) {
                 const int e = t + k * kBlock;
                 if (e < NE) {
                     const int jc = (int)(g[k] - wlo);
                     double dwd[P + 1];
-                    node_dweights<CT, P>(tb, cc[k], xh[k], dwd);
+                    if (uni) {
+#pragma unroll
+                        for (int b = 0; b <= P; ++b) dwd[b] = dwu[b];
+                    } else {
+                        node_dweights<CT, P>(tb, cc[k], xh[k], dwd);
+                    }
                     double dq = 0.0, up = 0.0, dn = 0.0;
 #pragma unroll
                     for (int b = LO + 1; b <= P; ++b) {

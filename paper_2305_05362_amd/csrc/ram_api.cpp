@@ -407,6 +407,7 @@ ram_status step_adjoint_shared(ram_ctx *ctx, const ram_layout *layout, ram_dtype
     // the residual transpose stages cells i0-2 .. i0+nd+1: the fused tile
     // size keeps them within one item per thread
     RowsPlan rp = plan_rows(cv, layout, ram::step_tile(true), order);
+    rp.uniform = dtype == RAM_F32;
     const int64_t nt = tiles_of(layout, rp.tile);
     const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(ram::kPlanW * sizeof(int32_t) * nt);
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;

@@ -493,6 +493,62 @@ __device__ inline void rec_weights(const CellRec<WT> &r, double xt, WT *w)
     for (int a = 0; a <= P; ++a) w[a] = r.rd[a] * (pre[a] * suf[a]);
 }
 
+// Lagrange weights of a uniform stencil (nodes at -LO .. P-LO cell sizes from
+// the cell's left node) at theta: the cell record's weights on a uniform run.
+template <typename CT, int P>
+__device__ inline void uniform_weights(CT th, CT *w)
+{
+    constexpr int LO = (P - 1) / 2;
+    CT t[P + 1], pre[P + 1], suf[P + 1];
+#pragma unroll
+    for (int a = 0; a <= P; ++a) t[a] = th - (CT)(a - LO);
+    pre[0] = (CT)1;
+#pragma unroll
+    for (int a = 1; a <= P; ++a) pre[a] = pre[a - 1] * t[a - 1];
+    suf[P] = (CT)1;
+#pragma unroll
+    for (int a = P - 1; a >= 0; --a) suf[a] = suf[a + 1] * t[a + 1];
+#pragma unroll
+    for (int a = 0; a <= P; ++a) {
+        double den = 1.0;                 // prod_{b != a} (a - b), exact
+        for (int b = 0; b <= P; ++b)
+            if (b != a) den *= (double)(a - b);
+        w[a] = (CT)(1.0 / den) * (pre[a] * suf[a]);
+    }
+}
+
+// Their derivatives with respect to x (theta over the cell size dx, 1/dx =
+// dxinv), in FP64 as the cell-record form gives them.
+template <typename CT, int P>
+__device__ inline void uniform_dweights(CT th, double dxinv, double *dw)
+{
+    constexpr int LO = (P - 1) / 2;
+    CT t[P + 1], pre[P + 1], suf[P + 1], dpre[P + 1], dsuf[P + 1];
+#pragma unroll
+    for (int a = 0; a <= P; ++a) t[a] = th - (CT)(a - LO);
+    pre[0] = (CT)1;
+    dpre[0] = (CT)0;
+#pragma unroll
+    for (int a = 1; a <= P; ++a) {
+        pre[a] = pre[a - 1] * t[a - 1];
+        dpre[a] = dpre[a - 1] * t[a - 1] + pre[a - 1];
+    }
+    suf[P] = (CT)1;
+    dsuf[P] = (CT)0;
+#pragma unroll
+    for (int a = P - 1; a >= 0; --a) {
+        suf[a] = suf[a + 1] * t[a + 1];
+        dsuf[a] = dsuf[a + 1] * t[a + 1] + suf[a + 1];
+    }
+#pragma unroll
+    for (int a = 0; a <= P; ++a) {
+        double den = 1.0;
+        for (int b = 0; b <= P; ++b)
+            if (b != a) den *= (double)(a - b);
+        dw[a] = (double)((CT)(1.0 / den) * (dpre[a] * suf[a] + pre[a] * dsuf[a])) * dxinv;
+    }
+}
+
 // Extended source index g = c + k n of node e of a row (any integer e; the
 // node is wrapped into the row with its period count kx).  The plan uses it
 // for the two end nodes of every tile; the step kernel evaluates the same

@@ -131,30 +131,6 @@ __device__ inline int density_cell(const double *x, int n, const MeshDensity &d,
     return c;
 }
 
-// Lagrange weights of a uniform stencil (nodes at -LO .. P-LO cell sizes from
-// the cell's left node) at theta: the cell record's weights on a uniform run.
-template <typename CT, int P>
-__device__ inline void uniform_weights(CT th, CT *w)
-{
-    constexpr int LO = (P - 1) / 2;
-    CT t[P + 1], pre[P + 1], suf[P + 1];
-#pragma unroll
-    for (int a = 0; a <= P; ++a) t[a] = th - (CT)(a - LO);
-    pre[0] = (CT)1;
-#pragma unroll
-    for (int a = 1; a <= P; ++a) pre[a] = pre[a - 1] * t[a - 1];
-    suf[P] = (CT)1;
-#pragma unroll
-    for (int a = P - 1; a >= 0; --a) suf[a] = suf[a + 1] * t[a + 1];
-#pragma unroll
-    for (int a = 0; a <= P; ++a) {
-        double den = 1.0;                 // prod_{b != a} (a - b), exact
-        for (int b = 0; b <= P; ++b)
-            if (b != a) den *= (double)(a - b);
-        w[a] = (CT)(1.0 / den) * (pre[a] * suf[a]);
-    }
-}
-
 // IDX 1: the source cells come from the mesh-density index (a.dens) instead of
 // the bucket index.
 template <typename TQ, int P, int S, int H, int RECON = 0, int NI = kItems, int IDX = 0>

@@ -7,7 +7,8 @@ with the FP64 oracle.
   transpose followed by its shift transpose, FP64 <= 1e-12 relative L1 (v0bar
   <= 1e-10 of its largest entry: a sum of many signed terms); FP32 state
   <= 1e-5 against the oracle run on the same FP32 inputs (v0bar <= 1e-3: it
-  sums differences of the FP32 reconstruction slope).  Covered: rows of
+  sums differences of the FP32 reconstruction slope), also on a uniform mesh
+  whose tiles all share one set of weights.  Covered: rows of
   one and of several tiles, ragged batches with per-row meshes, large shifts,
   a tile whose source window overflows the on-chip buffer, and steps without
   a residual.
@@ -32,11 +33,25 @@ def rel_l1(a, b):
     return float(np.sum(np.abs(a - b)) / np.sum(np.abs(b)))
 
 
+def _uniform(order, n_rows=5, n=3500, seed=13):
+    """Rows on one uniform mesh: every tile lies in the mesh's uniform run
+    (the FP32 paths then share one set of weights per tile)."""
+    rng = np.random.default_rng(seed)
+    e = W.uniform_edges(n, 0.0, 1.0)
+    xc = 0.5 * (e[:-1] + e[1:])
+    q = 1.0 + 0.3 * np.sin(2 * np.pi * xc)[None, :] + 0.05 * rng.standard_normal((n_rows, n))
+    dv = 0.2 / n * rng.uniform(-1, 1, (n_rows, n))
+    v0 = rng.uniform(-40.0, 40.0, n_rows) / n
+    return W.Workload("uniform", n_rows, n, np.arange(n_rows + 1) * n, e, True, q, dv, v0,
+                      1.0, order, 1)
+
+
 def _cases():
     return {
         "polar_one_tile": lambda o: W.small_polar(6, 800, order=o),
         "polar_tiles": lambda o: W.small_polar(3, 3500, order=o),
         "ragged": lambda o: W.small_ragged(12, 6, 2600, seed=31, order=o),
+        "uniform": lambda o: _uniform(o),
     }
 
 
@@ -144,7 +159,7 @@ def test_step_adjoint_window_overflow():
         assert abs(got[2][0] - ref[2][0]) <= 1e-10 * abs(ref[2][0]), s
 
 
-@pytest.mark.parametrize("kind", ["polar_tiles", "ragged"])
+@pytest.mark.parametrize("kind", ["polar_tiles", "ragged", "uniform"])
 def test_step_adjoint_fp32(kind):
     wl = _cases()[kind](5)
     qf, qh, rbar = _inputs(wl, 11)
