@@ -58,9 +58,11 @@ struct MeshTab {
     const double *ppmd = nullptr;
     const float *ppmf = nullptr;
     // prefix counts (n + 1) of the cells whose size differs from the mesh's
-    // largest by more than kUniformTol of it: a run with no such cell is
-    // uniformly spaced
+    // largest (nonu) or smallest (nonu_min) by more than kUniformTol of it: a
+    // range with no such cell is uniformly spaced (a refined-zone mesh has a
+    // coarse and a fine uniform run)
     const int32_t *nonu = nullptr;
+    const int32_t *nonu_min = nullptr;
 };
 
 // Relative spacing tolerance of a uniform run (a tile's shifted nodes then

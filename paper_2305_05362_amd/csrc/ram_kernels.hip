@@ -571,6 +571,7 @@ struct MeshTabW {
     double *ppmd;
     float *ppmf;
     int32_t *nonu;
+    int32_t *nonu_min;
 };
 
 template <int P>
@@ -646,48 +647,76 @@ __global__ __launch_bounds__(256) void k_mesh_prep(const double *x, int n, MeshT
 }
 
 // Uniform runs of a shared mesh: prefix counts of the cells whose size
-// differs from the largest by more than kUniformTol of it.  One workgroup of
-// 1024 threads: the largest size by a coalesced pass and a block reduction;
-// then, 32 Ki cells at a time, every lane's flags for up to 32 chunks of 1024
-// cells (loads pipelined, no barrier between them) and a prefix per chunk
-// from one ballot per wave and the waves' totals in LDS.
-__global__ __launch_bounds__(1024) void k_mesh_uniform(const double *x, int n, int32_t *nonu)
+// differs from the largest (nonu) and from the smallest (nonu_min) by more
+// than kUniformTol of it.  One workgroup of 1024 threads: both sizes by a
+// coalesced pass and block reductions; then, 32 Ki cells at a time, every
+// lane's two flags for up to 32 chunks of 1024 cells (loads pipelined, no
+// barrier between them) and a prefix per chunk from one ballot per wave and
+// flag and the waves' totals in LDS.
+__global__ __launch_bounds__(1024) void k_mesh_uniform(const double *x, int n, int32_t *nonu,
+                                                       int32_t *nonu_min)
 {
-    __shared__ double smax[16];
-    __shared__ int32_t swt[16];
+    __shared__ double smax[16], smin[16];
+    __shared__ int32_t swt[2][16];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    double m = 0.0;
-    for (int j = t; j < n; j += 1024) m = fmax(m, x[j + 1] - x[j]);
-    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
-    if (lane == 0) smax[wv] = m;
+    double mx = 0.0, mn = __builtin_huge_val();
+    for (int j = t; j < n; j += 1024) {
+        const double d = x[j + 1] - x[j];
+        mx = fmax(mx, d);
+        mn = fmin(mn, d);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        mx = fmax(mx, __shfl_xor(mx, o, 64));
+        mn = fmin(mn, __shfl_xor(mn, o, 64));
+    }
+    if (lane == 0) {
+        smax[wv] = mx;
+        smin[wv] = mn;
+    }
     __syncthreads();
-    double h = smax[0];
-    for (int w = 1; w < 16; ++w) h = fmax(h, smax[w]);
-    int32_t base = 0;
+    double hx = smax[0], hn = smin[0];
+    for (int w = 1; w < 16; ++w) {
+        hx = fmax(hx, smax[w]);
+        hn = fmin(hn, smin[w]);
+    }
+    int32_t base[2] = {0, 0};
     for (int s0 = 0; s0 < n; s0 += 32 * 1024) {
-        uint32_t bits = 0;
+        uint32_t bx = 0, bn = 0;
 #pragma unroll 8
         for (int k = 0; k < 32; ++k) {
             const int j = s0 + k * 1024 + t;
-            if (j < n && fabs((x[j + 1] - x[j]) - h) > kUniformTol * h) bits |= 1u << k;
+            if (j < n) {
+                const double d = x[j + 1] - x[j];
+                if (fabs(d - hx) > kUniformTol * hx) bx |= 1u << k;
+                if (fabs(d - hn) > kUniformTol * hn) bn |= 1u << k;
+            }
         }
         for (int k = 0; k < 32 && s0 + k * 1024 < n; ++k) {
             const int j = s0 + k * 1024 + t;
-            const uint64_t mask = __ballot((bits >> k) & 1u);
-            const int32_t below = __popcll(mask & ((1ull << lane) - 1ull));
-            if (lane == 0) swt[wv] = __popcll(mask);
-            __syncthreads();
-            int32_t before = base, tot = 0;
-            for (int w = 0; w < 16; ++w) {
-                if (w < wv) before += swt[w];
-                tot += swt[w];
+            const uint64_t mask[2] = {__ballot((bx >> k) & 1u), __ballot((bn >> k) & 1u)};
+            if (lane == 0) {
+                swt[0][wv] = __popcll(mask[0]);
+                swt[1][wv] = __popcll(mask[1]);
             }
-            if (j < n) nonu[j] = before + below;
-            base += tot;
+            __syncthreads();
+#pragma unroll
+            for (int f = 0; f < 2; ++f) {
+                int32_t before = base[f], tot = 0;
+                for (int w = 0; w < 16; ++w) {
+                    if (w < wv) before += swt[f][w];
+                    tot += swt[f][w];
+                }
+                const int32_t below = __popcll(mask[f] & ((1ull << lane) - 1ull));
+                if (j < n) (f == 0 ? nonu : nonu_min)[j] = before + below;
+                base[f] += tot;
+            }
             __syncthreads();
         }
     }
-    if (t == 0) nonu[n] = base;
+    if (t == 0) {
+        nonu[n] = base[0];
+        nonu_min[n] = base[1];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -758,7 +787,8 @@ size_t mesh_tab_bytes(int64_t n, int order)
     return 3 * al256(8 * n) + 3 * al256(4 * n) + al256(8 * n * 2 * (order + 1)) +
            al256(4 * n * 2 * (order + 1)) + al256(4 * nb) + al256(16 * nb) + al256(16) +
            al256(sizeof(CellRec<float>) * n) + al256(sizeof(CellRec<double>) * n) +
-           al256(8 * n) + al256(16 * n) + al256(40 * n) + al256(20 * n) + al256(4 * (n + 1));
+           al256(8 * n) + al256(16 * n) + al256(40 * n) + al256(20 * n) +
+           2 * al256(4 * (n + 1));
 }
 
 hipError_t launch_mesh_prep(const double *x, int64_t n, int order, void *mem,
@@ -784,7 +814,8 @@ hipError_t launch_mesh_prep(const double *x, int64_t n, int order, void *mem,
     w.rrd = (double2 *)p; p += al256(16 * n);
     w.ppmd = (double *)p; p += al256(40 * n);
     w.ppmf = (float *)p; p += al256(20 * n);
-    w.nonu = (int32_t *)p;
+    w.nonu = (int32_t *)p; p += al256(4 * (n + 1));
+    w.nonu_min = (int32_t *)p;
     tab.dx = w.dx; tab.dxinv = w.dxinv; tab.hinv = w.hinv; tab.stc = w.stc;
     tab.dxf = w.dxf; tab.dxinvf = w.dxinvf; tab.hinvf = w.hinvf; tab.stcf = w.stcf;
     tab.bucket = w.bucket;
@@ -798,6 +829,7 @@ hipError_t launch_mesh_prep(const double *x, int64_t n, int order, void *mem,
     tab.ppmd = w.ppmd;
     tab.ppmf = w.ppmf;
     tab.nonu = uniform ? w.nonu : nullptr;
+    tab.nonu_min = uniform ? w.nonu_min : nullptr;
     const unsigned grid = (unsigned)((w.nb + 255) / 256);
     switch (order) {
     case 1: hipLaunchKernelGGL(k_mesh_prep<1>, dim3(grid), dim3(256), 0, stream, x, (int)n, w); break;
@@ -806,7 +838,8 @@ hipError_t launch_mesh_prep(const double *x, int64_t n, int order, void *mem,
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !uniform) return e;
-    hipLaunchKernelGGL(k_mesh_uniform, dim3(1), dim3(1024), 0, stream, x, (int)n, w.nonu);
+    hipLaunchKernelGGL(k_mesh_uniform, dim3(1), dim3(1024), 0, stream, x, (int)n, w.nonu,
+                       w.nonu_min);
     return hipGetLastError();
 }
 

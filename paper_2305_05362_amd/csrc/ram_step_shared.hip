@@ -93,13 +93,16 @@ __global__ __launch_bounds__(256) void k_plan(StepArgs a, int64_t *wlo_out,
     const int64_t kk = wlo >= 0 ? wlo / n : -((-wlo + n - 1) / n);
     w_out[R.n_tiles + tile] = (int32_t)(wlo - kk * n);
     // a uniform tile: the cells on both sides of its nodes and its source
-    // window lie in the mesh's uniform run, and the window holds exactly one
+    // window lie in one of the mesh's uniform runs (all cells at the largest
+    // size, or all at the smallest), and the window holds exactly one
     // source cell per node (plus the stencil), so node i0 - H + k sits in
     // window cell LO + k at the first node's theta
     float thu = -1.0f;
-    if (R.tab.nonu && wide == nd + 2 * H + P &&
-        nonu_count(R.tab.nonu, n, i0 - H - 1, i0 + nd + H + 1) == 0 &&
-        nonu_count(R.tab.nonu, n, wlo, wlo + wide) == 0)
+    auto in_run = [&](const int32_t *pre) {
+        return nonu_count(pre, n, i0 - H - 1, i0 + nd + H + 1) == 0 &&
+               nonu_count(pre, n, wlo, wlo + wide) == 0;
+    };
+    if (R.tab.nonu && wide == nd + 2 * H + P && (in_run(R.tab.nonu) || in_run(R.tab.nonu_min)))
         thu = (float)((xt0 - x[c0]) * R.tab.dxinv[c0]);
     w_out[2 * R.n_tiles + tile] = __float_as_int(thu);
 }

@@ -9,8 +9,10 @@ L1:
 * the same mesh with one cell 0.1 % shorter (the rest stay the largest, so
   the run holds every other cell): the tiles that see it must not take the
   uniform path (the check would miss it by far more than 1e-6);
-* the polar disk's bump mesh, whose uniform run wraps over the periodic seam
-  and whose tiles straddle the run's ends;
+* a mesh of a coarse and a fine uniform half (the runs at the largest and at
+  the smallest size), and the same with one fine cell 0.1 % longer;
+* the polar disk's bump mesh, whose coarse run wraps over the periodic seam,
+  with its fine run inside the bump and tiles straddling the runs' ends;
 * the limited PLM / PPM step on the same three meshes (each node's cell
   cubic at the tile's shared theta), against the oracle's limited step.
 """
@@ -77,6 +79,26 @@ def test_one_shorter_cell(cell):
     e[cell + 1:] -= 1e-3 * h          # cell `cell` is 0.1 % shorter
     e = e * (1.0 / e[-1])
     assert _check(_rows(e, len(SHIFTS), 2, SHIFTS), 3, True) <= 1e-6
+
+
+def _two_levels(perturb=None):
+    # 1024 coarse cells on [0, 0.5), 4096 fine on [0.5, 1): both runs uniform
+    e = np.concatenate([np.linspace(0.0, 0.5, 1025), np.linspace(0.5, 1.0, 4097)[1:]])
+    if perturb is not None:
+        h = e[perturb + 1] - e[perturb]
+        e[perturb + 1:] += 1e-3 * h       # one fine cell 0.1 % longer
+        e = e * (1.0 / e[-1])
+    return e
+
+
+@pytest.mark.parametrize("perturb", [None, 3000])
+def test_coarse_and_fine_runs(perturb):
+    # the fine run (the mesh's smallest size) takes the uniform path too; a
+    # fine cell 0.1 % longer (neither the largest nor the smallest size) must
+    # keep its tiles off it
+    e = _two_levels(perturb)
+    shifts = [0.3 / 4096, 20.3 / 4096, -7.7 / 4096, 0.71]
+    assert _check(_rows(e, len(shifts), 6, shifts), 3, True) <= 1e-6
 
 
 def test_bump_mesh_runs_and_seam():
