@@ -873,7 +873,7 @@ ram_status ram_shift_limited_adjoint(ram_ctx *ctx, const ram_layout *layout,
     if ((st = enter(ctx)) != RAM_OK) return st;
     Carve cv;
     // a shared mesh brings its tables (centre gaps, PPM weights)
-    RowsPlan rp = plan_rows(cv, layout, ram::kTile, 1);
+    RowsPlan rp = plan_rows(cv, layout, ram::kAdjTile, 1);
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
     ram::ShiftAdjArgs a;
     if ((st = make_rows(ctx, layout, edges, rp, a.rows)) != RAM_OK) return st;
@@ -1182,7 +1182,7 @@ ram_status ram_shift_adjoint(ram_ctx *ctx, const ram_layout *layout,
         return step_adjoint_shared(ctx, layout, dtype, q_fwd, nullptr, nullptr, qbar_out,
                                    qbar_in, edges, v0, dt, order, nullptr, v0bar_accum);
     Carve cv;
-    RowsPlan rp = plan_rows(cv, layout, ram::kTile, 0);
+    RowsPlan rp = plan_rows(cv, layout, ram::kAdjTile, 0);
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
     ram::ShiftAdjArgs a;
     if ((st = make_rows(ctx, layout, edges, rp, a.rows)) != RAM_OK) return st;
@@ -1213,7 +1213,7 @@ ram_status ram_residual_adjoint(ram_ctx *ctx, const ram_layout *layout,
     if (qbar_in == qbar_out) return fail(RAM_E_INVALID_ARG, "qbar_in and qbar_out must not alias");
     if ((st = enter(ctx)) != RAM_OK) return st;
     Carve cv;
-    RowsPlan rp = plan_rows(cv, layout, ram::kTile, 0);
+    RowsPlan rp = plan_rows(cv, layout, ram::kAdjTile, 0);
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
     ram::ResidualAdjArgs a;
     if ((st = make_rows(ctx, layout, edges, rp, a.rows)) != RAM_OK) return st;
@@ -1307,7 +1307,7 @@ ram_status ram_step_adjoint(ram_ctx *ctx, const ram_layout *layout,
     const size_t state_bytes = elem_size(dtype) * (size_t)layout_cells(layout);
     Carve cv;
     const size_t mid_off = dv ? cv.take(state_bytes) : 0;
-    RowsPlan rp = plan_rows(cv, layout, ram::kTile, 0);
+    RowsPlan rp = plan_rows(cv, layout, ram::kAdjTile, 0);
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
     ram::Rows rows;
     if ((st = make_rows(ctx, layout, edges, rp, rows)) != RAM_OK) return st;

@@ -18,6 +18,11 @@ constexpr int kWindowCap = 2048;
 constexpr int kResTile = 1020;
 // int32 entries per tile of the window plan
 constexpr int kPlanW = 3;
+// Cells per tile of the one-node-per-thread adjoint kernels (the limited
+// shift's, the per-row shift's and the residual's): a tile's nodes (tile + 1)
+// and its window or halo (tile + up to 5) take one pass of kBlock threads,
+// so no thread runs a second node's chain while the others wait.
+constexpr int kAdjTile = kBlock - 5;
 // Centre value <-> cell average conversion: four cells per thread.
 constexpr int kAvgItems = 4;
 constexpr int kAvgTile = kBlock * kAvgItems;
