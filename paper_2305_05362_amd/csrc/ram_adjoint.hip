@@ -62,7 +62,7 @@ __device__ inline double mass_at(const double *x, const TQ *q, int n, int64_t m)
 
 // Shifted node e of a row (node N = node 0 of the next period): g = c + k N.
 __device__ inline int64_t locate(const double *x, int n, double s, int e,
-                                 double &xh)
+                                 double &xh, const Rows &R)
 {
     int64_t k;
     if (e == n) {
@@ -71,7 +71,11 @@ __device__ inline int64_t locate(const double *x, int n, double s, int e,
     } else {
         shifted_node(x, n, s, e, xh, k);
     }
-    return (int64_t)find_cell(x, n, xh) + k * (int64_t)n;
+    // a shared mesh's bucket index (one lookup and a short walk) or a binary
+    // search of the row; the same exact cell either way
+    const int c = R.has_tab ? find_cell_tab(x, n, R.tab, R.tab.scal[0], xh)
+                            : find_cell(x, n, xh);
+    return (int64_t)c + k * (int64_t)n;
 }
 
 // Zero the P window cells that start at each tile's first shifted node: the
@@ -88,7 +92,7 @@ __global__ __launch_bounds__(kBlock) void k_shift_adj_zero(ShiftAdjArgs a)
     if (n < P + 1) return;
     const double s = a.v0[ti.row] * a.dt;
     double xh;
-    const int64_t g0 = locate(ti.x, n, s, ti.i0, xh);
+    const int64_t g0 = locate(ti.x, n, s, ti.i0, xh, a.rows);
     TQ *qbi = (TQ *)a.qbar_in + ti.qoff;
     for (int b = 0; b < P; ++b) qbi[wrapi(g0 - LO + b, n)] = (TQ)0;
 }
@@ -120,7 +124,7 @@ __global__ __launch_bounds__(kBlock) void k_shift_adj(ShiftAdjArgs a)
     double vpart = 0.0;
     for (int t = threadIdx.x; t < ne; t += kBlock) {
         double xh;
-        const int64_t g = locate(x, n, s, i0 + t, xh);
+        const int64_t g = locate(x, n, s, i0 + t, xh, a.rows);
         const int c = wrapi(g, n);
         double X[P + 1], w[P + 1];
 #pragma unroll
@@ -364,7 +368,7 @@ __global__ __launch_bounds__(kBlock) void k_shift_lim_adj(ShiftAdjArgs a)
     double vpart = 0.0;
     for (int t = threadIdx.x; t < ne; t += kBlock) {
         double xh;
-        const int64_t g = locate(x, n, s, i0 + t, xh);
+        const int64_t g = locate(x, n, s, i0 + t, xh, a.rows);
         const int c = wrapi(g, n);
         double gw[P], qv;
         lim_grad<TQ, R>(x, qf, n, len, c, xh, hinv, pw, gw, qv);
