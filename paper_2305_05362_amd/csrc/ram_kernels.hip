@@ -649,17 +649,18 @@ __global__ __launch_bounds__(256) void k_mesh_prep(const double *x, int n, MeshT
 // Uniform runs of a shared mesh: prefix counts of the cells whose size
 // differs from the largest (nonu) and from the smallest (nonu_min) by more
 // than kUniformTol of it.  One workgroup of 1024 threads: both sizes by a
-// coalesced pass and block reductions; then, 32 Ki cells at a time, every
-// lane's two flags for up to 32 chunks of 1024 cells (loads pipelined, no
-// barrier between them) and a prefix per chunk from one ballot per wave and
-// flag and the waves' totals in LDS.
+// coalesced pass and block reductions; then each of the 16 waves takes one
+// contiguous segment of the row, counts its flagged cells, and after one
+// scan of the 16 counts writes its segment's prefix 64 cells at a time from
+// one ballot per flag (no barrier inside the segment loops).
 __global__ __launch_bounds__(1024) void k_mesh_uniform(const double *x, int n, int32_t *nonu,
                                                        int32_t *nonu_min)
 {
     __shared__ double smax[16], smin[16];
-    __shared__ int32_t swt[2][16];
+    __shared__ int32_t soff[2][17];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     double mx = 0.0, mn = __builtin_huge_val();
+#pragma unroll 8
     for (int j = t; j < n; j += 1024) {
         const double d = x[j + 1] - x[j];
         mx = fmax(mx, d);
@@ -679,43 +680,56 @@ __global__ __launch_bounds__(1024) void k_mesh_uniform(const double *x, int n, i
         hx = fmax(hx, smax[w]);
         hn = fmin(hn, smin[w]);
     }
-    int32_t base[2] = {0, 0};
-    for (int s0 = 0; s0 < n; s0 += 32 * 1024) {
-        uint32_t bx = 0, bn = 0;
-#pragma unroll 8
-        for (int k = 0; k < 32; ++k) {
-            const int j = s0 + k * 1024 + t;
-            if (j < n) {
-                const double d = x[j + 1] - x[j];
-                if (fabs(d - hx) > kUniformTol * hx) bx |= 1u << k;
-                if (fabs(d - hn) > kUniformTol * hn) bn |= 1u << k;
-            }
-        }
-        for (int k = 0; k < 32 && s0 + k * 1024 < n; ++k) {
-            const int j = s0 + k * 1024 + t;
-            const uint64_t mask[2] = {__ballot((bx >> k) & 1u), __ballot((bn >> k) & 1u)};
-            if (lane == 0) {
-                swt[0][wv] = __popcll(mask[0]);
-                swt[1][wv] = __popcll(mask[1]);
-            }
-            __syncthreads();
-#pragma unroll
-            for (int f = 0; f < 2; ++f) {
-                int32_t before = base[f], tot = 0;
-                for (int w = 0; w < 16; ++w) {
-                    if (w < wv) before += swt[f][w];
-                    tot += swt[f][w];
-                }
-                const int32_t below = __popcll(mask[f] & ((1ull << lane) - 1ull));
-                if (j < n) (f == 0 ? nonu : nonu_min)[j] = before + below;
-                base[f] += tot;
-            }
-            __syncthreads();
+    auto off_max = [&](double d) { return fabs(d - hx) > kUniformTol * hx; };
+    auto off_min = [&](double d) { return fabs(d - hn) > kUniformTol * hn; };
+    const int seg = (n + 15) / 16;
+    const int a0 = min(n, wv * seg), a1 = min(n, a0 + seg);
+    int32_t cx = 0, cn = 0;
+#pragma unroll 4
+    for (int j = a0 + lane; j < a1; j += 64) {
+        const double d = x[j + 1] - x[j];
+        cx += off_max(d) ? 1 : 0;
+        cn += off_min(d) ? 1 : 0;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        cx += __shfl_xor(cx, o, 64);
+        cn += __shfl_xor(cn, o, 64);
+    }
+    if (lane == 0) {
+        soff[0][wv + 1] = cx;
+        soff[1][wv + 1] = cn;
+    }
+    __syncthreads();
+    if (t == 0) {
+        soff[0][0] = soff[1][0] = 0;
+        for (int w = 1; w <= 16; ++w) {
+            soff[0][w] += soff[0][w - 1];
+            soff[1][w] += soff[1][w - 1];
         }
     }
+    __syncthreads();
+    int32_t bx = soff[0][wv], bn = soff[1][wv];
+    const uint64_t below = (1ull << lane) - 1ull;
+#pragma unroll 4
+    for (int j0 = a0; j0 < a1; j0 += 64) {
+        const int j = j0 + lane;
+        bool fx = false, fn = false;
+        if (j < a1) {
+            const double d = x[j + 1] - x[j];
+            fx = off_max(d);
+            fn = off_min(d);
+        }
+        const uint64_t mbx = __ballot(fx), mbn = __ballot(fn);
+        if (j < a1) {
+            nonu[j] = bx + __popcll(mbx & below);
+            nonu_min[j] = bn + __popcll(mbn & below);
+        }
+        bx += __popcll(mbx);
+        bn += __popcll(mbn);
+    }
     if (t == 0) {
-        nonu[n] = base[0];
-        nonu_min[n] = base[1];
+        nonu[n] = soff[0][16];
+        nonu_min[n] = soff[1][16];
     }
 }
 
