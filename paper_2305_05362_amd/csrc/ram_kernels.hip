@@ -844,11 +844,13 @@ hipError_t launch_mesh_prep(const double *x, int64_t n, int order, void *mem,
     tab.ppmf = w.ppmf;
     tab.nonu = uniform ? w.nonu : nullptr;
     tab.nonu_min = uniform ? w.nonu_min : nullptr;
-    const unsigned grid = (unsigned)((w.nb + 255) / 256);
+    // one wave per workgroup, so that the cells' tables (the first n threads,
+    // FP64 divisions) spread over every CU
+    const unsigned grid = (unsigned)((w.nb + 63) / 64);
     switch (order) {
-    case 1: hipLaunchKernelGGL(k_mesh_prep<1>, dim3(grid), dim3(256), 0, stream, x, (int)n, w); break;
-    case 3: hipLaunchKernelGGL(k_mesh_prep<3>, dim3(grid), dim3(256), 0, stream, x, (int)n, w); break;
-    default: hipLaunchKernelGGL(k_mesh_prep<5>, dim3(grid), dim3(256), 0, stream, x, (int)n, w); break;
+    case 1: hipLaunchKernelGGL(k_mesh_prep<1>, dim3(grid), dim3(64), 0, stream, x, (int)n, w); break;
+    case 3: hipLaunchKernelGGL(k_mesh_prep<3>, dim3(grid), dim3(64), 0, stream, x, (int)n, w); break;
+    default: hipLaunchKernelGGL(k_mesh_prep<5>, dim3(grid), dim3(64), 0, stream, x, (int)n, w); break;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !uniform) return e;

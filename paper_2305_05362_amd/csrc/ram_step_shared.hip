@@ -69,7 +69,7 @@ __global__ __launch_bounds__(256) void k_plan(StepArgs a, int64_t *wlo_out,
                                               int32_t *w_out)
 {
     constexpr int LO = (P - 1) / 2;
-    const int64_t tile = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t tile = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const Rows &R = a.rows;
     if (tile >= R.n_tiles) return;
     const int n = (int)R.n_cols;
@@ -134,10 +134,131 @@ __device__ inline int density_cell(const double *x, int n, const MeshDensity &d,
     return c;
 }
 
+// A uniform tile of the FP32 Lagrange step: the plan found the tile's nodes
+// and its source window in one uniform run of the mesh, so node k sits in
+// window cell LO + k at one theta and each shifted cell value is the same
+// (P+1)-point combination of the window's cell values (uniform_stencil); the
+// residual's cell sizes and centre gaps are the run's.  No node search, no
+// masses, no partial integrals, no per-cell geometry.  LDS: the shifted
+// state and the fluxes as in the general path, the window cell values in
+// the bytes of the staged cell records, so that no barrier separates them.
+template <typename TQ, int P, int H, int NI>
+__device__ __forceinline__ void step_uniform_tile(const StepArgs &a, unsigned char *su,
+                                                  float thu, int row, int i0, int nd, int W,
+                                                  int base, bool inner)
+{
+    static_assert(sizeof(TQ) == 4, "uniform tiles: FP32");
+    using CT = TQ;
+    using CT2 = typename TabT<CT>::T2;
+    constexpr int NODES = kBlock * NI;
+    static_assert(P <= kPad && 3 * sizeof(CT) * (NODES + kPad) <=
+                  ShLds<CT, double, CT, true, 0, NODES>::uni, "uniform tile LDS");
+    const int t = threadIdx.x;
+    const Rows &R = a.rows;
+    const MeshTab &tb = R.tab;
+    const int n = (int)R.n_cols;
+    const int NC = nd + 2 * H;
+    const int64_t qoff = (int64_t)row * n;
+    const TQ *q = (const TQ *)a.q_in + qoff;
+    TQ *qo = (TQ *)a.q_out + qoff;
+    TQ *qmid = a.q_mid ? (TQ *)a.q_mid + qoff : nullptr;
+    CT *sq = (CT *)su;
+    CT *sf = sq + (NODES + kPad);
+    CT *sw = sf + (NODES + kPad);
+    const bool wsmall = W + base <= 2 * n;
+    TQ wq[kWinRegs];
+#pragma unroll
+    for (int r = 0; r < kWinRegs; ++r) {
+        const int j = t + r * kBlock;
+        if (j < W) {
+            int mm = base + j;
+            if (wsmall) mm = mm >= n ? mm - n : mm;
+            else mm = wrap_small(mm, n);
+            wq[r] = q[mm];
+        }
+    }
+    TQ dvr[NI];
+    if (H) {
+        const TQ *dv = (const TQ *)a.dv + qoff;
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+            const int u = t + k * kBlock;
+            if (u < nd + 1) {
+                const int f = i0 + u;
+                dvr[k] = dv[inner ? f : wrap1(f, n)];
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < kWinRegs; ++r) {
+        const int j = t + r * kBlock;
+        if (j < W) sw[j] = (CT)wq[r];
+    }
+    CT cc[P + 1];
+    uniform_stencil<CT, P>((CT)thu, cc);
+    __syncthreads();
+    // destination cell ci (cell i0 - H + ci) from window cells ci .. ci + P,
+    // one cell at a time (sq does not overlap the window): six reads in
+    // flight rather than the tile's twenty-four keep the registers of the
+    // general path's occupancy
+#pragma unroll 1
+    for (int ci = t; ci < NC; ci += kBlock) {
+        CT v = (CT)0;
+#pragma unroll
+        for (int d = 0; d <= P; ++d) v += cc[d] * sw[ci + d];
+        const int c0 = i0 - H + ci;
+        const int cell = inner ? c0 : wrap1(c0, n);
+        if (H == 0) qo[cell] = (TQ)v;
+        else {
+            sq[ci] = v;
+            if (qmid && ci >= H && ci < H + nd) qmid[cell] = (TQ)v;
+        }
+    }
+    if (H == 0) return;
+    __syncthreads();
+    const CT2 rr0 = TabT<CT>::rr(tb)[i0];          // the run's (dx, 1 / centre gap)
+    const CT dxi0 = TabT<CT>::dxinv(tb)[i0];
+    // fluxes on faces i0 .. i0+nd (sq index j is cell i0-2+j), as in the
+    // general path with the run's geometry
+    const CT dt = (CT)a.dt;
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        const int u = t + k * kBlock;
+        if (u < nd + 1) {
+            const CT v = (CT)dvr[k];
+            const bool up = v >= (CT)0;
+            const int c = up ? u + 1 : u + 2;
+            const CT qm = sq[c - 1], q0 = sq[c], qp = sq[c + 1];
+            const CT dp = (qp - q0) * rr0.y;
+            const CT dm = (q0 - qm) * rr0.y;
+            const CT sig = (dp * dm <= (CT)0) ? (CT)0 : harmonic2(dp, dm);
+            const CT half = up ? (CT)0.5 * (rr0.x - v * dt) : (CT)-0.5 * (rr0.x + v * dt);
+            sf[u] = v * (q0 + sig * half);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        const int u = t + k * kBlock;
+        if (u < nd) qo[i0 + u] = (TQ)(sq[u + 2] - dt * (sf[u + 1] - sf[u]) * dxi0);
+    }
+}
+
+// The FP32 Lagrange direct-sum schedule asks for seven waves a SIMD, the
+// count its LDS allows: the compiler then fits it in 72 VGPRs (a spill or
+// so) where it would otherwise take 74 and six waves.
+template <typename TQ, int P, int S, int H, int RECON, int NI, int IDX>
+constexpr int step_min_waves()
+{
+    return (S == kSumDirect && RECON == 0 && sizeof(TQ) == 4 && NI == kItems && IDX == 0) ? 7
+                                                                                           : 1;
+}
+
 // IDX 1: the source cells come from the mesh-density index (a.dens) instead of
 // the bucket index.
 template <typename TQ, int P, int S, int H, int RECON = 0, int NI = kItems, int IDX = 0>
-__global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
+__global__ __launch_bounds__(kBlock, (step_min_waves<TQ, P, S, H, RECON, NI, IDX>()))
+void k_step_sh(StepArgs a)
 {
     constexpr bool kDirect = S == kSumDirect;
     constexpr bool kLim = RECON != 0;
@@ -200,14 +321,21 @@ __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
     // A uniform tile (FP32, direct sums): the plan found its nodes and source
     // window in the mesh's uniform run, so node k of the tile sits in window
     // cell LO + k at one theta -- no search, no cell record; the Lagrange
-    // shift shares one set of weights, the limited shift evaluates each
-    // cell's cubic at that theta (per-node values would agree to FP32
-    // rounding).
+    // shift becomes one stencil on the cell values (step_uniform_tile), the
+    // limited shift evaluates each cell's cubic at that theta (per-node
+    // values would agree to FP32 rounding).
     bool uni = false;
     float thu = -1.0f;
     if constexpr (kDirect && sizeof(TQ) == 4) {
         thu = __int_as_float(a.plan_w[2 * R.n_tiles + blockIdx.x]);
         uni = thu >= 0.0f;
+        if constexpr (!kLim) {
+            if (uni) {
+                step_uniform_tile<TQ, P, H, NI>(a, su, thu, row, i0, nd, W,
+                                                a.plan_w[R.n_tiles + blockIdx.x], inner);
+                return;
+            }
+        }
     }
     // ---- loads that do not depend on the search, issued first ------------
     double xe[NI];
@@ -328,32 +456,6 @@ __global__ __launch_bounds__(kBlock) void k_step_sh(StepArgs a)
                         const CT pa = sx2[j], pc = sx1[j];
                         const CT pb = (CT)sm[j] - pa - pc;
                         ell = tt * (pa + tt * (pb + tt * pc));
-                    }
-                    sell[ei] = ell;
-                    sjc[ei] = (short)j;
-                }
-            }
-        } else if (uni) {
-            CT wu[P + 1];
-            uniform_weights<CT, P>((CT)thu, wu);
-#pragma unroll
-            for (int k = 0; k < NI; ++k) {
-                const int ei = t + k * kBlock;
-                jc[k] = 0;
-                if (ei < NE) {
-                    const int j = LO + ei;
-                    jc[k] = j;
-                    ok = ok && j + P - LO <= W;
-                    CT ell = (CT)0, up = (CT)0, dn = (CT)0;
-#pragma unroll
-                    for (int b = LO + 1; b <= P; ++b) {
-                        up += (CT)sm[j + b - LO - 1];
-                        ell += wu[b] * up;
-                    }
-#pragma unroll
-                    for (int b = LO - 1; b >= 0; --b) {
-                        dn += (CT)sm[j - LO + b];
-                        ell -= wu[b] * dn;
                     }
                     sell[ei] = ell;
                     sjc[ei] = (short)j;
@@ -704,11 +806,13 @@ hipError_t launch_step_shared_limited(const StepArgs &a, bool f64, int recon,
 hipError_t launch_plan(const StepArgs &a, int order, int64_t *wlo, int32_t *w,
                        hipStream_t stream)
 {
-    const unsigned grid = (unsigned)((a.rows.n_tiles + 255) / 256);
+    // one wave per workgroup: a few hundred waves of dependent searches, spread
+    // over every CU rather than packed four to a workgroup
+    const unsigned grid = (unsigned)((a.rows.n_tiles + 63) / 64);
     switch (order) {
-    case 1: hipLaunchKernelGGL(k_plan<1>, dim3(grid), dim3(256), 0, stream, a, wlo, w); break;
-    case 3: hipLaunchKernelGGL(k_plan<3>, dim3(grid), dim3(256), 0, stream, a, wlo, w); break;
-    default: hipLaunchKernelGGL(k_plan<5>, dim3(grid), dim3(256), 0, stream, a, wlo, w); break;
+    case 1: hipLaunchKernelGGL(k_plan<1>, dim3(grid), dim3(64), 0, stream, a, wlo, w); break;
+    case 3: hipLaunchKernelGGL(k_plan<3>, dim3(grid), dim3(64), 0, stream, a, wlo, w); break;
+    default: hipLaunchKernelGGL(k_plan<5>, dim3(grid), dim3(64), 0, stream, a, wlo, w); break;
     }
     return hipGetLastError();
 }

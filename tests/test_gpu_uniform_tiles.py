@@ -14,7 +14,12 @@ L1:
 * the polar disk's bump mesh, whose coarse run wraps over the periodic seam,
   with its fine run inside the bump and tiles straddling the runs' ends;
 * the limited PLM / PPM step on the same three meshes (each node's cell
-  cubic at the tile's shared theta), against the oracle's limited step.
+  cubic at the tile's shared theta), against the oracle's limited step;
+* uniform rows of 6 .. 13 cells, whose windows wrap the row.
+
+In a uniform tile the FP32 Lagrange step is one (P+1)-point stencil on the
+cell values, so these cases also check its weights (from the Lagrange
+weights at theta) and the residual on the run's constant geometry.
 """
 import numpy as np
 import pytest
@@ -131,3 +136,13 @@ def test_limited_uniform_tiles(recon, mesh):
             e = e * (1.0 / e[-1])
         wl = _rows(e, len(SHIFTS), 5, SHIFTS)
     assert _check_limited(wl, 3, recon) <= 1e-6
+
+
+@pytest.mark.parametrize("n", [6, 7, 9, 13])
+def test_tiny_uniform_rows(n):
+    # rows of order+1 cells and a few more: the source window (the row's cells
+    # plus the residual's halo and the stencil) wraps the row, every tile is
+    # uniform
+    e = W.uniform_edges(n, 0.0, 1.0)
+    shifts = [0.3 / n, 2.7 / n, -1.4 / n, 5.05]
+    assert _check(_rows(e, len(shifts), 7, shifts), 3, True) <= 1e-6
