@@ -294,16 +294,72 @@ __global__ __launch_bounds__(kBlock) void k_adj_sh(StepAdjArgs a)
     }
     __syncthreads();
 
-    // ---- (2) shifted nodes, tile-local Vbar ---------------------------------
-    // A uniform tile (FP32; the window plan found its nodes and window in the
-    // mesh's uniform run): node e sits in window cell LO + e at the plan's
-    // theta, so every node shares one set of weights and no search is made.
-    bool uni = false;
-    float thu = -1.0f;
+    // ---- (2) a uniform tile ---------------------------------------------------
+    // FP32; the window plan found the tile's nodes and window in one uniform
+    // run of the mesh: node e sits in window cell LO + e at the plan's theta,
+    // and the shift is the forward kernel's stencil Q'_i = sum_d cc_d Q_{i+d}
+    // (window index i + d for destination cell i).  Its transpose gathers
+    // sum_d cc_d Mbar'_{j-d} for window cell j (times dx: the source value's
+    // gradient), with no search, scatter or scan; v0bar's telescoped sum
+    // -sum_i Mbar'_i (q~_{i+1} - q~_i) takes q~_{i+1} - q~_i =
+    // sum_d (d cc_d / d theta) Q^n_{i+d}.  The window's first and last p
+    // cells are shared with the neighbouring tiles and accumulated with
+    // atomics after the zeroing pass, as in the general path.
     if constexpr (sizeof(TQ) == 4) {
-        thu = __int_as_float(a.plan_w[2 * R.n_tiles + blockIdx.x]);
-        uni = thu >= 0.0f && W > 0 && W <= kWinA;
+        const float thu = __int_as_float(a.plan_w[2 * R.n_tiles + blockIdx.x]);
+        if (thu >= 0.0f && W > 0 && W <= kWinA) {
+            const int base = a.plan_w[R.n_tiles + blockIdx.x];   // wlo mod n
+            double *sw = (double *)su;                           // Q^n of the window
+            if (want_v0) {
+                for (int j = t; j < W; j += kBlock) {
+                    int mm = base + j;
+                    mm = mm >= n ? wrap_small(mm, n) : mm;
+                    sw[j] = (double)qf[mm];
+                }
+            }
+            double cs[P + 1];
+            uniform_stencil<double, P>((double)thu, cs);
+            for (int j = t; j < W; j += kBlock) {
+                double acc = 0.0;
+#pragma unroll
+                for (int d = 0; d <= P; ++d) {
+                    const int i = j - d;
+                    if (i >= 0 && i < nd) acc += cs[d] * (double)smb[i];
+                }
+                int mm = base + j;
+                mm = mm >= n ? wrap_small(mm, n) : mm;
+                const double val = acc * TabT<double>::dx(tb)[mm];
+                if (j >= P && j < W - P) qbi[mm] = (TQ)val;
+                else atomicAdd(&qbi[mm], (TQ)val);
+            }
+            if (want_v0) {
+                double dw[P + 1], gd[P + 2], dd[P + 1];
+                uniform_dweights<double, P>((double)thu, 1.0, dw);
+                outward_sums<double, P>(dw, gd);
+#pragma unroll
+                for (int d = 0; d <= P; ++d) dd[d] = gd[d] - gd[d + 1];
+                __syncthreads();
+                double vpart = 0.0;
+                for (int u = t; u < nd; u += kBlock) {
+                    double dq = 0.0;
+#pragma unroll
+                    for (int d = 0; d <= P; ++d) dq += dd[d] * sw[u + d];
+                    vpart -= (double)smb[u] * dq;
+                }
+                for (int d = 32; d >= 1; d >>= 1) vpart += __shfl_xor(vpart, d);
+                if ((t & 63) == 0) sred[t >> 6] = vpart;
+                __syncthreads();
+                if (t == 0) {
+                    double tot = 0.0;
+                    for (int wv = 0; wv < kBlock / 64; ++wv) tot += sred[wv];
+                    atomicAdd(&a.v0bar[row], a.dt * tot);
+                }
+            }
+            return;
+        }
     }
+
+    // ---- (2) shifted nodes, tile-local Vbar ---------------------------------
     int64_t g[NI];
     CT w[NI][P + 1];
     double vb[NI], xh[NI];
@@ -314,12 +370,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_sh(StepAdjArgs a)
         const int e = t + k * kBlock;
         g[k] = 0;
         vb[k] = 0.0;
-        if (e < NE && uni) {
-            g[k] = wlo + LO + e;
-            uniform_weights<CT, P>((CT)thu, w[k]);
-            cc[k] = 0;
-            xh[k] = 0.0;
-        } else if (e < NE) {
+        if (e < NE) {
             const int en = i0 + e;
             const int kx = en >= n ? 1 : 0;
             const double xe = x[en >= n ? en - n : en];
@@ -405,21 +456,13 @@ __global__ __launch_bounds__(kBlock) void k_adj_sh(StepAdjArgs a)
         // reconstruction q~ at the nodes: sum_b w'_b (C(g-lo+b) - C(g)) / dx_c,
         // the differences summed from the masses next to the node
         if (want_v0) {
-            // a uniform tile's derivative weights, once (one cell size in the run)
-            double dwu[P + 1];
-            if (uni) uniform_dweights<CT, P>((CT)thu, tb.dxinv[base], dwu);
 #pragma unroll
             for (int k = 0; k < NI; ++k) {
                 const int e = t + k * kBlock;
                 if (e < NE) {
                     const int jc = (int)(g[k] - wlo);
                     double dwd[P + 1];
-                    if (uni) {
-#pragma unroll
-                        for (int b = 0; b <= P; ++b) dwd[b] = dwu[b];
-                    } else {
-                        node_dweights<CT, P>(tb, cc[k], xh[k], dwd);
-                    }
+                    node_dweights<CT, P>(tb, cc[k], xh[k], dwd);
                     double dq = 0.0, up = 0.0, dn = 0.0;
 #pragma unroll
                     for (int b = LO + 1; b <= P; ++b) {

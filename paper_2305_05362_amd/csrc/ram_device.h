@@ -517,10 +517,32 @@ __device__ inline void uniform_weights(CT th, CT *w)
     }
 }
 
+// The weights of the masses M_{j+e} in the partial integral of a node in
+// cell j whose stencil weights are w: the weights above the node summed down
+// to e for e >= 0, minus the weights below summed up to e for e < 0, stored
+// at g[e + LO + 1] for e = -LO .. P-LO-1, with g[0] = g[P+1] = 0.
+template <typename T, int P>
+__device__ inline void outward_sums(const T *w, T *g)
+{
+    constexpr int LO = (P - 1) / 2;
+    g[0] = g[P + 1] = (T)0;
+    T acc = (T)0;
+#pragma unroll
+    for (int e = P - LO - 1; e >= 0; --e) {
+        acc += w[LO + 1 + e];
+        g[e + LO + 1] = acc;
+    }
+    acc = (T)0;
+#pragma unroll
+    for (int e = -LO; e < 0; ++e) {
+        acc += w[LO + e];
+        g[e + LO + 1] = -acc;
+    }
+}
+
 // The shift of a uniform run as one stencil on cell values.  With every cell
-// of size h, the partial integral of the node in cell j is a fixed
-// combination sum_e g_e M_{j+e} of the masses around it (the stencil
-// weights summed outward from cell j), so the destination mass
+// of size h, the partial integral of the node in cell j is the fixed
+// combination sum_e g_e M_{j+e} (outward_sums), so the destination mass
 // M_j + ell(j+1) - ell(j) weighs M_{j+d} by [d == 0] + g_{d-1} - g_d,
 // d = -LO .. P-LO, and dividing by h gives the shifted cell value as the same
 // combination of the values Q_{j+d}: cc[d + LO].  The weights sum to one
@@ -529,22 +551,9 @@ template <typename CT, int P>
 __device__ inline void uniform_stencil(CT th, CT *cc)
 {
     constexpr int LO = (P - 1) / 2;
-    CT w[P + 1];
+    CT w[P + 1], g[P + 2];
     uniform_weights<CT, P>(th, w);
-    CT g[P + 2];                       // g[e + LO + 1], zero past both ends
-    g[0] = g[P + 1] = (CT)0;
-    CT acc = (CT)0;
-#pragma unroll
-    for (int e = P - LO - 1; e >= 0; --e) {
-        acc += w[LO + 1 + e];
-        g[e + LO + 1] = acc;
-    }
-    acc = (CT)0;
-#pragma unroll
-    for (int e = -LO; e < 0; ++e) {
-        acc += w[LO + e];
-        g[e + LO + 1] = -acc;
-    }
+    outward_sums<CT, P>(w, g);
 #pragma unroll
     for (int d = 0; d <= P; ++d) cc[d] = (d == LO ? (CT)1 : (CT)0) + g[d] - g[d + 1];
 }

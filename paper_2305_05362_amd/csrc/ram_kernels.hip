@@ -710,7 +710,6 @@ __global__ __launch_bounds__(1024) void k_mesh_uniform(const double *x, int n, i
     __syncthreads();
     int32_t bx = soff[0][wv], bn = soff[1][wv];
     const uint64_t below = (1ull << lane) - 1ull;
-#pragma unroll 4
     for (int j0 = a0; j0 < a1; j0 += 64) {
         const int j = j0 + lane;
         bool fx = false, fn = false;

@@ -8,7 +8,9 @@ with the FP64 oracle.
   <= 1e-10 of its largest entry: a sum of many signed terms); FP32 state
   <= 1e-5 against the oracle run on the same FP32 inputs (v0bar <= 1e-3: it
   sums differences of the FP32 reconstruction slope), also on a uniform mesh
-  whose tiles all share one set of weights.  Covered: rows of
+  whose tiles all take the transposed stencil (orders 1, 3 and 5, with and
+  without the residual, shifts of many cells and of whole periods).
+  Covered: rows of
   one and of several tiles, ragged batches with per-row meshes, large shifts,
   a tile whose source window overflows the on-chip buffer, and steps without
   a residual.
@@ -175,4 +177,30 @@ def test_step_adjoint_fp32(kind):
     # neighbouring nodes: about 1e-4 relative rounding
     v0err = np.max(np.abs(got[2] - ref[2])) / np.max(np.abs(ref[2]))
     print(f"{kind} FP32 v0bar max rel {v0err:.2e}")
+    assert v0err <= 1e-3
+
+
+@pytest.mark.parametrize("residual", [True, False])
+@pytest.mark.parametrize("order", [1, 3, 5])
+def test_step_adjoint_fp32_uniform_stencil(order, residual):
+    # every tile of a uniform mesh gathers through the transposed stencil;
+    # rows shifted by under a cell, by tens of cells and by whole periods
+    # either way
+    wl = _uniform(order, n_rows=6, n=2600, seed=17 + order)
+    n = wl.n_cols
+    wl.v0[:] = np.array([0.37, -0.81, 23.6, -41.2, n + 5.3, -2 * n - 0.45]) / n
+    qf, qh, rbar = _inputs(wl, 29)
+    f32 = lambda a: a.astype(np.float32).astype(np.float64)
+    qf, rbar = f32(qf), f32(rbar)
+    qh = f32(qh) if residual else None
+    dv = f32(wl.dv.reshape(-1)) if residual else None
+    got = _gpu_step_adjoint(wl, qf, qh, dv, rbar, wl.v0, order, torch.float32)
+    ref = _oracle_step_adjoint(wl, qf, qh, dv, rbar, wl.v0, order)
+    err = rel_l1(got[0], ref[0])
+    print(f"order {order} residual {residual} FP32 qbar rel-L1 {err:.2e}")
+    assert err <= 1e-5
+    if residual:
+        assert rel_l1(got[1], ref[1]) <= 1e-5
+    v0err = np.max(np.abs(got[2] - ref[2])) / np.max(np.abs(ref[2]))
+    print(f"order {order} residual {residual} FP32 v0bar max rel {v0err:.2e}")
     assert v0err <= 1e-3

@@ -56,14 +56,14 @@ def _rows(edges, n_rows, seed, shifts):
     return wl
 
 
-def _check(wl, steps, with_dv):
+def _check(wl, steps, with_dv, order=5):
     rows = R.Rows.from_workload(wl, DEV)
     q = dev(wl.q0, torch.float32)
     dv = dev(wl.dv, torch.float32) if with_dv else None
-    R.ram_step(rows, q, dev(wl.v0), dv, wl.dt, 5, steps, R.RAM_SUM_DIRECT)
+    R.ram_step(rows, q, dev(wl.v0), dv, wl.dt, order, steps, R.RAM_SUM_DIRECT)
     torch.cuda.synchronize()
     want = oracle.step(oracle.Rows.from_workload(wl), wl.q0, wl.v0,
-                       wl.dv if with_dv else None, wl.dt, 5, steps)
+                       wl.dv if with_dv else None, wl.dt, order, steps)
     return rel_l1(q.cpu().numpy().astype(np.float64), want)
 
 
@@ -75,6 +75,13 @@ SHIFTS = [0.3 / 4096, 0.37 / 4096, 5.21 / 4096, -3.7 / 4096, 2.5 + 7.3 / 4096, -
 def test_uniform_mesh(steps, with_dv):
     e = W.uniform_edges(4096, 0.0, 1.0)
     assert _check(_rows(e, len(SHIFTS), 1, SHIFTS), steps, with_dv) <= 1e-6
+
+
+@pytest.mark.parametrize("order", [1, 3])
+def test_uniform_mesh_lower_orders(order):
+    # the stencil has order + 1 points
+    e = W.uniform_edges(4096, 0.0, 1.0)
+    assert _check(_rows(e, len(SHIFTS), 8, SHIFTS), 3, True, order) <= 1e-6
 
 
 @pytest.mark.parametrize("cell", [0, 1500, 4095])
