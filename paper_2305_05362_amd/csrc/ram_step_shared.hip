@@ -658,8 +658,13 @@ void k_step_sh(StepArgs a)
                 const int ja = sjc[ci], jb = sjc[ci + 1];
                 CT whole;
                 if constexpr (kDirect) {
-                    whole = (CT)0;
-                    for (int m = ja; m < jb; ++m) whole += (CT)sm[m];
+                    // the first two whole cells as independent reads (a node
+                    // step of at most two cells is the common case; ja + 1 <=
+                    // W stays inside the LDS buffer), the rest in order
+                    const CT m0 = (CT)sm[ja], m1 = (CT)sm[ja + 1];
+                    whole = jb > ja ? m0 : (CT)0;
+                    whole += jb > ja + 1 ? m1 : (CT)0;
+                    for (int m = ja + 2; m < jb; ++m) whole += (CT)sm[m];
                 } else {
                     whole = (jb - ja == 1) ? (CT)sm[ja] : (CT)AC::diff(sp[jb], sp[ja]);
                 }
@@ -668,7 +673,10 @@ void k_step_sh(StepArgs a)
                 mp = (CT)(direct_whole<TQ>(x, q, n, sg[ci], sg[ci + 1]) +
                           ((double)sell[ci + 1] - (double)sell[ci]));
             }
-            qs[k] = mp * TabT<CT>::dxinv(tb)[cell];
+            // 1/dx: from the cell's staged record (the residual's, loaded
+            // before the barrier) where there is one, else from the table
+            if constexpr (H != 0 && kStage) qs[k] = mp * __builtin_amdgcn_rcpf(rrv[k].x);
+            else qs[k] = mp * TabT<CT>::dxinv(tb)[cell];
             if (H == 0) qo[cell] = (TQ)qs[k];
             else if (qmid && ci >= H && ci < H + nd) qmid[cell] = (TQ)qs[k];
         }
