@@ -15,7 +15,9 @@ L1:
   with its fine run inside the bump and tiles straddling the runs' ends;
 * the limited PLM / PPM step on the same three meshes (each node's cell
   cubic at the tile's shared theta), against the oracle's limited step;
-* uniform rows of 6 .. 13 cells, whose windows wrap the row.
+* uniform rows of 6 .. 13 cells, whose windows wrap the row;
+* a cell 10 % shorter or longer on either side of a boundary of the wave
+  segments the uniform-run tables are built in.
 
 In a uniform tile the FP32 Lagrange step is one (P+1)-point stencil on the
 cell values, so these cases also check its weights (from the Lagrange
@@ -153,3 +155,19 @@ def test_tiny_uniform_rows(n):
     e = W.uniform_edges(n, 0.0, 1.0)
     shifts = [0.3 / n, 2.7 / n, -1.4 / n, 5.05]
     assert _check(_rows(e, len(shifts), 7, shifts), 3, True) <= 1e-6
+
+
+@pytest.mark.parametrize("n,cell", [(4096, 255), (4096, 256), (4096, 3840), (4099, 256),
+                                    (4099, 257), (4099, 4098)])
+@pytest.mark.parametrize("sign", [-1.0, 1.0])
+def test_run_tables_at_segment_boundaries(n, cell, sign):
+    # the uniform-run tables are prefix counts built one wave segment
+    # (ceil(n / 16) cells) at a time: one cell 10 % shorter (off the largest
+    # size) or 10 % longer (then the largest, the rest off it but at the
+    # smallest) on either side of a segment boundary must keep every tile that
+    # sees it off the uniform path; misread, the error would be ~1e-4
+    e = W.uniform_edges(n, 0.0, 1.0).copy()
+    e[cell + 1:] += sign * 0.1 * (e[1] - e[0])
+    e = e * (1.0 / e[-1])
+    shifts = [0.3 / n, 5.21 / n, -3.7 / n, 0.5 + 1.7 / n]
+    assert _check(_rows(e, len(shifts), 9, shifts), 2, True) <= 1e-6
