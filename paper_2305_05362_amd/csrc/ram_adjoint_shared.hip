@@ -289,8 +289,12 @@ __global__ __launch_bounds__(kBlock) void k_adj_sh(StepAdjArgs a)
             }
         }
     } else {
-        for (int u = t; u < nd; u += kBlock)
-            smb[u] = (CT)qbo[i0 + u] * TabT<CT>::dxinv(tb)[i0 + u];
+        // fixed slots, so that every thread's loads are in flight together
+#pragma unroll
+        for (int k = 0; k < NI; ++k) {
+            const int u = t + k * kBlock;
+            if (u < nd) smb[u] = (CT)qbo[i0 + u] * TabT<CT>::dxinv(tb)[i0 + u];
+        }
     }
     __syncthreads();
 
@@ -308,31 +312,44 @@ __global__ __launch_bounds__(kBlock) void k_adj_sh(StepAdjArgs a)
     if constexpr (sizeof(TQ) == 4) {
         const float thu = __int_as_float(a.plan_w[2 * R.n_tiles + blockIdx.x]);
         if (thu >= 0.0f && W > 0 && W <= kWinA) {
+            // window cells in fixed slots (W = nd + P <= NI * kBlock + P), so
+            // that each thread's loads are issued together; one cell size
             const int base = a.plan_w[R.n_tiles + blockIdx.x];   // wlo mod n
+            constexpr int NS = NI + (P + kBlock - 1) / kBlock;
             double *sw = (double *)su;                           // Q^n of the window
-            if (want_v0) {
-                for (int j = t; j < W; j += kBlock) {
-                    int mm = base + j;
-                    mm = mm >= n ? wrap_small(mm, n) : mm;
-                    sw[j] = (double)qf[mm];
-                }
+            const double dx0 = TabT<double>::dx(tb)[base];
+            int mms[NS];
+            double qw[NS];
+#pragma unroll
+            for (int r = 0; r < NS; ++r) {
+                const int j = t + r * kBlock;
+                const int mm = base + j;
+                mms[r] = j < W ? (mm >= n ? wrap_small(mm, n) : mm) : 0;
+                if (want_v0 && j < W) qw[r] = (double)qf[mms[r]];
             }
             double cs[P + 1];
             uniform_stencil<double, P>((double)thu, cs);
-            for (int j = t; j < W; j += kBlock) {
-                double acc = 0.0;
 #pragma unroll
-                for (int d = 0; d <= P; ++d) {
-                    const int i = j - d;
-                    if (i >= 0 && i < nd) acc += cs[d] * (double)smb[i];
+            for (int r = 0; r < NS; ++r) {
+                const int j = t + r * kBlock;
+                if (j < W) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int d = 0; d <= P; ++d) {
+                        const int i = j - d;
+                        if (i >= 0 && i < nd) acc += cs[d] * (double)smb[i];
+                    }
+                    const double val = acc * dx0;
+                    if (j >= P && j < W - P) qbi[mms[r]] = (TQ)val;
+                    else atomicAdd(&qbi[mms[r]], (TQ)val);
                 }
-                int mm = base + j;
-                mm = mm >= n ? wrap_small(mm, n) : mm;
-                const double val = acc * TabT<double>::dx(tb)[mm];
-                if (j >= P && j < W - P) qbi[mm] = (TQ)val;
-                else atomicAdd(&qbi[mm], (TQ)val);
             }
             if (want_v0) {
+#pragma unroll
+                for (int r = 0; r < NS; ++r) {
+                    const int j = t + r * kBlock;
+                    if (j < W) sw[j] = qw[r];
+                }
                 double dw[P + 1], gd[P + 2], dd[P + 1];
                 uniform_dweights<double, P>((double)thu, 1.0, dw);
                 outward_sums<double, P>(dw, gd);
@@ -340,11 +357,15 @@ __global__ __launch_bounds__(kBlock) void k_adj_sh(StepAdjArgs a)
                 for (int d = 0; d <= P; ++d) dd[d] = gd[d] - gd[d + 1];
                 __syncthreads();
                 double vpart = 0.0;
-                for (int u = t; u < nd; u += kBlock) {
-                    double dq = 0.0;
 #pragma unroll
-                    for (int d = 0; d <= P; ++d) dq += dd[d] * sw[u + d];
-                    vpart -= (double)smb[u] * dq;
+                for (int k = 0; k < NI; ++k) {
+                    const int u = t + k * kBlock;
+                    if (u < nd) {
+                        double dq = 0.0;
+#pragma unroll
+                        for (int d = 0; d <= P; ++d) dq += dd[d] * sw[u + d];
+                        vpart -= (double)smb[u] * dq;
+                    }
                 }
                 for (int d = 32; d >= 1; d >>= 1) vpart += __shfl_xor(vpart, d);
                 if ((t & 63) == 0) sred[t >> 6] = vpart;
