@@ -17,7 +17,8 @@ L1:
   cubic at the tile's shared theta), against the oracle's limited step;
 * uniform rows of 6 .. 13 cells, whose windows wrap the row;
 * a cell 10 % shorter or longer on either side of a boundary of the wave
-  segments the uniform-run tables are built in.
+  segments the uniform-run tables are built in;
+* one row of 2^20 + 3 cells (segments of ~65k cells, ~1000 tiles a row).
 
 In a uniform tile the FP32 Lagrange step is one (P+1)-point stencil on the
 cell values, so these cases also check its weights (from the Lagrange
@@ -171,3 +172,15 @@ def test_run_tables_at_segment_boundaries(n, cell, sign):
     e = e * (1.0 / e[-1])
     shifts = [0.3 / n, 5.21 / n, -3.7 / n, 0.5 + 1.7 / n]
     assert _check(_rows(e, len(shifts), 9, shifts), 2, True) <= 1e-6
+
+
+def test_long_row():
+    # one row of 2^20 + 3 cells: wave segments of ~65k cells in the run
+    # tables, a tile table of ~1000 tiles, a 10 % shorter cell deep inside,
+    # shifts across many tiles
+    n = (1 << 20) + 3
+    e = W.uniform_edges(n, 0.0, 1.0).copy()
+    e[700001:] -= 0.1 * (e[1] - e[0])
+    e = e * (1.0 / e[-1])
+    shifts = [0.37 / n, 3001.6 / n]
+    assert _check(_rows(e, len(shifts), 10, shifts), 2, True) <= 1e-6
