@@ -9,7 +9,8 @@ with the FP64 oracle.
   <= 1e-5 against the oracle run on the same FP32 inputs (v0bar <= 1e-3: it
   sums differences of the FP32 reconstruction slope), also on a uniform mesh
   whose tiles all take the transposed stencil (orders 1, 3 and 5, with and
-  without the residual, shifts of many cells and of whole periods).
+  without the residual, shifts of many cells and of whole periods), and one
+  row of 2^18 + 5 cells with a shorter cell (both paths, at scale).
   Covered: rows of
   one and of several tiles, ragged batches with per-row meshes, large shifts,
   a tile whose source window overflows the on-chip buffer, and steps without
@@ -204,3 +205,27 @@ def test_step_adjoint_fp32_uniform_stencil(order, residual):
     v0err = np.max(np.abs(got[2] - ref[2])) / np.max(np.abs(ref[2]))
     print(f"order {order} residual {residual} FP32 v0bar max rel {v0err:.2e}")
     assert v0err <= 1e-3
+
+
+def test_step_adjoint_fp32_long_row():
+    # one long uniform row with a 10 % shorter cell: ~260 tiles, most through
+    # the transposed stencil, those that see the cell through the scatter;
+    # the atomics on the cells shared by neighbouring windows at scale
+    n = (1 << 18) + 5
+    rng = np.random.default_rng(41)
+    e = W.uniform_edges(n, 0.0, 1.0).copy()
+    e[100001:] -= 0.1 * (e[1] - e[0])
+    e = e * (1.0 / e[-1])
+    xc = 0.5 * (e[:-1] + e[1:])
+    q = 1.0 + 0.3 * np.sin(2 * np.pi * xc)[None, :] + 0.05 * rng.standard_normal((2, n))
+    dv = 0.2 * np.diff(e).min() * rng.uniform(-1, 1, (2, n))
+    v0 = np.array([0.41, -2017.3]) / n
+    wl = W.Workload("long", 2, n, np.arange(3) * n, e, True, q, dv, v0, 1.0, 5, 1)
+    qf, qh, rbar = _inputs(wl, 43)
+    f32 = lambda a: a.astype(np.float32).astype(np.float64)
+    qf, qh, rbar, dvf = f32(qf), f32(qh), f32(rbar), f32(dv.reshape(-1))
+    got = _gpu_step_adjoint(wl, qf, qh, dvf, rbar, v0, 5, torch.float32)
+    ref = _oracle_step_adjoint(wl, qf, qh, dvf, rbar, v0, 5)
+    assert rel_l1(got[0], ref[0]) <= 1e-5
+    assert rel_l1(got[1], ref[1]) <= 1e-5
+    assert np.max(np.abs(got[2] - ref[2])) <= 1e-3 * np.max(np.abs(ref[2]))
