@@ -72,6 +72,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_sh_f32_direct_polar2048x16
 TRAFFIC_FILE_PPM = os.path.join(ROOT, "profiles", "k_step_sh_f32_ppm_polar2048x16384_traffic.md")
 TRAFFIC_FILE_RADIAL = os.path.join(ROOT, "profiles", "k_radial_f32_polar2048x16384_traffic.md")
 TRAFFIC_FILE_AVG4 = os.path.join(ROOT, "profiles", "k_average4_f32_polar2048x16384_traffic.md")
+TRAFFIC_FILE_ADJ = os.path.join(ROOT, "profiles", "k_adj_sh_f32_polar2048x16384_traffic.md")
+ADJ_KERNEL = "k_adj_sh<float, 5, true>"
 
 
 def _finite(v):
@@ -206,6 +208,14 @@ def main():
         # steps on centre values: the conversion kernel, both directions
         q.copy_(q32)
         ctx.ram_step_point4(rows, q, v0, dv32, wl.dt, order, args.steps, R.RAM_SUM_DIRECT)
+        # backward steps with every gradient (Q, dv, v0): the adjoint kernel
+        half = torch.empty_like(q32)
+        ctx.ram_shift(rows, q32, half, v0, wl.dt, order, R.RAM_SUM_DIRECT)
+        qb_in, qb_out = torch.ones_like(q32), torch.empty_like(q32)
+        dvb, v0b = torch.zeros_like(dv32), torch.zeros_like(v0)
+        for _ in range(args.steps):
+            ctx.ram_step_adjoint(rows, q32, half, dv32, qb_in, qb_out, v0, wl.dt, order, dvb,
+                                 v0b)
         src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         dst.copy_(src)
@@ -616,6 +626,27 @@ def main():
     torch.cuda.synchronize()
     v_adj_q0 = n_cells * ka / (a.elapsed_time(b) / 1e3) / 1e9
     del out, qo_
+    # one backward step with every gradient, alone: the call (its mesh tables,
+    # window plan and zeroing pass included) against the adjoint kernel's
+    # algorithmic bytes
+    half = torch.empty_like(q32)
+    ctx.ram_shift(rows, q32, half, v0, wl.dt, order, R.RAM_SUM_DIRECT)
+    qb_in, qb_out = torch.ones_like(q32), torch.empty_like(q32)
+    dvb, v0b = torch.zeros_like(dv32), torch.zeros_like(v0)
+    t_adj_call = time_kernel(lambda: ctx.ram_step_adjoint(rows, q32, half, dv32, qb_in, qb_out,
+                                                          v0, wl.dt, order, dvb, v0b), 20)
+    adj_bytes = 28 * n_cells
+    tr_adj = load_traffic(TRAFFIC_FILE_ADJ, ADJ_KERNEL)
+    adjoint_step = {
+        "kernel": ADJ_KERNEL + " (FP32, order 5, fused residual transpose, every gradient)",
+        "call_us": round(t_adj_call * 1e6, 2),
+        "algorithmic_bytes_per_cell": 28,
+        "bytes_note": "Qbar in and out, Q half-step, dv, dvbar read and written, Q for v0bar",
+        "hbm_frac_of_call": round(adj_bytes / t_adj_call / 1e9 / HBM_PEAK_GBS, 4),
+        "traffic": None if tr_adj is None else round(tr_adj["traffic_bytes_per_launch"]),
+        "traffic_over_algorithmic": None if tr_adj is None
+        else round(tr_adj["traffic_over_algorithmic"], 3)}
+    del half, qb_in, qb_out, dvb, v0b
 
     # --- accuracy: one FP32 step against the FP64 path (itself held to the
     # oracle at 1e-12 by the GPU tests) from the same FP32-rounded input, over
@@ -704,6 +735,7 @@ def main():
                         "steps": ka, "checkpoint": args.checkpoint},
         "fwd_adjoint_q0_grad_only": {"value": round(v_adj_q0, 3), "unit": "Gcell-updates/s",
                                      "steps": ka, "checkpoint": args.checkpoint},
+        "adjoint_step": adjoint_step,
         "fwd_adjoint_all_states_kept": {"value": round(v_adj_all, 3),
                                         "unit": "Gcell-updates/s", "steps": ka,
                                         "state_memory_gb": round((2 * ka + 1) * n_cells * 4
