@@ -74,6 +74,8 @@ TRAFFIC_FILE_RADIAL = os.path.join(ROOT, "profiles", "k_radial_f32_polar2048x163
 TRAFFIC_FILE_AVG4 = os.path.join(ROOT, "profiles", "k_average4_f32_polar2048x16384_traffic.md")
 TRAFFIC_FILE_ADJ = os.path.join(ROOT, "profiles", "k_adj_sh_f32_polar2048x16384_traffic.md")
 ADJ_KERNEL = "k_adj_sh<float, 5, true>"
+TRAFFIC_FILE_LADJ = os.path.join(ROOT, "profiles", "k_shift_lim_adj_f32_ppm_polar2048x16384_traffic.md")
+LADJ_KERNEL = "k_shift_lim_adj<float, 2>"
 
 
 def _finite(v):
@@ -216,6 +218,10 @@ def main():
         for _ in range(args.steps):
             ctx.ram_step_adjoint(rows, q32, half, dv32, qb_in, qb_out, v0, wl.dt, order, dvb,
                                  v0b)
+        # the limited (PPM) shift's adjoint
+        for _ in range(args.steps):
+            ctx.ram_shift_limited_adjoint(rows, q32, qb_in, qb_out, v0, wl.dt,
+                                          R.RAM_RECON_PPM)
         src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         dst.copy_(src)
@@ -574,10 +580,15 @@ def main():
     t_ladj = time_kernel(lambda: ctx.ram_shift_limited_adjoint(
         rows, q32, hh, oo, v0, wl.dt, R.RAM_RECON_PPM), reps)
     del hh, oo
+    tr_ladj = load_traffic(TRAFFIC_FILE_LADJ, LADJ_KERNEL)
     limited["ppm_f32"]["fwd_adjoint"] = {
         "value": round(n_cells * kla / (a.elapsed_time(b) / 1e3) / 1e9, 3),
         "steps": kla, "checkpoint": args.checkpoint,
-        "shift_adjoint_kernel_us": round(t_ladj * 1e6, 2)}
+        "shift_adjoint_kernel_us": round(t_ladj * 1e6, 2),
+        "shift_adjoint_algorithmic_bytes_per_cell": 12,
+        "shift_adjoint_hbm_frac_of_call": round(12.0 * n_cells / t_ladj / 1e9 / HBM_PEAK_GBS, 4),
+        "shift_adjoint_traffic": None if tr_ladj is None
+        else round(tr_ladj["traffic_bytes_per_launch"])}
 
     # --- forward + adjoint (checkpointed rollout) ---------------------------
     ka = args.adj_steps

@@ -39,7 +39,8 @@ STEP_KERNEL_SOURCES = ["ram_step_shared.hip", "ram_device.h", "ram_internal.h"]
 KERNEL_SOURCES = {"k_step_sh": STEP_KERNEL_SOURCES,
                   "k_radial": ["ram_radial.hip", "ram_device.h", "ram_internal.h"],
                   "k_average4": ["ram_average4.hip", "ram_device.h", "ram_internal.h"],
-                  "k_adj_sh": ["ram_adjoint_shared.hip", "ram_device.h", "ram_internal.h"]}
+                  "k_adj_sh": ["ram_adjoint_shared.hip", "ram_device.h", "ram_internal.h"],
+                  "k_shift_lim_adj": ["ram_adjoint.hip", "ram_device.h", "ram_internal.h"]}
 
 
 def kernel_digest(kernel: str = "k_step_sh") -> str:
