@@ -404,13 +404,28 @@ void k_step_sh(StepArgs a)
             const CT *pw;
             if constexpr (sizeof(CT) == 8) pw = (const CT *)tb.ppmd;
             else pw = (const CT *)tb.ppmf;
+            // a uniform tile: every window cell and its neighbours have the
+            // run's size, so one set of mesh weights serves the window
+            CT pu[5];
+            if (uni) {
+#pragma unroll
+                for (int k = 0; k < 5; ++k) pu[k] = pw[k * n + base];
+            }
             // limited slopes of window cells 1 .. W-2
 #pragma unroll
             for (int r = 0; r < kWinRegs; ++r) {
                 const int j = t + r * kBlock;
-                if (j >= 1 && j < W - 1)
-                    sx2[j] = ppm_delta<CT>(sx1[j - 1], wq[r], sx1[j + 1], pw[wm[r]],
-                                           pw[n + wm[r]]);
+                if (j >= 1 && j < W - 1) {
+                    CT d1, d2;
+                    if (uni) {
+                        d1 = pu[0];
+                        d2 = pu[1];
+                    } else {
+                        d1 = pw[wm[r]];
+                        d2 = pw[n + wm[r]];
+                    }
+                    sx2[j] = ppm_delta<CT>(sx1[j - 1], wq[r], sx1[j + 1], d1, d2);
+                }
             }
             __syncthreads();
             // interface values between cells j and j+1, j = 1 .. W-3
@@ -419,8 +434,17 @@ void k_step_sh(StepArgs a)
                 const int j = t + r * kBlock;
                 if (j >= 1 && j < W - 2) {
                     const int m = wm[r];
-                    sx3[j] = wq[r] + pw[2 * n + m] * (sx1[j + 1] - wq[r]) +
-                             pw[3 * n + m] * sx2[j + 1] + pw[4 * n + m] * sx2[j];
+                    CT e1, e2, e3;
+                    if (uni) {
+                        e1 = pu[2];
+                        e2 = pu[3];
+                        e3 = pu[4];
+                    } else {
+                        e1 = pw[2 * n + m];
+                        e2 = pw[3 * n + m];
+                        e3 = pw[4 * n + m];
+                    }
+                    sx3[j] = wq[r] + e1 * (sx1[j + 1] - wq[r]) + e2 * sx2[j + 1] + e3 * sx2[j];
                 }
             }
             __syncthreads();
