@@ -404,12 +404,16 @@ void k_step_sh(StepArgs a)
             const CT *pw;
             if constexpr (sizeof(CT) == 8) pw = (const CT *)tb.ppmd;
             else pw = (const CT *)tb.ppmf;
-            // a uniform tile: every window cell and its neighbours have the
-            // run's size, so one set of mesh weights serves the window
+            // a uniform tile: the cells that take weights (window cells 1 ..
+            // W-3) and their neighbours lie in the run, so one set serves
+            // them all -- window cell 1's, whose neighbours (window cells
+            // 0 .. 3) are in the window; window cell 0's left neighbour need
+            // not be
             CT pu[5];
             if (uni) {
+                const int c1 = base + 1 >= n ? base + 1 - n : base + 1;
 #pragma unroll
-                for (int k = 0; k < 5; ++k) pu[k] = pw[k * n + base];
+                for (int k = 0; k < 5; ++k) pu[k] = pw[k * n + c1];
             }
             // limited slopes of window cells 1 .. W-2
 #pragma unroll

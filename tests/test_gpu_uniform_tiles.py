@@ -18,7 +18,10 @@ L1:
 * uniform rows of 6 .. 13 cells, whose windows wrap the row;
 * a cell 10 % shorter or longer on either side of a boundary of the wave
   segments the uniform-run tables are built in;
-* one row of 2^20 + 3 cells (segments of ~65k cells, ~1000 tiles a row).
+* one row of 2^20 + 3 cells (segments of ~65k cells, ~1000 tiles a row);
+* a limited step whose uniform tile's window starts at a run's first cell
+  (its left neighbour off the run: the shared PPM weights must come from
+  cells whose neighbourhood is in the run).
 
 In a uniform tile the FP32 Lagrange step is one (P+1)-point stencil on the
 cell values, so these cases also check its weights (from the Lagrange
@@ -184,3 +187,17 @@ def test_long_row():
     e = e * (1.0 / e[-1])
     shifts = [0.37 / n, 3001.6 / n]
     assert _check(_rows(e, len(shifts), 10, shifts), 2, True) <= 1e-6
+
+
+@pytest.mark.parametrize("recon", [R.RAM_RECON_PLM, R.RAM_RECON_PPM])
+def test_limited_window_at_run_start(recon):
+    # 4096 coarse cells then 4096 four times finer: shifted by 1014.6 coarse
+    # cells, the second tile's source window starts at cell 0, the coarse
+    # run's first cell, whose left neighbour (across the seam) is fine.  The
+    # tile is uniform; its limited weights must come from cells whose whole
+    # neighbourhood is in the run
+    e = np.concatenate([np.linspace(0.0, 0.8, 4097), np.linspace(0.8, 1.0, 4097)[1:]])
+    hc = 0.8 / 4096
+    shifts = [1014.6 * hc, 1014.6 * hc + 0.3 * hc, 3.3 * hc]
+    wl = _rows(e, len(shifts), 11, shifts)
+    assert _check_limited(wl, 2, recon) <= 1e-6
