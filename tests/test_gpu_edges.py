@@ -13,6 +13,7 @@ import pytest
 import torch
 
 import oracle
+from parity import CELL_F32, CELL_F32_ADJ, CELL_F64, assert_parity
 from paper_2305_05362_amd import _lib as R
 from paper_2305_05362_amd import workloads as W
 
@@ -41,7 +42,7 @@ def test_zero_shift_is_identity(scan):
         got = q.cpu().numpy().reshape(wl.n_rows, -1)
         ref = oracle.step(oracle.Rows.from_workload(wl), wl.q0, v0, None, dt, 5, 3)
         ref = ref.reshape(wl.n_rows, -1)
-        assert rel_l1(got.reshape(-1), ref.reshape(-1)) <= 1e-12
+        assert_parity(got.reshape(-1), ref.reshape(-1), 1e-12, CELL_F64)
         still = v0 == 0.0 if dt != 0.0 else np.ones(wl.n_rows, bool)
         assert rel_l1(got[still].reshape(-1), wl.q0.reshape(wl.n_rows, -1)[still].reshape(-1)) \
             <= 1e-15
@@ -57,14 +58,14 @@ def test_negative_dt_and_short_rows(scan):
     R.ram_step(rows, q, dev(wl.v0), dev(wl.dv), -0.5 * wl.dt, 5, 2, scan)
     torch.cuda.synchronize()
     ref = oracle.step(orows, wl.q0, wl.v0, wl.dv, -0.5 * wl.dt, 5, 2)
-    assert rel_l1(q.cpu().numpy(), ref) <= 1e-12
+    assert_parity(q.cpu().numpy(), ref, 1e-12, CELL_F64)
     # shift only, shifts of many periods either way on rows of 6..40 cells
     for mult in (-37.5, 211.0):
         q = dev(wl.q0)
         R.ram_step(rows, q, dev(wl.v0 * mult), None, -wl.dt, 5, 2, scan)
         torch.cuda.synchronize()
         ref = oracle.step(orows, wl.q0, wl.v0 * mult, None, -wl.dt, 5, 2)
-        assert rel_l1(q.cpu().numpy(), ref) <= 1e-12, mult
+        assert_parity(q.cpu().numpy(), ref, 1e-12, CELL_F64, what=str(mult))
 
 
 def test_zero_steps_leave_state_untouched():
@@ -107,7 +108,7 @@ def test_many_tiny_ragged_rows():
     R.ram_step(rows, q, dev(wl.v0), dev(wl.dv), wl.dt, 5, 3)
     torch.cuda.synchronize()
     ref = oracle.step(oracle.Rows.from_workload(wl), wl.q0, wl.v0, wl.dv, wl.dt, 5, 3)
-    assert rel_l1(q.cpu().numpy(), ref) <= 1e-12
+    assert_parity(q.cpu().numpy(), ref, 1e-12, CELL_F64)
     # and the adjoint through the per-row path
     rng = np.random.default_rng(3)
     rbar = rng.standard_normal(wl.n_cells)
@@ -121,6 +122,6 @@ def test_many_tiny_ragged_rows():
     torch.cuda.synchronize()
     r1, dvr = oracle.residual_adjoint(orows, qh, wl.dv, rbar, wl.dt)
     r0, v0r = oracle.shift_adjoint(orows, wl.q0, r1, wl.v0, wl.dt, 5)
-    assert rel_l1(qb.cpu().numpy(), r0) <= 1e-12
-    assert rel_l1(dvb.cpu().numpy(), dvr) <= 1e-12
+    assert_parity(qb.cpu().numpy(), r0, 1e-12, CELL_F64)
+    assert_parity(dvb.cpu().numpy(), dvr, 1e-12, CELL_F64)
     assert np.max(np.abs(v0b.cpu().numpy() - v0r)) <= 1e-10 * np.max(np.abs(v0r))

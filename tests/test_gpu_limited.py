@@ -20,6 +20,7 @@ import pytest
 import torch
 
 import oracle
+from parity import CELL_F32, CELL_F32_ADJ, CELL_F64, assert_parity
 from paper_2305_05362_amd import _lib as R
 from paper_2305_05362_amd import workloads as W
 
@@ -62,8 +63,7 @@ def test_shift_limited_fp64(kind, recon):
         v0 = wl.v0 * mult
         got = _gpu_shift(wl, wl.q0, v0, recon)
         ref = oracle.shift_recon(orows, wl.q0, v0, wl.dt, recon)
-        err = rel_l1(got, ref)
-        assert err <= 1e-12, (mult, err)
+        assert_parity(got, ref, 1e-12, CELL_F64, what=str(mult))
 
 
 @pytest.mark.parametrize("recon", RECONS)
@@ -81,12 +81,12 @@ def test_shift_limited_window_overflow(recon):
                         np.array([s]), 1.0, 5, 1)
         got = _gpu_shift(wl, q, wl.v0, recon)
         ref = oracle.shift_recon(oracle.Rows.from_workload(wl), q, wl.v0, 1.0, recon)
-        assert rel_l1(got, ref) <= 1e-12, s
+        assert_parity(got, ref, 1e-12, CELL_F64, what=str(s))
         # the same mesh as per-row edges
         wr = W.Workload("row", 1, 0, np.array([0, n]), e, False, q[None, :], None,
                         np.array([s]), 1.0, 5, 1)
         got = _gpu_shift(wr, q, wr.v0, recon)
-        assert rel_l1(got, ref) <= 1e-12, s
+        assert_parity(got, ref, 1e-12, CELL_F64, what=str(s))
 
 
 @pytest.mark.parametrize("recon", RECONS)
@@ -99,7 +99,7 @@ def test_shift_limited_fp32(kind, recon):
         v0 = wl.v0 * mult
         got = _gpu_shift(wl, q32, v0, recon, torch.float32)
         ref = oracle.shift_recon(orows, q32, v0, wl.dt, recon)
-        err = rel_l1(got, ref)
+        err, ec = assert_parity(got, ref, 1e-6, CELL_F32, what=str(mult))
         print(f"{kind} recon {recon} FP32 rel-L1 {err:.2e}")
         assert err <= 1e-6, (mult, err)
 
@@ -145,7 +145,7 @@ def test_step_limited_fp64(recon):
             q = dev(wl.q0)
             R.ram_step_limited(rows, q, dev(wl.v0), dev(wl.dv), wl.dt, recon, k)
             torch.cuda.synchronize()
-            assert rel_l1(q.cpu().numpy(), ref) <= 1e-12, (k, call)
+            assert_parity(q.cpu().numpy(), ref, 1e-12, CELL_F64, what=str((k, call)))
     # shift-only steps on ragged per-row meshes (an odd count ends in scratch)
     wr = _cases()["ragged"]()
     rows = R.Rows.from_workload(wr, DEV)
@@ -153,7 +153,7 @@ def test_step_limited_fp64(recon):
     q = dev(wr.q0)
     R.ram_step_limited(rows, q, dev(wr.v0), None, wr.dt, recon, 5)
     torch.cuda.synchronize()
-    assert rel_l1(q.cpu().numpy(), ref) <= 1e-12
+    assert_parity(q.cpu().numpy(), ref, 1e-12, CELL_F64)
 
 
 def _sample_rows(wl, rows):
@@ -181,14 +181,14 @@ def test_limited_full_size_sampled_rows(recon):
     ref = oracle.step_recon(orows, q32.reshape(wl.n_rows, -1)[pick].astype(np.float64),
                             sw.v0, dv32.reshape(wl.n_rows, -1)[pick].astype(np.float64),
                             sw.dt, recon, 1)
-    assert rel_l1(got, ref) <= 1e-6
+    assert_parity(got, ref, 1e-6, CELL_F32)
     # FP64, two steps; every row's mass is conserved
     q = dev(wl.q0)
     R.ram_step_limited(rows, q, dev(wl.v0), dev(wl.dv), wl.dt, recon, 2)
     torch.cuda.synchronize()
     got = q.cpu().numpy().reshape(wl.n_rows, -1)
     ref = oracle.step_recon(orows, sw.q0, sw.v0, sw.dv, sw.dt, recon, 2)
-    assert rel_l1(got[pick].reshape(-1), ref) <= 1e-12
+    assert_parity(got[pick].reshape(-1), ref, 1e-12, CELL_F64)
     dx = np.diff(wl.edges)
     m0 = wl.q0.reshape(wl.n_rows, -1) @ dx
     m1 = got @ dx

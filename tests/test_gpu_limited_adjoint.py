@@ -13,6 +13,7 @@ import pytest
 import torch
 
 import oracle
+from parity import CELL_F32, CELL_F32_ADJ, CELL_F64, assert_parity
 from paper_2305_05362_amd import _lib as R
 from paper_2305_05362_amd import workloads as W
 
@@ -59,7 +60,7 @@ def test_limited_adjoint_fp64(kind, recon):
         v0 = wl.v0 * mult
         got, gv = _gpu(wl, wl.q0, qb, v0, recon)
         ref, rv = oracle.shift_recon_adjoint(orows, wl.q0, qb, v0, wl.dt, recon)
-        assert rel_l1(got, ref) <= 1e-12, (mult, rel_l1(got, ref))
+        assert_parity(got, ref, 1e-12, CELL_F64, what=str((mult, rel_l1(got, ref))))
         assert np.max(np.abs(gv - rv)) <= 1e-10 * np.max(np.abs(rv)), mult
 
 
@@ -78,7 +79,7 @@ def test_limited_adjoint_refinement_jump(recon):
         got, gv = _gpu(wl, q, qb, wl.v0, recon)
         ref, rv = oracle.shift_recon_adjoint(oracle.Rows.from_workload(wl), q, qb, wl.v0,
                                              1.0, recon)
-        assert rel_l1(got, ref) <= 1e-12, s
+        assert_parity(got, ref, 1e-12, CELL_F64, what=str(s))
         assert abs(gv[0] - rv[0]) <= 1e-10 * abs(rv[0]), s
 
 
@@ -93,7 +94,7 @@ def test_limited_adjoint_fp32(kind, recon):
     got, gv = _gpu(wl, q, qb, wl.v0, recon, torch.float32)
     ref, rv = oracle.shift_recon_adjoint(oracle.Rows.from_workload(wl), q, qb, wl.v0, wl.dt,
                                          recon)
-    assert rel_l1(got, ref) <= 1e-6
+    assert_parity(got, ref, 1e-6, CELL_F32)
     assert np.max(np.abs(gv - rv)) <= 1e-10 * np.max(np.abs(rv))
 
 
@@ -119,7 +120,7 @@ def test_limited_adjoint_full_size_sampled_rows(recon):
         ref, rv = oracle.shift_recon_adjoint(sub, wl.q0.reshape(wl.n_rows, -1)[r],
                                              qb.reshape(wl.n_rows, -1)[r], wl.v0[r:r + 1],
                                              wl.dt, recon)
-        assert rel_l1(got[r], ref) <= 1e-12, r
+        assert_parity(got[r], ref, 1e-12, CELL_F64, what=str(r))
         rvs.append(rv[0])
     rvs = np.array(rvs)
     assert np.max(np.abs(rvs)) > 0.0

@@ -11,6 +11,7 @@ import pytest
 import torch
 
 import oracle
+from parity import CELL_F32, CELL_F32_ADJ, CELL_F64, assert_parity, max_cell
 from paper_2305_05362_amd import _lib as R
 from paper_2305_05362_amd import workloads as W
 
@@ -59,7 +60,7 @@ def test_shift_polar_fp64(order):
         v0 = wl.v0 * mult
         got = gpu_shift(wl, wl.q0, order, v0=v0)
         ref = oracle_shift(wl, wl.q0, order, v0=v0)
-        assert rel_l1(got, ref) <= 1e-12, (mult, rel_l1(got, ref))
+        assert_parity(got, ref, 1e-12, CELL_F64, what=str((mult, rel_l1(got, ref))))
 
 
 @pytest.mark.parametrize("order", [1, 3, 5])
@@ -67,11 +68,11 @@ def test_shift_ragged_fp64(order):
     wl = W.small_ragged(40, 6, 900, seed=11, order=order)
     got = gpu_shift(wl, wl.q0, order)
     ref = oracle_shift(wl, wl.q0, order)
-    assert rel_l1(got, ref) <= 1e-12
+    assert_parity(got, ref, 1e-12, CELL_F64)
     # per row too (short rows must not be swamped by long ones)
     for r in range(wl.n_rows):
         a, b = wl.row_ptr[r], wl.row_ptr[r + 1]
-        assert rel_l1(got[a:b], ref[a:b]) <= 1e-12, r
+        assert_parity(got[a:b], ref[a:b], 1e-12, CELL_F64, what=str(r))
 
 
 @pytest.mark.parametrize("n", [6, 7, 255, 256, 257, 513, 1000])
@@ -83,7 +84,7 @@ def test_shift_row_lengths_and_tails(n):
     for s in (0.0, 0.31, -2.7, 123.456):
         got = gpu_shift(wl, q, 5, v0=np.array([s]), dt=1.0)
         ref = oracle_shift(wl, q, 5, v0=np.array([s]), dt=1.0)
-        assert rel_l1(got, ref) <= 1e-12, (n, s)
+        assert_parity(got, ref, 1e-12, CELL_F64, what=str((n, s)))
 
 
 def test_shift_window_overflow_direct_path():
@@ -99,7 +100,7 @@ def test_shift_window_overflow_direct_path():
     for s in (-0.5, -0.37):
         got = gpu_shift(wl, q, 5, v0=np.array([s]), dt=1.0)
         ref = oracle_shift(wl, q, 5, v0=np.array([s]), dt=1.0)
-        assert rel_l1(got, ref) <= 1e-12
+        assert_parity(got, ref, 1e-12, CELL_F64)
 
 
 @pytest.mark.parametrize("order", [1, 3, 5])
@@ -119,10 +120,13 @@ def test_shift_fp32_scans():
     for name, scan in (("f64", R.RAM_SCAN_F64), ("twosum", R.RAM_SCAN_F32_TWOSUM),
                        ("f32", R.RAM_SCAN_F32), ("direct", R.RAM_SUM_DIRECT)):
         got = gpu_shift(wl, q32, 5, torch.float32, scan)
-        errs[name] = rel_l1(got, ref)
-    print("one-step rel-L1 by scan precision:", errs)
-    assert errs["f64"] <= 1e-6 and errs["twosum"] <= 1e-6 and errs["direct"] <= 1e-6
-    assert np.isfinite(errs["f32"])
+        errs[name] = (rel_l1(got, ref), max_cell(got, ref))
+    print("one-step (rel-L1, max cell) by scan precision:", errs)
+    for name in ("f64", "twosum", "direct"):
+        assert errs[name][0] <= 1e-6 and errs[name][1] <= CELL_F32, (name, errs[name])
+    # the plain FP32 window prefix: window-long cumulative rounding (the
+    # compensated modes exist to remove it), held to 1e-4 rel-L1
+    assert errs["f32"][0] <= 1e-4, errs["f32"]
 
 
 @pytest.mark.parametrize("order", [1, 3, 5])
@@ -148,13 +152,13 @@ def test_direct_sums_fp64(kind, order):
         wl = W.small_polar(6, 800, order=order) if kind == "polar_one_tile" else \
             W.small_polar(3, 3500, order=order)
     got = gpu_shift(wl, wl.q0, order, scan=R.RAM_SUM_DIRECT)
-    assert rel_l1(got, oracle_shift(wl, wl.q0, order)) <= 1e-12
+    assert_parity(got, oracle_shift(wl, wl.q0, order), 1e-12, CELL_F64)
     rows = R.Rows.from_workload(wl, DEV)
     q = dev(wl.q0.reshape(-1))
     R.ram_step(rows, q, dev(wl.v0), dev(wl.dv.reshape(-1)), wl.dt, order, 3, R.RAM_SUM_DIRECT)
     torch.cuda.synchronize()
     ref = oracle.step(oracle.Rows.from_workload(wl), wl.q0, wl.v0, wl.dv, wl.dt, order, 3)
-    assert rel_l1(q.cpu().numpy(), ref) <= 1e-12
+    assert_parity(q.cpu().numpy(), ref, 1e-12, CELL_F64)
 
 
 # --------------------------------------------------------------------------
@@ -174,14 +178,14 @@ def test_residual_polar_fp64():
     wl = W.small_polar(8, 700)
     got = gpu_residual(wl, wl.q0)
     ref = oracle.residual(oracle.Rows.from_workload(wl), wl.q0, wl.dv, wl.dt)
-    assert rel_l1(got, ref) <= 1e-12
+    assert_parity(got, ref, 1e-12, CELL_F64)
 
 
 def test_residual_ragged_fp64():
     wl = W.small_ragged(30, 3, 800, seed=2)
     got = gpu_residual(wl, wl.q0)
     ref = oracle.residual(oracle.Rows.from_workload(wl), wl.q0, wl.dv, wl.dt)
-    assert rel_l1(got, ref) <= 1e-12
+    assert_parity(got, ref, 1e-12, CELL_F64)
 
 
 def test_residual_fp32():
@@ -192,7 +196,7 @@ def test_residual_fp32():
                       q32.astype(np.float64), dv32.astype(np.float64), wl.v0, wl.dt, 5, 1)
     got = gpu_residual(wl32, q32, torch.float32)
     ref = oracle.residual(oracle.Rows.from_workload(wl32), wl32.q0, wl32.dv, wl.dt)
-    assert rel_l1(got, ref) <= 1e-6
+    assert_parity(got, ref, 1e-6, CELL_F32)
 
 
 def test_step_cfg1_fp64():
@@ -203,7 +207,7 @@ def test_step_cfg1_fp64():
     torch.cuda.synchronize()
     got = q.cpu().numpy()
     ref = oracle.step(oracle.Rows.from_workload(wl), wl.q0, wl.v0, None, wl.dt, 5, wl.steps)
-    assert rel_l1(got, ref) <= 1e-12
+    assert_parity(got, ref, 1e-12, CELL_F64)
     # and both sit within the order-5 truncation error of the exact roll
     assert rel_l1(got, np.roll(wl.q0.reshape(-1), 6)) < 1e-10
 
@@ -216,7 +220,7 @@ def test_step_polar_with_residual(steps):
     R.ram_step(rows, q, dev(wl.v0), dev(wl.dv.reshape(-1)), wl.dt, 5, steps)
     torch.cuda.synchronize()
     ref = oracle.step(oracle.Rows.from_workload(wl), wl.q0, wl.v0, wl.dv, wl.dt, 5, steps)
-    assert rel_l1(q.cpu().numpy(), ref) <= 1e-12
+    assert_parity(q.cpu().numpy(), ref, 1e-12, CELL_F64)
 
 
 def test_step_ragged_shift_only_odd_steps():
@@ -226,7 +230,7 @@ def test_step_ragged_shift_only_odd_steps():
     R.ram_step(rows, q, dev(wl.v0), None, wl.dt, 3, 5)
     torch.cuda.synchronize()
     ref = oracle.step(oracle.Rows.from_workload(wl), wl.q0, wl.v0, None, wl.dt, 3, 5)
-    assert rel_l1(q.cpu().numpy(), ref) <= 1e-12
+    assert_parity(q.cpu().numpy(), ref, 1e-12, CELL_F64)
 
 
 # --------------------------------------------------------------------------
@@ -252,7 +256,7 @@ def test_cfg2_full_size_sampled_rows():
     pick = np.array([0, 1, 77, 255, 256, 400, 510, 511])
     sw = _sample_rows(wl, pick)
     ref = oracle.step(oracle.Rows.from_workload(sw), sw.q0, sw.v0, sw.dv, sw.dt, 5, wl.steps)
-    assert rel_l1(got[pick].reshape(-1), ref) <= 1e-12
+    assert_parity(got[pick].reshape(-1), ref, 1e-12, CELL_F64)
 
 
 def test_cfg5_full_size_sampled_rows():
@@ -267,7 +271,7 @@ def test_cfg5_full_size_sampled_rows():
     torch.cuda.synchronize()
     got = q.cpu().numpy().reshape(wl.n_rows, -1)[pick].reshape(-1)
     ref = oracle.step(orows, sw.q0, sw.v0, sw.dv, sw.dt, 5, 3)
-    assert rel_l1(got, ref) <= 1e-12
+    assert_parity(got, ref, 1e-12, CELL_F64)
     # FP32 state, compensated scan, one step from the same FP32 input
     q32 = wl.q0.astype(np.float32)
     dv32 = wl.dv.astype(np.float32)
@@ -280,7 +284,7 @@ def test_cfg5_full_size_sampled_rows():
                    scan)
         torch.cuda.synchronize()
         got = q.cpu().numpy().astype(np.float64).reshape(wl.n_rows, -1)[pick].reshape(-1)
-        assert rel_l1(got, ref) <= 1e-6, scan
+        assert_parity(got, ref, 1e-6, CELL_F32, what=str(scan))
 
 
 def test_cfg3_full_size_sampled_rows():
@@ -295,7 +299,7 @@ def test_cfg3_full_size_sampled_rows():
         a, b = wl.row_ptr[r], wl.row_ptr[r + 1]
         e = wl.row_edges(r)
         ref = oracle.step(oracle.Rows.single(e), wl.q0[a:b], wl.v0[r:r + 1], None, wl.dt, 5, 2)
-        assert rel_l1(got[a:b], ref) <= 1e-12, r
+        assert_parity(got[a:b], ref, 1e-12, CELL_F64, what=str(r))
     del orows
 
 
@@ -321,7 +325,7 @@ def test_shift_adjoint_fp64(order, kind):
         torch.cuda.synchronize()
         ref_qb, ref_v0b = oracle.shift_adjoint(oracle.Rows.from_workload(wl), wl.q0, rbar,
                                                v0, wl.dt, order)
-        assert rel_l1(qb.cpu().numpy(), ref_qb) <= 1e-12
+        assert_parity(qb.cpu().numpy(), ref_qb, 1e-12, CELL_F64)
         got_v = v0b.cpu().numpy()
         assert np.max(np.abs(got_v - ref_v0b)) <= 1e-10 * np.max(np.abs(ref_v0b))
 
@@ -351,8 +355,8 @@ def test_residual_adjoint_fp64():
     torch.cuda.synchronize()
     ref_qb, ref_dvb = oracle.residual_adjoint(oracle.Rows.from_workload(wl), wl.q0, wl.dv,
                                               rbar, wl.dt)
-    assert rel_l1(qb.cpu().numpy(), ref_qb) <= 1e-12
-    assert rel_l1(dvb.cpu().numpy() - 0.5, ref_dvb) <= 1e-12
+    assert_parity(qb.cpu().numpy(), ref_qb, 1e-12, CELL_F64)
+    assert_parity(dvb.cpu().numpy() - 0.5, ref_dvb, 1e-12, CELL_F64)
 
 
 def test_residual_adjoint_ragged_fp64():
@@ -366,8 +370,8 @@ def test_residual_adjoint_ragged_fp64():
     torch.cuda.synchronize()
     ref_qb, ref_dvb = oracle.residual_adjoint(oracle.Rows.from_workload(wl), wl.q0, wl.dv,
                                               rbar, wl.dt)
-    assert rel_l1(qb.cpu().numpy(), ref_qb) <= 1e-12
-    assert rel_l1(dvb.cpu().numpy(), ref_dvb) <= 1e-12
+    assert_parity(qb.cpu().numpy(), ref_qb, 1e-12, CELL_F64)
+    assert_parity(dvb.cpu().numpy(), ref_dvb, 1e-12, CELL_F64)
 
 
 # --------------------------------------------------------------------------

@@ -18,6 +18,7 @@ import pytest
 import torch
 
 import oracle
+from parity import CELL_F32, CELL_F32_ADJ, CELL_F64, assert_parity
 from paper_2305_05362_amd import _lib as R
 from paper_2305_05362_amd import tune
 from paper_2305_05362_amd import workloads as W
@@ -86,9 +87,9 @@ def test_schedules_agree_and_match_oracle(ctx, dtype):
         ref2 = oracle.step(orows, wl.q0, wl.v0, wl.dv, wl.dt, 5, 2)
         refs = oracle.shift(orows, wl.q0, wl.v0, wl.dt, 5)
         for k in ITEMS:
-            assert rel_l1(outs[k][0].cpu().numpy(), ref3) <= 1e-12, k
-            assert rel_l1(outs[k][1].cpu().numpy(), refs) <= 1e-12, k
-            assert rel_l1(outs[k][2][2].cpu().numpy(), ref2) <= 1e-12, k
+            assert_parity(outs[k][0].cpu().numpy(), ref3, 1e-12, CELL_F64, what=str(k))
+            assert_parity(outs[k][1].cpu().numpy(), refs, 1e-12, CELL_F64, what=str(k))
+            assert_parity(outs[k][2][2].cpu().numpy(), ref2, 1e-12, CELL_F64, what=str(k))
 
 
 def test_record_is_step_within_a_schedule(ctx):

@@ -32,6 +32,7 @@ import pytest
 import torch
 
 import oracle
+from parity import CELL_F32, assert_parity
 from paper_2305_05362_amd import _lib as R
 from paper_2305_05362_amd import workloads as W
 
@@ -70,7 +71,8 @@ def _check(wl, steps, with_dv, order=5):
     torch.cuda.synchronize()
     want = oracle.step(oracle.Rows.from_workload(wl), wl.q0, wl.v0,
                        wl.dv if with_dv else None, wl.dt, order, steps)
-    return rel_l1(q.cpu().numpy().astype(np.float64), want)
+    e1, ec = assert_parity(q.cpu().numpy().astype(np.float64), want, 1e-6, CELL_F32, "step")
+    print(f"rel-L1 {e1:.2e}, max cell {ec:.2e}")
 
 
 SHIFTS = [0.3 / 4096, 0.37 / 4096, 5.21 / 4096, -3.7 / 4096, 2.5 + 7.3 / 4096, -1.0 - 0.61 / 4096]
@@ -80,14 +82,14 @@ SHIFTS = [0.3 / 4096, 0.37 / 4096, 5.21 / 4096, -3.7 / 4096, 2.5 + 7.3 / 4096, -
 @pytest.mark.parametrize("with_dv", [False, True])
 def test_uniform_mesh(steps, with_dv):
     e = W.uniform_edges(4096, 0.0, 1.0)
-    assert _check(_rows(e, len(SHIFTS), 1, SHIFTS), steps, with_dv) <= 1e-6
+    _check(_rows(e, len(SHIFTS), 1, SHIFTS), steps, with_dv)
 
 
 @pytest.mark.parametrize("order", [1, 3])
 def test_uniform_mesh_lower_orders(order):
     # the stencil has order + 1 points
     e = W.uniform_edges(4096, 0.0, 1.0)
-    assert _check(_rows(e, len(SHIFTS), 8, SHIFTS), 3, True, order) <= 1e-6
+    _check(_rows(e, len(SHIFTS), 8, SHIFTS), 3, True, order)
 
 
 @pytest.mark.parametrize("cell", [0, 1500, 4095])
@@ -96,7 +98,7 @@ def test_one_shorter_cell(cell):
     h = e[1] - e[0]
     e[cell + 1:] -= 1e-3 * h          # cell `cell` is 0.1 % shorter
     e = e * (1.0 / e[-1])
-    assert _check(_rows(e, len(SHIFTS), 2, SHIFTS), 3, True) <= 1e-6
+    _check(_rows(e, len(SHIFTS), 2, SHIFTS), 3, True)
 
 
 def _two_levels(perturb=None):
@@ -116,13 +118,13 @@ def test_coarse_and_fine_runs(perturb):
     # keep its tiles off it
     e = _two_levels(perturb)
     shifts = [0.3 / 4096, 20.3 / 4096, -7.7 / 4096, 0.71]
-    assert _check(_rows(e, len(shifts), 6, shifts), 3, True) <= 1e-6
+    _check(_rows(e, len(shifts), 6, shifts), 3, True)
 
 
 def test_bump_mesh_runs_and_seam():
     wl = W.small_polar(8, 6000)
     w32 = _rows(wl.edges, 8, 3, wl.v0 * wl.dt)
-    assert _check(w32, 4, True) <= 1e-6
+    _check(w32, 4, True)
 
 
 def _check_limited(wl, steps, recon):
@@ -132,7 +134,8 @@ def _check_limited(wl, steps, recon):
     torch.cuda.synchronize()
     want = oracle.step_recon(oracle.Rows.from_workload(wl), wl.q0, wl.v0, wl.dv, wl.dt,
                              recon, steps)
-    return rel_l1(q.cpu().numpy().astype(np.float64), want)
+    e1, ec = assert_parity(q.cpu().numpy().astype(np.float64), want, 1e-6, CELL_F32, "limited")
+    print(f"rel-L1 {e1:.2e}, max cell {ec:.2e}")
 
 
 @pytest.mark.parametrize("recon", [R.RAM_RECON_PLM, R.RAM_RECON_PPM])
@@ -148,7 +151,7 @@ def test_limited_uniform_tiles(recon, mesh):
             e[2001:] -= 1e-3 * (e[1] - e[0])
             e = e * (1.0 / e[-1])
         wl = _rows(e, len(SHIFTS), 5, SHIFTS)
-    assert _check_limited(wl, 3, recon) <= 1e-6
+    _check_limited(wl, 3, recon)
 
 
 @pytest.mark.parametrize("n", [6, 7, 9, 13])
@@ -158,7 +161,7 @@ def test_tiny_uniform_rows(n):
     # uniform
     e = W.uniform_edges(n, 0.0, 1.0)
     shifts = [0.3 / n, 2.7 / n, -1.4 / n, 5.05]
-    assert _check(_rows(e, len(shifts), 7, shifts), 3, True) <= 1e-6
+    _check(_rows(e, len(shifts), 7, shifts), 3, True)
 
 
 @pytest.mark.parametrize("n,cell", [(4096, 255), (4096, 256), (4096, 3840), (4099, 256),
@@ -174,7 +177,7 @@ def test_run_tables_at_segment_boundaries(n, cell, sign):
     e[cell + 1:] += sign * 0.1 * (e[1] - e[0])
     e = e * (1.0 / e[-1])
     shifts = [0.3 / n, 5.21 / n, -3.7 / n, 0.5 + 1.7 / n]
-    assert _check(_rows(e, len(shifts), 9, shifts), 2, True) <= 1e-6
+    _check(_rows(e, len(shifts), 9, shifts), 2, True)
 
 
 def test_long_row():
@@ -186,7 +189,7 @@ def test_long_row():
     e[700001:] -= 0.1 * (e[1] - e[0])
     e = e * (1.0 / e[-1])
     shifts = [0.37 / n, 3001.6 / n]
-    assert _check(_rows(e, len(shifts), 10, shifts), 2, True) <= 1e-6
+    _check(_rows(e, len(shifts), 10, shifts), 2, True)
 
 
 @pytest.mark.parametrize("recon", [R.RAM_RECON_PLM, R.RAM_RECON_PPM])
@@ -200,4 +203,4 @@ def test_limited_window_at_run_start(recon):
     hc = 0.8 / 4096
     shifts = [1014.6 * hc, 1014.6 * hc + 0.3 * hc, 3.3 * hc]
     wl = _rows(e, len(shifts), 11, shifts)
-    assert _check_limited(wl, 2, recon) <= 1e-6
+    _check_limited(wl, 2, recon)
