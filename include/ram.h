@@ -97,18 +97,21 @@ ram_status ram_create(ram_ctx **ctx, int device, void *stream);
 /* Release the context and its scratch (after waiting for its stream). */
 ram_status ram_destroy(ram_ctx *ctx);
 /* Launch schedule of the shared-mesh step kernel with RAM_SUM_DIRECT (the
- * library's fastest path): each workgroup of 256 threads shifts
- * 256 * items_per_thread nodes, i.e. a tile of 256 * items_per_thread - 1
- * destination cells (4 fewer when the residual step is fused in).  Larger tiles
- * mean fewer workgroups and less overlap between neighbouring tiles' windows,
- * smaller ones more waves in flight; the best choice depends on the row length
- * and the GPU, which is what an autotuner measures.  0 restores the default
- * (4); other values than 0 and 2..5 give RAM_E_UNSUPPORTED.  The schedule is
- * per context and applies to later ram_shift, ram_step and ram_step_record
- * calls on shared meshes with RAM_SUM_DIRECT.  Every cell goes through the
- * same operations under any schedule; results agree to rounding, not bit for
- * bit (each variant is compiled on its own, and the compiler may fuse
- * multiply-adds differently in each). */
+ * library's fastest path).  0, the default, runs the FP32 streaming kernel
+ * (tiles of 256 destination cells, one a wave, four consecutive cells a lane;
+ * FP64 takes the general kernel with 4 nodes per thread).  2..5 select the general
+ * kernel with that many shifted nodes per thread: each workgroup of 256
+ * threads shifts 256 * items_per_thread nodes, a tile of
+ * 256 * items_per_thread - 1 destination cells (4 fewer when the residual
+ * step is fused in).  Larger tiles mean fewer workgroups and less overlap
+ * between neighbouring tiles' windows, smaller ones more waves in flight;
+ * the best choice depends on the row length and the GPU, which is what an
+ * autotuner measures.  Other values than 0 and 2..5 give RAM_E_UNSUPPORTED.
+ * The schedule is per context and applies to later ram_shift, ram_step and
+ * ram_step_record calls on shared meshes with RAM_SUM_DIRECT.  Every cell
+ * goes through the same operations under any schedule; results agree to
+ * rounding, not bit for bit (each variant is compiled on its own, and the
+ * compiler may fuse multiply-adds differently in each). */
 typedef struct {
     int32_t items_per_thread;
 } ram_schedule;
@@ -277,6 +280,24 @@ ram_status ram_step_adjoint(ram_ctx *ctx, const ram_layout *layout,
                             const void *qbar_out, void *qbar_in,
                             const double *edges, const double *v0, double dt,
                             int order, void *dvbar_accum, double *v0bar_accum);
+
+/* Which path each tile of the FP32 step with RAM_SUM_DIRECT on a shared mesh
+ * takes under the default schedule (tiles of 256 destination cells, one a
+ * wave, row by row): RAM_TILE_WINDOW (source window staged in LDS, every shifted node
+ * located by search, Eq. condition_p), RAM_TILE_UNIFORM (nodes and window in
+ * one uniformly spaced run of the mesh, where the shift is one stencil on the
+ * cell values, the FARGO limit of Section 4.1) or RAM_TILE_DIRECT (window
+ * wider than the on-chip buffer; sums from global memory).  The tiles are
+ * planned exactly as ram_step / ram_shift plan them for these arguments
+ * (with_residual: the step's two-cell halo a side).  paths: device int32
+ * array of at least n_tiles entries (n_tiles = n_rows * ceil(n_cols / 256)),
+ * capacity `cap`; *n_tiles (host) receives the count.  RAM_E_INVALID_ARG if
+ * cap is too small, RAM_E_UNSUPPORTED for layouts without a shared mesh.  For
+ * tests and profiles: the step itself never needs it. */
+typedef enum { RAM_TILE_WINDOW = 0, RAM_TILE_UNIFORM = 1, RAM_TILE_DIRECT = 2 } ram_tile_path;
+ram_status ram_step_tile_paths(ram_ctx *ctx, const ram_layout *layout, const double *edges,
+                               const double *v0, double dt, int order, int with_residual,
+                               int32_t *paths, int64_t cap, int64_t *n_tiles);
 
 /* Per-row checks of a state (not part of a step): for every row r, in FP64
  * whatever the state's dtype,

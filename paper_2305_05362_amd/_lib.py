@@ -37,6 +37,10 @@ SCANS = {"f64": RAM_SCAN_F64, "twosum": RAM_SCAN_F32_TWOSUM, "f32": RAM_SCAN_F32
 
 RAM_RECON_PLM = 1
 RAM_RECON_PPM = 2
+
+RAM_TILE_WINDOW = 0
+RAM_TILE_UNIFORM = 1
+RAM_TILE_DIRECT = 2
 RECONS = {"plm": RAM_RECON_PLM, "ppm": RAM_RECON_PPM}
 
 
@@ -97,6 +101,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ram_shift_limited": [P, LP, I, I, P, P, P, P, D],
         "ram_step_limited": [P, LP, I, I, P, P, P, P, D, I64],
         "ram_row_norms": [P, LP, I, P, P, P, P],
+        "ram_step_tile_paths": [P, LP, P, P, D, I, I, P, I64, ctypes.POINTER(I64)],
         "ram_shift_limited_adjoint": [P, LP, I, I, P, P, P, P, P, D, P],
         "ram_step_limited_record": [P, LP, I, I, P, P, P, P, P, D, I64],
         "ram_set_schedule": [P, ctypes.POINTER(Schedule)],
@@ -337,6 +342,19 @@ class Context:
             int(order), int(n_steps)))
         return q
 
+    def ram_step_tile_paths(self, rows: Rows, v0, dt: float, order: int, with_residual: bool):
+        """Path of every tile of the FP32 direct-sum step (RAM_TILE_*), an
+        int32 tensor of n_rows * ceil(n_cols / 256) entries on v0's device."""
+        self._stream()
+        nt = rows.n_rows * ((rows.n_cols + 255) // 256)
+        out = torch.empty(max(nt, 1), dtype=torch.int32, device=v0.device)
+        got = ctypes.c_int64(0)
+        check(self._lib.ram_step_tile_paths(
+            self._h, ctypes.byref(rows.layout), _dev_ptr(rows.edges, torch.float64, "edges"),
+            _dev_ptr(v0, torch.float64, "v0"), float(dt), int(order), int(bool(with_residual)),
+            _dev_ptr(out, torch.int32, "paths"), int(out.numel()), ctypes.byref(got)))
+        return out[:got.value]
+
     def ram_row_norms(self, rows: Rows, q, q_ref=None, out=None):
         """Per-row (mass, dx-weighted L1 distance to q_ref, max |q|), FP64
         tensor of shape [n_rows, 3] on q's device."""
@@ -465,6 +483,10 @@ def ram_step_limited(rows, q, v0, dv, dt, recon, n_steps):
 def ram_shift_limited_adjoint(rows, q_fwd, qbar_out, qbar_in, v0, dt, recon, v0bar=None):
     return context(qbar_out.device.index).ram_shift_limited_adjoint(
         rows, q_fwd, qbar_out, qbar_in, v0, dt, recon, v0bar)
+
+
+def ram_step_tile_paths(rows, v0, dt, order, with_residual):
+    return context(v0.device.index).ram_step_tile_paths(rows, v0, dt, order, with_residual)
 
 
 def ram_row_norms(rows, q, q_ref=None, out=None):

@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB_PATH = os.path.join(HERE, "libram.so")
 ARCH = os.environ.get("RAM_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["ram_kernels.hip", "ram_step_shared.hip", "ram_adjoint.hip",
+SOURCES = ["ram_kernels.hip", "ram_step_shared.hip", "ram_step_fast.hip", "ram_adjoint.hip",
            "ram_adjoint_shared.hip", "ram_limited.hip", "ram_reduce.hip", "ram_radial.hip",
            "ram_average4.hip", "ram_api.cpp"]
 

@@ -29,7 +29,7 @@ struct ram_ctx {
     std::vector<Graph> graphs;          // most recently used first
     // schedule of the shared-mesh step kernel with direct sums: shifted
     // nodes per thread (ram_set_schedule)
-    int items = ram::kItems;
+    int items = 0;                      // 0: the default (streaming kernel)
     // mesh-density description of the shared mesh (ram_set_mesh_density)
     ram_mesh_density density{};
 };
@@ -243,7 +243,50 @@ ram_status make_rows(ram_ctx *ctx, const ram_layout *L, const double *edges,
 int sched_items(const ram_ctx *ctx, const ram_layout *L, ram_scan scan)
 {
     const bool shared = L->edges_shared && L->n_cols > 0;
-    return (shared && scan == RAM_SUM_DIRECT) ? ctx->items : ram::kItems;
+    return (shared && scan == RAM_SUM_DIRECT && ctx->items != 0) ? ctx->items : ram::kItems;
+}
+
+// The FP32 direct-sum Lagrange step on a shared mesh at the default schedule
+// and the bucket index runs the streaming kernel (k_step_fast, tiles of
+// kFastTile cells a wave); every other combination the general shared-mesh
+// kernel.
+bool use_fast_shape(const ram_ctx *ctx, bool shared, int64_t n_cols, ram_dtype dtype,
+                    ram_scan scan)
+{
+    return shared && n_cols > 0 && dtype == RAM_F32 && scan == RAM_SUM_DIRECT &&
+           ctx->items == 0 && ctx->density.kind == RAM_DENSITY_NONE;
+}
+bool use_fast(const ram_ctx *ctx, const ram_layout *L, ram_dtype dtype, ram_scan scan)
+{
+    return use_fast_shape(ctx, L->edges_shared != 0, L->n_cols, dtype, scan);
+}
+
+// Tile size of the step kernel a call runs.
+int step_tile_of(const ram_ctx *ctx, const ram_layout *L, ram_dtype dtype, ram_scan scan,
+                 int items, bool fused)
+{
+    return use_fast(ctx, L, dtype, scan) ? ram::kFastTile : ram::step_tile_for(items, fused);
+}
+
+// Bytes of the per-tile plan (window plan, or the fast kernels' records and
+// tile lists).
+size_t plan_w_bytes(int64_t nt)
+{
+    return std::max(ram::kPlanW * sizeof(int32_t) * (size_t)nt, ram::fast_plan_bytes(nt));
+}
+
+// Plan the tiles of a shared-mesh step once per call: the fast kernels'
+// records, tile lists and node data, or the general kernel's window plan.
+hipError_t plan_shared(ram::StepArgs &a, int plan_order, bool fast, void *wlo_p, void *w_p,
+                       hipStream_t st)
+{
+    if (fast) {
+        a.fast = ram::fast_plan_at(w_p, a.rows.n_tiles);
+        return ram::launch_plan_fast(a, plan_order, a.fast, st);
+    }
+    a.plan_wlo = (const int64_t *)wlo_p;
+    a.plan_w = (const int32_t *)w_p;
+    return ram::launch_plan(a, plan_order, (int64_t *)wlo_p, (int32_t *)w_p, st);
 }
 
 // The kernel-side mesh-density index for a shared mesh of n cells.
@@ -355,13 +398,12 @@ ram_status launch_steps(ram_ctx *ctx, ram::StepArgs a, ram_dtype dtype,
         a.dens = make_density(ctx->density, a.rows.n_cols);
     hipError_t e;
     if (shared) {
-        int64_t *wlo = (int64_t *)((char *)ctx->scratch + wlo_off);
-        int32_t *w = (int32_t *)((char *)ctx->scratch + w_off);
         const int plan_order = recon == 0 ? order : (recon == RAM_RECON_PLM ? 3 : 5);
-        e = ram::launch_plan(a, plan_order, wlo, w, ctx->stream);
+        const bool fast = recon == 0 &&
+                          use_fast_shape(ctx, a.rows.shared != 0, a.rows.n_cols, dtype, scan);
+        e = plan_shared(a, plan_order, fast, (char *)ctx->scratch + wlo_off,
+                        (char *)ctx->scratch + w_off, ctx->stream);
         if (e != hipSuccess) return hip_fail(e, "window plan launch");
-        a.plan_wlo = wlo;
-        a.plan_w = w;
     }
     auto one = [&](const ram::StepArgs &s, hipStream_t st) {
         if (recon) return ram::launch_step_shared_limited(s, f64, recon, st);
@@ -495,8 +537,8 @@ ram_status ram_set_schedule(ram_ctx *ctx, const ram_schedule *sched)
 {
     if (!ctx) return fail(RAM_E_INVALID_ARG, "null context");
     if (!sched) return fail(RAM_E_INVALID_ARG, "null schedule");
-    const int items = sched->items_per_thread == 0 ? ram::kItems : sched->items_per_thread;
-    if (!ram::valid_items(items))
+    const int items = sched->items_per_thread;
+    if (items != 0 && !ram::valid_items(items))
         return fail(RAM_E_UNSUPPORTED, "items_per_thread must be 0 or 2..5 (got %d)",
                     (int)sched->items_per_thread);
     ctx->items = items;
@@ -578,10 +620,11 @@ ram_status ram_shift(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
     if ((st = enter(ctx)) != RAM_OK) return st;
     const int items = sched_items(ctx, layout, scan);
     Carve cv;
-    RowsPlan rp = plan_rows(cv, layout, ram::step_tile_for(items, false), order);
+    RowsPlan rp = plan_rows(cv, layout, step_tile_of(ctx, layout, dtype, scan, items, false),
+                            order);
     rp.uniform = wants_uniform(dtype, scan);
     const int64_t nt = tiles_of(layout, rp.tile);
-    const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(ram::kPlanW * sizeof(int32_t) * nt);
+    const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(plan_w_bytes(nt));
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
     ram::StepArgs a;
     if ((st = make_rows(ctx, layout, edges, rp, a.rows)) != RAM_OK) return st;
@@ -641,10 +684,11 @@ ram_status ram_step(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
     Carve cv;
     const size_t tmp_off = cv.take(state_bytes);
     const int items = sched_items(ctx, layout, scan);
-    RowsPlan rp = plan_rows(cv, layout, ram::step_tile_for(items, dv != nullptr), order);
+    RowsPlan rp = plan_rows(cv, layout,
+                            step_tile_of(ctx, layout, dtype, scan, items, dv != nullptr), order);
     rp.uniform = wants_uniform(dtype, scan);
     const int64_t nt = tiles_of(layout, rp.tile);
-    const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(ram::kPlanW * sizeof(int32_t) * nt);
+    const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(plan_w_bytes(nt));
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
     ram::StepArgs a;
     std::memset(&a, 0, sizeof(a));        // the graph key compares raw bytes
@@ -983,10 +1027,13 @@ ram_status setup_row_step(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtyp
     rs.f64 = dtype == RAM_F64;
     rs.items = recon ? ram::kItems : sched_items(ctx, layout, scan);
     const int plan_order = recon == 0 ? order : (recon == RAM_RECON_PLM ? 3 : 5);
-    RowsPlan rp = plan_rows(cv, layout, ram::step_tile_for(rs.items, dv != nullptr), plan_order);
+    const bool fast = recon == 0 && use_fast(ctx, layout, dtype, scan);
+    RowsPlan rp = plan_rows(cv, layout,
+                            fast ? ram::kFastTile : ram::step_tile_for(rs.items, dv != nullptr),
+                            plan_order);
     rp.uniform = dtype == RAM_F32 && (recon != 0 || scan == RAM_SUM_DIRECT);
     const int64_t nt = tiles_of(layout, rp.tile);
-    const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(ram::kPlanW * sizeof(int32_t) * nt);
+    const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(plan_w_bytes(nt));
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
     std::memset(&rs.a, 0, sizeof(rs.a));   // graph keys compare raw bytes
     if ((st = make_rows(ctx, layout, edges, rp, rs.a.rows)) != RAM_OK) return st;
@@ -995,12 +1042,9 @@ ram_status setup_row_step(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtyp
     rs.a.dt = dt;
     rs.shared = rs.a.rows.has_tab != 0 && rs.a.rows.n_cols > 0;
     if (rs.shared) {
-        int64_t *wlo = (int64_t *)((char *)ctx->scratch + wlo_off);
-        int32_t *w = (int32_t *)((char *)ctx->scratch + w_off);
-        hipError_t e = ram::launch_plan(rs.a, plan_order, wlo, w, ctx->stream);
+        hipError_t e = plan_shared(rs.a, plan_order, fast, (char *)ctx->scratch + wlo_off,
+                                   (char *)ctx->scratch + w_off, ctx->stream);
         if (e != hipSuccess) return hip_fail(e, "window plan launch");
-        rs.a.plan_wlo = wlo;
-        rs.a.plan_w = w;
         if (scan == RAM_SUM_DIRECT && recon == 0)
             rs.a.dens = make_density(ctx->density, rs.a.rows.n_cols);
     }
@@ -1139,6 +1183,45 @@ ram_status ram_step_point4(ram_ctx *ctx, const ram_layout *layout, ram_dtype dty
     return run_graphed(ctx, key_of(rs.a, RC, extra, t1), n_steps, loop);
 }
 
+ram_status ram_step_tile_paths(ram_ctx *ctx, const ram_layout *layout, const double *edges,
+                               const double *v0, double dt, int order, int with_residual,
+                               int32_t *paths, int64_t cap, int64_t *n_tiles)
+{
+    ram_status st;
+    g_last_error.clear();
+    if ((st = check_layout(layout, edges)) != RAM_OK) return st;
+    if ((st = check_order(layout, order)) != RAM_OK) return st;
+    if ((st = check_dt(dt)) != RAM_OK) return st;
+    if (!layout->edges_shared || layout->n_cols <= 0)
+        return fail(RAM_E_UNSUPPORTED, "tile paths exist for shared meshes only");
+    if (!v0 || !paths || !n_tiles) return fail(RAM_E_INVALID_ARG, "null v0, paths or n_tiles");
+    const int64_t nt = tiles_of(layout, ram::kFastTile);
+    *n_tiles = nt;
+    if (cap < nt) return fail(RAM_E_INVALID_ARG, "paths holds %lld entries, %lld tiles",
+                              (long long)cap, (long long)nt);
+    if ((st = enter(ctx)) != RAM_OK) return st;
+    Carve cv;
+    RowsPlan rp = plan_rows(cv, layout, ram::kFastTile, order);
+    rp.uniform = true;
+    const size_t rec_off = cv.take(ram::fast_plan_bytes(nt));
+    if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
+    ram::StepArgs a;
+    std::memset(&a, 0, sizeof(a));
+    if ((st = make_rows(ctx, layout, edges, rp, a.rows)) != RAM_OK) return st;
+    a.v0 = v0;
+    a.dt = dt;
+    // only its being non-null matters to the plan (the halo)
+    a.dv = with_residual ? (const void *)edges : nullptr;
+    const ram::FastPlan fp = ram::fast_plan_at((char *)ctx->scratch + rec_off, nt);
+    hipError_t e = ram::launch_plan_fast(a, order, fp, ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "tile plan launch");
+    // the kind is the record's first word
+    e = hipMemcpy2DAsync(paths, sizeof(int32_t), fp.rec, sizeof(ram::FastTile), sizeof(int32_t),
+                         (size_t)nt, hipMemcpyDeviceToDevice, ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "tile path copy");
+    return RAM_OK;
+}
+
 ram_status ram_row_norms(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
                          const void *q, const void *q_ref, const double *edges,
                          double *out)
@@ -1248,10 +1331,13 @@ ram_status ram_step_record(ram_ctx *ctx, const ram_layout *layout,
     const size_t state_bytes = elem_size(dtype) * (size_t)layout_cells(layout);
     Carve cv;
     const int items = sched_items(ctx, layout, scan);
-    RowsPlan rp = plan_rows(cv, layout, ram::step_tile_for(items, dv != nullptr), order);
+    const bool fast = use_fast(ctx, layout, dtype, scan);
+    RowsPlan rp = plan_rows(cv, layout,
+                            fast ? ram::kFastTile : ram::step_tile_for(items, dv != nullptr),
+                            order);
     rp.uniform = wants_uniform(dtype, scan);
     const int64_t nt = tiles_of(layout, rp.tile);
-    const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(ram::kPlanW * sizeof(int32_t) * nt);
+    const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(plan_w_bytes(nt));
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
     ram::StepArgs a;
     if ((st = make_rows(ctx, layout, edges, rp, a.rows)) != RAM_OK) return st;
@@ -1262,12 +1348,9 @@ ram_status ram_step_record(ram_ctx *ctx, const ram_layout *layout,
     const bool shared = a.rows.has_tab != 0 && a.rows.n_cols > 0;
     hipError_t e;
     if (shared) {
-        int64_t *wlo = (int64_t *)((char *)ctx->scratch + wlo_off);
-        int32_t *w = (int32_t *)((char *)ctx->scratch + w_off);
-        e = ram::launch_plan(a, order, wlo, w, ctx->stream);
+        e = plan_shared(a, order, fast, (char *)ctx->scratch + wlo_off,
+                        (char *)ctx->scratch + w_off, ctx->stream);
         if (e != hipSuccess) return hip_fail(e, "window plan launch");
-        a.plan_wlo = wlo;
-        a.plan_w = w;
     }
     for (int64_t k = 0; k < n_steps; ++k) {
         a.q_in = (const char *)q_traj + k * state_bytes;

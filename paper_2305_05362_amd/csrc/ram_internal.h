@@ -137,6 +137,65 @@ __host__ __device__ inline double bump_prim(double t, const MeshDensity &d)
     return copysign(v, t);
 }
 
+// The FP32 step on a shared mesh with direct sums (k_step_fast): tiles of
+// kFastTile destination cells, one a wave (four consecutive cells a lane),
+// each with a source window of at most kFastWin cells in LDS.  One record per
+// tile, planned once per call (k_plan_fast), read with scalar loads.
+constexpr int kFastTile = 256;
+constexpr int kFastWin = 768;
+enum FastKind { kFastWindow = 0, kFastUniform = 1, kFastDirect = 2 };
+struct FastTile {
+    int32_t kind;            // FastKind
+    int32_t w;               // window length, cells
+    int32_t base;            // window start mod n
+    int32_t wlo_lo, wlo_hi;  // extended source index of the window start
+    float cc[6];             // uniform: weights of the (order+1)-point stencil
+    float dx, hinv, dxinv;   // uniform: the run's cell size, 1/centre gap, 1/size
+    int32_t pad[2];
+};
+static_assert(sizeof(FastTile) == 64, "one record a tile");
+// The tiles of one call: their records (rec[0 .. n_tiles)), then the same
+// records compacted (rec[n_tiles ..)): the uniform tiles in tile order
+// (totals[0] of them), then the others in tile order, each with its tile id in
+// pad[0]; the per-1024-tile counts the compacted order is built from; and for
+// the k-th non-uniform tile, the source-window index (jc) and position in its
+// cell (theta, FP32) of each of its shifted nodes, kFastNodes entries a tile
+// (the shift of a row is the same at every step of a call).
+constexpr int kFastNodes = kFastTile + 8;
+struct FastPlan {
+    FastTile *rec = nullptr;
+    int32_t *counts = nullptr;
+    int32_t *totals = nullptr;
+    float *theta = nullptr;
+    int16_t *jc = nullptr;
+};
+// Device bytes of the plan of n_tiles tiles (each piece 256-byte aligned).
+inline size_t fast_plan_bytes(int64_t n_tiles)
+{
+    auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
+    const size_t nn = (size_t)n_tiles * kFastNodes;
+    return al(2 * sizeof(FastTile) * (size_t)n_tiles) +
+           al(sizeof(int32_t) * (size_t)((n_tiles + 1023) / 1024)) + al(2 * sizeof(int32_t)) +
+           al(sizeof(float) * nn) + al(sizeof(int16_t) * nn);
+}
+inline FastPlan fast_plan_at(void *mem, int64_t n_tiles)
+{
+    auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
+    const size_t nn = (size_t)n_tiles * kFastNodes;
+    char *p = (char *)mem;
+    FastPlan f;
+    f.rec = (FastTile *)p;
+    p += al(2 * sizeof(FastTile) * (size_t)n_tiles);
+    f.counts = (int32_t *)p;
+    p += al(sizeof(int32_t) * (size_t)((n_tiles + 1023) / 1024));
+    f.totals = (int32_t *)p;
+    p += al(2 * sizeof(int32_t));
+    f.theta = (float *)p;
+    p += al(sizeof(float) * nn);
+    f.jc = (int16_t *)p;
+    return f;
+}
+
 // Bulk shift, optionally fused with the residual step (dv != null).
 struct StepArgs {
     Rows rows;
@@ -150,6 +209,7 @@ struct StepArgs {
                                         // [n_tiles + tile]: start mod n
     void *q_mid = nullptr;              // optional: the state after the shift
     MeshDensity dens;                   // shared mesh, direct sums: closed-form index
+    FastPlan fast;                      // FP32 direct sums: the k_step_fast tiles (rec set)
 };
 
 // Radial transport of a polar grid (rows = radii): q [n_rows][n_cols], u on
@@ -245,6 +305,13 @@ hipError_t launch_plan(const StepArgs &a, int order, int64_t *wlo, int32_t *w,
                        hipStream_t stream);
 hipError_t launch_step_shared(const StepArgs &a, bool f64, int scan, int order,
                               int items, hipStream_t stream);
+// The FP32 direct-sum step on a shared mesh: plan the tiles into `plan`
+// (R.tile == kFastTile, tables with the uniform-run counts; records, then the
+// two tile lists), then per step the uniform-tile and the searching-tile
+// kernels (a.fast set).
+hipError_t launch_plan_fast(const StepArgs &a, int order, const FastPlan &plan,
+                            hipStream_t stream);
+hipError_t launch_step_fast(const StepArgs &a, int order, hipStream_t stream);
 hipError_t launch_residual(const ResidualArgs &a, bool f64,
                            hipStream_t stream);
 hipError_t launch_shift_adjoint(const ShiftAdjArgs &a, bool f64, int order,

@@ -1,0 +1,755 @@
+// ram_step_fast.hip -- the FP32 RAM step on rows that share one mesh, with the
+// cumulative differences summed directly from the window masses (gfx950).
+//
+// Same computation as k_step_sh with direct sums (bulk shift of Section 3,
+// Steps 1-3, Eqs. Qmass_i, condition_p, mass_shift_algo, step3, then the
+// residual upwind step with the van Leer slope of Section 3.1), laid out for
+// streaming rather than for the node search:
+//
+//   * one tile of kFastTile = 256 destination cells per wave, four
+//     consecutive cells a lane, whose residual-velocity loads and final
+//     stores are 16-byte vector accesses; each wave has its own LDS and never
+//     waits on the other waves of its workgroup (no workgroup barrier);
+//   * everything about a tile that does not change between steps is planned
+//     once per call: its source window, whether it lies in one of the mesh's
+//     uniform runs (then the stencil weights and the run's geometry), the
+//     records sorted into the uniform tiles and the others, and for the
+//     others each shifted node's window index and position in its cell;
+//   * a tile in a uniform run (every node of the tile in the next source cell
+//     at one theta) needs no search and no masses: the shifted value of a
+//     cell is a fixed (P+1)-point stencil on the window's cell values.  Those
+//     tiles run in their own kernel (k_step_uni, 26 registers, eight waves a
+//     SIMD) as straight-line code: the window and face loads issued together,
+//     the window through the wave's LDS once, each lane reading the thirteen
+//     values its eight cells need (its four and the residual's two-cell halo
+//     a side) with 16-byte LDS reads, and the residual on registers;
+//   * the other tiles (k_step_gen) stage the window masses M = Q dx in LDS,
+//     read their nodes' planned window index and theta, then each node's
+//     stencil record for its Lagrange weights and partial integral, then the
+//     destination masses one cell per lane, and the same register residual on
+//     four consecutive cells; a tile whose window exceeds the LDS capacity
+//     sums from global memory.
+// Tiles of 256 cells keep the searching tiles to the cells near the mesh's
+// non-uniform stretches.
+#include "ram_device.h"
+
+namespace ram {
+namespace {
+
+using namespace dev;
+
+constexpr int kFT = kFastTile;                      // destination cells per tile (wave)
+constexpr int kLanes = 64;
+constexpr int kWaves = kBlock / kLanes;             // tiles per workgroup
+constexpr int kFPad = 16;                           // slack for vector over-reads
+
+// LDS of one wave.  The window (values or masses), the direct path's extended
+// node indices and the shifted state share bytes (the wave moves from one to
+// the next after a wave-level fence); node partials and their window indices
+// have arrays of their own.
+struct WaveLds {
+    static constexpr int nodes = kFT + 5 + 3;       // up to 261 nodes, padded
+    static constexpr size_t win = sizeof(float) * (kFastWin + kFPad);
+    static constexpr size_t gidx = sizeof(int64_t) * nodes;
+    static constexpr size_t shifted = sizeof(float) * (kFT + 4 + kFPad);
+    static constexpr size_t u0 = win > gidx ? win : gidx;
+    static constexpr size_t u = u0 > shifted ? u0 : shifted;
+};
+
+// Every lane's LDS writes visible to the whole wave (a wave executes its LDS
+// instructions in order; the fences keep the compiler from moving accesses
+// across).
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The record of one tile: which path, its window, and for a uniform tile the
+// stencil and the run's geometry.  One thread per tile; the node search is the
+// shared-mesh one of the step kernels (bucket index, Eq. condition_p).
+template <int P>
+__global__ __launch_bounds__(64) void k_plan_fast(StepArgs a, FastTile *out)
+{
+    constexpr int LO = (P - 1) / 2;
+    const int64_t tile = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const Rows &R = a.rows;
+    if (tile >= R.n_tiles) return;
+    const int n = (int)R.n_cols;
+    const int64_t tpr = (n + kFT - 1) / kFT;
+    const int64_t row = tile / tpr;
+    const int i0 = (int)(tile - row * tpr) * kFT;
+    const int H = a.dv ? 2 : 0;
+    const int nd = min(kFT, n - i0);
+    const double *x = R.edges;
+    const double len = x[n] - x[0];
+    const RowShift rs = row_shift(a.v0[row] * a.dt, len, R.tab.scal[1]);
+    double xt0;
+    int c0;
+    const int64_t g0 = node_locate(x, n, R.tab, rs, i0 - H, xt0, c0);
+    const int64_t g1 = node_index(x, n, R.tab, rs, len, i0 + nd + H);
+    const int64_t wide = g1 - g0 + P;
+    const int64_t wlo = g0 - LO;
+    FastTile ft;
+    ft.kind = kFastWindow;
+    ft.w = (wide >= P && wide <= kFastWin) ? (int)wide : -1;
+    const int64_t kk = wlo >= 0 ? wlo / n : -((-wlo + n - 1) / n);
+    ft.base = (int)(wlo - kk * n);
+    ft.wlo_lo = (int32_t)(uint32_t)((uint64_t)wlo & 0xffffffffull);
+    ft.wlo_hi = (int32_t)((uint64_t)wlo >> 32);
+    for (int d = 0; d < 6; ++d) ft.cc[d] = 0.0f;
+    ft.dx = ft.hinv = ft.dxinv = 0.0f;
+    ft.pad[0] = (int32_t)tile;
+    ft.pad[1] = -1;
+    if (ft.w < 0) ft.kind = kFastDirect;
+    // uniform: the cells on both sides of the tile's nodes and its whole source
+    // window lie in one uniform run of the mesh, and the window holds one
+    // source cell per node plus the stencil, so node i0 - H + k sits in window
+    // cell LO + k at the first node's theta (rows shorter than a full tile's
+    // window stay with the other kernel, whose windows may wrap many times)
+    auto in_run = [&](const int32_t *pre) {
+        return nonu_count(pre, n, i0 - H - 1, i0 + nd + H + 1) == 0 &&
+               nonu_count(pre, n, wlo, wlo + wide) == 0;
+    };
+    if (ft.kind == kFastWindow && R.tab.nonu && wide == nd + 2 * H + P &&
+        n >= kFT + 2 * H + P && (in_run(R.tab.nonu) || in_run(R.tab.nonu_min))) {
+        ft.kind = kFastUniform;
+        const double th = (xt0 - x[c0]) * R.tab.dxinv[c0];
+        double cc[P + 1];
+        uniform_stencil<double, P>(th, cc);
+        for (int d = 0; d <= P; ++d) ft.cc[d] = (float)cc[d];
+        const float2 rr = R.tab.rrf[i0];
+        ft.dx = rr.x;
+        ft.hinv = rr.y;
+        ft.dxinv = R.tab.dxinvf[i0];
+    }
+    out[tile] = ft;
+}
+
+__device__ inline int wrap1f(int j, int n) { return j < 0 ? j + n : (j >= n ? j - n : j); }
+
+// Residual step on four consecutive cells of a lane from the shifted state
+// s[0..7] of cells i0+4l-2 .. i0+4l+5 (Section 3.1 reading R7): fluxes on the
+// five faces i0+4l .. i0+4l+4 with the upwind cell's van Leer slope and the
+// swept-interval average, then the conservative update of the four cells.
+// rr(c) gives (dx, 1/centre gap to the right) of s-index c, dxi(k) 1/dx of
+// own cell k.
+template <typename RR, typename DXI>
+__device__ __forceinline__ void residual4(const float *s, const float *dvv, float dt, RR rr,
+                                          DXI dxi, float *out)
+{
+    float F[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const float v = dvv[k];
+        const bool up = v >= 0.0f;
+        // upwind cell: s-index k+1 (left of the face) or k+2
+        const float qm = up ? s[k] : s[k + 1];
+        const float q0 = up ? s[k + 1] : s[k + 2];
+        const float qp = up ? s[k + 2] : s[k + 3];
+        const float2 rc = up ? rr(k + 1) : rr(k + 2);
+        const float gm = up ? rr(k).y : rr(k + 1).y;
+        const float dp = (qp - q0) * rc.y;
+        const float dm = (q0 - qm) * gm;
+        const float sig = (dp * dm <= 0.0f) ? 0.0f : harmonic2(dp, dm);
+        const float half = up ? 0.5f * (rc.x - v * dt) : -0.5f * (rc.x + v * dt);
+        F[k] = v * (q0 + sig * half);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) out[k] = s[k + 2] - dt * (F[k + 1] - F[k]) * dxi(k);
+}
+
+// Tile id -> row and first cell (tiles of kFT cells, row by row).
+struct TilePos {
+    int row, i0, nd;
+    bool inner;          // the tile and its halo do not wrap the row
+};
+__device__ inline TilePos tile_pos(int tile, int n, int H)
+{
+    const int tpr = (n + kFT - 1) / kFT;
+    TilePos p;
+    p.row = tile / tpr;
+    p.i0 = (tile - p.row * tpr) * kFT;
+    p.nd = min(kFT, n - p.i0);
+    p.inner = (p.i0 - H >= 0) && (p.i0 + p.nd + H < n);
+    return p;
+}
+
+// Residual velocity of faces i0+4l .. i0+4l+4 of a row (face n is face 0);
+// lanes past the tile read its last faces again (every load issued, no
+// branch).
+template <bool VEC>
+__device__ __forceinline__ void load_faces(const float *dvp, int n, int i0, int nd, int c4,
+                                           float *dvv)
+{
+    const int cc = min(c4, nd - 1);
+    if constexpr (VEC) {
+        const float4 v4 = *(const float4 *)(dvp + i0 + (cc & ~3));
+        dvv[0] = v4.x;
+        dvv[1] = v4.y;
+        dvv[2] = v4.z;
+        dvv[3] = v4.w;
+    } else {
+        // faces up to the tile's right face i0 + nd
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int f = i0 + min(cc + k, nd);
+            dvv[k] = dvp[f >= n ? f - n : f];
+        }
+    }
+    const int f4 = i0 + min(cc + 4, nd);
+    dvv[4] = dvp[f4 >= n ? f4 - n : f4];
+}
+
+template <bool VEC>
+__device__ __forceinline__ void store_cells(float *qo, int i0, int nd, int c4, const float *o)
+{
+    if (c4 >= nd) return;
+    if constexpr (VEC) {
+        *(float4 *)(qo + i0 + c4) = make_float4(o[0], o[1], o[2], o[3]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (c4 + k < nd) qo[i0 + c4 + k] = o[k];
+    }
+}
+
+// Record i, read through the constant address space: with a wave-uniform i
+// these are scalar loads (the host pass, which only checks device code, reads
+// it plainly).
+__device__ inline FastTile load_rec(const FastTile *rec, int i)
+{
+    FastTile r;
+#if defined(__HIP_DEVICE_COMPILE__)
+    typedef const __attribute__((address_space(4))) int32_t *CI;
+    const CI c = (CI)(rec + i);
+    int32_t *o = (int32_t *)&r;
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(FastTile) / 4); ++k) o[k] = c[k];
+#else
+    r = rec[i];
+#endif
+    return r;
+}
+
+// Wave index inside the workgroup, in a scalar register (so that what it
+// selects is read with scalar loads).
+__device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane((int)threadIdx.x / kLanes); }
+
+// ---------------------------------------------------------------------------
+// A tile in a uniform run of the mesh: straight-line code (clamped indices
+// instead of guards), the window's and the faces' loads issued together.
+// ---------------------------------------------------------------------------
+
+constexpr int kUniWin = 5 * kLanes + 16;            // window slots + over-read slack, floats
+
+// A tile in a uniform run.  VEC: rows of a multiple of four cells (16-byte
+// aligned vector loads of the residual velocity, vector stores of the
+// result).  Rows need at least kFT + 2H + P cells (k_plan_fast sends shorter
+// ones to the other path), so a window wraps the row at most once.
+template <int P, int H, bool VEC>
+__device__ __forceinline__ void uniform_tile(const StepArgs &a, const FastTile &r, float *sw,
+                                             int t)
+{
+    constexpr int NV = 4 + 2 * H;                    // shifted cells a lane reads
+    constexpr int NW = (NV + P + 3) / 4 * 4;         // window values, whole float4s
+    constexpr int NUW = (kFT + 2 * H + P + kLanes - 1) / kLanes;  // window slots a lane
+    static_assert(NUW * kLanes <= kUniWin && 4 * (kLanes - 1) + NW <= kUniWin, "window");
+    const int n = (int)a.rows.n_cols;
+    const float dt = (float)a.dt;
+    const int c4 = 4 * t;
+    const TilePos p = tile_pos(r.pad[0], n, H);
+    const int64_t qoff = (int64_t)p.row * n;
+
+    // window cells j = t + 64k (clamped into the window: the extra lanes read
+    // its last cell again) and face velocities i0+4l .. i0+4l+4 (clamped into
+    // the tile, face n is face 0)
+    float wv[NUW];
+    {
+        const float *q = (const float *)a.q_in + qoff;
+#pragma unroll
+        for (int k = 0; k < NUW; ++k) {
+            int mm = r.base + min(t + k * kLanes, r.w - 1);
+            mm = mm >= n ? mm - n : mm;
+            wv[k] = q[mm];
+        }
+    }
+    float dvv[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    if constexpr (H != 0) load_faces<VEC>((const float *)a.dv + qoff, n, p.i0, p.nd, c4, dvv);
+#pragma unroll
+    for (int k = 0; k < NUW; ++k) sw[t + k * kLanes] = wv[k];
+    wave_sync();
+    // shifted cells ci = 4l .. 4l+NV-1 of the tile (cell i0-H+ci) from window
+    // cells ci .. ci+P
+    float win[NW];
+#pragma unroll
+    for (int v = 0; v < NW / 4; ++v) {
+        const float4 w4 = *(const float4 *)(sw + c4 + 4 * v);
+        win[4 * v] = w4.x;
+        win[4 * v + 1] = w4.y;
+        win[4 * v + 2] = w4.z;
+        win[4 * v + 3] = w4.w;
+    }
+    float s[NV];
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+        float v = 0.0f;
+#pragma unroll
+        for (int d = 0; d <= P; ++d) v += r.cc[d] * win[c + d];
+        s[c] = v;
+    }
+    float *qo = (float *)a.q_out + qoff;
+    if constexpr (H == 0) {
+        store_cells<VEC>(qo, p.i0, p.nd, c4, s);
+    } else {
+        if (a.q_mid && c4 < p.nd) {
+            float *qm = (float *)a.q_mid + qoff;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (c4 + k < p.nd) qm[p.i0 + c4 + k] = s[k + 2];
+        }
+        const float2 g = make_float2(r.dx, r.hinv);
+        const float dxi = r.dxinv;
+        float o[4];
+        residual4(s, dvv, dt, [&](int) { return g; }, [&](int) { return dxi; }, o);
+        store_cells<VEC>(qo, p.i0, p.nd, c4, o);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Every other tile.  Its nodes' source cells do not change between the steps
+// of a call, so k_node_plan locates them once (bucket index, Eq.
+// condition_p) and keeps each node's window index and theta; per step a wave
+// then needs two round trips to memory: the window, node data, faces and
+// geometry together, then the source cells' stencil records.
+// ---------------------------------------------------------------------------
+
+// The k-th non-uniform tile's nodes (k = list position - totals[0]): window
+// index and FP32 theta of nodes i0-H .. i0+nd+H; a node outside the window
+// (not expected: the plan sized it from the end nodes) turns the tile into a
+// direct one.  One wave per tile.
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_node_plan(StepArgs a)
+{
+    constexpr int LO = (P - 1) / 2;
+    constexpr int NS = (kFT + 5 + kLanes - 1) / kLanes;
+    const Rows &R = a.rows;
+    const int nu = a.fast.totals[0];
+    const int nt = (int)R.n_tiles;
+    const int k = (int)blockIdx.x * kWaves + wave_id();
+    if (nu + k >= nt) return;
+    FastTile *crec = a.fast.rec + nt;
+    const FastTile ft = load_rec(crec, nu + k);
+    if (ft.kind != kFastWindow) return;
+    const int H = a.dv ? 2 : 0;
+    const int t = threadIdx.x % kLanes;
+    const MeshTab &tb = R.tab;
+    const int n = (int)R.n_cols;
+    const TilePos tp = tile_pos(ft.pad[0], n, H);
+    const int NE = tp.nd + 2 * H + 1;
+    const double *x = R.edges;
+    const double x0 = x[0], xN = x[n];
+    const double len = xN - x0;
+    const RowShift rs = row_shift(a.v0[tp.row] * a.dt, len, tb.scal[1]);
+    const int64_t wlo = (int64_t)(((uint64_t)(uint32_t)ft.wlo_hi << 32) | (uint32_t)ft.wlo_lo);
+    const int jbase = (int)(rs.kf0 * (int64_t)n - wlo);
+    float *th = a.fast.theta + (int64_t)k * kFastNodes;
+    int16_t *jcw = a.fast.jc + (int64_t)k * kFastNodes;
+    bool ok = true;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int m = t + s * kLanes;
+        if (m < NE) {
+            int e = tp.i0 - H + m;
+            const int kx = e < 0 ? -n : (e >= n ? n : 0);
+            e -= kx;
+            const NodePos np = node_pos(x[e], rs, x0, xN, tb.scal[0], tb.scal[2], tb.nb);
+            const double2 nx = tb.bnext[np.b];
+            int c = cell_from_bucket(tb.bucket[np.b], nx, np.xt);
+            if (np.xt >= nx.y) c = cell_walk(x, n, c, np.xt);
+            const CellRec<float> &rc = RecT<float>::get(tb)[c];
+            const int j = c + np.dk * n + kx + jbase;
+            ok = ok && j >= LO && j + P - LO <= ft.w;
+            th[m] = (float)((np.xt - rc.xc) * rc.dxinv);
+            jcw[m] = (int16_t)min(max(j, 0), kFastWin);
+        }
+    }
+    if (!__all(ok ? 1 : 0) && t == 0) a.fast.rec[ft.pad[0]].kind = kFastDirect;
+}
+
+template <int P, int H, bool VEC>
+__device__ __forceinline__ void general_tile(const StepArgs &a, const FastTile &ft,
+                                             unsigned char *su, float *sell, short *sjc, int t)
+{
+    constexpr int LO = (P - 1) / 2;
+    constexpr int NV = 4 + 2 * H;                    // shifted cells a lane reads
+    constexpr int NCS = (kFT + 2 * H + kLanes - 1) / kLanes;      // cell slots
+    constexpr int NS = (kFT + 2 * H + 1 + kLanes - 1) / kLanes;   // node slots
+    const Rows &R = a.rows;
+    float *sw = (float *)su;                         // window masses
+    int64_t *sg = (int64_t *)su;                     // direct path: node indices
+    float *sq = (float *)su;                         // shifted state
+    const int k = ft.pad[1];                         // position among the other tiles
+    const MeshTab &tb = R.tab;
+    const int n = (int)R.n_cols;
+    const int c4 = 4 * t;
+    const float dt = (float)a.dt;
+    const TilePos tp = tile_pos(ft.pad[0], n, H);
+    const int row = tp.row, i0 = tp.i0, nd = tp.nd;
+    const bool inner = tp.inner;
+    const int NC = nd + 2 * H;
+    const int NE = NC + 1;
+    const int64_t qoff = (int64_t)row * n;
+    const float *q = (const float *)a.q_in + qoff;
+    float *qo = (float *)a.q_out + qoff;
+    float *qmid = a.q_mid ? (float *)a.q_mid + qoff : nullptr;
+    const int W = ft.w, base = ft.base;
+    const bool windowed = ft.kind == kFastWindow;
+
+    if (windowed) {
+        // ---- round trip 1: window masses, the nodes' window index and theta
+        const float *thp = a.fast.theta + (int64_t)k * kFastNodes;
+        const int16_t *jcp = a.fast.jc + (int64_t)k * kFastNodes;
+        float thv[NS];
+        int jv[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int m = min(t + s * kLanes, NE - 1);
+            thv[s] = thp[m];
+            jv[s] = jcp[m];
+        }
+        // window masses M = Q dx, four slots of loads at a time, every load
+        // issued (clamped into the window) so that no per-slot branch makes
+        // the wave wait for each load in turn
+        const int nws = (W + kLanes - 1) / kLanes;
+        if (W + base <= 2 * n) {
+            for (int r0 = 0; r0 < nws; r0 += 4) {
+                float wq[4], wd[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    int mm = base + min(t + (r0 + u) * kLanes, W - 1);
+                    mm = mm >= n ? mm - n : mm;
+                    wq[u] = q[mm];
+                    wd[u] = tb.dxf[mm];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (r0 + u < nws) sw[t + (r0 + u) * kLanes] = wq[u] * wd[u];
+            }
+        } else {
+            // rows shorter than the window: it wraps several times
+            for (int j = t; j < W; j += kLanes) {
+                const int mm = wrap_small(base + j, n);
+                sw[j] = q[mm] * tb.dxf[mm];
+            }
+        }
+        wave_sync();
+        // ---- round trip 2: each node's stencil record, then its partial
+        // integral C~(x) - C(c) from the masses between (summed outward)
+        // (the lanes past the last node repeat it: same values, same LDS slot)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int m = min(t + s * kLanes, NE - 1);
+            {
+                const int j = jv[s];
+                int c = base + j;
+                c = c >= n ? c - n : c;
+                c = c >= n ? wrap_small(c, n) : c;
+                const CellRec<float> &rc = RecT<float>::get(tb)[c];
+                float wk[P + 1];
+                {
+                    const float th = thv[s];
+                    float tt[P + 1], pre[P + 1], suf[P + 1];
+#pragma unroll
+                    for (int b = 0; b <= P; ++b) tt[b] = th - rc.th[b];
+                    pre[0] = 1.0f;
+#pragma unroll
+                    for (int b = 1; b <= P; ++b) pre[b] = pre[b - 1] * tt[b - 1];
+                    suf[P] = 1.0f;
+#pragma unroll
+                    for (int b = P - 1; b >= 0; --b) suf[b] = suf[b + 1] * tt[b + 1];
+#pragma unroll
+                    for (int b = 0; b <= P; ++b) wk[b] = rc.rd[b] * (pre[b] * suf[b]);
+                }
+                float ell = 0.0f, up = 0.0f, dn = 0.0f;
+#pragma unroll
+                for (int b = LO + 1; b <= P; ++b) {
+                    up += sw[j + b - LO - 1];
+                    ell += wk[b] * up;
+                }
+#pragma unroll
+                for (int b = LO - 1; b >= 0; --b) {
+                    dn += sw[j - LO + b];
+                    ell -= wk[b] * dn;
+                }
+                sell[m] = ell;
+                sjc[m] = (short)j;
+            }
+        }
+        wave_sync();
+    } else {
+        // window wider than the LDS buffer: nodes located here, partial
+        // integrals and whole-cell sums from global memory, in FP64
+        const double *x = R.edges;
+        const double x0 = x[0], xN = x[n];
+        const double len = xN - x0;
+        const double sh = a.v0[row] * a.dt;
+        const RowShift rs = row_shift(sh, len, tb.scal[1]);
+        for (int m = t; m < NE; m += kLanes) {
+            int e = i0 - H + m;
+            const int kx = e < 0 ? -n : (e >= n ? n : 0);
+            e -= kx;
+            const NodePos np = node_pos(x[e], rs, x0, xN, tb.scal[0], tb.scal[2], tb.nb);
+            const double2 nx = tb.bnext[np.b];
+            int c = cell_from_bucket(tb.bucket[np.b], nx, np.xt);
+            if (np.xt >= nx.y) c = cell_walk(x, n, c, np.xt);
+            const int64_t g = (int64_t)c + (rs.kf0 + np.dk) * (int64_t)n + kx;
+            sg[m] = g;
+            sell[m] = (float)direct_partial<float, P>(x, q, n, len, sh, tb.scal[1], i0 - H + m, g);
+        }
+        wave_sync();
+    }
+
+    // ---- destination cells, one per lane: whole cells + two partials, / dx --
+    // (the lanes past the last cell repeat it: same values, same places)
+    float qs[NCS];
+#pragma unroll
+    for (int kk = 0; kk < NCS; ++kk) {
+        const int ci = min(t + kk * kLanes, NC - 1);
+        {
+            const int c0 = i0 - H + ci;
+            const int cell = inner ? c0 : wrap1f(c0, n);
+            float mp;
+            if (windowed) {
+                const int ja = sjc[ci], jb = sjc[ci + 1];
+                const float m0 = sw[ja], m1 = sw[ja + 1];
+                float whole = jb > ja ? m0 : 0.0f;
+                whole += jb > ja + 1 ? m1 : 0.0f;
+                for (int mm = ja + 2; mm < jb; ++mm) whole += sw[mm];
+                mp = whole + (sell[ci + 1] - sell[ci]);
+            } else {
+                mp = (float)(direct_whole<float>(R.edges, q, n, sg[ci], sg[ci + 1]) +
+                             ((double)sell[ci + 1] - (double)sell[ci]));
+            }
+            qs[kk] = mp * tb.dxinvf[cell];
+            if constexpr (H == 0) qo[cell] = qs[kk];
+            else if (qmid && ci >= H && ci < H + nd) qmid[cell] = qs[kk];
+        }
+    }
+    if constexpr (H != 0) {
+        float dvv[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+        load_faces<VEC>((const float *)a.dv + qoff, n, i0, nd, c4, dvv);
+        // per-cell geometry of cells i0+4l-2 .. i0+4l+5: (dx, 1/gap), and 1/dx
+        // of the four own cells
+        float2 rrv[NV];
+        float dxi[4];
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
+            const int cg = i0 + min(c4, nd - 1) - 2 + c;
+            rrv[c] = tb.rrf[wrap1f(cg, n)];
+        }
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) dxi[kk] = tb.dxinvf[min(i0 + c4 + kk, n - 1)];
+        wave_sync();                                 // the window is dead
+#pragma unroll
+        for (int kk = 0; kk < NCS; ++kk) sq[min(t + kk * kLanes, NC - 1)] = qs[kk];
+        wave_sync();
+        if (c4 < nd) {
+            float sv[NV];
+#pragma unroll
+            for (int v = 0; v < NV / 4; ++v) {
+                const float4 q4 = *(const float4 *)(sq + c4 + 4 * v);
+                sv[4 * v] = q4.x;
+                sv[4 * v + 1] = q4.y;
+                sv[4 * v + 2] = q4.z;
+                sv[4 * v + 3] = q4.w;
+            }
+            float o[4];
+            residual4(sv, dvv, dt, [&](int c) { return rrv[c]; }, [&](int kk) { return dxi[kk]; },
+                      o);
+            store_cells<VEC>(qo, i0, nd, c4, o);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The compacted records, in tile order: uniform tiles first, then the others
+// (for the node plan), each with its tile id in pad[0]; the others' position
+// among them (their node data) in pad[1] of both copies.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(1024) void k_tile_count(const FastTile *rec, int nt, int32_t *counts)
+{
+    __shared__ int swc[16];
+    const int j = (int)blockIdx.x * 1024 + (int)threadIdx.x;
+    const bool u = j < nt && rec[j].kind == kFastUniform;
+    const int c = __popcll(__ballot(u));
+    if ((threadIdx.x & 63) == 0) swc[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int s = 0;
+        for (int w = 0; w < 16; ++w) s += swc[w];
+        counts[blockIdx.x] = s;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_tile_lists(FastTile *rec, int nt,
+                                                     const int32_t *counts, int nb,
+                                                     FastTile *crec, int32_t *totals)
+{
+    __shared__ int sred[2][16];
+    __shared__ int swo[2][17];
+    const int tid = (int)threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    // uniform tiles before this block and in total
+    int before = 0, all = 0;
+    for (int b = tid; b < nb; b += 1024) {
+        const int c = counts[b];
+        all += c;
+        if (b < (int)blockIdx.x) before += c;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        before += __shfl_xor(before, o, 64);
+        all += __shfl_xor(all, o, 64);
+    }
+    if (lane == 0) {
+        sred[0][wv] = before;
+        sred[1][wv] = all;
+    }
+    const int j = (int)blockIdx.x * 1024 + tid;
+    const bool in = j < nt;
+    const bool u = in && rec[j].kind == kFastUniform;
+    const uint64_t mu = __ballot(u), mg = __ballot(in && !u);
+    const uint64_t below = (1ull << lane) - 1ull;
+    if (lane == 0) {
+        swo[0][wv + 1] = __popcll(mu);
+        swo[1][wv + 1] = __popcll(mg);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int b0 = 0, a0 = 0;
+        for (int w = 0; w < 16; ++w) {
+            b0 += sred[0][w];
+            a0 += sred[1][w];
+        }
+        sred[0][0] = b0;
+        sred[1][0] = a0;
+        swo[0][0] = swo[1][0] = 0;
+        for (int w = 1; w <= 16; ++w) {
+            swo[0][w] += swo[0][w - 1];
+            swo[1][w] += swo[1][w - 1];
+        }
+        if (blockIdx.x == 0) {
+            totals[0] = a0;
+            totals[1] = nt - a0;
+        }
+    }
+    __syncthreads();
+    const int ub = sred[0][0], utot = sred[1][0];
+    const int gb = (int)blockIdx.x * 1024 - ub;      // other tiles before this block
+    if (in) {
+        int pos;
+        if (u) pos = ub + swo[0][wv] + __popcll(mu & below);
+        else pos = utot + gb + swo[1][wv] + __popcll(mg & below);
+        FastTile r = rec[j];
+        if (!u) {
+            r.pad[1] = pos - utot;                   // the tile's node data
+            rec[j].pad[1] = r.pad[1];
+        }
+        crec[pos] = r;
+    }
+}
+
+// The step, in two kernels, one tile a wave: the uniform tiles (the
+// compacted list's first part; 26 registers, eight waves a SIMD), then the
+// other tiles (the rest of the list).  Both grids span the whole tile count
+// (the host does not know the split); the waves past their part of the list
+// return at once.  Measured alternatives on the refined disk: one kernel over
+// both kinds (in tile order, or the other tiles spread evenly through the
+// grid) ran the uniform tiles at the other path's register and LDS footprint
+// and took 135-163 us a step against 123; persistent waves striding over the
+// other tiles, 128-157; running the two kernels on two streams, 342.
+template <int P, int H, bool VEC>
+__global__ __launch_bounds__(kBlock, 8) void k_step_uni(StepArgs a)
+{
+    __shared__ __attribute__((aligned(16))) float swin[kWaves][kUniWin];
+    const int wid = wave_id();
+    const int i = (int)blockIdx.x * kWaves + wid;
+    if (i >= a.fast.totals[0]) return;
+    const FastTile r = load_rec(a.fast.rec + a.rows.n_tiles, i);
+    uniform_tile<P, H, VEC>(a, r, swin[wid], (int)threadIdx.x % kLanes);
+}
+
+template <int P, int H, bool VEC>
+__global__ __launch_bounds__(kBlock) void k_step_gen(StepArgs a)
+{
+    __shared__ __attribute__((aligned(16))) unsigned char su[kWaves][WaveLds::u];
+    __shared__ __attribute__((aligned(16))) float sell_[kWaves][WaveLds::nodes];
+    __shared__ __attribute__((aligned(16))) short sjc_[kWaves][WaveLds::nodes];
+    const int wid = wave_id();
+    const int i = a.fast.totals[0] + (int)blockIdx.x * kWaves + wid;
+    if (i >= a.rows.n_tiles) return;
+    const FastTile r = load_rec(a.fast.rec + a.rows.n_tiles, i);
+    general_tile<P, H, VEC>(a, r, su[wid], sell_[wid], sjc_[wid], (int)threadIdx.x % kLanes);
+}
+
+template <int P, int H, bool VEC>
+hipError_t step_fast_kernels(const StepArgs &a, hipStream_t st)
+{
+    const dim3 g((unsigned)((a.rows.n_tiles + kWaves - 1) / kWaves)), b(kBlock);
+    hipLaunchKernelGGL((k_step_uni<P, H, VEC>), g, b, 0, st, a);
+    hipLaunchKernelGGL((k_step_gen<P, H, VEC>), g, b, 0, st, a);
+    return hipGetLastError();
+}
+
+template <int P>
+hipError_t step_fast_p(const StepArgs &a, hipStream_t st)
+{
+    const bool vec = (a.rows.n_cols % 4) == 0 && ((uintptr_t)a.q_out % 16) == 0 &&
+                     (!a.dv || ((uintptr_t)a.dv % 16) == 0);
+    if (a.dv) return vec ? step_fast_kernels<P, 2, true>(a, st) : step_fast_kernels<P, 2, false>(a, st);
+    return vec ? step_fast_kernels<P, 0, true>(a, st) : step_fast_kernels<P, 0, false>(a, st);
+}
+
+} // namespace
+
+hipError_t launch_plan_fast(const StepArgs &a, int order, const FastPlan &plan,
+                            hipStream_t stream)
+{
+    if (a.rows.n_tiles <= 0) return hipSuccess;
+    if (a.rows.tile != kFastTile || a.rows.n_tiles > INT32_MAX / 2) return hipErrorInvalidValue;
+    const int nt = (int)a.rows.n_tiles;
+    const unsigned grid = (unsigned)((nt + 63) / 64);
+    switch (order) {
+    case 1: hipLaunchKernelGGL(k_plan_fast<1>, dim3(grid), dim3(64), 0, stream, a, plan.rec); break;
+    case 3: hipLaunchKernelGGL(k_plan_fast<3>, dim3(grid), dim3(64), 0, stream, a, plan.rec); break;
+    default: hipLaunchKernelGGL(k_plan_fast<5>, dim3(grid), dim3(64), 0, stream, a, plan.rec); break;
+    }
+    const int nb = (nt + 1023) / 1024;
+    hipLaunchKernelGGL(k_tile_count, dim3(nb), dim3(1024), 0, stream, plan.rec, nt, plan.counts);
+    // the compacted records follow the per-tile ones (fast_plan_bytes)
+    hipLaunchKernelGGL(k_tile_lists, dim3(nb), dim3(1024), 0, stream, plan.rec, nt, plan.counts,
+                       nb, plan.rec + nt, plan.totals);
+    StepArgs b = a;
+    b.fast = plan;
+    const dim3 gn((unsigned)((nt + kWaves - 1) / kWaves));
+    switch (order) {
+    case 1: hipLaunchKernelGGL(k_node_plan<1>, gn, dim3(kBlock), 0, stream, b); break;
+    case 3: hipLaunchKernelGGL(k_node_plan<3>, gn, dim3(kBlock), 0, stream, b); break;
+    default: hipLaunchKernelGGL(k_node_plan<5>, gn, dim3(kBlock), 0, stream, b); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_step_fast(const StepArgs &a, int order, hipStream_t stream)
+{
+    if (a.rows.n_tiles <= 0) return hipSuccess;
+    if (a.rows.tile != kFastTile) return hipErrorInvalidValue;
+    switch (order) {
+    case 1: return step_fast_p<1>(a, stream);
+    case 3: return step_fast_p<3>(a, stream);
+    default: return step_fast_p<5>(a, stream);
+    }
+}
+
+} // namespace ram

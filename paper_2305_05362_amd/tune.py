@@ -29,7 +29,7 @@ import torch
 
 from . import _lib as R
 
-CANDIDATES = (2, 3, 4, 5)
+CANDIDATES = (0, 2, 3, 4, 5)
 DEFAULT_CACHE = os.environ.get(
     "RAM_TUNE_CACHE",
     os.path.join(os.path.expanduser("~"), ".cache", "ram_mi355x", "schedules.json"))

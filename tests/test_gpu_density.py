@@ -4,8 +4,9 @@ App. B) on the GPU.
 * the closed form alone (ram_mesh_density_cells) puts every cell centre of the
   periodic-bump mesh in its own cell and every node within one cell of its
   index: the device formula reproduces the mesh generator's F;
-* a step with the index agrees with the bucket-index step to rounding (the
-  same source cells; the kernel variant is compiled on its own): 1e-15
+* a step with the index agrees with the bucket-index step of the same
+  general kernel (schedule 4) to rounding (the same source cells; the kernel
+  variant is compiled on its own): 1e-15
   relative L1 in FP64, 1e-7 in FP32, with and without the residual, one step
   and a captured multi-step loop, the 2048 x 16384 disk too; and it matches
   the oracle to 1e-12;
@@ -39,6 +40,7 @@ def ctx():
     c = R.context(0)
     yield c
     c.set_mesh_density(None)
+    c.set_schedule(0)
 
 
 def test_closed_form_matches_mesh(ctx):
@@ -62,7 +64,9 @@ def test_density_step_equals_bucket_step(ctx, dtype):
     for steps, dvv in ((1, dv), (5, dv), (6, None)):
         ref = dev(wl.q0, dtype)
         ctx.set_mesh_density(None)
+        ctx.set_schedule(4)          # the general kernel the index variant belongs to
         ctx.ram_step(rows, ref, v0, dvv, wl.dt, 5, steps, R.RAM_SUM_DIRECT)
+        ctx.set_schedule(0)
         for params in (bump, (bump[0], bump[1], 0.5 * bump[2])):   # right, then wrong c
             ctx.set_mesh_density(params, -math.pi, math.pi)
             q = dev(wl.q0, dtype)
@@ -86,7 +90,9 @@ def test_density_step_full_size(ctx):
     dv = dev(wl.dv.astype(np.float32), torch.float32)
     q0 = dev(wl.q0.astype(np.float32), torch.float32)
     ref = q0.clone()
+    ctx.set_schedule(4)
     ctx.ram_step(rows, ref, v0, dv, wl.dt, 5, 2, R.RAM_SUM_DIRECT)
+    ctx.set_schedule(0)
     ctx.set_mesh_density(wl.meta["bump"], -math.pi, math.pi)
     q = q0.clone()
     ctx.ram_step(rows, q, v0, dv, wl.dt, 5, 2, R.RAM_SUM_DIRECT)
