@@ -162,6 +162,27 @@ ram_status ram_shift(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
                      ram_scan scan, const void *q_in, void *q_out,
                      const double *edges, const double *v0, double dt,
                      int order);
+/* For callers that cannot allocate device memory (code under stream or graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * bulk shift as ram_shift, same arguments, same layouts, but its mesh tables,
+ * window plan or ragged tile table live in a static device buffer of 16 MiB
+ * that the library holds on each GPU it runs on until the process ends (its
+ * address is looked up once per device, by ram_create).  The call allocates
+ * nothing: no hipMalloc, hipFree or allocating library routine.  It always
+ * runs the general shift kernels (the schedule of ram_set_schedule, 0 meaning
+ * 4 nodes a thread), never the streaming FP32 kernel whose per-call plan is
+ * far larger; results agree with ram_shift under the same schedule bit for
+ * bit, and with the default schedule to rounding.  Layouts needing more than
+ * the buffer (a shared mesh's tables take about 530 bytes a cell, so meshes
+ * beyond about 30000 cells; a ragged batch's tile table 4 bytes a tile and 8
+ * a row) return RAM_E_NOMEM with the required size in ram_last_error, before
+ * any device work.  Every call on a GPU shares that GPU's buffer and rewrites all
+ * of what it reads (nothing must start at zero): calls that overlap on one GPU
+ * (other streams, other contexts, other host threads) race and must be
+ * ordered by the caller. */
+ram_status ram_shift_noalloc(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
+                             ram_scan scan, const void *q_in, void *q_out,
+                             const double *edges, const double *v0, double dt, int order);
 
 /* Residual upwind step (paper Eq. splitting_second): finite-volume update with
  * the PLM reconstruction and van Leer harmonic slope of Section 3.1; the face

@@ -91,6 +91,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ram_set_stream": [P, P],
         "ram_sync": [P],
         "ram_shift": [P, LP, I, I, P, P, P, P, D, I],
+        "ram_shift_noalloc": [P, LP, I, I, P, P, P, P, D, I],
         "ram_residual": [P, LP, I, P, P, P, P, D],
         "ram_step": [P, LP, I, I, P, P, P, P, D, I, I64],
         "ram_shift_adjoint": [P, LP, I, I, P, P, P, P, P, D, I, P],
@@ -223,6 +224,18 @@ class Context:
         dt_code = _dtype_code(q_in)
         check(self._lib.ram_shift(
             self._h, ctypes.byref(rows.layout), dt_code, int(scan),
+            _dev_ptr(q_in, q_in.dtype, "q_in"), _dev_ptr(q_out, q_in.dtype, "q_out"),
+            _dev_ptr(rows.edges, torch.float64, "edges"),
+            _dev_ptr(v0, torch.float64, "v0"), float(dt), int(order)))
+        return q_out
+
+    def ram_shift_noalloc(self, rows: Rows, q_in, q_out, v0, dt: float, order: int,
+                          scan: int = RAM_SCAN_F64):
+        """ram_shift through the entry point that allocates no device memory
+        (a static library buffer holds its tables and plan)."""
+        self._stream()
+        check(self._lib.ram_shift_noalloc(
+            self._h, ctypes.byref(rows.layout), _dtype_code(q_in), int(scan),
             _dev_ptr(q_in, q_in.dtype, "q_in"), _dev_ptr(q_out, q_in.dtype, "q_out"),
             _dev_ptr(rows.edges, torch.float64, "edges"),
             _dev_ptr(v0, torch.float64, "v0"), float(dt), int(order)))

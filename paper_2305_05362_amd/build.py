@@ -21,7 +21,7 @@ ARCH = os.environ.get("RAM_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["ram_kernels.hip", "ram_step_shared.hip", "ram_step_fast.hip", "ram_adjoint.hip",
            "ram_adjoint_shared.hip", "ram_limited.hip", "ram_reduce.hip", "ram_radial.hip",
-           "ram_average4.hip", "ram_api.cpp"]
+           "ram_average4.hip", "ram_noalloc.hip", "ram_api.cpp"]
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

@@ -208,8 +208,9 @@ RowsPlan plan_rows(Carve &cv, const ram_layout *L, int tile, int tab_order)
 // Fill the kernel-side row description (after ensure_scratch): ragged
 // batches get their tile table, shared meshes their tables.
 ram_status make_rows(ram_ctx *ctx, const ram_layout *L, const double *edges,
-                     const RowsPlan &p, ram::Rows &R)
+                     const RowsPlan &p, ram::Rows &R, char *base_mem = nullptr)
 {
+    char *mem = base_mem ? base_mem : (char *)ctx->scratch;
     R.n_rows = L->n_rows;
     R.n_cols = L->n_cols;
     R.edges = edges;
@@ -220,7 +221,7 @@ ram_status make_rows(ram_ctx *ctx, const ram_layout *L, const double *edges,
     } else {
         R.row_ptr = L->row_ptr;
         R.n_tiles = ram::ragged_tile_bound(L->n_cells, L->n_rows, p.tile);
-        char *base = (char *)ctx->scratch + p.rag_off;
+        char *base = mem + p.rag_off;
         R.tile_ptr = (const int64_t *)base;
         R.tile_row = (const int32_t *)(base + align_up(sizeof(int64_t) * (L->n_rows + 1)));
         hipError_t e = ram::launch_tiles_prep(L->row_ptr, L->n_rows, p.tile,
@@ -229,8 +230,7 @@ ram_status make_rows(ram_ctx *ctx, const ram_layout *L, const double *edges,
         if (e != hipSuccess) return hip_fail(e, "tile table launch");
     }
     if (p.order > 0) {
-        hipError_t e = ram::launch_mesh_prep(edges, L->n_cols, p.order,
-                                             (char *)ctx->scratch + p.tab_off,
+        hipError_t e = ram::launch_mesh_prep(edges, L->n_cols, p.order, mem + p.tab_off,
                                              R.tab, ctx->stream, p.uniform);
         if (e != hipSuccess) return hip_fail(e, "mesh table launch");
         R.has_tab = 1;
@@ -389,8 +389,10 @@ std::vector<unsigned char> key_of(const T &...parts)
 ram_status launch_steps(ram_ctx *ctx, ram::StepArgs a, ram_dtype dtype,
                         ram_scan scan, int order, int64_t n_steps, void *tmp,
                         size_t wlo_off, size_t w_off, size_t state_bytes,
-                        int items, int recon = 0)
+                        int items, int recon = 0, char *base_mem = nullptr,
+                        bool allow_fast = true)
 {
+    char *mem = base_mem ? base_mem : (char *)ctx->scratch;
     const bool f64 = dtype == RAM_F64;
     const bool shared = a.rows.has_tab != 0 && a.rows.n_cols > 0;
     if (recon && !shared) return fail(RAM_E_UNSUPPORTED, "internal: limited step loop needs a shared mesh");
@@ -399,10 +401,9 @@ ram_status launch_steps(ram_ctx *ctx, ram::StepArgs a, ram_dtype dtype,
     hipError_t e;
     if (shared) {
         const int plan_order = recon == 0 ? order : (recon == RAM_RECON_PLM ? 3 : 5);
-        const bool fast = recon == 0 &&
+        const bool fast = recon == 0 && allow_fast &&
                           use_fast_shape(ctx, a.rows.shared != 0, a.rows.n_cols, dtype, scan);
-        e = plan_shared(a, plan_order, fast, (char *)ctx->scratch + wlo_off,
-                        (char *)ctx->scratch + w_off, ctx->stream);
+        e = plan_shared(a, plan_order, fast, mem + wlo_off, mem + w_off, ctx->stream);
         if (e != hipSuccess) return hip_fail(e, "window plan launch");
     }
     auto one = [&](const ram::StepArgs &s, hipStream_t st) {
@@ -516,6 +517,9 @@ ram_status ram_create(ram_ctx **out, int device, void *stream)
     if (!ctx) return fail(RAM_E_NOMEM, "host allocation failed");
     ctx->device = device;
     ctx->stream = (hipStream_t)stream;
+    // the static scratch of ram_shift_noalloc: its address on this device,
+    // looked up once (a failure surfaces when that entry point is called)
+    (void)ram::noalloc_setup(device);
     *out = ctx;
     g_last_error.clear();
     return RAM_OK;
@@ -636,6 +640,50 @@ ram_status ram_shift(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
                            items)) != RAM_OK)
         return st;
     return RAM_OK;
+}
+
+ram_status ram_shift_noalloc(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
+                             ram_scan scan, const void *q_in, void *q_out,
+                             const double *edges, const double *v0, double dt, int order)
+{
+    ram_status st;
+    g_last_error.clear();
+    if ((st = check_layout(layout, edges)) != RAM_OK) return st;
+    if ((st = check_dtype(dtype)) != RAM_OK) return st;
+    if ((st = check_scan(dtype, scan)) != RAM_OK) return st;
+    if ((st = check_order(layout, order)) != RAM_OK) return st;
+    if ((st = check_dt(dt)) != RAM_OK) return st;
+    if (!q_in || !q_out || !v0) return fail(RAM_E_INVALID_ARG, "null q_in, q_out or v0");
+    if (q_in == q_out) return fail(RAM_E_INVALID_ARG, "q_in and q_out must not alias");
+    if ((st = enter(ctx)) != RAM_OK) return st;
+    char *mem = (char *)ram::noalloc_scratch(ctx->device);
+    if (!mem) {
+        const hipError_t e = ram::noalloc_setup(ctx->device);
+        mem = (char *)ram::noalloc_scratch(ctx->device);
+        if (!mem) return hip_fail(e, "static scratch of ram_shift_noalloc");
+    }
+    // the general kernels (the streaming kernel's per-call node data would
+    // not fit a modest static buffer)
+    const int items = sched_items(ctx, layout, scan);
+    Carve cv;
+    RowsPlan rp = plan_rows(cv, layout, ram::step_tile_for(items, false), order);
+    rp.uniform = wants_uniform(dtype, scan);
+    const int64_t nt = tiles_of(layout, rp.tile);
+    const size_t wlo_off = cv.take(sizeof(int64_t) * nt),
+                 w_off = cv.take(ram::kPlanW * sizeof(int32_t) * nt);
+    if (cv.off > ram::kNoAllocBytes)
+        return fail(RAM_E_NOMEM,
+                    "ram_shift_noalloc needs %zu bytes of device scratch for this layout; "
+                    "its static buffer holds %zu",
+                    cv.off, ram::kNoAllocBytes);
+    ram::StepArgs a;
+    if ((st = make_rows(ctx, layout, edges, rp, a.rows, mem)) != RAM_OK) return st;
+    a.q_in = q_in;
+    a.q_out = q_out;
+    a.v0 = v0;
+    a.dt = dt;
+    return launch_steps(ctx, a, dtype, scan, order, 1, nullptr, wlo_off, w_off, 0, items, 0, mem,
+                        false);
 }
 
 ram_status ram_residual(ram_ctx *ctx, const ram_layout *layout,

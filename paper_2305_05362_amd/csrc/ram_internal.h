@@ -286,6 +286,13 @@ inline int step_tile(bool fused) { return kStepNodes - 1 - (fused ? 4 : 0); }
 inline bool valid_items(int items) { return items >= 2 && items <= 5; }
 inline int step_tile_for(int items, bool fused) { return kBlock * items - 1 - (fused ? 4 : 0); }
 
+// The static device scratch of ram_shift_noalloc (ram_noalloc.hip): its size,
+// the once-per-device lookup of its address (with the device current; call
+// from ram_create), and that address (null until the lookup succeeded).
+constexpr size_t kNoAllocBytes = size_t(16) << 20;
+hipError_t noalloc_setup(int device);
+void *noalloc_scratch(int device);
+
 hipError_t launch_tiles_prep(const int64_t *row_ptr, int64_t n_rows, int tile,
                              int64_t *tile_ptr, int32_t *tile_row,
                              hipStream_t stream);
