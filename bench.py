@@ -69,6 +69,11 @@ def parse():
 
 COPY_BYTES = 256 << 20
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_sh_f32_direct_polar2048x16384_traffic.md")
+# the streaming step's two kernels (the default schedule)
+UNI_KERNEL = "k_step_uni<5, 2, true>"
+GEN_KERNEL = "k_step_gen<5, 2, true>"
+TRAFFIC_FILE_UNI = os.path.join(ROOT, "profiles", "k_step_uni_f32_polar2048x16384_traffic.md")
+TRAFFIC_FILE_GEN = os.path.join(ROOT, "profiles", "k_step_gen_f32_polar2048x16384_traffic.md")
 TRAFFIC_FILE_PPM = os.path.join(ROOT, "profiles", "k_step_sh_f32_ppm_polar2048x16384_traffic.md")
 TRAFFIC_FILE_RADIAL = os.path.join(ROOT, "profiles", "k_radial_f32_polar2048x16384_traffic.md")
 TRAFFIC_FILE_AVG4 = os.path.join(ROOT, "profiles", "k_average4_f32_polar2048x16384_traffic.md")
@@ -188,7 +193,12 @@ def main():
     else:
         use_density = False
     idx = 1 if use_density else 0
-    schedule = {"items_per_thread": items, "tile_cells": 256 * items - 5,
+    schedule = {"items_per_thread": items,
+                "kernel": ("streaming: k_step_uni (uniform-run tiles) + k_step_gen (the rest), "
+                           "256-cell wave tiles") if items == 0 and not use_density
+                else "general k_step_sh",
+                "tile_cells": 256 if items == 0 and not use_density
+                else 256 * (items or 4) - 5,
                 "index": "mesh-density closed form" if use_density else "bucket",
                 "tuned_us_per_step": {str(k): round(v, 2) for k, v in tune_us.items()},
                 "density_index_us_per_step": None if dens_us is None else round(dens_us, 2),
@@ -482,9 +492,63 @@ def main():
               "f32_plain_prefix": round(wl3.n_cells * k3 / t3p / 1e9, 3),
               "f64": round(wl3.n_cells * k3 / t3d / 1e9, 3),
               "unit": "Gcell-updates/s",
+              "algorithmic_bytes_per_cell": {"f32": 16, "f64": 24,
+                                             "note": "Q in, Q out, the row's FP64 nodes"},
+              "hbm_frac": {"f32_twosum": round(16.0 * wl3.n_cells * k3 / t3 / 1e9
+                                               / HBM_PEAK_GBS, 4),
+                           "f32_plain_prefix": round(16.0 * wl3.n_cells * k3 / t3p / 1e9
+                                                     / HBM_PEAK_GBS, 4),
+                           "f64": round(24.0 * wl3.n_cells * k3 / t3d / 1e9
+                                        / HBM_PEAK_GBS, 4)},
               "one_step_rel_l1_vs_f64": {"f32_twosum": e3(ones["f32_twosum"]),
                                          "f32_plain_prefix": e3(ones["f32_plain_prefix"])}}
-    del q3, ones
+    del ones
+
+    # --- growth of max |Q| per configuration (reading C14) ------------------
+    # the unlimited order-p interpolant can amplify on rough meshes; each
+    # config reports max|Q_T| / max|Q_0| over its configured steps (FP64),
+    # and for the ragged rows the first 10-step mark where an order's max |Q|
+    # has more than doubled, with the limited reconstructions beside them
+    def growth(rws, qq, vv, dd, dtt, od, steps, chunk=10, recon=0):
+        q = qq.clone()
+        m0 = float(q.abs().max())
+        first = None
+        done = 0
+        while done < steps:
+            k = min(chunk, steps - done)
+            if recon:
+                for _ in range(k):
+                    tmp = torch.empty_like(q)
+                    ctx.ram_shift_limited(rws, q, tmp, vv, dtt, recon)
+                    q = tmp
+            else:
+                ctx.ram_step(rws, q, vv, dd, dtt, od, k, R.RAM_SCAN_F64)
+            done += k
+            m = float(q.abs().max())
+            if first is None and not (m <= 2.0 * m0):
+                first = done
+        return {"steps": steps, "max_growth": float(q.abs().max()) / m0,
+                "first_step_doubled": first}
+    stability = {"note": "FP64 paths; max|Q_T| / max|Q_0| and the first 10-step mark where "
+                         "max|Q| exceeded twice its start (null: never)"}
+    q3d = q3.double()
+    for od in (1, 3, 5):
+        stability[f"cfg3_ragged_order{od}"] = growth(rows3, q3d, v03, None, wl3.dt, od, 200)
+    for name, rc in (("plm", R.RAM_RECON_PLM), ("ppm", R.RAM_RECON_PPM)):
+        stability[f"cfg3_ragged_{name}"] = growth(rows3, q3d, v03, None, wl3.dt, 0, 200,
+                                                  recon=rc)
+    del q3d, q3
+    stability["cfg5_disk_order5"] = growth(rows, q64, v0, dv64, wl.dt, order, 200)
+    for cfg in (1, 2, 4):
+        wc = W.CONFIGS[cfg]()
+        rc_ = R.Rows.from_workload(wc, dev)
+        qc = torch.as_tensor(wc.q0.reshape(-1), dtype=torch.float64, device=dev)
+        dc = None if wc.dv is None else torch.as_tensor(wc.dv.reshape(-1), dtype=torch.float64,
+                                                        device=dev)
+        vc = torch.as_tensor(wc.v0, dtype=torch.float64, device=dev)
+        stability[f"cfg{cfg}"] = growth(rc_, qc, vc, dc, wc.dt, wc.order, wc.steps, chunk=50)
+        del rc_, qc, dc, vc, wc
+    torch.cuda.synchronize()
 
     # --- the shift-only and residual-only kernels on their own --------------
     h32 = torch.empty_like(q32)
@@ -507,18 +571,41 @@ def main():
     t_copy = time_kernel(lambda: dst_c.copy_(src_c), 20)
     copy_gbs = 2.0 * COPY_BYTES / t_copy / 1e9
     del src_c, dst_c
-    head_kernel = f"k_step_sh<float, 5, 3, 2, 0, {items}, {idx}>"
-    tr = load_traffic(TRAFFIC_FILE, head_kernel)
+    streaming = items == 0 and not use_density
+    if streaming:
+        # one step = the uniform-run tiles' kernel, then the other tiles'
+        head_kernel = f"{UNI_KERNEL} + {GEN_KERNEL}"
+        tru = load_traffic(TRAFFIC_FILE_UNI, UNI_KERNEL)
+        trg = load_traffic(TRAFFIC_FILE_GEN, GEN_KERNEL)
+        traffic = None if tru is None or trg is None else \
+            tru["traffic_bytes_per_launch"] + trg["traffic_bytes_per_launch"]
+        paths = ctx.ram_step_tile_paths(rows, v0, wl.dt, order, True).cpu().numpy()
+        tiles = {"uniform_run": int((paths == R.RAM_TILE_UNIFORM).sum()),
+                 "searching": int((paths == R.RAM_TILE_WINDOW).sum()),
+                 "direct": int((paths == R.RAM_TILE_DIRECT).sum()), "cells_per_tile": 256}
+    else:
+        head_kernel = f"k_step_sh<float, 5, 3, 2, 0, {items or 4}, {idx}>"
+        tr = load_traffic(TRAFFIC_FILE, head_kernel)
+        traffic = None if tr is None else tr["traffic_bytes_per_launch"]
+        tiles = None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None if tr is None else round(tr["traffic_bytes_per_launch"]),
-                "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+                "traffic": None if traffic is None else round(traffic),
+                "traffic_unit": "HBM bytes per step (FETCH_SIZE + WRITE_SIZE, copy-scaled, "
+                                "summed over the step's kernels)",
+                "traffic_over_algorithmic": None if traffic is None
+                else round(traffic / fused_bytes, 3),
                 "algorithmic_bytes_per_launch": fused_bytes,
+                "algorithmic_unit": "12 B a cell (Q in, dv in, Q out; FP32) x 33554432 cells, "
+                                    "per step",
                 "copy_achieved": round(copy_gbs, 1),
                 "copy_note": "torch device copy of 256 MiB (read + write) on the same GPU",
-                "kernel": head_kernel + " (FP32, order 5, direct sums, fused residual, "
-                                        f"{items} nodes per thread, "
-                                        f"{'closed-form' if idx else 'bucket'} index)"}
+                "tiles": tiles,
+                "kernel": head_kernel + " (FP32, order 5, direct sums, fused residual; "
+                          + ("the step's two kernels timed together by HIP events around "
+                             "the step loop" if streaming
+                             else f"{items or 4} nodes per thread, "
+                                  f"{'closed-form' if idx else 'bucket'} index") + ")"}
 
     # --- limited reconstructions (PLM / PPM bulk shift, then the residual) --
     # two kernels a step: the limited shift and the residual step alone
@@ -692,43 +779,126 @@ def main():
 
     # --- CPU oracle baseline on a bounded sample ----------------------------
     cpu = None
+    oracle_err = None
     if not args.no_cpu:
         import oracle                      # the CPU baseline leg only
+        cores = len(os.sched_getaffinity(0))
+
+        def cpu_model_string():
+            fields = {}
+            try:
+                with open("/proc/cpuinfo") as fh:
+                    for line in fh:
+                        if ":" in line:
+                            k_, v_ = line.split(":", 1)
+                            fields.setdefault(k_.strip(), v_.strip())
+            except OSError:
+                return None
+            return (f"{fields.get('model name', '?')} (family {fields.get('cpu family', '?')}, "
+                    f"model {fields.get('model', '?')}, stepping {fields.get('stepping', '?')}, "
+                    f"{fields.get('cpu MHz', '?')} MHz)")
+
+        def run_oracle(orows, q, vv, dd, dtt, od, steps, nthreads):
+            t0 = time.perf_counter()
+            out_ = oracle.step(orows, q, vv, dd, dtt, od, steps, nthreads=nthreads)
+            return time.perf_counter() - t0, out_
+
+        # the headline workload: the first rows of the disk, as many FP64
+        # steps as fit the time budget, on every core this process may use
         n_s = 128
         sub = oracle.Rows(np.arange(n_s + 1) * n, wl.edges, True)
         qs = wl.q0[:n_s].astype(np.float64)
-        t0 = time.perf_counter()
-        oracle.step(sub, qs, wl.v0[:n_s], wl.dv[:n_s], wl.dt, order, 1)
-        t1 = time.perf_counter() - t0
+        t1, _ = run_oracle(sub, qs, wl.v0[:n_s], wl.dv[:n_s], wl.dt, order, 1, cores)
         steps_s = max(1, int(args.cpu_seconds / max(t1, 1e-3)))
-        t0 = time.perf_counter()
-        oracle.step(sub, qs, wl.v0[:n_s], wl.dv[:n_s], wl.dt, order, steps_s)
-        tc = time.perf_counter() - t0
-        cores = oracle.max_threads()
+        tc, _ = run_oracle(sub, qs, wl.v0[:n_s], wl.dv[:n_s], wl.dt, order, steps_s, cores)
         # one thread on a smaller sample (the same rows' first 16)
         n_1 = 16
         sub1 = oracle.Rows(np.arange(n_1 + 1) * n, wl.edges, True)
-        q1 = wl.q0[:n_1].astype(np.float64)
         k_1 = max(1, steps_s // 4)
-        t0 = time.perf_counter()
-        oracle.step(sub1, q1, wl.v0[:n_1], wl.dv[:n_1], wl.dt, order, k_1, nthreads=1)
-        t_1 = time.perf_counter() - t0
-        cpu_model = None
-        try:
-            with open("/proc/cpuinfo") as fh:
-                for line in fh:
-                    if line.startswith("model name"):
-                        cpu_model = line.split(":", 1)[1].strip()
-                        break
-        except OSError:
-            pass
+        t_1, _ = run_oracle(sub1, wl.q0[:n_1].astype(np.float64), wl.v0[:n_1], wl.dv[:n_1],
+                            wl.dt, order, k_1, 1)
+        # every configuration: configs 1-3 over their full step counts on every
+        # core (config 3 on one thread over its first 64 rows), configs 4-5 over
+        # a 20-step window; one thread over bounded samples of each
+        plan = {}
+
+        def rate(cells, steps, sec):
+            return round(cells * steps / sec / 1e9, 5)
+        for cfg in (1, 2, 3, 4, 5):
+            wc = wl3 if cfg == 3 else (wl if cfg == 5 else W.CONFIGS[cfg]())
+            orows_c = oracle.Rows.from_workload(wc)
+            q0c = wc.q0.reshape(-1).astype(np.float64)
+            dvc = None if wc.dv is None else wc.dv.reshape(-1)
+            full = cfg in (1, 2, 3)
+            st_all = wc.steps if full else 20
+            t_all, _ = run_oracle(orows_c, q0c, wc.v0, dvc, wc.dt, wc.order, st_all, cores)
+            ent = {"all_cores": {"threads": cores, "steps": st_all, "cells": wc.n_cells,
+                                 "seconds": round(t_all, 3),
+                                 "value": rate(wc.n_cells, st_all, t_all)}}
+            # one thread: the whole batch for config 1, the first rows otherwise
+            nr = wc.n_rows if cfg == 1 else min(wc.n_rows, {2: 64, 3: 64, 4: 16, 5: 4}[cfg])
+            if wc.n_cols > 0:
+                w1 = W.Workload("s", nr, wc.n_cols, np.arange(nr + 1) * wc.n_cols, wc.edges, True,
+                                wc.q0.reshape(wc.n_rows, -1)[:nr],
+                                None if wc.dv is None else wc.dv.reshape(wc.n_rows, -1)[:nr],
+                                wc.v0[:nr], wc.dt, wc.order, wc.steps)
+            else:
+                nc1 = int(wc.row_ptr[nr])
+                w1 = W.Workload("s", nr, 0, wc.row_ptr[:nr + 1], wc.edges[:nc1 + nr], False,
+                                wc.q0[:nc1], None, wc.v0[:nr], wc.dt, wc.order, wc.steps)
+            st_1 = wc.steps if cfg in (1, 3) else 20
+            t_one, _ = run_oracle(oracle.Rows.from_workload(w1), w1.q0.reshape(-1).astype(
+                np.float64), w1.v0, None if w1.dv is None else w1.dv.reshape(-1), w1.dt,
+                w1.order, st_1, 1)
+            ent["one_thread"] = {"rows": nr, "steps": st_1, "cells": w1.n_cells,
+                                 "seconds": round(t_one, 3),
+                                 "value": rate(w1.n_cells, st_1, t_one)}
+            if not full:
+                ent["extrapolation"] = (f"full run of {wc.steps} steps: about "
+                                        f"{t_all * wc.steps / st_all:.0f} s on every core")
+            plan[f"cfg{cfg}"] = ent
+            del orows_c
+        # the GPU's results against the oracle after the same 20 steps from the
+        # same start, on sampled rows (FP64 state; the headline FP32 path from
+        # the FP32-rounded start)
+        pick = np.array([0, 1, 700, 1024, 1025, 1700, 2046, 2047])
+        sw_ = W.Workload("pick", len(pick), n, np.arange(len(pick) + 1) * n, wl.edges, True,
+                         wl.q0[pick], wl.dv[pick], wl.v0[pick], wl.dt, order, 20)
+        orp = oracle.Rows.from_workload(sw_)
+        area = (np.diff(wl.edges)[None, :] * 0.5 *
+                np.diff(np.asarray(wl.meta["r_edges"]) ** 2)[pick][:, None]).reshape(-1)
+        ref64 = oracle.step(orp, sw_.q0.reshape(-1), sw_.v0, sw_.dv.reshape(-1), wl.dt, order,
+                            20, nthreads=cores)
+        q32h = wl.q0.astype(np.float32).astype(np.float64)[pick]
+        dv32h = wl.dv.astype(np.float32).astype(np.float64)[pick]
+        ref32 = oracle.step(orp, q32h.reshape(-1), sw_.v0, dv32h.reshape(-1), wl.dt, order, 20,
+                            nthreads=cores)
+        g64 = q64.clone()
+        ctx.ram_step(rows, g64, v0, dv64, wl.dt, order, 20, R.RAM_SCAN_F64)
+        g32 = q32.clone()
+        ctx.ram_step(rows, g32, v0, dv32, wl.dt, order, 20, HEAD)
+        torch.cuda.synchronize()
+
+        def rel_w(got, ref):
+            return float(np.sum(np.abs(got - ref) * area) / np.sum(np.abs(ref) * area))
+        got64 = g64.cpu().numpy().reshape(wl.n_rows, -1)[pick].reshape(-1)
+        got32 = g32.double().cpu().numpy().reshape(wl.n_rows, -1)[pick].reshape(-1)
+        oracle_err = {"steps": 20, "rows": pick.tolist(),
+                      "norm": "rel-L1 weighted by cell area (r dr dphi)",
+                      "fp64_plain_rel_l1": rel_w(got64, ref64),
+                      "fp32_direct_rel_l1": rel_w(got32, ref32),
+                      "fp32_direct_max_cell_rel": float(np.max(np.abs(got32 - ref32))
+                                                        / np.max(np.abs(ref32)))}
+        del g64, g32
         cpu = {"value": n_s * n * steps_s / tc / 1e9, "unit": "Gcell-updates/s",
                "cores": cores, "kind": "oracle",
                "sample": f"first {n_s} of 2048 rows x 16384 cells, {steps_s} FP64 steps "
-                         f"(shift + residual), {tc:.1f} s",
+                         f"(shift + residual), {tc:.1f} s, {cores} threads "
+                         f"(os.sched_getaffinity)",
                "single_thread_value": n_1 * n * k_1 / t_1 / 1e9,
                "single_thread_sample": f"first {n_1} rows, {k_1} steps, {t_1:.1f} s",
-               "cpu_model": cpu_model}
+               "cpu_model": cpu_model_string(),
+               "configs": plan}
 
     res = {
         "metric": METRIC, "value": round(value, 3), "unit": "Gcell-updates/s",
@@ -763,7 +933,9 @@ def main():
         "mixed_speedup_vs_fp64_direct": round(value / v64d, 3),
         "error": {"one_step_rel_l1_vs_fp64_path": err1,
                   "rollout_rel_l1_vs_fp64_path": drift,
-                  "rollout_steps": args.steps + args.warmup},
+                  "rollout_steps": args.steps + args.warmup,
+                  "vs_oracle": oracle_err},
+        "stability": stability,
         "schedule": schedule,
         "fast_index": fast_index,
         "std_baseline": std_baseline,
