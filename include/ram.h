@@ -146,7 +146,14 @@ ram_status ram_mesh_density_cells(ram_ctx *ctx, const ram_mesh_density *density,
                                   int64_t n, const double *x, int64_t m,
                                   int32_t *cells);
 
-/* Change the stream later calls are issued on. */
+/* Change the stream later calls are issued on.  The context's calls share its
+ * device scratch, so the new stream first waits for everything already issued
+ * on the old one (an event recorded there): calls made on different streams
+ * run one after the other, in the order they were issued.  Streams under graph
+ * capture take no part in that hand-off; the capturing caller orders captured
+ * calls against uncaptured ones.  Setting the current stream again does
+ * nothing.  Errors: RAM_E_INVALID_ARG (null context), RAM_E_HIP (the event
+ * record or wait failed; the context keeps its old stream). */
 ram_status ram_set_stream(ram_ctx *ctx, void *stream);
 /* Wait until every call issued so far on the context's stream has finished;
  * reports asynchronous device errors as RAM_E_HIP. */

@@ -2,6 +2,7 @@
 // checks, context and scratch management, dispatch to the HIP kernels.
 #include "ram.h"
 #include "ram_internal.h"
+#include "ram_stream.h"
 
 #include <hip/hip_runtime.h>
 
@@ -16,6 +17,9 @@
 struct ram_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    // marks the end of the old stream's work when the context moves to
+    // another stream (ram_set_stream): the new one waits for it
+    hipEvent_t handoff = nullptr;
     void *scratch = nullptr;
     size_t scratch_bytes = 0;
     // multi-step loops are captured once into a graph and replayed while the
@@ -65,6 +69,32 @@ ram_status enter(ram_ctx *ctx)
 }
 
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+// The HIP side of ram::switch_stream.
+struct HipStreams {
+    using stream_t = hipStream_t;
+    using event_t = hipEvent_t;
+    hipError_t err = hipSuccess;
+    bool capturing(hipStream_t s)
+    {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s, &cs) != hipSuccess) {
+            (void)hipGetLastError();     // leave no stale error for the caller's checks
+            return true;
+        }
+        return cs != hipStreamCaptureStatusNone;
+    }
+    int record(hipEvent_t ev, hipStream_t s)
+    {
+        err = hipEventRecord(ev, s);
+        return err != hipSuccess;
+    }
+    int wait(hipStream_t s, hipEvent_t ev)
+    {
+        err = hipStreamWaitEvent(s, ev, 0);
+        return err != hipSuccess;
+    }
+};
 
 // Step loops of at least this many launches are captured into a graph; the
 // context keeps the most recent few.
@@ -517,6 +547,11 @@ ram_status ram_create(ram_ctx **out, int device, void *stream)
     if (!ctx) return fail(RAM_E_NOMEM, "host allocation failed");
     ctx->device = device;
     ctx->stream = (hipStream_t)stream;
+    e = hipEventCreateWithFlags(&ctx->handoff, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        delete ctx;
+        return hip_fail(e, "hipEventCreateWithFlags");
+    }
     // the static scratch of ram_shift_noalloc: its address on this device,
     // looked up once (a failure surfaces when that entry point is called)
     (void)ram::noalloc_setup(device);
@@ -532,6 +567,7 @@ ram_status ram_destroy(ram_ctx *ctx)
     (void)hipStreamSynchronize(ctx->stream);
     for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    if (ctx->handoff) (void)hipEventDestroy(ctx->handoff);
     if (ctx->scratch) (void)hipFree(ctx->scratch);
     delete ctx;
     return RAM_OK;
@@ -594,7 +630,12 @@ ram_status ram_get_schedule(const ram_ctx *ctx, ram_schedule *sched)
 ram_status ram_set_stream(ram_ctx *ctx, void *stream)
 {
     if (!ctx) return fail(RAM_E_INVALID_ARG, "null context");
-    ctx->stream = (hipStream_t)stream;
+    if ((hipStream_t)stream == ctx->stream) return RAM_OK;
+    ram_status st = enter(ctx);
+    if (st != RAM_OK) return st;
+    HipStreams api;
+    if (ram::switch_stream(api, ctx->stream, (hipStream_t)stream, ctx->handoff) != 0)
+        return hip_fail(api.err, "stream hand-off");
     return RAM_OK;
 }
 
