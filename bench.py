@@ -52,9 +52,11 @@ def parse():
     p.add_argument("--fp64-steps", type=int, default=200)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
-    p.add_argument("--items", type=int, default=0,
-                   help="shifted nodes per thread of the headline kernel (2..5); "
-                        "0: let the autotuner choose (untimed, before the timed region)")
+    p.add_argument("--items", type=int, default=-1,
+                   help="launch schedule of the headline step: 0 the streaming kernels "
+                        "(256-cell wave tiles), 2..5 the general kernel with that many "
+                        "shifted nodes per thread; -1: let the autotuner choose (untimed, "
+                        "before the timed region)")
     p.add_argument("--index", choices=("auto", "bucket", "density"), default="auto",
                    help="source-cell index of the headline kernel: the bucket index, the "
                         "closed-form mesh-density index, or the autotuner's choice")
@@ -173,14 +175,15 @@ def main():
     # closed-form index of the disk's periodic-bump mesh (Section 3.2.1)
     from paper_2305_05362_amd.tune import choose_index, tuned_schedule
     density = (wl.meta["bump"], -math.pi, math.pi)
-    if args.items:
+    given = args.items >= 0
+    if given:
         ctx.set_schedule(args.items)
         items, tune_us = args.items, {}
     else:
         items, tune_us, _ = tuned_schedule(ctx, rows, q32, v0, dv32, wl.dt, order,
                                            R.RAM_SUM_DIRECT, cache_path=None)
     dens_us = None
-    if args.index == "density" or (args.index == "auto" and not args.items):
+    if args.index == "density" or (args.index == "auto" and not given):
         if args.index == "density":
             ctx.set_schedule(0)
             ctx.set_mesh_density(*density)
@@ -202,7 +205,7 @@ def main():
                 "index": "mesh-density closed form" if use_density else "bucket",
                 "tuned_us_per_step": {str(k): round(v, 2) for k, v in tune_us.items()},
                 "density_index_us_per_step": None if dens_us is None else round(dens_us, 2),
-                "how": "given" if (args.items or args.index != "auto")
+                "how": "given" if (given or args.index != "auto")
                        else "autotuned before the timed region"}
 
     if args.profile_pass:

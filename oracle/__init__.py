@@ -43,6 +43,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ram_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "libram_oracle.so")
+# a separately built copy (the sanitizer test's ASan/UBSan build) can stand in
+_LIB_OVERRIDE = os.environ.get("RAM_ORACLE_LIB")
 _lib = None
 
 
@@ -62,9 +64,12 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB_PATH):
-        build(force=True)
-    lib = ctypes.CDLL(_LIB_PATH)
+    if _LIB_OVERRIDE:
+        lib = ctypes.CDLL(_LIB_OVERRIDE)
+    else:
+        if not os.path.exists(_LIB_PATH):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB_PATH)
     P = ctypes.c_void_p
     I64 = ctypes.c_int64
     D = ctypes.c_double
