@@ -9,7 +9,11 @@
 // straddle m, so each source cell of the tile's window is a short gather.
 // Window cells shared with the neighbouring tiles (the P cells of the stencil
 // of each tile-boundary node) are accumulated with atomics after a zeroing
-// pass; every other cell is written once.
+// pass; every other cell is written once.  A shared cell takes exactly two
+// terms (the tiles on either side of the boundary node) onto the zero, and
+// the sum of two does not depend on their order, so the result is the same
+// in every run; v0bar takes one term per tile, summed per row in tile order
+// by a second kernel.
 //
 // The derivative with respect to v0 enters through x~ = x - v0 dt:
 //     dM'_i/ds = -(q~(x~_{i+1}) - q~(x~_i)),
@@ -174,7 +178,7 @@ __global__ __launch_bounds__(kBlock) void k_shift_adj(ShiftAdjArgs a)
     if (want_v0 && threadIdx.x == 0) {
         double tot = 0.0;
         for (int w = 0; w < kBlock / 64; ++w) tot += sred[w];
-        atomicAdd(&a.v0bar[ti.row], a.dt * tot);
+        a.v0part[blockIdx.x] = a.dt * tot;
     }
 
     const int64_t wlo = sg[0] - LO;
@@ -395,7 +399,7 @@ __global__ __launch_bounds__(kBlock) void k_shift_lim_adj(ShiftAdjArgs a)
     if (want_v0 && threadIdx.x == 0) {
         double tot = 0.0;
         for (int w = 0; w < kBlock / 64; ++w) tot += sred[w];
-        atomicAdd(&a.v0bar[ti.row], a.dt * tot);
+        a.v0part[blockIdx.x] = a.dt * tot;
     }
 
     const int64_t wlo = sg[0] - LO;
@@ -569,15 +573,51 @@ hipError_t launch_shift_limited_adjoint(const ShiftAdjArgs &a, bool f64, int rec
             hipLaunchKernelGGL((k_shift_lim_adj<float, kReconPPM>), g, b, 0, stream, a);
         }
     }
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !(a.v0bar && a.q_fwd)) return e;
+    return launch_v0_reduce(a.rows, a.v0part, a.v0bar, stream);
 }
 
 hipError_t launch_shift_adjoint(const ShiftAdjArgs &a, bool f64, int order,
                                 hipStream_t stream)
 {
     if (a.rows.n_tiles <= 0) return hipSuccess;
-    if (f64) return shift_adj_dispatch<double>(a, order, stream);
-    return shift_adj_dispatch<float>(a, order, stream);
+    hipError_t e = f64 ? shift_adj_dispatch<double>(a, order, stream)
+                       : shift_adj_dispatch<float>(a, order, stream);
+    if (e != hipSuccess || !(a.v0bar && a.q_fwd)) return e;
+    return launch_v0_reduce(a.rows, a.v0part, a.v0bar, stream);
+}
+
+namespace {
+
+// One thread per row: its tiles' v0bar terms in tile order.
+__global__ __launch_bounds__(256) void k_v0_reduce(Rows R, const double *part, double *v0bar)
+{
+    const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (row >= R.n_rows) return;
+    int64_t t0, t1;
+    if (R.n_cols > 0) {
+        const int64_t tpr = (R.n_cols + R.tile - 1) / R.tile;
+        t0 = row * tpr;
+        t1 = t0 + tpr;
+    } else {
+        t0 = R.tile_ptr[row];
+        t1 = R.tile_ptr[row + 1];
+    }
+    double s = 0.0;
+    for (int64_t t = t0; t < t1; ++t) s += part[t];
+    v0bar[row] += s;
+}
+
+} // namespace
+
+hipError_t launch_v0_reduce(const Rows &R, const double *part, double *v0bar,
+                            hipStream_t stream)
+{
+    if (R.n_rows <= 0 || !v0bar) return hipSuccess;
+    const dim3 g((unsigned)((R.n_rows + 255) / 256));
+    hipLaunchKernelGGL(k_v0_reduce, g, dim3(256), 0, stream, R, part, v0bar);
+    return hipGetLastError();
 }
 
 hipError_t launch_residual_adjoint(const ResidualAdjArgs &a, bool f64,

@@ -12,14 +12,20 @@
 //   (2) the shift adjoint.  With V_e the interpolated cumulative at shifted
 //       node e and M'_i = V_{i+1} - V_i, the transpose scatters
 //       Vbar_e = Mbar'_{e-1} - Mbar'_e through each node's Lagrange weights
-//       onto the window's node cumulative (Cbar, FP64 LDS atomics), and the
-//       source masses are the suffix sums Mbar_m = sum_{j > m} Cbar_j (a DPP
-//       block scan).  Source cells shared with the neighbouring tiles (the p
-//       cells of each boundary node's stencil) are accumulated with atomics
-//       after a zeroing pass; every other cell is written once;
+//       onto the window's node cumulative (Cbar), and the source masses are
+//       the suffix sums Mbar_m = sum_{j > m} Cbar_j (a DPP block scan).
+//       Source cells shared with the neighbouring tiles (the p cells of each
+//       boundary node's stencil) are accumulated with atomics after a zeroing
+//       pass (two terms onto the zero: the same sum in either order); every
+//       other cell is written once;
 //   (3) v0bar += dt * sum_e -Vbar_e q~(x~_e), with q~ the reconstruction
 //       (derivative of the interpolated cumulative of Q^n) at the shifted
-//       node.
+//       node: one term per tile, summed per row in tile order afterwards.
+//
+// FP64 results are the same in every run: the Cbar scatter goes in p+1
+// passes, one stencil offset each, in which the nodes that share a source
+// cell (and so a target) are summed in node order by the first of them; the
+// FP32 state's scatter uses LDS atomics (FP64) instead.
 //
 // Tiles whose source window does not fit in LDS gather instead: each window
 // cell telescopes the tile's Vbar down to one Mbar' plus the few stencils
@@ -140,7 +146,11 @@ struct AdjLds {
     using CT2 = typename TabT<CT>::T2;
     static constexpr int NP = kStepNodes + 8;
     static constexpr size_t res = (4 * sizeof(CT) + sizeof(CT2)) * NP;
-    static constexpr size_t win = 2 * sizeof(double) * (kWinA + 1);
+    // Cbar and the window masses; for an FP64 state also each node's window
+    // index and one pass's terms (the ordered scatter)
+    static constexpr bool ordered = sizeof(CT) == 8;
+    static constexpr size_t win = 2 * sizeof(double) * (kWinA + 1) +
+                                  (ordered ? (sizeof(int) + sizeof(double)) * kStepNodes : 0);
     static constexpr size_t nodes = 2 * sizeof(int64_t) * kStepNodes;
     static constexpr size_t u0 = res > win ? res : win;
     static constexpr size_t uni = u0 > nodes ? u0 : nodes;
@@ -172,6 +182,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_sh(StepAdjArgs a)
     // shift-adjoint arrays
     double *scb = (double *)su;                  // Cbar on window nodes
     double *spm = scb + (kWinA + 1);             // masses of the Q^n window
+    int *sjn = (int *)(spm + (kWinA + 1));       // ordered scatter: node window index
+    double *sct = (double *)(sjn + kStepNodes);  //   and the pass's term per node
     // direct path
     int64_t *sgd = (int64_t *)su;
 
@@ -373,7 +385,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_sh(StepAdjArgs a)
                 if (t == 0) {
                     double tot = 0.0;
                     for (int wv = 0; wv < kBlock / 64; ++wv) tot += sred[wv];
-                    atomicAdd(&a.v0bar[row], a.dt * tot);
+                    a.v0part[blockIdx.x] = a.dt * tot;
                 }
             }
             return;
@@ -429,22 +441,59 @@ __global__ __launch_bounds__(kBlock) void k_adj_sh(StepAdjArgs a)
         // V_e = C(g) + sum_{a != lo} w_a (C(g-lo+a) - C(g)): the node's own
         // cumulative enters with weight exactly one, so the suffix sums of
         // cells below the stencil telescope without the weights' rounding
+        if constexpr (L::ordered) {
+            double part[NI];
 #pragma unroll
-        for (int k = 0; k < NI; ++k) {
-            if (t + k * kBlock < NE) {
-                const int jc = (int)(g[k] - wlo);
-                double part = 0.0;
+            for (int k = 0; k < NI; ++k) {
+                const int e = t + k * kBlock;
+                part[k] = 0.0;
+                if (e < NE) {
+                    sjn[e] = (int)(g[k] - wlo);
 #pragma unroll
-                for (int b = 0; b <= P; ++b) {
-                    if (b == LO) continue;
-                    const double c = (double)w[k][b] * vb[k];
-                    atomicAdd(&scb[jc - LO + b], c);
-                    part += c;
+                    for (int b = 0; b <= P; ++b)
+                        if (b != LO) part[k] += (double)w[k][b] * vb[k];
                 }
-                atomicAdd(&scb[jc], vb[k] - part);
             }
+            // pass b: node e's term goes to window node jc_e - lo + b; the
+            // targets rise with e, equal only for nodes in one source cell
+#pragma unroll
+            for (int b = 0; b <= P; ++b) {
+#pragma unroll
+                for (int k = 0; k < NI; ++k) {
+                    const int e = t + k * kBlock;
+                    if (e < NE) sct[e] = b == LO ? vb[k] - part[k] : (double)w[k][b] * vb[k];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < NI; ++k) {
+                    const int e = t + k * kBlock;
+                    if (e < NE && (e == 0 || sjn[e - 1] != sjn[e])) {
+                        const int jc = sjn[e];
+                        double sum = sct[e];
+                        for (int f = e + 1; f < NE && sjn[f] == jc; ++f) sum += sct[f];
+                        scb[jc - LO + b] += sum;
+                    }
+                }
+                __syncthreads();
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < NI; ++k) {
+                if (t + k * kBlock < NE) {
+                    const int jc = (int)(g[k] - wlo);
+                    double part = 0.0;
+#pragma unroll
+                    for (int b = 0; b <= P; ++b) {
+                        if (b == LO) continue;
+                        const double c = (double)w[k][b] * vb[k];
+                        atomicAdd(&scb[jc - LO + b], c);
+                        part += c;
+                    }
+                    atomicAdd(&scb[jc], vb[k] - part);
+                }
+            }
+            __syncthreads();
         }
-        __syncthreads();
         // ---- suffix sums over the window nodes -----------------------------
         const int NN = W + 1;
         const int per = (NN + kBlock - 1) / kBlock;
@@ -598,7 +647,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_sh(StepAdjArgs a)
         if (t == 0) {
             double tot = 0.0;
             for (int wv = 0; wv < kBlock / 64; ++wv) tot += sred[wv];
-            atomicAdd(&a.v0bar[row], a.dt * tot);
+            a.v0part[blockIdx.x] = a.dt * tot;
         }
     }
 }
@@ -629,7 +678,9 @@ hipError_t adj_order(const StepAdjArgs &a, hipStream_t st)
     const dim3 g((unsigned)a.rows.n_tiles), b(kBlock);
     if (a.dv) hipLaunchKernelGGL((k_adj_sh<TQ, P, true>), g, b, 0, st, a);
     else hipLaunchKernelGGL((k_adj_sh<TQ, P, false>), g, b, 0, st, a);
-    return hipGetLastError();
+    e = hipGetLastError();
+    if (e != hipSuccess || !(a.v0bar && a.q_fwd)) return e;
+    return launch_v0_reduce(a.rows, a.v0part, a.v0bar, st);
 }
 
 template <typename TQ>

@@ -483,6 +483,7 @@ ram_status step_adjoint_shared(ram_ctx *ctx, const ram_layout *layout, ram_dtype
     rp.uniform = dtype == RAM_F32;
     const int64_t nt = tiles_of(layout, rp.tile);
     const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(ram::kPlanW * sizeof(int32_t) * nt);
+    const size_t v0_off = cv.take(v0bar ? sizeof(double) * nt : 0);
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
     ram::StepArgs p;
     if ((st = make_rows(ctx, layout, edges, rp, p.rows)) != RAM_OK) return st;
@@ -501,6 +502,7 @@ ram_status step_adjoint_shared(ram_ctx *ctx, const ram_layout *layout, ram_dtype
     a.qbar_in = qbar_in;
     a.dvbar = dvbar;
     a.v0bar = v0bar;
+    a.v0part = (double *)((char *)ctx->scratch + v0_off);
     a.v0 = v0;
     a.dt = dt;
     a.plan_wlo = wlo;
@@ -1007,6 +1009,8 @@ ram_status ram_shift_limited_adjoint(ram_ctx *ctx, const ram_layout *layout,
     Carve cv;
     // a shared mesh brings its tables (centre gaps, PPM weights)
     RowsPlan rp = plan_rows(cv, layout, ram::kAdjTile, 1);
+    const size_t v0_off =
+        cv.take(v0bar_accum ? sizeof(double) * tiles_of(layout, ram::kAdjTile) : 0);
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
     ram::ShiftAdjArgs a;
     if ((st = make_rows(ctx, layout, edges, rp, a.rows)) != RAM_OK) return st;
@@ -1016,6 +1020,7 @@ ram_status ram_shift_limited_adjoint(ram_ctx *ctx, const ram_layout *layout,
     a.v0 = v0;
     a.dt = dt;
     a.v0bar = v0bar_accum;
+    a.v0part = (double *)((char *)ctx->scratch + v0_off);
     hipError_t e = ram::launch_shift_limited_adjoint(a, dtype == RAM_F64, (int)recon,
                                                      ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "limited shift adjoint launch");
@@ -1355,6 +1360,8 @@ ram_status ram_shift_adjoint(ram_ctx *ctx, const ram_layout *layout,
                                    qbar_in, edges, v0, dt, order, nullptr, v0bar_accum);
     Carve cv;
     RowsPlan rp = plan_rows(cv, layout, ram::kAdjTile, 0);
+    const size_t v0_off =
+        cv.take(v0bar_accum ? sizeof(double) * tiles_of(layout, ram::kAdjTile) : 0);
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
     ram::ShiftAdjArgs a;
     if ((st = make_rows(ctx, layout, edges, rp, a.rows)) != RAM_OK) return st;
@@ -1364,6 +1371,7 @@ ram_status ram_shift_adjoint(ram_ctx *ctx, const ram_layout *layout,
     a.v0 = v0;
     a.dt = dt;
     a.v0bar = v0bar_accum;
+    a.v0part = (double *)((char *)ctx->scratch + v0_off);
     hipError_t e = ram::launch_shift_adjoint(a, dtype == RAM_F64, order, ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "shift adjoint launch");
     return RAM_OK;
@@ -1480,6 +1488,8 @@ ram_status ram_step_adjoint(ram_ctx *ctx, const ram_layout *layout,
     Carve cv;
     const size_t mid_off = dv ? cv.take(state_bytes) : 0;
     RowsPlan rp = plan_rows(cv, layout, ram::kAdjTile, 0);
+    const size_t v0_off =
+        cv.take(v0bar_accum ? sizeof(double) * tiles_of(layout, ram::kAdjTile) : 0);
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
     ram::Rows rows;
     if ((st = make_rows(ctx, layout, edges, rp, rows)) != RAM_OK) return st;
@@ -1506,6 +1516,7 @@ ram_status ram_step_adjoint(ram_ctx *ctx, const ram_layout *layout,
     a.v0 = v0;
     a.dt = dt;
     a.v0bar = v0bar_accum;
+    a.v0part = (double *)((char *)ctx->scratch + v0_off);
     e = ram::launch_shift_adjoint(a, dtype == RAM_F64, order, ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "shift adjoint launch");
     return RAM_OK;

@@ -55,6 +55,7 @@ struct MeshTab {
     int32_t nb = 0;
     const double *scal = nullptr;     // device scalars: nb / L, 1 / L, x0 nb / L
     const float2 *rrf = nullptr;      // per cell: (dx, 1/centre gap), FP32
+    const float4 *geof = nullptr;     // per cell: (dx, 1/centre gap, 1/dx, 0), FP32
     const double2 *rrd = nullptr;     // the same in FP64
     const void *crf = nullptr;        // CellRec<float>[n]
     const void *crd = nullptr;        // CellRec<double>[n]
@@ -240,6 +241,7 @@ struct ShiftAdjArgs {
     const double *v0 = nullptr;
     double dt = 0.0;
     double *v0bar = nullptr;          // per-row accumulator or null
+    double *v0part = nullptr;         // [n_tiles] each tile's v0bar term (v0bar set)
 };
 
 // One step backwards on a shared mesh (fused residual adjoint, then shift
@@ -253,6 +255,7 @@ struct StepAdjArgs {
     void *qbar_in = nullptr;
     void *dvbar = nullptr;              // accumulator or null
     double *v0bar = nullptr;            // accumulator or null
+    double *v0part = nullptr;           // [n_tiles] each tile's v0bar term (v0bar set)
     const double *v0 = nullptr;
     double dt = 0.0;
     const int64_t *plan_wlo = nullptr;  // window plan of the shift (no halo)
@@ -325,6 +328,11 @@ hipError_t launch_shift_adjoint(const ShiftAdjArgs &a, bool f64, int order,
                                 hipStream_t stream);
 hipError_t launch_residual_adjoint(const ResidualAdjArgs &a, bool f64,
                                    hipStream_t stream);
+// v0bar[row] += the row's per-tile terms part[tile], summed in tile order (the
+// adjoint kernels write one term per tile instead of adding atomically, so
+// that v0bar does not depend on the order the tiles finish in).
+hipError_t launch_v0_reduce(const Rows &R, const double *part, double *v0bar,
+                            hipStream_t stream);
 // Zero the cells several tiles accumulate into, then the fused adjoint.
 hipError_t launch_step_adjoint_shared(const StepAdjArgs &a, bool f64, int order,
                                       hipStream_t stream);
