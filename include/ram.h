@@ -180,8 +180,8 @@ ram_status ram_shift(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
  * 4 nodes a thread), never the streaming FP32 kernel whose per-call plan is
  * far larger; results agree with ram_shift under the same schedule bit for
  * bit, and with the default schedule to rounding.  Layouts needing more than
- * the buffer (a shared mesh's tables take about 530 bytes a cell, so meshes
- * beyond about 30000 cells; a ragged batch's tile table 4 bytes a tile and 8
+ * the buffer (a shared mesh's tables take about 560 bytes a cell, so meshes
+ * beyond about 29000 cells; a ragged batch's tile table 4 bytes a tile and 8
  * a row) return RAM_E_NOMEM with the required size in ram_last_error, before
  * any device work.  Every call on a GPU shares that GPU's buffer and rewrites all
  * of what it reads (nothing must start at zero): calls that overlap on one GPU

@@ -55,7 +55,12 @@ struct MeshTab {
     int32_t nb = 0;
     const double *scal = nullptr;     // device scalars: nb / L, 1 / L, x0 nb / L
     const float2 *rrf = nullptr;      // per cell: (dx, 1/centre gap), FP32
-    const float4 *geof = nullptr;     // per cell: (dx, 1/centre gap, 1/dx, 0), FP32
+    // FP32 stencil data of each source cell in planes (float4 [n], float4 [n],
+    // float [n] back to back): the offsets th_b other than the cell's own edges
+    // (0 and 1), then the reciprocal denominators rd_b other than the own
+    // node's, in that order (nine values at order 5); planes, so that the
+    // records of neighbouring cells are neighbours in memory
+    const float *stp = nullptr;
     const double2 *rrd = nullptr;     // the same in FP64
     const void *crf = nullptr;        // CellRec<float>[n]
     const void *crd = nullptr;        // CellRec<double>[n]

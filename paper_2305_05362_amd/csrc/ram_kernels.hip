@@ -567,6 +567,7 @@ struct MeshTabW {
     CellRec<float> *crf;
     CellRec<double> *crd;
     float2 *rrf;
+    float *stp;
     double2 *rrd;
     double *ppmd;
     float *ppmf;
@@ -594,7 +595,9 @@ __global__ __launch_bounds__(256) void k_mesh_prep(const double *x, int n, MeshT
         double th[P + 1];
         const double xc = x[j];
         for (int a = 0; a <= P; ++a) th[a] = (node_x(x, n, len, j - LO + a) - xc) / dx;
+        // the cell's own edges, exactly (the FP32 streaming kernel relies on it)
         th[LO] = 0.0;
+        th[LO + 1] = 1.0;
         double *st = T.stc + j * (2 * (P + 1));
         float *sf = T.stcf + j * (2 * (P + 1));
         CellRec<float> rf;
@@ -620,6 +623,19 @@ __global__ __launch_bounds__(256) void k_mesh_prep(const double *x, int n, MeshT
         }
         T.crf[j] = rf;
         T.crd[j] = rd;
+        {
+            float v[9];
+            int k = 0;
+            for (int a = 0; a <= P; ++a)
+                if (a != LO && a != LO + 1) v[k++] = rf.th[a];
+            for (int a = 0; a <= P; ++a)
+                if (a != LO) v[k++] = rf.rd[a];
+            for (; k < 9; ++k) v[k] = 0.0f;
+            float4 *p4 = (float4 *)T.stp;
+            p4[j] = make_float4(v[0], v[1], v[2], v[3]);
+            p4[n + j] = make_float4(v[4], v[5], v[6], v[7]);
+            T.stp[8 * n + j] = v[8];
+        }
         const PpmW pw = ppm_weights(x[wrap_small(j - 1, n) + 1] - x[wrap_small(j - 1, n)], dx,
                                     x[wrap_small(j + 1, n) + 1] - x[wrap_small(j + 1, n)],
                                     x[wrap_small(j + 2, n) + 1] - x[wrap_small(j + 2, n)]);
@@ -800,7 +816,7 @@ size_t mesh_tab_bytes(int64_t n, int order)
     return 3 * al256(8 * n) + 3 * al256(4 * n) + al256(8 * n * 2 * (order + 1)) +
            al256(4 * n * 2 * (order + 1)) + al256(4 * nb) + al256(16 * nb) + al256(16) +
            al256(sizeof(CellRec<float>) * n) + al256(sizeof(CellRec<double>) * n) +
-           al256(8 * n) + al256(16 * n) + al256(40 * n) + al256(20 * n) +
+           al256(8 * n) + al256(36 * n) + al256(16 * n) + al256(40 * n) + al256(20 * n) +
            2 * al256(4 * (n + 1));
 }
 
@@ -824,6 +840,7 @@ hipError_t launch_mesh_prep(const double *x, int64_t n, int order, void *mem,
     w.crf = (CellRec<float> *)p; p += al256(sizeof(CellRec<float>) * n);
     w.crd = (CellRec<double> *)p; p += al256(sizeof(CellRec<double>) * n);
     w.rrf = (float2 *)p; p += al256(8 * n);
+    w.stp = (float *)p; p += al256(36 * n);
     w.rrd = (double2 *)p; p += al256(16 * n);
     w.ppmd = (double *)p; p += al256(40 * n);
     w.ppmf = (float *)p; p += al256(20 * n);
@@ -838,6 +855,7 @@ hipError_t launch_mesh_prep(const double *x, int64_t n, int order, void *mem,
     tab.crf = w.crf;
     tab.crd = w.crd;
     tab.rrf = w.rrf;
+    tab.stp = w.stp;
     tab.rrd = w.rrd;
     tab.ppmd = w.ppmd;
     tab.ppmf = w.ppmf;

@@ -326,14 +326,16 @@ __device__ __forceinline__ void uniform_tile(const StepArgs &a, const FastTile &
 // ---------------------------------------------------------------------------
 
 // The k-th non-uniform tile's nodes (k = list position - totals[0]): window
-// index and FP32 theta of nodes i0-H .. i0+nd+H; a node outside the window
-// (not expected: the plan sized it from the end nodes) turns the tile into a
-// direct one.  One wave per tile.
+// index and FP32 theta of nodes i0-H .. i0+nd+H, and in the slots past the
+// last node (up to kFastNodes) the last node again, so that whole 16-byte
+// groups of slots can be read; a node outside the window (not expected: the
+// plan sized it from the end nodes) turns the tile into a direct one, in both
+// copies of its record.  One wave per tile.
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_node_plan(StepArgs a)
 {
     constexpr int LO = (P - 1) / 2;
-    constexpr int NS = (kFT + 5 + kLanes - 1) / kLanes;
+    constexpr int NS = (kFastNodes + kLanes - 1) / kLanes;
     const Rows &R = a.rows;
     const int nu = a.fast.totals[0];
     const int nt = (int)R.n_tiles;
@@ -360,8 +362,8 @@ __global__ __launch_bounds__(kBlock) void k_node_plan(StepArgs a)
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         const int m = t + s * kLanes;
-        if (m < NE) {
-            int e = tp.i0 - H + m;
+        if (m < kFastNodes) {
+            int e = tp.i0 - H + min(m, NE - 1);
             const int kx = e < 0 ? -n : (e >= n ? n : 0);
             e -= kx;
             const NodePos np = node_pos(x[e], rs, x0, xN, tb.scal[0], tb.scal[2], tb.nb);
@@ -375,7 +377,10 @@ __global__ __launch_bounds__(kBlock) void k_node_plan(StepArgs a)
             jcw[m] = (int16_t)min(max(j, 0), kFastWin);
         }
     }
-    if (!__all(ok ? 1 : 0) && t == 0) a.fast.rec[ft.pad[0]].kind = kFastDirect;
+    if (!__all(ok ? 1 : 0) && t == 0) {
+        a.fast.rec[ft.pad[0]].kind = kFastDirect;
+        crec[nu + k].kind = kFastDirect;
+    }
 }
 
 template <int P, int H, bool VEC>
@@ -574,6 +579,212 @@ __device__ __forceinline__ void general_tile(const StepArgs &a, const FastTile &
 }
 
 // ---------------------------------------------------------------------------
+// A searching tile whose window fits the wave's LDS, on rows of a multiple of
+// four cells (16-byte aligned), with every load of a phase in flight at once:
+//   1. the nodes' plan (window index, theta), the window's values and cell
+//      sizes in 16-byte groups, the faces' residual velocity;
+//   2. the window masses into LDS; the stencil data of all the lane's
+//      nodes' source cells (three planes of the mesh table);
+//   3. each node's Lagrange weights and partial integral (from the masses
+//      beside its window cell) into LDS;
+//   4. each shifted cell's mass (the whole window cells between its nodes
+//      plus the difference of the two partial integrals), while the cell
+//      geometry of the residual is on its way;
+//   5. the masses through LDS to four consecutive cells a lane and their
+//      residual neighbourhoods, the residual, 16-byte stores.
+// Nodes and shifted cells go to lanes in turn (node m, cell ci on lane
+// m mod 64, counted from the tile's first halo node/cell), so that the LDS
+// gathers of neighbouring lanes fall on neighbouring words: four consecutive
+// nodes a lane put their gathers 16 bytes apart, eight lanes on each bank.
+// The window is stored from the 16-byte boundary at or below its start (LDS
+// index j + off for window cell j), so that its groups go in whole.
+// ---------------------------------------------------------------------------
+
+template <int P, int H>
+__device__ __forceinline__ void window_tile(const StepArgs &a, const FastTile &ft,
+                                            unsigned char *su, float *sell, short *sjc, int t)
+{
+    constexpr int LO = (P - 1) / 2;
+    constexpr int NG = 2;                            // window groups of 4 a lane loads first
+    constexpr int NS = (kFT + 2 * H + 1 + kLanes - 1) / kLanes;   // node slots
+    constexpr int NCS = (kFT + 2 * H + kLanes - 1) / kLanes;      // shifted-cell slots
+    const Rows &R = a.rows;
+    const MeshTab &tb = R.tab;
+    const int n = (int)R.n_cols;
+    const int c4 = 4 * t;
+    const TilePos tp = tile_pos(ft.pad[0], n, H);
+    const int i0 = tp.i0, nd = tp.nd;
+    const int NC = nd + 2 * H;
+    const int64_t qoff = (int64_t)tp.row * n;
+    const float *q = (const float *)a.q_in + qoff;
+    float *qo = (float *)a.q_out + qoff;
+    const int W = ft.w, base = ft.base;
+    const int a0 = base & ~3, off = base - a0;
+    const int gl = (W + off - 1) >> 2;               // last window group
+    float *sw = (float *)su;                         // window mass j at sw[j + off]
+
+    // ---- 1. node plan, window, faces ------------------------------------------
+    const float *thp = a.fast.theta + (int64_t)ft.pad[1] * kFastNodes;
+    const int16_t *jcp = a.fast.jc + (int64_t)ft.pad[1] * kFastNodes;
+    float thv[NS];
+    int jv[NS];
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+        const int m = min(t + u * kLanes, kFastNodes - 1);
+        thv[u] = thp[m];
+        jv[u] = jcp[m];
+    }
+    float4 wq[NG], wd[NG];
+#pragma unroll
+    for (int u = 0; u < NG; ++u) {
+        int c = a0 + 4 * min(t + u * kLanes, gl);
+        c = c >= n ? c - n : c;
+        wq[u] = *(const float4 *)(q + c);
+        wd[u] = *(const float4 *)(tb.dxf + c);
+    }
+    float dvv[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    if constexpr (H != 0) load_faces<true>((const float *)a.dv + qoff, n, i0, nd, c4, dvv);
+    float4 di4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    if constexpr (H == 0) di4 = *(const float4 *)(tb.dxinvf + i0 + min(c4, nd - 4));
+#pragma unroll
+    for (int u = 0; u < NG; ++u) {
+        const int g = min(t + u * kLanes, gl);
+        *(float4 *)(sw + 4 * g) = make_float4(wq[u].x * wd[u].x, wq[u].y * wd[u].y,
+                                              wq[u].z * wd[u].z, wq[u].w * wd[u].w);
+    }
+    // windows longer than NG groups a lane (compressing stretches of mesh)
+    for (int u = NG; u * kLanes <= gl; ++u) {
+        const int g = min(t + u * kLanes, gl);
+        int c = a0 + 4 * g;
+        c = c >= n ? c - n : c;
+        const float4 vq = *(const float4 *)(q + c);
+        const float4 vd = *(const float4 *)(tb.dxf + c);
+        *(float4 *)(sw + 4 * g) = make_float4(vq.x * vd.x, vq.y * vd.y, vq.z * vd.z, vq.w * vd.w);
+    }
+
+    // ---- 2. stencil data of the nodes' source cells, all at once -----------------
+    // (planes: neighbouring lanes read neighbouring cells' data; the offsets
+    // of the cell's own edges are 0 and 1 exactly, the own node's weight is not
+    // needed)
+    constexpr int NV = 2 * P - 1;                    // values a cell
+    float rth[NS][P + 1], rrd[NS][P + 1];
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+        int c = base + jv[u];
+        c = c >= n ? c - n : c;
+        float v[12];
+        const float4 A = ((const float4 *)tb.stp)[c];
+        v[0] = A.x; v[1] = A.y; v[2] = A.z; v[3] = A.w;
+        if constexpr (NV > 4) {
+            const float4 B = ((const float4 *)tb.stp)[n + c];
+            v[4] = B.x; v[5] = B.y; v[6] = B.z; v[7] = B.w;
+        }
+        if constexpr (NV > 8) v[8] = tb.stp[8 * n + c];
+        int k = 0;
+#pragma unroll
+        for (int b = 0; b <= P; ++b)
+            rth[u][b] = b == LO ? 0.0f : (b == LO + 1 ? 1.0f : v[k++]);
+#pragma unroll
+        for (int b = 0; b <= P; ++b) rrd[u][b] = b == LO ? 0.0f : v[k++];
+    }
+    wave_sync();                                     // the window masses
+
+    // ---- 3. weights and partial integrals C~(x) - C(c), summed outward ------------
+    // (lanes past the last node repeat it: the plan's padding, same slots)
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+        const float th = thv[u];
+        float tt[P + 1], pre[P + 1], suf[P + 1], wk[P + 1];
+#pragma unroll
+        for (int b = 0; b <= P; ++b) tt[b] = th - rth[u][b];
+        pre[0] = 1.0f;
+#pragma unroll
+        for (int b = 1; b <= P; ++b) pre[b] = pre[b - 1] * tt[b - 1];
+        suf[P] = 1.0f;
+#pragma unroll
+        for (int b = P - 1; b >= 0; --b) suf[b] = suf[b + 1] * tt[b + 1];
+#pragma unroll
+        for (int b = 0; b <= P; ++b) wk[b] = rrd[u][b] * (pre[b] * suf[b]);
+        const int j = jv[u] + off;
+        float e = 0.0f, up = 0.0f, dn = 0.0f;
+#pragma unroll
+        for (int b = LO + 1; b <= P; ++b) {
+            up += sw[j + b - LO - 1];
+            e += wk[b] * up;
+        }
+#pragma unroll
+        for (int b = LO - 1; b >= 0; --b) {
+            dn += sw[j - LO + b];
+            e -= wk[b] * dn;
+        }
+        const int m = min(t + u * kLanes, kFastNodes - 1);
+        sell[m] = e;
+        sjc[m] = (short)j;
+    }
+    wave_sync();
+
+    // ---- 4. shifted masses (lanes past the last cell repeat it) --------------------
+    float ms[NCS];
+#pragma unroll
+    for (int u = 0; u < NCS; ++u) {
+        const int ci = min(t + u * kLanes, NC - 1);
+        const int ja = sjc[ci], jb = sjc[ci + 1];
+        const float m0 = sw[ja], m1 = sw[ja + 1];
+        float whole = jb > ja ? m0 : 0.0f;
+        whole += jb > ja + 1 ? m1 : 0.0f;
+        for (int mm = ja + 2; mm < jb; ++mm) whole += sw[mm];
+        ms[u] = whole + (sell[ci + 1] - sell[ci]);
+    }
+    // geometry of cells i0+4l-2 .. i0+4l+5 (lanes past the tile: its last
+    // cells): (dx, 1/centre gap) as four 16-byte pairs, 1/dx as 8 + 16 + 8
+    // bytes (the row holds a multiple of four cells: no group straddles its end)
+    float2 rr[8];
+    float dxi[8];
+    if constexpr (H != 0) {
+        const int cb = i0 + min(c4, nd - 4) - 2;
+        auto wr = [&](int c) { return c < 0 ? c + n : (c >= n ? c - n : c); };
+#pragma unroll
+        for (int pr = 0; pr < 4; ++pr) {
+            const float4 r2 = *(const float4 *)(tb.rrf + wr(cb + 2 * pr));
+            rr[2 * pr] = make_float2(r2.x, r2.y);
+            rr[2 * pr + 1] = make_float2(r2.z, r2.w);
+        }
+        const float2 d0 = *(const float2 *)(tb.dxinvf + wr(cb));
+        const float4 d1 = *(const float4 *)(tb.dxinvf + wr(cb + 2));
+        const float2 d2 = *(const float2 *)(tb.dxinvf + wr(cb + 6));
+        dxi[0] = d0.x; dxi[1] = d0.y;
+        dxi[2] = d1.x; dxi[3] = d1.y; dxi[4] = d1.z; dxi[5] = d1.w;
+        dxi[6] = d2.x; dxi[7] = d2.y;
+    }
+    wave_sync();                                     // the window is dead
+    float *sm = (float *)su;                         // shifted masses, index ci
+#pragma unroll
+    for (int u = 0; u < NCS; ++u) sm[min(t + u * kLanes, NC - 1)] = ms[u];
+    wave_sync();
+
+    // ---- 5. residual (or, without one, the shifted values) ------------------------
+    if (c4 < nd) {
+        if constexpr (H == 0) {
+            const float4 m4 = *(const float4 *)(sm + c4);
+            float o[4] = {m4.x * di4.x, m4.y * di4.y, m4.z * di4.z, m4.w * di4.w};
+            store_cells<true>(qo, i0, nd, c4, o);
+        } else {
+            const float4 m0 = *(const float4 *)(sm + c4), m1 = *(const float4 *)(sm + c4 + 4);
+            const float mv[8] = {m0.x, m0.y, m0.z, m0.w, m1.x, m1.y, m1.z, m1.w};
+            float sv[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) sv[c] = mv[c] * dxi[c];
+            if (a.q_mid)
+                *(float4 *)((float *)a.q_mid + qoff + i0 + c4) = make_float4(sv[2], sv[3], sv[4], sv[5]);
+            float o[4];
+            residual4(sv, dvv, (float)a.dt, [&](int c) { return rr[c]; },
+                      [&](int kk) { return dxi[kk + 2]; }, o);
+            store_cells<true>(qo, i0, nd, c4, o);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // The compacted records, in tile order: uniform tiles first, then the others
 // (for the node plan), each with its tile id in pad[0]; the others' position
 // among them (their node data) in pad[1] of both copies.
@@ -680,6 +891,11 @@ __global__ __launch_bounds__(kBlock, 8) void k_step_uni(StepArgs a)
     uniform_tile<P, H, VEC>(a, r, swin[wid], (int)threadIdx.x % kLanes);
 }
 
+// The other tiles: a grid of a quarter of the tile count in waves (the host
+// does not know how many there are; a quarter covers the refined disk with
+// one tile a wave), each wave stepping through the list by the grid's size.
+constexpr int kGenShare = 4;
+
 template <int P, int H, bool VEC>
 __global__ __launch_bounds__(kBlock) void k_step_gen(StepArgs a)
 {
@@ -687,18 +903,27 @@ __global__ __launch_bounds__(kBlock) void k_step_gen(StepArgs a)
     __shared__ __attribute__((aligned(16))) float sell_[kWaves][WaveLds::nodes];
     __shared__ __attribute__((aligned(16))) short sjc_[kWaves][WaveLds::nodes];
     const int wid = wave_id();
-    const int i = a.fast.totals[0] + (int)blockIdx.x * kWaves + wid;
-    if (i >= a.rows.n_tiles) return;
-    const FastTile r = load_rec(a.fast.rec + a.rows.n_tiles, i);
-    general_tile<P, H, VEC>(a, r, su[wid], sell_[wid], sjc_[wid], (int)threadIdx.x % kLanes);
+    const int nt = (int)a.rows.n_tiles;
+    const int n = (int)a.rows.n_cols;
+    const int t = (int)threadIdx.x % kLanes;
+    const int stride = (int)gridDim.x * kWaves;
+    for (int i = a.fast.totals[0] + (int)blockIdx.x * kWaves + wid; i < nt; i += stride) {
+        const FastTile r = load_rec(a.fast.rec + nt, i);
+        if (VEC && r.kind == kFastWindow && r.base + r.w + 3 < 2 * n)
+            window_tile<P, H>(a, r, su[wid], sell_[wid], sjc_[wid], t);
+        else
+            general_tile<P, H, VEC>(a, r, su[wid], sell_[wid], sjc_[wid], t);
+        wave_sync();                                 // the next tile reuses the LDS
+    }
 }
 
 template <int P, int H, bool VEC>
 hipError_t step_fast_kernels(const StepArgs &a, hipStream_t st)
 {
     const dim3 g((unsigned)((a.rows.n_tiles + kWaves - 1) / kWaves)), b(kBlock);
+    const dim3 gg((unsigned)((a.rows.n_tiles + kWaves * kGenShare - 1) / (kWaves * kGenShare)));
     hipLaunchKernelGGL((k_step_uni<P, H, VEC>), g, b, 0, st, a);
-    hipLaunchKernelGGL((k_step_gen<P, H, VEC>), g, b, 0, st, a);
+    hipLaunchKernelGGL((k_step_gen<P, H, VEC>), gg, b, 0, st, a);
     return hipGetLastError();
 }
 
@@ -706,6 +931,8 @@ template <int P>
 hipError_t step_fast_p(const StepArgs &a, hipStream_t st)
 {
     const bool vec = (a.rows.n_cols % 4) == 0 && ((uintptr_t)a.q_out % 16) == 0 &&
+                     ((uintptr_t)a.q_in % 16) == 0 &&
+                     (!a.q_mid || ((uintptr_t)a.q_mid % 16) == 0) &&
                      (!a.dv || ((uintptr_t)a.dv % 16) == 0);
     if (a.dv) return vec ? step_fast_kernels<P, 2, true>(a, st) : step_fast_kernels<P, 2, false>(a, st);
     return vec ? step_fast_kernels<P, 0, true>(a, st) : step_fast_kernels<P, 0, false>(a, st);
