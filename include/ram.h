@@ -96,11 +96,16 @@ typedef struct ram_ctx ram_ctx;
 ram_status ram_create(ram_ctx **ctx, int device, void *stream);
 /* Release the context and its scratch (after waiting for its stream). */
 ram_status ram_destroy(ram_ctx *ctx);
-/* Launch schedule of the shared-mesh step kernel with RAM_SUM_DIRECT (the
- * library's fastest path).  0, the default, runs the FP32 streaming kernel
- * (tiles of 256 destination cells, one a wave, four consecutive cells a lane;
- * FP64 takes the general kernel with 4 nodes per thread).  2..5 select the general
- * kernel with that many shifted nodes per thread: each workgroup of 256
+/* Launch schedule of the shared-mesh step kernel.  0, the default, runs the
+ * FP32 streaming kernels for every cumulative mode (tiles of 256 destination
+ * cells, one a wave, four consecutive cells a lane; a tile in a uniform run
+ * of the mesh is a fixed stencil on the cell values, whose cumulative
+ * differences cancel exactly, so the mode governs the other tiles; rows whose
+ * length is not a multiple of four, or arrays not 16-byte aligned, sum those
+ * tiles' cumulative differences directly whatever the mode); FP64 takes the
+ * general kernel with 4 nodes per thread.  2..5 select the general
+ * kernel with that many shifted nodes per thread (RAM_SUM_DIRECT; the prefix
+ * modes then take 4): each workgroup of 256
  * threads shifts 256 * items_per_thread nodes, a tile of
  * 256 * items_per_thread - 1 destination cells (4 fewer when the residual
  * step is fused in).  Larger tiles mean fewer workgroups and less overlap
@@ -108,7 +113,7 @@ ram_status ram_destroy(ram_ctx *ctx);
  * the best choice depends on the row length and the GPU, which is what an
  * autotuner measures.  Other values than 0 and 2..5 give RAM_E_UNSUPPORTED.
  * The schedule is per context and applies to later ram_shift, ram_step and
- * ram_step_record calls on shared meshes with RAM_SUM_DIRECT.  Every cell
+ * ram_step_record calls on shared meshes.  Every cell
  * goes through the same operations under any schedule; results agree to
  * rounding, not bit for bit (each variant is compiled on its own, and the
  * compiler may fuse multiply-adds differently in each). */

@@ -276,15 +276,15 @@ int sched_items(const ram_ctx *ctx, const ram_layout *L, ram_scan scan)
     return (shared && scan == RAM_SUM_DIRECT && ctx->items != 0) ? ctx->items : ram::kItems;
 }
 
-// The FP32 direct-sum Lagrange step on a shared mesh at the default schedule
-// and the bucket index runs the streaming kernel (k_step_fast, tiles of
-// kFastTile cells a wave); every other combination the general shared-mesh
-// kernel.
+// The FP32 Lagrange step on a shared mesh at the default schedule and the
+// bucket index runs the streaming kernels (k_step_uni / k_step_gen, tiles of
+// kFastTile cells a wave; every cumulative mode); every other combination the
+// general shared-mesh kernel.
 bool use_fast_shape(const ram_ctx *ctx, bool shared, int64_t n_cols, ram_dtype dtype,
                     ram_scan scan)
 {
-    return shared && n_cols > 0 && dtype == RAM_F32 && scan == RAM_SUM_DIRECT &&
-           ctx->items == 0 && ctx->density.kind == RAM_DENSITY_NONE;
+    return shared && n_cols > 0 && dtype == RAM_F32 && ctx->items == 0 &&
+           ctx->density.kind == RAM_DENSITY_NONE;
 }
 bool use_fast(const ram_ctx *ctx, const ram_layout *L, ram_dtype dtype, ram_scan scan)
 {
@@ -669,7 +669,7 @@ ram_status ram_shift(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
     Carve cv;
     RowsPlan rp = plan_rows(cv, layout, step_tile_of(ctx, layout, dtype, scan, items, false),
                             order);
-    rp.uniform = wants_uniform(dtype, scan);
+    rp.uniform = wants_uniform(dtype, scan) || use_fast(ctx, layout, dtype, scan);
     const int64_t nt = tiles_of(layout, rp.tile);
     const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(plan_w_bytes(nt));
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
@@ -777,7 +777,7 @@ ram_status ram_step(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
     const int items = sched_items(ctx, layout, scan);
     RowsPlan rp = plan_rows(cv, layout,
                             step_tile_of(ctx, layout, dtype, scan, items, dv != nullptr), order);
-    rp.uniform = wants_uniform(dtype, scan);
+    rp.uniform = wants_uniform(dtype, scan) || use_fast(ctx, layout, dtype, scan);
     const int64_t nt = tiles_of(layout, rp.tile);
     const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(plan_w_bytes(nt));
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
@@ -1125,7 +1125,7 @@ ram_status setup_row_step(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtyp
     RowsPlan rp = plan_rows(cv, layout,
                             fast ? ram::kFastTile : ram::step_tile_for(rs.items, dv != nullptr),
                             plan_order);
-    rp.uniform = dtype == RAM_F32 && (recon != 0 || scan == RAM_SUM_DIRECT);
+    rp.uniform = dtype == RAM_F32 && (recon != 0 || scan == RAM_SUM_DIRECT || fast);
     const int64_t nt = tiles_of(layout, rp.tile);
     const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(plan_w_bytes(nt));
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
@@ -1432,7 +1432,7 @@ ram_status ram_step_record(ram_ctx *ctx, const ram_layout *layout,
     RowsPlan rp = plan_rows(cv, layout,
                             fast ? ram::kFastTile : ram::step_tile_for(items, dv != nullptr),
                             order);
-    rp.uniform = wants_uniform(dtype, scan);
+    rp.uniform = wants_uniform(dtype, scan) || use_fast(ctx, layout, dtype, scan);
     const int64_t nt = tiles_of(layout, rp.tile);
     const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(plan_w_bytes(nt));
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;

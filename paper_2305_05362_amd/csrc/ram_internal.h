@@ -215,7 +215,7 @@ struct StepArgs {
                                         // [n_tiles + tile]: start mod n
     void *q_mid = nullptr;              // optional: the state after the shift
     MeshDensity dens;                   // shared mesh, direct sums: closed-form index
-    FastPlan fast;                      // FP32 direct sums: the k_step_fast tiles (rec set)
+    FastPlan fast;                      // FP32 streaming kernels: their tile plan (rec set)
 };
 
 // Radial transport of a polar grid (rows = radii): q [n_rows][n_cols], u on
@@ -326,7 +326,7 @@ hipError_t launch_step_shared(const StepArgs &a, bool f64, int scan, int order,
 // kernels (a.fast set).
 hipError_t launch_plan_fast(const StepArgs &a, int order, const FastPlan &plan,
                             hipStream_t stream);
-hipError_t launch_step_fast(const StepArgs &a, int order, hipStream_t stream);
+hipError_t launch_step_fast(const StepArgs &a, int order, int scan, hipStream_t stream);
 hipError_t launch_residual(const ResidualArgs &a, bool f64,
                            hipStream_t stream);
 hipError_t launch_shift_adjoint(const ShiftAdjArgs &a, bool f64, int order,

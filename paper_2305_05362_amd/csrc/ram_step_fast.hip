@@ -33,6 +33,8 @@
 // non-uniform stretches.
 #include "ram_device.h"
 
+#include <type_traits>
+
 namespace ram {
 namespace {
 
@@ -54,7 +56,15 @@ struct WaveLds {
     static constexpr size_t shifted = sizeof(float) * (kFT + 4 + kFPad);
     static constexpr size_t u0 = win > gidx ? win : gidx;
     static constexpr size_t u = u0 > shifted ? u0 : shifted;
+    // the prefix modes keep the window's cumulative (8-byte values: FP64, or
+    // a two-sum pair) instead of its masses
+    static constexpr size_t pre = 8 * (kFastWin + 16);
+    static constexpr size_t u_pre = pre > u ? pre : u;
 };
+template <int S> constexpr size_t wave_lds_bytes()
+{
+    return S == kSumDirect ? WaveLds::u : WaveLds::u_pre;
+}
 
 // Every lane's LDS writes visible to the whole wave (a wave executes its LDS
 // instructions in order; the fences keep the compiler from moving accesses
@@ -600,10 +610,61 @@ __device__ __forceinline__ void general_tile(const StepArgs &a, const FastTile &
 // index j + off for window cell j), so that its groups go in whole.
 // ---------------------------------------------------------------------------
 
-template <int P, int H>
+// The prefix modes (S other than kSumDirect): the window's exclusive
+// cumulative of the masses, in the mode's precision (Acc<S>), at LDS index
+// j + off for window cell j and one past the window's last group; partial
+// integrals and whole-cell sums are then its differences (only differences:
+// the cells below the window start in the first group cancel).  Masses of
+// groups g = l + 64 s (s = 0, 1, ...), four a lane: each group's lane totals
+// scanned across the wave, the groups before carried on.
+template <int S>
+__device__ __forceinline__ void wave_prefix(typename Acc<S>::A *sp, const typename Acc<S>::M (&m)[4],
+                                            int g, int gl, typename Acc<S>::A &carry)
+{
+    using AC = Acc<S>;
+    using A = typename AC::A;
+    const int lane = (int)threadIdx.x % kLanes;
+    const bool live = g <= gl;
+    A tot = AC::zero();
+    if (live) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) tot = AC::add(tot, m[k]);
+    }
+    // inclusive scan of the lane totals over the wave
+    A inc = tot;
+#pragma unroll
+    for (int d = 1; d < kLanes; d <<= 1) {
+        const A y = AC::shfl_up(inc, d);
+        if (lane >= d) inc = AC::comb(y, inc);
+    }
+    A ex = AC::shfl_up(inc, 1);
+    if (lane == 0) ex = AC::zero();
+    A e = AC::comb(carry, ex);
+    if (live) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            sp[4 * g + k] = e;
+            e = AC::add(e, m[k]);
+        }
+        if (g == gl) sp[4 * g + 4] = e;
+    }
+    A wt;
+    if constexpr (sizeof(A) == 8 && !std::is_same<A, double>::value) {
+        wt = make_float2(__shfl(inc.x, kLanes - 1), __shfl(inc.y, kLanes - 1));
+    } else {
+        wt = __shfl(inc, kLanes - 1);
+    }
+    carry = AC::comb(carry, wt);
+}
+
+template <int P, int H, int S>
 __device__ __forceinline__ void window_tile(const StepArgs &a, const FastTile &ft,
                                             unsigned char *su, float *sell, short *sjc, int t)
 {
+    using AC = Acc<S == kSumDirect ? kScanF32 : S>;
+    using A = typename AC::A;
+    using M = typename AC::M;
+    constexpr bool kDirect = S == kSumDirect;
     constexpr int LO = (P - 1) / 2;
     constexpr int NG = 2;                            // window groups of 4 a lane loads first
     constexpr int NS = (kFT + 2 * H + 1 + kLanes - 1) / kLanes;   // node slots
@@ -634,32 +695,82 @@ __device__ __forceinline__ void window_tile(const StepArgs &a, const FastTile &f
         thv[u] = thp[m];
         jv[u] = jcp[m];
     }
+    // window values and cell sizes (FP64 sizes for the FP64 prefix)
+    constexpr bool kDx64 = S == kScanF64;
     float4 wq[NG], wd[NG];
+    double2 wd2[kDx64 ? NG : 1][2];
 #pragma unroll
     for (int u = 0; u < NG; ++u) {
         int c = a0 + 4 * min(t + u * kLanes, gl);
         c = c >= n ? c - n : c;
         wq[u] = *(const float4 *)(q + c);
-        wd[u] = *(const float4 *)(tb.dxf + c);
+        if constexpr (kDx64) {
+            wd2[u][0] = *(const double2 *)(tb.dx + c);
+            wd2[u][1] = *(const double2 *)(tb.dx + c + 2);
+        } else {
+            wd[u] = *(const float4 *)(tb.dxf + c);
+        }
     }
     float dvv[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
     if constexpr (H != 0) load_faces<true>((const float *)a.dv + qoff, n, i0, nd, c4, dvv);
     float4 di4 = make_float4(0.f, 0.f, 0.f, 0.f);
     if constexpr (H == 0) di4 = *(const float4 *)(tb.dxinvf + i0 + min(c4, nd - 4));
+    A *sp = (A *)su;                                 // prefix modes: cumulative at j + off
+    if constexpr (kDirect) {
 #pragma unroll
-    for (int u = 0; u < NG; ++u) {
-        const int g = min(t + u * kLanes, gl);
-        *(float4 *)(sw + 4 * g) = make_float4(wq[u].x * wd[u].x, wq[u].y * wd[u].y,
-                                              wq[u].z * wd[u].z, wq[u].w * wd[u].w);
-    }
-    // windows longer than NG groups a lane (compressing stretches of mesh)
-    for (int u = NG; u * kLanes <= gl; ++u) {
-        const int g = min(t + u * kLanes, gl);
-        int c = a0 + 4 * g;
-        c = c >= n ? c - n : c;
-        const float4 vq = *(const float4 *)(q + c);
-        const float4 vd = *(const float4 *)(tb.dxf + c);
-        *(float4 *)(sw + 4 * g) = make_float4(vq.x * vd.x, vq.y * vd.y, vq.z * vd.z, vq.w * vd.w);
+        for (int u = 0; u < NG; ++u) {
+            const int g = min(t + u * kLanes, gl);
+            *(float4 *)(sw + 4 * g) = make_float4(wq[u].x * wd[u].x, wq[u].y * wd[u].y,
+                                                  wq[u].z * wd[u].z, wq[u].w * wd[u].w);
+        }
+        // windows longer than NG groups a lane (compressing stretches of mesh)
+        for (int u = NG; u * kLanes <= gl; ++u) {
+            const int g = min(t + u * kLanes, gl);
+            int c = a0 + 4 * g;
+            c = c >= n ? c - n : c;
+            const float4 vq = *(const float4 *)(q + c);
+            const float4 vd = *(const float4 *)(tb.dxf + c);
+            *(float4 *)(sw + 4 * g) = make_float4(vq.x * vd.x, vq.y * vd.y, vq.z * vd.z, vq.w * vd.w);
+        }
+    } else {
+        A carry = AC::zero();
+        auto masses = [&](const float4 &vq, const float4 &vd, const double2 (&v2)[2], M (&m)[4]) {
+            if constexpr (kDx64) {
+                m[0] = AC::mass(vq.x, v2[0].x);
+                m[1] = AC::mass(vq.y, v2[0].y);
+                m[2] = AC::mass(vq.z, v2[1].x);
+                m[3] = AC::mass(vq.w, v2[1].y);
+            } else {
+                m[0] = (M)(vq.x * vd.x);
+                m[1] = (M)(vq.y * vd.y);
+                m[2] = (M)(vq.z * vd.z);
+                m[3] = (M)(vq.w * vd.w);
+            }
+        };
+#pragma unroll
+        for (int u = 0; u < NG; ++u) {
+            if (u * kLanes > gl) break;
+            M m[4];
+            masses(wq[u], wd[u], wd2[kDx64 ? u : 0], m);
+            wave_prefix<S == kSumDirect ? kScanF32 : S>(sp, m, t + u * kLanes, gl, carry);
+        }
+        for (int u = NG; u * kLanes <= gl; ++u) {
+            const int g = min(t + u * kLanes, gl);
+            int c = a0 + 4 * g;
+            c = c >= n ? c - n : c;
+            const float4 vq = *(const float4 *)(q + c);
+            float4 vd = make_float4(0.f, 0.f, 0.f, 0.f);
+            double2 v2[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+            if constexpr (kDx64) {
+                v2[0] = *(const double2 *)(tb.dx + c);
+                v2[1] = *(const double2 *)(tb.dx + c + 2);
+            } else {
+                vd = *(const float4 *)(tb.dxf + c);
+            }
+            M m[4];
+            masses(vq, vd, v2, m);
+            wave_prefix<S == kSumDirect ? kScanF32 : S>(sp, m, t + u * kLanes, gl, carry);
+        }
     }
 
     // ---- 2. stencil data of the nodes' source cells, all at once -----------------
@@ -706,16 +817,24 @@ __device__ __forceinline__ void window_tile(const StepArgs &a, const FastTile &f
 #pragma unroll
         for (int b = 0; b <= P; ++b) wk[b] = rrd[u][b] * (pre[b] * suf[b]);
         const int j = jv[u] + off;
-        float e = 0.0f, up = 0.0f, dn = 0.0f;
+        float e = 0.0f;
+        if constexpr (kDirect) {
+            float up = 0.0f, dn = 0.0f;
 #pragma unroll
-        for (int b = LO + 1; b <= P; ++b) {
-            up += sw[j + b - LO - 1];
-            e += wk[b] * up;
-        }
+            for (int b = LO + 1; b <= P; ++b) {
+                up += sw[j + b - LO - 1];
+                e += wk[b] * up;
+            }
 #pragma unroll
-        for (int b = LO - 1; b >= 0; --b) {
-            dn += sw[j - LO + b];
-            e -= wk[b] * dn;
+            for (int b = LO - 1; b >= 0; --b) {
+                dn += sw[j - LO + b];
+                e -= wk[b] * dn;
+            }
+        } else {
+            const A pc = sp[j];
+#pragma unroll
+            for (int b = 0; b <= P; ++b)
+                if (b != LO) e += wk[b] * (float)AC::diff(sp[j - LO + b], pc);
         }
         const int m = min(t + u * kLanes, kFastNodes - 1);
         sell[m] = e;
@@ -729,10 +848,15 @@ __device__ __forceinline__ void window_tile(const StepArgs &a, const FastTile &f
     for (int u = 0; u < NCS; ++u) {
         const int ci = min(t + u * kLanes, NC - 1);
         const int ja = sjc[ci], jb = sjc[ci + 1];
-        const float m0 = sw[ja], m1 = sw[ja + 1];
-        float whole = jb > ja ? m0 : 0.0f;
-        whole += jb > ja + 1 ? m1 : 0.0f;
-        for (int mm = ja + 2; mm < jb; ++mm) whole += sw[mm];
+        float whole;
+        if constexpr (kDirect) {
+            const float m0 = sw[ja], m1 = sw[ja + 1];
+            whole = jb > ja ? m0 : 0.0f;
+            whole += jb > ja + 1 ? m1 : 0.0f;
+            for (int mm = ja + 2; mm < jb; ++mm) whole += sw[mm];
+        } else {
+            whole = (float)AC::diff(sp[jb], sp[ja]);
+        }
         ms[u] = whole + (sell[ci + 1] - sell[ci]);
     }
     // geometry of cells i0+4l-2 .. i0+4l+5 (lanes past the tile: its last
@@ -896,10 +1020,10 @@ __global__ __launch_bounds__(kBlock, 8) void k_step_uni(StepArgs a)
 // one tile a wave), each wave stepping through the list by the grid's size.
 constexpr int kGenShare = 4;
 
-template <int P, int H, bool VEC>
+template <int P, int H, bool VEC, int S>
 __global__ __launch_bounds__(kBlock) void k_step_gen(StepArgs a)
 {
-    __shared__ __attribute__((aligned(16))) unsigned char su[kWaves][WaveLds::u];
+    __shared__ __attribute__((aligned(16))) unsigned char su[kWaves][wave_lds_bytes<S>()];
     __shared__ __attribute__((aligned(16))) float sell_[kWaves][WaveLds::nodes];
     __shared__ __attribute__((aligned(16))) short sjc_[kWaves][WaveLds::nodes];
     const int wid = wave_id();
@@ -910,32 +1034,43 @@ __global__ __launch_bounds__(kBlock) void k_step_gen(StepArgs a)
     for (int i = a.fast.totals[0] + (int)blockIdx.x * kWaves + wid; i < nt; i += stride) {
         const FastTile r = load_rec(a.fast.rec + nt, i);
         if (VEC && r.kind == kFastWindow && r.base + r.w + 3 < 2 * n)
-            window_tile<P, H>(a, r, su[wid], sell_[wid], sjc_[wid], t);
+            window_tile<P, H, S>(a, r, su[wid], sell_[wid], sjc_[wid], t);
         else
             general_tile<P, H, VEC>(a, r, su[wid], sell_[wid], sjc_[wid], t);
         wave_sync();                                 // the next tile reuses the LDS
     }
 }
 
-template <int P, int H, bool VEC>
+template <int P, int H, bool VEC, int S>
 hipError_t step_fast_kernels(const StepArgs &a, hipStream_t st)
 {
     const dim3 g((unsigned)((a.rows.n_tiles + kWaves - 1) / kWaves)), b(kBlock);
     const dim3 gg((unsigned)((a.rows.n_tiles + kWaves * kGenShare - 1) / (kWaves * kGenShare)));
     hipLaunchKernelGGL((k_step_uni<P, H, VEC>), g, b, 0, st, a);
-    hipLaunchKernelGGL((k_step_gen<P, H, VEC>), gg, b, 0, st, a);
+    hipLaunchKernelGGL((k_step_gen<P, H, VEC, S>), gg, b, 0, st, a);
     return hipGetLastError();
 }
 
+template <int P, int S>
+hipError_t step_fast_ps(const StepArgs &a, bool vec, hipStream_t st)
+{
+    if (a.dv) return vec ? step_fast_kernels<P, 2, true, S>(a, st) : step_fast_kernels<P, 2, false, S>(a, st);
+    return vec ? step_fast_kernels<P, 0, true, S>(a, st) : step_fast_kernels<P, 0, false, S>(a, st);
+}
+
 template <int P>
-hipError_t step_fast_p(const StepArgs &a, hipStream_t st)
+hipError_t step_fast_p(const StepArgs &a, int scan, hipStream_t st)
 {
     const bool vec = (a.rows.n_cols % 4) == 0 && ((uintptr_t)a.q_out % 16) == 0 &&
                      ((uintptr_t)a.q_in % 16) == 0 &&
                      (!a.q_mid || ((uintptr_t)a.q_mid % 16) == 0) &&
                      (!a.dv || ((uintptr_t)a.dv % 16) == 0);
-    if (a.dv) return vec ? step_fast_kernels<P, 2, true>(a, st) : step_fast_kernels<P, 2, false>(a, st);
-    return vec ? step_fast_kernels<P, 0, true>(a, st) : step_fast_kernels<P, 0, false>(a, st);
+    switch (scan) {
+    case kScanF64: return step_fast_ps<P, kScanF64>(a, vec, st);
+    case kScanTwoSum: return step_fast_ps<P, kScanTwoSum>(a, vec, st);
+    case kScanF32: return step_fast_ps<P, kScanF32>(a, vec, st);
+    default: return step_fast_ps<P, kSumDirect>(a, vec, st);
+    }
 }
 
 } // namespace
@@ -968,14 +1103,14 @@ hipError_t launch_plan_fast(const StepArgs &a, int order, const FastPlan &plan,
     return hipGetLastError();
 }
 
-hipError_t launch_step_fast(const StepArgs &a, int order, hipStream_t stream)
+hipError_t launch_step_fast(const StepArgs &a, int order, int scan, hipStream_t stream)
 {
     if (a.rows.n_tiles <= 0) return hipSuccess;
     if (a.rows.tile != kFastTile) return hipErrorInvalidValue;
     switch (order) {
-    case 1: return step_fast_p<1>(a, stream);
-    case 3: return step_fast_p<3>(a, stream);
-    default: return step_fast_p<5>(a, stream);
+    case 1: return step_fast_p<1>(a, scan, stream);
+    case 3: return step_fast_p<3>(a, scan, stream);
+    default: return step_fast_p<5>(a, scan, stream);
     }
 }
 

@@ -858,8 +858,8 @@ hipError_t launch_step_shared(const StepArgs &a, bool f64, int scan, int order,
 {
     if (a.rows.n_tiles <= 0) return hipSuccess;
     if (a.fast.rec) {
-        if (f64 || scan != kSumDirect) return hipErrorInvalidValue;
-        return launch_step_fast(a, order, stream);
+        if (f64) return hipErrorInvalidValue;
+        return launch_step_fast(a, order, scan, stream);
     }
     if (a.rows.tile != step_tile_for(scan == kSumDirect ? items : kItems, a.dv != nullptr))
         return hipErrorInvalidValue;       // the tiles were planned for another schedule
