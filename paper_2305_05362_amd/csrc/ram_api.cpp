@@ -291,6 +291,18 @@ bool use_fast(const ram_ctx *ctx, const ram_layout *L, ram_dtype dtype, ram_scan
     return use_fast_shape(ctx, L->edges_shared != 0, L->n_cols, dtype, scan);
 }
 
+// The FP32 shift-only step on per-row meshes at the default schedule runs the
+// streaming kernel (k_step_rag) when the call is long enough to pay for its
+// per-call plan (every node's weights); shorter calls and every other
+// combination the general per-row kernel.
+constexpr int64_t kRagMinSteps = 4;
+bool use_rag(const ram_ctx *ctx, const ram_layout *L, ram_dtype dtype, const void *dv,
+             int64_t n_steps)
+{
+    return !L->edges_shared && dtype == RAM_F32 && !dv && ctx->items == 0 &&
+           n_steps >= kRagMinSteps;
+}
+
 // Tile size of the step kernel a call runs.
 int step_tile_of(const ram_ctx *ctx, const ram_layout *L, ram_dtype dtype, ram_scan scan,
                  int items, bool fused)
@@ -420,7 +432,7 @@ ram_status launch_steps(ram_ctx *ctx, ram::StepArgs a, ram_dtype dtype,
                         ram_scan scan, int order, int64_t n_steps, void *tmp,
                         size_t wlo_off, size_t w_off, size_t state_bytes,
                         int items, int recon = 0, char *base_mem = nullptr,
-                        bool allow_fast = true)
+                        bool allow_fast = true, int64_t rag_off = -1)
 {
     char *mem = base_mem ? base_mem : (char *)ctx->scratch;
     const bool f64 = dtype == RAM_F64;
@@ -435,6 +447,10 @@ ram_status launch_steps(ram_ctx *ctx, ram::StepArgs a, ram_dtype dtype,
                           use_fast_shape(ctx, a.rows.shared != 0, a.rows.n_cols, dtype, scan);
         e = plan_shared(a, plan_order, fast, mem + wlo_off, mem + w_off, ctx->stream);
         if (e != hipSuccess) return hip_fail(e, "window plan launch");
+    } else if (rag_off >= 0) {
+        a.rag = ram::rag_plan_at(mem + rag_off, a.rows.n_tiles);
+        e = ram::launch_plan_rag(a, order, a.rag, ctx->stream);
+        if (e != hipSuccess) return hip_fail(e, "per-row plan launch");
     }
     auto one = [&](const ram::StepArgs &s, hipStream_t st) {
         if (recon) return ram::launch_step_shared_limited(s, f64, recon, st);
@@ -775,11 +791,16 @@ ram_status ram_step(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
     Carve cv;
     const size_t tmp_off = cv.take(state_bytes);
     const int items = sched_items(ctx, layout, scan);
+    const bool rag = use_rag(ctx, layout, dtype, dv, n_steps);
     RowsPlan rp = plan_rows(cv, layout,
-                            step_tile_of(ctx, layout, dtype, scan, items, dv != nullptr), order);
+                            rag ? ram::kRagTile
+                                : step_tile_of(ctx, layout, dtype, scan, items, dv != nullptr),
+                            order);
     rp.uniform = wants_uniform(dtype, scan) || use_fast(ctx, layout, dtype, scan);
     const int64_t nt = tiles_of(layout, rp.tile);
     const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(plan_w_bytes(nt));
+    const int64_t rag_off =
+        rag ? (int64_t)cv.take(ram::rag_plan_bytes(nt, layout_cells(layout))) : -1;
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
     ram::StepArgs a;
     std::memset(&a, 0, sizeof(a));        // the graph key compares raw bytes
@@ -790,7 +811,7 @@ ram_status ram_step(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
     a.dt = dt;
     void *tmp = (char *)ctx->scratch + tmp_off;
     if ((st = launch_steps(ctx, a, dtype, scan, order, n_steps, tmp, wlo_off, w_off,
-                           state_bytes, items)) != RAM_OK)
+                           state_bytes, items, 0, nullptr, true, rag_off)) != RAM_OK)
         return st;
     return RAM_OK;
 }

@@ -154,6 +154,35 @@ __device__ inline void lagrange_weights(double xh, const double *X, double *w)
     }
 }
 
+// Lagrange weights at t of the nodes X[0..P] given relative to the stencil's
+// cell (X[lo] = 0, X[lo+1] = dx_c): normalised by dx_c, products of all
+// differences but one, one division per weight, in WT.
+template <typename WT, int P>
+__device__ inline void lagrange_rel(double t, const double *X, WT *w)
+{
+    constexpr int LO = (P - 1) / 2;
+    const double inv = 1.0 / X[LO + 1];
+    WT th[P + 1];
+#pragma unroll
+    for (int a = 0; a <= P; ++a) th[a] = (WT)(X[a] * inv);
+    const WT tt = (WT)(t * inv);
+    WT pre[P + 1], suf[P + 1];
+    pre[0] = (WT)1;
+#pragma unroll
+    for (int a = 1; a <= P; ++a) pre[a] = pre[a - 1] * (tt - th[a - 1]);
+    suf[P] = (WT)1;
+#pragma unroll
+    for (int a = P - 1; a >= 0; --a) suf[a] = suf[a + 1] * (tt - th[a + 1]);
+#pragma unroll
+    for (int a = 0; a <= P; ++a) {
+        WT den = (WT)1;
+#pragma unroll
+        for (int b = 0; b <= P; ++b)
+            if (b != a) den *= th[a] - th[b];
+        w[a] = pre[a] * suf[a] / den;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // prefix-sum precisions
 // ---------------------------------------------------------------------------

@@ -203,6 +203,58 @@ inline FastPlan fast_plan_at(void *mem, int64_t n_tiles)
 }
 
 // Bulk shift, optionally fused with the residual step (dv != null).
+// Streaming shift on per-row meshes (FP32 state, no residual): tiles of
+// kRagTile cells of one row, one a wave.  The shift is fixed for a call, so
+// each shifted node's source cell and Lagrange weights are too: planned once
+// per call into a record per tile, per node slot (kFastNodes a tile; the
+// slots past the tile's last node repeat it) the weights other than the own
+// node's (four in wa, the fifth in wb) and the source cell's index in the
+// tile's window, and the row cells' FP32 sizes.
+struct RagTile {
+    int32_t kind;        // kFastWindow, or kFastDirect (window beyond the LDS)
+    int32_t row, i0, nd; // row, first cell, cells
+    int32_t n, w, base;  // row length, window length, window start mod n
+    int32_t pad0;
+    int64_t qoff, eoff;  // the row's first cell and first node
+    int64_t wlo;         // the window start as an extended source index
+    int32_t pad[2];
+};
+static_assert(sizeof(RagTile) == 64, "one record a cache line half");
+// Cells of a per-row streaming tile: 255, so that its 256 shifted nodes fill
+// four slots of a wave (no residual halo on this path).
+constexpr int kRagTile = 255;
+struct RagPlan {
+    RagTile *rec = nullptr;
+    float4 *wa = nullptr;
+    float *wb = nullptr;
+    int16_t *jc = nullptr;
+    float *dx = nullptr;       // FP32 sizes of the row cells, [n_cells]
+};
+inline size_t rag_plan_bytes(int64_t n_tiles, int64_t n_cells)
+{
+    auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
+    const size_t nn = (size_t)n_tiles * kFastNodes;
+    return al(sizeof(RagTile) * (size_t)n_tiles) + al(sizeof(float4) * nn) +
+           al(sizeof(float) * nn) + al(sizeof(int16_t) * nn) + al(sizeof(float) * (size_t)n_cells);
+}
+inline RagPlan rag_plan_at(void *mem, int64_t n_tiles)
+{
+    auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
+    const size_t nn = (size_t)n_tiles * kFastNodes;
+    char *p = (char *)mem;
+    RagPlan r;
+    r.rec = (RagTile *)p;
+    p += al(sizeof(RagTile) * (size_t)n_tiles);
+    r.wa = (float4 *)p;
+    p += al(sizeof(float4) * nn);
+    r.wb = (float *)p;
+    p += al(sizeof(float) * nn);
+    r.jc = (int16_t *)p;
+    p += al(sizeof(int16_t) * nn);
+    r.dx = (float *)p;
+    return r;
+}
+
 struct StepArgs {
     Rows rows;
     const void *q_in = nullptr;
@@ -216,6 +268,7 @@ struct StepArgs {
     void *q_mid = nullptr;              // optional: the state after the shift
     MeshDensity dens;                   // shared mesh, direct sums: closed-form index
     FastPlan fast;                      // FP32 streaming kernels: their tile plan (rec set)
+    RagPlan rag;                        // per-row meshes, FP32 streaming shift (rec set)
 };
 
 // Radial transport of a polar grid (rows = radii): q [n_rows][n_cols], u on
@@ -327,6 +380,11 @@ hipError_t launch_step_shared(const StepArgs &a, bool f64, int scan, int order,
 hipError_t launch_plan_fast(const StepArgs &a, int order, const FastPlan &plan,
                             hipStream_t stream);
 hipError_t launch_step_fast(const StepArgs &a, int order, int scan, hipStream_t stream);
+// Per-row meshes, FP32, shift only: the per-call plan into `plan` (R.tile ==
+// kRagTile, a.dv null), then per step the streaming shift (a.rag set).
+hipError_t launch_plan_rag(const StepArgs &a, int order, const RagPlan &plan,
+                           hipStream_t stream);
+hipError_t launch_step_rag(const StepArgs &a, int order, int scan, hipStream_t stream);
 hipError_t launch_residual(const ResidualArgs &a, bool f64,
                            hipStream_t stream);
 hipError_t launch_shift_adjoint(const ShiftAdjArgs &a, bool f64, int order,

@@ -103,35 +103,6 @@ struct StepLds {
     static constexpr size_t uni = uni1 > stage ? uni1 : stage;
 };
 
-// Lagrange weights at t of the nodes X[0..P] given relative to the stencil's
-// cell (X[lo] = 0, X[lo+1] = dx_c): normalised by dx_c, products of all
-// differences but one, one division per weight, in WT.
-template <typename WT, int P>
-__device__ inline void lagrange_rel(double t, const double *X, WT *w)
-{
-    constexpr int LO = (P - 1) / 2;
-    const double inv = 1.0 / X[LO + 1];
-    WT th[P + 1];
-#pragma unroll
-    for (int a = 0; a <= P; ++a) th[a] = (WT)(X[a] * inv);
-    const WT tt = (WT)(t * inv);
-    WT pre[P + 1], suf[P + 1];
-    pre[0] = (WT)1;
-#pragma unroll
-    for (int a = 1; a <= P; ++a) pre[a] = pre[a - 1] * (tt - th[a - 1]);
-    suf[P] = (WT)1;
-#pragma unroll
-    for (int a = P - 1; a >= 0; --a) suf[a] = suf[a + 1] * (tt - th[a + 1]);
-#pragma unroll
-    for (int a = 0; a <= P; ++a) {
-        WT den = (WT)1;
-#pragma unroll
-        for (int b = 0; b <= P; ++b)
-            if (b != a) den *= th[a] - th[b];
-        w[a] = pre[a] * suf[a] / den;
-    }
-}
-
 template <typename TQ, int P, int S>
 __global__ __launch_bounds__(kBlock) void k_step(StepArgs a)
 {
@@ -889,6 +860,10 @@ hipError_t launch_step(const StepArgs &a, bool f64, int scan, int order,
                        hipStream_t stream)
 {
     if (a.rows.n_tiles <= 0) return hipSuccess;
+    if (a.rag.rec) {
+        if (f64) return hipErrorInvalidValue;
+        return launch_step_rag(a, order, scan, stream);
+    }
     if (f64) return step_order<double>(a, kScanF64, order, stream);
     return step_order<float>(a, scan, order, stream);
 }

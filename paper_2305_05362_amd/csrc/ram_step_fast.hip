@@ -1073,6 +1073,335 @@ hipError_t step_fast_p(const StepArgs &a, int scan, hipStream_t st)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Per-row meshes (every row its own nodes, ragged or not), FP32 state, the
+// shift alone.  The tiles are the ragged tile table's, kRagTile cells of one
+// row, one a wave.  Per call, k_plan_rag locates every shifted node of a tile
+// (a binary search of the row, Eq. condition_p), takes its Lagrange weights
+// from the row's nodes (Section 3, Step 2: the cumulative's interpolant
+// through the p+1 nodes around the source cell) and its source cell's index
+// in the tile's window, and writes the row cells' FP32 sizes.  Per step,
+// k_step_rag then needs no search and no division by the mesh: the window's
+// masses into LDS (or, for the prefix modes, their cumulative), each node's
+// partial integral from its planned weights, each cell's whole source cells
+// and the two partials, over the cell size (Eqs. mass_shift_algo, step3).
+// ---------------------------------------------------------------------------
+
+__device__ inline RagTile load_rag(const RagTile *rec, int64_t i)
+{
+    RagTile r;
+#if defined(__HIP_DEVICE_COMPILE__)
+    typedef const __attribute__((address_space(4))) int32_t *CI;
+    const CI c = (CI)(rec + i);
+    int32_t *o = (int32_t *)&r;
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(RagTile) / 4); ++k) o[k] = c[k];
+#else
+    r = rec[i];
+#endif
+    return r;
+}
+
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_plan_rag(StepArgs a, RagPlan pl)
+{
+    constexpr int LO = (P - 1) / 2;
+    constexpr int NS = (kFastNodes + kLanes - 1) / kLanes;
+    const Rows &R = a.rows;
+    const int t = (int)threadIdx.x % kLanes;
+    const int64_t tile = (int64_t)blockIdx.x * kWaves + wave_id();
+    if (tile >= R.n_tiles) return;
+    RagTile rt;
+    rt.kind = -1;
+    rt.row = rt.i0 = rt.nd = rt.n = rt.w = rt.base = rt.pad0 = 0;
+    rt.qoff = rt.eoff = rt.wlo = 0;
+    rt.pad[0] = rt.pad[1] = 0;
+    Tile ti;
+    if (!get_tile(R, tile, ti)) {                    // past the batch's last tile
+        if (t == 0) pl.rec[tile] = rt;
+        return;
+    }
+    const int n = ti.n, i0 = ti.i0;
+    const int nd = min(R.tile, n - i0);
+    const int NE = nd + 1;
+    const double *x = ti.x;
+    const double len = x[n] - x[0];
+    const double invlen = 1.0 / len;
+    const double s = a.v0[ti.row] * a.dt;
+    for (int c = t; c < nd; c += kLanes)
+        pl.dx[ti.qoff + i0 + c] = (float)(x[i0 + c + 1] - x[i0 + c]);
+    // extended source index g = c + k n of row node e (node n: node 0 one
+    // period on) and the wrapped shifted position
+    auto locate = [&](int e, double &xh) -> int64_t {
+        int kx = 0;
+        if (e >= n) {
+            e -= n;
+            kx = 1;
+        }
+        int64_t k;
+        shifted_node_inv(x, n, s, e, invlen, len, xh, k);
+        return (int64_t)find_cell(x, n, xh) + (k + kx) * (int64_t)n;
+    };
+    double xh0, xh1;
+    const int64_t g0 = locate(i0, xh0);
+    const int64_t g1 = locate(i0 + nd, xh1);
+    const int64_t wlo = g0 - LO;
+    const int64_t wide = g1 - g0 + P;
+    bool ok = wide >= P && wide <= kFastWin;
+    const int64_t slot = tile * kFastNodes;
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+        const int m = t + u * kLanes;
+        if (m < kFastNodes) {
+            double xh;
+            const int64_t g = locate(i0 + min(m, NE - 1), xh);
+            const int c = (int)(g - (g >= 0 ? g / n : -((-g + n - 1) / n)) * (int64_t)n);
+            double X[P + 1];
+#pragma unroll
+            for (int b = 0; b <= P; ++b) X[b] = node_x(x, n, len, c - LO + b) - x[c];
+            float w[P + 1];
+            lagrange_rel<float, P>(xh - x[c], X, w);
+            float v[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+            int k = 0;
+#pragma unroll
+            for (int b = 0; b <= P; ++b)
+                if (b != LO) v[k++] = w[b];
+            pl.wa[slot + m] = make_float4(v[0], v[1], v[2], v[3]);
+            pl.wb[slot + m] = v[4];
+            const int64_t j = g - wlo;
+            ok = ok && j >= LO && j + P - LO <= wide;
+            pl.jc[slot + m] = (int16_t)min(max(j, (int64_t)0), (int64_t)kFastWin);
+        }
+    }
+    const bool all = __all(ok ? 1 : 0) != 0;
+    if (t == 0) {
+        rt.kind = all ? kFastWindow : kFastDirect;
+        rt.row = (int32_t)ti.row;
+        rt.i0 = i0;
+        rt.nd = nd;
+        rt.n = n;
+        rt.w = all ? (int32_t)wide : 0;
+        rt.base = (int32_t)(wlo - (wlo >= 0 ? wlo / n : -((-wlo + n - 1) / n)) * (int64_t)n);
+        rt.qoff = ti.qoff;
+        rt.eoff = (int64_t)(x - R.edges);
+        rt.wlo = wlo;
+        pl.rec[tile] = rt;
+    }
+}
+
+// The prefix modes on per-row tiles: one window cell a lane per slot (cell j
+// = l + 64 u), the slot's masses scanned across the wave, the slots before
+// carried on; sp[j] = cumulative before cell j, sp[W] the total.
+template <int S>
+__device__ __forceinline__ void wave_prefix1(typename Acc<S>::A *sp, typename Acc<S>::M m, int j,
+                                             int W, typename Acc<S>::A &carry)
+{
+    using AC = Acc<S>;
+    using A = typename AC::A;
+    const int lane = (int)threadIdx.x % kLanes;
+    const bool live = j < W;
+    A inc = live ? AC::add(AC::zero(), m) : AC::zero();
+#pragma unroll
+    for (int d = 1; d < kLanes; d <<= 1) {
+        const A y = AC::shfl_up(inc, d);
+        if (lane >= d) inc = AC::comb(y, inc);
+    }
+    A ex = AC::shfl_up(inc, 1);
+    if (lane == 0) ex = AC::zero();
+    if (live) {
+        sp[j] = AC::comb(carry, ex);
+        if (j == W - 1) sp[W] = AC::comb(carry, inc);
+    }
+    A wt;
+    if constexpr (sizeof(A) == 8 && !std::is_same<A, double>::value) {
+        wt = make_float2(__shfl(inc.x, kLanes - 1), __shfl(inc.y, kLanes - 1));
+    } else {
+        wt = __shfl(inc, kLanes - 1);
+    }
+    carry = AC::comb(carry, wt);
+}
+
+template <int P, int S>
+__device__ __forceinline__ void rag_tile(const StepArgs &a, const RagTile &r, int64_t tile,
+                                         unsigned char *su, float *sell, short *sjc, int t)
+{
+    using AC = Acc<S == kSumDirect ? kScanF32 : S>;
+    using A = typename AC::A;
+    using M = typename AC::M;
+    constexpr bool kDirect = S == kSumDirect;
+    constexpr int LO = (P - 1) / 2;
+    constexpr int NS = (kRagTile + 1 + kLanes - 1) / kLanes;     // node slots
+    constexpr int NCS = (kRagTile + kLanes - 1) / kLanes;        // cell slots
+    constexpr int NB = 5;                                         // window slots a batch
+    const int n = r.n, i0 = r.i0, nd = r.nd, W = r.w, base = r.base;
+    const float *q = (const float *)a.q_in + r.qoff;
+    float *qo = (float *)a.q_out + r.qoff;
+    const float *dxr = a.rag.dx + r.qoff;
+    const int64_t slot = tile * kFastNodes;
+    float *sw = (float *)su;                         // direct sums: window masses
+    A *sp = (A *)su;                                 // prefix modes: the cumulative
+
+    // ---- plan of the nodes, sizes of the destination cells -------------------
+    float4 wa[NS];
+    float wb[NS];
+    int jv[NS];
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+        const int m = min(t + u * kLanes, kFastNodes - 1);
+        wa[u] = a.rag.wa[slot + m];
+        wb[u] = a.rag.wb[slot + m];
+        jv[u] = a.rag.jc[slot + m];
+    }
+    float dxd[NCS];
+#pragma unroll
+    for (int u = 0; u < NCS; ++u) dxd[u] = dxr[i0 + min(t + u * kLanes, nd - 1)];
+
+    // ---- window masses, five slots of loads at a time (a whole window of
+    // up to 320 cells in one batch); the FP64 prefix widens the FP32 masses
+    const bool once = base + W <= 2 * n;             // the window wraps the row at most once
+    A carry = AC::zero();
+    for (int s0 = 0; s0 * kLanes < W; s0 += NB) {
+        float vq[NB], vd[NB];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int j = min(t + (s0 + u) * kLanes, W - 1);
+            int c = base + j;
+            c = once ? (c >= n ? c - n : c) : c % n;
+            vq[u] = q[c];
+            vd[u] = dxr[c];
+        }
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            if ((s0 + u) * kLanes >= W) break;
+            const int j = t + (s0 + u) * kLanes;
+            if constexpr (kDirect) {
+                if (j < W) sw[j] = vq[u] * vd[u];
+            } else {
+                const M m = (M)(vq[u] * vd[u]);
+                wave_prefix1<S == kSumDirect ? kScanF32 : S>(sp, m, j, W, carry);
+            }
+        }
+    }
+    wave_sync();
+
+    // ---- partial integrals C~(x) - C(c) of the nodes ---------------------------
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+        const float v[5] = {wa[u].x, wa[u].y, wa[u].z, wa[u].w, wb[u]};
+        float wk[P + 1];
+        int k = 0;
+#pragma unroll
+        for (int b = 0; b <= P; ++b) wk[b] = b == LO ? 0.0f : v[k++];
+        const int j = jv[u];
+        float e = 0.0f;
+        if constexpr (kDirect) {
+            float up = 0.0f, dn = 0.0f;
+#pragma unroll
+            for (int b = LO + 1; b <= P; ++b) {
+                up += sw[j + b - LO - 1];
+                e += wk[b] * up;
+            }
+#pragma unroll
+            for (int b = LO - 1; b >= 0; --b) {
+                dn += sw[j - LO + b];
+                e -= wk[b] * dn;
+            }
+        } else {
+            const A pc = sp[j];
+#pragma unroll
+            for (int b = 0; b <= P; ++b)
+                if (b != LO) e += wk[b] * (float)AC::diff(sp[j - LO + b], pc);
+        }
+        const int m = min(t + u * kLanes, kFastNodes - 1);
+        sell[m] = e;
+        sjc[m] = (short)j;
+    }
+    wave_sync();
+
+    // ---- destination cells: whole source cells + two partials, / dx ----------
+#pragma unroll
+    for (int u = 0; u < NCS; ++u) {
+        const int ci = t + u * kLanes;
+        if (ci < nd) {
+            const int ja = sjc[ci], jb = sjc[ci + 1];
+            float whole;
+            if constexpr (kDirect) {
+                const float m0 = sw[ja], m1 = sw[ja + 1];
+                whole = jb > ja ? m0 : 0.0f;
+                whole += jb > ja + 1 ? m1 : 0.0f;
+                for (int mm = ja + 2; mm < jb; ++mm) whole += sw[mm];
+            } else {
+                whole = (float)AC::diff(sp[jb], sp[ja]);
+            }
+            qo[i0 + ci] = (whole + (sell[ci + 1] - sell[ci])) / dxd[u];
+        }
+    }
+}
+
+// A per-row tile whose window exceeds the LDS: nodes located again and the
+// masses summed from global memory, FP64.
+template <int P>
+__device__ __forceinline__ void rag_direct(const StepArgs &a, const RagTile &r,
+                                           unsigned char *su, float *sell, int t)
+{
+    const int n = r.n, i0 = r.i0, nd = r.nd;
+    const float *q = (const float *)a.q_in + r.qoff;
+    float *qo = (float *)a.q_out + r.qoff;
+    const double *x = a.rows.edges + r.eoff;
+    const double len = x[n] - x[0];
+    const double invlen = 1.0 / len;
+    const double s = a.v0[r.row] * a.dt;
+    int64_t *sg = (int64_t *)su;
+    for (int m = t; m <= nd; m += kLanes) {
+        int e = i0 + m, kx = 0;
+        if (e >= n) {
+            e -= n;
+            kx = 1;
+        }
+        double xh;
+        int64_t k;
+        shifted_node_inv(x, n, s, e, invlen, len, xh, k);
+        const int64_t g = (int64_t)find_cell(x, n, xh) + (k + kx) * (int64_t)n;
+        sg[m] = g;
+        sell[m] = (float)direct_partial<float, P>(x, q, n, len, s, invlen, i0 + m, g);
+    }
+    wave_sync();
+    for (int ci = t; ci < nd; ci += kLanes) {
+        const int c = i0 + ci;
+        const double mp = direct_whole<float>(x, q, n, sg[ci], sg[ci + 1]) +
+                          ((double)sell[ci + 1] - (double)sell[ci]);
+        qo[c] = (float)(mp / (x[c + 1] - x[c]));
+    }
+}
+
+template <int P, int S>
+__global__ __launch_bounds__(kBlock) void k_step_rag(StepArgs a)
+{
+    __shared__ __attribute__((aligned(16))) unsigned char su[kWaves][wave_lds_bytes<S>()];
+    __shared__ __attribute__((aligned(16))) float sell_[kWaves][WaveLds::nodes];
+    __shared__ __attribute__((aligned(16))) short sjc_[kWaves][WaveLds::nodes];
+    const int wid = wave_id();
+    const int64_t tile = (int64_t)blockIdx.x * kWaves + wid;
+    if (tile >= a.rows.n_tiles) return;
+    const RagTile r = load_rag(a.rag.rec, tile);
+    const int t = (int)threadIdx.x % kLanes;
+    if (r.kind == kFastWindow) rag_tile<P, S>(a, r, tile, su[wid], sell_[wid], sjc_[wid], t);
+    else if (r.kind == kFastDirect) rag_direct<P>(a, r, su[wid], sell_[wid], t);
+}
+
+template <int P>
+hipError_t step_rag_p(const StepArgs &a, int scan, hipStream_t st)
+{
+    const dim3 g((unsigned)((a.rows.n_tiles + kWaves - 1) / kWaves)), b(kBlock);
+    switch (scan) {
+    case kScanF64: hipLaunchKernelGGL((k_step_rag<P, kScanF64>), g, b, 0, st, a); break;
+    case kScanTwoSum: hipLaunchKernelGGL((k_step_rag<P, kScanTwoSum>), g, b, 0, st, a); break;
+    case kScanF32: hipLaunchKernelGGL((k_step_rag<P, kScanF32>), g, b, 0, st, a); break;
+    default: hipLaunchKernelGGL((k_step_rag<P, kSumDirect>), g, b, 0, st, a); break;
+    }
+    return hipGetLastError();
+}
+
 } // namespace
 
 hipError_t launch_plan_fast(const StepArgs &a, int order, const FastPlan &plan,
@@ -1111,6 +1440,31 @@ hipError_t launch_step_fast(const StepArgs &a, int order, int scan, hipStream_t 
     case 1: return step_fast_p<1>(a, scan, stream);
     case 3: return step_fast_p<3>(a, scan, stream);
     default: return step_fast_p<5>(a, scan, stream);
+    }
+}
+
+hipError_t launch_plan_rag(const StepArgs &a, int order, const RagPlan &plan,
+                           hipStream_t stream)
+{
+    if (a.rows.n_tiles <= 0) return hipSuccess;
+    if (a.rows.tile != kRagTile || a.dv) return hipErrorInvalidValue;
+    const dim3 g((unsigned)((a.rows.n_tiles + kWaves - 1) / kWaves)), b(kBlock);
+    switch (order) {
+    case 1: hipLaunchKernelGGL(k_plan_rag<1>, g, b, 0, stream, a, plan); break;
+    case 3: hipLaunchKernelGGL(k_plan_rag<3>, g, b, 0, stream, a, plan); break;
+    default: hipLaunchKernelGGL(k_plan_rag<5>, g, b, 0, stream, a, plan); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_step_rag(const StepArgs &a, int order, int scan, hipStream_t stream)
+{
+    if (a.rows.n_tiles <= 0) return hipSuccess;
+    if (a.rows.tile != kRagTile || a.dv) return hipErrorInvalidValue;
+    switch (order) {
+    case 1: return step_rag_p<1>(a, scan, stream);
+    case 3: return step_rag_p<3>(a, scan, stream);
+    default: return step_rag_p<5>(a, scan, stream);
     }
 }
 
