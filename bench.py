@@ -73,10 +73,13 @@ COPY_BYTES = 256 << 20
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_sh_f32_direct_polar2048x16384_traffic.md")
 # the streaming step's two kernels (the default schedule)
 UNI_KERNEL = "k_step_uni<5, 2, true>"
-GEN_KERNEL = "k_step_gen<5, 2, true>"
+GEN_KERNEL = "k_step_gen<5, 2, true, 3>"
 TRAFFIC_FILE_UNI = os.path.join(ROOT, "profiles", "k_step_uni_f32_polar2048x16384_traffic.md")
 TRAFFIC_FILE_GEN = os.path.join(ROOT, "profiles", "k_step_gen_f32_polar2048x16384_traffic.md")
 TRAFFIC_FILE_PPM = os.path.join(ROOT, "profiles", "k_step_sh_f32_ppm_polar2048x16384_traffic.md")
+# the per-row streaming shift (cfg3 ragged batch, two-sum prefix)
+RAG_KERNEL = "k_step_rag<5, 1>"
+TRAFFIC_FILE_RAG = os.path.join(ROOT, "profiles", "k_step_rag_f32_twosum_cfg3_traffic.md")
 TRAFFIC_FILE_RADIAL = os.path.join(ROOT, "profiles", "k_radial_f32_polar2048x16384_traffic.md")
 TRAFFIC_FILE_AVG4 = os.path.join(ROOT, "profiles", "k_average4_f32_polar2048x16384_traffic.md")
 TRAFFIC_FILE_ADJ = os.path.join(ROOT, "profiles", "k_adj_sh_f32_polar2048x16384_traffic.md")
@@ -235,6 +238,12 @@ def main():
         for _ in range(args.steps):
             ctx.ram_shift_limited_adjoint(rows, q32, qb_in, qb_out, v0, wl.dt,
                                           R.RAM_RECON_PPM)
+        # the per-row streaming shift: the cfg3 ragged batch, two-sum prefix
+        wl3 = W.cfg3()
+        rows3 = R.Rows.from_workload(wl3, dev)
+        q3 = torch.as_tensor(wl3.q0, dtype=torch.float32, device=dev)
+        ctx.ram_step(rows3, q3, torch.as_tensor(wl3.v0, dtype=torch.float64, device=dev),
+                     None, wl3.dt, order, max(4, args.steps), R.RAM_SCAN_F32_TWOSUM)
         src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         dst.copy_(src)
@@ -274,6 +283,18 @@ def main():
     k2 = max(1, args.steps // 4)
     t_f64s, _ = time_steps(q32, dv32, R.RAM_SCAN_F64, k2, args.warmup)
     v_f64s = n_cells * k2 / t_f64s / 1e9
+    # --- FP32 state, plain FP32 prefix sums ----------------------------------
+    t_p32, _ = time_steps(q32, dv32, R.RAM_SCAN_F32, k2, args.warmup)
+    v_p32 = n_cells * k2 / t_p32 / 1e9
+
+    def mode_rec(v, t, k, nbytes, kernel):
+        us = t / k * 1e6
+        return {"value": round(v, 3), "steps": k, "us_per_step": round(us, 2),
+                "algorithmic_bytes_per_cell": nbytes,
+                "hbm_frac": round(nbytes * n_cells / (t / k) / 1e9 / HBM_PEAK_GBS, 4),
+                "kernel": kernel}
+    fp32_kernel = ("k_step_uni + k_step_gen (the streaming kernels; the mode's prefix in "
+                   "the searching tiles)" if items == 0 and not use_density else "k_step_sh")
     # --- FP64 plain path ----------------------------------------------------
     t64, q_64 = time_steps(q64, dv64, R.RAM_SCAN_F64, args.fp64_steps, args.warmup)
     v64 = n_cells * args.fp64_steps / t64 / 1e9
@@ -472,6 +493,8 @@ def main():
     k3 = max(1, args.steps // 5)
     t3, _ = time_steps(q3, None, R.RAM_SCAN_F32_TWOSUM, k3, args.warmup, rows3, v03, wl3.dt)
     t3p, _ = time_steps(q3, None, R.RAM_SCAN_F32, k3, args.warmup, rows3, v03, wl3.dt)
+    t3s, _ = time_steps(q3, None, R.RAM_SUM_DIRECT, k3, args.warmup, rows3, v03, wl3.dt)
+    rag_rec = load_traffic(TRAFFIC_FILE_RAG, RAG_KERNEL)
     t3d, _ = time_steps(q3.double(), None, R.RAM_SCAN_F64, k3, args.warmup, rows3, v03,
                         wl3.dt)
     # one step of each FP32 path against the FP64 one from the same
@@ -491,9 +514,16 @@ def main():
     e3 = lambda a32: float((a32.double() - ones["f64"]).abs().sum() / ones["f64"].abs().sum())
     ragged = {"workload": "4096 ragged rows, 64..8192 cells (16.9 M), per-row stretched "
                           "meshes, shift only, order 5", "steps": k3,
+              "kernel": ("FP32: k_step_rag (255-cell wave tiles; each call plans every "
+                         "node's weights and window cell once, k_plan_rag, inside the "
+                         "timed call); FP64: k_step"),
               "f32_twosum": round(wl3.n_cells * k3 / t3 / 1e9, 3),
               "f32_plain_prefix": round(wl3.n_cells * k3 / t3p / 1e9, 3),
+              "f32_direct": round(wl3.n_cells * k3 / t3s / 1e9, 3),
               "f64": round(wl3.n_cells * k3 / t3d / 1e9, 3),
+              "traffic_f32_twosum": None if rag_rec is None else rag_rec["traffic_bytes_per_launch"],
+              "traffic_over_algorithmic_f32_twosum": (None if rag_rec is None else
+                                                      round(rag_rec["traffic_over_algorithmic"], 3)),
               "unit": "Gcell-updates/s",
               "algorithmic_bytes_per_cell": {"f32": 16, "f64": 24,
                                              "note": "Q in, Q out, the row's FP64 nodes"},
@@ -501,6 +531,8 @@ def main():
                                                / HBM_PEAK_GBS, 4),
                            "f32_plain_prefix": round(16.0 * wl3.n_cells * k3 / t3p / 1e9
                                                      / HBM_PEAK_GBS, 4),
+                           "f32_direct": round(16.0 * wl3.n_cells * k3 / t3s / 1e9
+                                               / HBM_PEAK_GBS, 4),
                            "f64": round(24.0 * wl3.n_cells * k3 / t3d / 1e9
                                         / HBM_PEAK_GBS, 4)},
               "one_step_rel_l1_vs_f64": {"f32_twosum": e3(ones["f32_twosum"]),
@@ -924,10 +956,11 @@ def main():
                                         "unit": "Gcell-updates/s", "steps": ka,
                                         "state_memory_gb": round((2 * ka + 1) * n_cells * 4
                                                                  / 1e9, 1)},
-        "fp32_fp64scan": {"value": round(v_f64s, 3), "steps": k2},
-        "fp32_twosum_prefix": {"value": round(v_two, 3), "steps": k2s},
-        "fp64_plain": {"value": round(v64, 3), "steps": args.fp64_steps,
-                       "cumulative_differences": "FP64 window prefix sums"},
+        "fp32_fp64scan": mode_rec(v_f64s, t_f64s, k2, 12, fp32_kernel),
+        "fp32_twosum_prefix": mode_rec(v_two, t_two, k2s, 12, fp32_kernel),
+        "fp32_plain_prefix": mode_rec(v_p32, t_p32, k2, 12, fp32_kernel),
+        "fp64_plain": dict(mode_rec(v64, t64, args.fp64_steps, 24, "k_step_sh"),
+                           cumulative_differences="FP64 window prefix sums"),
         "fp64_direct": {"value": round(v64d, 3), "steps": args.fp64_steps,
                         "cumulative_differences": "summed directly in FP64",
                         "items_per_thread": items64,

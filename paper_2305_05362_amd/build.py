@@ -39,6 +39,7 @@ STEP_KERNEL_SOURCES = ["ram_step_shared.hip", "ram_device.h", "ram_internal.h"]
 KERNEL_SOURCES = {"k_step_sh": STEP_KERNEL_SOURCES,
                   "k_step_uni": ["ram_step_fast.hip", "ram_device.h", "ram_internal.h"],
                   "k_step_gen": ["ram_step_fast.hip", "ram_device.h", "ram_internal.h"],
+                  "k_step_rag": ["ram_step_fast.hip", "ram_device.h", "ram_internal.h"],
                   "k_radial": ["ram_radial.hip", "ram_device.h", "ram_internal.h"],
                   "k_average4": ["ram_average4.hip", "ram_device.h", "ram_internal.h"],
                   "k_adj_sh": ["ram_adjoint_shared.hip", "ram_device.h", "ram_internal.h"],

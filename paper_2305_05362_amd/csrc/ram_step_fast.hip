@@ -610,6 +610,33 @@ __device__ __forceinline__ void general_tile(const StepArgs &a, const FastTile &
 // index j + off for window cell j), so that its groups go in whole.
 // ---------------------------------------------------------------------------
 
+// Inclusive scan of one value a lane over the wave in DPP steps (row shifts,
+// then the row-15 and row-31 broadcasts; lanes without a source read zero),
+// and lane 63's value read back as a scalar.
+template <class AC>
+__device__ __forceinline__ typename AC::A wave_inclusive(typename AC::A inc)
+{
+    inc = AC::comb(AC::template dpp<kDppRowShr1, 0xf, 0xf>(inc), inc);
+    inc = AC::comb(AC::template dpp<kDppRowShr2, 0xf, 0xf>(inc), inc);
+    inc = AC::comb(AC::template dpp<kDppRowShr4, 0xf, 0xf>(inc), inc);
+    inc = AC::comb(AC::template dpp<kDppRowShr8, 0xf, 0xf>(inc), inc);
+    inc = AC::comb(AC::template dpp<kDppBcast15, 0xa, 0xf>(inc), inc);
+    inc = AC::comb(AC::template dpp<kDppBcast31, 0xc, 0xf>(inc), inc);
+    return inc;
+}
+__device__ __forceinline__ float lane63(float v)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), kLanes - 1));
+}
+__device__ __forceinline__ float2 lane63(float2 v) { return make_float2(lane63(v.x), lane63(v.y)); }
+__device__ __forceinline__ double lane63(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), kLanes - 1);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), kLanes - 1);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // The prefix modes (S other than kSumDirect): the window's exclusive
 // cumulative of the masses, in the mode's precision (Acc<S>), at LDS index
 // j + off for window cell j and one past the window's last group; partial
@@ -631,13 +658,8 @@ __device__ __forceinline__ void wave_prefix(typename Acc<S>::A *sp, const typena
         for (int k = 0; k < 4; ++k) tot = AC::add(tot, m[k]);
     }
     // inclusive scan of the lane totals over the wave
-    A inc = tot;
-#pragma unroll
-    for (int d = 1; d < kLanes; d <<= 1) {
-        const A y = AC::shfl_up(inc, d);
-        if (lane >= d) inc = AC::comb(y, inc);
-    }
-    A ex = AC::shfl_up(inc, 1);
+    const A inc = wave_inclusive<AC>(tot);
+    A ex = AC::template dpp<kDppWaveShr1, 0xf, 0xf>(inc);
     if (lane == 0) ex = AC::zero();
     A e = AC::comb(carry, ex);
     if (live) {
@@ -648,13 +670,7 @@ __device__ __forceinline__ void wave_prefix(typename Acc<S>::A *sp, const typena
         }
         if (g == gl) sp[4 * g + 4] = e;
     }
-    A wt;
-    if constexpr (sizeof(A) == 8 && !std::is_same<A, double>::value) {
-        wt = make_float2(__shfl(inc.x, kLanes - 1), __shfl(inc.y, kLanes - 1));
-    } else {
-        wt = __shfl(inc, kLanes - 1);
-    }
-    carry = AC::comb(carry, wt);
+    carry = AC::comb(carry, lane63(inc));
 }
 
 template <int P, int H, int S>
@@ -1200,25 +1216,14 @@ __device__ __forceinline__ void wave_prefix1(typename Acc<S>::A *sp, typename Ac
     using A = typename AC::A;
     const int lane = (int)threadIdx.x % kLanes;
     const bool live = j < W;
-    A inc = live ? AC::add(AC::zero(), m) : AC::zero();
-#pragma unroll
-    for (int d = 1; d < kLanes; d <<= 1) {
-        const A y = AC::shfl_up(inc, d);
-        if (lane >= d) inc = AC::comb(y, inc);
-    }
-    A ex = AC::shfl_up(inc, 1);
+    const A inc = wave_inclusive<AC>(live ? AC::add(AC::zero(), m) : AC::zero());
+    A ex = AC::template dpp<kDppWaveShr1, 0xf, 0xf>(inc);
     if (lane == 0) ex = AC::zero();
     if (live) {
         sp[j] = AC::comb(carry, ex);
         if (j == W - 1) sp[W] = AC::comb(carry, inc);
     }
-    A wt;
-    if constexpr (sizeof(A) == 8 && !std::is_same<A, double>::value) {
-        wt = make_float2(__shfl(inc.x, kLanes - 1), __shfl(inc.y, kLanes - 1));
-    } else {
-        wt = __shfl(inc, kLanes - 1);
-    }
-    carry = AC::comb(carry, wt);
+    carry = AC::comb(carry, lane63(inc));
 }
 
 template <int P, int S>
