@@ -60,7 +60,8 @@ typedef enum { RAM_F64 = 0, RAM_F32 = 1 } ram_dtype;
  * modes build a window prefix sum and subtract; RAM_SUM_DIRECT sums the masses
  * between the two nodes instead (at most p masses for a partial integral),
  * so no prefix and no cancellation arise.  On per-row meshes RAM_SUM_DIRECT
- * uses the FP64 prefix.  FP64 state requires RAM_SCAN_F64 or RAM_SUM_DIRECT. */
+ * uses the FP64 prefix, except on the streaming path of ram_step (below),
+ * which sums directly.  FP64 state requires RAM_SCAN_F64 or RAM_SUM_DIRECT. */
 typedef enum {
     RAM_SCAN_F64 = 0,         /* FP64 prefix sums                              */
     RAM_SCAN_F32_TWOSUM = 1,  /* compensated FP32 prefix (hi, lo) pairs        */
@@ -207,7 +208,12 @@ ram_status ram_residual(ram_ctx *ctx, const ram_layout *layout,
 
 /* n_steps operator-split steps (paper Section 1): shift, then residual; q is
  * updated in place (the context's scratch holds the intermediate state).
- * dv == NULL means dv = 0 (shift only). */
+ * dv == NULL means dv = 0 (shift only).  On per-row meshes an FP32 call
+ * without dv of at least 4 steps at the default schedule plans every shifted
+ * node's Lagrange weights and source cell once (the shift is the same at
+ * every step of a call) and then streams the steps; its scratch holds that
+ * plan, about 24 bytes a cell.  Results agree with the other path to
+ * rounding. */
 ram_status ram_step(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
                     ram_scan scan, void *q, const double *edges,
                     const double *v0, const void *dv, double dt, int order,
