@@ -82,8 +82,10 @@ RAG_KERNEL = "k_step_rag<5, 1>"
 TRAFFIC_FILE_RAG = os.path.join(ROOT, "profiles", "k_step_rag_f32_twosum_cfg3_traffic.md")
 TRAFFIC_FILE_RADIAL = os.path.join(ROOT, "profiles", "k_radial_f32_polar2048x16384_traffic.md")
 TRAFFIC_FILE_AVG4 = os.path.join(ROOT, "profiles", "k_average4_f32_polar2048x16384_traffic.md")
-TRAFFIC_FILE_ADJ = os.path.join(ROOT, "profiles", "k_adj_sh_f32_polar2048x16384_traffic.md")
-ADJ_KERNEL = "k_adj_sh<float, 5, true>"
+TRAFFIC_FILE_ADJ_UNI = os.path.join(ROOT, "profiles", "k_adjf_uni_f32_polar2048x16384_traffic.md")
+TRAFFIC_FILE_ADJ_GEN = os.path.join(ROOT, "profiles", "k_adjf_gen_f32_polar2048x16384_traffic.md")
+ADJ_UNI_KERNEL = "k_adjf_uni<5, true, true>"
+ADJ_GEN_KERNEL = "k_adjf_gen<5, true, true>"
 TRAFFIC_FILE_LADJ = os.path.join(ROOT, "profiles", "k_shift_lim_adj_f32_ppm_polar2048x16384_traffic.md")
 LADJ_KERNEL = "k_shift_lim_adj<float, 2>"
 
@@ -760,25 +762,47 @@ def main():
     v_adj_q0 = n_cells * ka / (a.elapsed_time(b) / 1e3) / 1e9
     del out, qo_
     # one backward step with every gradient, alone: the call (its mesh tables,
-    # window plan and zeroing pass included) against the adjoint kernel's
-    # algorithmic bytes
+    # tile plan and edge sums included) against the step's algorithmic bytes;
+    # then the same steps walked back over a recorded trajectory in one call
+    # (ram_step_adjoint_steps: one tile plan for all of them), per step
     half = torch.empty_like(q32)
     ctx.ram_shift(rows, q32, half, v0, wl.dt, order, R.RAM_SUM_DIRECT)
     qb_in, qb_out = torch.ones_like(q32), torch.empty_like(q32)
     dvb, v0b = torch.zeros_like(dv32), torch.zeros_like(v0)
     t_adj_call = time_kernel(lambda: ctx.ram_step_adjoint(rows, q32, half, dv32, qb_in, qb_out,
                                                           v0, wl.dt, order, dvb, v0b), 20)
+    ks = 20
+    traj_s = torch.empty((ks + 1, n_cells), dtype=torch.float32, device=dev)
+    half_s = torch.empty((ks, n_cells), dtype=torch.float32, device=dev)
+    traj_s[0].copy_(q32)
+    ctx.ram_step_record(rows, traj_s, half_s, v0, dv32, wl.dt, order, ks, HEAD)
+    qb_s, work_s = torch.ones_like(q32), torch.empty_like(q32)
+    t_adj_steps = time_kernel(lambda: ctx.ram_step_adjoint_steps(
+        rows, traj_s, half_s, dv32, qb_s, work_s, v0, wl.dt, order, ks, dvb, v0b), 3) / ks
+    del traj_s, half_s, qb_s, work_s
     adj_bytes = 28 * n_cells
-    tr_adj = load_traffic(TRAFFIC_FILE_ADJ, ADJ_KERNEL)
+    tr_au = load_traffic(TRAFFIC_FILE_ADJ_UNI, ADJ_UNI_KERNEL)
+    tr_ag = load_traffic(TRAFFIC_FILE_ADJ_GEN, ADJ_GEN_KERNEL)
+    adj_traffic = None if tr_au is None or tr_ag is None else \
+        tr_au["traffic_bytes_per_launch"] + tr_ag["traffic_bytes_per_launch"]
+    apaths = ctx.ram_step_tile_paths(rows, v0, wl.dt, order, False).cpu().numpy()
     adjoint_step = {
-        "kernel": ADJ_KERNEL + " (FP32, order 5, fused residual transpose, every gradient)",
+        "kernel": f"{ADJ_UNI_KERNEL} + {ADJ_GEN_KERNEL} (FP32, order 5, fused residual "
+                  "transpose, every gradient; tiles of 256 cells a wave on the shift's plan)",
+        "tiles": {"uniform_run": int((apaths == R.RAM_TILE_UNIFORM).sum()),
+                  "searching": int((apaths == R.RAM_TILE_WINDOW).sum()),
+                  "direct": int((apaths == R.RAM_TILE_DIRECT).sum())},
         "call_us": round(t_adj_call * 1e6, 2),
+        "per_step_us_in_a_multi_step_call": round(t_adj_steps * 1e6, 2),
+        "multi_step_call_steps": ks,
         "algorithmic_bytes_per_cell": 28,
         "bytes_note": "Qbar in and out, Q half-step, dv, dvbar read and written, Q for v0bar",
         "hbm_frac_of_call": round(adj_bytes / t_adj_call / 1e9 / HBM_PEAK_GBS, 4),
-        "traffic": None if tr_adj is None else round(tr_adj["traffic_bytes_per_launch"]),
-        "traffic_over_algorithmic": None if tr_adj is None
-        else round(tr_adj["traffic_over_algorithmic"], 3)}
+        "hbm_frac_per_step_multi_step": round(adj_bytes / t_adj_steps / 1e9 / HBM_PEAK_GBS, 4),
+        "traffic": None if adj_traffic is None else round(adj_traffic),
+        "traffic_unit": "HBM bytes per step, both kernels (FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+        "traffic_over_algorithmic": None if adj_traffic is None
+        else round(adj_traffic / adj_bytes, 3)}
     del half, qb_in, qb_out, dvb, v0b
 
     # --- accuracy: one FP32 step against the FP64 path (itself held to the

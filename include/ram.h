@@ -311,7 +311,8 @@ ram_status ram_step_record(ram_ctx *ctx, const ram_layout *layout,
  * (needed when dv != NULL; ram_step_record writes it).  dv == NULL: the step
  * had no residual.  Same conventions at kinks as ram_residual_adjoint.  The
  * residual part computes in dtype; the shift part accumulates in FP64 and
- * rounds to dtype on the store.
+ * rounds to dtype on the store (an FP32 state on a shared mesh: the
+ * transposed stencil of the mesh's uniform runs sums its p+1 terms in FP32).
  * qbar_in must not alias any input. */
 ram_status ram_step_adjoint(ram_ctx *ctx, const ram_layout *layout,
                             ram_dtype dtype, const void *q_fwd,
@@ -319,6 +320,26 @@ ram_status ram_step_adjoint(ram_ctx *ctx, const ram_layout *layout,
                             const void *qbar_out, void *qbar_in,
                             const double *edges, const double *v0, double dt,
                             int order, void *dvbar_accum, double *v0bar_accum);
+
+/* The adjoint of n_steps recorded steps (ram_step_record's trajectory),
+ * walked from the last step to the first: on entry qbar holds the gradient of
+ * Q^{n_steps}, on return the gradient of Q^0 (overwritten), with
+ * dvbar_accum and v0bar_accum accumulating every step's terms as
+ * ram_step_adjoint does.  q_traj: states Q^0 .. Q^{n_steps-1} back to back
+ * (n_cells each; ram_step_record's q_traj, whose last slot is not read);
+ * q_half: the post-shift states of the same steps (needed when dv != NULL).
+ * qbar_work: caller-owned device memory for one state (the other half of the
+ * ping-pong), overwritten.  Results equal n_steps calls of ram_step_adjoint
+ * bit for bit; the steps share one tile plan (the shift is the same at each),
+ * which is what makes the call cheaper than those calls.  Neither qbar nor
+ * qbar_work may overlap an input or each other (RAM_E_INVALID_ARG). */
+ram_status ram_step_adjoint_steps(ram_ctx *ctx, const ram_layout *layout,
+                                  ram_dtype dtype, const void *q_traj,
+                                  const void *q_half, const void *dv, void *qbar,
+                                  void *qbar_work, const double *edges,
+                                  const double *v0, double dt, int order,
+                                  int64_t n_steps, void *dvbar_accum,
+                                  double *v0bar_accum);
 
 /* Which path each tile of the FP32 step with RAM_SUM_DIRECT on a shared mesh
  * takes under the default schedule (tiles of 256 destination cells, one a

@@ -98,6 +98,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ram_residual_adjoint": [P, LP, I, P, P, P, P, P, D, P],
         "ram_step_record": [P, LP, I, I, P, P, P, P, P, D, I, I64],
         "ram_step_adjoint": [P, LP, I, P, P, P, P, P, P, P, D, I, P, P],
+        "ram_step_adjoint_steps": [P, LP, I, P, P, P, P, P, P, P, D, I, I64, P, P],
         "ram_validate": [P, LP, I, P, P, D],
         "ram_shift_limited": [P, LP, I, I, P, P, P, P, D],
         "ram_step_limited": [P, LP, I, I, P, P, P, P, D, I64],
@@ -458,6 +459,26 @@ class Context:
             _dev_ptr(dvbar, t, "dvbar"), _dev_ptr(v0bar, torch.float64, "v0bar")))
         return qbar_in
 
+    def ram_step_adjoint_steps(self, rows: Rows, q_traj, q_half, dv, qbar, qbar_work, v0,
+                               dt: float, order: int, n_steps: int, dvbar=None, v0bar=None):
+        """qbar (in: gradient of Q^n_steps; out: gradient of Q^0) through
+        n_steps recorded steps; q_traj / q_half hold at least n_steps states."""
+        self._stream()
+        t = qbar.dtype
+        n = int(n_steps)
+        need = n * rows.n_cells
+        if q_traj.numel() < need or (dv is not None and (q_half is None or q_half.numel() < need)):
+            raise ValueError("q_traj / q_half hold fewer than n_steps states")
+        check(self._lib.ram_step_adjoint_steps(
+            self._h, ctypes.byref(rows.layout), _dtype_code(qbar),
+            _dev_ptr(q_traj, t, "q_traj"), _dev_ptr(q_half, t, "q_half"),
+            _dev_ptr(dv, t, "dv"), _dev_ptr(qbar, t, "qbar"),
+            _dev_ptr(qbar_work, t, "qbar_work"),
+            _dev_ptr(rows.edges, torch.float64, "edges"),
+            _dev_ptr(v0, torch.float64, "v0"), float(dt), int(order), n,
+            _dev_ptr(dvbar, t, "dvbar"), _dev_ptr(v0bar, torch.float64, "v0bar")))
+        return qbar
+
     def ram_validate(self, rows: Rows, dtype, dv=None, dt: float = 0.0):
         self._stream()
         code = RAM_F64 if dtype == torch.float64 else RAM_F32
@@ -553,6 +574,12 @@ def ram_step_adjoint(rows, q_fwd, q_half, dv, qbar_out, qbar_in, v0, dt, order,
                      dvbar=None, v0bar=None):
     return context(qbar_out.device.index).ram_step_adjoint(
         rows, q_fwd, q_half, dv, qbar_out, qbar_in, v0, dt, order, dvbar, v0bar)
+
+
+def ram_step_adjoint_steps(rows, q_traj, q_half, dv, qbar, qbar_work, v0, dt, order, n_steps,
+                           dvbar=None, v0bar=None):
+    return context(qbar.device.index).ram_step_adjoint_steps(
+        rows, q_traj, q_half, dv, qbar, qbar_work, v0, dt, order, n_steps, dvbar, v0bar)
 
 
 def ram_validate(rows, dtype, dv=None, dt=0.0):

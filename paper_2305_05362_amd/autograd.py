@@ -7,8 +7,9 @@ Forward: n steps of (bulk shift, residual), keeping one state every
 state, so the backward pass needs no recomputation).  Backward: for each
 segment, newest first, recompute the segment from its checkpoint with
 ram_step_record (every state and every post-shift state), then walk it
-backwards with ram_step_adjoint (the residual transpose, dv-bar accumulating,
-then the shift transpose, v0-bar accumulating).
+backwards with ram_step_adjoint_steps (per step the residual transpose,
+dv-bar accumulating, then the shift transpose, v0-bar accumulating; one tile
+plan for the segment).
 
 With ``recon`` (RAM_RECON_PLM or RAM_RECON_PPM) the bulk shift is the limited
 one of Section 3.1: the forward runs ram_step_limited /
@@ -50,6 +51,24 @@ def _step_adjoint(ctx, rows, q_fwd, q_half, dv, qbar, out, work, v0, dt, order, 
         ctx.ram_residual_adjoint(rows, q_half, dv, qbar, work, dt, dvbar)
         qbar = work
     ctx.ram_shift_limited_adjoint(rows, q_fwd, qbar, out, v0, dt, recon, v0bar)
+
+
+def _walk_back(ctx, rows, traj, half, dv, qbar, tmp, work, v0, dt, order, recon, k,
+               dvbar, v0bar):
+    """qbar (in place): the gradient of the segment's last state back to its
+    first, through its k recorded steps (one call without a limiter: the
+    steps share the shift's tile plan)."""
+    if not recon:
+        ctx.ram_step_adjoint_steps(rows, traj, half, dv, qbar, tmp, v0, dt, order, k,
+                                   dvbar, v0bar)
+        return
+    cur, oth = qbar, tmp
+    for i in range(k - 1, -1, -1):
+        _step_adjoint(ctx, rows, traj[i], None if half is None else half[i], dv,
+                      cur, oth, work, v0, dt, order, recon, dvbar, v0bar)
+        cur, oth = oth, cur
+    if cur is not qbar:
+        qbar.copy_(cur)
 
 
 def _rollout(ctx: R.Context, rows: R.Rows, q0, dv, v0, dt, order, n_steps,
@@ -119,10 +138,8 @@ class RamRollout(torch.autograd.Function):
         if fctx.stored:
             traj = checkpoints[0]
             half = checkpoints[1] if dv is not None else None
-            for i in range(fctx.n_steps - 1, -1, -1):
-                _step_adjoint(ctx, rows, traj[i], None if half is None else half[i], dv,
-                              qbar, tmp, work, v0, dt, order, recon, dvbar, v0bar)
-                qbar, tmp = tmp, qbar
+            _walk_back(ctx, rows, traj, half, dv, qbar, tmp, work, v0, dt, order, recon,
+                       fctx.n_steps, dvbar, v0bar)
             return (qbar, dvbar, None if v0bar is None else v0bar.to(v0.dtype), None, None,
                     None, None, None, None, None)
         n_seg = len(checkpoints)
@@ -137,10 +154,8 @@ class RamRollout(torch.autograd.Function):
             # the state each residual step read (one fused launch per step)
             traj[0].copy_(checkpoints[sgi].reshape(-1))
             _record(ctx, rows, traj, half, v0, dv, dt, order, k, scan, recon)
-            for i in range(k - 1, -1, -1):
-                _step_adjoint(ctx, rows, traj[i], None if half is None else half[i], dv,
-                              qbar, tmp, work, v0, dt, order, recon, dvbar, v0bar)
-                qbar, tmp = tmp, qbar
+            _walk_back(ctx, rows, traj, half, dv, qbar, tmp, work, v0, dt, order, recon, k,
+                       dvbar, v0bar)
         return (qbar, dvbar, None if v0bar is None else v0bar.to(v0.dtype), None, None, None,
                 None, None, None, None)
 

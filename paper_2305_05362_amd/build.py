@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libram.so")
 ARCH = os.environ.get("RAM_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["ram_kernels.hip", "ram_step_shared.hip", "ram_step_fast.hip", "ram_adjoint.hip",
-           "ram_adjoint_shared.hip", "ram_limited.hip", "ram_reduce.hip", "ram_radial.hip",
+           "ram_adjoint_shared.hip", "ram_adjoint_fast.hip", "ram_limited.hip", "ram_reduce.hip", "ram_radial.hip",
            "ram_average4.hip", "ram_noalloc.hip", "ram_api.cpp"]
 
 HIPCC_FLAGS = [
@@ -36,13 +36,19 @@ HIPCC_FLAGS = [
 # sources of the shared-mesh step kernel (the one the traffic counters cover)
 STEP_KERNEL_SOURCES = ["ram_step_shared.hip", "ram_device.h", "ram_internal.h"]
 # sources of each kernel family whose counters are committed
+FAST_SOURCES = ["ram_step_fast.hip", "ram_wave.h", "ram_device.h", "ram_internal.h"]
+ADJ_FAST_SOURCES = ["ram_adjoint_fast.hip", "ram_adjoint_dev.h", "ram_wave.h", "ram_device.h",
+                    "ram_internal.h"]
 KERNEL_SOURCES = {"k_step_sh": STEP_KERNEL_SOURCES,
-                  "k_step_uni": ["ram_step_fast.hip", "ram_device.h", "ram_internal.h"],
-                  "k_step_gen": ["ram_step_fast.hip", "ram_device.h", "ram_internal.h"],
-                  "k_step_rag": ["ram_step_fast.hip", "ram_device.h", "ram_internal.h"],
+                  "k_step_uni": FAST_SOURCES,
+                  "k_step_gen": FAST_SOURCES,
+                  "k_step_rag": FAST_SOURCES,
+                  "k_adjf_uni": ADJ_FAST_SOURCES,
+                  "k_adjf_gen": ADJ_FAST_SOURCES,
                   "k_radial": ["ram_radial.hip", "ram_device.h", "ram_internal.h"],
                   "k_average4": ["ram_average4.hip", "ram_device.h", "ram_internal.h"],
-                  "k_adj_sh": ["ram_adjoint_shared.hip", "ram_device.h", "ram_internal.h"],
+                  "k_adj_sh": ["ram_adjoint_shared.hip", "ram_adjoint_dev.h", "ram_device.h",
+                               "ram_internal.h"],
                   "k_shift_lim_adj": ["ram_adjoint.hip", "ram_device.h", "ram_internal.h"]}
 
 

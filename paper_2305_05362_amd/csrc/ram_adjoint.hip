@@ -590,10 +590,12 @@ hipError_t launch_shift_adjoint(const ShiftAdjArgs &a, bool f64, int order,
 
 namespace {
 
-// One thread per row: its tiles' v0bar terms in tile order.
+// One wave per row: lane l sums the row's tile terms l, l + 64, ... in order,
+// then the lanes combine in a fixed butterfly (the same sum in every run).
 __global__ __launch_bounds__(256) void k_v0_reduce(Rows R, const double *part, double *v0bar)
 {
-    const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t row = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+    const int lane = (int)threadIdx.x % 64;
     if (row >= R.n_rows) return;
     int64_t t0, t1;
     if (R.n_cols > 0) {
@@ -605,8 +607,9 @@ __global__ __launch_bounds__(256) void k_v0_reduce(Rows R, const double *part, d
         t1 = R.tile_ptr[row + 1];
     }
     double s = 0.0;
-    for (int64_t t = t0; t < t1; ++t) s += part[t];
-    v0bar[row] += s;
+    for (int64_t t = t0 + lane; t < t1; t += 64) s += part[t];
+    for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d);
+    if (lane == 0) v0bar[row] += s;
 }
 
 } // namespace
@@ -615,7 +618,7 @@ hipError_t launch_v0_reduce(const Rows &R, const double *part, double *v0bar,
                             hipStream_t stream)
 {
     if (R.n_rows <= 0 || !v0bar) return hipSuccess;
-    const dim3 g((unsigned)((R.n_rows + 255) / 256));
+    const dim3 g((unsigned)((R.n_rows + 3) / 4));
     hipLaunchKernelGGL(k_v0_reduce, g, dim3(256), 0, stream, R, part, v0bar);
     return hipGetLastError();
 }

@@ -12,6 +12,8 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <utility>
+#include <initializer_list>
 #include <vector>
 
 struct ram_ctx {
@@ -303,6 +305,20 @@ bool use_rag(const ram_ctx *ctx, const ram_layout *L, ram_dtype dtype, const voi
            n_steps >= kRagMinSteps;
 }
 
+// The FP32 step adjoint on a shared mesh at the default schedule runs the
+// streaming adjoint (k_adjf_uni / k_adjf_gen) on rows of a multiple of four
+// cells, at least a tile and a halo long, with 16-byte aligned arrays; every
+// other combination the general shared-mesh adjoint.
+bool use_fast_adjoint(const ram_ctx *ctx, const ram_layout *L, ram_dtype dtype,
+                      std::initializer_list<const void *> arrays)
+{
+    if (!use_fast_shape(ctx, L->edges_shared != 0, L->n_cols, dtype, RAM_SCAN_F64)) return false;
+    if (L->n_cols % 4 != 0 || L->n_cols < ram::kFastTile + 8) return false;
+    for (const void *p : arrays)
+        if (p && ((uintptr_t)p % 16) != 0) return false;
+    return true;
+}
+
 // Tile size of the step kernel a call runs.
 int step_tile_of(const ram_ctx *ctx, const ram_layout *L, ram_dtype dtype, ram_scan scan,
                  int items, bool fused)
@@ -483,6 +499,42 @@ ram_status launch_steps(ram_ctx *ctx, ram::StepArgs a, ram_dtype dtype,
     return run_graphed(ctx, key_of(a, extra), n_steps, loop);
 }
 
+// The streaming adjoint's per-call set-up: mesh tables, the shift's tile plan
+// without halo (records, tile lists, node data), the v0bar and edge buffers;
+// the per-step pointers (states, gradients) are left to the caller.
+ram_status plan_adjoint_fast(ram_ctx *ctx, const ram_layout *layout, const double *edges,
+                             const double *v0, double dt, int order, const void *dv,
+                             void *dvbar, double *v0bar, ram::StepAdjArgs &a)
+{
+    ram_status st;
+    Carve cv;
+    RowsPlan rp = plan_rows(cv, layout, ram::kFastTile, order);
+    rp.uniform = true;
+    const int64_t nt = tiles_of(layout, rp.tile);
+    const size_t rec_off = cv.take(ram::fast_plan_bytes(nt));
+    const size_t v0_off = cv.take(v0bar ? sizeof(double) * nt : 0);
+    const size_t edge_off = cv.take(sizeof(float) * 2 * (size_t)order * nt);
+    if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
+    ram::StepArgs p;
+    if ((st = make_rows(ctx, layout, edges, rp, p.rows)) != RAM_OK) return st;
+    p.v0 = v0;
+    p.dt = dt;
+    const ram::FastPlan fp = ram::fast_plan_at((char *)ctx->scratch + rec_off, nt);
+    const hipError_t e = ram::launch_plan_fast(p, order, fp, ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "tile plan launch");
+    a = ram::StepAdjArgs();
+    a.rows = p.rows;
+    a.dv = dv;
+    a.dvbar = dvbar;
+    a.v0bar = v0bar;
+    a.v0part = (double *)((char *)ctx->scratch + v0_off);
+    a.v0 = v0;
+    a.dt = dt;
+    a.fast = fp;
+    a.edge = (float *)((char *)ctx->scratch + edge_off);
+    return RAM_OK;
+}
+
 // One step backwards on a shared mesh: window plan of the shift (no halo),
 // then the zeroing pass and the fused adjoint.
 ram_status step_adjoint_shared(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
@@ -493,6 +545,19 @@ ram_status step_adjoint_shared(ram_ctx *ctx, const ram_layout *layout, ram_dtype
 {
     ram_status st;
     Carve cv;
+    if (use_fast_adjoint(ctx, layout, dtype, {q_fwd, q_half, dv, qbar_out, qbar_in, dvbar})) {
+        ram::StepAdjArgs a;
+        if ((st = plan_adjoint_fast(ctx, layout, edges, v0, dt, order, dv, dvbar, v0bar, a)) !=
+            RAM_OK)
+            return st;
+        a.q_fwd = q_fwd;
+        a.q_half = q_half;
+        a.qbar_out = qbar_out;
+        a.qbar_in = qbar_in;
+        const hipError_t e = ram::launch_step_adjoint_fast(a, order, ctx->stream);
+        if (e != hipSuccess) return hip_fail(e, "step adjoint launch");
+        return RAM_OK;
+    }
     // the residual transpose stages cells i0-2 .. i0+nd+1: the fused tile
     // size keeps them within one item per thread
     RowsPlan rp = plan_rows(cv, layout, ram::step_tile(true), order);
@@ -1540,6 +1605,76 @@ ram_status ram_step_adjoint(ram_ctx *ctx, const ram_layout *layout,
     a.v0part = (double *)((char *)ctx->scratch + v0_off);
     e = ram::launch_shift_adjoint(a, dtype == RAM_F64, order, ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "shift adjoint launch");
+    return RAM_OK;
+}
+
+ram_status ram_step_adjoint_steps(ram_ctx *ctx, const ram_layout *layout,
+                                  ram_dtype dtype, const void *q_traj,
+                                  const void *q_half, const void *dv, void *qbar,
+                                  void *qbar_work, const double *edges,
+                                  const double *v0, double dt, int order,
+                                  int64_t n_steps, void *dvbar_accum,
+                                  double *v0bar_accum)
+{
+    ram_status st;
+    g_last_error.clear();
+    if ((st = check_layout(layout, edges)) != RAM_OK) return st;
+    if ((st = check_dtype(dtype)) != RAM_OK) return st;
+    if ((st = check_order(layout, order)) != RAM_OK) return st;
+    if ((st = check_dt(dt)) != RAM_OK) return st;
+    if (!q_traj || !qbar || !qbar_work || !v0)
+        return fail(RAM_E_INVALID_ARG, "null q_traj, qbar, qbar_work or v0");
+    if (dv && !q_half) return fail(RAM_E_INVALID_ARG, "steps with dv need q_half");
+    if (dvbar_accum && !dv) return fail(RAM_E_INVALID_ARG, "dvbar needs dv");
+    if (n_steps < 0) return fail(RAM_E_INVALID_ARG, "n_steps must be >= 0");
+    const size_t state_bytes = elem_size(dtype) * (size_t)layout_cells(layout);
+    auto hits = [&](const void *p, const void *base, size_t bytes) {
+        return base && (const char *)p + state_bytes > (const char *)base &&
+               (const char *)p < (const char *)base + bytes;
+    };
+    const size_t traj_bytes = state_bytes * (size_t)n_steps;
+    for (const void *p : {(const void *)qbar, (const void *)qbar_work})
+        if (hits(p, q_traj, traj_bytes) || hits(p, q_half, traj_bytes) ||
+            hits(p, dv, state_bytes) || hits(p, dvbar_accum, state_bytes))
+            return fail(RAM_E_INVALID_ARG, "qbar and qbar_work must not overlap an input");
+    if (hits(qbar, qbar_work, state_bytes))
+        return fail(RAM_E_INVALID_ARG, "qbar and qbar_work must not overlap");
+    if (n_steps == 0) return RAM_OK;
+    if ((st = enter(ctx)) != RAM_OK) return st;
+    void *cur = qbar, *oth = qbar_work;
+    auto at = [&](const void *base, int64_t k) {
+        return base ? (const void *)((const char *)base + (size_t)k * state_bytes) : nullptr;
+    };
+    if (layout->edges_shared &&
+        use_fast_adjoint(ctx, layout, dtype, {q_traj, q_half, dv, qbar, qbar_work, dvbar_accum}) &&
+        state_bytes % 16 == 0) {
+        // one plan for every step: the shift is the same at each
+        ram::StepAdjArgs a;
+        if ((st = plan_adjoint_fast(ctx, layout, edges, v0, dt, order, dv, dvbar_accum,
+                                    v0bar_accum, a)) != RAM_OK)
+            return st;
+        for (int64_t k = n_steps - 1; k >= 0; --k) {
+            a.q_fwd = at(q_traj, k);
+            a.q_half = dv ? at(q_half, k) : nullptr;
+            a.qbar_out = cur;
+            a.qbar_in = oth;
+            const hipError_t e = ram::launch_step_adjoint_fast(a, order, ctx->stream);
+            if (e != hipSuccess) return hip_fail(e, "step adjoint launch");
+            std::swap(cur, oth);
+        }
+    } else {
+        for (int64_t k = n_steps - 1; k >= 0; --k) {
+            if ((st = ram_step_adjoint(ctx, layout, dtype, at(q_traj, k),
+                                       dv ? at(q_half, k) : nullptr, dv, cur, oth, edges, v0,
+                                       dt, order, dvbar_accum, v0bar_accum)) != RAM_OK)
+                return st;
+            std::swap(cur, oth);
+        }
+    }
+    if (cur != qbar) {
+        const hipError_t e = ram::launch_copy(cur, qbar, (int64_t)state_bytes, ctx->stream);
+        if (e != hipSuccess) return hip_fail(e, "copy launch");
+    }
     return RAM_OK;
 }
 

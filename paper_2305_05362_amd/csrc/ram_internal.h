@@ -157,7 +157,8 @@ struct FastTile {
     int32_t wlo_lo, wlo_hi;  // extended source index of the window start
     float cc[6];             // uniform: weights of the (order+1)-point stencil
     float dx, hinv, dxinv;   // uniform: the run's cell size, 1/centre gap, 1/size
-    int32_t pad[2];
+    int32_t pad[2];          // tile id; the k-th other tile: k (its node data),
+                             // a uniform tile: the bits of its FP32 theta
 };
 static_assert(sizeof(FastTile) == 64, "one record a tile");
 // The tiles of one call: their records (rec[0 .. n_tiles)), then the same
@@ -318,6 +319,9 @@ struct StepAdjArgs {
     double dt = 0.0;
     const int64_t *plan_wlo = nullptr;  // window plan of the shift (no halo)
     const int32_t *plan_w = nullptr;    // [n_tiles] lengths, [n_tiles] starts mod n
+    FastPlan fast;                      // streaming adjoint: the shift's tile plan (no halo)
+    float *edge = nullptr;              // streaming adjoint: [n_tiles][2 order] the window's
+                                        // first and last cells' terms of each tile
 };
 
 struct ResidualAdjArgs {
@@ -399,6 +403,12 @@ hipError_t launch_v0_reduce(const Rows &R, const double *part, double *v0bar,
 // Zero the cells several tiles accumulate into, then the fused adjoint.
 hipError_t launch_step_adjoint_shared(const StepAdjArgs &a, bool f64, int order,
                                       hipStream_t stream);
+// The same step backwards for an FP32 state on rows of a multiple of four
+// cells (16-byte aligned states), one tile of kFastTile cells a wave, on the
+// shift's tile plan without halo (a.fast, from launch_plan_fast): the
+// uniform-run tiles, the other tiles, the sums of the window cells that
+// neighbouring tiles share (a.edge), the v0bar sums.
+hipError_t launch_step_adjoint_fast(const StepAdjArgs &a, int order, hipStream_t stream);
 hipError_t launch_copy(const void *src, void *dst, int64_t bytes,
                        hipStream_t stream);
 // Bulk shift with a limited reconstruction (recon: Recon) on any layout; a.dv

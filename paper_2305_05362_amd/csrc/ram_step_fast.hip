@@ -32,6 +32,7 @@
 // Tiles of 256 cells keep the searching tiles to the cells near the mesh's
 // non-uniform stretches.
 #include "ram_device.h"
+#include "ram_wave.h"
 
 #include <type_traits>
 
@@ -41,8 +42,6 @@ namespace {
 using namespace dev;
 
 constexpr int kFT = kFastTile;                      // destination cells per tile (wave)
-constexpr int kLanes = 64;
-constexpr int kWaves = kBlock / kLanes;             // tiles per workgroup
 constexpr int kFPad = 16;                           // slack for vector over-reads
 
 // LDS of one wave.  The window (values or masses), the direct path's extended
@@ -66,15 +65,6 @@ template <int S> constexpr size_t wave_lds_bytes()
     return S == kSumDirect ? WaveLds::u : WaveLds::u_pre;
 }
 
-// Every lane's LDS writes visible to the whole wave (a wave executes its LDS
-// instructions in order; the fences keep the compiler from moving accesses
-// across).
-__device__ inline void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // The record of one tile: which path, its window, and for a uniform tile the
 // stencil and the run's geometry.  One thread per tile; the node search is the
@@ -129,6 +119,7 @@ __global__ __launch_bounds__(64) void k_plan_fast(StepArgs a, FastTile *out)
         double cc[P + 1];
         uniform_stencil<double, P>(th, cc);
         for (int d = 0; d <= P; ++d) ft.cc[d] = (float)cc[d];
+        ft.pad[1] = __float_as_int((float)th);
         const float2 rr = R.tab.rrf[i0];
         ft.dx = rr.x;
         ft.hinv = rr.y;
@@ -137,7 +128,6 @@ __global__ __launch_bounds__(64) void k_plan_fast(StepArgs a, FastTile *out)
     out[tile] = ft;
 }
 
-__device__ inline int wrap1f(int j, int n) { return j < 0 ? j + n : (j >= n ? j - n : j); }
 
 // Residual step on four consecutive cells of a lane from the shifted state
 // s[0..7] of cells i0+4l-2 .. i0+4l+5 (Section 3.1 reading R7): fluxes on the
@@ -170,21 +160,6 @@ __device__ __forceinline__ void residual4(const float *s, const float *dvv, floa
     for (int k = 0; k < 4; ++k) out[k] = s[k + 2] - dt * (F[k + 1] - F[k]) * dxi(k);
 }
 
-// Tile id -> row and first cell (tiles of kFT cells, row by row).
-struct TilePos {
-    int row, i0, nd;
-    bool inner;          // the tile and its halo do not wrap the row
-};
-__device__ inline TilePos tile_pos(int tile, int n, int H)
-{
-    const int tpr = (n + kFT - 1) / kFT;
-    TilePos p;
-    p.row = tile / tpr;
-    p.i0 = (tile - p.row * tpr) * kFT;
-    p.nd = min(kFT, n - p.i0);
-    p.inner = (p.i0 - H >= 0) && (p.i0 + p.nd + H < n);
-    return p;
-}
 
 // Residual velocity of faces i0+4l .. i0+4l+4 of a row (face n is face 0);
 // lanes past the tile read its last faces again (every load issued, no
@@ -225,27 +200,7 @@ __device__ __forceinline__ void store_cells(float *qo, int i0, int nd, int c4, c
     }
 }
 
-// Record i, read through the constant address space: with a wave-uniform i
-// these are scalar loads (the host pass, which only checks device code, reads
-// it plainly).
-__device__ inline FastTile load_rec(const FastTile *rec, int i)
-{
-    FastTile r;
-#if defined(__HIP_DEVICE_COMPILE__)
-    typedef const __attribute__((address_space(4))) int32_t *CI;
-    const CI c = (CI)(rec + i);
-    int32_t *o = (int32_t *)&r;
-#pragma unroll
-    for (int k = 0; k < (int)(sizeof(FastTile) / 4); ++k) o[k] = c[k];
-#else
-    r = rec[i];
-#endif
-    return r;
-}
 
-// Wave index inside the workgroup, in a scalar register (so that what it
-// selects is read with scalar loads).
-__device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane((int)threadIdx.x / kLanes); }
 
 // ---------------------------------------------------------------------------
 // A tile in a uniform run of the mesh: straight-line code (clamped indices
@@ -609,33 +564,6 @@ __device__ __forceinline__ void general_tile(const StepArgs &a, const FastTile &
 // The window is stored from the 16-byte boundary at or below its start (LDS
 // index j + off for window cell j), so that its groups go in whole.
 // ---------------------------------------------------------------------------
-
-// Inclusive scan of one value a lane over the wave in DPP steps (row shifts,
-// then the row-15 and row-31 broadcasts; lanes without a source read zero),
-// and lane 63's value read back as a scalar.
-template <class AC>
-__device__ __forceinline__ typename AC::A wave_inclusive(typename AC::A inc)
-{
-    inc = AC::comb(AC::template dpp<kDppRowShr1, 0xf, 0xf>(inc), inc);
-    inc = AC::comb(AC::template dpp<kDppRowShr2, 0xf, 0xf>(inc), inc);
-    inc = AC::comb(AC::template dpp<kDppRowShr4, 0xf, 0xf>(inc), inc);
-    inc = AC::comb(AC::template dpp<kDppRowShr8, 0xf, 0xf>(inc), inc);
-    inc = AC::comb(AC::template dpp<kDppBcast15, 0xa, 0xf>(inc), inc);
-    inc = AC::comb(AC::template dpp<kDppBcast31, 0xc, 0xf>(inc), inc);
-    return inc;
-}
-__device__ __forceinline__ float lane63(float v)
-{
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), kLanes - 1));
-}
-__device__ __forceinline__ float2 lane63(float2 v) { return make_float2(lane63(v.x), lane63(v.y)); }
-__device__ __forceinline__ double lane63(double v)
-{
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), kLanes - 1);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), kLanes - 1);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
 
 // The prefix modes (S other than kSumDirect): the window's exclusive
 // cumulative of the masses, in the mode's precision (Acc<S>), at LDS index

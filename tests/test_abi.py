@@ -127,6 +127,32 @@ def test_record_and_step_adjoint_argument_errors(lib):
     assert st == R.RAM_E_INVALID_ARG and b"context" in lib.ram_last_error()
 
 
+def test_step_adjoint_steps_argument_errors(lib):
+    from paper_2305_05362_amd import _lib as R
+    L = _layout()                            # 2 x 16 cells: 256 bytes a state in FP64
+    traj, half, dv, qb, wk, e, v0 = (ctypes.c_void_p(0x100000 * i) for i in range(1, 8))
+    I64 = ctypes.c_int64
+
+    def call(*, q_traj=traj, q_half=half, dvp=dv, qbar=qb, work=wk, n=4, dvbar=None):
+        return lib.ram_step_adjoint_steps(None, ctypes.byref(L), R.RAM_F64, q_traj, q_half,
+                                          dvp, qbar, work, e, v0, 0.1, 5, I64(n), dvbar, None)
+    assert call(work=None) == R.RAM_E_INVALID_ARG and b"qbar_work" in lib.ram_last_error()
+    assert call(q_half=None) == R.RAM_E_INVALID_ARG and b"q_half" in lib.ram_last_error()
+    st = call(dvp=None, q_half=None, dvbar=ctypes.c_void_p(0x900000))
+    assert st == R.RAM_E_INVALID_ARG and b"dvbar" in lib.ram_last_error()
+    assert call(n=-1) == R.RAM_E_INVALID_ARG and b"n_steps" in lib.ram_last_error()
+    # the workspace inside the trajectory, the gradient on the workspace
+    st = call(work=ctypes.c_void_p(0x100000 + 3 * 256))
+    assert st == R.RAM_E_INVALID_ARG and b"overlap" in lib.ram_last_error()
+    st = call(qbar=ctypes.c_void_p(0x500000 + 100))
+    assert st == R.RAM_E_INVALID_ARG and b"overlap" in lib.ram_last_error()
+    # the workspace past the trajectory's n_steps states is free
+    st = call(work=ctypes.c_void_p(0x100000 + 4 * 256))
+    assert st == R.RAM_E_INVALID_ARG and b"context" in lib.ram_last_error()
+    # no steps: nothing to do, before the context is needed
+    assert call(n=0) == R.RAM_OK
+
+
 def test_limited_argument_errors(lib):
     from paper_2305_05362_amd import _lib as R
     L = _layout()
