@@ -267,6 +267,29 @@ ram_status ram_shift_limited_adjoint(ram_ctx *ctx, const ram_layout *layout,
                                      const double *v0, double dt,
                                      double *v0bar_accum);
 
+/* Adjoint of one limited step Q^{n+1} = Res(ShiftLimited(Q^n)) (the
+ * transposes of ram_residual_adjoint and ram_shift_limited_adjoint composed,
+ * in one pass over the data on a shared mesh):
+ *   qbar_in = (dS/dQ at q_fwd)^T R_q^T qbar_out (overwritten),
+ *   dvbar_accum += R_dv^T qbar_out      (when non-NULL, dtype of q),
+ *   v0bar_accum[r] += dt d<R^T qbar_out, S(s) q_fwd>/ds at s = v0[r] dt
+ *                                        (when non-NULL, FP64).
+ * q_fwd: the state the limited shift read (required); q_half: the state the
+ * residual read (needed when dv != NULL; ram_step_limited_record writes it);
+ * dv == NULL: the step had no residual (then this is
+ * ram_shift_limited_adjoint).  Conventions at kinks as the two adjoints
+ * composed.  The residual part computes in dtype; the limited shift's
+ * Jacobian rows in FP64 (positions in cells, limiter branches, mesh weights),
+ * accumulated in FP64 and rounded to dtype on the store.  qbar_in must not
+ * alias any input. */
+ram_status ram_step_limited_adjoint(ram_ctx *ctx, const ram_layout *layout,
+                                    ram_dtype dtype, ram_recon recon,
+                                    const void *q_fwd, const void *q_half,
+                                    const void *dv, const void *qbar_out,
+                                    void *qbar_in, const double *edges,
+                                    const double *v0, double dt,
+                                    void *dvbar_accum, double *v0bar_accum);
+
 /* Adjoint of ram_shift (the shift is linear in Q): qbar_in = S^T qbar_out,
  * overwritten.  When v0bar_accum != NULL, also accumulates per row
  *   v0bar_accum[r] += dt * d<qbar_out, S(s) q_fwd>/ds  at s = v0[r] dt,

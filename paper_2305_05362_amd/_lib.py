@@ -105,6 +105,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ram_row_norms": [P, LP, I, P, P, P, P],
         "ram_step_tile_paths": [P, LP, P, P, D, I, I, P, I64, ctypes.POINTER(I64)],
         "ram_shift_limited_adjoint": [P, LP, I, I, P, P, P, P, P, D, P],
+        "ram_step_limited_adjoint": [P, LP, I, I, P, P, P, P, P, P, P, D, P, P],
         "ram_step_limited_record": [P, LP, I, I, P, P, P, P, P, D, I64],
         "ram_set_schedule": [P, ctypes.POINTER(Schedule)],
         "ram_get_schedule": [P, ctypes.POINTER(Schedule)],
@@ -318,6 +319,19 @@ class Context:
             _dev_ptr(v0bar, torch.float64, "v0bar")))
         return qbar_in
 
+    def ram_step_limited_adjoint(self, rows: Rows, q_fwd, q_half, dv, qbar_out, qbar_in, v0,
+                                 dt: float, recon: int, dvbar=None, v0bar=None):
+        self._stream()
+        t = qbar_out.dtype
+        check(self._lib.ram_step_limited_adjoint(
+            self._h, ctypes.byref(rows.layout), _dtype_code(qbar_out), int(recon),
+            _dev_ptr(q_fwd, t, "q_fwd"), _dev_ptr(q_half, t, "q_half"), _dev_ptr(dv, t, "dv"),
+            _dev_ptr(qbar_out, t, "qbar_out"), _dev_ptr(qbar_in, t, "qbar_in"),
+            _dev_ptr(rows.edges, torch.float64, "edges"),
+            _dev_ptr(v0, torch.float64, "v0"), float(dt),
+            _dev_ptr(dvbar, t, "dvbar"), _dev_ptr(v0bar, torch.float64, "v0bar")))
+        return qbar_in
+
     def ram_radial_step(self, rows: Rows, q_in, q_out, r_edges, u, dt: float):
         self._stream()
         check(self._lib.ram_radial_step(
@@ -517,6 +531,12 @@ def ram_step_limited(rows, q, v0, dv, dt, recon, n_steps):
 def ram_shift_limited_adjoint(rows, q_fwd, qbar_out, qbar_in, v0, dt, recon, v0bar=None):
     return context(qbar_out.device.index).ram_shift_limited_adjoint(
         rows, q_fwd, qbar_out, qbar_in, v0, dt, recon, v0bar)
+
+
+def ram_step_limited_adjoint(rows, q_fwd, q_half, dv, qbar_out, qbar_in, v0, dt, recon,
+                             dvbar=None, v0bar=None):
+    return context(qbar_out.device.index).ram_step_limited_adjoint(
+        rows, q_fwd, q_half, dv, qbar_out, qbar_in, v0, dt, recon, dvbar, v0bar)
 
 
 def ram_step_tile_paths(rows, v0, dt, order, with_residual):

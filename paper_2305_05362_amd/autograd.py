@@ -13,9 +13,9 @@ plan for the segment).
 
 With ``recon`` (RAM_RECON_PLM or RAM_RECON_PPM) the bulk shift is the limited
 one of Section 3.1: the forward runs ram_step_limited /
-ram_step_limited_record, and each backward step is ram_residual_adjoint
-followed by ram_shift_limited_adjoint (the transposed Jacobian at the state
-the shift read).  Every step of both directions runs in the library's HIP
+ram_step_limited_record, and each backward step is ram_step_limited_adjoint
+(the residual's transpose, then the limited shift's transposed Jacobian at
+the state the shift read, in one pass).  Every step of both directions runs in the library's HIP
 kernels; torch only holds the tensors.
 """
 from __future__ import annotations
@@ -41,20 +41,18 @@ def _record(ctx, rows, traj, half, v0, dv, dt, order, k, scan, recon):
         ctx.ram_step_record(rows, traj, half, v0, dv, dt, order, k, scan)
 
 
-def _step_adjoint(ctx, rows, q_fwd, q_half, dv, qbar, out, work, v0, dt, order, recon,
-                  dvbar, v0bar):
+def _step_adjoint(ctx, rows, q_fwd, q_half, dv, qbar, out, v0, dt, order, recon, dvbar,
+                  v0bar):
     """out = (one step's Jacobian)^T qbar; dvbar, v0bar accumulate."""
     if not recon:
         ctx.ram_step_adjoint(rows, q_fwd, q_half, dv, qbar, out, v0, dt, order, dvbar, v0bar)
         return
-    if dv is not None:
-        ctx.ram_residual_adjoint(rows, q_half, dv, qbar, work, dt, dvbar)
-        qbar = work
-    ctx.ram_shift_limited_adjoint(rows, q_fwd, qbar, out, v0, dt, recon, v0bar)
+    ctx.ram_step_limited_adjoint(rows, q_fwd, q_half, dv, qbar, out, v0, dt, recon, dvbar,
+                                 v0bar)
 
 
-def _walk_back(ctx, rows, traj, half, dv, qbar, tmp, work, v0, dt, order, recon, k,
-               dvbar, v0bar):
+def _walk_back(ctx, rows, traj, half, dv, qbar, tmp, v0, dt, order, recon, k, dvbar,
+               v0bar):
     """qbar (in place): the gradient of the segment's last state back to its
     first, through its k recorded steps (one call without a limiter: the
     steps share the shift's tile plan)."""
@@ -65,7 +63,7 @@ def _walk_back(ctx, rows, traj, half, dv, qbar, tmp, work, v0, dt, order, recon,
     cur, oth = qbar, tmp
     for i in range(k - 1, -1, -1):
         _step_adjoint(ctx, rows, traj[i], None if half is None else half[i], dv,
-                      cur, oth, work, v0, dt, order, recon, dvbar, v0bar)
+                      cur, oth, v0, dt, order, recon, dvbar, v0bar)
         cur, oth = oth, cur
     if cur is not qbar:
         qbar.copy_(cur)
@@ -127,7 +125,6 @@ class RamRollout(torch.autograd.Function):
         rows, dt, order, scan, recon = fctx.rows, fctx.dt, fctx.order, fctx.scan, fctx.recon
         qbar = gq.contiguous().clone()
         tmp = torch.empty_like(qbar)
-        work = torch.empty_like(qbar) if recon and dv is not None else None
         # only the gradients an input asks for: the v0 term (the
         # reconstruction at every shifted node) and the dv accumulation are
         # skipped in the kernels when v0 or dv needs none
@@ -138,7 +135,7 @@ class RamRollout(torch.autograd.Function):
         if fctx.stored:
             traj = checkpoints[0]
             half = checkpoints[1] if dv is not None else None
-            _walk_back(ctx, rows, traj, half, dv, qbar, tmp, work, v0, dt, order, recon,
+            _walk_back(ctx, rows, traj, half, dv, qbar, tmp, v0, dt, order, recon,
                        fctx.n_steps, dvbar, v0bar)
             return (qbar, dvbar, None if v0bar is None else v0bar.to(v0.dtype), None, None,
                     None, None, None, None, None)
@@ -154,7 +151,7 @@ class RamRollout(torch.autograd.Function):
             # the state each residual step read (one fused launch per step)
             traj[0].copy_(checkpoints[sgi].reshape(-1))
             _record(ctx, rows, traj, half, v0, dv, dt, order, k, scan, recon)
-            _walk_back(ctx, rows, traj, half, dv, qbar, tmp, work, v0, dt, order, recon, k,
+            _walk_back(ctx, rows, traj, half, dv, qbar, tmp, v0, dt, order, recon, k,
                        dvbar, v0bar)
         return (qbar, dvbar, None if v0bar is None else v0bar.to(v0.dtype), None, None, None,
                 None, None, None, None)

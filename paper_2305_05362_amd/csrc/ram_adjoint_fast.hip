@@ -344,11 +344,11 @@ __device__ __forceinline__ void adj_uniform_tile(const StepAdjArgs &a, const Fas
 // Qbar^{n+1/2} / dx of the tile's cells into smb[1 + u] (smb[0] and
 // smb[nd + 1] zero: the tile's nodes' Vbar_e = smb[e] - smb[e + 1]).
 // ---------------------------------------------------------------------------
-template <bool RES, class After>
+template <bool RES, class After, class Store>
 __device__ __forceinline__ void res_general(const StepAdjArgs &a, const ResIn &ri,
                                             const float2 (&rr)[8], const float (&dxi)[8],
                                             int64_t qoff, int i0, int nd, int cl, int t,
-                                            bool want_dvb, float *st, float *smb, After after)
+                                            bool want_dvb, float *st, After after, Store store)
 {
     const int c4 = 4 * t;
     float gs[4];
@@ -370,6 +370,15 @@ __device__ __forceinline__ void res_general(const StepAdjArgs &a, const ResIn &r
         after();
         f4(ri.qb4, gs);
     }
+    store(gs);
+}
+
+// Mbar' = Qbar^{n+1/2} / dx of the lane's four cells into smb[1 + u], with
+// smb[0] and smb[nd + 1] zero (FP32 from the FP32 sizes).
+__device__ __forceinline__ void store_mb(float *smb, const float (&gs)[4], const float (&dxi)[8],
+                                         int nd, int t)
+{
+    const int c4 = 4 * t;
     if (c4 < nd) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) smb[1 + c4 + k] = gs[k] * dxi[2 + k];
@@ -403,9 +412,9 @@ __device__ __forceinline__ void load_geom(const MeshTab &tb, int n, int cb, floa
 
 // v0bar of a tile from q~ at its nodes (node m = t + 64u in slot u) and Mbar'
 // in smb: -dt sum_i Mbar'_i (q~_{i+1} - q~_i), one term a tile.
-template <int NS>
+template <int NS, typename MT>
 __device__ __forceinline__ void v0_term(const StepAdjArgs &a, int tile, const double (&qt)[NS],
-                                        const float *smb, int nd, int t)
+                                        const MT *smb, int nd, int t)
 {
     double vp = 0.0;
 #pragma unroll
@@ -498,7 +507,8 @@ __device__ __forceinline__ void adj_window_tile(const StepAdjArgs &a, const Fast
     }
 
     // ---- 3. the residual's transpose -> Mbar' ------------------------------------
-    res_general<RES>(a, ri, rr, dxi, qoff, i0, nd, cl, t, want_dvb, (float *)su, smb, load_win);
+    res_general<RES>(a, ri, rr, dxi, qoff, i0, nd, cl, t, want_dvb, (float *)su, load_win,
+                     [&](const float (&gs)[4]) { store_mb(smb, gs, dxi, nd, t); });
     wave_sync();                                     // staging dead, smb visible
 
     // ---- 4. q~ at the nodes from the window masses (FP64), v0bar -----------------
@@ -697,7 +707,8 @@ __device__ __forceinline__ void adj_direct_tile(const StepAdjArgs &a, const Fast
     float dxi[8];
     if constexpr (RES) load_geom(tb, n, i0 + cl - 2, rr, dxi);
     else f4(*(const float4 *)(tb.dxinvf + i0 + cl), dxi + 2);
-    res_general<RES>(a, ri, rr, dxi, qoff, i0, nd, cl, t, want_dvb, (float *)su, smb, [] {});
+    res_general<RES>(a, ri, rr, dxi, qoff, i0, nd, cl, t, want_dvb, (float *)su, [] {},
+                     [&](const float (&gs)[4]) { store_mb(smb, gs, dxi, nd, t); });
     wave_sync();
 
     int64_t *sgd = (int64_t *)su;                    // node m's extended source index
@@ -826,6 +837,350 @@ __global__ __launch_bounds__(256) void k_adjf_edges(StepAdjArgs a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// The limited (PLM / PPM) step backwards: the same tiles, plan and edge sums
+// with p = 2 lo + 1 (the reconstruction's stencil, lo cells a side).  The
+// limited shift is nonlinear in Q, and its transpose is that of its Jacobian
+// at Q^n with each limiter differentiated on the branch it takes there (a
+// zero slope where the one-sided differences do not share a sign):
+//     Qbar_m = dx_m Mbar'_i (m a whole cell of destination i)
+//            + sum_e Vbar_e d ell_e / d Q_m   (|c_e - m| <= lo),
+// ell_e the partial integral of node e's cell.  Each node's Jacobian row and
+// reconstruction value are evaluated in FP64 from the FP32 state and the
+// mesh's FP64 tables, at its FP64 position in its cell (the plan gives the
+// cell; uniform runs and searching tiles alike), so the limiters take the
+// branches the FP64 evaluation takes; the terms accumulate in FP64 in LDS.
+// ---------------------------------------------------------------------------
+
+__device__ inline int64_t rec_wlo(const FastTile &r)
+{
+    return (int64_t)(((uint64_t)(uint32_t)r.wlo_hi << 32) | (uint32_t)r.wlo_lo);
+}
+
+// d ell / d Q_{c-lo+j} (j = 0 .. 2 lo) of the limited partial integral of
+// cell c (size h) at theta, and the reconstruction's value there, from the
+// averages qv of cells c-lo .. c+lo: PLM with the van Leer slope over the
+// reciprocal centre gaps; PPM with the limited slopes of cells c-1 .. c+1,
+// the interface values c-1/2 and c+1/2 and the constrained parabola (the
+// forward's reconstruction of Section 3.1's reading), chained back through
+// the branch each limiter takes.
+template <int R>
+__device__ __forceinline__ void lim_node(const MeshTab &tb, int n, int c, double h, double th,
+                                         const double (&qv)[2 * LimHalo<R>::lo + 1],
+                                         double (&gw)[2 * LimHalo<R>::lo + 1], double &qval)
+{
+    if constexpr (R == kReconPLM) {
+        const int cm = c == 0 ? n - 1 : c - 1;
+        const double gp = tb.hinv[c], gm = tb.hinv[cm];
+        const double av = (qv[2] - qv[1]) * gp, bv = (qv[1] - qv[0]) * gm;
+        double sig = 0.0, dsa = 0.0, dsb = 0.0;
+        if (av * bv > 0.0) {
+            const double s2 = (av + bv) * (av + bv);
+            sig = 2.0 * av * bv / (av + bv);
+            dsa = 2.0 * bv * bv / s2;
+            dsb = 2.0 * av * av / s2;
+        }
+        // ell = Q_c h theta + sigma h^2 (theta^2 - theta) / 2
+        const double ks = 0.5 * h * h * (th * th - th);
+        gw[0] = -ks * dsb * gm;
+        gw[1] = h * th + ks * (dsb * gm - dsa * gp);
+        gw[2] = ks * dsa * gp;
+        qval = qv[1] + sig * h * (th - 0.5);
+    } else {
+        // slope weights of cells c-1 .. c+1, interface weights of c-1 and c
+        const double *pw = tb.ppmd;
+        double d1[3], d2[3], e1[2], e2[2], e3[2];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            int m = c - 1 + k;
+            m = m < 0 ? m + n : (m >= n ? m - n : m);
+            d1[k] = pw[m];
+            d2[k] = pw[n + m];
+            if (k < 2) {
+                e1[k] = pw[2 * n + m];
+                e2[k] = pw[3 * n + m];
+                e3[k] = pw[4 * n + m];
+            }
+        }
+        // limited slopes of cells c-1, c, c+1 and their derivatives with
+        // respect to the averages of each slope's cells
+        double dl[3], dd[3][3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double up = qv[k + 2] - qv[k + 1], dn = qv[k + 1] - qv[k];
+            const double d = d1[k] * up + d2[k] * dn;
+            dd[k][0] = dd[k][1] = dd[k][2] = 0.0;
+            dl[k] = 0.0;
+            if (up * dn > 0.0) {
+                dl[k] = copysign(fmin(fabs(d), 2.0 * fmin(fabs(up), fabs(dn))), d);
+                if (fabs(d) <= 2.0 * fabs(up) && fabs(d) <= 2.0 * fabs(dn)) {
+                    dd[k][0] = -d2[k];
+                    dd[k][1] = d2[k] - d1[k];
+                    dd[k][2] = d1[k];
+                } else if (fabs(up) <= fabs(dn)) {
+                    dd[k][1] = -2.0;                 // twice the upper difference
+                    dd[k][2] = 2.0;
+                } else {
+                    dd[k][0] = -2.0;                 // twice the lower difference
+                    dd[k][1] = 2.0;
+                }
+            }
+        }
+        // interface values c-1/2 and c+1/2 before the constraints
+        const double Lr = qv[1] + e1[0] * (qv[2] - qv[1]) + e2[0] * dl[1] + e3[0] * dl[0];
+        const double Rr = qv[2] + e1[1] * (qv[3] - qv[2]) + e2[1] * dl[2] + e3[1] * dl[1];
+        const double a = qv[2];
+        double L = Lr, Rv = Rr;
+        int branch = 0;                              // 1 flat, 2 L pulled in, 3 R pulled in
+        if ((Rv - a) * (a - L) <= 0.0) {
+            L = a;
+            Rv = a;
+            branch = 1;
+        } else {
+            const double dq = Rv - L, qa = a - 0.5 * (L + Rv);
+            if (dq * qa > dq * dq / 6.0) { L = 3.0 * a - 2.0 * Rv; branch = 2; }
+            else if (-dq * dq / 6.0 > dq * qa) { Rv = 3.0 * a - 2.0 * L; branch = 3; }
+        }
+        const double q6 = 6.0 * a - 3.0 * (L + Rv);
+        qval = L + th * (Rv - L) + q6 * th * (1.0 - th);
+        // d ell / d (a, L, R) with q6 expanded, then back through the branch
+        const double th2 = th * th, th3 = th2 * th;
+        const double ga = h * (3.0 * th2 - 2.0 * th3);
+        const double gl = h * (th - 2.0 * th2 + th3);
+        const double gr = h * (th3 - th2);
+        double ba = ga, bl = gl, br = gr;
+        if (branch == 1) { ba = ga + gl + gr; bl = 0.0; br = 0.0; }
+        else if (branch == 2) { ba = ga + 3.0 * gl; bl = 0.0; br = gr - 2.0 * gl; }
+        else if (branch == 3) { ba = ga + 3.0 * gr; bl = gl - 2.0 * gr; br = 0.0; }
+        double gb[5] = {0.0, 0.0, ba, 0.0, 0.0};
+        const double bd[3] = {bl * e3[0], bl * e2[0] + br * e3[1], br * e2[1]};
+        gb[1] += bl * (1.0 - e1[0]);
+        gb[2] += bl * e1[0] + br * (1.0 - e1[1]);
+        gb[3] += br * e1[1];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) gb[k + j] += bd[k] * dd[k][j];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) gw[k] = gb[k];
+    }
+}
+
+constexpr size_t kLimStage = 4 * (kFastWin + 16);   // a tile's window averages, LDS bytes
+
+// One tile of the limited step backwards (any kind: the uniform runs save
+// only the search, every node's Jacobian row is evaluated).
+template <int R, bool RES, bool V0>
+__device__ __forceinline__ void lim_tile(const StepAdjArgs &a, const FastTile &ft,
+                                         unsigned char *su, float *sqw, double *smb, int t)
+{
+    constexpr int LO = LimHalo<R>::lo;
+    constexpr int P = 2 * LO + 1;
+    constexpr int NS = (kFastNodes + kLanes - 1) / kLanes;
+    constexpr int NG = (kFastWin + 3 + 4 * kLanes - 1) / (4 * kLanes);   // window groups a lane
+    constexpr int kCh = (int)(kGenU / 8) - 8;        // window cells a chunk of the accumulator
+    const Rows &Rw = a.rows;
+    const MeshTab &tb = Rw.tab;
+    const int n = (int)Rw.n_cols;
+    const int tile = ft.pad[0];
+    const TilePos p = tile_pos(tile, n, 0);
+    const int i0 = p.i0, nd = p.nd, NE = nd + 1, c4 = 4 * t, cl = min(c4, nd - 4);
+    const int64_t qoff = (int64_t)p.row * n;
+    const float *qf = (const float *)a.q_fwd + qoff;
+    float *qbi = (float *)a.qbar_in + qoff;
+    const double *x = Rw.edges;
+    const double x0 = x[0], xN = x[n], len = xN - x0;
+    const RowShift rs = row_shift(a.v0[p.row] * a.dt, len, tb.scal[1]);
+    const bool uniform = ft.kind == kFastUniform;
+    const bool windowed =
+        uniform || (ft.kind == kFastWindow && ft.base + ft.w + 3 < 2 * n && ft.w <= kFastWin);
+    // the window: this tile's first node's stencil up to the next tile's
+    // (the row's first tile one period on, for the last tile of a row)
+    const int tpr = (n + kFT - 1) / kFT;
+    const int64_t wl = rec_wlo(a.fast.rec[tile]);
+    const int64_t wend =
+        (i0 + nd >= n ? rec_wlo(a.fast.rec[tile - (tpr - 1)]) + n : rec_wlo(a.fast.rec[tile + 1])) +
+        P;
+    const int W = (int)(wend - wl);
+    const int base = ft.base, a0 = base & ~3, off = base - a0;
+    const int gl = (W + off - 1) >> 2;
+
+    // ---- 1. the residual's transpose (or the gradient as given): Mbar' in FP64
+    const bool want_dvb = RES && a.dvbar != nullptr;
+    const ResIn ri = res_load<RES>(a, qoff, n, i0, nd, cl, want_dvb);
+    float2 rr[8];
+    float dxi[8];
+    if constexpr (RES) load_geom(tb, n, i0 + cl - 2, rr, dxi);
+    const double2 di01 = *(const double2 *)(tb.dxinv + i0 + cl);
+    const double2 di23 = *(const double2 *)(tb.dxinv + i0 + cl + 2);
+    float wq[NG][4];
+    auto load_win = [&]() {
+        if (windowed) {
+#pragma unroll
+            for (int u = 0; u < NG; ++u) {
+                int c = a0 + 4 * min(t + u * kLanes, gl);
+                c = c >= n ? c - n : c;
+                f4(*(const float4 *)(qf + c), wq[u]);
+            }
+        }
+    };
+    res_general<RES>(a, ri, rr, dxi, qoff, i0, nd, cl, t, want_dvb, (float *)su, load_win,
+                     [&](const float (&gs)[4]) {
+                         const double di[4] = {di01.x, di01.y, di23.x, di23.y};
+                         if (c4 < nd) {
+#pragma unroll
+                             for (int k = 0; k < 4; ++k) smb[1 + c4 + k] = (double)gs[k] * di[k];
+                         }
+                         if (t == 0) {
+                             smb[0] = 0.0;
+                             smb[nd + 1] = 0.0;
+                         }
+                     });
+    // the window's averages at j + off (memory-aligned groups as loaded)
+    if (windowed) {
+#pragma unroll
+        for (int u = 0; u < NG; ++u) {
+            const int g = t + u * kLanes;
+            if (g <= gl)
+                *(float4 *)(sqw + 4 * g) = make_float4(wq[u][0], wq[u][1], wq[u][2], wq[u][3]);
+        }
+    }
+    wave_sync();                                     // staging dead; smb, averages visible
+
+    // ---- 2. every node's window index, cell and FP64 position in the cell ---------
+    const int16_t *jcp =
+        windowed && !uniform ? a.fast.jc + (int64_t)ft.pad[1] * kFastNodes : nullptr;
+    int kv[NS], cv[NS];
+    double thv[NS], hv[NS];
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+        const int m = min(t + u * kLanes, NE - 1);
+        const int e = i0 + m;
+        const int kx = e >= n ? 1 : 0;
+        const NodePos np = node_pos(x[e - kx * n], rs, x0, xN, tb.scal[0], tb.scal[2], tb.nb);
+        int c, k;
+        if (windowed) {
+            k = uniform ? LO + m : (int)jcp[m];
+            c = base + k;
+            c = c >= n ? c - n : c;
+        } else {
+            const double2 nx = tb.bnext[np.b];
+            c = cell_from_bucket(tb.bucket[np.b], nx, np.xt);
+            if (np.xt >= nx.y) c = cell_walk(x, n, c, np.xt);
+            const int64_t g = (int64_t)c + (rs.kf0 + np.dk + kx) * (int64_t)n;
+            k = (int)(g - wl);
+        }
+        const double h = tb.dx[c];
+        double d = np.xt - x[c];
+        d = d > 0.5 * len ? d - len : (d < -0.5 * len ? d + len : d);
+        kv[u] = k;
+        cv[u] = c;
+        thv[u] = d / h;
+        hv[u] = h;
+    }
+    // the next node's window index (node m + 1: the next lane, lane 63 the next slot's lane 0)
+    int kn[NS];
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+        kn[u] = __shfl_down(kv[u], 1);
+        if (u + 1 < NS) {
+            const int k0 = __shfl(kv[u + 1 < NS ? u + 1 : u], 0);
+            if (t == kLanes - 1) kn[u] = k0;
+        }
+    }
+
+    // ---- 3. Jacobian rows through Vbar, and the whole cells, chunk by chunk -------
+    // (one node slot at a time: each row is a long FP64 chain; v0bar as
+    // -sum_e Vbar_e q~_e, one term a node)
+    double *cacc = (double *)su;
+    double vp = 0.0;
+    float *edge = a.edge + (int64_t)tile * (2 * P);
+    for (int c0 = 0; c0 < W; c0 += kCh) {
+        const int cw = min(kCh, W - c0);
+        for (int j = t; j < cw; j += kLanes) cacc[j] = 0.0;
+        wave_sync();
+#pragma unroll 1
+        for (int u = 0; u < NS; ++u) {
+            const int m = t + u * kLanes;
+            const int k = kv[u], c = cv[u];
+            double qv[P];
+#pragma unroll
+            for (int j = 0; j < P; ++j) {
+                if (windowed) {
+                    qv[j] = (double)sqw[k - LO + j + off];
+                } else {
+                    int mm = c - LO + j;
+                    mm = mm < 0 ? mm + n : (mm >= n ? mm - n : mm);
+                    qv[j] = (double)qf[mm];
+                }
+            }
+            double gw[P], qval;
+            lim_node<R>(tb, n, c, hv[u], thv[u], qv, gw, qval);
+            if (m < NE) {
+                const double vb = smb[m] - smb[m + 1];
+                if (c0 == 0) vp -= vb * qval;
+#pragma unroll
+                for (int j = 0; j < P; ++j) {
+                    const int jj = k - LO + j - c0;
+                    if (jj >= 0 && jj < cw) atomicAdd(&cacc[jj], vb * gw[j]);
+                }
+                // destination m's whole cells: window cells k .. kn - 1
+                if (m < nd) {
+                    const double mb = smb[m + 1];
+                    for (int j = max(k, c0); j < min(kn[u], c0 + cw); ++j) {
+                        const double dxj =
+                            j == k ? hv[u] : tb.dx[wrapi(wl + j, n)];
+                        atomicAdd(&cacc[j - c0], mb * dxj);
+                    }
+                }
+            }
+        }
+        wave_sync();
+        for (int j = t; j < cw; j += kLanes)
+            put_cell<P>(qbi, edge, wrapi(wl + c0 + j, n), c0 + j, W, (float)cacc[j]);
+        wave_sync();
+    }
+    if constexpr (V0) {
+        vp = wave_sum(vp);
+        if (t == 0) a.v0part[tile] = a.dt * vp;
+    }
+}
+
+// Every tile, one a wave, in tile order.
+template <int R, bool RES, bool V0>
+__global__ __launch_bounds__(kBlock) void k_ladj(StepAdjArgs a)
+{
+    __shared__ __attribute__((aligned(16))) unsigned char su[kWaves][kGenU];
+    __shared__ __attribute__((aligned(16))) float sqw[kWaves][kLimStage / 4];
+    __shared__ __attribute__((aligned(16))) double smb[kWaves][kFT + 8];
+    const int wid = wave_id();
+    const int i = (int)blockIdx.x * kWaves + wid;
+    if (i >= (int)a.rows.n_tiles) return;
+    const FastTile r = load_rec(a.fast.rec, i);
+    lim_tile<R, RES, V0>(a, r, su[wid], sqw[wid], smb[wid], (int)threadIdx.x % kLanes);
+}
+
+template <int R, bool RES, bool V0>
+hipError_t ladj_kernels(const StepAdjArgs &a, hipStream_t st)
+{
+    constexpr int P = 2 * LimHalo<R>::lo + 1;
+    const int64_t nt = a.rows.n_tiles;
+    hipLaunchKernelGGL((k_ladj<R, RES, V0>), dim3((unsigned)((nt + kWaves - 1) / kWaves)),
+                       dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL((k_adjf_edges<P>), dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !V0) return e;
+    return launch_v0_reduce(a.rows, a.v0part, a.v0bar, st);
+}
+
+template <int R>
+hipError_t ladj_r(const StepAdjArgs &a, hipStream_t st)
+{
+    const bool v0 = a.v0bar != nullptr;
+    if (a.dv) return v0 ? ladj_kernels<R, true, true>(a, st) : ladj_kernels<R, true, false>(a, st);
+    return v0 ? ladj_kernels<R, false, true>(a, st) : ladj_kernels<R, false, false>(a, st);
+}
+
 // The uniform tiles (the compacted list's first part), one a wave.
 template <int P, bool RES, bool V0>
 __global__ __launch_bounds__(kBlock) void k_adjf_uni(StepAdjArgs a)
@@ -884,6 +1239,15 @@ hipError_t adjf_p(const StepAdjArgs &a, hipStream_t st)
 }
 
 } // namespace
+
+hipError_t launch_step_limited_adjoint_fast(const StepAdjArgs &a, int recon, hipStream_t stream)
+{
+    if (a.rows.n_tiles <= 0) return hipSuccess;
+    if (a.rows.tile != kFastTile || a.rows.n_cols % 4 != 0 || a.rows.n_cols < kFastTile + 8 ||
+        a.rows.n_tiles > INT32_MAX / 2 || !a.edge || !a.q_fwd)
+        return hipErrorInvalidValue;
+    return recon == kReconPLM ? ladj_r<kReconPLM>(a, stream) : ladj_r<kReconPPM>(a, stream);
+}
 
 hipError_t launch_step_adjoint_fast(const StepAdjArgs &a, int order, hipStream_t stream)
 {

@@ -1075,6 +1075,73 @@ ram_status ram_step_limited_record(ram_ctx *ctx, const ram_layout *layout,
     return RAM_OK;
 }
 
+} // extern "C"
+
+namespace {
+
+// The limited shift's transpose on the general kernel (any layout): into
+// qbar_in, or with qbar_in null into a scratch state copied back over
+// qbar_out's buffer `back` afterwards (a residual transpose's output).
+ram_status limited_adjoint_general(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtype,
+                                   ram_recon recon, const void *q_fwd, const void *qbar_out,
+                                   void *qbar_in, void *back, const double *edges,
+                                   const double *v0, double dt, double *v0bar_accum)
+{
+    ram_status st;
+    Carve cv;
+    // a shared mesh brings its tables (centre gaps, PPM weights)
+    RowsPlan rp = plan_rows(cv, layout, ram::kAdjTile, 1);
+    const size_t v0_off =
+        cv.take(v0bar_accum ? sizeof(double) * tiles_of(layout, ram::kAdjTile) : 0);
+    const size_t state_bytes = elem_size(dtype) * (size_t)layout_cells(layout);
+    const size_t tmp_off = qbar_in ? 0 : cv.take(state_bytes);
+    if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
+    ram::ShiftAdjArgs a;
+    if ((st = make_rows(ctx, layout, edges, rp, a.rows)) != RAM_OK) return st;
+    a.q_fwd = q_fwd;
+    a.qbar_out = qbar_out;
+    a.qbar_in = qbar_in ? qbar_in : (char *)ctx->scratch + tmp_off;
+    a.v0 = v0;
+    a.dt = dt;
+    a.v0bar = v0bar_accum;
+    a.v0part = (double *)((char *)ctx->scratch + v0_off);
+    hipError_t e = ram::launch_shift_limited_adjoint(a, dtype == RAM_F64, (int)recon,
+                                                     ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "limited shift adjoint launch");
+    if (!qbar_in) {
+        e = ram::launch_copy(a.qbar_in, back, (int64_t)state_bytes, ctx->stream);
+        if (e != hipSuccess) return hip_fail(e, "copy launch");
+    }
+    return RAM_OK;
+}
+
+// The streaming limited adjoint (FP32 state, shared mesh, default schedule,
+// rows of a multiple of four cells): one tile plan of the reconstruction's
+// stencil width, then the fused kernel.
+ram_status limited_adjoint_fast(ram_ctx *ctx, const ram_layout *layout, ram_recon recon,
+                                const void *q_fwd, const void *q_half, const void *dv,
+                                const void *qbar_out, void *qbar_in, const double *edges,
+                                const double *v0, double dt, void *dvbar, double *v0bar)
+{
+    ram_status st;
+    const int order = recon == RAM_RECON_PLM ? 3 : 5;
+    ram::StepAdjArgs a;
+    if ((st = plan_adjoint_fast(ctx, layout, edges, v0, dt, order, dv, dvbar, v0bar, a)) !=
+        RAM_OK)
+        return st;
+    a.q_fwd = q_fwd;
+    a.q_half = q_half;
+    a.qbar_out = qbar_out;
+    a.qbar_in = qbar_in;
+    const hipError_t e = ram::launch_step_limited_adjoint_fast(a, (int)recon, ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "limited step adjoint launch");
+    return RAM_OK;
+}
+
+} // namespace
+
+extern "C" {
+
 ram_status ram_shift_limited_adjoint(ram_ctx *ctx, const ram_layout *layout,
                                      ram_dtype dtype, ram_recon recon, const void *q_fwd,
                                      const void *qbar_out, void *qbar_in,
@@ -1092,25 +1159,47 @@ ram_status ram_shift_limited_adjoint(ram_ctx *ctx, const ram_layout *layout,
     if (qbar_in == qbar_out || qbar_in == q_fwd)
         return fail(RAM_E_INVALID_ARG, "qbar_in must not alias qbar_out or q_fwd");
     if ((st = enter(ctx)) != RAM_OK) return st;
-    Carve cv;
-    // a shared mesh brings its tables (centre gaps, PPM weights)
-    RowsPlan rp = plan_rows(cv, layout, ram::kAdjTile, 1);
-    const size_t v0_off =
-        cv.take(v0bar_accum ? sizeof(double) * tiles_of(layout, ram::kAdjTile) : 0);
-    if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
-    ram::ShiftAdjArgs a;
-    if ((st = make_rows(ctx, layout, edges, rp, a.rows)) != RAM_OK) return st;
-    a.q_fwd = q_fwd;
-    a.qbar_out = qbar_out;
-    a.qbar_in = qbar_in;
-    a.v0 = v0;
-    a.dt = dt;
-    a.v0bar = v0bar_accum;
-    a.v0part = (double *)((char *)ctx->scratch + v0_off);
-    hipError_t e = ram::launch_shift_limited_adjoint(a, dtype == RAM_F64, (int)recon,
-                                                     ctx->stream);
-    if (e != hipSuccess) return hip_fail(e, "limited shift adjoint launch");
-    return RAM_OK;
+    if (layout->edges_shared && use_fast_adjoint(ctx, layout, dtype, {q_fwd, qbar_out, qbar_in}))
+        return limited_adjoint_fast(ctx, layout, recon, q_fwd, nullptr, nullptr, qbar_out,
+                                    qbar_in, edges, v0, dt, nullptr, v0bar_accum);
+    return limited_adjoint_general(ctx, layout, dtype, recon, q_fwd, qbar_out, qbar_in, nullptr,
+                                   edges, v0, dt, v0bar_accum);
+}
+
+ram_status ram_step_limited_adjoint(ram_ctx *ctx, const ram_layout *layout,
+                                    ram_dtype dtype, ram_recon recon, const void *q_fwd,
+                                    const void *q_half, const void *dv,
+                                    const void *qbar_out, void *qbar_in,
+                                    const double *edges, const double *v0, double dt,
+                                    void *dvbar_accum, double *v0bar_accum)
+{
+    ram_status st;
+    g_last_error.clear();
+    if ((st = check_layout(layout, edges)) != RAM_OK) return st;
+    if ((st = check_dtype(dtype)) != RAM_OK) return st;
+    if ((st = check_recon(layout, recon)) != RAM_OK) return st;
+    if ((st = check_dt(dt)) != RAM_OK) return st;
+    if (!q_fwd || !qbar_out || !qbar_in || !v0)
+        return fail(RAM_E_INVALID_ARG, "null q_fwd, qbar_out, qbar_in or v0");
+    if (dv && !q_half) return fail(RAM_E_INVALID_ARG, "a step with dv needs q_half");
+    if (dvbar_accum && !dv) return fail(RAM_E_INVALID_ARG, "dvbar needs dv");
+    if (qbar_in == qbar_out || qbar_in == q_fwd || qbar_in == q_half || qbar_in == dv)
+        return fail(RAM_E_INVALID_ARG, "qbar_in must not alias an input");
+    if ((st = enter(ctx)) != RAM_OK) return st;
+    if (layout->edges_shared &&
+        use_fast_adjoint(ctx, layout, dtype, {q_fwd, q_half, dv, qbar_out, qbar_in, dvbar_accum}))
+        return limited_adjoint_fast(ctx, layout, recon, q_fwd, q_half, dv, qbar_out, qbar_in,
+                                    edges, v0, dt, dvbar_accum, v0bar_accum);
+    if (!dv)
+        return limited_adjoint_general(ctx, layout, dtype, recon, q_fwd, qbar_out, qbar_in,
+                                       nullptr, edges, v0, dt, v0bar_accum);
+    // the residual's transpose into qbar_in, then the limited shift's into
+    // scratch, copied back over qbar_in
+    if ((st = ram_residual_adjoint(ctx, layout, dtype, q_half, dv, qbar_out, qbar_in, edges, dt,
+                                   dvbar_accum)) != RAM_OK)
+        return st;
+    return limited_adjoint_general(ctx, layout, dtype, recon, q_fwd, qbar_in, nullptr, qbar_in,
+                                   edges, v0, dt, v0bar_accum);
 }
 
 // q_out == nullptr checks an in-place caller (q_in is its state)

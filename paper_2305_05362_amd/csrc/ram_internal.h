@@ -409,6 +409,10 @@ hipError_t launch_step_adjoint_shared(const StepAdjArgs &a, bool f64, int order,
 // uniform-run tiles, the other tiles, the sums of the window cells that
 // neighbouring tiles share (a.edge), the v0bar sums.
 hipError_t launch_step_adjoint_fast(const StepAdjArgs &a, int order, hipStream_t stream);
+// The limited (PLM / PPM) step backwards on the same tiles (plan of order
+// 2 lo + 1, a.q_fwd the state the shift read; a.dv null: the shift alone).
+hipError_t launch_step_limited_adjoint_fast(const StepAdjArgs &a, int recon,
+                                            hipStream_t stream);
 hipError_t launch_copy(const void *src, void *dst, int64_t bytes,
                        hipStream_t stream);
 // Bulk shift with a limited reconstruction (recon: Recon) on any layout; a.dv
