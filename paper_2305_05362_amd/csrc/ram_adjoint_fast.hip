@@ -966,7 +966,183 @@ __device__ __forceinline__ void lim_node(const MeshTab &tb, int n, int c, double
     }
 }
 
-constexpr size_t kLimStage = 4 * (kFastWin + 16);   // a tile's window averages, LDS bytes
+// A window of at most kLimTab cells is tabulated in LDS (per cell its limited
+// slope, per interface its value and derivatives); wider windows evaluate
+// each node's row from global memory, the accumulator in chunks.
+constexpr int kLimTab = 320;
+constexpr size_t kLimTabI = 8 * (kLimTab + 8);      // bytes: one FP64 value a cell
+constexpr size_t kLimTabD = 16 * (kLimTab + 8);     //        four FP32 values a cell
+constexpr size_t kLimU0 = 2 * kLimTabI + kLimTabD;  // table and accumulator
+constexpr size_t kLimU = kLimU0 > kGenU ? kLimU0 : kGenU;
+constexpr size_t kLimStage = 4 * (kLimTab + 16);    // the window's averages
+
+// A window that fits the LDS: per window cell j (one a lane) the limited
+// slope (PPM: FP64 value, FP32 derivatives with respect to the averages of
+// cells j-1 .. j+1; PLM: the van Leer slope in FP64, its derivatives times
+// the gap inverses in FP32) from the FP64 mesh weights, loaded once a cell;
+// then (PPM) per interface j+1/2 its value in FP64 and its derivatives with
+// respect to cells j-1 .. j+2 in FP32; then per node only LDS reads: the
+// constraint branch in FP64 from the average and the two interface values,
+// the row through the branch, its terms and the destination's whole cells
+// into the FP64 accumulator.  Every branch decision takes FP64 values from
+// FP64 weights; the FP32 derivatives only scale terms.
+template <int R, int NS>
+__device__ __forceinline__ void lim_tab_rows(const StepAdjArgs &a, const MeshTab &tb, int n,
+                                             int base, int off, int W, int NE, int nd,
+                                             int64_t wl, int t, const int (&kv)[NS],
+                                             const int (&kn)[NS], const double (&thv)[NS],
+                                             const double (&hv)[NS], const float *sqw,
+                                             const double *smb, double *tI, float4 *tD,
+                                             double *cacc, double &vp)
+{
+    constexpr int LO = LimHalo<R>::lo;
+    constexpr int NT = (kLimTab + kLanes - 1) / kLanes;
+    auto cell = [&](int j) { const int c = base + j; return c >= n ? c - n : c; };
+    auto qa = [&](int j) { return (double)sqw[j + off]; };
+    for (int j = t; j < W; j += kLanes) cacc[j] = 0.0;
+    // ---- slopes (cells 1 .. W-2) ----------------------------------------------
+    double e1v[NT], e2v[NT], e3v[NT];
+#pragma unroll
+    for (int s = 0; s < NT; ++s) {
+        const int j = t + s * kLanes;
+        e1v[s] = e2v[s] = e3v[s] = 0.0;
+        if (j < 1 || j > W - 2) continue;
+        const int c = cell(j);
+        const double qm = qa(j - 1), q0 = qa(j), qp = qa(j + 1);
+        if constexpr (R == kReconPLM) {
+            const double gp = tb.hinv[c], gm = tb.hinv[c == 0 ? n - 1 : c - 1];
+            const double av = (qp - q0) * gp, bv = (q0 - qm) * gm;
+            double sig = 0.0, dsa = 0.0, dsb = 0.0;
+            if (av * bv > 0.0) {
+                const double inv = 1.0 / (av + bv);
+                sig = 2.0 * av * bv * inv;
+                dsa = 2.0 * bv * bv * inv * inv;
+                dsb = 2.0 * av * av * inv * inv;
+            }
+            tI[j] = sig;
+            tD[j] = make_float4((float)(dsb * gm), (float)(dsa * gp), 0.0f, 0.0f);
+        } else {
+            const double *pw = tb.ppmd;
+            const double d1 = pw[c], d2 = pw[n + c];
+            e1v[s] = pw[2 * n + c];
+            e2v[s] = pw[3 * n + c];
+            e3v[s] = pw[4 * n + c];
+            const double up = qp - q0, dn = q0 - qm;
+            const double d = d1 * up + d2 * dn;
+            double dl = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
+            if (up * dn > 0.0) {
+                dl = copysign(fmin(fabs(d), 2.0 * fmin(fabs(up), fabs(dn))), d);
+                if (fabs(d) <= 2.0 * fabs(up) && fabs(d) <= 2.0 * fabs(dn)) {
+                    g0 = -d2;
+                    g1 = d2 - d1;
+                    g2 = d1;
+                } else if (fabs(up) <= fabs(dn)) {
+                    g1 = -2.0;                       // twice the upper difference
+                    g2 = 2.0;
+                } else {
+                    g0 = -2.0;                       // twice the lower difference
+                    g1 = 2.0;
+                }
+            }
+            tI[j] = dl;
+            tD[j] = make_float4((float)g0, (float)g1, (float)g2, 0.0f);
+        }
+    }
+    wave_sync();
+    if constexpr (R == kReconPPM) {
+        // ---- interfaces j+1/2 (j = 1 .. W-3), replacing the slopes in place --------
+        double Iv[NT];
+        float4 Dv[NT];
+#pragma unroll
+        for (int s = 0; s < NT; ++s) {
+            const int j = t + s * kLanes;
+            Iv[s] = 0.0;
+            Dv[s] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (j < 1 || j > W - 3) continue;
+            const double dl0 = tI[j], dl1 = tI[j + 1];
+            const float4 g0 = tD[j], g1 = tD[j + 1];
+            const double e1 = e1v[s], e2 = e2v[s], e3 = e3v[s];
+            const double q0 = qa(j), q1 = qa(j + 1);
+            Iv[s] = q0 + e1 * (q1 - q0) + e2 * dl1 + e3 * dl0;
+            Dv[s] = make_float4((float)(e3 * g0.x),
+                                (float)(1.0 - e1 + e3 * g0.y + e2 * g1.x),
+                                (float)(e1 + e3 * g0.z + e2 * g1.y),
+                                (float)(e2 * g1.z));
+        }
+        wave_sync();
+#pragma unroll
+        for (int s = 0; s < NT; ++s) {
+            const int j = t + s * kLanes;
+            if (j < 1 || j > W - 3) continue;
+            tI[j] = Iv[s];
+            tD[j] = Dv[s];
+        }
+        wave_sync();
+    }
+    // ---- nodes ----------------------------------------------------------------------
+#pragma unroll 1
+    for (int u = 0; u < NS; ++u) {
+        const int m = t + u * kLanes;
+        if (m >= NE) continue;
+        const int k = kv[u];
+        const double h = hv[u], th = thv[u];
+        double gw[2 * LO + 1], qval;
+        if constexpr (R == kReconPLM) {
+            const double sig = tI[k];
+            const float4 ab = tD[k];
+            const double ks = 0.5 * h * h * (th * th - th);
+            gw[0] = -ks * (double)ab.x;
+            gw[1] = h * th + ks * ((double)ab.x - (double)ab.y);
+            gw[2] = ks * (double)ab.y;
+            qval = qa(k) + sig * h * (th - 0.5);
+        } else {
+            const double av = qa(k);
+            const double Lr = tI[k - 1], Rr = tI[k];
+            const float4 dL = tD[k - 1], dR = tD[k];
+            double L = Lr, Rv = Rr;
+            int branch = 0;                          // 1 flat, 2 L pulled in, 3 R pulled in
+            if ((Rv - av) * (av - L) <= 0.0) {
+                L = av;
+                Rv = av;
+                branch = 1;
+            } else {
+                const double dq = Rv - L, qd = av - 0.5 * (L + Rv);
+                if (dq * qd > dq * dq / 6.0) { L = 3.0 * av - 2.0 * Rv; branch = 2; }
+                else if (-dq * dq / 6.0 > dq * qd) { Rv = 3.0 * av - 2.0 * L; branch = 3; }
+            }
+            const double q6 = 6.0 * av - 3.0 * (L + Rv);
+            qval = L + th * (Rv - L) + q6 * th * (1.0 - th);
+            const double th2 = th * th, th3 = th2 * th;
+            const double ga = h * (3.0 * th2 - 2.0 * th3);
+            const double gl = h * (th - 2.0 * th2 + th3);
+            const double gr = h * (th3 - th2);
+            double ba = ga, bl = gl, br = gr;
+            if (branch == 1) { ba = ga + gl + gr; bl = 0.0; br = 0.0; }
+            else if (branch == 2) { ba = ga + 3.0 * gl; bl = 0.0; br = gr - 2.0 * gl; }
+            else if (branch == 3) { ba = ga + 3.0 * gr; bl = gl - 2.0 * gr; br = 0.0; }
+            // cells k-2 .. k+2: the left interface's derivatives cover k-2 .. k+1,
+            // the right one's k-1 .. k+2
+            gw[0] = bl * (double)dL.x;
+            gw[1] = bl * (double)dL.y + br * (double)dR.x;
+            gw[2] = ba + bl * (double)dL.z + br * (double)dR.y;
+            gw[3] = bl * (double)dL.w + br * (double)dR.z;
+            gw[4] = br * (double)dR.w;
+        }
+        const double vb = smb[m] - smb[m + 1];
+        vp -= vb * qval;
+#pragma unroll
+        for (int j = 0; j <= 2 * LO; ++j) atomicAdd(&cacc[k - LO + j], vb * gw[j]);
+        if (m < nd) {
+            // destination m's whole cells: window cells k .. kn - 1
+            const double mb = smb[m + 1];
+            for (int j = k; j < kn[u]; ++j) {
+                const double dxj = j == k ? h : tb.dx[wrapi(wl + j, n)];
+                atomicAdd(&cacc[j], mb * dxj);
+            }
+        }
+    }
+    wave_sync();
+}
 
 // One tile of the limited step backwards (any kind: the uniform runs save
 // only the search, every node's Jacobian row is evaluated).
@@ -977,8 +1153,8 @@ __device__ __forceinline__ void lim_tile(const StepAdjArgs &a, const FastTile &f
     constexpr int LO = LimHalo<R>::lo;
     constexpr int P = 2 * LO + 1;
     constexpr int NS = (kFastNodes + kLanes - 1) / kLanes;
-    constexpr int NG = (kFastWin + 3 + 4 * kLanes - 1) / (4 * kLanes);   // window groups a lane
-    constexpr int kCh = (int)(kGenU / 8) - 8;        // window cells a chunk of the accumulator
+    constexpr int NG = (kLimTab + 3 + 4 * kLanes - 1) / (4 * kLanes);    // window groups a lane
+    constexpr int kCh = (int)(kLimU / 8) - 8;        // window cells a chunk of the accumulator
     const Rows &Rw = a.rows;
     const MeshTab &tb = Rw.tab;
     const int n = (int)Rw.n_cols;
@@ -992,7 +1168,8 @@ __device__ __forceinline__ void lim_tile(const StepAdjArgs &a, const FastTile &f
     const double x0 = x[0], xN = x[n], len = xN - x0;
     const RowShift rs = row_shift(a.v0[p.row] * a.dt, len, tb.scal[1]);
     const bool uniform = ft.kind == kFastUniform;
-    const bool windowed =
+    // the plan locates the nodes; the window fits the table
+    const bool planned =
         uniform || (ft.kind == kFastWindow && ft.base + ft.w + 3 < 2 * n && ft.w <= kFastWin);
     // the window: this tile's first node's stencil up to the next tile's
     // (the row's first tile one period on, for the last tile of a row)
@@ -1002,6 +1179,7 @@ __device__ __forceinline__ void lim_tile(const StepAdjArgs &a, const FastTile &f
         (i0 + nd >= n ? rec_wlo(a.fast.rec[tile - (tpr - 1)]) + n : rec_wlo(a.fast.rec[tile + 1])) +
         P;
     const int W = (int)(wend - wl);
+    const bool windowed = planned && W <= kLimTab;
     const int base = ft.base, a0 = base & ~3, off = base - a0;
     const int gl = (W + off - 1) >> 2;
 
@@ -1049,7 +1227,7 @@ __device__ __forceinline__ void lim_tile(const StepAdjArgs &a, const FastTile &f
 
     // ---- 2. every node's window index, cell and FP64 position in the cell ---------
     const int16_t *jcp =
-        windowed && !uniform ? a.fast.jc + (int64_t)ft.pad[1] * kFastNodes : nullptr;
+        planned && !uniform ? a.fast.jc + (int64_t)ft.pad[1] * kFastNodes : nullptr;
     int kv[NS], cv[NS];
     double thv[NS], hv[NS];
 #pragma unroll
@@ -1059,7 +1237,7 @@ __device__ __forceinline__ void lim_tile(const StepAdjArgs &a, const FastTile &f
         const int kx = e >= n ? 1 : 0;
         const NodePos np = node_pos(x[e - kx * n], rs, x0, xN, tb.scal[0], tb.scal[2], tb.nb);
         int c, k;
-        if (windowed) {
+        if (planned) {
             k = uniform ? LO + m : (int)jcp[m];
             c = base + k;
             c = c >= n ? c - n : c;
@@ -1075,7 +1253,7 @@ __device__ __forceinline__ void lim_tile(const StepAdjArgs &a, const FastTile &f
         d = d > 0.5 * len ? d - len : (d < -0.5 * len ? d + len : d);
         kv[u] = k;
         cv[u] = c;
-        thv[u] = d / h;
+        thv[u] = d * tb.dxinv[c];
         hv[u] = h;
     }
     // the next node's window index (node m + 1: the next lane, lane 63 the next slot's lane 0)
@@ -1089,12 +1267,26 @@ __device__ __forceinline__ void lim_tile(const StepAdjArgs &a, const FastTile &f
         }
     }
 
+    double vp = 0.0;
+    float *edge = a.edge + (int64_t)tile * (2 * P);
+    if (windowed) {
+        lim_tab_rows<R>(a, tb, n, base, off, W, NE, nd, wl, t, kv, kn, thv, hv, sqw, smb,
+                        (double *)su, (float4 *)(su + kLimTabI),
+                        (double *)(su + kLimTabI + kLimTabD), vp);
+        const double *cacc = (const double *)(su + kLimTabI + kLimTabD);
+        for (int j = t; j < W; j += kLanes)
+            put_cell<P>(qbi, edge, wrapi(wl + j, n), j, W, (float)cacc[j]);
+        if constexpr (V0) {
+            vp = wave_sum(vp);
+            if (t == 0) a.v0part[tile] = a.dt * vp;
+        }
+        return;
+    }
+
     // ---- 3. Jacobian rows through Vbar, and the whole cells, chunk by chunk -------
     // (one node slot at a time: each row is a long FP64 chain; v0bar as
     // -sum_e Vbar_e q~_e, one term a node)
     double *cacc = (double *)su;
-    double vp = 0.0;
-    float *edge = a.edge + (int64_t)tile * (2 * P);
     for (int c0 = 0; c0 < W; c0 += kCh) {
         const int cw = min(kCh, W - c0);
         for (int j = t; j < cw; j += kLanes) cacc[j] = 0.0;
@@ -1146,18 +1338,18 @@ __device__ __forceinline__ void lim_tile(const StepAdjArgs &a, const FastTile &f
     }
 }
 
-// Every tile, one a wave, in tile order.
+// Every tile in tile order, one a workgroup of one wave (the LDS a tile
+// needs, not four tiles' worth, sets how many share a CU).
 template <int R, bool RES, bool V0>
-__global__ __launch_bounds__(kBlock) void k_ladj(StepAdjArgs a)
+__global__ __launch_bounds__(kLanes) void k_ladj(StepAdjArgs a)
 {
-    __shared__ __attribute__((aligned(16))) unsigned char su[kWaves][kGenU];
-    __shared__ __attribute__((aligned(16))) float sqw[kWaves][kLimStage / 4];
-    __shared__ __attribute__((aligned(16))) double smb[kWaves][kFT + 8];
-    const int wid = wave_id();
-    const int i = (int)blockIdx.x * kWaves + wid;
+    __shared__ __attribute__((aligned(16))) unsigned char su[kLimU];
+    __shared__ __attribute__((aligned(16))) float sqw[kLimStage / 4];
+    __shared__ __attribute__((aligned(16))) double smb[kFT + 8];
+    const int i = (int)blockIdx.x;
     if (i >= (int)a.rows.n_tiles) return;
     const FastTile r = load_rec(a.fast.rec, i);
-    lim_tile<R, RES, V0>(a, r, su[wid], sqw[wid], smb[wid], (int)threadIdx.x % kLanes);
+    lim_tile<R, RES, V0>(a, r, su, sqw, smb, (int)threadIdx.x);
 }
 
 template <int R, bool RES, bool V0>
@@ -1165,8 +1357,7 @@ hipError_t ladj_kernels(const StepAdjArgs &a, hipStream_t st)
 {
     constexpr int P = 2 * LimHalo<R>::lo + 1;
     const int64_t nt = a.rows.n_tiles;
-    hipLaunchKernelGGL((k_ladj<R, RES, V0>), dim3((unsigned)((nt + kWaves - 1) / kWaves)),
-                       dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL((k_ladj<R, RES, V0>), dim3((unsigned)nt), dim3(kLanes), 0, st, a);
     hipLaunchKernelGGL((k_adjf_edges<P>), dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !V0) return e;
