@@ -86,8 +86,10 @@ TRAFFIC_FILE_ADJ_UNI = os.path.join(ROOT, "profiles", "k_adjf_uni_f32_polar2048x
 TRAFFIC_FILE_ADJ_GEN = os.path.join(ROOT, "profiles", "k_adjf_gen_f32_polar2048x16384_traffic.md")
 ADJ_UNI_KERNEL = "k_adjf_uni<5, true, true>"
 ADJ_GEN_KERNEL = "k_adjf_gen<5, true, true>"
-TRAFFIC_FILE_LADJ = os.path.join(ROOT, "profiles", "k_shift_lim_adj_f32_ppm_polar2048x16384_traffic.md")
-LADJ_KERNEL = "k_shift_lim_adj<float, 2>"
+TRAFFIC_FILE_LADJ = os.path.join(ROOT, "profiles", "k_ladj_shift_f32_ppm_polar2048x16384_traffic.md")
+LADJ_KERNEL = "k_ladj<2, false, false>"
+TRAFFIC_FILE_LSADJ = os.path.join(ROOT, "profiles", "k_ladj_step_f32_ppm_polar2048x16384_traffic.md")
+LSADJ_KERNEL = "k_ladj<2, true, true>"
 
 
 def _finite(v):
@@ -236,10 +238,13 @@ def main():
         for _ in range(args.steps):
             ctx.ram_step_adjoint(rows, q32, half, dv32, qb_in, qb_out, v0, wl.dt, order, dvb,
                                  v0b)
-        # the limited (PPM) shift's adjoint
+        # the limited (PPM) shift's adjoint, alone and with the residual's
         for _ in range(args.steps):
             ctx.ram_shift_limited_adjoint(rows, q32, qb_in, qb_out, v0, wl.dt,
                                           R.RAM_RECON_PPM)
+        for _ in range(args.steps):
+            ctx.ram_step_limited_adjoint(rows, q32, half, dv32, qb_in, qb_out, v0, wl.dt,
+                                         R.RAM_RECON_PPM, dvb, v0b)
         # the per-row streaming shift: the cfg3 ragged batch, two-sum prefix
         wl3 = W.cfg3()
         rows3 = R.Rows.from_workload(wl3, dev)
@@ -700,19 +705,33 @@ def main():
     b.record()
     torch.cuda.synchronize()
     del out
-    hh, oo = torch.empty_like(q32), torch.empty_like(q32)
+    hh, oo = torch.ones_like(q32), torch.empty_like(q32)
     t_ladj = time_kernel(lambda: ctx.ram_shift_limited_adjoint(
         rows, q32, hh, oo, v0, wl.dt, R.RAM_RECON_PPM), reps)
-    del hh, oo
+    # one limited step backwards with every gradient (the residual's
+    # transpose fused)
+    dvb_l, v0b_l = torch.zeros_like(dv32), torch.zeros_like(v0)
+    g1 = torch.ones_like(q32)
+    t_lsadj = time_kernel(lambda: ctx.ram_step_limited_adjoint(
+        rows, q32, q32, dv32, g1, oo, v0, wl.dt, R.RAM_RECON_PPM, dvb_l, v0b_l), reps)
+    del hh, oo, dvb_l, v0b_l, g1
     tr_ladj = load_traffic(TRAFFIC_FILE_LADJ, LADJ_KERNEL)
+    tr_lsadj = load_traffic(TRAFFIC_FILE_LSADJ, LSADJ_KERNEL)
     limited["ppm_f32"]["fwd_adjoint"] = {
         "value": round(n_cells * kla / (a.elapsed_time(b) / 1e3) / 1e9, 3),
         "steps": kla, "checkpoint": args.checkpoint,
-        "shift_adjoint_kernel_us": round(t_ladj * 1e6, 2),
+        "shift_adjoint_kernel": LADJ_KERNEL,
+        "shift_adjoint_call_us": round(t_ladj * 1e6, 2),
         "shift_adjoint_algorithmic_bytes_per_cell": 12,
         "shift_adjoint_hbm_frac_of_call": round(12.0 * n_cells / t_ladj / 1e9 / HBM_PEAK_GBS, 4),
         "shift_adjoint_traffic": None if tr_ladj is None
-        else round(tr_ladj["traffic_bytes_per_launch"])}
+        else round(tr_ladj["traffic_bytes_per_launch"]),
+        "step_adjoint_kernel": LSADJ_KERNEL + " (residual transpose fused, every gradient)",
+        "step_adjoint_call_us": round(t_lsadj * 1e6, 2),
+        "step_adjoint_algorithmic_bytes_per_cell": 28,
+        "step_adjoint_hbm_frac_of_call": round(28.0 * n_cells / t_lsadj / 1e9 / HBM_PEAK_GBS, 4),
+        "step_adjoint_traffic": None if tr_lsadj is None
+        else round(tr_lsadj["traffic_bytes_per_launch"])}
 
     # --- forward + adjoint (checkpointed rollout) ---------------------------
     ka = args.adj_steps

@@ -45,6 +45,7 @@ KERNEL_SOURCES = {"k_step_sh": STEP_KERNEL_SOURCES,
                   "k_step_rag": FAST_SOURCES,
                   "k_adjf_uni": ADJ_FAST_SOURCES,
                   "k_adjf_gen": ADJ_FAST_SOURCES,
+                  "k_ladj": ADJ_FAST_SOURCES,
                   "k_radial": ["ram_radial.hip", "ram_device.h", "ram_internal.h"],
                   "k_average4": ["ram_average4.hip", "ram_device.h", "ram_internal.h"],
                   "k_adj_sh": ["ram_adjoint_shared.hip", "ram_adjoint_dev.h", "ram_device.h",

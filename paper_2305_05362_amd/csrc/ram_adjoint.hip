@@ -8,12 +8,12 @@
 // tile the sum telescopes to one Mbar' value plus the few stencils that
 // straddle m, so each source cell of the tile's window is a short gather.
 // Window cells shared with the neighbouring tiles (the P cells of the stencil
-// of each tile-boundary node) are accumulated with atomics after a zeroing
-// pass; every other cell is written once.  A shared cell takes exactly two
-// terms (the tiles on either side of the boundary node) onto the zero, and
-// the sum of two does not depend on their order, so the result is the same
-// in every run; v0bar takes one term per tile, summed per row in tile order
-// by a second kernel.
+// of each tile-boundary node) go to a per-tile side buffer, and a second
+// kernel sums each of them over the tiles whose windows hold it, in a fixed
+// order (usually two; more where a row's last tile is shorter than P cells
+// and its window overlaps itself); every other cell is written once, so the
+// result is the same in every run.  v0bar takes one term per tile, summed per
+// row in a fixed order by another kernel.
 //
 // The derivative with respect to v0 enters through x~ = x - v0 dt:
 //     dM'_i/ds = -(q~(x~_{i+1}) - q~(x~_i)),
@@ -82,23 +82,15 @@ __device__ inline int64_t locate(const double *x, int n, double s, int e,
     return (int64_t)c + k * (int64_t)n;
 }
 
-// Zero the P window cells that start at each tile's first shifted node: the
-// only cells that more than one tile accumulates into.
+// Window cell j (of W; row cell mm) of a tile: a cell only this tile's window
+// holds goes to the state, the window's first P and last P cells to the
+// tile's side buffer (head, tail; overlap-free when W < 2P).
 template <typename TQ, int P>
-__global__ __launch_bounds__(kBlock) void k_shift_adj_zero(ShiftAdjArgs a)
+__device__ inline void put_window_cell(TQ *qbi, TQ *edge, int mm, int j, int W, TQ v)
 {
-    constexpr int LO = (P - 1) / 2;
-    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (t >= a.rows.n_tiles) return;
-    Tile ti;
-    if (!get_tile(a.rows, t, ti)) return;
-    const int n = ti.n;
-    if (n < P + 1) return;
-    const double s = a.v0[ti.row] * a.dt;
-    double xh;
-    const int64_t g0 = locate(ti.x, n, s, ti.i0, xh, a.rows);
-    TQ *qbi = (TQ *)a.qbar_in + ti.qoff;
-    for (int b = 0; b < P; ++b) qbi[wrapi(g0 - LO + b, n)] = (TQ)0;
+    if (j >= P && j < W - P) qbi[mm] = v;
+    else if (j < P) edge[j] = v;
+    else edge[P + j - max(P, W - P)] = v;
 }
 
 template <typename TQ, int P>
@@ -184,6 +176,8 @@ __global__ __launch_bounds__(kBlock) void k_shift_adj(ShiftAdjArgs a)
     const int64_t wlo = sg[0] - LO;
     const int W = (int)(sg[nd] - sg[0] + P);
     const int base = wrapi(wlo, n);
+    TQ *edge = (TQ *)a.edge + (int64_t)blockIdx.x * (2 * P);
+    if (threadIdx.x == 0) a.wstart[blockIdx.x] = wlo;
     for (int j = threadIdx.x; j < W; j += kBlock) {
         const int64_t target = wlo + j + LO;
         // first tile node whose stencil lies wholly above cell j
@@ -201,10 +195,7 @@ __global__ __launch_bounds__(kBlock) void k_shift_adj(ShiftAdjArgs a)
         }
         const int mm = (base + j) % n;
         const double val = S * (x[mm + 1] - x[mm]);
-        if (j >= P && j < W - P)
-            qbi[mm] = (TQ)val;
-        else
-            atomicAdd(&qbi[mm], (TQ)val);
+        put_window_cell<TQ, P>(qbi, edge, mm, j, W, (TQ)val);
     }
 }
 
@@ -405,6 +396,8 @@ __global__ __launch_bounds__(kBlock) void k_shift_lim_adj(ShiftAdjArgs a)
     const int64_t wlo = sg[0] - LO;
     const int W = (int)(sg[nd] - sg[0] + P);
     const int base = wrapi(wlo, n);
+    TQ *edge = (TQ *)a.edge + (int64_t)blockIdx.x * (2 * P);
+    if (threadIdx.x == 0) a.wstart[blockIdx.x] = wlo;
     for (int j = threadIdx.x; j < W; j += kBlock) {
         const int64_t m = wlo + j;
         const int mm = (base + j) % n;
@@ -428,10 +421,7 @@ __global__ __launch_bounds__(kBlock) void k_shift_lim_adj(ShiftAdjArgs a)
         }
         for (int t = lo; t < ne && sg[t] <= m + LO; ++t)
             val += svb[t] * sgw[t][(int)(m - (sg[t] - LO))];
-        if (j >= P && j < W - P)
-            qbi[mm] = (TQ)val;
-        else
-            atomicAdd(&qbi[mm], (TQ)val);
+        put_window_cell<TQ, P>(qbi, edge, mm, j, W, (TQ)val);
     }
 }
 
@@ -529,13 +519,11 @@ __global__ __launch_bounds__(kBlock) void k_residual_adj(ResidualAdjArgs a)
 template <typename TQ, int P>
 hipError_t shift_adj_order(const ShiftAdjArgs &a, hipStream_t st)
 {
-    const unsigned zgrid = (unsigned)((a.rows.n_tiles + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL((k_shift_adj_zero<TQ, P>), dim3(zgrid), dim3(kBlock), 0, st, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_shift_adj<TQ, P>), dim3((unsigned)a.rows.n_tiles),
                        dim3(kBlock), 0, st, a);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_edge_sum(a.rows, a.wstart, a.edge, a.qbar_in, sizeof(TQ) == 8, P, st);
 }
 
 template <typename TQ>
@@ -554,26 +542,22 @@ hipError_t launch_shift_limited_adjoint(const ShiftAdjArgs &a, bool f64, int rec
                                         hipStream_t stream)
 {
     if (a.rows.n_tiles <= 0) return hipSuccess;
-    const dim3 gz((unsigned)((a.rows.n_tiles + kBlock - 1) / kBlock)), b(kBlock);
-    const dim3 g((unsigned)a.rows.n_tiles);
+    const dim3 g((unsigned)a.rows.n_tiles), b(kBlock);
     if (f64) {
-        if (recon == kReconPLM) {
-            hipLaunchKernelGGL((k_shift_adj_zero<double, 3>), gz, b, 0, stream, a);
+        if (recon == kReconPLM)
             hipLaunchKernelGGL((k_shift_lim_adj<double, kReconPLM>), g, b, 0, stream, a);
-        } else {
-            hipLaunchKernelGGL((k_shift_adj_zero<double, 5>), gz, b, 0, stream, a);
+        else
             hipLaunchKernelGGL((k_shift_lim_adj<double, kReconPPM>), g, b, 0, stream, a);
-        }
     } else {
-        if (recon == kReconPLM) {
-            hipLaunchKernelGGL((k_shift_adj_zero<float, 3>), gz, b, 0, stream, a);
+        if (recon == kReconPLM)
             hipLaunchKernelGGL((k_shift_lim_adj<float, kReconPLM>), g, b, 0, stream, a);
-        } else {
-            hipLaunchKernelGGL((k_shift_adj_zero<float, 5>), gz, b, 0, stream, a);
+        else
             hipLaunchKernelGGL((k_shift_lim_adj<float, kReconPPM>), g, b, 0, stream, a);
-        }
     }
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = launch_edge_sum(a.rows, a.wstart, a.edge, a.qbar_in, f64, recon == kReconPLM ? 3 : 5,
+                        stream);
     if (e != hipSuccess || !(a.v0bar && a.q_fwd)) return e;
     return launch_v0_reduce(a.rows, a.v0part, a.v0bar, stream);
 }
@@ -586,6 +570,91 @@ hipError_t launch_shift_adjoint(const ShiftAdjArgs &a, bool f64, int order,
                        : shift_adj_dispatch<float>(a, order, stream);
     if (e != hipSuccess || !(a.v0bar && a.q_fwd)) return e;
     return launch_v0_reduce(a.rows, a.v0part, a.v0bar, stream);
+}
+
+namespace {
+
+// Boundary T of a row (one thread): the cells from its window start up to p
+// cells on or the next tile's start, each the sum, tile T first and then
+// down, of the terms the tiles whose windows hold it stored (tile k's window
+// runs from wstart[k] to the next tile's start plus p; across the row's ends
+// the row's tiles one period away).
+template <typename TQ, int P>
+__global__ __launch_bounds__(256) void k_edge_sum(Rows R, const int64_t *wstart, const TQ *edge,
+                                                  TQ *qbar)
+{
+    const int64_t tile = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    Tile ti;
+    if (tile >= R.n_tiles || !get_tile(R, tile, ti)) return;
+    const int n = ti.n;
+    if (n < P + 1) return;                  // the adjoint kernels skip such rows
+    int64_t t0;
+    int tpr;
+    if (R.n_cols > 0) {
+        tpr = (int)((n + R.tile - 1) / R.tile);
+        t0 = ti.row * tpr;
+    } else {
+        t0 = R.tile_ptr[ti.row];
+        tpr = (int)(R.tile_ptr[ti.row + 1] - t0);
+    }
+    const int k0 = (int)(tile - t0);
+    auto start = [&](int k, int64_t &id) {
+        const int q = k >= 0 ? k / tpr : -((-k + tpr - 1) / tpr);
+        id = t0 + (k - q * tpr);
+        return wstart[id] + (int64_t)q * n;
+    };
+    int64_t idp, id0, idn;
+    const int64_t ap = start(k0 - 1, idp), a0 = start(k0, id0), a1 = start(k0 + 1, idn);
+    TQ *q = qbar + ti.qoff;
+    if (a1 - a0 >= P && a0 - ap >= P) {
+        // two terms a cell: this tile's head and the previous tile's tail
+        const TQ *e0 = edge + id0 * (2 * P), *ep = edge + idp * (2 * P);
+        for (int k = 0; k < P; ++k) q[wrapi(a0 + k, n)] = ((TQ)0 + e0[k]) + ep[P + k];
+        return;
+    }
+    const int64_t mend = min(a0 + P, a1);
+    for (int64_t m = a0; m < mend; ++m) {
+        TQ sum = (TQ)0;
+        int64_t at = a0, an = a1, id = id0;
+        for (int k = k0; k > k0 - tpr - 1; --k) {
+            if (k != k0) {
+                an = at;
+                at = start(k, id);
+            }
+            const int64_t W = an - at + P;
+            if (at + W <= m) break;
+            const int pos = (int)(m - at);
+            const TQ *e = edge + id * (2 * P);
+            sum += pos < P ? e[pos] : e[P + pos - (int)max((int64_t)P, W - P)];
+        }
+        q[wrapi(m, n)] = sum;
+    }
+}
+
+template <typename TQ>
+hipError_t edge_sum_t(const Rows &R, const int64_t *wstart, const void *edge, void *qbar, int p,
+                      hipStream_t st)
+{
+    const dim3 g((unsigned)((R.n_tiles + 255) / 256)), b(256);
+    const TQ *e = (const TQ *)edge;
+    TQ *q = (TQ *)qbar;
+    switch (p) {
+    case 1: hipLaunchKernelGGL((k_edge_sum<TQ, 1>), g, b, 0, st, R, wstart, e, q); break;
+    case 3: hipLaunchKernelGGL((k_edge_sum<TQ, 3>), g, b, 0, st, R, wstart, e, q); break;
+    default: hipLaunchKernelGGL((k_edge_sum<TQ, 5>), g, b, 0, st, R, wstart, e, q); break;
+    }
+    return hipGetLastError();
+}
+
+} // namespace
+
+hipError_t launch_edge_sum(const Rows &R, const int64_t *wstart, const void *edge, void *qbar,
+                           bool f64, int p, hipStream_t stream)
+{
+    if (R.n_tiles <= 0) return hipSuccess;
+    if (!wstart || !edge) return hipErrorInvalidValue;
+    return f64 ? edge_sum_t<double>(R, wstart, edge, qbar, p, stream)
+               : edge_sum_t<float>(R, wstart, edge, qbar, p, stream);
 }
 
 namespace {

@@ -304,7 +304,7 @@ __device__ __forceinline__ void adj_uniform_tile(const StepAdjArgs &a, const Fas
 
     // ---- 4. Qbar^n_j = sum_d cc_d Qbar^{n+1/2}_{j-d}, one window cell a lane
     constexpr int NJ = (kFT + P + kLanes - 1) / kLanes;
-    float *edge = a.edge + (int64_t)r.pad[0] * (2 * P);
+    float *edge = (float *)a.edge + (int64_t)r.pad[0] * (2 * P);
 #pragma unroll
     for (int u = 0; u < NJ; ++u) {
         const int j = t + u * kLanes;
@@ -643,7 +643,7 @@ __device__ __forceinline__ void adj_window_tile(const StepAdjArgs &a, const Fast
     wave_sync();
 
     // ---- 7. Qbar^n = Mbar dx, one window cell a lane --------------------------------
-    float *edge = a.edge + (int64_t)ft.pad[0] * (2 * P);
+    float *edge = (float *)a.edge + (int64_t)ft.pad[0] * (2 * P);
     for (int j = t; j < W; j += kLanes) {
         int c = base + j;
         c = c >= n ? c - n : c;
@@ -745,7 +745,7 @@ __device__ __forceinline__ void adj_direct_tile(const StepAdjArgs &a, const Fast
     const int64_t wl = wlo_of(tile);
     const int64_t wend = (last ? wlo_of(tile - (tpr - 1)) + n : wlo_of(tile + 1)) + P;
     const int Wd = (int)(wend - wl);
-    float *edge = a.edge + (int64_t)tile * (2 * P);
+    float *edge = (float *)a.edge + (int64_t)tile * (2 * P);
     for (int j = t; j < Wd; j += kLanes) {
         const int64_t target = wl + j + LO;
         int lo = 0, hi = NE;
@@ -810,7 +810,8 @@ __global__ __launch_bounds__(256) void k_adjf_edges(StepAdjArgs a)
     if (a1 - a0 >= P && a0 - ap >= P) {
         // two terms a cell: this tile's head and the previous tile's tail
         // (its window [ap, a0 + p) of at least 2p cells ends its tail there)
-        const float *e0 = a.edge + id0 * (2 * P), *ep = a.edge + idp * (2 * P);
+        const float *e0 = (const float *)a.edge + id0 * (2 * P);
+        const float *ep = (const float *)a.edge + idp * (2 * P);
         float v[P];
 #pragma unroll
         for (int k = 0; k < P; ++k) v[k] = (0.0f + e0[k]) + ep[P + k];
@@ -830,7 +831,7 @@ __global__ __launch_bounds__(256) void k_adjf_edges(StepAdjArgs a)
             const int64_t W = an - at + P;
             if (at + W <= m) break;
             const int pos = (int)(m - at);
-            const float *e = a.edge + id * (2 * P);
+            const float *e = (const float *)a.edge + id * (2 * P);
             sum += pos < P ? e[pos] : e[P + pos - (int)max((int64_t)P, W - P)];
         }
         qbi[wrapi(m, n)] = sum;
@@ -1268,7 +1269,7 @@ __device__ __forceinline__ void lim_tile(const StepAdjArgs &a, const FastTile &f
     }
 
     double vp = 0.0;
-    float *edge = a.edge + (int64_t)tile * (2 * P);
+    float *edge = (float *)a.edge + (int64_t)tile * (2 * P);
     if (windowed) {
         lim_tab_rows<R>(a, tb, n, base, off, W, NE, nd, wl, t, kv, kn, thv, hv, sqw, smb,
                         (double *)su, (float4 *)(su + kLimTabI),

@@ -15,9 +15,9 @@
 //       onto the window's node cumulative (Cbar), and the source masses are
 //       the suffix sums Mbar_m = sum_{j > m} Cbar_j (a DPP block scan).
 //       Source cells shared with the neighbouring tiles (the p cells of each
-//       boundary node's stencil) are accumulated with atomics after a zeroing
-//       pass (two terms onto the zero: the same sum in either order); every
-//       other cell is written once;
+//       boundary node's stencil) go to a per-tile side buffer, summed per
+//       cell in a fixed order by a second kernel; every other cell is
+//       written once;
 //   (3) v0bar += dt * sum_e -Vbar_e q~(x~_e), with q~ the reconstruction
 //       (derivative of the interpolated cumulative of Q^n) at the shifted
 //       node: one term per tile, summed per row in tile order afterwards.
@@ -70,6 +70,16 @@ __device__ inline void lds_read8(const T *p, T (&o)[8])
 #pragma unroll
         for (int i = 0; i < 8; ++i) o[i] = p[i];
     }
+}
+
+// Window cell j (of W) of a tile: cells only this tile's window holds go to
+// the state, the window's first and last p cells to the tile's side buffer.
+template <typename TQ, int P>
+__device__ inline void put_cell_any(TQ *qbi, TQ *edge, int mm, int j, int W, TQ v)
+{
+    if (j >= P && j < W - P) qbi[mm] = v;
+    else if (j < P) edge[j] = v;
+    else edge[P + j - max(P, W - P)] = v;
 }
 
 template <typename CT>
@@ -139,6 +149,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_sh(StepAdjArgs a)
     const int64_t wlo = a.plan_wlo[blockIdx.x];
     const int W = a.plan_w[blockIdx.x];
     const int t = threadIdx.x;
+    TQ *edge = (TQ *)a.edge + (int64_t)blockIdx.x * (2 * P);
     auto wr = [&](int j) { return inner ? j : wrap1a(j, n); };
     const CT dt = (CT)a.dt;
 
@@ -283,8 +294,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_sh(StepAdjArgs a)
                         if (i >= 0 && i < nd) acc += cs[d] * (double)smb[i];
                     }
                     const double val = acc * dx0;
-                    if (j >= P && j < W - P) qbi[mms[r]] = (TQ)val;
-                    else atomicAdd(&qbi[mms[r]], (TQ)val);
+                    put_cell_any<TQ, P>(qbi, edge, mms[r], j, W, (TQ)val);
                 }
             }
             if (want_v0) {
@@ -451,8 +461,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_sh(StepAdjArgs a)
             int mm = base + j;
             mm = mm >= n ? wrap_small(mm, n) : mm;
             const double val = scb[j] * TabT<double>::dx(tb)[mm];
-            if (j >= P && j < W - P) qbi[mm] = (TQ)val;
-            else atomicAdd(&qbi[mm], (TQ)val);
+            put_cell_any<TQ, P>(qbi, edge, mm, j, W, (TQ)val);
         }
         // reconstruction q~ at the nodes: sum_b w'_b (C(g-lo+b) - C(g)) / dx_c,
         // the differences summed from the masses next to the node
@@ -528,8 +537,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_sh(StepAdjArgs a)
             }
             const int mm = wrapi(wl + j, n);
             const double val = S * TabT<double>::dx(tb)[mm];
-            if (j >= P && j < Wd - P) qbi[mm] = (TQ)val;
-            else atomicAdd(&qbi[mm], (TQ)val);
+            put_cell_any<TQ, P>(qbi, edge, mm, j, Wd, (TQ)val);
         }
         if (want_v0) {
 #pragma unroll
@@ -583,33 +591,15 @@ __global__ __launch_bounds__(kBlock) void k_adj_sh(StepAdjArgs a)
     }
 }
 
-// Zero the p cells at the start of every tile's window: the only cells more
-// than one tile accumulates into (a tile's last p window cells start the next
-// tile's window; the last tile of a row wraps onto the first).
-template <typename TQ, int P>
-__global__ __launch_bounds__(256) void k_adj_zero(StepAdjArgs a)
-{
-    const int64_t tile = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (tile >= a.rows.n_tiles) return;
-    const int n = (int)a.rows.n_cols;
-    const int tpr = (n + a.rows.tile - 1) / a.rows.tile;
-    const int64_t row = tile / tpr;
-    TQ *qbi = (TQ *)a.qbar_in + row * n;
-    const int64_t wlo = a.plan_wlo[tile];
-    for (int b = 0; b < P; ++b) qbi[wrapi(wlo + b, n)] = (TQ)0;
-}
-
 template <typename TQ, int P>
 hipError_t adj_order(const StepAdjArgs &a, hipStream_t st)
 {
-    const unsigned zg = (unsigned)((a.rows.n_tiles + 255) / 256);
-    hipLaunchKernelGGL((k_adj_zero<TQ, P>), dim3(zg), dim3(256), 0, st, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
     const dim3 g((unsigned)a.rows.n_tiles), b(kBlock);
     if (a.dv) hipLaunchKernelGGL((k_adj_sh<TQ, P, true>), g, b, 0, st, a);
     else hipLaunchKernelGGL((k_adj_sh<TQ, P, false>), g, b, 0, st, a);
-    e = hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = launch_edge_sum(a.rows, a.plan_wlo, a.edge, a.qbar_in, sizeof(TQ) == 8, P, st);
     if (e != hipSuccess || !(a.v0bar && a.q_fwd)) return e;
     return launch_v0_reduce(a.rows, a.v0part, a.v0bar, st);
 }

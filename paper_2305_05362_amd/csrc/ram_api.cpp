@@ -565,6 +565,7 @@ ram_status step_adjoint_shared(ram_ctx *ctx, const ram_layout *layout, ram_dtype
     const int64_t nt = tiles_of(layout, rp.tile);
     const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(ram::kPlanW * sizeof(int32_t) * nt);
     const size_t v0_off = cv.take(v0bar ? sizeof(double) * nt : 0);
+    const size_t edge_off = cv.take(ram::adj_edge_bytes(nt, order, elem_size(dtype)));
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
     ram::StepArgs p;
     if ((st = make_rows(ctx, layout, edges, rp, p.rows)) != RAM_OK) return st;
@@ -588,6 +589,7 @@ ram_status step_adjoint_shared(ram_ctx *ctx, const ram_layout *layout, ram_dtype
     a.dt = dt;
     a.plan_wlo = wlo;
     a.plan_w = w;
+    a.edge = (char *)ctx->scratch + edge_off;
     e = ram::launch_step_adjoint_shared(a, dtype == RAM_F64, order, ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "step adjoint launch");
     return RAM_OK;
@@ -1095,6 +1097,10 @@ ram_status limited_adjoint_general(ram_ctx *ctx, const ram_layout *layout, ram_d
         cv.take(v0bar_accum ? sizeof(double) * tiles_of(layout, ram::kAdjTile) : 0);
     const size_t state_bytes = elem_size(dtype) * (size_t)layout_cells(layout);
     const size_t tmp_off = qbar_in ? 0 : cv.take(state_bytes);
+    const int64_t nt = tiles_of(layout, ram::kAdjTile);
+    const int p = recon == RAM_RECON_PLM ? 3 : 5;
+    const size_t edge_off = cv.take(ram::adj_edge_bytes(nt, p, elem_size(dtype)));
+    const size_t ws_off = cv.take(sizeof(int64_t) * nt);
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
     ram::ShiftAdjArgs a;
     if ((st = make_rows(ctx, layout, edges, rp, a.rows)) != RAM_OK) return st;
@@ -1105,6 +1111,8 @@ ram_status limited_adjoint_general(ram_ctx *ctx, const ram_layout *layout, ram_d
     a.dt = dt;
     a.v0bar = v0bar_accum;
     a.v0part = (double *)((char *)ctx->scratch + v0_off);
+    a.edge = (char *)ctx->scratch + edge_off;
+    a.wstart = (int64_t *)((char *)ctx->scratch + ws_off);
     hipError_t e = ram::launch_shift_limited_adjoint(a, dtype == RAM_F64, (int)recon,
                                                      ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "limited shift adjoint launch");
@@ -1535,8 +1543,10 @@ ram_status ram_shift_adjoint(ram_ctx *ctx, const ram_layout *layout,
                                    qbar_in, edges, v0, dt, order, nullptr, v0bar_accum);
     Carve cv;
     RowsPlan rp = plan_rows(cv, layout, ram::kAdjTile, 0);
-    const size_t v0_off =
-        cv.take(v0bar_accum ? sizeof(double) * tiles_of(layout, ram::kAdjTile) : 0);
+    const int64_t nt = tiles_of(layout, ram::kAdjTile);
+    const size_t v0_off = cv.take(v0bar_accum ? sizeof(double) * nt : 0);
+    const size_t edge_off = cv.take(ram::adj_edge_bytes(nt, order, elem_size(dtype)));
+    const size_t ws_off = cv.take(sizeof(int64_t) * nt);
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
     ram::ShiftAdjArgs a;
     if ((st = make_rows(ctx, layout, edges, rp, a.rows)) != RAM_OK) return st;
@@ -1547,6 +1557,8 @@ ram_status ram_shift_adjoint(ram_ctx *ctx, const ram_layout *layout,
     a.dt = dt;
     a.v0bar = v0bar_accum;
     a.v0part = (double *)((char *)ctx->scratch + v0_off);
+    a.edge = (char *)ctx->scratch + edge_off;
+    a.wstart = (int64_t *)((char *)ctx->scratch + ws_off);
     hipError_t e = ram::launch_shift_adjoint(a, dtype == RAM_F64, order, ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "shift adjoint launch");
     return RAM_OK;
@@ -1663,8 +1675,10 @@ ram_status ram_step_adjoint(ram_ctx *ctx, const ram_layout *layout,
     Carve cv;
     const size_t mid_off = dv ? cv.take(state_bytes) : 0;
     RowsPlan rp = plan_rows(cv, layout, ram::kAdjTile, 0);
-    const size_t v0_off =
-        cv.take(v0bar_accum ? sizeof(double) * tiles_of(layout, ram::kAdjTile) : 0);
+    const int64_t nt = tiles_of(layout, ram::kAdjTile);
+    const size_t v0_off = cv.take(v0bar_accum ? sizeof(double) * nt : 0);
+    const size_t edge_off = cv.take(ram::adj_edge_bytes(nt, order, elem_size(dtype)));
+    const size_t ws_off = cv.take(sizeof(int64_t) * nt);
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
     ram::Rows rows;
     if ((st = make_rows(ctx, layout, edges, rp, rows)) != RAM_OK) return st;
@@ -1692,6 +1706,8 @@ ram_status ram_step_adjoint(ram_ctx *ctx, const ram_layout *layout,
     a.dt = dt;
     a.v0bar = v0bar_accum;
     a.v0part = (double *)((char *)ctx->scratch + v0_off);
+    a.edge = (char *)ctx->scratch + edge_off;
+    a.wstart = (int64_t *)((char *)ctx->scratch + ws_off);
     e = ram::launch_shift_adjoint(a, dtype == RAM_F64, order, ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "shift adjoint launch");
     return RAM_OK;

@@ -301,6 +301,9 @@ struct ShiftAdjArgs {
     double dt = 0.0;
     double *v0bar = nullptr;          // per-row accumulator or null
     double *v0part = nullptr;         // [n_tiles] each tile's v0bar term (v0bar set)
+    void *edge = nullptr;             // [n_tiles][2 p] (state's type) each tile's terms for
+                                      // its window's first and last p cells
+    int64_t *wstart = nullptr;        // [n_tiles] each tile's window start (extended index)
 };
 
 // One step backwards on a shared mesh (fused residual adjoint, then shift
@@ -320,8 +323,9 @@ struct StepAdjArgs {
     const int64_t *plan_wlo = nullptr;  // window plan of the shift (no halo)
     const int32_t *plan_w = nullptr;    // [n_tiles] lengths, [n_tiles] starts mod n
     FastPlan fast;                      // streaming adjoint: the shift's tile plan (no halo)
-    float *edge = nullptr;              // streaming adjoint: [n_tiles][2 order] the window's
-                                        // first and last cells' terms of each tile
+    void *edge = nullptr;               // [n_tiles][2 p] each tile's terms for its window's
+                                        // first and last p cells (FP32 on the streaming
+                                        // kernels, the state's type on the general one)
 };
 
 struct ResidualAdjArgs {
@@ -400,6 +404,17 @@ hipError_t launch_residual_adjoint(const ResidualAdjArgs &a, bool f64,
 // that v0bar does not depend on the order the tiles finish in).
 hipError_t launch_v0_reduce(const Rows &R, const double *part, double *v0bar,
                             hipStream_t stream);
+// The window cells neighbouring tiles share (the first p of each tile's
+// window), each the sum in a fixed order of the terms the tiles holding it
+// stored in `edge` (tile k's window starts at wstart[k]; [n_tiles][2 p]
+// values of the state's type, head then tail).
+hipError_t launch_edge_sum(const Rows &R, const int64_t *wstart, const void *edge, void *qbar,
+                           bool f64, int p, hipStream_t stream);
+// Bytes of those buffers for n_tiles tiles.
+inline size_t adj_edge_bytes(int64_t n_tiles, int p, size_t elem)
+{
+    return 2 * (size_t)p * elem * (size_t)n_tiles;
+}
 // Zero the cells several tiles accumulate into, then the fused adjoint.
 hipError_t launch_step_adjoint_shared(const StepAdjArgs &a, bool f64, int order,
                                       hipStream_t stream);

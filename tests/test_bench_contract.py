@@ -51,13 +51,7 @@ def test_traffic_record_matches_kernel_and_sources(tmp_path):
     assert kernel_digest("k_step_sh<float, 5, 3, 2, 0, 4, 1>") != kernel_digest(kernel)
 
 
-@pytest.mark.parametrize("name", ["kernels_polar2048x16384_bench.md",
-                                  "k_step_sh_f32_direct_polar2048x16384_traffic.md",
-                                  "k_step_sh_f32_ppm_polar2048x16384_traffic.md",
-                                  "k_radial_f32_polar2048x16384_traffic.md",
-                                  "k_average4_f32_polar2048x16384_traffic.md",
-                                  "k_adj_sh_f32_polar2048x16384_traffic.md",
-                                  "k_shift_lim_adj_f32_ppm_polar2048x16384_traffic.md"])
+@pytest.mark.parametrize("name", sorted(os.listdir(os.path.join(ROOT, "profiles"))))
 def test_profiles_name_their_command(name):
     text = open(os.path.join(ROOT, "profiles", name)).read()
     assert "rocprofv3" in text and "bench.py" in text
