@@ -90,6 +90,9 @@ TRAFFIC_FILE_LADJ = os.path.join(ROOT, "profiles", "k_ladj_shift_f32_ppm_polar20
 LADJ_KERNEL = "k_ladj<2, false, false>"
 TRAFFIC_FILE_LSADJ = os.path.join(ROOT, "profiles", "k_ladj_step_f32_ppm_polar2048x16384_traffic.md")
 LSADJ_KERNEL = "k_ladj<2, true, true>"
+# the FP64 plain path's kernel (window prefix sums, fused residual)
+TRAFFIC_FILE_F64 = os.path.join(ROOT, "profiles", "k_step64_f64_prefix_polar2048x16384_traffic.md")
+F64_KERNEL = "k_step64<5, 2, 0, true>"
 
 
 def _finite(v):
@@ -245,6 +248,10 @@ def main():
         for _ in range(args.steps):
             ctx.ram_step_limited_adjoint(rows, q32, half, dv32, qb_in, qb_out, v0, wl.dt,
                                          R.RAM_RECON_PPM, dvb, v0b)
+        # FP64 steps (the plain path: window prefix sums)
+        q6 = q64.clone()
+        ctx.ram_step(rows, q6, v0, dv64, wl.dt, order, args.steps, R.RAM_SCAN_F64)
+        del q6
         # the per-row streaming shift: the cfg3 ragged batch, two-sum prefix
         wl3 = W.cfg3()
         rows3 = R.Rows.from_workload(wl3, dev)
@@ -302,6 +309,11 @@ def main():
                 "kernel": kernel}
     fp32_kernel = ("k_step_uni + k_step_gen (the streaming kernels; the mode's prefix in "
                    "the searching tiles)" if items == 0 and not use_density else "k_step_sh")
+    def fp64_kernel_of(sched, density):
+        return ("k_step64 (the streaming plan, tiles of 256 cells a wave, every node's "
+                "weights in FP64)" if sched == 0 and not density else "k_step_sh")
+    fp64_kernel = fp64_kernel_of(items, use_density)
+    tr_f64 = load_traffic(TRAFFIC_FILE_F64, F64_KERNEL) if items == 0 and not use_density else None
     # --- FP64 plain path ----------------------------------------------------
     t64, q_64 = time_steps(q64, dv64, R.RAM_SCAN_F64, args.fp64_steps, args.warmup)
     v64 = n_cells * args.fp64_steps / t64 / 1e9
@@ -1002,12 +1014,16 @@ def main():
         "fp32_fp64scan": mode_rec(v_f64s, t_f64s, k2, 12, fp32_kernel),
         "fp32_twosum_prefix": mode_rec(v_two, t_two, k2s, 12, fp32_kernel),
         "fp32_plain_prefix": mode_rec(v_p32, t_p32, k2, 12, fp32_kernel),
-        "fp64_plain": dict(mode_rec(v64, t64, args.fp64_steps, 24, "k_step_sh"),
-                           cumulative_differences="FP64 window prefix sums"),
-        "fp64_direct": {"value": round(v64d, 3), "steps": args.fp64_steps,
-                        "cumulative_differences": "summed directly in FP64",
-                        "items_per_thread": items64,
-                        "tuned_us_per_step": {str(k): round(v, 2) for k, v in tune64.items()}},
+        "fp64_plain": dict(mode_rec(v64, t64, args.fp64_steps, 24, fp64_kernel),
+                           cumulative_differences="FP64 window prefix sums",
+                           traffic=tr_f64["traffic_bytes_per_launch"] if tr_f64 else None,
+                           traffic_over_algorithmic=(round(tr_f64["traffic_over_algorithmic"], 3)
+                                                     if tr_f64 else None)),
+        "fp64_direct": dict(mode_rec(v64d, t64d, args.fp64_steps, 24,
+                                     fp64_kernel_of(items64, False)),
+                            cumulative_differences="summed directly in FP64",
+                            items_per_thread=items64,
+                            tuned_us_per_step={str(k): round(v, 2) for k, v in tune64.items()}),
         "mixed_speedup_vs_fp64": round(value / v64, 3),
         "mixed_speedup_vs_fp64_direct": round(value / v64d, 3),
         "error": {"one_step_rel_l1_vs_fp64_path": err1,

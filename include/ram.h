@@ -103,8 +103,11 @@ ram_status ram_destroy(ram_ctx *ctx);
  * of the mesh is a fixed stencil on the cell values, whose cumulative
  * differences cancel exactly, so the mode governs the other tiles; rows whose
  * length is not a multiple of four, or arrays not 16-byte aligned, sum those
- * tiles' cumulative differences directly whatever the mode); FP64 takes the
- * general kernel with 4 nodes per thread.  2..5 select the general
+ * tiles' cumulative differences directly whatever the mode); FP64 runs the
+ * streaming FP64 kernel on the same tile plan (every node's Lagrange weights
+ * formed in FP64 from its source cell's stencil data, RAM_SCAN_F64 or
+ * RAM_SUM_DIRECT; a tile whose source window exceeds 768 cells sums from
+ * global memory).  2..5 select the general
  * kernel with that many shifted nodes per thread (RAM_SUM_DIRECT; the prefix
  * modes then take 4): each workgroup of 256
  * threads shifts 256 * items_per_thread nodes, a tile of

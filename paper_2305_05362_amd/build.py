@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB_PATH = os.path.join(HERE, "libram.so")
 ARCH = os.environ.get("RAM_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["ram_kernels.hip", "ram_step_shared.hip", "ram_step_fast.hip", "ram_adjoint.hip",
+SOURCES = ["ram_kernels.hip", "ram_step_shared.hip", "ram_step_fast.hip", "ram_step_fast64.hip", "ram_adjoint.hip",
            "ram_adjoint_shared.hip", "ram_adjoint_fast.hip", "ram_limited.hip", "ram_reduce.hip", "ram_radial.hip",
            "ram_average4.hip", "ram_noalloc.hip", "ram_api.cpp"]
 
@@ -43,6 +43,8 @@ KERNEL_SOURCES = {"k_step_sh": STEP_KERNEL_SOURCES,
                   "k_step_uni": FAST_SOURCES,
                   "k_step_gen": FAST_SOURCES,
                   "k_step_rag": FAST_SOURCES,
+                  "k_step64": ["ram_step_fast64.hip", "ram_kernels.hip", "ram_wave.h", "ram_device.h",
+                               "ram_internal.h"],
                   "k_adjf_uni": ADJ_FAST_SOURCES,
                   "k_adjf_gen": ADJ_FAST_SOURCES,
                   "k_ladj": ADJ_FAST_SOURCES,

@@ -990,9 +990,9 @@ constexpr size_t kLimStage = 4 * (kLimTab + 16);    // the window's averages
 template <int R, int NS>
 __device__ __forceinline__ void lim_tab_rows(const StepAdjArgs &a, const MeshTab &tb, int n,
                                              int base, int off, int W, int NE, int nd,
-                                             int64_t wl, int t, const int (&kv)[NS],
-                                             const int (&kn)[NS], const double (&thv)[NS],
-                                             const double (&hv)[NS], const float *sqw,
+                                             int64_t wl, int t, int (&kv)[NS],
+                                             int (&kn)[NS], double (&thv)[NS],
+                                             double (&hv)[NS], const float *sqw,
                                              const double *smb, double *tI, float4 *tD,
                                              double *cacc, double &vp)
 {
@@ -1080,13 +1080,17 @@ __device__ __forceinline__ void lim_tab_rows(const StepAdjArgs &a, const MeshTab
         }
         wave_sync();
     }
-    // ---- nodes ----------------------------------------------------------------------
+    // ---- nodes (slot 0 each trip, the slots moved down after it) ------------------
 #pragma unroll 1
     for (int u = 0; u < NS; ++u) {
         const int m = t + u * kLanes;
+        const int k = kv[0], kne = kn[0];
+        const double h = hv[0], th = thv[0];
+        slot_down(kv);
+        slot_down(kn);
+        slot_down(hv);
+        slot_down(thv);
         if (m >= NE) continue;
-        const int k = kv[u];
-        const double h = hv[u], th = thv[u];
         double gw[2 * LO + 1], qval;
         if constexpr (R == kReconPLM) {
             const double sig = tI[k];
@@ -1136,7 +1140,7 @@ __device__ __forceinline__ void lim_tab_rows(const StepAdjArgs &a, const MeshTab
         if (m < nd) {
             // destination m's whole cells: window cells k .. kn - 1
             const double mb = smb[m + 1];
-            for (int j = k; j < kn[u]; ++j) {
+            for (int j = k; j < kne; ++j) {
                 const double dxj = j == k ? h : tb.dx[wrapi(wl + j, n)];
                 atomicAdd(&cacc[j], mb * dxj);
             }
@@ -1292,10 +1296,26 @@ __device__ __forceinline__ void lim_tile(const StepAdjArgs &a, const FastTile &f
         const int cw = min(kCh, W - c0);
         for (int j = t; j < cw; j += kLanes) cacc[j] = 0.0;
         wave_sync();
+        int ku[NS], cu[NS], knu[NS];
+        double hu[NS], thu[NS];
+#pragma unroll
+        for (int u = 0; u < NS; ++u) {
+            ku[u] = kv[u];
+            cu[u] = cv[u];
+            knu[u] = kn[u];
+            hu[u] = hv[u];
+            thu[u] = thv[u];
+        }
 #pragma unroll 1
         for (int u = 0; u < NS; ++u) {
             const int m = t + u * kLanes;
-            const int k = kv[u], c = cv[u];
+            const int k = ku[0], c = cu[0], kne = knu[0];
+            const double h = hu[0], th = thu[0];
+            slot_down(ku);
+            slot_down(cu);
+            slot_down(knu);
+            slot_down(hu);
+            slot_down(thu);
             double qv[P];
 #pragma unroll
             for (int j = 0; j < P; ++j) {
@@ -1308,7 +1328,7 @@ __device__ __forceinline__ void lim_tile(const StepAdjArgs &a, const FastTile &f
                 }
             }
             double gw[P], qval;
-            lim_node<R>(tb, n, c, hv[u], thv[u], qv, gw, qval);
+            lim_node<R>(tb, n, c, h, th, qv, gw, qval);
             if (m < NE) {
                 const double vb = smb[m] - smb[m + 1];
                 if (c0 == 0) vp -= vb * qval;
@@ -1320,9 +1340,8 @@ __device__ __forceinline__ void lim_tile(const StepAdjArgs &a, const FastTile &f
                 // destination m's whole cells: window cells k .. kn - 1
                 if (m < nd) {
                     const double mb = smb[m + 1];
-                    for (int j = max(k, c0); j < min(kn[u], c0 + cw); ++j) {
-                        const double dxj =
-                            j == k ? hv[u] : tb.dx[wrapi(wl + j, n)];
+                    for (int j = max(k, c0); j < min(kne, c0 + cw); ++j) {
+                        const double dxj = j == k ? h : tb.dx[wrapi(wl + j, n)];
                         atomicAdd(&cacc[j - c0], mb * dxj);
                     }
                 }

@@ -278,14 +278,14 @@ int sched_items(const ram_ctx *ctx, const ram_layout *L, ram_scan scan)
     return (shared && scan == RAM_SUM_DIRECT && ctx->items != 0) ? ctx->items : ram::kItems;
 }
 
-// The FP32 Lagrange step on a shared mesh at the default schedule and the
-// bucket index runs the streaming kernels (k_step_uni / k_step_gen, tiles of
-// kFastTile cells a wave; every cumulative mode); every other combination the
-// general shared-mesh kernel.
+// The Lagrange step on a shared mesh at the default schedule and the bucket
+// index runs the streaming kernels on tiles of kFastTile cells a wave: FP32
+// k_step_uni / k_step_gen (every cumulative mode), FP64 k_step64; every other
+// combination the general shared-mesh kernel.
 bool use_fast_shape(const ram_ctx *ctx, bool shared, int64_t n_cols, ram_dtype dtype,
                     ram_scan scan)
 {
-    return shared && n_cols > 0 && dtype == RAM_F32 && ctx->items == 0 &&
+    return shared && n_cols > 0 && (dtype == RAM_F32 || dtype == RAM_F64) && ctx->items == 0 &&
            ctx->density.kind == RAM_DENSITY_NONE;
 }
 bool use_fast(const ram_ctx *ctx, const ram_layout *L, ram_dtype dtype, ram_scan scan)
@@ -312,7 +312,8 @@ bool use_rag(const ram_ctx *ctx, const ram_layout *L, ram_dtype dtype, const voi
 bool use_fast_adjoint(const ram_ctx *ctx, const ram_layout *L, ram_dtype dtype,
                       std::initializer_list<const void *> arrays)
 {
-    if (!use_fast_shape(ctx, L->edges_shared != 0, L->n_cols, dtype, RAM_SCAN_F64)) return false;
+    if (dtype != RAM_F32 || !use_fast_shape(ctx, L->edges_shared != 0, L->n_cols, dtype, RAM_SCAN_F64))
+        return false;
     if (L->n_cols % 4 != 0 || L->n_cols < ram::kFastTile + 8) return false;
     for (const void *p : arrays)
         if (p && ((uintptr_t)p % 16) != 0) return false;
@@ -1308,7 +1309,7 @@ ram_status setup_row_step(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtyp
     RowsPlan rp = plan_rows(cv, layout,
                             fast ? ram::kFastTile : ram::step_tile_for(rs.items, dv != nullptr),
                             plan_order);
-    rp.uniform = dtype == RAM_F32 && (recon != 0 || scan == RAM_SUM_DIRECT || fast);
+    rp.uniform = (dtype == RAM_F32 && (recon != 0 || scan == RAM_SUM_DIRECT)) || fast;
     const int64_t nt = tiles_of(layout, rp.tile);
     const size_t wlo_off = cv.take(sizeof(int64_t) * nt), w_off = cv.take(plan_w_bytes(nt));
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;

@@ -61,7 +61,15 @@ struct MeshTab {
     // node's, in that order (nine values at order 5); planes, so that the
     // records of neighbouring cells are neighbours in memory
     const float *stp = nullptr;
-    const double2 *rrd = nullptr;     // the same in FP64
+    const double2 *rrd = nullptr;     // per cell: (dx, 1/centre gap), FP64
+    // FP64 per cell, six planes of n pairs: (x_c, 1/dx_c), then stp's values
+    // in FP64 two at a time (the last pair padded with 0)
+    const double2 *stpd = nullptr;
+    // the same offsets and denominators as FP32 deviations from those of
+    // equally spaced nodes (planes as stp): th_b - (b - lo), rd_b / rd_eq_b - 1;
+    // on a uniform run they are below about 1e-9, so their FP32 rounding is
+    // far below FP64 rounding of the values they restore
+    const float *stdv = nullptr;
     const void *crf = nullptr;        // CellRec<float>[n]
     const void *crd = nullptr;        // CellRec<double>[n]
     // PPM interface weights (d1, d2, e1, e2, e3 of every cell; five arrays of
@@ -388,6 +396,8 @@ hipError_t launch_step_shared(const StepArgs &a, bool f64, int scan, int order,
 hipError_t launch_plan_fast(const StepArgs &a, int order, const FastPlan &plan,
                             hipStream_t stream);
 hipError_t launch_step_fast(const StepArgs &a, int order, int scan, hipStream_t stream);
+// The same plan's FP64 step (k_step64, ram_step_fast64.hip): scan kScanF64 or kSumDirect.
+hipError_t launch_step_fast64(const StepArgs &a, int order, int scan, hipStream_t stream);
 // Per-row meshes, FP32, shift only: the per-call plan into `plan` (R.tile ==
 // kRagTile, a.dv null), then per step the streaming shift (a.rag set).
 hipError_t launch_plan_rag(const StepArgs &a, int order, const RagPlan &plan,

@@ -540,6 +540,8 @@ struct MeshTabW {
     float2 *rrf;
     float *stp;
     double2 *rrd;
+    double2 *stpd;
+    float *stdv;
     double *ppmd;
     float *ppmf;
     int32_t *nonu;
@@ -606,6 +608,39 @@ __global__ __launch_bounds__(256) void k_mesh_prep(const double *x, int n, MeshT
             p4[j] = make_float4(v[0], v[1], v[2], v[3]);
             p4[n + j] = make_float4(v[4], v[5], v[6], v[7]);
             T.stp[8 * n + j] = v[8];
+        }
+        {
+            // FP64: the cell's left edge and 1/dx, then the same values, in
+            // pairs (six planes of double2)
+            double v[12];
+            int k = 0;
+            v[k++] = xc;
+            v[k++] = 1.0 / dx;
+            for (int a = 0; a <= P; ++a)
+                if (a != LO && a != LO + 1) v[k++] = rd.th[a];
+            for (int a = 0; a <= P; ++a)
+                if (a != LO) v[k++] = rd.rd[a];
+            for (; k < 12; ++k) v[k] = 0.0;
+            for (int pl = 0; pl < 6; ++pl) T.stpd[pl * n + j] = make_double2(v[2 * pl], v[2 * pl + 1]);
+            // the same offsets and denominators as FP32 deviations from those
+            // of equally spaced nodes (offset b - LO, denominator 1 / prod_{a != b}
+            // (b - a)): th_b - (b - LO), and rd_b / rd_eq_b - 1
+            float dv9[9];
+            int m = 0;
+            for (int a = 0; a <= P; ++a)
+                if (a != LO && a != LO + 1) dv9[m++] = (float)(rd.th[a] - (double)(a - LO));
+            for (int a = 0; a <= P; ++a) {
+                if (a == LO) continue;
+                double eq = 1.0;
+                for (int b = 0; b <= P; ++b)
+                    if (b != a) eq *= (double)(a - b);
+                dv9[m++] = (float)(rd.rd[a] * eq - 1.0);
+            }
+            for (; m < 9; ++m) dv9[m] = 0.0f;
+            float4 *d4 = (float4 *)T.stdv;
+            d4[j] = make_float4(dv9[0], dv9[1], dv9[2], dv9[3]);
+            d4[n + j] = make_float4(dv9[4], dv9[5], dv9[6], dv9[7]);
+            T.stdv[8 * n + j] = dv9[8];
         }
         const PpmW pw = ppm_weights(x[wrap_small(j - 1, n) + 1] - x[wrap_small(j - 1, n)], dx,
                                     x[wrap_small(j + 1, n) + 1] - x[wrap_small(j + 1, n)],
@@ -787,7 +822,8 @@ size_t mesh_tab_bytes(int64_t n, int order)
     return 3 * al256(8 * n) + 3 * al256(4 * n) + al256(8 * n * 2 * (order + 1)) +
            al256(4 * n * 2 * (order + 1)) + al256(4 * nb) + al256(16 * nb) + al256(16) +
            al256(sizeof(CellRec<float>) * n) + al256(sizeof(CellRec<double>) * n) +
-           al256(8 * n) + al256(36 * n) + al256(16 * n) + al256(40 * n) + al256(20 * n) +
+           al256(8 * n) + al256(36 * n) + al256(16 * n) + al256(96 * n) + al256(36 * n) + al256(40 * n) +
+           al256(20 * n) +
            2 * al256(4 * (n + 1));
 }
 
@@ -813,6 +849,8 @@ hipError_t launch_mesh_prep(const double *x, int64_t n, int order, void *mem,
     w.rrf = (float2 *)p; p += al256(8 * n);
     w.stp = (float *)p; p += al256(36 * n);
     w.rrd = (double2 *)p; p += al256(16 * n);
+    w.stpd = (double2 *)p; p += al256(96 * n);
+    w.stdv = (float *)p; p += al256(36 * n);
     w.ppmd = (double *)p; p += al256(40 * n);
     w.ppmf = (float *)p; p += al256(20 * n);
     w.nonu = (int32_t *)p; p += al256(4 * (n + 1));
@@ -828,6 +866,8 @@ hipError_t launch_mesh_prep(const double *x, int64_t n, int order, void *mem,
     tab.rrf = w.rrf;
     tab.stp = w.stp;
     tab.rrd = w.rrd;
+    tab.stpd = w.stpd;
+    tab.stdv = w.stdv;
     tab.ppmd = w.ppmd;
     tab.ppmf = w.ppmf;
     tab.nonu = uniform ? w.nonu : nullptr;

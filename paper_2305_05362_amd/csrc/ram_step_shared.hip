@@ -857,10 +857,9 @@ hipError_t launch_step_shared(const StepArgs &a, bool f64, int scan, int order,
                               int items, hipStream_t stream)
 {
     if (a.rows.n_tiles <= 0) return hipSuccess;
-    if (a.fast.rec) {
-        if (f64) return hipErrorInvalidValue;
-        return launch_step_fast(a, order, scan, stream);
-    }
+    if (a.fast.rec)
+        return f64 ? launch_step_fast64(a, order, scan, stream)
+                   : launch_step_fast(a, order, scan, stream);
     if (a.rows.tile != step_tile_for(scan == kSumDirect ? items : kItems, a.dv != nullptr))
         return hipErrorInvalidValue;       // the tiles were planned for another schedule
     if (f64) return step_sh_order<double>(a, scan == kSumDirect ? kSumDirect : kScanF64,

@@ -89,5 +89,16 @@ __device__ __forceinline__ double lane63(double v)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Moves a small per-lane array down one slot (v[0] = v[1], ...), for loops
+// over slots that are not unrolled: they read slot 0 each trip, since an
+// array indexed at run time is placed in scratch memory, whose stores reach
+// HBM.
+template <class T, int N>
+__device__ __forceinline__ void slot_down(T (&v)[N])
+{
+#pragma unroll
+    for (int i = 0; i + 1 < N; ++i) v[i] = v[i + 1];
+}
+
 } // namespace dev
 } // namespace ram
