@@ -157,6 +157,15 @@ __device__ __forceinline__ void node_weights_uni(const float *stdv, int n, int c
     for (int b = 0; b <= P; ++b) wk[b] = rrd[b] * (pre[b] * suf[b]);
 }
 
+// A node's shifted coordinate wrapped into [x0, xN), as node_pos forms it
+// (the bucket, which a planned node does not need, left out).
+__device__ __forceinline__ double shifted_xt(double xe, const RowShift &rs, double x0, double xN)
+{
+    const double xs = xe - rs.s;
+    const double v0 = xs - rs.p0, vp = xs - rs.pp, vm = xs - rs.pm;
+    return v0 >= xN ? vp : (v0 < x0 ? vm : v0);
+}
+
 // Position in cell c (pair 0 of stpd: its left edge and 1/dx) of a node at
 // xt, taken across the period seam when c is the neighbour over it.
 __device__ __forceinline__ double cell_theta(const double2 *stpd, int c, double xt, double len)
@@ -274,23 +283,32 @@ __device__ __forceinline__ void tile64(const StepArgs &a, const FastTile &ft, do
         // ---- each node's window index and position in its cell ---------------------
         const int16_t *jcp =
             ft.kind == kFastWindow ? a.fast.jc + (int64_t)ft.pad[1] * kFastNodes : nullptr;
-        int jv[NS];
+        // (a window wraps the row at most once unless the row is shorter than it)
+        const bool wrapw = W + base > 2 * n;
+        auto wcell = [&](int j) {
+            const int c = base + j;
+            return wrapw ? wrap_small(c, n) : (c >= n ? c - n : c);
+        };
+        int jv[NS], cv[NS];
         double thv[NS];
 #pragma unroll
         for (int u = 0; u < NS; ++u) {
             const int m = min(t + u * kLanes, NE - 1);
             int e = i0 - H + m;
             e = e < 0 ? e + n : (e >= n ? e - n : e);
-            const NodePos np = node_pos(x[e], rs, x0, xN, tb.scal[0], tb.scal[2], tb.nb);
+            const double xt = shifted_xt(x[e], rs, x0, xN);
             int j = jcp ? (int)jcp[m] : LO + m;
-            double th = cell_theta(tb.stpd, wrap_small(base + j, n), np.xt, len);
+            int c = wcell(j);
+            double th = cell_theta(tb.stpd, c, xt, len);
             // a uniform tile's inner node that the mesh's rounding puts in a
             // neighbouring cell (the end nodes' cells came from the search)
             if (!jcp && m > 0 && m < NE - 1 && (th < 0.0 || th >= 1.0)) {
                 j += th < 0.0 ? -1 : 1;
-                th = cell_theta(tb.stpd, wrap_small(base + j, n), np.xt, len);
+                c = wcell(j);
+                th = cell_theta(tb.stpd, c, xt, len);
             }
             jv[u] = j;
+            cv[u] = c;
             thv[u] = th;
         }
         wave_sync();                                 // the window masses
@@ -330,9 +348,9 @@ __device__ __forceinline__ void tile64(const StepArgs &a, const FastTile &ft, do
             const int m = min(t + u * kLanes, NE - 1);
             double wk[P + 1];
             if (uniform)
-                node_weights_uni<P>(tb.stdv, n, wrap_small(base + jv[u], n), thv[u], wk);
+                node_weights_uni<P>(tb.stdv, n, cv[u], thv[u], wk);
             else
-                node_weights<P>(tb.stpd, n, wrap_small(base + jv[u], n), thv[u], wk);
+                node_weights<P>(tb.stpd, n, cv[u], thv[u], wk);
             const int j = jv[u] + off;
             double ell = 0.0;
             if constexpr (kPre) {
