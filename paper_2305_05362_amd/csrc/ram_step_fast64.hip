@@ -394,14 +394,16 @@ __device__ __forceinline__ void tile64(const StepArgs &a, const FastTile &ft, do
         wave_sync();
     }
 
-    // the residual's geometry of cells i0+4l-2 .. i0+4l+5 (on its way during the
-    // destination cells' sums)
-    double2 rr[H != 0 ? 4 + 2 * H : 1];
+    // the residual's geometry (on its way during the destination cells' sums):
+    // each tile cell's (dx, 1/centre gap) one cell a lane, passed through LDS
+    // to the four-cells-a-lane layout (read there directly, the lanes' 16-byte
+    // pairs four cells apart would each span 32 cache lines), and 1/dx of the
+    // lane's own four cells
+    double2 gq[H != 0 ? NCS : 1];
     double dxi[4] = {0.0, 0.0, 0.0, 0.0};
     if constexpr (H != 0) {
-        const int cb = i0 + min(c4, nd - 1) - 2;
 #pragma unroll
-        for (int c = 0; c < 4 + 2 * H; ++c) rr[c] = tb.rrd[wrap1f(cb + c, n)];
+        for (int u = 0; u < NCS; ++u) gq[u] = tb.rrd[wrap1f(i0 - H + min(t + u * kLanes, NC - 1), n)];
         if constexpr (VEC) {
             const int d0 = i0 + (min(c4, nd - 1) & ~3);
             const double2 x01 = *(const double2 *)(tb.dxinv + d0);
@@ -446,14 +448,28 @@ __device__ __forceinline__ void tile64(const StepArgs &a, const FastTile &ft, do
     }
     if constexpr (H != 0) {
         wave_sync();                                 // window and partials are dead
-        double *sq = sw;                             // shifted value of tile cell ci - H
+        // tile cell ci (cell i0 - H + ci): shifted value, dx, 1/centre gap
+        double *sq = sell;
+        double *sdx = sw;
+        double *shi = kPre ? sp : sw + kFastNodes;
 #pragma unroll
-        for (int u = 0; u < NCS; ++u) sq[min(t + u * kLanes, NC - 1)] = qs[u];
+        for (int u = 0; u < NCS; ++u) {
+            const int ci = min(t + u * kLanes, NC - 1);
+            sq[ci] = qs[u];
+            sdx[ci] = gq[u].x;
+            shi[ci] = gq[u].y;
+        }
         wave_sync();
         if (c4 < nd) {
             double sv[8];
+            double2 rr[7];
 #pragma unroll
             for (int c = 0; c < 8; ++c) sv[c] = sq[min(c4 + c, NC - 1)];
+#pragma unroll
+            for (int c = 0; c < 7; ++c) {
+                const int ci = min(c4 + c, NC - 1);
+                rr[c] = make_double2(sdx[ci], shi[ci]);
+            }
             double o[4];
             residual4d(sv, dvv, a.dt, [&](int c) { return rr[c]; },
                        [&](int k) { return dxi[k]; }, o);
