@@ -130,7 +130,9 @@ __global__ __launch_bounds__(64) void k_plan_fast(StepArgs a, FastTile *out)
 
 
 // Residual step on four consecutive cells of a lane from the shifted state
-// s[0..7] of cells i0+4l-2 .. i0+4l+5 (Section 3.1 reading R7): fluxes on the
+// s[0..7] of cells i0+4l-2 .. i0+4l+5 (Section 3.1's upwind step with the van
+// Leer slope, the face state the upwind linear profile averaged over the
+// interval the face velocity sweeps in dt): fluxes on the
 // five faces i0+4l .. i0+4l+4 with the upwind cell's van Leer slope and the
 // swept-interval average, then the conservative update of the four cells.
 // rr(c) gives (dx, 1/centre gap to the right) of s-index c, dxi(k) 1/dx of

@@ -45,7 +45,8 @@ constexpr int kWinPre = 384;
 template <int S> constexpr int win64_cells() { return S == kScanF64 ? kWinPre : kFastWin; }
 
 // Residual step in FP64 on four consecutive cells of a lane from the shifted
-// state s[0..7] of cells i0+4l-2 .. i0+4l+5 (Section 3.1 reading R7): fluxes
+// state s[0..7] of cells i0+4l-2 .. i0+4l+5 (Section 3.1's upwind step, the
+// face state the upwind linear profile averaged over the swept interval): fluxes
 // on the five faces i0+4l .. i0+4l+4 with the upwind cell's van Leer slope
 // and the swept-interval average, then the conservative update.  rr(c) gives
 // (dx, 1/centre gap to the right) of s-index c, dxi(k) 1/dx of own cell k.

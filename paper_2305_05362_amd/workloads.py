@@ -10,7 +10,7 @@ Meshes
   * the periodic-bump mesh density of the paper's Appendix B.1 (two uniform
     resolution levels joined by a cos^2 ramp; normalisation Eq. Inorm), whose
     nodes satisfy F(x_j) = j with F = N * int psi / I_psi (Section 3.2.1,
-    Eq. mesh; read with unit index steps over N cells, see DESIGN.md);
+    Eq. mesh, read with one index step per cell: N cells, N + 1 nodes);
   * randomly stretched rows (cell-size ratio bounded by a given factor).
 
 Workloads (the five synthetic configurations)
