@@ -292,6 +292,14 @@ bool use_fast(const ram_ctx *ctx, const ram_layout *L, ram_dtype dtype, ram_scan
 {
     return use_fast_shape(ctx, L->edges_shared != 0, L->n_cols, dtype, scan);
 }
+// The limited (PLM / PPM) FP32 step on a shared mesh at the default schedule
+// runs on the same plan (k_step_uni_lim / k_step_gen_lim); FP64 and every
+// other combination the general limited kernel.
+bool use_fast_lim(const ram_ctx *ctx, const ram_layout *L, ram_dtype dtype)
+{
+    return dtype == RAM_F32 && use_fast_shape(ctx, L->edges_shared != 0, L->n_cols, dtype,
+                                              RAM_SUM_DIRECT);
+}
 
 // The FP32 shift-only step on per-row meshes at the default schedule runs the
 // streaming kernel (k_step_rag) when the call is long enough to pay for its
@@ -460,7 +468,7 @@ ram_status launch_steps(ram_ctx *ctx, ram::StepArgs a, ram_dtype dtype,
     hipError_t e;
     if (shared) {
         const int plan_order = recon == 0 ? order : (recon == RAM_RECON_PLM ? 3 : 5);
-        const bool fast = recon == 0 && allow_fast &&
+        const bool fast = (recon == 0 || dtype == RAM_F32) && allow_fast &&
                           use_fast_shape(ctx, a.rows.shared != 0, a.rows.n_cols, dtype, scan);
         e = plan_shared(a, plan_order, fast, mem + wlo_off, mem + w_off, ctx->stream);
         if (e != hipSuccess) return hip_fail(e, "window plan launch");
@@ -898,11 +906,13 @@ ram_status ram_shift_limited(ram_ctx *ctx, const ram_layout *layout, ram_dtype d
     if (q_in == q_out) return fail(RAM_E_INVALID_ARG, "q_in and q_out must not alias");
     if ((st = enter(ctx)) != RAM_OK) return st;
     const bool shared = layout->edges_shared && layout->n_cols > 0;
+    const bool fast = shared && use_fast_lim(ctx, layout, dtype);
     Carve cv;
-    RowsPlan rp = plan_rows(cv, layout, ram::step_tile(false), 1);
+    RowsPlan rp = plan_rows(cv, layout, fast ? ram::kFastTile : ram::step_tile(false), 1);
+    rp.uniform = fast;
     const int64_t nt = tiles_of(layout, rp.tile);
     const size_t wlo_off = shared ? cv.take(sizeof(int64_t) * nt) : 0;
-    const size_t w_off = shared ? cv.take(ram::kPlanW * sizeof(int32_t) * nt) : 0;
+    const size_t w_off = shared ? cv.take(plan_w_bytes(nt)) : 0;
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
     ram::StepArgs a;
     if ((st = make_rows(ctx, layout, edges, rp, a.rows)) != RAM_OK) return st;
@@ -937,11 +947,13 @@ ram_status ram_step_limited(ram_ctx *ctx, const ram_layout *layout, ram_dtype dt
         // one fused kernel a step (limited shift + residual), window plan once
         Carve cv;
         const size_t tmp_off = cv.take(state_bytes);
-        RowsPlan rp = plan_rows(cv, layout, ram::step_tile(dv != nullptr), 1);
+        const bool fast = use_fast_lim(ctx, layout, dtype);
+        RowsPlan rp = plan_rows(cv, layout,
+                                fast ? ram::kFastTile : ram::step_tile(dv != nullptr), 1);
         rp.uniform = dtype == RAM_F32;
         const int64_t nt = tiles_of(layout, rp.tile);
         const size_t wlo_off = cv.take(sizeof(int64_t) * nt);
-        const size_t w_off = cv.take(ram::kPlanW * sizeof(int32_t) * nt);
+        const size_t w_off = cv.take(plan_w_bytes(nt));
         if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
         ram::StepArgs a;
         std::memset(&a, 0, sizeof(a));    // the graph key compares raw bytes
@@ -1025,12 +1037,15 @@ ram_status ram_step_limited_record(ram_ctx *ctx, const ram_layout *layout,
     Carve cv;
     // shared mesh: the fused kernel with the post-shift state written out;
     // per-row meshes: the shift kernel into q_half, then the residual kernel
+    const bool fast = shared && use_fast_lim(ctx, layout, dtype);
     RowsPlan rp = plan_rows(cv, layout,
-                            shared ? ram::step_tile(dv != nullptr) : ram::step_tile(false), 1);
+                            fast ? ram::kFastTile
+                                 : (shared ? ram::step_tile(dv != nullptr) : ram::step_tile(false)),
+                            1);
     rp.uniform = shared && dtype == RAM_F32;
     const int64_t nt = tiles_of(layout, rp.tile);
     const size_t wlo_off = shared ? cv.take(sizeof(int64_t) * nt) : 0;
-    const size_t w_off = shared ? cv.take(ram::kPlanW * sizeof(int32_t) * nt) : 0;
+    const size_t w_off = shared ? cv.take(plan_w_bytes(nt)) : 0;
     RowsPlan rr = plan_rows(cv, layout, ram::kResTile, 0);
     if ((st = ensure_scratch(ctx, cv.off)) != RAM_OK) return st;
     ram::StepArgs a;
@@ -1048,12 +1063,9 @@ ram_status ram_step_limited_record(ram_ctx *ctx, const ram_layout *layout,
     hipError_t e;
     if (shared) {
         a.dv = dv;
-        int64_t *wlo = (int64_t *)((char *)ctx->scratch + wlo_off);
-        int32_t *w = (int32_t *)((char *)ctx->scratch + w_off);
-        e = ram::launch_plan(a, recon == RAM_RECON_PLM ? 3 : 5, wlo, w, ctx->stream);
+        e = plan_shared(a, recon == RAM_RECON_PLM ? 3 : 5, fast, (char *)ctx->scratch + wlo_off,
+                        (char *)ctx->scratch + w_off, ctx->stream);
         if (e != hipSuccess) return hip_fail(e, "window plan launch");
-        a.plan_wlo = wlo;
-        a.plan_w = w;
     }
     for (int64_t k = 0; k < n_steps; ++k) {
         void *qi = (char *)q_traj + k * state_bytes;
@@ -1305,7 +1317,8 @@ ram_status setup_row_step(ram_ctx *ctx, const ram_layout *layout, ram_dtype dtyp
     rs.f64 = dtype == RAM_F64;
     rs.items = recon ? ram::kItems : sched_items(ctx, layout, scan);
     const int plan_order = recon == 0 ? order : (recon == RAM_RECON_PLM ? 3 : 5);
-    const bool fast = recon == 0 && use_fast(ctx, layout, dtype, scan);
+    const bool fast = recon == 0 ? use_fast(ctx, layout, dtype, scan)
+                                 : use_fast_lim(ctx, layout, dtype);
     RowsPlan rp = plan_rows(cv, layout,
                             fast ? ram::kFastTile : ram::step_tile_for(rs.items, dv != nullptr),
                             plan_order);

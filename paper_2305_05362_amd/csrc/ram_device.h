@@ -776,5 +776,32 @@ __device__ __attribute__((noinline)) double lim_partial_global(const double *x,
     return th * (A + th * (B + th * C));
 }
 
+// The same for PPM with the shared mesh's FP64 weights tables (tb.ppmd: d1,
+// d2, e1, e2, e3 of every cell, the values ppm_weights gives from the same
+// cell sizes) instead of forming the weights of five cells per node.
+template <typename TQ>
+__device__ __attribute__((noinline)) double ppm_partial_tab(const MeshTab &tb, const double *x,
+                                                            const TQ *q, int n, int c,
+                                                            double xh)
+{
+    double qv[5];
+#pragma unroll
+    for (int a = 0; a < 5; ++a) qv[a] = (double)q[wrapi(c - 2 + a, n)];
+    const int cm = wrapi(c - 1, n), cp = wrapi(c + 1, n);
+    const double *pw = tb.ppmd;
+    const double h0 = x[c + 1] - x[c];
+    const double th = (xh - x[c]) / h0;
+    const double d0 = ppm_delta<double>(qv[0], qv[1], qv[2], pw[cm], pw[n + cm]);
+    const double d1 = ppm_delta<double>(qv[1], qv[2], qv[3], pw[c], pw[n + c]);
+    const double d2 = ppm_delta<double>(qv[2], qv[3], qv[4], pw[cp], pw[n + cp]);
+    const double L = qv[1] + pw[2 * n + cm] * (qv[2] - qv[1]) + pw[3 * n + cm] * d1 +
+                     pw[4 * n + cm] * d0;
+    const double Rv = qv[2] + pw[2 * n + c] * (qv[3] - qv[2]) + pw[3 * n + c] * d2 +
+                      pw[4 * n + c] * d1;
+    double A, B, C;
+    ppm_cubic<double>(qv[2], L, Rv, h0, A, B, C);
+    return th * (A + th * (B + th * C));
+}
+
 } // namespace dev
 } // namespace ram

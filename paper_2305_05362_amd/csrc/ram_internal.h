@@ -396,6 +396,8 @@ hipError_t launch_step_shared(const StepArgs &a, bool f64, int scan, int order,
 hipError_t launch_plan_fast(const StepArgs &a, int order, const FastPlan &plan,
                             hipStream_t stream);
 hipError_t launch_step_fast(const StepArgs &a, int order, int scan, hipStream_t stream);
+// The same plan's limited FP32 step (PLM / PPM: k_step_uni_lim, k_step_gen_lim).
+hipError_t launch_step_fast_lim(const StepArgs &a, int recon, hipStream_t stream);
 // The same plan's FP64 step (k_step64, ram_step_fast64.hip): scan kScanF64 or kSumDirect.
 hipError_t launch_step_fast64(const StepArgs &a, int order, int scan, hipStream_t stream);
 // Per-row meshes, FP32, shift only: the per-call plan into `plan` (R.tile ==

@@ -350,7 +350,10 @@ __global__ __launch_bounds__(kBlock) void k_node_plan(StepArgs a)
     }
 }
 
-template <int P, int H, bool VEC>
+// LR != 0: the limited reconstruction LR (PLM / PPM, P its plan order); every
+// such tile takes the global-memory path, each node's partial integral the
+// limited profile of its cell (Section 3.1).
+template <int P, int H, bool VEC, int LR = 0>
 __device__ __forceinline__ void general_tile(const StepArgs &a, const FastTile &ft,
                                              unsigned char *su, float *sell, short *sjc, int t)
 {
@@ -377,7 +380,7 @@ __device__ __forceinline__ void general_tile(const StepArgs &a, const FastTile &
     float *qo = (float *)a.q_out + qoff;
     float *qmid = a.q_mid ? (float *)a.q_mid + qoff : nullptr;
     const int W = ft.w, base = ft.base;
-    const bool windowed = ft.kind == kFastWindow;
+    const bool windowed = LR == 0 && ft.kind == kFastWindow;
 
     if (windowed) {
         // ---- round trip 1: window masses, the nodes' window index and theta
@@ -478,7 +481,12 @@ __device__ __forceinline__ void general_tile(const StepArgs &a, const FastTile &
             if (np.xt >= nx.y) c = cell_walk(x, n, c, np.xt);
             const int64_t g = (int64_t)c + (rs.kf0 + np.dk) * (int64_t)n + kx;
             sg[m] = g;
-            sell[m] = (float)direct_partial<float, P>(x, q, n, len, sh, tb.scal[1], i0 - H + m, g);
+            if constexpr (LR == kReconPPM)
+                sell[m] = (float)ppm_partial_tab<float>(tb, x, q, n, c, np.xt);
+            else if constexpr (LR == kReconPLM)
+                sell[m] = (float)lim_partial_global<float, LR>(x, q, n, c, np.xt);
+            else
+                sell[m] = (float)direct_partial<float, P>(x, q, n, len, sh, tb.scal[1], i0 - H + m, g);
         }
         wave_sync();
     }
@@ -961,6 +969,126 @@ __global__ __launch_bounds__(kBlock, 8) void k_step_uni(StepArgs a)
     uniform_tile<P, H, VEC>(a, r, swin[wid], (int)threadIdx.x % kLanes);
 }
 
+// A uniform-run tile of the limited step (Section 3.1's PLM / PPM, App. A),
+// FP32: every node of the tile sits in the next window cell at the tile's
+// theta, so shifted cell ci is the average of window cell LO + ci plus the
+// difference of the limited cubics of window cells LO + ci + 1 and LO + ci
+// at theta (in value units: the run's cells are all of one size).  Each lane
+// forms, from its window values in registers, the slopes, the PPM interface
+// values and the constrained parabolas its eight shifted cells need (the
+// mesh's weights of window cell 1, whose neighbours lie in the run, serve the
+// whole tile), then the residual as in uniform_tile.
+template <int R, int H, bool VEC>
+__device__ __forceinline__ void uniform_tile_lim(const StepArgs &a, const FastTile &r, float *sw,
+                                                 int t)
+{
+    constexpr int LO = LimHalo<R>::lo;
+    constexpr int P = 2 * LO + 1;
+    constexpr int NV = 4 + 2 * H;                    // shifted cells a lane
+    constexpr int NQ = NV + 2 * LO + 1;             // window values c4 .. c4 + NQ - 1
+    constexpr int NW = (NQ + 3) / 4 * 4;             // whole float4s
+    constexpr int NUW = (kFT + 2 * H + P + kLanes - 1) / kLanes;  // window slots a lane
+    static_assert(NUW * kLanes <= kUniWin && 4 * (kLanes - 1) + NW <= kUniWin, "window");
+    const MeshTab &tb = a.rows.tab;
+    const int n = (int)a.rows.n_cols;
+    const float dt = (float)a.dt;
+    const int c4 = 4 * t;
+    const TilePos p = tile_pos(r.pad[0], n, H);
+    const int64_t qoff = (int64_t)p.row * n;
+    const float th = __int_as_float(r.pad[1]);
+
+    float wv[NUW];
+    {
+        const float *q = (const float *)a.q_in + qoff;
+#pragma unroll
+        for (int k = 0; k < NUW; ++k) {
+            int mm = r.base + min(t + k * kLanes, r.w - 1);
+            mm = mm >= n ? mm - n : mm;
+            wv[k] = q[mm];
+        }
+    }
+    float pw[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    {
+        const int c1 = r.base + 1 >= n ? r.base + 1 - n : r.base + 1;
+        if constexpr (R == kReconPPM) {
+#pragma unroll
+            for (int k = 0; k < 5; ++k) pw[k] = tb.ppmf[k * n + c1];
+        }
+    }
+    float dvv[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    if constexpr (H != 0) load_faces<VEC>((const float *)a.dv + qoff, n, p.i0, p.nd, c4, dvv);
+#pragma unroll
+    for (int k = 0; k < NUW; ++k) sw[t + k * kLanes] = wv[k];
+    wave_sync();
+    float win[NW];
+#pragma unroll
+    for (int v = 0; v < NW / 4; ++v) {
+        const float4 w4 = *(const float4 *)(sw + c4 + 4 * v);
+        win[4 * v] = w4.x;
+        win[4 * v + 1] = w4.y;
+        win[4 * v + 2] = w4.z;
+        win[4 * v + 3] = w4.w;
+    }
+    // ell[v]: the limited cubic at theta of window cell c4 + LO + v (value units)
+    float ell[NV + 1];
+    if constexpr (R == kReconPPM) {
+        // slope of window cell c4 + 1 + s, then the interface between window
+        // cells c4 + 1 + s and c4 + 2 + s
+        float dl[NV + 3], iv[NV + 2];
+#pragma unroll
+        for (int k = 0; k < NV + 3; ++k) dl[k] = ppm_delta<float>(win[k], win[k + 1], win[k + 2], pw[0], pw[1]);
+#pragma unroll
+        for (int k = 0; k < NV + 2; ++k)
+            iv[k] = win[k + 1] + pw[2] * (win[k + 2] - win[k + 1]) + pw[3] * dl[k + 1] + pw[4] * dl[k];
+#pragma unroll
+        for (int v = 0; v <= NV; ++v) {
+            float pa, pb, pc;
+            ppm_cubic<float>(win[v + 2], iv[v], iv[v + 1], 1.0f, pa, pb, pc);
+            pb = win[v + 2] - pa - pc;
+            ell[v] = th * (pa + th * (pb + th * pc));
+        }
+    } else {
+        const float g = r.hinv, hh = r.dx;
+#pragma unroll
+        for (int v = 0; v <= NV; ++v) {
+            const float dp = (win[v + 2] - win[v + 1]) * g, dm = (win[v + 1] - win[v]) * g;
+            const float sig = (dp * dm <= 0.0f) ? 0.0f : harmonic2(dp, dm);
+            const float kap = 0.5f * sig * hh;
+            ell[v] = th * (win[v + 1] - kap + th * kap);
+        }
+    }
+    float s[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) s[v] = win[v + LO] + (ell[v + 1] - ell[v]);
+    float *qo = (float *)a.q_out + qoff;
+    if constexpr (H == 0) {
+        store_cells<VEC>(qo, p.i0, p.nd, c4, s);
+    } else {
+        if (a.q_mid && c4 < p.nd) {
+            float *qm = (float *)a.q_mid + qoff;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (c4 + k < p.nd) qm[p.i0 + c4 + k] = s[k + 2];
+        }
+        const float2 g = make_float2(r.dx, r.hinv);
+        const float dxi = r.dxinv;
+        float o[4];
+        residual4(s, dvv, dt, [&](int) { return g; }, [&](int) { return dxi; }, o);
+        store_cells<VEC>(qo, p.i0, p.nd, c4, o);
+    }
+}
+
+template <int R, int H, bool VEC>
+__global__ __launch_bounds__(kBlock) void k_step_uni_lim(StepArgs a)
+{
+    __shared__ __attribute__((aligned(16))) float swin[kWaves][kUniWin];
+    const int wid = wave_id();
+    const int i = (int)blockIdx.x * kWaves + wid;
+    if (i >= a.fast.totals[0]) return;
+    const FastTile r = load_rec(a.fast.rec + a.rows.n_tiles, i);
+    uniform_tile_lim<R, H, VEC>(a, r, swin[wid], (int)threadIdx.x % kLanes);
+}
+
 // The other tiles: a grid of a quarter of the tile count in waves (the host
 // does not know how many there are; a quarter covers the refined disk with
 // one tile a wave), each wave stepping through the list by the grid's size.
@@ -1017,6 +1145,48 @@ hipError_t step_fast_p(const StepArgs &a, int scan, hipStream_t st)
     case kScanF32: return step_fast_ps<P, kScanF32>(a, vec, st);
     default: return step_fast_ps<P, kSumDirect>(a, vec, st);
     }
+}
+
+// The limited step's other tiles: the global-memory path of general_tile,
+// every node located by the bucket index and its partial integral the
+// limited profile of its cell.
+template <int R, int H, bool VEC>
+__global__ __launch_bounds__(kBlock) void k_step_gen_lim(StepArgs a)
+{
+    constexpr int P = 2 * LimHalo<R>::lo + 1;
+    __shared__ __attribute__((aligned(16))) unsigned char su[kWaves][WaveLds::u];
+    __shared__ __attribute__((aligned(16))) float sell_[kWaves][WaveLds::nodes];
+    __shared__ __attribute__((aligned(16))) short sjc_[kWaves][WaveLds::nodes];
+    const int wid = wave_id();
+    const int nt = (int)a.rows.n_tiles;
+    const int t = (int)threadIdx.x % kLanes;
+    const int stride = (int)gridDim.x * kWaves;
+    for (int i = a.fast.totals[0] + (int)blockIdx.x * kWaves + wid; i < nt; i += stride) {
+        const FastTile r = load_rec(a.fast.rec + nt, i);
+        general_tile<P, H, VEC, R>(a, r, su[wid], sell_[wid], sjc_[wid], t);
+        wave_sync();                                 // the next tile reuses the LDS
+    }
+}
+
+template <int R, int H, bool VEC>
+hipError_t step_fast_lim_kernels(const StepArgs &a, hipStream_t st)
+{
+    const dim3 g((unsigned)((a.rows.n_tiles + kWaves - 1) / kWaves)), b(kBlock);
+    const dim3 gg((unsigned)((a.rows.n_tiles + kWaves * kGenShare - 1) / (kWaves * kGenShare)));
+    hipLaunchKernelGGL((k_step_uni_lim<R, H, VEC>), g, b, 0, st, a);
+    hipLaunchKernelGGL((k_step_gen_lim<R, H, VEC>), gg, b, 0, st, a);
+    return hipGetLastError();
+}
+
+template <int R>
+hipError_t step_fast_lim_r(const StepArgs &a, hipStream_t st)
+{
+    const bool vec = (a.rows.n_cols % 4) == 0 && ((uintptr_t)a.q_out % 16) == 0 &&
+                     ((uintptr_t)a.q_in % 16) == 0 &&
+                     (!a.q_mid || ((uintptr_t)a.q_mid % 16) == 0) &&
+                     (!a.dv || ((uintptr_t)a.dv % 16) == 0);
+    if (a.dv) return vec ? step_fast_lim_kernels<R, 2, true>(a, st) : step_fast_lim_kernels<R, 2, false>(a, st);
+    return vec ? step_fast_lim_kernels<R, 0, true>(a, st) : step_fast_lim_kernels<R, 0, false>(a, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -1376,6 +1546,14 @@ hipError_t launch_step_fast(const StepArgs &a, int order, int scan, hipStream_t 
     case 3: return step_fast_p<3>(a, scan, stream);
     default: return step_fast_p<5>(a, scan, stream);
     }
+}
+
+hipError_t launch_step_fast_lim(const StepArgs &a, int recon, hipStream_t stream)
+{
+    if (a.rows.n_tiles <= 0) return hipSuccess;
+    if (a.rows.tile != kFastTile) return hipErrorInvalidValue;
+    return recon == kReconPLM ? step_fast_lim_r<kReconPLM>(a, stream)
+                              : step_fast_lim_r<kReconPPM>(a, stream);
 }
 
 hipError_t launch_plan_rag(const StepArgs &a, int order, const RagPlan &plan,

@@ -833,6 +833,7 @@ hipError_t launch_step_shared_limited(const StepArgs &a, bool f64, int recon,
                                       hipStream_t stream)
 {
     if (a.rows.n_tiles <= 0) return hipSuccess;
+    if (a.fast.rec) return f64 ? hipErrorInvalidValue : launch_step_fast_lim(a, recon, stream);
     if (f64) return recon == kReconPLM ? step_sh_lim<double, kReconPLM>(a, stream)
                                        : step_sh_lim<double, kReconPPM>(a, stream);
     return recon == kReconPLM ? step_sh_lim<float, kReconPLM>(a, stream)
