@@ -76,7 +76,11 @@ UNI_KERNEL = "k_step_uni<5, 2, true>"
 GEN_KERNEL = "k_step_gen<5, 2, true, 3>"
 TRAFFIC_FILE_UNI = os.path.join(ROOT, "profiles", "k_step_uni_f32_polar2048x16384_traffic.md")
 TRAFFIC_FILE_GEN = os.path.join(ROOT, "profiles", "k_step_gen_f32_polar2048x16384_traffic.md")
-TRAFFIC_FILE_PPM = os.path.join(ROOT, "profiles", "k_step_sh_f32_ppm_polar2048x16384_traffic.md")
+# the limited (PPM) FP32 step's two streaming kernels
+TRAFFIC_FILE_PPM_UNI = os.path.join(ROOT, "profiles", "k_step_uni_lim_f32_ppm_polar2048x16384_traffic.md")
+TRAFFIC_FILE_PPM_GEN = os.path.join(ROOT, "profiles", "k_step_gen_lim_f32_ppm_polar2048x16384_traffic.md")
+PPM_UNI_KERNEL = "k_step_uni_lim<2, 2, true>"
+PPM_GEN_KERNEL = "k_step_gen_lim<2, 2, true>"
 # the per-row streaming shift (cfg3 ragged batch, two-sum prefix)
 RAG_KERNEL = "k_step_rag<5, 1>"
 TRAFFIC_FILE_RAG = os.path.join(ROOT, "profiles", "k_step_rag_f32_twosum_cfg3_traffic.md")
@@ -680,9 +684,15 @@ def main():
     # is the region time over the steps; algorithmic bytes as the headline
     limited = {"unit": "Gcell-updates/s", "steps": max(1, args.steps // 4),
                "step_algorithmic_bytes_per_cell": {"f32": 12, "f64": 24},
-               "kernel": "k_step_sh<T, 3 (PLM) / 5 (PPM), direct sums, fused residual, recon>"}
+               "kernel": ("FP32: k_step_uni_lim (uniform-run tiles at the tile's theta) + "
+                          "k_step_gen_lim (the rest, nodes located and integrated from global "
+                          "memory) on the streaming plan; FP64: k_step_sh<double, 3 (PLM) / 5 "
+                          "(PPM), direct sums, fused residual, recon>")}
     kl = limited["steps"]
-    tr_ppm = load_traffic(TRAFFIC_FILE_PPM, "k_step_sh<float, 5, 3, 2, 2, 4, 0>")
+    tr_pu = load_traffic(TRAFFIC_FILE_PPM_UNI, PPM_UNI_KERNEL)
+    tr_pg = load_traffic(TRAFFIC_FILE_PPM_GEN, PPM_GEN_KERNEL)
+    tr_ppm = (tr_pu["traffic_bytes_per_launch"] + tr_pg["traffic_bytes_per_launch"]
+              if tr_pu and tr_pg else None)
     for name, recon in (("plm", R.RAM_RECON_PLM), ("ppm", R.RAM_RECON_PPM)):
         for tag, qq, dd, nb in (("f32", q32, dv32, 12.0), ("f64", q64, dv64, 24.0)):
             t_l = time_limited(qq, dd, recon, kl, args.warmup)
@@ -695,8 +705,9 @@ def main():
                    "hbm_frac": round(nb * n_cells / (t_l / kl) / 1e9 / HBM_PEAK_GBS, 4),
                    "shift_only_kernel_us": round(t_sh * 1e6, 2)}
             if name == "ppm" and tag == "f32":
-                ent["traffic"] = None if tr_ppm is None else \
-                    round(tr_ppm["traffic_bytes_per_launch"])
+                ent["traffic"] = None if tr_ppm is None else round(tr_ppm)
+                ent["traffic_over_algorithmic"] = (None if tr_ppm is None
+                                                   else round(tr_ppm / (12.0 * n_cells), 3))
             limited[f"{name}_{tag}"] = ent
     # forward + adjoint of the PPM rollout (checkpointed, FP32 state): each
     # backward step is the residual adjoint, then the limited shift adjoint

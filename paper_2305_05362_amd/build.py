@@ -43,6 +43,8 @@ KERNEL_SOURCES = {"k_step_sh": STEP_KERNEL_SOURCES,
                   "k_step_uni": FAST_SOURCES,
                   "k_step_gen": FAST_SOURCES,
                   "k_step_rag": FAST_SOURCES,
+                  "k_step_uni_lim": FAST_SOURCES,
+                  "k_step_gen_lim": FAST_SOURCES,
                   "k_step64": ["ram_step_fast64.hip", "ram_kernels.hip", "ram_wave.h", "ram_device.h",
                                "ram_internal.h"],
                   "k_adjf_uni": ADJ_FAST_SOURCES,
