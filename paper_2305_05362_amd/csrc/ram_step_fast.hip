@@ -350,9 +350,98 @@ __global__ __launch_bounds__(kBlock) void k_node_plan(StepArgs a)
     }
 }
 
-// LR != 0: the limited reconstruction LR (PLM / PPM, P its plan order); every
-// such tile takes the global-memory path, each node's partial integral the
-// limited profile of its cell (Section 3.1).
+// LDS window of the limited step's searching tiles, in cells: four arrays of
+// it (masses; averages, later the cubics' C; slopes or PLM kappa, later A;
+// PPM interface values).  Wider windows take the global-memory path.
+constexpr int kGenLimWin = 400;
+constexpr size_t kGenLimLds = 4 * sizeof(float) * (kGenLimWin + 8);
+
+// A searching tile's window for the limited step (Section 3.1, App. A): the
+// window's masses and averages in LDS, then one pass a stage over the window
+// cells -- the limited slopes (PPM; PLM: kappa = sigma dx^2 / 2), the PPM
+// interface values, each cell's constrained parabola as the cubic
+// ell(theta) = theta (A + theta (B + theta C)), B = M - A - C -- with the
+// mesh's weights of each cell, then each node's cubic at its planned theta.
+// Node m's window index goes to sjc[m], its partial integral to sell[m].
+template <int LR, int NS>
+__device__ __forceinline__ void lim_window_partials(const StepArgs &a, const MeshTab &tb, int n,
+                                                    int base, int W, int NE, int64_t qoff,
+                                                    int t, const float (&thv)[NS],
+                                                    const int (&jv)[NS], float *su,
+                                                    float *sell, short *sjc)
+{
+    constexpr int CAP = kGenLimWin + 8;
+    float *sw = su;                                  // masses
+    float *sq = su + CAP;                            // averages, then C
+    float *sd = su + 2 * CAP;                        // slopes or kappa, then A
+    float *si = su + 3 * CAP;                        // PPM interface values
+    const float *q = (const float *)a.q_in + qoff;
+    auto cell = [&](int j) { const int c = base + j; return c >= n ? c - n : c; };
+    for (int j = t; j < W; j += kLanes) {
+        const int c = cell(j);
+        const float qv = q[c];
+        sq[j] = qv;
+        sw[j] = qv * tb.dxf[c];
+    }
+    wave_sync();
+    const float *pw = tb.ppmf;
+    for (int j = t; j < W; j += kLanes) {
+        if (j < 1 || j > W - 2) continue;
+        const int c = cell(j);
+        if constexpr (LR == kReconPPM) {
+            sd[j] = ppm_delta<float>(sq[j - 1], sq[j], sq[j + 1], pw[c], pw[n + c]);
+        } else {
+            const float gp = tb.hinvf[c], gm = tb.hinvf[c == 0 ? n - 1 : c - 1];
+            const float dp = (sq[j + 1] - sq[j]) * gp, dm = (sq[j] - sq[j - 1]) * gm;
+            const float sig = (dp * dm <= 0.0f) ? 0.0f : harmonic2(dp, dm);
+            const float h = tb.dxf[c];
+            sd[j] = 0.5f * sig * h * h;
+        }
+    }
+    wave_sync();
+    if constexpr (LR == kReconPPM) {
+        // interface values between window cells j and j+1, j = 1 .. W-3
+        for (int j = t; j < W; j += kLanes) {
+            if (j < 1 || j > W - 3) continue;
+            const int c = cell(j);
+            si[j] = sq[j] + pw[2 * n + c] * (sq[j + 1] - sq[j]) + pw[3 * n + c] * sd[j + 1] +
+                    pw[4 * n + c] * sd[j];
+        }
+        wave_sync();
+        // constrained parabolas of window cells 2 .. W-3: A into sd, C into sq
+        for (int j = t; j < W; j += kLanes) {
+            if (j < 2 || j > W - 3) continue;
+            float pa, pb, pc;
+            ppm_cubic<float>(sq[j], si[j - 1], si[j], tb.dxf[cell(j)], pa, pb, pc);
+            sd[j] = pa;
+            sq[j] = pc;
+        }
+        wave_sync();
+    }
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+        const int m = min(t + u * kLanes, NE - 1);
+        const int k = jv[u];
+        const float th = thv[u];
+        float ell;
+        if constexpr (LR == kReconPPM) {
+            const float pa = sd[k], pc = sq[k];
+            const float pb = sw[k] - pa - pc;
+            ell = th * (pa + th * (pb + th * pc));
+        } else {
+            const float kap = sd[k];
+            ell = th * (sw[k] - kap + th * kap);
+        }
+        sell[m] = ell;
+        sjc[m] = (short)k;
+    }
+    wave_sync();
+}
+
+// LR != 0: the limited reconstruction LR (PLM / PPM, P its plan order): a
+// window of at most kGenLimWin cells is tabulated in LDS (lim_window_partials,
+// su then holds kGenLimLds bytes); wider ones take the global-memory path,
+// each node's partial integral the limited profile of its cell (Section 3.1).
 template <int P, int H, bool VEC, int LR = 0>
 __device__ __forceinline__ void general_tile(const StepArgs &a, const FastTile &ft,
                                              unsigned char *su, float *sell, short *sjc, int t)
@@ -380,7 +469,8 @@ __device__ __forceinline__ void general_tile(const StepArgs &a, const FastTile &
     float *qo = (float *)a.q_out + qoff;
     float *qmid = a.q_mid ? (float *)a.q_mid + qoff : nullptr;
     const int W = ft.w, base = ft.base;
-    const bool windowed = LR == 0 && ft.kind == kFastWindow;
+    const bool windowed = ft.kind == kFastWindow &&
+                          (LR == 0 || (ft.w <= kGenLimWin && ft.w + ft.base <= 2 * n));
 
     if (windowed) {
         // ---- round trip 1: window masses, the nodes' window index and theta
@@ -394,6 +484,10 @@ __device__ __forceinline__ void general_tile(const StepArgs &a, const FastTile &
             thv[s] = thp[m];
             jv[s] = jcp[m];
         }
+        if constexpr (LR != 0) {
+            lim_window_partials<LR, NS>(a, tb, n, base, W, NE, qoff, t, thv, jv, (float *)su,
+                                        sell, sjc);
+        } else {
         // window masses M = Q dx, four slots of loads at a time, every load
         // issued (clamped into the window) so that no per-slot branch makes
         // the wave wait for each load in turn
@@ -463,6 +557,7 @@ __device__ __forceinline__ void general_tile(const StepArgs &a, const FastTile &
             }
         }
         wave_sync();
+        }
     } else {
         // window wider than the LDS buffer: nodes located here, partial
         // integrals and whole-cell sums from global memory, in FP64
@@ -1147,14 +1242,15 @@ hipError_t step_fast_p(const StepArgs &a, int scan, hipStream_t st)
     }
 }
 
-// The limited step's other tiles: the global-memory path of general_tile,
-// every node located by the bucket index and its partial integral the
-// limited profile of its cell.
+// The limited step's other tiles: general_tile with the limited partials, the
+// window tabulated in LDS where it fits, else every node located by the bucket
+// index and its partial integral the limited profile of its cell.
 template <int R, int H, bool VEC>
 __global__ __launch_bounds__(kBlock) void k_step_gen_lim(StepArgs a)
 {
     constexpr int P = 2 * LimHalo<R>::lo + 1;
-    __shared__ __attribute__((aligned(16))) unsigned char su[kWaves][WaveLds::u];
+    constexpr size_t U = kGenLimLds > WaveLds::u ? kGenLimLds : WaveLds::u;
+    __shared__ __attribute__((aligned(16))) unsigned char su[kWaves][U];
     __shared__ __attribute__((aligned(16))) float sell_[kWaves][WaveLds::nodes];
     __shared__ __attribute__((aligned(16))) short sjc_[kWaves][WaveLds::nodes];
     const int wid = wave_id();
