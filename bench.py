@@ -562,6 +562,34 @@ def main():
                                          "f32_plain_prefix": e3(ones["f32_plain_prefix"])}}
     del ones
 
+    # --- the disk on a mesh of random cell sizes (every tile searching) -----
+    # the headline's rows, shifts and residual on widths 8**u: no uniform run,
+    # so the step's time is the searching tiles' (the arbitrary-mesh case)
+    wls = W.stretched_disk()
+    rows_s = R.Rows.from_workload(wls, dev)
+    v0s = torch.as_tensor(wls.v0, dtype=torch.float64, device=dev)
+    qs32 = torch.as_tensor(wls.q0.reshape(-1), dtype=torch.float32, device=dev)
+    dvs32 = torch.as_tensor(wls.dv.reshape(-1), dtype=torch.float32, device=dev)
+    sched_keep = ctx.get_schedule()
+    ctx.set_schedule(0)
+    spaths = ctx.ram_step_tile_paths(rows_s, v0s, wls.dt, order, True).cpu().numpy()
+    ks = max(1, args.steps // 5)
+    stretched = {"workload": wls.name + " (the disk's rows, shifts and residual; azimuthal "
+                             "cell widths 8**u, u ~ U[0,1)), FP32, order 5, fused residual, "
+                             "default schedule",
+                 "steps": ks, "unit": "Gcell-updates/s", "algorithmic_bytes_per_cell": 12,
+                 "tiles": {"uniform_run": int((spaths == R.RAM_TILE_UNIFORM).sum()),
+                           "searching": int((spaths == R.RAM_TILE_WINDOW).sum()),
+                           "direct": int((spaths == R.RAM_TILE_DIRECT).sum())}}
+    for name, scan in (("f32_direct", R.RAM_SUM_DIRECT), ("f32_twosum", R.RAM_SCAN_F32_TWOSUM)):
+        ts, _ = time_steps(qs32, dvs32, scan, ks, args.warmup, rows_s, v0s, wls.dt)
+        stretched[name] = round(wls.n_cells * ks / ts / 1e9, 3)
+        stretched[name + "_us_per_step"] = round(ts / ks * 1e6, 2)
+        stretched[name + "_hbm_frac"] = round(12.0 * wls.n_cells * ks / ts / 1e9
+                                              / HBM_PEAK_GBS, 4)
+    ctx.set_schedule(sched_keep)
+    del rows_s, qs32, dvs32, v0s
+
     # --- growth of max |Q| per configuration (reading C14) ------------------
     # the unlimited order-p interpolant can amplify on rough meshes; each
     # config reports max|Q_T| / max|Q_0| over its configured steps (FP64),
@@ -1066,6 +1094,7 @@ def main():
         "split_2d": split_2d,
         "centre_values_4th_order": point4,
         "ragged_cfg": ragged,
+        "stretched_disk": stretched,
         "limited_reconstructions": limited,
         "kernels": kernels,
         "roofline": roofline,

@@ -244,8 +244,9 @@ def cfg1() -> Workload:
 def polar(n_r: int, n_phi: int, cfg: int, order: int, steps: int,
           sigma: float = 0.05, noise: float = 1e-3, r0: float = 0.4,
           r1: float = 2.5, a: float = 0.2, b: float = 0.3, c: float = 9.0,
-          name: str = "polar") -> Workload:
-    """Polar disk rows: one row per radius, azimuthal periodic-bump mesh.
+          name: str = "polar", phi: Optional[np.ndarray] = None) -> Workload:
+    """Polar disk rows: one row per radius, azimuthal periodic-bump mesh
+    (or the azimuthal edges ``phi`` given, n_phi + 1 of them on [-pi, pi]).
 
     v0_j = r_j^-1.5 (angular Keplerian speed, r_j the arithmetic centre);
     dv_{j,i-1/2} = 0.01 v0_j sin(phi_{i-1/2}) xi (xi ~ N(0,1), stream 1);
@@ -255,7 +256,8 @@ def polar(n_r: int, n_phi: int, cfg: int, order: int, steps: int,
     """
     redges = log_edges(n_r, r0, r1)
     rc = 0.5 * (redges[:-1] + redges[1:])
-    phi = bump_edges(n_phi, -math.pi, math.pi, a, b, c)
+    if phi is None:
+        phi = bump_edges(n_phi, -math.pi, math.pi, a, b, c)
     pc = 0.5 * (phi[:-1] + phi[1:])
     v0 = rc ** -1.5
     xi = rng_for(cfg, 1).standard_normal((n_r, n_phi))
@@ -325,6 +327,16 @@ def cfg5() -> Workload:
     the refined azimuthal zone; residual velocity from the same recipe."""
     return polar(2048, 16384, 5, 5, 1000, sigma=0.01, noise=0.0,
                  name="cfg5_polar2048x16384")
+
+
+def stretched_disk(ratio: float = 8.0) -> Workload:
+    """cfg5's disk (2048 x 16384, the same density bump, Keplerian shifts and
+    residual recipe) on an azimuthal mesh of random cell sizes, widths
+    ratio**u (u ~ U[0,1), stream 2 of seed 7): no run of equal cells, so
+    every tile of the streaming step locates its shifted nodes."""
+    phi = stretched_edges(16384, ratio, rng_for(7, 2), -math.pi, math.pi)
+    return polar(2048, 16384, 5, 5, 1000, sigma=0.01, noise=0.0,
+                 name=f"disk_stretched{ratio:g}_2048x16384", phi=phi)
 
 
 def cfg3(n_rows: int = 4096, nmin: int = 64, nmax: int = 8192,

@@ -287,6 +287,37 @@ def test_cfg5_full_size_sampled_rows():
         assert_parity(got, ref, 1e-6, CELL_F32, what=str(scan))
 
 
+def test_stretched_disk_full_size_sampled_rows():
+    # the disk on a mesh of random cell sizes: every tile locates its nodes
+    # (no uniform-run stencil), at the full size in the default schedule
+    wl = W.stretched_disk()
+    rows = R.Rows.from_workload(wl, DEV)
+    R.context(0).set_schedule(0)
+    paths = R.context(0).ram_step_tile_paths(rows, dev(wl.v0), wl.dt, 5, True).cpu().numpy()
+    assert (paths == R.RAM_TILE_UNIFORM).sum() == 0 and (paths == R.RAM_TILE_WINDOW).sum() > 0
+    pick = np.array([0, 5, 1024, 2047])
+    sw = _sample_rows(wl, pick)
+    orows = oracle.Rows.from_workload(sw)
+    q = dev(wl.q0.reshape(-1))
+    R.ram_step(rows, q, dev(wl.v0), dev(wl.dv.reshape(-1)), wl.dt, 5, 2)
+    torch.cuda.synchronize()
+    got = q.cpu().numpy().reshape(wl.n_rows, -1)[pick].reshape(-1)
+    ref = oracle.step(orows, sw.q0, sw.v0, sw.dv, sw.dt, 5, 2)
+    assert_parity(got, ref, 1e-12, CELL_F64, what="FP64")
+    q32 = wl.q0.astype(np.float32)
+    dv32 = wl.dv.astype(np.float32)
+    ref = oracle.step(orows, q32.reshape(wl.n_rows, -1)[pick].astype(np.float64), sw.v0,
+                      dv32.reshape(wl.n_rows, -1)[pick].astype(np.float64), sw.dt, 5, 1)
+    for scan in (R.RAM_SUM_DIRECT, R.RAM_SCAN_F32_TWOSUM):
+        q = dev(q32.reshape(-1), torch.float32)
+        R.ram_step(rows, q, dev(wl.v0), dev(dv32.reshape(-1), torch.float32), wl.dt, 5, 1,
+                   scan)
+        torch.cuda.synchronize()
+        got = q.cpu().numpy().astype(np.float64).reshape(wl.n_rows, -1)[pick].reshape(-1)
+        e1, ec = assert_parity(got, ref, 1e-6, CELL_F32, what=str(scan))
+        print(f"stretched disk FP32 scan {scan}: rel-L1 {e1:.2e}, max cell {ec:.2e}")
+
+
 def test_cfg3_full_size_sampled_rows():
     wl = W.cfg3()
     rows = R.Rows.from_workload(wl, DEV)
