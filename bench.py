@@ -51,6 +51,10 @@ def parse():
     p.add_argument("--checkpoint", type=int, default=20)
     p.add_argument("--fp64-steps", type=int, default=200)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--no-stretched", action="store_true",
+                   help="skip the stretched-mesh disk (its step runs the same kernels at the "
+                        "same launch shape as the headline: a kernel trace of the headline "
+                        "leaves it out)")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--items", type=int, default=-1,
                    help="launch schedule of the headline step: 0 the streaming kernels "
@@ -565,32 +569,40 @@ def main():
     # --- the disk on a mesh of random cell sizes (every tile searching) -----
     # the headline's rows, shifts and residual on widths 8**u: no uniform run,
     # so the step's time is the searching tiles' (the arbitrary-mesh case)
-    wls = W.stretched_disk()
-    rows_s = R.Rows.from_workload(wls, dev)
-    v0s = torch.as_tensor(wls.v0, dtype=torch.float64, device=dev)
-    qs32 = torch.as_tensor(wls.q0.reshape(-1), dtype=torch.float32, device=dev)
-    dvs32 = torch.as_tensor(wls.dv.reshape(-1), dtype=torch.float32, device=dev)
-    sched_keep = ctx.get_schedule()
-    ctx.set_schedule(0)
-    spaths = ctx.ram_step_tile_paths(rows_s, v0s, wls.dt, order, True).cpu().numpy()
-    ks = max(1, args.steps // 5)
-    stretched = {"workload": wls.name + " (the disk's rows, shifts and residual; azimuthal "
-                             "cell widths 8**u, u ~ U[0,1)), FP32, order 5, fused residual, "
-                             "default schedule",
-                 "steps": ks, "unit": "Gcell-updates/s", "algorithmic_bytes_per_cell": 12,
-                 "tiles": {"uniform_run": int((spaths == R.RAM_TILE_UNIFORM).sum()),
-                           "searching": int((spaths == R.RAM_TILE_WINDOW).sum()),
-                           "direct": int((spaths == R.RAM_TILE_DIRECT).sum())}}
-    for name, scan in (("f32_direct", R.RAM_SUM_DIRECT), ("f32_twosum", R.RAM_SCAN_F32_TWOSUM)):
-        ts, _ = time_steps(qs32, dvs32, scan, ks, args.warmup, rows_s, v0s, wls.dt)
-        stretched[name] = round(wls.n_cells * ks / ts / 1e9, 3)
-        stretched[name + "_us_per_step"] = round(ts / ks * 1e6, 2)
-        stretched[name + "_hbm_frac"] = round(12.0 * wls.n_cells * ks / ts / 1e9
-                                              / HBM_PEAK_GBS, 4)
-    ctx.set_schedule(sched_keep)
-    del rows_s, qs32, dvs32, v0s
+    def time_stretched():
+        wls = W.stretched_disk()
+        rows_s = R.Rows.from_workload(wls, dev)
+        v0s = torch.as_tensor(wls.v0, dtype=torch.float64, device=dev)
+        qs32 = torch.as_tensor(wls.q0.reshape(-1), dtype=torch.float32, device=dev)
+        dvs32 = torch.as_tensor(wls.dv.reshape(-1), dtype=torch.float32, device=dev)
+        sched_keep = ctx.get_schedule()
+        ctx.set_schedule(0)
+        spaths = ctx.ram_step_tile_paths(rows_s, v0s, wls.dt, order, True).cpu().numpy()
+        ks = max(1, args.steps // 5)
+        stretched = {"workload": wls.name + " (the disk's rows, shifts and residual; azimuthal "
+                                 "cell widths 8**u, u ~ U[0,1)), FP32, order 5, fused residual, "
+                                 "default schedule",
+                     "steps": ks, "unit": "Gcell-updates/s", "algorithmic_bytes_per_cell": 12,
+                     "tiles": {"uniform_run": int((spaths == R.RAM_TILE_UNIFORM).sum()),
+                               "searching": int((spaths == R.RAM_TILE_WINDOW).sum()),
+                               "direct": int((spaths == R.RAM_TILE_DIRECT).sum())}}
+        for name, scan in (("f32_direct", R.RAM_SUM_DIRECT),
+                           ("f32_twosum", R.RAM_SCAN_F32_TWOSUM)):
+            ts, _ = time_steps(qs32, dvs32, scan, ks, args.warmup, rows_s, v0s, wls.dt)
+            stretched[name] = round(wls.n_cells * ks / ts / 1e9, 3)
+            stretched[name + "_us_per_step"] = round(ts / ks * 1e6, 2)
+            stretched[name + "_hbm_frac"] = round(12.0 * wls.n_cells * ks / ts / 1e9
+                                                  / HBM_PEAK_GBS, 4)
+        ctx.set_schedule(sched_keep)
+        del rows_s, qs32, dvs32, v0s
+        return stretched
+
+    stretched = None
+    if not args.no_stretched:
+        stretched = time_stretched()
 
     # --- growth of max |Q| per configuration (reading C14) ------------------
+
     # the unlimited order-p interpolant can amplify on rough meshes; each
     # config reports max|Q_T| / max|Q_0| over its configured steps (FP64),
     # and for the ragged rows the first 10-step mark where an order's max |Q|

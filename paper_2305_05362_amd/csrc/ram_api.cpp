@@ -285,8 +285,8 @@ int sched_items(const ram_ctx *ctx, const ram_layout *L, ram_scan scan)
 bool use_fast_shape(const ram_ctx *ctx, bool shared, int64_t n_cols, ram_dtype dtype,
                     ram_scan scan)
 {
-    return shared && n_cols > 0 && (dtype == RAM_F32 || dtype == RAM_F64) && ctx->items == 0 &&
-           ctx->density.kind == RAM_DENSITY_NONE;
+    return shared && n_cols > 0 && n_cols < ram::kFastMaxCols && (dtype == RAM_F32 || dtype == RAM_F64) &&
+           ctx->items == 0 && ctx->density.kind == RAM_DENSITY_NONE;
 }
 bool use_fast(const ram_ctx *ctx, const ram_layout *L, ram_dtype dtype, ram_scan scan)
 {

@@ -157,6 +157,10 @@ __host__ __device__ inline double bump_prim(double t, const MeshDensity &d)
 // tile, planned once per call (k_plan_fast), read with scalar loads.
 constexpr int kFastTile = 256;
 constexpr int kFastWin = 768;
+// Rows of the streaming kernels hold fewer cells than this (64 Mi): their
+// per-lane byte offsets into a row or a mesh table (16 bytes a cell at most)
+// fit 32 bits.  Longer rows take the general kernels.
+constexpr int64_t kFastMaxCols = int64_t(1) << 26;
 enum FastKind { kFastWindow = 0, kFastUniform = 1, kFastDirect = 2 };
 struct FastTile {
     int32_t kind;            // FastKind

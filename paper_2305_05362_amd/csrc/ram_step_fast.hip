@@ -172,7 +172,7 @@ __device__ __forceinline__ void load_faces(const float *dvp, int n, int i0, int 
 {
     const int cc = min(c4, nd - 1);
     if constexpr (VEC) {
-        const float4 v4 = *(const float4 *)(dvp + i0 + (cc & ~3));
+        const float4 v4 = ld_at<float4>(dvp + i0, 4u * (uint32_t)(cc & ~3));
         dvv[0] = v4.x;
         dvv[1] = v4.y;
         dvv[2] = v4.z;
@@ -194,7 +194,7 @@ __device__ __forceinline__ void store_cells(float *qo, int i0, int nd, int c4, c
 {
     if (c4 >= nd) return;
     if constexpr (VEC) {
-        *(float4 *)(qo + i0 + c4) = make_float4(o[0], o[1], o[2], o[3]);
+        st_at<float4>(qo + i0, 4u * (uint32_t)c4, make_float4(o[0], o[1], o[2], o[3]));
     } else {
 #pragma unroll
         for (int k = 0; k < 4; ++k)
@@ -752,12 +752,12 @@ __device__ __forceinline__ void window_tile(const StepArgs &a, const FastTile &f
     for (int u = 0; u < NG; ++u) {
         int c = a0 + 4 * min(t + u * kLanes, gl);
         c = c >= n ? c - n : c;
-        wq[u] = *(const float4 *)(q + c);
+        wq[u] = ld_at<float4>(q, 4u * (uint32_t)c);
         if constexpr (kDx64) {
-            wd2[u][0] = *(const double2 *)(tb.dx + c);
-            wd2[u][1] = *(const double2 *)(tb.dx + c + 2);
+            wd2[u][0] = ld_at<double2>(tb.dx, 8u * (uint32_t)c);
+            wd2[u][1] = ld_at<double2>(tb.dx, 8u * (uint32_t)c + 16u);
         } else {
-            wd[u] = *(const float4 *)(tb.dxf + c);
+            wd[u] = ld_at<float4>(tb.dxf, 4u * (uint32_t)c);
         }
     }
     float dvv[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
@@ -777,8 +777,8 @@ __device__ __forceinline__ void window_tile(const StepArgs &a, const FastTile &f
             const int g = min(t + u * kLanes, gl);
             int c = a0 + 4 * g;
             c = c >= n ? c - n : c;
-            const float4 vq = *(const float4 *)(q + c);
-            const float4 vd = *(const float4 *)(tb.dxf + c);
+            const float4 vq = ld_at<float4>(q, 4u * (uint32_t)c);
+            const float4 vd = ld_at<float4>(tb.dxf, 4u * (uint32_t)c);
             *(float4 *)(sw + 4 * g) = make_float4(vq.x * vd.x, vq.y * vd.y, vq.z * vd.z, vq.w * vd.w);
         }
     } else {
@@ -828,18 +828,19 @@ __device__ __forceinline__ void window_tile(const StepArgs &a, const FastTile &f
     // needed)
     constexpr int NV = 2 * P - 1;                    // values a cell
     float rth[NS][P + 1], rrd[NS][P + 1];
+    const float *stp1 = tb.stp + 4 * n, *stp2 = tb.stp + 8 * n;
 #pragma unroll
     for (int u = 0; u < NS; ++u) {
         int c = base + jv[u];
         c = c >= n ? c - n : c;
         float v[12];
-        const float4 A = ((const float4 *)tb.stp)[c];
+        const float4 A = ld_at<float4>(tb.stp, 16u * (uint32_t)c);
         v[0] = A.x; v[1] = A.y; v[2] = A.z; v[3] = A.w;
         if constexpr (NV > 4) {
-            const float4 B = ((const float4 *)tb.stp)[n + c];
+            const float4 B = ld_at<float4>(stp1, 16u * (uint32_t)c);
             v[4] = B.x; v[5] = B.y; v[6] = B.z; v[7] = B.w;
         }
-        if constexpr (NV > 8) v[8] = tb.stp[8 * n + c];
+        if constexpr (NV > 8) v[8] = ld_at<float>(stp2, 4u * (uint32_t)c);
         int k = 0;
 #pragma unroll
         for (int b = 0; b <= P; ++b)
@@ -918,13 +919,13 @@ __device__ __forceinline__ void window_tile(const StepArgs &a, const FastTile &f
         auto wr = [&](int c) { return c < 0 ? c + n : (c >= n ? c - n : c); };
 #pragma unroll
         for (int pr = 0; pr < 4; ++pr) {
-            const float4 r2 = *(const float4 *)(tb.rrf + wr(cb + 2 * pr));
+            const float4 r2 = ld_at<float4>(tb.rrf, 8u * (uint32_t)wr(cb + 2 * pr));
             rr[2 * pr] = make_float2(r2.x, r2.y);
             rr[2 * pr + 1] = make_float2(r2.z, r2.w);
         }
-        const float2 d0 = *(const float2 *)(tb.dxinvf + wr(cb));
-        const float4 d1 = *(const float4 *)(tb.dxinvf + wr(cb + 2));
-        const float2 d2 = *(const float2 *)(tb.dxinvf + wr(cb + 6));
+        const float2 d0 = ld_at<float2>(tb.dxinvf, 4u * (uint32_t)wr(cb));
+        const float4 d1 = ld_at<float4>(tb.dxinvf, 4u * (uint32_t)wr(cb + 2));
+        const float2 d2 = ld_at<float2>(tb.dxinvf, 4u * (uint32_t)wr(cb + 6));
         dxi[0] = d0.x; dxi[1] = d0.y;
         dxi[2] = d1.x; dxi[3] = d1.y; dxi[4] = d1.z; dxi[5] = d1.w;
         dxi[6] = d2.x; dxi[7] = d2.y;

@@ -62,6 +62,21 @@ __device__ inline FastTile load_rec(const FastTile *rec, int i)
 // selects is read with scalar loads).
 __device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane((int)threadIdx.x / kLanes); }
 
+// Load / store at a 32-bit byte offset from a wave-uniform base: the access
+// takes the scalar-base form (base in SGPRs, one 32-bit offset a lane)
+// instead of a 64-bit address formed in every lane.  The streaming kernels
+// run on rows of fewer than kFastMaxCols cells, so no offset wraps.
+template <class T>
+__device__ __forceinline__ T ld_at(const void *base, uint32_t byte_off)
+{
+    return *(const T *)((const char *)base + byte_off);
+}
+template <class T>
+__device__ __forceinline__ void st_at(void *base, uint32_t byte_off, const T &v)
+{
+    *(T *)((char *)base + byte_off) = v;
+}
+
 // Inclusive scan of one value a lane over the wave in DPP steps (row shifts,
 // then the row-15 and row-31 broadcasts; lanes without a source read zero),
 // and lane 63's value read back as a scalar.
