@@ -107,7 +107,8 @@ ram_status ram_destroy(ram_ctx *ctx);
  * streaming FP64 kernel on the same tile plan (every node's Lagrange weights
  * formed in FP64 from its source cell's stencil data, RAM_SCAN_F64 or
  * RAM_SUM_DIRECT; a tile whose source window exceeds 768 cells sums from
- * global memory).  2..5 select the general
+ * global memory); rows of 2^26 cells or more run the general kernel with 4
+ * shifted nodes per thread instead.  2..5 select the general
  * kernel with that many shifted nodes per thread (RAM_SUM_DIRECT; the prefix
  * modes then take 4): each workgroup of 256
  * threads shifts 256 * items_per_thread nodes, a tile of
