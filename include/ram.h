@@ -294,7 +294,8 @@ ram_status ram_step_limited_adjoint(ram_ctx *ctx, const ram_layout *layout,
                                     const double *v0, double dt,
                                     void *dvbar_accum, double *v0bar_accum);
 
-/* Adjoint of ram_shift (the shift is linear in Q): qbar_in = S^T qbar_out,
+/* Adjoint of ram_shift: the bulk shift of paper Section 3, Steps 1-3 (Eqs.
+ * Qmass_i, mass_advected, step3), is linear in Q, so qbar_in = S^T qbar_out,
  * overwritten.  When v0bar_accum != NULL, also accumulates per row
  *   v0bar_accum[r] += dt * d<qbar_out, S(s) q_fwd>/ds  at s = v0[r] dt,
  * which needs the forward input q_fwd (else q_fwd may be NULL). */
@@ -305,8 +306,9 @@ ram_status ram_shift_adjoint(ram_ctx *ctx, const ram_layout *layout,
                              const double *v0, double dt, int order,
                              double *v0bar_accum);
 
-/* Adjoint of ram_residual at the forward state q_fwd (the state the residual
- * step read): qbar_in = J_q^T qbar_out (overwritten); when dvbar_accum != NULL
+/* Adjoint of ram_residual (the residual upwind step of paper Eq.
+ * splitting_second with the van Leer slope of Section 3.1) at the forward
+ * state q_fwd (the state the residual step read): qbar_in = J_q^T qbar_out (overwritten); when dvbar_accum != NULL
  * it accumulates J_dv^T qbar_out (same dtype as q).  At the limiter's kink the
  * slope derivative is taken as zero and at dv = 0 the dv >= 0 branch is used. */
 ram_status ram_residual_adjoint(ram_ctx *ctx, const ram_layout *layout,
@@ -460,8 +462,11 @@ ram_status ram_step_point4(ram_ctx *ctx, const ram_layout *layout, ram_dtype dty
                            int64_t n_steps);
 
 /* Host-side check of the inputs (synchronous; copies to the host): strictly
- * increasing finite nodes (RAM_E_MESH), and when dv != NULL the residual
- * Courant condition |dv_f| dt <= min(dx_{f-1}, dx_f) (RAM_E_CFL). */
+ * increasing finite nodes (RAM_E_MESH; the mesh of paper Section 2), and when
+ * dv != NULL the residual Courant condition |dv_f| dt <= min(dx_{f-1}, dx_f)
+ * (RAM_E_CFL: information carried by the residual moves less than the
+ * smaller neighbouring cell in a step, the limit the paper's Section 1
+ * describes for upwind fluxes and Eq. cfl's advective terms apply). */
 ram_status ram_validate(ram_ctx *ctx, const ram_layout *layout,
                         ram_dtype dtype, const double *edges, const void *dv,
                         double dt);
