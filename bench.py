@@ -725,8 +725,10 @@ def main():
     limited = {"unit": "Gcell-updates/s", "steps": max(1, args.steps // 4),
                "step_algorithmic_bytes_per_cell": {"f32": 12, "f64": 24},
                "kernel": ("FP32: k_step_uni_lim (uniform-run tiles at the tile's theta) + "
-                          "k_step_gen_lim (the rest, nodes located and integrated from global "
-                          "memory) on the streaming plan; FP64: k_step_sh<double, 3 (PLM) / 5 "
+                          "k_step_gen_lim (the rest: windows of up to 400 cells tabulated in "
+                          "LDS -- slopes, interfaces, each cell's cubic -- wider ones integrated "
+                          "from global memory) on the streaming plan; FP64: k_step_sh<double, "
+                          "3 (PLM) / 5 "
                           "(PPM), direct sums, fused residual, recon>")}
     kl = limited["steps"]
     tr_pu = load_traffic(TRAFFIC_FILE_PPM_UNI, PPM_UNI_KERNEL)
