@@ -108,7 +108,9 @@ ram_status ram_destroy(ram_ctx *ctx);
  * formed in FP64 from its source cell's stencil data, RAM_SCAN_F64 or
  * RAM_SUM_DIRECT; a tile whose source window exceeds 768 cells sums from
  * global memory); rows of 2^26 cells or more run the general kernel with 4
- * shifted nodes per thread instead.  2..5 select the general
+ * shifted nodes per thread instead.  In a multi-step call's captured graph
+ * the FP32 step's two kernels (uniform-run tiles, searching tiles) are
+ * parallel branches on a second stream of the context.  2..5 select the general
  * kernel with that many shifted nodes per thread (RAM_SUM_DIRECT; the prefix
  * modes then take 4): each workgroup of 256
  * threads shifts 256 * items_per_thread nodes, a tile of

@@ -16,6 +16,11 @@
 #include <initializer_list>
 #include <vector>
 
+// set while a step loop is captured (ram_internal.h)
+namespace ram {
+thread_local const ForkJoin *capture_fork = nullptr;
+}
+
 struct ram_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -28,6 +33,7 @@ struct ram_ctx {
     // arguments stay the same (capture needs a stream of its own: the
     // caller's may be the null stream)
     hipStream_t cap_stream = nullptr;
+    ram::ForkJoin fork;                 // parallel branches inside a captured step
     struct Graph {
         std::vector<unsigned char> key;
         hipGraphExec_t exec = nullptr;
@@ -411,9 +417,17 @@ ram_status run_graphed(ram_ctx *ctx, std::vector<unsigned char> key, int64_t n_s
             e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
             if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
         }
+        if (!ctx->fork.side) {
+            e = hipStreamCreateWithFlags(&ctx->fork.side, hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->fork.fork, hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->fork.join, hipEventDisableTiming);
+            if (e != hipSuccess) return hip_fail(e, "fork stream / events");
+        }
         e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        ram::capture_fork = &ctx->fork;
         const hipError_t le = loop(ctx->cap_stream);
+        ram::capture_fork = nullptr;
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(ctx->cap_stream, &g);
         if (le != hipSuccess || e != hipSuccess) {
@@ -661,6 +675,9 @@ ram_status ram_destroy(ram_ctx *ctx)
     (void)hipStreamSynchronize(ctx->stream);
     for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    if (ctx->fork.side) (void)hipStreamDestroy(ctx->fork.side);
+    if (ctx->fork.fork) (void)hipEventDestroy(ctx->fork.fork);
+    if (ctx->fork.join) (void)hipEventDestroy(ctx->fork.join);
     if (ctx->handoff) (void)hipEventDestroy(ctx->handoff);
     if (ctx->scratch) (void)hipFree(ctx->scratch);
     delete ctx;

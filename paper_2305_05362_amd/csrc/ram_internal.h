@@ -400,6 +400,16 @@ hipError_t launch_step_shared(const StepArgs &a, bool f64, int scan, int order,
 hipError_t launch_plan_fast(const StepArgs &a, int order, const FastPlan &plan,
                             hipStream_t stream);
 hipError_t launch_step_fast(const StepArgs &a, int order, int scan, hipStream_t stream);
+// A second stream and two events of a context: while a step loop is being
+// captured into a graph (the calling thread's capture_fork points at them),
+// the FP32 streaming step forks its searching tiles' kernel onto the side
+// stream and joins it back, so that the graph holds the two kernels as
+// parallel branches.  Outside a capture the kernels run one after the other.
+struct ForkJoin {
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+extern thread_local const ForkJoin *capture_fork;
 // The same plan's limited FP32 step (PLM / PPM: k_step_uni_lim, k_step_gen_lim).
 hipError_t launch_step_fast_lim(const StepArgs &a, int recon, hipStream_t stream);
 // The same plan's FP64 step (k_step64, ram_step_fast64.hip): scan kScanF64 or kSumDirect.

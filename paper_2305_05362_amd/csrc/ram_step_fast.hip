@@ -1053,7 +1053,10 @@ __global__ __launch_bounds__(1024) void k_tile_lists(FastTile *rec, int nt,
 // both kinds (in tile order, or the other tiles spread evenly through the
 // grid) ran the uniform tiles at the other path's register and LDS footprint
 // and took 135-163 us a step against 123; persistent waves striding over the
-// other tiles, 128-157; running the two kernels on two streams, 342.
+// other tiles, 128-157; the two kernels on two streams with an event pair
+// around every eager step, 342.  Inside a captured step loop the two kernels
+// are parallel branches of the graph (fork / join events, ForkJoin): the
+// latency-bound searching tiles then run beside the HBM-bound uniform ones.
 template <int P, int H, bool VEC>
 __global__ __launch_bounds__(kBlock, 8) void k_step_uni(StepArgs a)
 {
@@ -1216,6 +1219,20 @@ hipError_t step_fast_kernels(const StepArgs &a, hipStream_t st)
 {
     const dim3 g((unsigned)((a.rows.n_tiles + kWaves - 1) / kWaves)), b(kBlock);
     const dim3 gg((unsigned)((a.rows.n_tiles + kWaves * kGenShare - 1) / (kWaves * kGenShare)));
+    if (const ForkJoin *fj = capture_fork) {
+        // the two kinds of tile write disjoint cells and read only q_in: the
+        // searching tiles' kernel on the side stream, between a fork after
+        // everything before the step and a join before everything after it
+        hipError_t e = hipEventRecord(fj->fork, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(fj->side, fj->fork, 0);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_step_gen<P, H, VEC, S>), gg, b, 0, fj->side, a);
+        e = hipEventRecord(fj->join, fj->side);
+        hipLaunchKernelGGL((k_step_uni<P, H, VEC>), g, b, 0, st, a);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, fj->join, 0);
+        if (e != hipSuccess) return e;
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL((k_step_uni<P, H, VEC>), g, b, 0, st, a);
     hipLaunchKernelGGL((k_step_gen<P, H, VEC, S>), gg, b, 0, st, a);
     return hipGetLastError();
