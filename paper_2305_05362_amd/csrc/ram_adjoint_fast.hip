@@ -1430,11 +1430,23 @@ hipError_t adjf_kernels(const StepAdjArgs &a, hipStream_t st)
 {
     const int64_t nt = a.rows.n_tiles;
     const dim3 b(kBlock);
-    hipLaunchKernelGGL((k_adjf_uni<P, RES, V0>), dim3((unsigned)((nt + kWaves - 1) / kWaves)), b,
-                       0, st, a);
-    hipLaunchKernelGGL((k_adjf_gen<P, RES, V0>),
-                       dim3((unsigned)((nt + kWaves * kGenShareA - 1) / (kWaves * kGenShareA))),
-                       b, 0, st, a);
+    const dim3 gu((unsigned)((nt + kWaves - 1) / kWaves));
+    const dim3 gg((unsigned)((nt + kWaves * kGenShareA - 1) / (kWaves * kGenShareA)));
+    if (const ForkJoin *fj = capture_fork) {
+        // inside a captured loop: the two kinds of tile (disjoint outputs and
+        // partials) as parallel graph branches, joined before the edges pass
+        hipError_t e = hipEventRecord(fj->fork, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(fj->side, fj->fork, 0);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_adjf_gen<P, RES, V0>), gg, b, 0, fj->side, a);
+        e = hipEventRecord(fj->join, fj->side);
+        hipLaunchKernelGGL((k_adjf_uni<P, RES, V0>), gu, b, 0, st, a);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, fj->join, 0);
+        if (e != hipSuccess) return e;
+    } else {
+        hipLaunchKernelGGL((k_adjf_uni<P, RES, V0>), gu, b, 0, st, a);
+        hipLaunchKernelGGL((k_adjf_gen<P, RES, V0>), gg, b, 0, st, a);
+    }
     hipLaunchKernelGGL((k_adjf_edges<P>), dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !V0) return e;

@@ -1287,6 +1287,18 @@ hipError_t step_fast_lim_kernels(const StepArgs &a, hipStream_t st)
 {
     const dim3 g((unsigned)((a.rows.n_tiles + kWaves - 1) / kWaves)), b(kBlock);
     const dim3 gg((unsigned)((a.rows.n_tiles + kWaves * kGenShare - 1) / (kWaves * kGenShare)));
+    if (const ForkJoin *fj = capture_fork) {
+        // parallel graph branches, as in step_fast_kernels
+        hipError_t e = hipEventRecord(fj->fork, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(fj->side, fj->fork, 0);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_step_gen_lim<R, H, VEC>), gg, b, 0, fj->side, a);
+        e = hipEventRecord(fj->join, fj->side);
+        hipLaunchKernelGGL((k_step_uni_lim<R, H, VEC>), g, b, 0, st, a);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, fj->join, 0);
+        if (e != hipSuccess) return e;
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL((k_step_uni_lim<R, H, VEC>), g, b, 0, st, a);
     hipLaunchKernelGGL((k_step_gen_lim<R, H, VEC>), gg, b, 0, st, a);
     return hipGetLastError();
